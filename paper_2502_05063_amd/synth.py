@@ -1,0 +1,107 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+Holds no arithmetic of the persistence method: only random point clouds and
+distance matrices with the shapes and distributions of the workloads:
+
+  uniform_cube(64)            64 points i.i.d. U[0,1)^3
+  sphere(192, 3)              192 points on S^3 in R^4 (normalised Gaussians);
+                              stands in for the paper's sphere_3_192 dataset
+  orthogonal_3x3(1024)        random O(3) matrices (QR of a Gaussian, signs fixed
+                              by diag(R)), flattened row-major into R^9; stands
+                              in for the paper's o3 dataset
+  circle_or_torus_batch(256)  clouds of U{50..400} points, each a noisy circle
+                              (radius 1) or torus (R=2, r=0.5), sigma 0.05
+  torus_batch(64, 500)        noisy tori, sigma 0.1
+  permutation_distances(n)    a random permutation of 1..n(n-1)/2 filling a
+                              symmetric matrix (random distance matrices of the
+                              paper's apparent-fraction experiment)
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def uniform_cube(n: int = 64, dim: int = 3, seed: int = 0) -> np.ndarray:
+    return _rng(seed).random((n, dim)).astype(np.float32)
+
+
+def sphere(n: int = 192, k: int = 3, seed: int = 0) -> np.ndarray:
+    g = _rng(seed).standard_normal((n, k + 1))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    return g.astype(np.float32)
+
+
+def orthogonal_3x3(n: int = 1024, seed: int = 0) -> np.ndarray:
+    rng = _rng(seed)
+    out = np.empty((n, 9), np.float64)
+    for i in range(n):
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        q = q * np.sign(np.diag(r))[None, :]
+        out[i] = q.reshape(-1)
+    return out.astype(np.float32)
+
+
+def circle(n: int, radius: float, sigma: float, rng) -> np.ndarray:
+    a = rng.uniform(0.0, 2.0 * np.pi, n)
+    x = np.stack([radius * np.cos(a), radius * np.sin(a), np.zeros(n)], axis=1)
+    return (x + rng.normal(0.0, sigma, (n, 3))).astype(np.float32)
+
+
+def torus(n: int, R: float, r: float, sigma: float, rng) -> np.ndarray:
+    a = rng.uniform(0.0, 2.0 * np.pi, n)
+    b = rng.uniform(0.0, 2.0 * np.pi, n)
+    x = np.stack(
+        [(R + r * np.cos(b)) * np.cos(a), (R + r * np.cos(b)) * np.sin(a), r * np.sin(b)], axis=1
+    )
+    return (x + rng.normal(0.0, sigma, (n, 3))).astype(np.float32)
+
+
+def circle_or_torus_batch(count: int = 256, nmin: int = 50, nmax: int = 400, sigma: float = 0.05,
+                          seed: int = 0):
+    rng = _rng(seed)
+    clouds = []
+    for _ in range(count):
+        n = int(rng.integers(nmin, nmax + 1))
+        if rng.random() < 0.5:
+            clouds.append(circle(n, 1.0, sigma, rng))
+        else:
+            clouds.append(torus(n, 2.0, 0.5, sigma, rng))
+    return clouds
+
+
+def torus_batch(count: int = 64, n: int = 500, sigma: float = 0.1, seed: int = 0):
+    rng = _rng(seed)
+    return [torus(n, 2.0, 0.5, sigma, rng) for _ in range(count)]
+
+
+def permutation_distances(n: int, seed: int = 0) -> np.ndarray:
+    """Symmetric float32 matrix whose n(n-1)/2 off-diagonal entries are a random
+    permutation of 1..n(n-1)/2 (exact in float32 while n(n-1)/2 < 2^24)."""
+    m = n * (n - 1) // 2
+    vals = _rng(seed).permutation(m).astype(np.float64) + 1.0
+    D = np.zeros((n, n), np.float32)
+    iu = np.tril_indices(n, -1)
+    D[iu] = vals
+    return D + D.T
+
+
+def integer_distances(n: int, levels: int, seed: int = 0) -> np.ndarray:
+    """Symmetric matrix with entries drawn from {1..levels}: many exact ties."""
+    rng = _rng(seed)
+    D = np.zeros((n, n), np.float32)
+    iu = np.tril_indices(n, -1)
+    D[iu] = rng.integers(1, levels + 1, len(iu[0])).astype(np.float32)
+    return D + D.T
+
+
+CONFIGS = {
+    "c1_cube64": dict(max_dim=1, threshold=float("inf")),
+    "c2_sphere192": dict(max_dim=3, threshold=float("inf")),
+    "c3_o3_1024": dict(max_dim=3, threshold=1.8),
+    "c4_batch256": dict(max_dim=1, threshold=float("inf")),
+    "c5_torus64x500": dict(max_dim=1, threshold=float("inf")),
+}

@@ -1,0 +1,432 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: a worked
+example printed in the paper, a closed form, an invariant, a textbook or
+library routine, or brute force on tiny inputs.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.sparse.csgraph import minimum_spanning_tree
+
+from oracle import brute
+from paper_2502_05063_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+INF = float("inf")
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def cidx(vs):
+    return sum(math.comb(v, i + 1) for i, v in enumerate(sorted(vs)))
+
+
+def rand_metric(n, seed, dim=3):
+    X = np.random.default_rng(seed).random((n, dim)).astype(np.float32)
+    return X
+
+
+# --------------------------------------------------------------------------
+# Eq. 5.6 and binomials
+
+
+def test_binomial_matches_math_comb(orc):
+    for v in range(0, 200, 7):
+        for k in range(0, 9):
+            assert orc.binomial(v, k) == math.comb(v, k)
+    # 2^64 saturation: C(200, 100) does not fit
+    assert orc.binomial(200, 100) == 2**64 - 1
+    assert orc.binomial(67, 33) == math.comb(67, 33)  # < 2^64
+
+
+# --------------------------------------------------------------------------
+# distances
+
+
+def _rn32_exact_check(c, S):
+    """True iff float32 c is a nearest float32 to sqrt(S) (S an exact Fraction)."""
+    from fractions import Fraction
+    c = np.float32(c)
+    up = np.nextafter(c, np.float32(np.inf))
+    dn = np.nextafter(c, np.float32(0)) if c > 0 else np.float32(0)
+    lo = (Fraction(float(c)) + Fraction(float(dn))) / 2
+    hi = (Fraction(float(c)) + Fraction(float(up))) / 2
+    return (c == 0 and S == 0) or (lo * lo <= S <= hi * hi)
+
+
+def test_pdist_is_nearest_float32_to_exact_distance(orc):
+    """Exact rational arithmetic: each D_ij is the float32 nearest to the true
+    Euclidean distance (the binary64 evaluation can only differ on a set of
+    inputs of measure ~1e-9, none of which these seeds hit)."""
+    from fractions import Fraction
+    rng = np.random.default_rng(3)
+    for m in (1, 3, 4, 9):
+        X = (rng.standard_normal((23, m)) * rng.choice([1e-3, 1.0, 1e3], (23, 1))).astype(np.float32)
+        D = orc.pdist(X)
+        assert np.array_equal(D, D.T) and not np.any(np.diag(D))
+        for i in range(23):
+            for j in range(i):
+                S = sum((Fraction(float(X[i, k])) - Fraction(float(X[j, k]))) ** 2 for k in range(m))
+                assert _rn32_exact_check(D[i, j], S), (m, i, j)
+
+
+def test_pdist_pythagorean_values(orc):
+    X = np.array([[0, 0, 0], [3, 4, 0], [3, 4, 12], [-5, 0, 0]], np.float32)
+    D = orc.pdist(X)
+    assert D[1, 0] == 5 and D[2, 0] == 13 and D[2, 1] == 12 and D[3, 1] == np.float32(np.sqrt(80.0))
+
+
+def test_diameter_edge_ties_take_largest_edge_index(orc):
+    D = np.ones((4, 4), np.float32) - np.eye(4, dtype=np.float32)  # all edges tie
+    assert orc.diameter_edge(D, 2, cidx((3, 1, 0))) == (3, 1)
+    assert orc.diameter_edge(D, 3, cidx((3, 2, 1, 0))) == (3, 2)
+    D[3, 2] = D[2, 3] = 0.5  # the longest edges of (3,2,0) are (3,0) and (2,0)
+    assert orc.diameter_edge(D, 2, cidx((3, 2, 0))) == (3, 0)
+
+
+def test_enclosing_radius_worked_values(orc):
+    # unit square (Fig. 5.1): every vertex is sqrt(2) from its opposite corner
+    X = np.asarray(gold("fig5_1_square.json")["points"], np.float32)
+    assert orc.enclosing_radius(orc.pdist(X)) == np.float32(np.sqrt(2.0))
+    # a star: the centre is within 1 of everything, the leaves are 2 apart
+    X = np.array([[0, 0], [1, 0], [-1, 0], [0, 1], [0, -1]], np.float32)
+    assert orc.enclosing_radius(orc.pdist(X)) == 1.0
+
+
+# --------------------------------------------------------------------------
+# Alg. 2 worked example (Fig. 4.1 / 4.2)
+
+
+def test_fig4_1_pivots(orc):
+    g = gold("fig4_1_boundary.json")
+    cols = g["columns"]
+    lows_before = [max(c) if c else -1 for c in cols]
+    assert lows_before == g["lows_before"]
+    low = orc.reduce_explicit(cols)
+    pivots = sorted([int(low[j]), j] for j in range(len(cols)) if low[j] >= 0)
+    assert pivots == sorted(g["pivots"])
+
+
+# --------------------------------------------------------------------------
+# Fig. 5.1: unit square
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_fig5_1_square_h1_bar(orc, mode):
+    g = gold("fig5_1_square.json")
+    X = np.asarray(g["points"], np.float32)
+    D = orc.pdist(X)
+    P = orc.barcode(D, 1, mode=mode)
+    h1 = orc.nonzero(P[P["dim"] == 1])
+    assert len(h1) == 1
+    assert h1["birth_diam"][0] == np.float32(g["h1_bars"][0][0])
+    assert h1["death_diam"][0] == np.float32(g["h1_bars"][0][1])
+    h0 = P[P["dim"] == 0]
+    assert (h0["essential"] == 1).sum() == 1 and len(h0) == 4
+
+
+# --------------------------------------------------------------------------
+# Fig. 5.5 / 5.6 / Thm 5.4.2: apparent pairs
+
+
+def test_fig5_5_apparent_pairs(orc):
+    g = gold("fig5_5_apparent.json")
+    n = g["n"]
+    D = np.ones((n, n), np.float32) - np.eye(n, dtype=np.float32)
+    s, t = orc.apparent_pairs(D, 1)
+    want = sorted((cidx(a), cidx(b)) for a, b in g["apparent_vertices"])
+    assert sorted(zip(s.tolist(), t.tolist())) == want
+    # the printed column order is the coboundary order: increasing cidx at equal diameter
+    assert [cidx(c) for c in g["column_order_printed"]] == sorted(cidx(c) for c in g["column_order_printed"])
+
+
+def test_fig5_6_reassigned_distances_keep_apparent_set(orc):
+    g = gold("fig5_6_distances.json")
+    g5 = gold("fig5_5_apparent.json")
+    n = g["n"]
+    D = np.zeros((n, n), np.float32)
+    for (a, b), v in zip(g["edges_in_lex_order"], g["values"]):
+        D[a, b] = D[b, a] = v
+    s, t = orc.apparent_pairs(D, 1, flags=orc.FLAG_NO_ENCLOSING)
+    want = sorted((cidx(a), cidx(b)) for a, b in g5["apparent_vertices"])
+    assert sorted(zip(s.tolist(), t.tolist())) == want
+
+
+@pytest.mark.parametrize("n0,d", [(4, 1), (5, 1), (7, 1), (9, 1), (5, 2), (7, 2), (8, 3), (6, 4)])
+def test_thm5_4_2_equal_diameters_upper_bound(orc, n0, d):
+    """All diameters equal: exactly C(n0-1, d+1) apparent (d, d+1) pairs, the
+    upper bound (n0-d-1)/n0 of all C(n0, d+1) d-simplices; for d = 1 this is
+    also the closed form of recurrence (5.11), T(n0) = C(n0-1, 2)."""
+    D = np.ones((n0, n0), np.float32) - np.eye(n0, dtype=np.float32)
+    s, t = orc.apparent_pairs(D, d)
+    assert len(s) == math.comb(n0 - 1, d + 1)
+    assert len(s) * n0 == (n0 - d - 1) * math.comb(n0, d + 1)
+    # every apparent cofacet contains the maximum vertex n0-1 (Lemma 5.4.1)
+    for tt in t.tolist():
+        assert tt >= math.comb(n0 - 1, d + 2)
+
+
+def test_recurrence_5_11(orc):
+    T = {3: 1}
+    for n0 in range(4, 10):
+        T[n0] = T[n0 - 1] + n0 - 2
+    for n0 in range(3, 10):
+        D = np.ones((n0, n0), np.float32) - np.eye(n0, dtype=np.float32)
+        s, _ = orc.apparent_pairs(D, 1)
+        assert len(s) == T[n0]
+
+
+def test_matrix_and_per_column_definitions_agree(orc):
+    """Two codings of Def. 5.3.4: row/column zeros of the explicit matrix and
+    youngest-facet/oldest-cofacet per column."""
+    for seed, (n, d, levels) in enumerate([(9, 1, 0), (10, 2, 0), (9, 1, 3), (9, 2, 2), (8, 3, 0)]):
+        D = synth.integer_distances(n, levels, seed) if levels else synth.permutation_distances(n, seed)
+        s, t = orc.apparent_pairs(D, d)
+        got = {}
+        for vs in itertools.combinations(range(n), d + 1):
+            c = cidx(vs)
+            r = orc.is_apparent(D, d, c)
+            if r is not None:
+                got[c] = r
+        assert got == dict(zip(s.tolist(), t.tolist()))
+
+
+def test_apparent_pairs_have_zero_persistence_and_are_pairs(orc):
+    for seed in range(4):
+        D = orc.pdist(rand_metric(12, seed))
+        P = orc.barcode(D, 2)
+        for d in (1, 2):
+            s, t = orc.apparent_pairs(D, d)
+            pairs = {(int(p["birth"]), int(p["death"])): p for p in P[P["dim"] == d]}
+            for a, b in zip(s.tolist(), t.tolist()):
+                p = pairs[(a, b)]  # every apparent pair is a persistence pair
+                assert p["birth_diam"] == p["death_diam"]
+
+
+def test_lemma_5_4_9_apparent_edges_are_not_mst_edges(orc):
+    for seed in range(4):
+        D = orc.pdist(rand_metric(15, seed))
+        h0 = orc.h0_kruskal(D)
+        mst = set(int(p["death"]) for p in h0 if not p["essential"])
+        s, _ = orc.apparent_pairs(D, 1)
+        assert mst.isdisjoint(set(s.tolist()))
+
+
+# --------------------------------------------------------------------------
+# brute force from ranks (Thm 3.2.20 / Eq. 3.99)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize(
+    "n,max_dim,kind,seed",
+    [(6, 1, "metric", 0), (7, 1, "metric", 1), (6, 2, "metric", 2), (6, 2, "ties", 3),
+     (7, 1, "ties", 4), (5, 3, "perm", 5), (6, 2, "perm", 6)],
+)
+def test_pairs_reproduce_rank_invariant(orc, mode, n, max_dim, kind, seed):
+    if kind == "metric":
+        D = orc.pdist(rand_metric(n, seed))
+    elif kind == "ties":
+        D = synth.integer_distances(n, 2, seed)
+    else:
+        D = synth.permutation_distances(n, seed)
+    tau = orc.enclosing_radius(D)
+    P = orc.barcode(D, max_dim, mode=mode)
+    brute.check_pairs_against_ranks(D, max_dim, tau, P)
+    # also without truncation at the enclosing radius
+    P2 = orc.barcode(D, max_dim, mode=mode, flags=orc.FLAG_NO_ENCLOSING)
+    brute.check_pairs_against_ranks(D, max_dim, INF, P2)
+
+
+def test_rank_invariant_detects_a_wrong_pair(orc):
+    """The brute force is strong enough to see a single swapped death."""
+    D = orc.pdist(rand_metric(7, 11))
+    P = orc.barcode(D, 1).copy()
+    fin = np.nonzero((P["dim"] == 1) & (P["essential"] == 0))[0]
+    assert len(fin) >= 2
+    i, j = fin[0], fin[-1]
+    P["death"][i], P["death"][j] = P["death"][j], P["death"][i]
+    with pytest.raises(AssertionError):
+        brute.check_pairs_against_ranks(D, 1, orc.enclosing_radius(D), P)
+
+
+# --------------------------------------------------------------------------
+# the three modes (Prop. 4.3.5 duality, Lemma 5.2.10) and clearing (Prop. 5.3.9)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_modes_agree(orc, seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(8, 15))
+    max_dim = int(rng.integers(1, 3))
+    kind = seed % 3
+    if kind == 0:
+        D = orc.pdist(rng.random((n, 3)).astype(np.float32))
+    elif kind == 1:
+        D = synth.integer_distances(n, 3, seed)
+    else:
+        D = synth.permutation_distances(n, seed)
+    thr = [INF, float(np.quantile(D[D > 0], 0.6))][seed % 2]
+    ref = orc.barcode(D, max_dim, thr, mode=orc.M1_BOUNDARY)
+    for mode in (orc.M1_COBOUNDARY, orc.M2_STREAMED):
+        for flags in (0, orc.FLAG_NO_CLEARING):
+            got = orc.barcode(D, max_dim, thr, mode=mode, flags=flags)
+            assert np.array_equal(got, ref)
+
+
+# --------------------------------------------------------------------------
+# H0 (Sec. 5.2.5): Kruskal and a library MST
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_h0_equals_kruskal_and_mst_weight(orc, seed):
+    D = orc.pdist(rand_metric(40, seed))
+    P = orc.barcode(D, 0)
+    K = orc.h0_kruskal(D)
+    assert np.array_equal(P, K)
+    fin = P[P["essential"] == 0]
+    assert len(fin) == 39 and (P["essential"] == 1).sum() == 1
+    T = minimum_spanning_tree(D.astype(np.float64)).toarray()
+    assert np.isclose(float(fin["death_diam"].astype(np.float64).sum()), T.sum(), rtol=1e-12, atol=0)
+    assert sorted(fin["death_diam"].tolist()) == sorted(T[T > 0].astype(np.float32).tolist())
+
+
+def test_h0_elder_rule_with_ties(orc):
+    for seed in range(5):
+        D = synth.integer_distances(12, 2, seed)
+        assert np.array_equal(orc.barcode(D, 0), orc.h0_kruskal(D))
+        assert np.array_equal(orc.barcode(D, 0, mode=orc.M1_BOUNDARY), orc.h0_kruskal(D))
+
+
+def test_h0_components_below_threshold(orc):
+    D = orc.pdist(rand_metric(30, 7))
+    thr = float(np.quantile(D[D > 0], 0.05))
+    P = orc.barcode(D, 0, thr)
+    A = (D <= thr).astype(np.uint8)
+    from scipy.sparse.csgraph import connected_components
+    ncomp, _ = connected_components(A, directed=False)
+    assert (P["essential"] == 1).sum() == ncomp
+    assert np.array_equal(P, orc.h0_kruskal(D, thr))
+
+
+# --------------------------------------------------------------------------
+# counting identities and invariances
+
+
+def simplex_counts(D, tau, max_dim):
+    n = D.shape[0]
+    cnt = []
+    for k in range(max_dim + 1):
+        c = 0
+        for vs in itertools.combinations(range(n), k + 1):
+            if all(D[a, b] <= tau for a, b in itertools.combinations(vs, 2)):
+                c += 1
+        cnt.append(c)
+    return cnt
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_every_simplex_pairs_once_obs_3_2_14(orc, seed):
+    D = orc.pdist(rand_metric(11, seed))
+    for flags, tau in ((0, orc.enclosing_radius(D)), (orc.FLAG_NO_ENCLOSING, INF)):
+        P = orc.barcode(D, 2, flags=flags)
+        n_k = simplex_counts(D, tau, 2)
+        for k in range(3):
+            Pk = ((P["dim"] == k) & (P["essential"] == 0)).sum()
+            Pk1 = ((P["dim"] == k - 1) & (P["essential"] == 0)).sum() if k else 0
+            Ek = ((P["dim"] == k) & (P["essential"] == 1)).sum()
+            assert n_k[k] == Pk + Pk1 + Ek
+        # Euler characteristic of the (max_dim)-skeleton vs the pairs
+        chi = sum((-1) ** k * n_k[k] for k in range(3))
+        E = [((P["dim"] == k) & (P["essential"] == 1)).sum() for k in range(3)]
+        P2 = ((P["dim"] == 2) & (P["essential"] == 0)).sum()
+        assert chi == E[0] - E[1] + (E[2] + P2)
+
+
+def test_order_only_dependence_obs_5_6_8(orc):
+    """Replacing distances by their dense ranks keeps every (birth, death) index."""
+    for seed in range(3):
+        D = orc.pdist(rand_metric(13, seed))
+        vals = np.unique(D)
+        R = np.searchsorted(vals, D).astype(np.float32)
+        a = orc.barcode(D, 2)
+        b = orc.barcode(R, 2)
+        for f in ("dim", "essential", "birth", "death"):
+            assert np.array_equal(a[f], b[f])
+
+
+def test_enclosing_radius_truncation_prop_5_2_13(orc):
+    for seed in range(3):
+        D = orc.pdist(rand_metric(14, seed))
+        full = orc.nonzero(orc.barcode(D, 2, flags=orc.FLAG_NO_ENCLOSING))
+        cut = orc.nonzero(orc.barcode(D, 2))
+        assert np.array_equal(full, cut)
+
+
+# --------------------------------------------------------------------------
+# known shapes (external mathematics, qualitative)
+
+
+def test_circle_has_one_dominant_h1_bar(orc):
+    rng = np.random.default_rng(0)
+    X = synth.circle(40, 1.0, 0.02, rng)
+    P = orc.barcode(orc.pdist(X), 1)
+    h1 = P[P["dim"] == 1]
+    pers = np.sort(h1["death_diam"] - h1["birth_diam"])[::-1]
+    assert pers[0] > 1.0 and pers[1] < 0.2  # born at the largest sampling gap, dies near sqrt(3)
+
+
+# --------------------------------------------------------------------------
+# the gradient oracle against central finite differences in binary64
+
+
+def test_gradient_against_finite_differences(orc):
+    rng = np.random.default_rng(5)
+    X = synth.torus(25, 2.0, 0.5, 0.1, rng)
+    D = orc.pdist(X)
+    P = orc.barcode(D, 1)
+    h1 = P[(P["dim"] == 1) & (P["essential"] == 0)]
+    pers = (h1["death_diam"] - h1["birth_diam"]).astype(np.float32)
+    gb, gd = -2.0 * pers, 2.0 * pers
+    G = orc.gradient(X, D, h1, gb, gd)
+
+    def verts(dim, c):
+        out, c = [], int(c)
+        v = X.shape[0] - 1
+        for i in range(dim, -1, -1):
+            while math.comb(v, i + 1) > c:
+                v -= 1
+            out.append(v)
+            c -= math.comb(v, i + 1)
+            v -= 1
+        return out
+
+    def loss64(Xd, pairs):
+        L = 0.0
+        for p in pairs:
+            b = max(np.linalg.norm(Xd[a] - Xd[c]) for a, c in itertools.combinations(verts(1, p["birth"]), 2))
+            d = max(np.linalg.norm(Xd[a] - Xd[c]) for a, c in itertools.combinations(verts(2, p["death"]), 2))
+            L += (d - b) ** 2
+        return L
+
+    h = 1e-5
+    Xd = X.astype(np.float64)
+    for i in range(X.shape[0]):
+        for k in range(3):
+            Xp, Xm = Xd.copy(), Xd.copy()
+            Xp[i, k] += h
+            Xm[i, k] -= h
+            # the pairing must not change across the stencil
+            for Xs in (Xp, Xm):
+                Ps = orc.barcode(orc.pdist(Xs.astype(np.float32)), 1)
+                hs = Ps[(Ps["dim"] == 1) & (Ps["essential"] == 0)]
+                assert np.array_equal(hs["birth"], h1["birth"]) and np.array_equal(hs["death"], h1["death"])
+            fd = (loss64(Xp, h1) - loss64(Xm, h1)) / (2 * h)
+            assert abs(fd - G[i, k]) <= 1e-5 * max(1.0, abs(G).max()), (i, k, fd, G[i, k])
