@@ -1,0 +1,130 @@
+"""Benchmark of the Vietoris–Rips barcode hot path on one MI355X.
+
+A step is one whole barcode computation (distances, enclosing radius, H0,
+enumeration + apparent-pairs test per dimension, coboundary-order sort,
+host submatrix reduction, result assembly) of 192 points on S^3 in R^4
+(normalised Gaussians, seed 0), dimensions 0..3, full threshold; the points
+are resident in HBM before the timed region starts.
+
+Prints one JSON line (see the design doc for every field).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "barcode wall time (ms) + simplices/sec and HBM GB/s; batched fwd+bwd clouds/sec vs plain"
+# MI355X published peaks used for the roofline
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit integer / compare lane-ops per second
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def cpu_baseline(X, max_dim):
+    """The oracle as it stands, on a bounded sample: same points, dims 0..2."""
+    import oracle
+
+    n = X.shape[0]
+    sample_dim = min(max_dim, 2)
+    t0 = time.perf_counter()
+    D = oracle.pdist(X)
+    oracle.barcode(D, sample_dim, mode=oracle.M2_STREAMED)
+    dt = time.perf_counter() - t0
+    simplices = sum(math.comb(n, d + 1) for d in range(sample_dim + 1))
+    return {
+        "value": simplices / dt,
+        "unit": "simplices/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"same {n} points, dimensions 0..{sample_dim} (streamed mode, Alg. 12), {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2502_05063_amd import synth, vrph
+
+    n, max_dim = 192, 3
+    X = synth.sphere(n, 3, seed=0)
+    Xd = torch.from_numpy(X).cuda()
+    ctx = vrph.Context(0)
+    for i in range(args.warmup):
+        bc = ctx.barcode(X=Xd, max_dim=max_dim)
+        print(f"warmup {i}: {bc.stats['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        bc = ctx.barcode(X=Xd, max_dim=max_dim)
+        stats.append(bc.stats)
+        print(f"step {i}: {bc.stats['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    s0 = stats[-1]
+    simplices = sum(s0["candidates"])
+    value = simplices / (ms / 1e3)
+
+    # dominant kernel: the dimension-3 enumeration + apparent-pairs kernel
+    d = max_dim
+    k_ms = float(np.mean([s["apparent_ms"][d] for s in stats]))
+    cand, cof, cols = s0["candidates"][d], s0["cofacets"][d], s0["columns"][d]
+    # algorithmic 32-bit weight comparisons: C(d+1,2) per candidate for its
+    # diameter, d+1 per cofacet examined by the scans
+    ops = cand * math.comb(d + 1, 2) + cof * (d + 1)
+    achieved = ops / (k_ms / 1e3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "simplices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sphere_3_192-like: 192 points on S^3 (seed 0), dims 0-3, full Rips",
+                   "n": n, "max_dim": max_dim, "threshold": "inf"},
+        "barcode_ms": ms,
+        "kernel_ms_per_dim": [float(np.mean([s["apparent_ms"][k] for s in stats])) for k in range(d + 1)],
+        "gpu_ms_per_dim": [float(np.mean([s["gpu_ms"][k] for s in stats])) for k in range(d + 1)],
+        "host_ms_per_dim": [float(np.mean([s["host_ms"][k] for s in stats])) for k in range(d + 1)],
+        "columns_per_dim": s0["columns"],
+        "apparent_per_dim": s0["apparent"],
+        "reduced_per_dim": s0["reduced"],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "kernel": f"enum_apparent_kernel<{d}>", "kernel_ms": k_ms,
+                     "ops_per_launch": ops},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(X, max_dim)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

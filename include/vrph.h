@@ -1,0 +1,180 @@
+/*
+ * vrph.h — C ABI of the MI355X (gfx950) Vietoris–Rips persistence library.
+ *
+ * The problem (Zhang, "Computing and Learning on Combinatorial Data", Ch. 5):
+ * a finite metric space given as a distance matrix D (Sec. 5.1, Def. 5.1.1)
+ * or as points in R^m, a maximum dimension and a diameter threshold (Eq. 5.3)
+ * go in; the persistence pairs of every dimension 0..max_dim of the
+ * Vietoris–Rips filtration come out (Alg. 11 output, Sec. 5.2).
+ *
+ * Conventions used throughout:
+ *  - Simplices are named by their combinatorial index (Eq. 5.6): vertices
+ *    v_k > ... > v_0 map to sum_i C(v_i, i+1). A vertex v has index v.
+ *  - The filtration order is the simplex-wise refinement of Sec. 5.1.4:
+ *    diameter ascending, then dimension ascending, then index descending.
+ *    A pair (birth, death) is a pivot of the reduced boundary matrix.
+ *  - The threshold is inclusive (diam <= threshold). Unless
+ *    VRPH_NO_ENCLOSING_RADIUS is given, the effective threshold is
+ *    min(threshold, R) with R = min_i max_j D_ij the enclosing radius
+ *    (Sec. 5.2.12); this never changes a pair of nonzero persistence
+ *    (Prop. 5.2.13). threshold = +inf means the full Rips filtration.
+ *  - Distances computed from points are
+ *      D_ij = float32( sqrt( sum_k (x_ik - x_jk)^2 ) )
+ *    with the differences, squares, left-to-right sum and a correctly rounded
+ *    square root in IEEE binary64 and one final rounding to float32.
+ *  - Pointer arguments named X, D, gX, edges, g_birth, g_death, X_packed are
+ *    DEVICE pointers owned by the caller, read (or for gX accumulated into)
+ *    in stream order on the given stream (NULL = the context's own stream).
+ *    The call returns after the stream work it needs has completed.
+ *  - Results (vrph_barcode) are owned by the library, live in host memory and
+ *    are released with vrph_barcode_free.
+ *  - Every entry point returns a vrph_status; nothing aborts or throws across
+ *    the ABI. On failure no output object is produced and vrph_last_error()
+ *    returns a thread-local description.
+ *  - A context is not thread safe: use one per host thread.
+ */
+#ifndef VRPH_H
+#define VRPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VRPH_OK = 0,
+  VRPH_EINVAL = -1,    /* bad argument or invalid distance matrix */
+  VRPH_ENOMEM = -2,    /* device or host allocation failed */
+  VRPH_EOVERFLOW = -3, /* C(n, max_dim + 2) >= 2^63: indices do not fit */
+  VRPH_EDEVICE = -4,   /* a HIP call failed */
+  VRPH_ESTATE = -5     /* call not valid in the object's current state */
+} vrph_status;
+
+/* flags */
+#define VRPH_KEEP_ZERO_PERSISTENCE 1u /* report every pair, also birth == death */
+#define VRPH_NO_ENCLOSING_RADIUS 2u   /* do not cut at the enclosing radius */
+
+#define VRPH_MAX_DIM 6 /* largest supported max_dim */
+
+typedef struct vrph_ctx vrph_ctx;
+typedef struct vrph_barcode vrph_barcode;
+typedef struct vrph_batch vrph_batch;
+
+/* One persistence pair; 48 bytes. birth/death are combinatorial indices of
+ * the birth simplex (dimension dim) and death simplex (dimension dim+1).
+ * Essential classes (never killed below the threshold) have essential = 1,
+ * death = UINT64_MAX and death_diam = +inf. birth_edge / death_edge give the
+ * vertices (u > v) of the edge realising the simplex's diameter: among the
+ * longest edges, the one with the largest edge index. They are -1 for a
+ * vertex birth and for an essential death. */
+typedef struct {
+  int32_t dim;
+  int32_t essential;
+  uint64_t birth;
+  uint64_t death;
+  float birth_diam;
+  float death_diam;
+  int32_t birth_edge[2];
+  int32_t death_edge[2];
+} vrph_pair;
+
+/* Counts per dimension d (index d), in the terms of Ch. 5:
+ *   candidates      simplices examined by the enumeration
+ *   columns         columns of the coboundary matrix after the threshold and
+ *                   clearing (Alg. 17)
+ *   apparent        columns found apparent (Lemma 5.3.6)
+ *   reduced         non-apparent columns reduced on the host (Sec. 5.5.1)
+ *   additions       column additions made by that reduction
+ *   pairs           pairs of dimension d, all of them (also zero persistence)
+ *   cofacets        cofacets examined by the apparent-pairs scans
+ *   gpu_ms          device time of dimension d's kernels (HIP events)
+ *   apparent_ms     device time of the enumeration + apparent-pairs kernel
+ *                   of dimension d alone (HIP events on the call's stream)
+ *   host_ms         host time of dimension d's reduction                     */
+typedef struct {
+  int64_t candidates[VRPH_MAX_DIM + 1];
+  int64_t columns[VRPH_MAX_DIM + 1];
+  int64_t apparent[VRPH_MAX_DIM + 1];
+  int64_t reduced[VRPH_MAX_DIM + 1];
+  int64_t additions[VRPH_MAX_DIM + 1];
+  int64_t pairs[VRPH_MAX_DIM + 1];
+  int64_t cofacets[VRPH_MAX_DIM + 1];
+  double gpu_ms[VRPH_MAX_DIM + 1];
+  double apparent_ms[VRPH_MAX_DIM + 1];
+  double host_ms[VRPH_MAX_DIM + 1];
+  float tau_eff;       /* the threshold actually applied */
+  int32_t max_dim;
+  double total_ms;     /* host wall time of the whole call */
+} vrph_stats;
+
+/* Create a context on HIP device `device` (it becomes current for the calling
+ * thread). The context owns a stream, device workspaces that grow on demand
+ * and are reused across calls, and the binomial tables. */
+vrph_status vrph_create(int device, vrph_ctx** out);
+void vrph_destroy(vrph_ctx* ctx);
+
+/* Thread-local text for the last non-OK status returned on this thread. */
+const char* vrph_last_error(void);
+
+/* Pairwise distances (Def. 5.1.1, formula above): X is n x m row-major
+ * float32, D receives n x n float32 (symmetric, zero diagonal). */
+vrph_status vrph_pdist(vrph_ctx* ctx, const float* X, int64_t n, int32_t m, float* D,
+                       void* hip_stream);
+
+/* Barcode of a distance matrix. D: n x n float32, finite, >= 0, symmetric,
+ * zero diagonal (VRPH_EINVAL otherwise; the triangle inequality is not
+ * required, Sec. 5.6.6). 1 <= n <= 2048, 0 <= max_dim <= VRPH_MAX_DIM,
+ * threshold >= 0 or +inf. */
+vrph_status vrph_barcode_from_dist(vrph_ctx* ctx, const float* D, int64_t n, int32_t max_dim,
+                                   float threshold, uint32_t flags, void* hip_stream,
+                                   vrph_barcode** out);
+
+/* Same from points: pdist, then the above. */
+vrph_status vrph_barcode_from_points(vrph_ctx* ctx, const float* X, int64_t n, int32_t m,
+                                     int32_t max_dim, float threshold, uint32_t flags,
+                                     void* hip_stream, vrph_barcode** out);
+
+/* Pairs of dimension dim (dim = -1: all dimensions), canonical order: by
+ * dimension, then birth index, then death index. Without
+ * VRPH_KEEP_ZERO_PERSISTENCE, pairs with birth_diam == death_diam are left
+ * out, as in Ripser's output. */
+int64_t vrph_barcode_count(const vrph_barcode* bc, int32_t dim);
+const vrph_pair* vrph_barcode_pairs(const vrph_barcode* bc, int32_t dim);
+const vrph_stats* vrph_barcode_stats(const vrph_barcode* bc);
+void vrph_barcode_free(vrph_barcode* bc);
+
+/* ---- batched point clouds -------------------------------------------------
+ * A plan fixes the cloud sizes, the ambient dimension m, max_dim, threshold
+ * and flags, and allocates every device buffer the batch needs up front.
+ * Clouds are packed row-major one after another in X_packed
+ * (sum(sizes) x m floats). vrph_batch_forward replays one captured HIP graph
+ * over all clouds (distances, enclosing radii, H0, enumeration and the
+ * apparent-pairs test), then reduces the few non-apparent columns of every
+ * cloud on host threads. Each size must satisfy 2 <= size <= 2048 and every
+ * cloud uses the same max_dim (<= 1). */
+vrph_status vrph_batch_plan(vrph_ctx* ctx, const int64_t* sizes, int32_t count, int32_t m,
+                            int32_t max_dim, float threshold, uint32_t flags, vrph_batch** out);
+vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, void* hip_stream);
+/* Result of cloud i of the last forward; owned by the batch, valid until the
+ * next forward or vrph_batch_destroy. Vertex and edge numbers are local to
+ * the cloud. */
+vrph_status vrph_batch_result(vrph_batch* b, int32_t cloud, const vrph_barcode** view);
+void vrph_batch_destroy(vrph_batch* b);
+
+/* ---- backward (gradient of a loss on birth and death values) ---------------
+ * For pair p, edges[4p+0..1] is the diameter edge (u, v) of its birth simplex
+ * and edges[4p+2..3] that of its death simplex, as global point numbers into
+ * X (-1 = no edge: vertex birth or essential death). g_birth / g_death hold
+ * dL/d(birth value) and dL/d(death value). Since the value is |x_u - x_v|,
+ *   gX[u] += g (x_u - x_v) / |x_u - x_v|,  gX[v] -= the same,
+ * with nothing added for coincident points. gX (n_total x m) is accumulated
+ * into, with float32 atomics (summation order is not fixed). */
+vrph_status vrph_backward(vrph_ctx* ctx, const float* X, int64_t n_total, int32_t m,
+                          const int32_t* edges, int64_t npairs, const float* g_birth,
+                          const float* g_death, float* gX, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,800 @@
+// HIP kernels of the Vietoris–Rips hot path for gfx950 (wave64).
+//
+// Stages (Zhang, Ch. 5): distances (Def. 5.1.1), enclosing radius
+// (Sec. 5.2.12), H0 by a minimum spanning forest and union-find with the
+// elder rule (Sec. 5.2.5), and per dimension d >= 1 the enumeration of
+// d-simplices in the combinatorial number system (Eq. 5.6) with threshold
+// and clearing (Alg. 17) fused with the apparent-pairs test (Lemma 5.3.6,
+// Alg. 13). Every column is tested independently (Cor. 5.3.7) and clearing
+// does not change the apparent set (Prop. 5.3.9), so the test runs on the
+// enumerated candidates directly and only the few non-apparent columns are
+// compacted for the coboundary-order sort and the host reduction.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "vrph_internal.h"
+
+namespace vrph {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t float_key(float x) {
+  // +0.0 and -0.0 compare equal; give both the pattern of +0.0
+  return x == 0.0f ? 0u : __float_as_uint(x);
+}
+
+__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long x, int src) {
+  unsigned lo = (unsigned)x, hi = (unsigned)(x >> 32);
+  lo = __shfl(lo, src);
+  hi = __shfl(hi, src);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long x, int m) {
+  unsigned lo = (unsigned)x, hi = (unsigned)(x >> 32);
+  lo = __shfl_xor(lo, m);
+  hi = __shfl_xor(hi, m);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Edge index C(a,2) + b (a > b) and its inverse.
+__device__ __forceinline__ uint64_t edge_index(int a, int b) {
+  return (uint64_t)a * (uint64_t)(a - 1) / 2 + (uint64_t)b;
+}
+
+__device__ __forceinline__ void edge_vertices(uint64_t c, int& a, int& b) {
+  // largest a with a(a-1)/2 <= c, from the square root and a one-step fix-up
+  double r = sqrt(8.0 * (double)c + 1.0);
+  int64_t x = (int64_t)((1.0 + r) * 0.5);
+  while ((uint64_t)x * (uint64_t)(x - 1) / 2 > c) --x;
+  while ((uint64_t)(x + 1) * (uint64_t)x / 2 <= c) ++x;
+  a = (int)x;
+  b = (int)(c - (uint64_t)x * (uint64_t)(x - 1) / 2);
+}
+
+__device__ __forceinline__ int find_cloud(const Cloud* clouds, int count, int64_t key,
+                                          int64_t Cloud::*field) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (clouds[mid].*field <= key)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// fill
+// ---------------------------------------------------------------------------
+
+__global__ void fill_u32_kernel(uint32_t* p, int64_t count, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void init_states_kernel(CloudState* st, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    st[i].r_bits = kInf;
+    st[i].tau_bits = 0;
+    st[i].err = 0;
+    st[i].h0_count = 0;
+  }
+}
+
+hipError_t launch_init_states(CloudState* st, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  init_states_kernel<<<(count + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  fill_u32_kernel<<<(int)blocks, kBlock, 0, s>>>(p, count, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// distances (Def. 5.1.1): binary64 differences, squares, left-to-right sum and
+// square root, one rounding to float32 (compiled with -ffp-contract=off).
+// One workgroup per point (row); rows of all clouds are numbered together.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void batch_pdist_kernel(const float* __restrict__ X, int m,
+                                                             const Cloud* __restrict__ clouds,
+                                                             int count, float* __restrict__ D) {
+  const int64_t row = blockIdx.x;
+  const int c = find_cloud(clouds, count, row, &Cloud::x_off);
+  const Cloud cl = clouds[c];
+  const int i = (int)(row - cl.x_off);
+  const float* xi = X + (cl.x_off + i) * (int64_t)m;
+  for (int j = threadIdx.x; j < cl.n; j += blockDim.x) {
+    const float* xj = X + (cl.x_off + j) * (int64_t)m;
+    double s = 0.0;
+    for (int k = 0; k < m; ++k) {
+      double d = (double)xi[k] - (double)xj[k];
+      double sq = d * d;
+      s = s + sq;
+    }
+    D[cl.w_off + (int64_t)i * cl.n + j] = (float)sqrt(s);
+  }
+}
+
+hipError_t launch_batch_pdist(const float* X, int m, const Cloud* clouds, int count,
+                              int64_t total_points, float* D, hipStream_t s) {
+  if (total_points <= 0) return hipSuccess;
+  batch_pdist_kernel<<<(unsigned)total_points, kBlock, 0, s>>>(X, m, clouds, count, D);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// validation and enclosing radius (Sec. 5.2.12): R = min_i max_j D_ij.
+// Max and min are order-free, so the float-bit atomics are deterministic.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void batch_validate_kernel(const float* __restrict__ D,
+                                                                const Cloud* __restrict__ clouds,
+                                                                int count,
+                                                                CloudState* __restrict__ st) {
+  __shared__ uint32_t red[kBlock / 64];
+  __shared__ uint32_t errs;
+  const int64_t row = blockIdx.x;
+  const int c = find_cloud(clouds, count, row, &Cloud::x_off);
+  const Cloud cl = clouds[c];
+  const int i = (int)(row - cl.x_off);
+  const float* Drow = D + cl.w_off + (int64_t)i * cl.n;
+  if (threadIdx.x == 0) errs = 0;
+  __syncthreads();
+  uint32_t mx = 0, err = 0;
+  for (int j = threadIdx.x; j < cl.n; j += blockDim.x) {
+    float x = Drow[j];
+    if (!isfinite(x)) err |= 1u;
+    if (x < 0.0f) err |= 2u;
+    if (x != D[cl.w_off + (int64_t)j * cl.n + i]) err |= 4u;
+    if (j == i && x != 0.0f) err |= 8u;
+    uint32_t k = float_key(x);
+    if (isfinite(x) && x >= 0.0f && k > mx) mx = k;
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  if (err) atomicOr(&errs, err);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m2 = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m2 = max(m2, red[w]);
+    atomicMin(&st[c].r_bits, m2);
+    if (errs) atomicOr(&st[c].err, errs);
+  }
+}
+
+// Weights: W_ij = bits(D_ij) if i != j and D_ij <= tau_eff, else kInf.
+__global__ __launch_bounds__(kBlock) void batch_weights_kernel(const float* __restrict__ D,
+                                                               const Cloud* __restrict__ clouds,
+                                                               int count, int enclosing,
+                                                               uint32_t* __restrict__ W,
+                                                               CloudState* __restrict__ st) {
+  const int64_t row = blockIdx.x;
+  const int c = find_cloud(clouds, count, row, &Cloud::x_off);
+  const Cloud cl = clouds[c];
+  const int i = (int)(row - cl.x_off);
+  uint32_t tau = cl.tau_bits;
+  if (enclosing) tau = min(tau, st[c].r_bits);
+  if (i == 0 && threadIdx.x == 0) st[c].tau_bits = tau;
+  const float* Drow = D + cl.w_off + (int64_t)i * cl.n;
+  uint32_t* Wrow = W + cl.w_off + (int64_t)i * cl.n;
+  for (int j = threadIdx.x; j < cl.n; j += blockDim.x) {
+    uint32_t k = float_key(Drow[j]);
+    Wrow[j] = (j != i && k <= tau) ? k : kInf;
+  }
+}
+
+hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, int count,
+                                         int64_t total_points, bool enclosing, uint32_t* W,
+                                         CloudState* st, hipStream_t s) {
+  if (total_points <= 0) return hipSuccess;
+  batch_validate_kernel<<<(unsigned)total_points, kBlock, 0, s>>>(D, clouds, count, st);
+  batch_weights_kernel<<<(unsigned)total_points, kBlock, 0, s>>>(D, clouds, count,
+                                                                 enclosing ? 1 : 0, W, st);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// H0 (Sec. 5.2.5): the pairs of dimension 0 are the merges of Kruskal's
+// algorithm over the edges in filtration order, i.e. the edges of the minimum
+// spanning forest under that total order. One workgroup per cloud:
+//   1. Prim's algorithm builds the forest (edge key = diameter bits, then
+//      reversed edge index, so the minimum key is the oldest edge);
+//   2. a bitonic sort in LDS puts the forest edges in filtration order;
+//   3. one lane runs union-find with the elder rule: each component is
+//      represented by its oldest vertex (the largest index); a merge kills
+//      the component whose representative is younger.
+// The forest edges are the deaths of H0 pairs and are cleared for dim 1.
+// ---------------------------------------------------------------------------
+
+constexpr int kH0Threads = 256;
+
+__global__ __launch_bounds__(kH0Threads) void batch_h0_kernel(const uint32_t* __restrict__ W,
+                                                              const Cloud* __restrict__ clouds,
+                                                              CloudState* __restrict__ st,
+                                                              H0Pair* __restrict__ out,
+                                                              int64_t out_stride,
+                                                              uint32_t* __restrict__ bitmaps) {
+  __shared__ unsigned long long keyA[kMaxN];  // Prim keys, then parent/rep
+  __shared__ unsigned long long mst[kMaxN];
+  __shared__ unsigned long long redk[2][kH0Threads / 64];
+  __shared__ int redv[2][kH0Threads / 64];
+  constexpr unsigned long long kDone = 0ull;  // marks a vertex already in the forest
+  constexpr unsigned long long kNone = ~0ull; // no edge to the forest yet
+
+  const int c = blockIdx.x;
+  const Cloud cl = clouds[c];
+  const int n = cl.n;
+  const uint32_t* Wc = W + cl.w_off;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+
+  for (int v = tid; v < n; v += kH0Threads) keyA[v] = kNone;
+  __syncthreads();
+
+  int m = 0;  // forest edges so far (uniform across the workgroup)
+  for (int it = 0; it < n; ++it) {
+    // argmin over vertices not yet in the forest; among keys kNone (start of a
+    // new component) the largest vertex wins
+    unsigned long long bk = ~0ull;
+    int bv = -1;
+    for (int v = tid; v < n; v += kH0Threads) {
+      unsigned long long k = keyA[v];
+      if (k == kDone) continue;
+      if (bv < 0 || k < bk || (k == bk && v > bv)) {
+        bk = k;
+        bv = v;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      unsigned long long ok = shfl_xor_u64(bk, o);
+      int ov = __shfl_xor(bv, o);
+      if (ov >= 0 && (bv < 0 || ok < bk || (ok == bk && ov > bv))) {
+        bk = ok;
+        bv = ov;
+      }
+    }
+    const int buf = it & 1;
+    if (lane == 0) {
+      redk[buf][wave] = bk;
+      redv[buf][wave] = bv;
+    }
+    __syncthreads();
+    bk = redk[buf][0];
+    bv = redv[buf][0];
+    for (int w = 1; w < kH0Threads / 64; ++w) {
+      unsigned long long ok = redk[buf][w];
+      int ov = redv[buf][w];
+      if (ov >= 0 && (bv < 0 || ok < bk || (ok == bk && ov > bv))) {
+        bk = ok;
+        bv = ov;
+      }
+    }
+    const int u = bv;
+    if (bk != kNone) {
+      if (tid == 0) mst[m] = bk;
+      ++m;
+    }
+    // u joins the forest; its owner marks it, every owner relaxes its vertices
+    const uint32_t* Wu = Wc + (int64_t)u * n;
+    for (int v = tid; v < n; v += kH0Threads) {
+      if (v == u) {
+        keyA[v] = kDone;
+        continue;
+      }
+      unsigned long long k = keyA[v];
+      if (k == kDone) continue;
+      uint32_t w = Wu[v];
+      if (w == kInf) continue;
+      uint64_t e = u > v ? edge_index(u, v) : edge_index(v, u);
+      unsigned long long cand = ((unsigned long long)w << 32) | (0xFFFFFFFFu - (uint32_t)e);
+      if (cand < k) keyA[v] = cand;
+    }
+  }
+  __syncthreads();
+
+  // bitonic sort of the m forest edges, ascending (padding with ~0)
+  int P = 1;
+  while (P < m) P <<= 1;
+  for (int i = m + tid; i < P; i += kH0Threads) mst[i] = ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < P; i += kH0Threads) {
+        int l = i ^ j;
+        if (l > i) {
+          unsigned long long a = mst[i], b = mst[l];
+          bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            mst[i] = b;
+            mst[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // the forest edges are H0 deaths: clear them for dimension 1
+  uint32_t* bm = bitmaps + cl.bm_off;
+  for (int i = tid; i < m; i += kH0Threads) {
+    uint32_t e = 0xFFFFFFFFu - (uint32_t)mst[i];
+    atomicOr(&bm[e >> 5], 1u << (e & 31));
+  }
+
+  // union-find with the elder rule, one lane
+  int* parent = reinterpret_cast<int*>(keyA);
+  int* rep = parent + kMaxN;
+  for (int v = tid; v < n; v += kH0Threads) {
+    parent[v] = v;
+    rep[v] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    H0Pair* o = out + (int64_t)c * out_stride;
+    int k = 0;
+    for (int i = 0; i < m; ++i) {
+      unsigned long long key = mst[i];
+      uint64_t e = 0xFFFFFFFFu - (uint32_t)key;
+      int a, b;
+      edge_vertices(e, a, b);
+      int ra = a, rb = b;
+      while (parent[ra] != ra) {
+        parent[ra] = parent[parent[ra]];
+        ra = parent[ra];
+      }
+      while (parent[rb] != rb) {
+        parent[rb] = parent[parent[rb]];
+        rb = parent[rb];
+      }
+      int young = rep[ra] < rep[rb] ? ra : rb;
+      int old = young == ra ? rb : ra;
+      o[k].death = e;
+      o[k].birth = (uint32_t)rep[young];
+      o[k].diam = (uint32_t)(key >> 32);
+      ++k;
+      parent[young] = old;
+    }
+    for (int v = 0; v < n; ++v)
+      if (parent[v] == v) {
+        o[k].death = ~0ull;
+        o[k].birth = (uint32_t)rep[v];
+        o[k].diam = kInf;
+        ++k;
+      }
+    st[c].h0_count = (uint32_t)k;
+  }
+}
+
+hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, CloudState* st,
+                           H0Pair* out, int64_t out_stride, uint32_t* bitmaps, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  batch_h0_kernel<<<count, kH0Threads, 0, s>>>(W, clouds, st, out, out_stride, bitmaps);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The apparent-pairs test of one column (Lemma 5.3.6, Alg. 13).
+//
+// s has vertices v[D] > ... > v[0], pairwise weights pw and diameter diam.
+// Condition 1: t is the lexicographically greatest cofacet with diam(t) =
+// diam(s): scanning the added vertex x from n-1 down (cofacet indices
+// decrease with x, Alg. 14), the first x with max_i W(v_i, x) <= diam.
+// Condition 2: no facet of t with a smaller index than s has the same
+// diameter. The facets below s are t minus a vertex u > x (Alg. 16: removing
+// a higher vertex gives a smaller index). If no cofacet keeps the diameter,
+// s is not apparent. Returns the added vertex x, or -1 if s is not apparent.
+// ---------------------------------------------------------------------------
+
+template <int D>
+__device__ __forceinline__ int apparent_cofacet(const uint32_t* __restrict__ W, int n,
+                                                const int (&v)[D + 1],
+                                                const uint32_t (&pw)[D + 1][D + 1],
+                                                uint32_t diam, unsigned long long& steps) {
+  uint32_t mv[D + 1];
+  int pos = D;
+  int x = n - 1;
+  for (; x >= 0; --x) {
+    if (pos >= 0 && x == v[pos]) {
+      --pos;
+      continue;
+    }
+    ++steps;
+    uint32_t mx = 0;
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+      mv[i] = W[(int64_t)v[i] * n + x];
+      mx = max(mx, mv[i]);
+    }
+    if (mx <= diam) break;
+  }
+  if (x < 0) return -1;
+#pragma unroll
+  for (int u = 0; u <= D; ++u) {
+    if (v[u] < x) continue;
+    uint32_t mx = 0;
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+      if (i == u) continue;
+      mx = max(mx, mv[i]);
+#pragma unroll
+      for (int j = 0; j < i; ++j)
+        if (j != u) mx = max(mx, pw[i][j]);
+    }
+    if (mx == diam) return -1;
+  }
+  return x;
+}
+
+// Index of the cofacet s + {x} (Eq. 5.6): vertices above x move up one position.
+template <int D>
+__device__ __forceinline__ uint64_t cofacet_index(const int (&v)[D + 1], int x,
+                                                  const uint64_t* __restrict__ binom, int np1) {
+  uint64_t c = 0;
+  int p = D + 1;
+  bool placed = false;
+#pragma unroll
+  for (int i = D; i >= 0; --i) {
+    if (!placed && x > v[i]) {
+      c += binom[(p + 1) * np1 + x];
+      --p;
+      placed = true;
+    }
+    c += binom[(p + 1) * np1 + v[i]];
+    --p;
+  }
+  if (!placed) c += (uint64_t)x;  // C(x, 1)
+  return c;
+}
+
+// Wave-aggregated append: every active lane with `take` gets a distinct slot
+// from one atomic per wave. All lanes of the wave must call it together.
+__device__ __forceinline__ uint64_t wave_append(bool take, unsigned long long* counter,
+                                                bool& any) {
+  const unsigned long long mask = __ballot(take);
+  any = mask != 0;
+  if (!any) return 0;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+  base = shfl_u64(base, leader);
+  const unsigned long long below = lane ? (mask & ((~0ull) >> (64 - lane))) : 0ull;
+  return base + (uint64_t)__popcll(below);
+}
+
+// ---------------------------------------------------------------------------
+// Dimension-d enumeration + threshold + clearing + apparent test, one cloud.
+// Thread <-> candidate index c in [0, C(n, d+1)) (Alg. 17 launches one thread
+// per index). The candidate is decoded from Eq. 5.6 by binary search in the
+// LDS-resident binomial table, its diameter is the largest pairwise weight.
+// Outputs: non-apparent columns (compacted, any order; the sort that follows
+// makes the order canonical), the clearing bits of the apparent cofacets for
+// dimension d+1, counts, and optionally every apparent pair.
+// ---------------------------------------------------------------------------
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
+    const uint32_t* __restrict__ W, int n, const uint64_t* __restrict__ binom_g, int kmax,
+    uint64_t ncand, const uint32_t* __restrict__ clear_in, uint32_t* __restrict__ clear_out,
+    Column* __restrict__ cols, uint64_t cols_cap, ApparentPair* __restrict__ ap, uint64_t ap_cap,
+    Scalars* __restrict__ sc, int use_lds) {
+  extern __shared__ uint64_t lds_binom[];  // (D + 3) x (n + 1), k-major
+  const int np1 = n + 1;
+  const uint64_t* binom = binom_g;
+  if (use_lds) {
+    for (int i = threadIdx.x; i < (D + 3) * np1; i += blockDim.x) lds_binom[i] = binom_g[i];
+    __syncthreads();
+    binom = lds_binom;
+  }
+
+  unsigned long long n_cols = 0, n_app = 0, n_steps = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < ncand; base += stride) {
+    const uint64_t c = base + threadIdx.x;
+    bool is_col = false, is_app = false;
+    int v[D + 1];
+    uint32_t pw[D + 1][D + 1];
+    uint32_t diam = kInf;
+    uint64_t t = 0;
+    if (c < ncand) {
+      // decode: position i holds the largest v with C(v, i+1) <= remainder
+      uint64_t rem = c;
+      int hi = n - 1;
+#pragma unroll
+      for (int i = D; i >= 1; --i) {
+        const uint64_t* col = binom + (i + 1) * np1;
+        int lo = i, h = hi;
+        while (lo < h) {
+          int mid = (lo + h + 1) >> 1;
+          if (col[mid] <= rem)
+            lo = mid;
+          else
+            h = mid - 1;
+        }
+        v[i] = lo;
+        rem -= col[lo];
+        hi = lo - 1;
+      }
+      v[0] = (int)rem;
+      diam = 0;
+#pragma unroll
+      for (int i = 1; i <= D; ++i)
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+          pw[i][j] = W[(int64_t)v[i] * n + v[j]];
+          diam = max(diam, pw[i][j]);
+        }
+      const bool cleared = clear_in && ((clear_in[c >> 5] >> (c & 31)) & 1u);
+      is_col = diam != kInf && !cleared;
+      if (is_col) {
+        ++n_cols;
+        const int x = apparent_cofacet<D>(W, n, v, pw, diam, n_steps);
+        if (x >= 0) {
+          is_app = true;
+          ++n_app;
+          t = cofacet_index<D>(v, x, binom, np1);
+          if (clear_out) atomicOr(&clear_out[t >> 5], 1u << (t & 31));
+        }
+      }
+    }
+    bool any;
+    const uint64_t slot = wave_append(is_col && !is_app, &sc->nonapparent, any);
+    if (is_col && !is_app && slot < cols_cap) {
+      Column r;
+      r.key_hi = ~diam;
+      r.cloud = 0;
+      r.cidx = c;
+      cols[slot] = r;
+    }
+    if (ap) {
+      const uint64_t as = wave_append(is_app, &sc->apparent_written, any);
+      if (is_app && as < ap_cap) {
+        ApparentPair p;
+        p.s = c;
+        p.t = t;
+        p.diam = diam;
+        p.cloud = 0;
+        ap[as] = p;
+      }
+    }
+  }
+  // workgroup totals, one atomic each
+  __shared__ unsigned long long red[3][kBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) {
+    n_cols += shfl_xor_u64(n_cols, o);
+    n_app += shfl_xor_u64(n_app, o);
+    n_steps += shfl_xor_u64(n_steps, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = n_cols;
+    red[1][threadIdx.x >> 6] = n_app;
+    red[2][threadIdx.x >> 6] = n_steps;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long a = 0, b = 0, c3 = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      a += red[0][w];
+      b += red[1][w];
+      c3 += red[2][w];
+    }
+    atomicAdd(&sc->columns, a);
+    atomicAdd(&sc->apparent, b);
+    atomicAdd(&sc->scan_steps, c3);
+  }
+}
+
+template <int D>
+static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom, int kmax,
+                                uint64_t ncand, const uint32_t* clear_in, uint32_t* clear_out,
+                                Column* cols, uint64_t cols_cap, ApparentPair* ap,
+                                uint64_t ap_cap, Scalars* sc, hipStream_t s, int grid) {
+  // the binomial columns 0..D+2 live in LDS when they fit in 48 KiB
+  size_t lds = (size_t)(D + 3) * (size_t)(n + 1) * sizeof(uint64_t);
+  const int use_lds = lds <= 48 * 1024;
+  enum_apparent_kernel<D><<<grid, kBlock, use_lds ? lds : 0, s>>>(
+      W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, use_lds);
+  return hipGetLastError();
+}
+
+hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int kmax,
+                                uint64_t ncand, const uint32_t* clear_in, uint32_t* clear_out,
+                                Column* cols, uint64_t cols_cap, ApparentPair* ap,
+                                uint64_t ap_cap, Scalars* sc, int grid, hipStream_t s) {
+  if (ncand == 0) return hipSuccess;
+  uint64_t need = (ncand + kBlock - 1) / kBlock;
+  if ((uint64_t)grid > need) grid = (int)need;
+  switch (d) {
+    case 1: return launch_enum_D<1>(W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s, grid);
+    case 2: return launch_enum_D<2>(W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s, grid);
+    case 3: return launch_enum_D<3>(W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s, grid);
+    case 4: return launch_enum_D<4>(W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s, grid);
+    case 5: return launch_enum_D<5>(W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s, grid);
+    case 6: return launch_enum_D<6>(W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s, grid);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dimension-1 columns of a batch of clouds: thread <-> edge of some cloud.
+// The edge index of a cloud is C(a,2)+b; the edge is a column iff its weight
+// is finite (<= tau_eff) and it is not a forest edge (cleared by H0).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void batch_edges_kernel(
+    const uint32_t* __restrict__ W, const Cloud* __restrict__ clouds, int count,
+    int64_t total_edges, const uint32_t* __restrict__ bitmaps, Column* __restrict__ cols,
+    uint64_t cols_cap, ApparentPair* __restrict__ ap, uint64_t ap_cap, uint32_t* __restrict__ clear_out,
+    const uint64_t* __restrict__ binom_g, int np1, unsigned long long* __restrict__ counters) {
+  unsigned long long n_cols = 0, n_app = 0, n_steps = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total_edges; base += stride) {
+    const int64_t e = base + threadIdx.x;
+    bool is_col = false, is_app = false;
+    uint32_t diam = kInf;
+    uint64_t le = 0, t = 0;
+    int cidx_cloud = 0;
+    if (e < total_edges) {
+      const int c = find_cloud(clouds, count, e, &Cloud::e_off);
+      const Cloud cl = clouds[c];
+      cidx_cloud = c;
+      le = (uint64_t)(e - cl.e_off);
+      int a, b;
+      edge_vertices(le, a, b);
+      const uint32_t* Wc = W + cl.w_off;
+      diam = Wc[(int64_t)a * cl.n + b];
+      const bool cleared = (bitmaps[cl.bm_off + (le >> 5)] >> (le & 31)) & 1u;
+      is_col = diam != kInf && !cleared;
+      if (is_col) {
+        ++n_cols;
+        int v[2] = {b, a};
+        uint32_t pw[2][2];
+        pw[1][0] = diam;
+        const int x = apparent_cofacet<1>(Wc, cl.n, v, pw, diam, n_steps);
+        if (x >= 0) {
+          is_app = true;
+          ++n_app;
+          // triangle index of {x, a, b} (Eq. 5.6)
+          int hi = max(x, a), lo = min(x, b), mid = x + a + b - hi - lo;
+          t = (uint64_t)hi * (hi - 1) * (hi - 2) / 6 + (uint64_t)mid * (mid - 1) / 2 + (uint64_t)lo;
+          if (clear_out) atomicOr(&clear_out[t >> 5], 1u << (t & 31));
+        }
+      }
+    }
+    bool any;
+    const uint64_t slot = wave_append(is_col && !is_app, &counters[2], any);
+    if (is_col && !is_app && slot < cols_cap) {
+      Column r;
+      r.key_hi = ~diam;
+      r.cloud = (uint32_t)cidx_cloud;
+      r.cidx = le;
+      cols[slot] = r;
+    }
+    if (ap) {
+      const uint64_t as = wave_append(is_app, &counters[4], any);
+      if (is_app && as < ap_cap) {
+        ApparentPair p;
+        p.s = le;
+        p.t = t;
+        p.diam = diam;
+        p.cloud = (uint32_t)cidx_cloud;
+        ap[as] = p;
+      }
+    }
+  }
+  __shared__ unsigned long long red[3][kBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) {
+    n_cols += shfl_xor_u64(n_cols, o);
+    n_app += shfl_xor_u64(n_app, o);
+    n_steps += shfl_xor_u64(n_steps, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = n_cols;
+    red[1][threadIdx.x >> 6] = n_app;
+    red[2][threadIdx.x >> 6] = n_steps;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long a = 0, b = 0, c3 = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      a += red[0][w];
+      b += red[1][w];
+      c3 += red[2][w];
+    }
+    atomicAdd(&counters[0], a);
+    atomicAdd(&counters[1], b);
+    atomicAdd(&counters[5], c3);
+  }
+  (void)binom_g;
+  (void)np1;
+}
+
+hipError_t launch_batch_edges(const uint32_t* W, const Cloud* clouds, int count,
+                              int64_t total_edges, const uint32_t* bitmaps, Column* cols,
+                              uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
+                              uint32_t* clear_out, unsigned long long* counters, int grid,
+                              hipStream_t s) {
+  if (total_edges <= 0) return hipSuccess;
+  int64_t need = (total_edges + kBlock - 1) / kBlock;
+  if (grid > need) grid = (int)need;
+  batch_edges_kernel<<<grid, kBlock, 0, s>>>(W, clouds, count, total_edges, bitmaps, cols,
+                                             cols_cap, ap, ap_cap, clear_out, nullptr, 0,
+                                             counters);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// set clearing bits for the deaths found by the host reduction
+// ---------------------------------------------------------------------------
+
+__global__ void set_bits_kernel(const uint64_t* __restrict__ idx, int64_t count,
+                                uint32_t* __restrict__ bitmap) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t t = idx[i];
+    atomicOr(&bitmap[t >> 5], 1u << (t & 31));
+  }
+}
+
+hipError_t launch_set_bits(const uint64_t* idx, int64_t count, uint32_t* bitmap, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + kBlock - 1) / kBlock;
+  if (blocks > 1024) blocks = 1024;
+  set_bits_kernel<<<(int)blocks, kBlock, 0, s>>>(idx, count, bitmap);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// backward: scatter dL/d(value) onto the two points of each diameter edge
+// ---------------------------------------------------------------------------
+
+__global__ void backward_kernel(const float* __restrict__ X, int m,
+                                const int32_t* __restrict__ edges, int64_t npairs,
+                                const float* __restrict__ g_birth,
+                                const float* __restrict__ g_death, float* __restrict__ gX) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < 2 * npairs;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = q >> 1;
+    const int which = (int)(q & 1);  // 0 birth, 1 death
+    const int u = edges[4 * p + 2 * which], v = edges[4 * p + 2 * which + 1];
+    const float g = which ? g_death[p] : g_birth[p];
+    if (u < 0 || v < 0 || g == 0.0f) continue;
+    const float* xu = X + (int64_t)u * m;
+    const float* xv = X + (int64_t)v * m;
+    float s = 0.0f;
+    for (int k = 0; k < m; ++k) {
+      float d = xu[k] - xv[k];
+      s += d * d;
+    }
+    if (s == 0.0f) continue;
+    const float scale = g / sqrtf(s);
+    for (int k = 0; k < m; ++k) {
+      float d = (xu[k] - xv[k]) * scale;
+      atomicAdd(&gX[(int64_t)u * m + k], d);
+      atomicAdd(&gX[(int64_t)v * m + k], -d);
+    }
+  }
+}
+
+hipError_t launch_backward(const float* X, int m, const int32_t* edges, int64_t npairs,
+                           const float* g_birth, const float* g_death, float* gX, hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  int64_t blocks = (2 * npairs + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  backward_kernel<<<(int)blocks, kBlock, 0, s>>>(X, m, edges, npairs, g_birth, g_death, gX);
+  return hipGetLastError();
+}
+
+}  // namespace vrph

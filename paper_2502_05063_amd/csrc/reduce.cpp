@@ -1,0 +1,329 @@
+// Host submatrix reduction (Sec. 5.2.9, 5.5.1) over the columns the GPU
+// found non-apparent. Columns of the dimension-d coboundary matrix are
+// d-simplices in coboundary order (diameter descending, index ascending);
+// rows are (d+1)-simplices in the same order. A row is represented by a
+// 128-bit key (~diameter, index): increasing key = increasing row index, so
+// the lowest nonzero of a column (its pivot, the oldest cofacet) is the
+// largest key.
+#include "reduce.h"
+
+#include <algorithm>
+#include <unordered_map>
+
+namespace vrph {
+
+using u128 = unsigned __int128;
+
+static inline u128 row_key(uint32_t diam, uint64_t c) {
+  return ((u128)(uint32_t)~diam << 64) | (u128)c;
+}
+static inline uint64_t key_index(u128 k) { return (uint64_t)k; }
+static inline uint32_t key_diam(u128 k) { return ~(uint32_t)(k >> 64); }
+
+void decode_simplex(const HostComplex& H, uint64_t c, int d, int* v) {
+  int hi = H.n - 1;
+  for (int i = d; i >= 1; --i) {
+    int lo = i, h = hi;
+    while (lo < h) {
+      int mid = (lo + h + 1) >> 1;
+      if (H.C(mid, i + 1) <= c)
+        lo = mid;
+      else
+        h = mid - 1;
+    }
+    v[i] = lo;
+    c -= H.C(lo, i + 1);
+    hi = lo - 1;
+  }
+  v[0] = (int)c;
+}
+
+static uint32_t diameter_of(const HostComplex& H, const int* v, int d) {
+  uint32_t m = 0;
+  for (int i = 1; i <= d; ++i)
+    for (int j = 0; j < i; ++j) m = std::max(m, H.w(v[i], v[j]));
+  return m;
+}
+
+void diameter_edge(const HostComplex& H, uint64_t c, int d, int32_t* u, int32_t* w) {
+  int v[kMaxDim + 3];
+  decode_simplex(H, c, d, v);
+  uint32_t dm = diameter_of(H, v, d);
+  uint64_t best = 0;
+  bool have = false;
+  for (int i = 1; i <= d; ++i)
+    for (int j = 0; j < i; ++j)
+      if (H.w(v[i], v[j]) == dm) {
+        uint64_t e = H.C(v[i], 2) + (uint64_t)v[j];
+        if (!have || e > best) {
+          best = e;
+          *u = v[i];
+          *w = v[j];
+          have = true;
+        }
+      }
+}
+
+// index of s + {x} (Eq. 5.6); vertices above x move up one position
+static uint64_t cofacet_index(const HostComplex& H, const int* v, int d, int x) {
+  uint64_t c = 0;
+  int p = d + 1;
+  bool placed = false;
+  for (int i = d; i >= 0; --i) {
+    if (!placed && x > v[i]) {
+      c += H.C(x, p + 1);
+      --p;
+      placed = true;
+    }
+    c += H.C(v[i], p + 1);
+    --p;
+  }
+  if (!placed) c += (uint64_t)x;
+  return c;
+}
+
+// max over the vertices of s of W(v_i, x); kInf if some edge is above tau_eff
+static inline uint32_t reach(const HostComplex& H, const int* v, int d, int x) {
+  uint32_t m = 0;
+  for (int i = 0; i <= d; ++i) m = std::max(m, H.w(v[i], x));
+  return m;
+}
+
+static inline bool contains(const int* v, int d, int x) {
+  for (int i = 0; i <= d; ++i)
+    if (v[i] == x) return true;
+  return false;
+}
+
+// low(D_s): the oldest cofacet = smallest diameter, then largest index. The
+// first x from the top whose cofacet keeps the diameter is it; otherwise the
+// largest key over all cofacets.
+static bool oldest_cofacet(const HostComplex& H, const int* v, int d, uint32_t diam, u128* low) {
+  bool found = false;
+  for (int x = H.n - 1; x >= 0; --x) {
+    if (contains(v, d, x)) continue;
+    uint32_t m = reach(H, v, d, x);
+    if (m == kInf) continue;
+    u128 k = row_key(std::max(diam, m), cofacet_index(H, v, d, x));
+    if (!found || k > *low) *low = k;
+    found = true;
+    if (m <= diam) break;
+  }
+  return found;
+}
+
+// If row t (a (d+1)-simplex) is the cofacet of an apparent pair (s, t),
+// return s. Def. 5.3.4: s is the youngest facet of t (largest diameter, then
+// smallest index: remove the largest vertex u whose removal keeps diam(t)),
+// and t is the oldest cofacet of s (no x > u outside s keeps the diameter).
+static bool apparent_partner(const HostComplex& H, uint64_t t, uint32_t dt, int d, uint64_t* s,
+                             int* sv) {
+  int tv[kMaxDim + 3];
+  decode_simplex(H, t, d + 1, tv);
+  int drop = -1;
+  for (int r = d + 1; r >= 0; --r) {  // vertices from the largest down
+    uint32_t m = 0;
+    for (int i = 1; i <= d + 1; ++i)
+      for (int j = 0; j < i; ++j)
+        if (i != r && j != r) m = std::max(m, H.w(tv[i], tv[j]));
+    if (m == dt) {
+      drop = r;
+      break;
+    }
+  }
+  if (drop < 0) return false;
+  int k = 0;
+  for (int i = 0; i <= d + 1; ++i)
+    if (i != drop) sv[k++] = tv[i];
+  const int u = tv[drop];
+  for (int x = H.n - 1; x > u; --x) {
+    if (contains(sv, d, x)) continue;
+    if (reach(H, sv, d, x) <= dt) return false;
+  }
+  uint64_t c = 0;
+  for (int i = 0; i <= d; ++i) c += H.C(sv[i], i + 1);
+  *s = c;
+  return true;
+}
+
+// A column in the pivot store: its simplex and, for a column reduced here,
+// the other columns whose sum with it is its reduced column (the V column of
+// the reduction-matrix technique, R = D V, Sec. 5.2.9). Apparent columns and
+// columns paired at their first pivot need no additions: their reduced column
+// is their coboundary (v = -1).
+struct Partner {
+  uint64_t c;
+  uint32_t diam;
+  int32_t v;  // index into the stored V columns, -1 for none
+};
+
+struct Simplex {
+  uint64_t c;
+  uint32_t diam;
+  bool operator<(const Simplex& o) const { return c < o.c; }
+  bool operator==(const Simplex& o) const { return c == o.c; }
+};
+
+// The working column: a monotone max-priority queue of row keys (a radix
+// heap). Every key pushed is <= the current pivot and pivots only decrease,
+// so a key lives in the bucket of the highest bit where it differs from the
+// last extracted maximum; bucket 0 holds copies of that maximum, and since
+// equal keys cancel in pairs over Z/2 the maximum survives iff bucket 0 has
+// odd size.
+class WorkColumn {
+ public:
+  void clear() {
+    for (auto& b : b_) b.clear();
+    last_ = ~(u128)0;
+  }
+  void push(u128 k) { b_[bucket(k)].push_back(k); }
+  // the pivot (largest key of odd multiplicity), kept; false if zero
+  bool pivot(u128* k) {
+    for (;;) {
+      if (b_[0].empty() && !refill()) return false;
+      if (b_[0].size() & 1) {
+        b_[0].resize(1);
+        *k = last_;
+        return true;
+      }
+      b_[0].clear();
+    }
+  }
+
+ private:
+  static int high_bit(u128 x) {  // index of the highest set bit, x != 0
+    const uint64_t hi = (uint64_t)(x >> 64), lo = (uint64_t)x;
+    return hi ? 127 - __builtin_clzll(hi) : 63 - __builtin_clzll(lo);
+  }
+  int bucket(u128 k) const { return k == last_ ? 0 : high_bit(k ^ last_) + 1; }
+  bool refill() {
+    int i = 1;
+    while (i < 129 && b_[i].empty()) ++i;
+    if (i == 129) return false;
+    std::vector<u128>& src = b_[i];
+    u128 m = src[0];
+    for (u128 x : src) m = x > m ? x : m;
+    last_ = m;
+    std::vector<u128> moved;
+    moved.swap(src);
+    for (u128 x : moved) b_[bucket(x)].push_back(x);
+    moved.clear();
+    moved.swap(src);  // keep the capacity
+    return true;
+  }
+  std::vector<u128> b_[129];
+  u128 last_ = ~(u128)0;
+};
+
+// Push the cofacets of one column with row key <= limit. Used to add a
+// reduced column R_k whose pivot is `limit`: R_k is zero below its pivot, so
+// the parts of its summands below the pivot cancel and are not pushed.
+// Cofacets s + {x} come in decreasing index order as x goes down (Alg. 14);
+// the index is kept incrementally: vertices of s above x contribute
+// C(v_i, i+2) (they moved up one position), those below C(v_i, i+1), and x
+// itself C(x, j+1) with j the number of vertices below it.
+static void push_coboundary(const HostComplex& H, uint64_t c, uint32_t diam, int d, u128 limit,
+                            WorkColumn& w) {
+  int v[kMaxDim + 3];
+  decode_simplex(H, c, d, v);
+  uint64_t high = 0, low = c;
+  int pos = d;  // vertices v[pos+1..d] are above x
+  const uint32_t* Wv[kMaxDim + 3];
+  for (int i = 0; i <= d; ++i) Wv[i] = H.W + (size_t)v[i] * (size_t)H.n;
+  for (int x = H.n - 1; x >= 0; --x) {
+    if (pos >= 0 && x == v[pos]) {
+      high += H.C(v[pos], pos + 2);
+      low -= H.C(v[pos], pos + 1);
+      --pos;
+      continue;
+    }
+    uint32_t m = 0;
+    for (int i = 0; i <= d; ++i) m = std::max(m, Wv[i][x]);
+    if (m == kInf) continue;
+    const u128 k = row_key(std::max(diam, m), high + H.C(x, pos + 2) + low);
+    if (k <= limit) w.push(k);
+  }
+}
+
+void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,
+                      std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
+                      ReduceStats& stats) {
+  std::unordered_map<uint64_t, Partner> pivots;  // row index -> column, this dimension
+  pivots.reserve((size_t)ncols * 2 + 16);
+  std::vector<std::vector<Simplex>> vstore;       // V columns of the reduced columns
+  WorkColumn work;
+  std::vector<Simplex> vj;
+  int v[kMaxDim + 3], pv[kMaxDim + 3];
+
+  // two-layer lookup (Fig. 5.10): pairs found by this reduction first, then
+  // the apparent pairs, recognised from Def. 5.3.4 instead of a stored array
+  auto lookup = [&](u128 row, Partner* p) -> bool {
+    auto it = pivots.find(key_index(row));
+    if (it != pivots.end()) {
+      *p = it->second;
+      return true;
+    }
+    uint64_t s;
+    if (apparent_partner(H, key_index(row), key_diam(row), d, &s, pv)) {
+      *p = Partner{s, key_diam(row), -1};
+      return true;
+    }
+    return false;
+  };
+
+  for (int64_t j = 0; j < ncols; ++j) {
+    const uint64_t c = cols[j].cidx;
+    const uint32_t diam = ~cols[j].key_hi;
+    decode_simplex(H, c, d, v);
+    u128 low;
+    Partner p;
+    bool nonzero = oldest_cofacet(H, v, d, diam, &low);
+    vj.clear();
+    if (nonzero && lookup(low, &p)) {
+      // Alg. 2 on column j: while its pivot is the pivot of an earlier column
+      // k, add R_k = D_k + sum_{i in V_k} D_i (the pivot then moves up)
+      work.clear();
+      push_coboundary(H, c, diam, d, low, work);
+      for (;;) {
+        push_coboundary(H, p.c, p.diam, d, low, work);
+        vj.push_back(Simplex{p.c, p.diam});
+        if (p.v >= 0)
+          for (const Simplex& q : vstore[p.v]) {
+            push_coboundary(H, q.c, q.diam, d, low, work);
+            vj.push_back(q);
+          }
+        ++stats.additions;
+        if (!work.pivot(&low)) {
+          nonzero = false;
+          break;
+        }
+        if (!lookup(low, &p)) break;
+      }
+    } else if (nonzero) {
+      ++stats.emergent;
+    }
+    if (nonzero) {
+      int32_t vi = -1;
+      if (!vj.empty()) {
+        // V over Z/2: a column added twice cancels
+        std::sort(vj.begin(), vj.end());
+        std::vector<Simplex> red;
+        for (size_t a = 0; a < vj.size();) {
+          size_t b = a;
+          while (b < vj.size() && vj[b] == vj[a]) ++b;
+          if ((b - a) & 1) red.push_back(vj[a]);
+          a = b;
+        }
+        vi = (int32_t)vstore.size();
+        vstore.push_back(std::move(red));
+      }
+      pivots.emplace(key_index(low), Partner{c, diam, vi});
+      pairs.push_back(PairRec{c, key_index(low), diam, key_diam(low)});
+      deaths.push_back(key_index(low));
+    } else {
+      pairs.push_back(PairRec{c, ~0ull, diam, kInf});
+    }
+  }
+}
+
+}  // namespace vrph

@@ -1,0 +1,50 @@
+// Host submatrix reduction over the non-apparent columns (Sec. 5.5.1).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "vrph_internal.h"
+
+namespace vrph {
+
+// Read-only view of one cloud's filtration data on the host.
+struct HostComplex {
+  int n = 0;
+  const uint32_t* W = nullptr;      // n x n weights (float bits, kInf above tau_eff)
+  const uint64_t* binom = nullptr;  // k-major binomial table, (kmax + 1) x (n + 1)
+  int kmax = 0;
+  uint64_t C(int v, int k) const { return binom[(size_t)k * (size_t)(n + 1) + (size_t)v]; }
+  uint32_t w(int a, int b) const { return W[(size_t)a * (size_t)n + (size_t)b]; }
+};
+
+struct PairRec {
+  uint64_t birth, death;  // death = ~0 for an essential class
+  uint32_t bdiam, ddiam;  // float bits; ddiam = kInf for an essential class
+};
+
+struct ReduceStats {
+  int64_t additions = 0;
+  int64_t emergent = 0;  // columns paired without building them (their first pivot was free)
+};
+
+// Reduce the non-apparent columns of dimension d, given in coboundary order,
+// with the reduction-matrix technique (Sec. 5.2.9: R = D V; a column adds the
+// reduced columns of earlier pivots, so its pivot only moves up; the working
+// column is a lazy max-heap). A column whose first pivot is free is paired
+// without building it (the emergent case of Sec. 5.2.11). Pivot lookups go to a hash map of the pairs found so far,
+// then to the apparent pairs, recognised on the fly from Def. 5.3.4 instead
+// of a stored array. Appends the pairs of dimension d
+// to `pairs` and the death indices to `deaths`.
+void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,
+                      std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
+                      ReduceStats& stats);
+
+// Vertices v[d] > ... > v[0] of simplex `c` of dimension d (Eq. 5.6).
+void decode_simplex(const HostComplex& H, uint64_t c, int d, int* v);
+
+// Diameter edge (u > v) of simplex c of dimension d >= 1: among the longest
+// edges, the one with the largest edge index.
+void diameter_edge(const HostComplex& H, uint64_t c, int d, int32_t* u, int32_t* v);
+
+}  // namespace vrph

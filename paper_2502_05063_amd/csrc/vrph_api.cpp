@@ -1,0 +1,806 @@
+// C ABI of the library (include/vrph.h): argument checks, device workspaces,
+// the per-dimension pipeline, result assembly and the batched path.
+#include "vrph.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "reduce.h"
+#include "vrph_internal.h"
+
+
+using namespace vrph;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_last_error;
+
+static vrph_status fail(vrph_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? VRPH_ENOMEM : VRPH_EDEVICE,                 \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                     \
+  } while (0)
+
+extern "C" const char* vrph_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// buffers
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap && p) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) cap = want;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+struct HostPinned {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap && p) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e == hipSuccess) cap = want;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+using u128 = unsigned __int128;
+
+// k-major table C(v, k), v <= n, k <= kmax, by Pascal's rule; false if some
+// entry reaches 2^63.
+bool binomial_table(int n, int kmax, std::vector<uint64_t>& t) {
+  t.assign((size_t)(kmax + 1) * (size_t)(n + 1), 0);
+  std::vector<u128> prev(kmax + 1, 0), cur(kmax + 1, 0);
+  const u128 lim = (u128)1 << 63;
+  bool ok = true;
+  for (int v = 0; v <= n; ++v) {
+    for (int k = 0; k <= kmax; ++k) {
+      u128 x = (k == 0) ? 1 : (v == 0 ? 0 : prev[k - 1] + prev[k]);
+      if (x >= lim) {
+        ok = false;
+        x = lim;
+      }
+      cur[k] = x;
+      t[(size_t)k * (n + 1) + v] = (uint64_t)x;
+    }
+    prev.swap(cur);
+  }
+  return ok;
+}
+
+uint32_t fbits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return f == 0.0f ? 0u : u;
+}
+
+float bitsf(uint32_t u) {
+  if (u == kInf) return INFINITY;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+int bits_needed(uint64_t x) {
+  int b = 0;
+  while (b < 64 && (x >> b) != 0) ++b;
+  return b;
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context and results
+// ---------------------------------------------------------------------------
+
+struct vrph_ctx {
+  int device = 0;
+  int num_cus = 256;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  DevBuf D, W, binom, bitmaps, cols, cols_tmp, sort_work, ap, scal, clouds, cstate, h0, deaths;
+  HostPinned h_scal, h_cstate;
+  std::vector<uint64_t> h_binom;
+  int binom_n = -1, binom_k = -1;
+};
+
+struct vrph_barcode {
+  std::vector<vrph_pair> pairs;  // canonical order
+  int64_t off[VRPH_MAX_DIM + 3] = {0};
+  vrph_stats stats;
+};
+
+extern "C" vrph_status vrph_create(int device, vrph_ctx** out) {
+  if (!out) return fail(VRPH_EINVAL, "vrph_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(VRPH_EINVAL, "vrph_create: no such device");
+  HIP_TRY(hipSetDevice(device));
+  std::unique_ptr<vrph_ctx> c(new (std::nothrow) vrph_ctx());
+  if (!c) return fail(VRPH_ENOMEM, "vrph_create: out of host memory");
+  c->device = device;
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  // a blocking stream: ordered against the legacy default stream, which is where
+  // torch puts work when the caller passes stream 0
+  HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamDefault));
+  HIP_TRY(hipEventCreate(&c->ev0));
+  HIP_TRY(hipEventCreate(&c->ev1));
+  HIP_TRY(hipEventCreate(&c->ev2));
+  *out = c.release();
+  return VRPH_OK;
+}
+
+extern "C" void vrph_destroy(vrph_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  DevBuf* bufs[] = {&c->D,   &c->W,     &c->binom,     &c->bitmaps, &c->cols,
+                    &c->cols_tmp, &c->sort_work, &c->ap, &c->scal, &c->clouds,
+                    &c->cstate, &c->h0, &c->deaths};
+  for (DevBuf* b : bufs) b->release();
+  c->h_scal.release();
+  c->h_cstate.release();
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->ev2) (void)hipEventDestroy(c->ev2);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+extern "C" int64_t vrph_barcode_count(const vrph_barcode* bc, int32_t dim) {
+  if (!bc) return 0;
+  if (dim < 0) return (int64_t)bc->pairs.size();
+  if (dim > VRPH_MAX_DIM) return 0;
+  return bc->off[dim + 1] - bc->off[dim];
+}
+
+extern "C" const vrph_pair* vrph_barcode_pairs(const vrph_barcode* bc, int32_t dim) {
+  if (!bc || bc->pairs.empty()) return nullptr;
+  if (dim < 0) return bc->pairs.data();
+  if (dim > VRPH_MAX_DIM) return nullptr;
+  return bc->pairs.data() + bc->off[dim];
+}
+
+extern "C" const vrph_stats* vrph_barcode_stats(const vrph_barcode* bc) {
+  return bc ? &bc->stats : nullptr;
+}
+
+extern "C" void vrph_barcode_free(vrph_barcode* bc) { delete bc; }
+
+// ---------------------------------------------------------------------------
+// pdist
+// ---------------------------------------------------------------------------
+
+// One cloud described for the batched kernels. The staging structs are
+// pageable stack memory: the copy has consumed them when the call returns.
+static vrph_status upload_single_cloud(vrph_ctx* c, int n, float threshold, hipStream_t s) {
+  HIP_TRY(c->clouds.ensure(sizeof(Cloud)));
+  HIP_TRY(c->cstate.ensure(sizeof(CloudState)));
+  HIP_TRY(c->h_cstate.ensure(sizeof(CloudState)));
+  Cloud cl;
+  cl.x_off = 0;
+  cl.w_off = 0;
+  cl.e_off = 0;
+  cl.bm_off = 0;
+  cl.n = n;
+  cl.tau_bits = std::isinf(threshold) ? 0x7F800000u : fbits(threshold);
+  CloudState cs;
+  cs.r_bits = kInf;
+  cs.tau_bits = 0;
+  cs.err = 0;
+  cs.h0_count = 0;
+  HIP_TRY(hipMemcpyAsync(c->clouds.p, &cl, sizeof(Cloud), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->cstate.p, &cs, sizeof(CloudState), hipMemcpyHostToDevice, s));
+  return VRPH_OK;
+}
+
+extern "C" vrph_status vrph_pdist(vrph_ctx* c, const float* X, int64_t n, int32_t m, float* D,
+                                  void* hip_stream) {
+  if (!c || !X || !D) return fail(VRPH_EINVAL, "vrph_pdist: NULL argument");
+  if (n < 1 || n > kMaxN || m < 1) return fail(VRPH_EINVAL, "vrph_pdist: bad n or m");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  vrph_status st = upload_single_cloud(c, (int)n, INFINITY, s);
+  if (st) return st;
+  HIP_TRY(launch_batch_pdist(X, m, c->clouds.as<Cloud>(), 1, n, D, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return VRPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the single-cloud pipeline
+// ---------------------------------------------------------------------------
+
+static void finish_pairs(vrph_barcode* bc, const HostComplex& H, int max_dim, bool keep_zero) {
+  std::vector<vrph_pair>& P = bc->pairs;
+  if (!keep_zero)
+    P.erase(std::remove_if(P.begin(), P.end(),
+                           [](const vrph_pair& p) { return !p.essential && p.birth_diam == p.death_diam; }),
+            P.end());
+  for (vrph_pair& p : P) {
+    p.birth_edge[0] = p.birth_edge[1] = -1;
+    p.death_edge[0] = p.death_edge[1] = -1;
+    if (p.dim >= 1) diameter_edge(H, p.birth, p.dim, &p.birth_edge[0], &p.birth_edge[1]);
+    if (!p.essential) diameter_edge(H, p.death, p.dim + 1, &p.death_edge[0], &p.death_edge[1]);
+  }
+  std::sort(P.begin(), P.end(), [](const vrph_pair& a, const vrph_pair& b) {
+    if (a.dim != b.dim) return a.dim < b.dim;
+    if (a.birth != b.birth) return a.birth < b.birth;
+    return a.death < b.death;
+  });
+  for (int d = 0; d <= VRPH_MAX_DIM + 1; ++d) bc->off[d] = 0;
+  for (const vrph_pair& p : P) bc->off[p.dim + 1]++;
+  for (int d = 1; d <= VRPH_MAX_DIM + 2; ++d) bc->off[d] += bc->off[d - 1];
+  (void)max_dim;
+}
+
+static vrph_pair make_pair(int dim, uint64_t b, uint32_t bd, uint64_t d, uint32_t dd) {
+  vrph_pair p;
+  std::memset(&p, 0, sizeof(p));
+  p.dim = dim;
+  p.essential = d == ~0ull ? 1 : 0;
+  p.birth = b;
+  p.death = d == ~0ull ? UINT64_MAX : d;
+  p.birth_diam = bitsf(bd);
+  p.death_diam = p.essential ? INFINITY : bitsf(dd);
+  return p;
+}
+
+static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim, float threshold,
+                                uint32_t flags, hipStream_t s, vrph_barcode** out) {
+  const double t_start = now_ms();
+  const bool keep_zero = flags & VRPH_KEEP_ZERO_PERSISTENCE;
+  const int kmax = max_dim + 2;
+  if (c->binom_n != n || c->binom_k != kmax) {
+    if (!binomial_table(n, kmax, c->h_binom))
+      return fail(VRPH_EOVERFLOW, "C(n, max_dim + 2) >= 2^63: simplex indices do not fit");
+    HIP_TRY(c->binom.ensure(c->h_binom.size() * sizeof(uint64_t)));
+    HIP_TRY(hipMemcpyAsync(c->binom.p, c->h_binom.data(), c->h_binom.size() * sizeof(uint64_t),
+                           hipMemcpyHostToDevice, s));
+    c->binom_n = n;
+    c->binom_k = kmax;
+  }
+  HostComplex H;
+  H.n = n;
+  H.binom = c->h_binom.data();
+  H.kmax = kmax;
+
+  // clearing bitmaps: dimension d columns are C(n, d+1) bits
+  // (dimension 1 always: the H0 kernel marks the forest edges there)
+  std::vector<int64_t> bm_off(max_dim + 3, 0);
+  int64_t words = 0;
+  for (int d = 1; d <= max_dim + 1; ++d) {
+    bm_off[d] = words;
+    if (d <= std::max(max_dim, 1)) words += (int64_t)((H.C(n, d + 1) + 31) / 32);
+  }
+  HIP_TRY(c->bitmaps.ensure((size_t)std::max<int64_t>(words, 1) * 4));
+  uint32_t* bm = c->bitmaps.as<uint32_t>();
+  HIP_TRY(launch_fill_u32(bm, words, 0u, s));
+
+  vrph_status st = upload_single_cloud(c, n, threshold, s);
+  if (st) return st;
+  HIP_TRY(c->W.ensure((size_t)n * n * 4));
+  HIP_TRY(c->h0.ensure((size_t)n * sizeof(H0Pair)));
+  HIP_TRY(hipEventRecord(c->ev0, s));
+  HIP_TRY(launch_batch_validate_weights(D, c->clouds.as<Cloud>(), 1, n,
+                                        !(flags & VRPH_NO_ENCLOSING_RADIUS), c->W.as<uint32_t>(),
+                                        c->cstate.as<CloudState>(), s));
+  HIP_TRY(launch_batch_h0(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1,
+                          c->cstate.as<CloudState>(), c->h0.as<H0Pair>(), n, bm + bm_off[1], s));
+  HIP_TRY(hipEventRecord(c->ev1, s));
+  CloudState cs;
+  HIP_TRY(hipMemcpyAsync(c->h_cstate.p, c->cstate.p, sizeof(CloudState), hipMemcpyDeviceToHost, s));
+  std::vector<uint32_t> hW((size_t)n * n);
+  std::vector<H0Pair> h0(n);
+  HIP_TRY(hipMemcpyAsync(hW.data(), c->W.p, (size_t)n * n * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h0.data(), c->h0.p, (size_t)n * sizeof(H0Pair), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::memcpy(&cs, c->h_cstate.p, sizeof(cs));
+  if (cs.err)
+    return fail(VRPH_EINVAL, std::string("invalid distance matrix:") +
+                                 ((cs.err & 1) ? " non-finite" : "") + ((cs.err & 2) ? " negative" : "") +
+                                 ((cs.err & 4) ? " asymmetric" : "") +
+                                 ((cs.err & 8) ? " nonzero diagonal" : ""));
+  H.W = hW.data();
+
+  std::unique_ptr<vrph_barcode> bc(new (std::nothrow) vrph_barcode());
+  if (!bc) return fail(VRPH_ENOMEM, "out of host memory");
+  std::memset(&bc->stats, 0, sizeof(bc->stats));
+  bc->stats.tau_eff = bitsf(cs.tau_bits);
+  bc->stats.max_dim = max_dim;
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  bc->stats.gpu_ms[0] = ms;
+  bc->stats.candidates[0] = n;
+  bc->stats.columns[0] = n;
+  for (uint32_t i = 0; i < cs.h0_count && i < (uint32_t)n; ++i) {
+    const H0Pair& q = h0[i];
+    bc->pairs.push_back(make_pair(0, q.birth, 0u, q.death, q.diam));
+  }
+  bc->stats.pairs[0] = cs.h0_count;
+
+  HIP_TRY(c->scal.ensure(sizeof(Scalars)));
+  HIP_TRY(c->h_scal.ensure(sizeof(Scalars)));
+  std::vector<Column> hcols;
+  std::vector<ApparentPair> hap;
+  std::vector<PairRec> prs;
+  std::vector<uint64_t> deaths;
+  for (int d = 1; d <= max_dim; ++d) {
+    const uint64_t ncand = H.C(n, d + 1);
+    uint32_t* clear_in = bm + bm_off[d];
+    uint32_t* clear_out = d < max_dim ? bm + bm_off[d + 1] : nullptr;
+    uint64_t cap = c->cols.cap / sizeof(Column);
+    if (cap < 4096) cap = std::min<uint64_t>(ncand, 1 << 16) + 1;
+    uint64_t ap_cap = keep_zero ? ncand : 0;
+    Scalars sc;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      HIP_TRY(c->cols.ensure(cap * sizeof(Column)));
+      if (keep_zero) HIP_TRY(c->ap.ensure(std::max<uint64_t>(ap_cap, 1) * sizeof(ApparentPair)));
+      HIP_TRY(hipMemsetAsync(c->scal.p, 0, sizeof(Scalars), s));
+      HIP_TRY(hipEventRecord(c->ev0, s));
+      Scalars* dsc = c->scal.as<Scalars>();
+      if (d == 1) {
+        HIP_TRY(launch_batch_edges(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1, (int64_t)ncand,
+                                   clear_in, c->cols.as<Column>(), cap,
+                                   keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
+                                   clear_out, &dsc->columns, c->num_cus * 8, s));
+      } else {
+        HIP_TRY(launch_enum_apparent(d, c->W.as<uint32_t>(), n, c->binom.as<uint64_t>(), kmax,
+                                     ncand, clear_in, clear_out, c->cols.as<Column>(), cap,
+                                     keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap, dsc,
+                                     c->num_cus * 8, s));
+      }
+      HIP_TRY(hipEventRecord(c->ev2, s));
+      HIP_TRY(hipMemcpyAsync(c->h_scal.p, c->scal.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      std::memcpy(&sc, c->h_scal.p, sizeof(sc));
+      if (sc.nonapparent <= cap) break;
+      cap = sc.nonapparent + 1024;  // grow to the exact need and run the dimension again
+    }
+    if (sc.nonapparent > cap) return fail(VRPH_EDEVICE, "non-apparent column count changed between runs");
+    const int64_t nna = (int64_t)sc.nonapparent;
+    HIP_TRY(c->cols_tmp.ensure(std::max<int64_t>(nna, 1) * sizeof(Column)));
+    HIP_TRY(c->sort_work.ensure(radix_sort_work_bytes(nna)));
+    HIP_TRY(radix_sort_columns(c->cols.as<Column>(), c->cols_tmp.as<Column>(), nna,
+                               bits_needed(ncand), 0, c->sort_work.p, s));
+    HIP_TRY(hipEventRecord(c->ev1, s));
+    hcols.resize(nna);
+    if (nna) HIP_TRY(hipMemcpyAsync(hcols.data(), c->cols.p, nna * sizeof(Column), hipMemcpyDeviceToHost, s));
+    if (keep_zero) {
+      hap.resize(sc.apparent_written);
+      if (sc.apparent_written)
+        HIP_TRY(hipMemcpyAsync(hap.data(), c->ap.p, sc.apparent_written * sizeof(ApparentPair),
+                               hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    bc->stats.gpu_ms[d] = ms;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev2));
+    bc->stats.apparent_ms[d] = ms;
+    bc->stats.cofacets[d] = (int64_t)sc.scan_steps;
+    bc->stats.candidates[d] = (int64_t)ncand;
+    bc->stats.columns[d] = (int64_t)sc.columns;
+    bc->stats.apparent[d] = (int64_t)sc.apparent;
+    bc->stats.reduced[d] = nna;
+
+    const double h0t = now_ms();
+    prs.clear();
+    deaths.clear();
+    ReduceStats rs;
+    reduce_dimension(H, d, hcols.data(), nna, prs, deaths, rs);
+    bc->stats.additions[d] = rs.additions;
+    for (const PairRec& r : prs) bc->pairs.push_back(make_pair(d, r.birth, r.bdiam, r.death, r.ddiam));
+    if (keep_zero)
+      for (const ApparentPair& a : hap) bc->pairs.push_back(make_pair(d, a.s, a.diam, a.t, a.diam));
+    bc->stats.pairs[d] = (int64_t)prs.size() + (int64_t)sc.apparent;
+    bc->stats.host_ms[d] = now_ms() - h0t;
+    if (clear_out && !deaths.empty()) {
+      HIP_TRY(c->deaths.ensure(deaths.size() * sizeof(uint64_t)));
+      HIP_TRY(hipMemcpyAsync(c->deaths.p, deaths.data(), deaths.size() * sizeof(uint64_t),
+                             hipMemcpyHostToDevice, s));
+      HIP_TRY(launch_set_bits(c->deaths.as<uint64_t>(), (int64_t)deaths.size(), clear_out, s));
+      HIP_TRY(hipStreamSynchronize(s));  // `deaths` is reused by the next dimension
+    }
+  }
+  finish_pairs(bc.get(), H, max_dim, keep_zero);
+  bc->stats.total_ms = now_ms() - t_start;
+  *out = bc.release();
+  return VRPH_OK;
+}
+
+static vrph_status check_common(vrph_ctx* c, int64_t n, int32_t max_dim, float threshold,
+                                vrph_barcode** out) {
+  if (!c || !out) return fail(VRPH_EINVAL, "NULL context or output");
+  *out = nullptr;
+  if (n < 1 || n > kMaxN) return fail(VRPH_EINVAL, "n must be in [1, 2048]");
+  if (max_dim < 0 || max_dim > VRPH_MAX_DIM) return fail(VRPH_EINVAL, "max_dim out of range");
+  if (std::isnan(threshold) || threshold < 0) return fail(VRPH_EINVAL, "threshold must be >= 0");
+  return VRPH_OK;
+}
+
+extern "C" vrph_status vrph_barcode_from_dist(vrph_ctx* c, const float* D, int64_t n,
+                                              int32_t max_dim, float threshold, uint32_t flags,
+                                              void* hip_stream, vrph_barcode** out) {
+  vrph_status st = check_common(c, n, max_dim, threshold, out);
+  if (st) return st;
+  if (!D) return fail(VRPH_EINVAL, "D is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  return barcode_impl(c, D, (int)n, max_dim, threshold, flags, s, out);
+}
+
+extern "C" vrph_status vrph_barcode_from_points(vrph_ctx* c, const float* X, int64_t n,
+                                                int32_t m, int32_t max_dim, float threshold,
+                                                uint32_t flags, void* hip_stream,
+                                                vrph_barcode** out) {
+  vrph_status st = check_common(c, n, max_dim, threshold, out);
+  if (st) return st;
+  if (!X || m < 1) return fail(VRPH_EINVAL, "X is NULL or m < 1");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  HIP_TRY(c->D.ensure((size_t)n * n * 4));
+  st = upload_single_cloud(c, (int)n, INFINITY, s);
+  if (st) return st;
+  HIP_TRY(launch_batch_pdist(X, m, c->clouds.as<Cloud>(), 1, n, c->D.as<float>(), s));
+  return barcode_impl(c, c->D.as<float>(), (int)n, max_dim, threshold, flags, s, out);
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+
+extern "C" vrph_status vrph_backward(vrph_ctx* c, const float* X, int64_t n_total, int32_t m,
+                                     const int32_t* edges, int64_t npairs, const float* g_birth,
+                                     const float* g_death, float* gX, void* hip_stream) {
+  if (!c || !X || !gX || m < 1 || n_total < 0 || npairs < 0)
+    return fail(VRPH_EINVAL, "vrph_backward: bad argument");
+  if (npairs > 0 && (!edges || !g_birth || !g_death))
+    return fail(VRPH_EINVAL, "vrph_backward: NULL pair arrays");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  HIP_TRY(launch_backward(X, m, edges, npairs, g_birth, g_death, gX, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return VRPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched point clouds
+// ---------------------------------------------------------------------------
+
+struct vrph_batch {
+  vrph_ctx* ctx = nullptr;
+  int count = 0, m = 0, max_dim = 0, max_n = 0;
+  float threshold = INFINITY;
+  uint32_t flags = 0;
+  std::vector<Cloud> clouds;
+  std::vector<int64_t> sizes;
+  int64_t total_points = 0, total_w = 0, total_edges = 0, total_words = 0;
+  int max_kmax = 0;
+  DevBuf X, D, W, dclouds, cstate, h0, bitmaps, cols, cols_tmp, sort_work, ap, counters;
+  HostPinned h_cstate, h_counters;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<std::vector<uint64_t>> binoms;  // per cloud, k-major (kmax+1) x (n+1)
+  std::vector<vrph_barcode> results;
+  std::vector<uint32_t> hW;
+  std::vector<H0Pair> hh0;
+  std::vector<Column> hcols;
+  std::vector<ApparentPair> hap;
+  bool sorted_in_tmp = false;
+  int64_t last_columns = 0, last_apparent = 0, last_nonapparent = 0;
+};
+
+extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_t count,
+                                       int32_t m, int32_t max_dim, float threshold,
+                                       uint32_t flags, vrph_batch** out) {
+  if (!c || !sizes || !out || count < 1 || m < 1)
+    return fail(VRPH_EINVAL, "vrph_batch_plan: bad argument");
+  *out = nullptr;
+  if (max_dim < 0 || max_dim > 1) return fail(VRPH_EINVAL, "vrph_batch_plan: max_dim must be 0 or 1");
+  if (std::isnan(threshold) || threshold < 0) return fail(VRPH_EINVAL, "threshold must be >= 0");
+  HIP_TRY(hipSetDevice(c->device));
+  std::unique_ptr<vrph_batch> b(new (std::nothrow) vrph_batch());
+  if (!b) return fail(VRPH_ENOMEM, "out of host memory");
+  b->ctx = c;
+  b->count = count;
+  b->m = m;
+  b->max_dim = max_dim;
+  b->threshold = threshold;
+  b->flags = flags;
+  b->sizes.assign(sizes, sizes + count);
+  b->clouds.resize(count);
+  b->binoms.resize(count);
+  for (int i = 0; i < count; ++i) {
+    const int64_t n = sizes[i];
+    if (n < 2 || n > kMaxN) return fail(VRPH_EINVAL, "vrph_batch_plan: cloud size out of [2, 2048]");
+    Cloud& cl = b->clouds[i];
+    cl.x_off = b->total_points;
+    cl.w_off = b->total_w;
+    cl.e_off = b->total_edges;
+    cl.bm_off = b->total_words;
+    cl.n = (int)n;
+    cl.tau_bits = std::isinf(threshold) ? 0x7F800000u : fbits(threshold);
+    const int64_t ne = n * (n - 1) / 2;
+    b->total_points += n;
+    b->total_w += n * n;
+    b->total_edges += ne;
+    b->total_words += (ne + 31) / 32;
+    b->max_n = std::max<int>(b->max_n, (int)n);
+    if (!binomial_table((int)n, 3, b->binoms[i]))
+      return fail(VRPH_EOVERFLOW, "simplex indices do not fit");
+  }
+  const uint64_t cap = (uint64_t)std::max<int64_t>(b->total_edges, 1);
+  const bool keep_zero = flags & VRPH_KEEP_ZERO_PERSISTENCE;
+  HIP_TRY(b->X.ensure((size_t)b->total_points * m * 4));
+  HIP_TRY(b->D.ensure((size_t)b->total_w * 4));
+  HIP_TRY(b->W.ensure((size_t)b->total_w * 4));
+  HIP_TRY(b->dclouds.ensure((size_t)count * sizeof(Cloud)));
+  HIP_TRY(b->cstate.ensure((size_t)count * sizeof(CloudState)));
+  HIP_TRY(b->h0.ensure((size_t)count * b->max_n * sizeof(H0Pair)));
+  HIP_TRY(b->bitmaps.ensure((size_t)std::max<int64_t>(b->total_words, 1) * 4));
+  HIP_TRY(b->cols.ensure(cap * sizeof(Column)));
+  HIP_TRY(b->cols_tmp.ensure(cap * sizeof(Column)));
+  HIP_TRY(b->sort_work.ensure(radix_sort_work_bytes((int64_t)cap)));
+  if (keep_zero) HIP_TRY(b->ap.ensure(cap * sizeof(ApparentPair)));
+  HIP_TRY(b->counters.ensure(sizeof(Scalars)));
+  HIP_TRY(b->h_cstate.ensure((size_t)count * sizeof(CloudState)));
+  HIP_TRY(b->h_counters.ensure(sizeof(Scalars)));
+  HIP_TRY(hipMemcpy(b->dclouds.p, b->clouds.data(), (size_t)count * sizeof(Cloud),
+                    hipMemcpyHostToDevice));
+  b->results.resize(count);
+  *out = b.release();
+  return VRPH_OK;
+}
+
+extern "C" void vrph_batch_destroy(vrph_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->ctx->device);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  DevBuf* bufs[] = {&b->X,    &b->D,        &b->W,         &b->dclouds, &b->cstate,
+                    &b->h0,   &b->bitmaps,  &b->cols,      &b->cols_tmp, &b->sort_work,
+                    &b->ap,   &b->counters};
+  for (DevBuf* d : bufs) d->release();
+  b->h_cstate.release();
+  b->h_counters.release();
+  delete b;
+}
+
+// Device work of one forward, recorded once into a graph and replayed:
+// reset of the per-cloud state with fill kernels (no memset nodes), distances,
+// validation + weights, H0, the dimension-1 enumeration + apparent test over
+// the edges of every cloud, the coboundary-order sort with the record count
+// read on the device, and the copies of the small results to pinned memory.
+static hipError_t batch_record(vrph_batch* b, hipStream_t s) {
+  const bool keep_zero = b->flags & VRPH_KEEP_ZERO_PERSISTENCE;
+  const bool enclosing = !(b->flags & VRPH_NO_ENCLOSING_RADIUS);
+  Scalars* sc = b->counters.as<Scalars>();
+  hipError_t e;
+  if ((e = launch_init_states(b->cstate.as<CloudState>(), b->count, s))) return e;
+  if ((e = launch_fill_u32(b->bitmaps.as<uint32_t>(), b->total_words, 0u, s))) return e;
+  if ((e = launch_fill_u32(b->counters.as<uint32_t>(), sizeof(Scalars) / 4, 0u, s))) return e;
+  if ((e = launch_batch_pdist(b->X.as<float>(), b->m, b->dclouds.as<Cloud>(), b->count,
+                              b->total_points, b->D.as<float>(), s)))
+    return e;
+  if ((e = launch_batch_validate_weights(b->D.as<float>(), b->dclouds.as<Cloud>(), b->count,
+                                         b->total_points, enclosing, b->W.as<uint32_t>(),
+                                         b->cstate.as<CloudState>(), s)))
+    return e;
+  if ((e = launch_batch_h0(b->W.as<uint32_t>(), b->dclouds.as<Cloud>(), b->count,
+                           b->cstate.as<CloudState>(), b->h0.as<H0Pair>(), b->max_n,
+                           b->bitmaps.as<uint32_t>(), s)))
+    return e;
+  if (b->max_dim >= 1) {
+    const uint64_t cap = (uint64_t)std::max<int64_t>(b->total_edges, 1);
+    if ((e = launch_batch_edges(b->W.as<uint32_t>(), b->dclouds.as<Cloud>(), b->count,
+                                b->total_edges, b->bitmaps.as<uint32_t>(), b->cols.as<Column>(),
+                                cap, keep_zero ? b->ap.as<ApparentPair>() : nullptr,
+                                keep_zero ? cap : 0, nullptr, &sc->columns,
+                                b->ctx->num_cus * 8, s)))
+      return e;
+    int max_edges_bits = 0;
+    while ((int64_t(1) << max_edges_bits) < (int64_t)b->max_n * (b->max_n - 1) / 2) ++max_edges_bits;
+    int cloud_bits = 0;
+    while ((1 << cloud_bits) < b->count) ++cloud_bits;
+    bool in_tmp = false;
+    if ((e = radix_sort_columns(b->cols.as<Column>(), b->cols_tmp.as<Column>(), (int64_t)cap,
+                                max_edges_bits, cloud_bits, b->sort_work.p, s, &sc->nonapparent,
+                                &in_tmp)))
+      return e;
+    b->sorted_in_tmp = in_tmp;
+  }
+  if ((e = hipMemcpyAsync(b->h_cstate.p, b->cstate.p, (size_t)b->count * sizeof(CloudState),
+                          hipMemcpyDeviceToHost, s)))
+    return e;
+  if ((e = hipMemcpyAsync(b->h_counters.p, b->counters.p, sizeof(Scalars), hipMemcpyDeviceToHost,
+                          s)))
+    return e;
+  return hipSuccess;
+}
+
+extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, void* hip_stream) {
+  if (!b || !X_packed) return fail(VRPH_EINVAL, "vrph_batch_forward: NULL argument");
+  vrph_ctx* c = b->ctx;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  const double t_start = now_ms();
+  HIP_TRY(hipMemcpyAsync(b->X.p, X_packed, (size_t)b->total_points * b->m * 4,
+                         hipMemcpyDeviceToDevice, s));
+  if (!b->exec) {
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = batch_record(b, s);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(VRPH_EDEVICE, std::string("graph capture failed: ") +
+                                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipEventRecord(c->ev0, s));
+  HIP_TRY(hipGraphLaunch(b->exec, s));
+  HIP_TRY(hipEventRecord(c->ev1, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  float gms = 0;
+  HIP_TRY(hipEventElapsedTime(&gms, c->ev0, c->ev1));
+  Scalars sc;
+  std::memcpy(&sc, b->h_counters.p, sizeof(sc));
+  const CloudState* cst = b->h_cstate.as<CloudState>();
+  for (int i = 0; i < b->count; ++i)
+    if (cst[i].err) return fail(VRPH_EINVAL, "invalid distances in cloud " + std::to_string(i));
+
+  // results of the device part
+  const bool keep_zero = b->flags & VRPH_KEEP_ZERO_PERSISTENCE;
+  const int64_t nna = (int64_t)sc.nonapparent;
+  b->hW.resize((size_t)b->total_w);
+  b->hh0.resize((size_t)b->count * b->max_n);
+  b->hcols.resize((size_t)nna);
+  HIP_TRY(hipMemcpyAsync(b->hW.data(), b->W.p, (size_t)b->total_w * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(b->hh0.data(), b->h0.p, b->hh0.size() * sizeof(H0Pair),
+                         hipMemcpyDeviceToHost, s));
+  if (nna)
+    HIP_TRY(hipMemcpyAsync(b->hcols.data(), b->sorted_in_tmp ? b->cols_tmp.p : b->cols.p,
+                           (size_t)nna * sizeof(Column), hipMemcpyDeviceToHost, s));
+  if (keep_zero) {
+    b->hap.resize(sc.apparent_written);
+    if (sc.apparent_written)
+      HIP_TRY(hipMemcpyAsync(b->hap.data(), b->ap.p, sc.apparent_written * sizeof(ApparentPair),
+                             hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+
+  // per-cloud slices of the sorted columns and of the apparent pairs
+  std::vector<int64_t> col_begin(b->count + 1, nna);
+  for (int64_t j = nna - 1; j >= 0; --j) col_begin[b->hcols[j].cloud] = j;
+  for (int i = b->count - 1; i >= 0; --i)
+    if (col_begin[i] > col_begin[i + 1]) col_begin[i] = col_begin[i + 1];
+  std::vector<std::vector<uint32_t>> ap_of(keep_zero ? b->count : 0);
+  if (keep_zero)
+    for (size_t j = 0; j < b->hap.size(); ++j) ap_of[b->hap[j].cloud].push_back((uint32_t)j);
+
+  // host submatrix reduction, one cloud per task, on a small thread pool
+  const double th = now_ms();
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= b->count) return;
+      const Cloud& cl = b->clouds[i];
+      HostComplex H;
+      H.n = cl.n;
+      H.W = b->hW.data() + cl.w_off;
+      H.binom = b->binoms[i].data();
+      H.kmax = 3;
+      vrph_barcode& r = b->results[i];
+      r.pairs.clear();
+      std::memset(&r.stats, 0, sizeof(r.stats));
+      r.stats.max_dim = b->max_dim;
+      r.stats.tau_eff = bitsf(cst[i].tau_bits);
+      const H0Pair* h0 = b->hh0.data() + (size_t)i * b->max_n;
+      for (uint32_t k = 0; k < cst[i].h0_count && k < (uint32_t)cl.n; ++k)
+        r.pairs.push_back(make_pair(0, h0[k].birth, 0u, h0[k].death, h0[k].diam));
+      r.stats.pairs[0] = cst[i].h0_count;
+      if (b->max_dim >= 1) {
+        std::vector<PairRec> prs;
+        std::vector<uint64_t> deaths;
+        ReduceStats rs;
+        const int64_t cb = col_begin[i], ce = col_begin[i + 1];
+        reduce_dimension(H, 1, b->hcols.data() + cb, ce - cb, prs, deaths, rs);
+        for (const PairRec& q : prs) r.pairs.push_back(make_pair(1, q.birth, q.bdiam, q.death, q.ddiam));
+        if (keep_zero)
+          for (uint32_t j : ap_of[i]) {
+            const ApparentPair& a = b->hap[j];
+            r.pairs.push_back(make_pair(1, a.s, a.diam, a.t, a.diam));
+          }
+        r.stats.reduced[1] = ce - cb;
+        r.stats.additions[1] = rs.additions;
+      }
+      finish_pairs(&r, H, b->max_dim, keep_zero);
+    }
+  };
+  const int nthreads = std::max(1, std::min<int>(b->count, std::min<int>(16, (int)std::thread::hardware_concurrency())));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
+  work();
+  for (std::thread& t : pool) t.join();
+  const double host_ms = now_ms() - th;
+  for (int i = 0; i < b->count; ++i) {
+    b->results[i].stats.gpu_ms[0] = gms;
+    b->results[i].stats.host_ms[1] = host_ms;
+    b->results[i].stats.total_ms = now_ms() - t_start;
+  }
+  b->last_columns = (int64_t)sc.columns;
+  b->last_apparent = (int64_t)sc.apparent;
+  b->last_nonapparent = nna;
+  return VRPH_OK;
+}
+
+extern "C" vrph_status vrph_batch_result(vrph_batch* b, int32_t cloud, const vrph_barcode** view) {
+  if (!b || !view || cloud < 0 || cloud >= b->count)
+    return fail(VRPH_EINVAL, "vrph_batch_result: bad argument");
+  *view = &b->results[cloud];
+  return VRPH_OK;
+}

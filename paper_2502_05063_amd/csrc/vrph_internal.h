@@ -1,0 +1,109 @@
+// Internal declarations shared by the HIP kernels (kernels.hip, sort.hip)
+// and the host runtime (vrph_api.cpp, reduce.cpp). Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vrph {
+
+// Edge weights are the IEEE bit patterns of the float32 distances, which
+// order like the values for non-negative floats. Entries above the effective
+// threshold (and the diagonal) hold kInf, larger than any finite pattern.
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+constexpr int kMaxDim = 6;        // largest max_dim
+constexpr int kMaxN = 2048;       // largest cloud the one-workgroup H0 kernel takes
+constexpr int kBlock = 256;       // threads per workgroup of the streaming kernels
+
+// A non-apparent column of the coboundary matrix. Sorting ascending by
+// (cloud, key_hi, cidx) gives coboundary order within each cloud: diameter
+// descending (key_hi = ~diameter bits), index ascending (Sec. 5.2.1).
+struct Column {
+  uint32_t key_hi;
+  uint32_t cloud;
+  uint64_t cidx;
+};
+static_assert(sizeof(Column) == 16, "Column is 16 bytes");
+
+// An apparent pair (s, t) (Def. 5.3.4) with their common diameter.
+struct ApparentPair {
+  uint64_t s;
+  uint64_t t;
+  uint32_t diam;
+  uint32_t cloud;
+};
+static_assert(sizeof(ApparentPair) == 24, "ApparentPair is 24 bytes");
+
+// An H0 pair: vertex birth (diameter 0) and edge death, or essential.
+struct H0Pair {
+  uint64_t death;  // edge index, or ~0 for an essential class
+  uint32_t birth;  // vertex
+  uint32_t diam;   // death diameter bits (kInf for essential)
+};
+static_assert(sizeof(H0Pair) == 16, "H0Pair is 16 bytes");
+
+// Per-call device scalars, read back once per stage.
+struct Scalars {
+  uint32_t err;       // bit0 non-finite, bit1 negative, bit2 asymmetric, bit3 diagonal
+  uint32_t r_bits;    // enclosing radius
+  uint32_t tau_bits;  // effective threshold
+  uint32_t h0_count;  // H0 pairs written
+  unsigned long long columns, apparent, nonapparent, candidates, apparent_written, scan_steps;
+};
+
+// Per-cloud description for the batched kernels.
+struct Cloud {
+  int64_t x_off;    // first point of the cloud in the packed point array
+  int64_t w_off;    // offset of the cloud's n*n weight block
+  int64_t e_off;    // first edge of the cloud in the flat edge numbering
+  int64_t bm_off;   // first 32-bit word of the cloud's edge-clearing bitmap
+  int32_t n;
+  uint32_t tau_bits;  // requested threshold (bits); the effective one is stored in CloudState
+};
+
+struct CloudState {
+  uint32_t r_bits;
+  uint32_t tau_bits;
+  uint32_t err;
+  uint32_t h0_count;
+};
+
+// ---- launchers (kernels.hip) ----
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);
+hipError_t launch_batch_pdist(const float* X, int m, const Cloud* clouds, int count,
+                              int64_t total_points, float* D, hipStream_t s);
+hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, int count,
+                                         int64_t total_points, bool enclosing, uint32_t* W,
+                                         CloudState* st, hipStream_t s);
+hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, CloudState* st,
+                           H0Pair* out, int64_t out_stride, uint32_t* bitmaps, hipStream_t s);
+hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int kmax,
+                                uint64_t ncand, const uint32_t* clear_in, uint32_t* clear_out,
+                                Column* cols, uint64_t cols_cap, ApparentPair* ap,
+                                uint64_t ap_cap, Scalars* sc, int grid, hipStream_t s);
+hipError_t launch_batch_edges(const uint32_t* W, const Cloud* clouds, int count,
+                              int64_t total_edges, const uint32_t* bitmaps, Column* cols,
+                              uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
+                              uint32_t* clear_out, unsigned long long* counters, int grid,
+                              hipStream_t s);
+hipError_t launch_set_bits(const uint64_t* idx, int64_t count, uint32_t* bitmap, hipStream_t s);
+hipError_t launch_backward(const float* X, int m, const int32_t* edges, int64_t npairs,
+                           const float* g_birth, const float* g_death, float* gX, hipStream_t s);
+
+// ---- sort.hip ----
+// Stable LSD radix sort of Column records ascending by (cloud, key_hi, cidx),
+// looking only at the low `cidx_bits` of cidx, all 32 bits of key_hi and the
+// low `cloud_bits` of cloud. `tmp` has room for n records; `work` for
+// radix_sort_work_bytes(n) bytes. With n_dev, the count is min(*n_dev, n)
+// read on the device (n is then the capacity). The result ends in `a`, or,
+// when result_in_tmp is given, possibly in `tmp` (*result_in_tmp says which),
+// which avoids a copy node in a recorded graph.
+size_t radix_sort_work_bytes(int64_t n);
+hipError_t radix_sort_columns(Column* a, Column* tmp, int64_t n, int cidx_bits, int cloud_bits,
+                              void* work, hipStream_t s,
+                              const unsigned long long* n_dev = nullptr,
+                              bool* result_in_tmp = nullptr);
+hipError_t launch_init_states(CloudState* st, int count, hipStream_t s);
+
+}  // namespace vrph

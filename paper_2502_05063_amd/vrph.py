@@ -1,0 +1,246 @@
+"""Python binding of libvrph.so (include/vrph.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library. PyTorch supplies
+device memory and the current stream. If the library is missing the import
+fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvrph.so")
+
+OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
+KEEP_ZERO_PERSISTENCE = 1
+NO_ENCLOSING_RADIUS = 2
+MAX_DIM = 6
+
+PAIR_DTYPE = np.dtype(
+    [
+        ("dim", "<i4"),
+        ("essential", "<i4"),
+        ("birth", "<u8"),
+        ("death", "<u8"),
+        ("birth_diam", "<f4"),
+        ("death_diam", "<f4"),
+        ("birth_edge", "<i4", (2,)),
+        ("death_edge", "<i4", (2,)),
+    ]
+)
+assert PAIR_DTYPE.itemsize == 48
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("candidates", ctypes.c_int64 * (MAX_DIM + 1)),
+        ("columns", ctypes.c_int64 * (MAX_DIM + 1)),
+        ("apparent", ctypes.c_int64 * (MAX_DIM + 1)),
+        ("reduced", ctypes.c_int64 * (MAX_DIM + 1)),
+        ("additions", ctypes.c_int64 * (MAX_DIM + 1)),
+        ("pairs", ctypes.c_int64 * (MAX_DIM + 1)),
+        ("cofacets", ctypes.c_int64 * (MAX_DIM + 1)),
+        ("gpu_ms", ctypes.c_double * (MAX_DIM + 1)),
+        ("apparent_ms", ctypes.c_double * (MAX_DIM + 1)),
+        ("host_ms", ctypes.c_double * (MAX_DIM + 1)),
+        ("tau_eff", ctypes.c_float),
+        ("max_dim", ctypes.c_int32),
+        ("total_ms", ctypes.c_double),
+    ]
+
+    def to_dict(self):
+        k = self.max_dim + 1
+        out = {f: list(getattr(self, f))[:k] for f, _ in self._fields_[:10]}
+        out.update(tau_eff=self.tau_eff, max_dim=self.max_dim, total_ms=self.total_ms)
+        return out
+
+
+class VrphError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"vrph status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2502_05063_amd.build_lib`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float
+    P = ctypes.POINTER
+    sig = {
+        "vrph_create": (i32, [ctypes.c_int, P(vp)]),
+        "vrph_destroy": (None, [vp]),
+        "vrph_last_error": (ctypes.c_char_p, []),
+        "vrph_pdist": (i32, [vp, vp, i64, i32, vp, vp]),
+        "vrph_barcode_from_dist": (i32, [vp, vp, i64, i32, f32, u32, vp, P(vp)]),
+        "vrph_barcode_from_points": (i32, [vp, vp, i64, i32, i32, f32, u32, vp, P(vp)]),
+        "vrph_barcode_count": (i64, [vp, i32]),
+        "vrph_barcode_pairs": (vp, [vp, i32]),
+        "vrph_barcode_stats": (P(Stats), [vp]),
+        "vrph_barcode_free": (None, [vp]),
+        "vrph_batch_plan": (i32, [vp, vp, i32, i32, i32, f32, u32, P(vp)]),
+        "vrph_batch_forward": (i32, [vp, vp, vp]),
+        "vrph_batch_result": (i32, [vp, i32, P(vp)]),
+        "vrph_batch_destroy": (None, [vp]),
+        "vrph_backward": (i32, [vp, vp, i64, i32, vp, i64, vp, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != OK:
+        raise VrphError(status, lib().vrph_last_error().decode(errors="replace"))
+
+
+def _stream_ptr():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Barcode:
+    """Host copy of a result: `pairs` (PAIR_DTYPE records, canonical order) and `stats`."""
+
+    def __init__(self, handle, owned=True):
+        L = lib()
+        cnt = L.vrph_barcode_count(handle, -1)
+        self.pairs = np.empty(cnt, PAIR_DTYPE)
+        if cnt:
+            ctypes.memmove(self.pairs.ctypes.data, L.vrph_barcode_pairs(handle, -1),
+                           cnt * PAIR_DTYPE.itemsize)
+        self.stats = L.vrph_barcode_stats(handle).contents.to_dict()
+        if owned:
+            L.vrph_barcode_free(handle)
+
+    def dim(self, d):
+        return self.pairs[self.pairs["dim"] == d]
+
+
+class Context:
+    """A library context on the current torch CUDA device."""
+
+    def __init__(self, device=None):
+        import torch
+
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _check(lib().vrph_create(self.device, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vrph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _f32(t):
+        import torch
+
+        if not t.is_cuda or t.dtype != torch.float32:
+            raise ValueError("expected a float32 CUDA tensor")
+        return t.contiguous()
+
+    def pdist(self, X):
+        import torch
+
+        X = self._f32(X)
+        n, m = X.shape
+        D = torch.empty((n, n), dtype=torch.float32, device=X.device)
+        _check(lib().vrph_pdist(self.h, _dev_ptr(X), n, m, _dev_ptr(D), _stream_ptr()))
+        return D
+
+    def barcode(self, *, X=None, D=None, max_dim=1, threshold=float("inf"), keep_zero=False,
+                no_enclosing=False):
+        flags = (KEEP_ZERO_PERSISTENCE if keep_zero else 0) | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
+        out = ctypes.c_void_p()
+        if X is not None:
+            X = self._f32(X)
+            n, m = X.shape
+            _check(lib().vrph_barcode_from_points(self.h, _dev_ptr(X), n, m, max_dim, threshold,
+                                                  flags, _stream_ptr(), ctypes.byref(out)))
+        else:
+            D = self._f32(D)
+            _check(lib().vrph_barcode_from_dist(self.h, _dev_ptr(D), D.shape[0], max_dim,
+                                                threshold, flags, _stream_ptr(), ctypes.byref(out)))
+        return Barcode(out)
+
+    def backward(self, X, edges, g_birth, g_death, gX):
+        """gX += scatter of g_birth/g_death onto the diameter edges (edges: int32 [npairs, 4])."""
+        import torch
+
+        X = self._f32(X)
+        edges = edges.to(torch.int32).contiguous()
+        g_birth, g_death = self._f32(g_birth), self._f32(g_death)
+        if not gX.is_contiguous():
+            raise ValueError("gX must be contiguous")
+        _check(lib().vrph_backward(self.h, _dev_ptr(X), X.shape[0], X.shape[1], _dev_ptr(edges),
+                                   edges.shape[0], _dev_ptr(g_birth), _dev_ptr(g_death),
+                                   _dev_ptr(gX), _stream_ptr()))
+        return gX
+
+    def batch(self, sizes, m, max_dim=1, threshold=float("inf"), keep_zero=False,
+              no_enclosing=False):
+        return Batch(self, sizes, m, max_dim, threshold, keep_zero, no_enclosing)
+
+
+class Batch:
+    """A batch plan: fixed cloud sizes, one captured graph replayed per forward."""
+
+    def __init__(self, ctx, sizes, m, max_dim, threshold, keep_zero, no_enclosing):
+        self.ctx = ctx
+        self.sizes = np.ascontiguousarray(sizes, dtype=np.int64)
+        flags = (KEEP_ZERO_PERSISTENCE if keep_zero else 0) | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
+        h = ctypes.c_void_p()
+        _check(lib().vrph_batch_plan(ctx.h, self.sizes.ctypes.data_as(ctypes.c_void_p),
+                                     len(self.sizes), m, max_dim, threshold, flags,
+                                     ctypes.byref(h)))
+        self.h = h
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)])
+
+    def forward(self, X_packed):
+        X_packed = Context._f32(X_packed)
+        _check(lib().vrph_batch_forward(self.h, _dev_ptr(X_packed), _stream_ptr()))
+        out = []
+        for i in range(len(self.sizes)):
+            v = ctypes.c_void_p()
+            _check(lib().vrph_batch_result(self.h, i, ctypes.byref(v)))
+            out.append(Barcode(v, owned=False))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vrph_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

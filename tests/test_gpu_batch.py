@@ -1,0 +1,132 @@
+"""Batched graph path and autograd on the GPU.
+
+The batch must reproduce, bit for bit, the single-cloud path and the oracle
+for every cloud; graph replays with new data must stay exact; the gradient
+must match the binary64 oracle gradient within 1e-5 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_05063_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2502_05063_amd import vrph
+
+    assert torch.cuda.is_available()
+    c = vrph.Context()
+    yield c
+    c.close()
+
+
+def packed(clouds):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(np.concatenate(clouds), np.float32)).cuda()
+
+
+def strip(pairs):
+    out = np.empty(len(pairs), oracle.PAIR_DTYPE)
+    for f in oracle.PAIR_DTYPE.names:
+        out[f] = pairs[f]
+    return out
+
+
+def test_small_batch_matches_single_path_and_oracle(ctx):
+    import torch
+
+    clouds = synth.circle_or_torus_batch(9, 20, 70, 0.05, seed=3)
+    b = ctx.batch([len(c) for c in clouds], 3, max_dim=1, keep_zero=True)
+    res = b.forward(packed(clouds))
+    for i, X in enumerate(clouds):
+        ref = oracle.barcode(oracle.pdist(X), 1)
+        assert np.array_equal(strip(res[i].pairs), ref), f"cloud {i} vs oracle"
+        single = ctx.barcode(X=torch.from_numpy(X).cuda(), max_dim=1, keep_zero=True)
+        assert np.array_equal(res[i].pairs, single.pairs), f"cloud {i} vs single path"
+    b.close()
+
+
+def test_graph_replay_with_new_data(ctx):
+    sizes = [33, 50, 64, 17]
+    b = ctx.batch(sizes, 3, max_dim=1)
+    for seed in range(4):
+        rng = np.random.default_rng(seed)
+        clouds = [synth.torus(n, 2.0, 0.5, 0.1, rng) for n in sizes]
+        res = b.forward(packed(clouds))
+        for i, X in enumerate(clouds):
+            ref = oracle.nonzero(oracle.barcode(oracle.pdist(X), 1))
+            assert np.array_equal(strip(res[i].pairs), ref), (seed, i)
+    b.close()
+
+
+def test_c4_full_batch(ctx):
+    """256 clouds of 50..400 points: every cloud equals the single-cloud path;
+    a sample of clouds equals the oracle."""
+    import torch
+
+    clouds = synth.circle_or_torus_batch(256, 50, 400, 0.05, seed=0)
+    b = ctx.batch([len(c) for c in clouds], 3, max_dim=1)
+    res = b.forward(packed(clouds))
+    for i, X in enumerate(clouds):
+        single = ctx.barcode(X=torch.from_numpy(X).cuda(), max_dim=1)
+        assert np.array_equal(res[i].pairs, single.pairs), f"cloud {i}"
+    for i in (0, 97, 255):
+        ref = oracle.nonzero(oracle.barcode(oracle.pdist(clouds[i]), 1))
+        assert np.array_equal(strip(res[i].pairs), ref), f"cloud {i} vs oracle"
+    b.close()
+
+
+def _oracle_grad(X, pairs, gb, gd):
+    P = strip(pairs)
+    return oracle.gradient(X, oracle.pdist(X), P, gb, gd)
+
+
+def test_autograd_single_cloud_matches_oracle_gradient(ctx):
+    import torch
+
+    from paper_2502_05063_amd.autograd import cloud_persistence
+
+    rng = np.random.default_rng(2)
+    X = synth.torus(120, 2.0, 0.5, 0.1, rng)
+    Xt = torch.from_numpy(X).cuda().requires_grad_(True)
+    b, d = cloud_persistence(Xt, ctx, dim=1)
+    loss = ((d - b) ** 2).sum()
+    loss.backward()
+    bc = ctx.barcode(X=Xt.detach(), max_dim=1)
+    h1 = bc.dim(1)
+    h1 = h1[h1["essential"] == 0]
+    pers = (h1["death_diam"] - h1["birth_diam"]).astype(np.float32)
+    G = _oracle_grad(X, h1, -2 * pers, 2 * pers)
+    err = np.abs(Xt.grad.cpu().numpy() - G).max() / np.abs(G).max()
+    assert err <= 1e-5, err
+
+
+def test_autograd_batch_matches_oracle_gradient(ctx):
+    import torch
+
+    from paper_2502_05063_amd.autograd import batch_persistence
+
+    clouds = synth.torus_batch(6, 90, 0.1, seed=4)
+    b = ctx.batch([len(c) for c in clouds], 3, max_dim=1)
+    Xt = packed(clouds).requires_grad_(True)
+    births, deaths, cloud = batch_persistence(Xt, b, dim=1)
+    loss = ((deaths - births) ** 2).sum()
+    loss.backward()
+    G = np.zeros((Xt.shape[0], 3))
+    res = b.forward(Xt.detach())
+    off = 0
+    for i, X in enumerate(clouds):
+        h1 = res[i].dim(1)
+        h1 = h1[h1["essential"] == 0]
+        pers = (h1["death_diam"] - h1["birth_diam"]).astype(np.float32)
+        G[off:off + len(X)] = _oracle_grad(X, h1, -2 * pers, 2 * pers)
+        off += len(X)
+    err = np.abs(Xt.grad.cpu().numpy() - G).max() / np.abs(G).max()
+    assert err <= 1e-5, err
+    b.close()

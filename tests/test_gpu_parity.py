@@ -1,0 +1,180 @@
+"""GPU path vs the CPU oracle, through the C ABI, element by element.
+
+Barcodes must match bit-exactly (indices and float32 diameters) given the
+same float32 distance matrix; distances from points must match the oracle's
+distances bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_05063_amd import synth
+
+pytestmark = pytest.mark.gpu
+INF = float("inf")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2502_05063_amd import vrph
+
+    assert torch.cuda.is_available()
+    c = vrph.Context()
+    yield c
+    c.close()
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def strip(pairs):
+    """GPU records -> the oracle's 32-byte records."""
+    out = np.empty(len(pairs), oracle.PAIR_DTYPE)
+    for f in oracle.PAIR_DTYPE.names:
+        out[f] = pairs[f]
+    return out
+
+
+def assert_same(gpu_pairs, orc_pairs, ctx_msg=""):
+    g = strip(gpu_pairs)
+    if len(g) != len(orc_pairs) or not np.array_equal(g, orc_pairs):
+        gs = set(map(tuple, g.tolist()))
+        os_ = set(map(tuple, orc_pairs.tolist()))
+        raise AssertionError(f"{ctx_msg}: {len(g)} vs {len(orc_pairs)} pairs; "
+                             f"gpu-only {sorted(gs - os_)[:5]} oracle-only {sorted(os_ - gs)[:5]}")
+
+
+# ---------------------------------------------------------------------------
+# distances
+
+
+@pytest.mark.parametrize("n,m,scale", [(64, 3, 1.0), (192, 4, 1.0), (1024, 9, 1.0), (200, 3, 1e-3),
+                                        (200, 5, 1e3), (1, 3, 1.0), (67, 1, 1.0)])
+def test_pdist_bitexact(ctx, n, m, scale):
+    rng = np.random.default_rng(n * 31 + m)
+    X = (rng.standard_normal((n, m)) * scale).astype(np.float32)
+    D = ctx.pdist(dev(X)).cpu().numpy()
+    assert np.array_equal(D.view(np.uint32), oracle.pdist(X).view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# full barcodes at oracle-friendly sizes
+
+
+def test_c1_cube64_full_list(ctx):
+    X = synth.uniform_cube(64, 3, seed=0)
+    bc = ctx.barcode(X=dev(X), max_dim=1, keep_zero=True)
+    ref = oracle.barcode(oracle.pdist(X), 1)
+    assert_same(bc.pairs, ref, "c1 keep_zero")
+    bc2 = ctx.barcode(X=dev(X), max_dim=1)
+    assert_same(bc2.pairs, oracle.nonzero(ref), "c1 nonzero")
+    s = bc.stats
+    assert s["columns"][1] == sum(1 for p in ref if p["dim"] == 1)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_sweep(ctx, seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(4, 48))
+    max_dim = int(rng.integers(1, 4)) if n <= 24 else int(rng.integers(1, 3))
+    kind = seed % 4
+    if kind == 0:
+        D = oracle.pdist(rng.random((n, 3)).astype(np.float32))
+    elif kind == 1:
+        D = synth.integer_distances(n, 4, seed)
+    elif kind == 2:
+        D = synth.permutation_distances(n, seed)
+    else:
+        D = oracle.pdist(synth.sphere(n, 2, seed))
+    thr = [INF, float(np.quantile(D[D > 0], 0.7))][seed % 2]
+    flags = [0, oracle.FLAG_NO_ENCLOSING][(seed // 2) % 2]
+    ref = oracle.barcode(D, max_dim, thr, flags=flags)
+    bc = ctx.barcode(D=dev(D), max_dim=max_dim, threshold=thr, keep_zero=True,
+                     no_enclosing=bool(flags))
+    assert_same(bc.pairs, ref, f"seed {seed} n {n} d {max_dim}")
+
+
+def test_ragged_tile_sizes(ctx):
+    """Sizes that leave ragged tails in every kernel's launch."""
+    for n in (2, 3, 65, 129):
+        X = synth.uniform_cube(n, 3, seed=n)
+        D = oracle.pdist(X)
+        md = 2 if n < 100 else 1
+        ref = oracle.barcode(D, md)
+        bc = ctx.barcode(D=dev(D), max_dim=md, keep_zero=True)
+        assert_same(bc.pairs, ref, f"n {n}")
+
+
+def test_all_equal_distances_thm_5_4_2(ctx):
+    for n0, d in ((9, 1), (9, 2), (8, 3)):
+        D = np.ones((n0, n0), np.float32) - np.eye(n0, dtype=np.float32)
+        bc = ctx.barcode(D=dev(D), max_dim=d, keep_zero=True)
+        assert bc.stats["apparent"][d] == __import__("math").comb(n0 - 1, d + 1)
+        assert_same(bc.pairs, oracle.barcode(D, d), f"equal {n0} {d}")
+
+
+def test_diameter_edges(ctx):
+    X = synth.uniform_cube(40, 3, seed=5)
+    D = oracle.pdist(X)
+    bc = ctx.barcode(D=dev(D), max_dim=2, keep_zero=True)
+    for p in bc.pairs[::7]:
+        if p["dim"] >= 1:
+            assert tuple(p["birth_edge"]) == oracle.diameter_edge(D, int(p["dim"]), int(p["birth"]))
+        if not p["essential"]:
+            assert tuple(p["death_edge"]) == oracle.diameter_edge(D, int(p["dim"]) + 1, int(p["death"]))
+
+
+def test_apparent_count_matches_definition(ctx):
+    X = synth.sphere(30, 2, seed=3)
+    D = oracle.pdist(X)
+    bc = ctx.barcode(D=dev(D), max_dim=2, keep_zero=True)
+    for d in (1, 2):
+        s, _ = oracle.apparent_pairs(D, d)
+        assert bc.stats["apparent"][d] == len(s)
+
+
+def test_deterministic(ctx):
+    X = synth.sphere(60, 3, seed=1)
+    a = ctx.barcode(X=dev(X), max_dim=2, keep_zero=True).pairs
+    for _ in range(3):
+        assert np.array_equal(a, ctx.barcode(X=dev(X), max_dim=2, keep_zero=True).pairs)
+
+
+# ---------------------------------------------------------------------------
+# error paths (forced from the host)
+
+
+def test_invalid_inputs_are_rejected(ctx):
+    from paper_2502_05063_amd import vrph
+
+    D = oracle.pdist(synth.uniform_cube(10, 3, 0))
+    bad = []
+    x = D.copy(); x[1, 2] = np.nan; bad.append(x)
+    x = D.copy(); x[1, 2] += 1; bad.append(x)
+    x = D.copy(); x[3, 3] = 1; bad.append(x)
+    x = D.copy(); x[1, 2] = x[2, 1] = -1; bad.append(x)
+    for B in bad:
+        with pytest.raises(vrph.VrphError) as e:
+            ctx.barcode(D=dev(B), max_dim=1)
+        assert e.value.status == vrph.EINVAL
+    with pytest.raises(vrph.VrphError):
+        ctx.barcode(D=dev(D), max_dim=7)
+    with pytest.raises(vrph.VrphError):
+        ctx.barcode(D=dev(D), max_dim=1, threshold=-1.0)
+    # the context still works afterwards
+    ref = oracle.barcode(D, 1)
+    assert_same(ctx.barcode(D=dev(D), max_dim=1, keep_zero=True).pairs, ref, "after errors")
+
+
+def test_index_overflow_is_reported(ctx):
+    from paper_2502_05063_amd import vrph
+
+    X = synth.uniform_cube(2048, 3, 0)
+    with pytest.raises(vrph.VrphError) as e:
+        ctx.barcode(X=dev(X), max_dim=6)
+    assert e.value.status == vrph.EOVERFLOW
