@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvroracle.so")
 SRC = os.path.join(HERE, "vr_oracle.c")
 
-M1_BOUNDARY, M1_COBOUNDARY, M2_STREAMED = 0, 1, 2
+M1_BOUNDARY, M1_COBOUNDARY, M2_STREAMED, M3_REDUCTION_MATRIX = 0, 1, 2, 3
 FLAG_NO_ENCLOSING, FLAG_NO_CLEARING = 1, 2
 
 PAIR_DTYPE = np.dtype(

@@ -774,6 +774,182 @@ static int barcode_coboundary(const ctx* c, int32_t max_dim, int streamed, int c
   return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Mode M3: the reduction-matrix technique (Sec. 5.2.9), streamed             */
+/* ------------------------------------------------------------------------ */
+
+/* binary max-heap of row keys */
+typedef struct {
+  u128* a;
+  int64_t len, cap;
+} heap;
+
+static int heap_push(heap* h, u128 k) {
+  if (h->len == h->cap) {
+    int64_t nc = h->cap ? 2 * h->cap : 256;
+    u128* na = (u128*)realloc(h->a, (size_t)nc * sizeof(u128));
+    if (!na) return ORC_ENOMEM;
+    h->a = na;
+    h->cap = nc;
+  }
+  int64_t i = h->len++;
+  h->a[i] = k;
+  while (i > 0 && h->a[(i - 1) / 2] < h->a[i]) {
+    u128 t = h->a[i];
+    h->a[i] = h->a[(i - 1) / 2];
+    h->a[(i - 1) / 2] = t;
+    i = (i - 1) / 2;
+  }
+  return ORC_OK;
+}
+
+static u128 heap_pop(heap* h) {
+  u128 top = h->a[0];
+  h->a[0] = h->a[--h->len];
+  int64_t i = 0;
+  for (;;) {
+    int64_t l = 2 * i + 1, r = l + 1, m = i;
+    if (l < h->len && h->a[l] > h->a[m]) m = l;
+    if (r < h->len && h->a[r] > h->a[m]) m = r;
+    if (m == i) break;
+    u128 t = h->a[i];
+    h->a[i] = h->a[m];
+    h->a[m] = t;
+    i = m;
+  }
+  return top;
+}
+
+/* The low of the column the heap holds: the largest key that appears an odd
+ * number of times (Z/2). Keys that cancel are removed; the low stays. */
+static int heap_low(heap* h, u128* low) {
+  while (h->len > 0) {
+    u128 t = heap_pop(h);
+    int count = 1;
+    while (h->len > 0 && h->a[0] == t) {
+      heap_pop(h);
+      count++;
+    }
+    if (count & 1) {
+      *low = t;
+      return heap_push(h, t) == ORC_OK ? 1 : -1;
+    }
+  }
+  return 0;
+}
+
+static int heap_add_coboundary(const ctx* c, const simplex* s, heap* h, col* scratch) {
+  if (coboundary(c, s, scratch)) return ORC_ENOMEM;
+  for (int64_t i = 0; i < scratch->len; i++)
+    if (heap_push(h, scratch->a[i])) return ORC_ENOMEM;
+  return ORC_OK;
+}
+
+typedef struct {
+  int64_t* a;
+  int64_t len, cap;
+} i64vec;
+
+static int iv_push(i64vec* v, int64_t x) {
+  if (v->len == v->cap) {
+    int64_t nc = v->cap ? 2 * v->cap : 8;
+    int64_t* na = (int64_t*)realloc(v->a, (size_t)nc * sizeof(int64_t));
+    if (!na) return ORC_ENOMEM;
+    v->a = na;
+    v->cap = nc;
+  }
+  v->a[v->len++] = x;
+  return ORC_OK;
+}
+
+static int cmp_i64(const void* x, const void* y) {
+  int64_t a = *(const int64_t*)x, b = *(const int64_t*)y;
+  return (a > b) - (a < b);
+}
+
+static int barcode_reduction_matrix(const ctx* c, int32_t max_dim, int clearing, orc_result* res) {
+  int rc = ORC_OK;
+  map64 deaths_prev = {0};
+  int have_prev = 0;
+  for (int32_t q = 0; q <= max_dim; q++) {
+    simplex_vec cols = {0};
+    map64 lookup = {0}, deaths = {0};
+    i64vec* V = NULL; /* V[j]: columns (indices into cols) added to column j */
+    heap h = {0};
+    col scratch = {0};
+    i64vec vj = {0};
+    if ((rc = columns_of_dim(c, q, have_prev ? &deaths_prev : NULL, clearing, &cols))) goto next;
+    res->columns[q] = cols.len;
+    V = (i64vec*)calloc((size_t)(cols.len ? cols.len : 1), sizeof(i64vec));
+    if (!V || (rc = map_init(&lookup, cols.len)) || (rc = map_init(&deaths, cols.len))) {
+      if (!rc) rc = ORC_ENOMEM;
+      goto next;
+    }
+    for (int64_t j = 0; j < cols.len; j++) {
+      u128 lo;
+      int64_t k;
+      int nonzero = coboundary_low(c, &cols.a[j], &lo);
+      vj.len = 0;
+      if (nonzero && map_get(&lookup, key_cidx(lo), &k)) {
+        /* the column is needed: build it, then add reduced columns R_k */
+        h.len = 0;
+        if ((rc = heap_add_coboundary(c, &cols.a[j], &h, &scratch))) goto next;
+        while (nonzero && map_get(&lookup, key_cidx(lo), &k)) {
+          if ((rc = heap_add_coboundary(c, &cols.a[k], &h, &scratch))) goto next;
+          if ((rc = iv_push(&vj, k))) goto next;
+          for (int64_t i = 0; i < V[k].len; i++) {
+            if ((rc = heap_add_coboundary(c, &cols.a[V[k].a[i]], &h, &scratch))) goto next;
+            if ((rc = iv_push(&vj, V[k].a[i]))) goto next;
+          }
+          nonzero = heap_low(&h, &lo);
+          if (nonzero < 0) {
+            rc = ORC_ENOMEM;
+            goto next;
+          }
+        }
+        /* V_j over Z/2 */
+        qsort(vj.a, (size_t)vj.len, sizeof(int64_t), cmp_i64);
+        for (int64_t a = 0; a < vj.len;) {
+          int64_t b = a;
+          while (b < vj.len && vj.a[b] == vj.a[a]) b++;
+          if (((b - a) & 1) && (rc = iv_push(&V[j], vj.a[a]))) goto next;
+          a = b;
+        }
+      }
+      if (nonzero) {
+        if ((rc = map_put(&lookup, key_cidx(lo), j))) goto next;
+        if ((rc = map_put(&deaths, key_cidx(lo), 1))) goto next;
+        if ((rc = pv_push(&res->pairs, make_pair(q, cols.a[j].cidx, cols.a[j].diam,
+                                                 key_cidx(lo), key_diam(lo)))))
+          goto next;
+      } else {
+        int64_t dummy;
+        if (have_prev && map_get(&deaths_prev, cols.a[j].cidx, &dummy)) continue;
+        if ((rc = pv_push(&res->pairs, make_essential(q, cols.a[j].cidx, cols.a[j].diam))))
+          goto next;
+      }
+    }
+  next:
+    if (V)
+      for (int64_t j = 0; j < cols.len; j++) free(V[j].a);
+    free(V);
+    free(h.a);
+    free(scratch.a);
+    free(vj.a);
+    free(cols.a);
+    map_free(&lookup);
+    if (have_prev) map_free(&deaths_prev);
+    if (rc) {
+      map_free(&deaths);
+      return rc;
+    }
+    deaths_prev = deaths;
+    have_prev = 1;
+  }
+  if (have_prev) map_free(&deaths_prev);
+  return ORC_OK;
+}
+
 int orc_barcode(const float* D, int64_t n, int32_t max_dim, float threshold, int32_t mode,
                 uint32_t flags, orc_result** out) {
   if (!out || max_dim < 0 || max_dim > 60) return ORC_EINVAL;
@@ -791,6 +967,8 @@ int orc_barcode(const float* D, int64_t n, int32_t max_dim, float threshold, int
   else if (mode == ORC_M1_COBOUNDARY || mode == ORC_M2_STREAMED)
     rc = barcode_coboundary(&c, max_dim, mode == ORC_M2_STREAMED,
                             !(flags & ORC_FLAG_NO_CLEARING), res);
+  else if (mode == ORC_M3_REDUCTION_MATRIX)
+    rc = barcode_reduction_matrix(&c, max_dim, !(flags & ORC_FLAG_NO_CLEARING), res);
   else
     rc = ORC_EINVAL;
   free(c.binom);

@@ -14,7 +14,7 @@
  *   simplices of dimension <= max_dim + 1. The persistence pairs are the
  *   pivots (low(j), j) of the standard reduction of the Z/2 boundary matrix of
  *   S (Alg. 2). Pivots do not depend on the reduction variant (Sec. 4.2), so
- *   three modes must agree:
+ *   all four modes must agree:
  *     ORC_M1_BOUNDARY   explicit boundary matrix, Alg. 2.
  *     ORC_M1_COBOUNDARY explicit anti-transposed (coboundary) matrix per
  *                       dimension (Def. 4.3.4, Prop. 4.3.5), Alg. 2, clearing
@@ -22,6 +22,12 @@
  *     ORC_M2_STREAMED   the same coboundary matrix, each column generated only
  *                       when it is reduced, oblivious reduction (Alg. 12,
  *                       equivalent by Lemma 5.2.10). Memory = pivots only.
+ *     ORC_M3_REDUCTION_MATRIX
+ *                       the same coboundary matrix, streamed, reduced with the
+ *                       reduction-matrix technique (Sec. 5.2.9): column j adds
+ *                       R_k = D_k + sum_{i in V_k} D_i, so its low only moves
+ *                       up; V_j is kept. The working column is a binary heap
+ *                       in which equal row keys cancel in pairs.
  *
  * Readings where the paper is silent (each also listed in the design doc):
  *   - tau_eff = min(tau, R), R = min_i max_j D_ij the enclosing radius
@@ -53,7 +59,7 @@ extern "C" {
 #define ORC_FLAG_NO_ENCLOSING 1u /* use tau as given, no enclosing-radius cut */
 #define ORC_FLAG_NO_CLEARING 2u  /* coboundary modes: reduce cleared columns too */
 
-enum { ORC_M1_BOUNDARY = 0, ORC_M1_COBOUNDARY = 1, ORC_M2_STREAMED = 2 };
+enum { ORC_M1_BOUNDARY = 0, ORC_M1_COBOUNDARY = 1, ORC_M2_STREAMED = 2, ORC_M3_REDUCTION_MATRIX = 3 };
 
 /* One persistence pair. birth/death are combinatorial indices (Eq. 5.6) of the
  * birth simplex (dimension dim) and death simplex (dimension dim+1). */

@@ -224,7 +224,7 @@ def test_lemma_5_4_9_apparent_edges_are_not_mst_edges(orc):
 # brute force from ranks (Thm 3.2.20 / Eq. 3.99)
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 @pytest.mark.parametrize(
     "n,max_dim,kind,seed",
     [(6, 1, "metric", 0), (7, 1, "metric", 1), (6, 2, "metric", 2), (6, 2, "ties", 3),
@@ -275,7 +275,7 @@ def test_modes_agree(orc, seed):
         D = synth.permutation_distances(n, seed)
     thr = [INF, float(np.quantile(D[D > 0], 0.6))][seed % 2]
     ref = orc.barcode(D, max_dim, thr, mode=orc.M1_BOUNDARY)
-    for mode in (orc.M1_COBOUNDARY, orc.M2_STREAMED):
+    for mode in (orc.M1_COBOUNDARY, orc.M2_STREAMED, orc.M3_REDUCTION_MATRIX):
         for flags in (0, orc.FLAG_NO_CLEARING):
             got = orc.barcode(D, max_dim, thr, mode=mode, flags=flags)
             assert np.array_equal(got, ref)
