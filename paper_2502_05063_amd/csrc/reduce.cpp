@@ -14,11 +14,37 @@ namespace vrph {
 
 using u128 = unsigned __int128;
 
-static inline u128 row_key(uint32_t diam, uint64_t c) {
-  return ((u128)(uint32_t)~diam << 64) | (u128)c;
-}
-static inline uint64_t key_index(u128 k) { return (uint64_t)k; }
-static inline uint32_t key_diam(u128 k) { return ~(uint32_t)(k >> 64); }
+// Row keys. A diameter is a non-negative float, so its bit pattern has a
+// zero sign bit and fits in 31 bits; when 31 + (bits of the largest cofacet
+// index) <= 64 the key is a u64 ((2^31-1 - diameter) above the index),
+// otherwise a u128 with the diameter in the high word.
+template <class K>
+struct Keys;
+
+template <>
+struct Keys<uint64_t> {
+  int cbits;
+  uint64_t make(uint32_t diam, uint64_t c) const {
+    return ((uint64_t)(0x7FFFFFFFu - diam) << cbits) | c;
+  }
+  uint64_t index(uint64_t k) const { return k & ((cbits == 64) ? ~0ull : ((1ull << cbits) - 1)); }
+  uint32_t diam(uint64_t k) const { return 0x7FFFFFFFu - (uint32_t)(k >> cbits); }
+  static int high_bit(uint64_t x) { return 63 - __builtin_clzll(x); }
+  static constexpr int kBits = 64;
+};
+
+template <>
+struct Keys<u128> {
+  int cbits;
+  u128 make(uint32_t diam, uint64_t c) const { return ((u128)(uint32_t)~diam << 64) | (u128)c; }
+  uint64_t index(u128 k) const { return (uint64_t)k; }
+  uint32_t diam(u128 k) const { return ~(uint32_t)(k >> 64); }
+  static int high_bit(u128 x) {
+    const uint64_t hi = (uint64_t)(x >> 64), lo = (uint64_t)x;
+    return hi ? 127 - __builtin_clzll(hi) : 63 - __builtin_clzll(lo);
+  }
+  static constexpr int kBits = 128;
+};
 
 void decode_simplex(const HostComplex& H, uint64_t c, int d, int* v) {
   int hi = H.n - 1;
@@ -98,13 +124,15 @@ static inline bool contains(const int* v, int d, int x) {
 // low(D_s): the oldest cofacet = smallest diameter, then largest index. The
 // first x from the top whose cofacet keeps the diameter is it; otherwise the
 // largest key over all cofacets.
-static bool oldest_cofacet(const HostComplex& H, const int* v, int d, uint32_t diam, u128* low) {
+template <class K>
+static bool oldest_cofacet(const HostComplex& H, const Keys<K>& ks, const int* v, int d,
+                           uint32_t diam, K* low) {
   bool found = false;
   for (int x = H.n - 1; x >= 0; --x) {
     if (contains(v, d, x)) continue;
     uint32_t m = reach(H, v, d, x);
     if (m == kInf) continue;
-    u128 k = row_key(std::max(diam, m), cofacet_index(H, v, d, x));
+    K k = ks.make(std::max(diam, m), cofacet_index(H, v, d, x));
     if (!found || k > *low) *low = k;
     found = true;
     if (m <= diam) break;
@@ -170,15 +198,16 @@ struct Simplex {
 // last extracted maximum; bucket 0 holds copies of that maximum, and since
 // equal keys cancel in pairs over Z/2 the maximum survives iff bucket 0 has
 // odd size.
+template <class K>
 class WorkColumn {
  public:
   void clear() {
     for (auto& b : b_) b.clear();
-    last_ = ~(u128)0;
+    last_ = ~(K)0;
   }
-  void push(u128 k) { b_[bucket(k)].push_back(k); }
+  void push(K k) { b_[bucket(k)].push_back(k); }
   // the pivot (largest key of odd multiplicity), kept; false if zero
-  bool pivot(u128* k) {
+  bool pivot(K* k) {
     for (;;) {
       if (b_[0].empty() && !refill()) return false;
       if (b_[0].size() & 1) {
@@ -191,28 +220,24 @@ class WorkColumn {
   }
 
  private:
-  static int high_bit(u128 x) {  // index of the highest set bit, x != 0
-    const uint64_t hi = (uint64_t)(x >> 64), lo = (uint64_t)x;
-    return hi ? 127 - __builtin_clzll(hi) : 63 - __builtin_clzll(lo);
-  }
-  int bucket(u128 k) const { return k == last_ ? 0 : high_bit(k ^ last_) + 1; }
+  int bucket(K k) const { return k == last_ ? 0 : Keys<K>::high_bit(k ^ last_) + 1; }
   bool refill() {
     int i = 1;
-    while (i < 129 && b_[i].empty()) ++i;
-    if (i == 129) return false;
-    std::vector<u128>& src = b_[i];
-    u128 m = src[0];
-    for (u128 x : src) m = x > m ? x : m;
+    while (i <= Keys<K>::kBits && b_[i].empty()) ++i;
+    if (i > Keys<K>::kBits) return false;
+    std::vector<K>& src = b_[i];
+    K m = src[0];
+    for (K x : src) m = x > m ? x : m;
     last_ = m;
-    std::vector<u128> moved;
+    std::vector<K> moved;
     moved.swap(src);
-    for (u128 x : moved) b_[bucket(x)].push_back(x);
+    for (K x : moved) b_[bucket(x)].push_back(x);
     moved.clear();
     moved.swap(src);  // keep the capacity
     return true;
   }
-  std::vector<u128> b_[129];
-  u128 last_ = ~(u128)0;
+  std::vector<K> b_[Keys<K>::kBits + 1];
+  K last_ = ~(K)0;
 };
 
 // Push the cofacets of one column with row key <= limit. Used to add a
@@ -222,14 +247,21 @@ class WorkColumn {
 // the index is kept incrementally: vertices of s above x contribute
 // C(v_i, i+2) (they moved up one position), those below C(v_i, i+1), and x
 // itself C(x, j+1) with j the number of vertices below it.
-static void push_coboundary(const HostComplex& H, uint64_t c, uint32_t diam, int d, u128 limit,
-                            WorkColumn& w) {
+template <class K>
+static void push_coboundary(const HostComplex& H, const Keys<K>& ks, uint64_t c, uint32_t diam,
+                            int d, K limit, WorkColumn<K>& w, uint32_t* reach_buf) {
   int v[kMaxDim + 3];
   decode_simplex(H, c, d, v);
+  // reach_buf[x] = max_i W(v_i, x): elementwise max of d+1 weight rows
+  const size_t n = (size_t)H.n;
+  const uint32_t* r0 = H.W + (size_t)v[0] * n;
+  for (size_t x = 0; x < n; ++x) reach_buf[x] = r0[x];
+  for (int i = 1; i <= d; ++i) {
+    const uint32_t* ri = H.W + (size_t)v[i] * n;
+    for (size_t x = 0; x < n; ++x) reach_buf[x] = std::max(reach_buf[x], ri[x]);
+  }
   uint64_t high = 0, low = c;
   int pos = d;  // vertices v[pos+1..d] are above x
-  const uint32_t* Wv[kMaxDim + 3];
-  for (int i = 0; i <= d; ++i) Wv[i] = H.W + (size_t)v[i] * (size_t)H.n;
   for (int x = H.n - 1; x >= 0; --x) {
     if (pos >= 0 && x == v[pos]) {
       high += H.C(v[pos], pos + 2);
@@ -237,35 +269,36 @@ static void push_coboundary(const HostComplex& H, uint64_t c, uint32_t diam, int
       --pos;
       continue;
     }
-    uint32_t m = 0;
-    for (int i = 0; i <= d; ++i) m = std::max(m, Wv[i][x]);
+    const uint32_t m = reach_buf[x];
     if (m == kInf) continue;
-    const u128 k = row_key(std::max(diam, m), high + H.C(x, pos + 2) + low);
+    const K k = ks.make(std::max(diam, m), high + H.C(x, pos + 2) + low);
     if (k <= limit) w.push(k);
   }
 }
 
-void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,
-                      std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
-                      ReduceStats& stats) {
+template <class K>
+static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Column* cols,
+                        int64_t ncols, std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
+                        ReduceStats& stats) {
   std::unordered_map<uint64_t, Partner> pivots;  // row index -> column, this dimension
   pivots.reserve((size_t)ncols * 2 + 16);
   std::vector<std::vector<Simplex>> vstore;       // V columns of the reduced columns
-  WorkColumn work;
+  WorkColumn<K> work;
   std::vector<Simplex> vj;
+  std::vector<uint32_t> reach_buf((size_t)H.n);
   int v[kMaxDim + 3], pv[kMaxDim + 3];
 
   // two-layer lookup (Fig. 5.10): pairs found by this reduction first, then
   // the apparent pairs, recognised from Def. 5.3.4 instead of a stored array
-  auto lookup = [&](u128 row, Partner* p) -> bool {
-    auto it = pivots.find(key_index(row));
+  auto lookup = [&](K row, Partner* p) -> bool {
+    auto it = pivots.find(ks.index(row));
     if (it != pivots.end()) {
       *p = it->second;
       return true;
     }
     uint64_t s;
-    if (apparent_partner(H, key_index(row), key_diam(row), d, &s, pv)) {
-      *p = Partner{s, key_diam(row), -1};
+    if (apparent_partner(H, ks.index(row), ks.diam(row), d, &s, pv)) {
+      *p = Partner{s, ks.diam(row), -1};
       return true;
     }
     return false;
@@ -275,21 +308,21 @@ void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t n
     const uint64_t c = cols[j].cidx;
     const uint32_t diam = ~cols[j].key_hi;
     decode_simplex(H, c, d, v);
-    u128 low;
+    K low;
     Partner p;
-    bool nonzero = oldest_cofacet(H, v, d, diam, &low);
+    bool nonzero = oldest_cofacet(H, ks, v, d, diam, &low);
     vj.clear();
     if (nonzero && lookup(low, &p)) {
       // Alg. 2 on column j: while its pivot is the pivot of an earlier column
       // k, add R_k = D_k + sum_{i in V_k} D_i (the pivot then moves up)
       work.clear();
-      push_coboundary(H, c, diam, d, low, work);
+      push_coboundary(H, ks, c, diam, d, low, work, reach_buf.data());
       for (;;) {
-        push_coboundary(H, p.c, p.diam, d, low, work);
+        push_coboundary(H, ks, p.c, p.diam, d, low, work, reach_buf.data());
         vj.push_back(Simplex{p.c, p.diam});
         if (p.v >= 0)
           for (const Simplex& q : vstore[p.v]) {
-            push_coboundary(H, q.c, q.diam, d, low, work);
+            push_coboundary(H, ks, q.c, q.diam, d, low, work, reach_buf.data());
             vj.push_back(q);
           }
         ++stats.additions;
@@ -317,13 +350,27 @@ void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t n
         vi = (int32_t)vstore.size();
         vstore.push_back(std::move(red));
       }
-      pivots.emplace(key_index(low), Partner{c, diam, vi});
-      pairs.push_back(PairRec{c, key_index(low), diam, key_diam(low)});
-      deaths.push_back(key_index(low));
+      pivots.emplace(ks.index(low), Partner{c, diam, vi});
+      pairs.push_back(PairRec{c, ks.index(low), diam, ks.diam(low)});
+      deaths.push_back(ks.index(low));
     } else {
       pairs.push_back(PairRec{c, ~0ull, diam, kInf});
     }
   }
+}
+
+void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,
+                      std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
+                      ReduceStats& stats) {
+  // bits of the largest cofacet index, C(n, d+2) - 1
+  const uint64_t top = H.C(H.n, d + 2);
+  const uint64_t largest = top ? top - 1 : 0;
+  int cbits = 1;
+  while (cbits < 64 && (largest >> cbits)) ++cbits;
+  if (31 + cbits <= 64)
+    reduce_keys<uint64_t>(H, Keys<uint64_t>{cbits}, d, cols, ncols, pairs, deaths, stats);
+  else
+    reduce_keys<u128>(H, Keys<u128>{64}, d, cols, ncols, pairs, deaths, stats);
 }
 
 }  // namespace vrph

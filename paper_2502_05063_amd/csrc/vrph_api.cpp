@@ -390,9 +390,15 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     const uint64_t ncand = H.C(n, d + 1);
     uint32_t* clear_in = bm + bm_off[d];
     uint32_t* clear_out = d < max_dim ? bm + bm_off[d + 1] : nullptr;
+    // output capacities grow on demand: the kernel counts past the end
+    // without writing, and the dimension runs again with the exact need
     uint64_t cap = c->cols.cap / sizeof(Column);
     if (cap < 4096) cap = std::min<uint64_t>(ncand, 1 << 16) + 1;
-    uint64_t ap_cap = keep_zero ? ncand : 0;
+    uint64_t ap_cap = 0;
+    if (keep_zero) {
+      ap_cap = c->ap.cap / sizeof(ApparentPair);
+      if (ap_cap < 4096) ap_cap = std::min<uint64_t>(ncand, 1 << 24) + 1;
+    }
     Scalars sc;
     for (int attempt = 0; attempt < 2; ++attempt) {
       HIP_TRY(c->cols.ensure(cap * sizeof(Column)));
@@ -415,10 +421,12 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       HIP_TRY(hipMemcpyAsync(c->h_scal.p, c->scal.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       std::memcpy(&sc, c->h_scal.p, sizeof(sc));
-      if (sc.nonapparent <= cap) break;
-      cap = sc.nonapparent + 1024;  // grow to the exact need and run the dimension again
+      if (sc.nonapparent <= cap && (!keep_zero || sc.apparent_written <= ap_cap)) break;
+      cap = std::max<uint64_t>(cap, sc.nonapparent + 1024);
+      if (keep_zero) ap_cap = std::max<uint64_t>(ap_cap, sc.apparent_written + 1024);
     }
-    if (sc.nonapparent > cap) return fail(VRPH_EDEVICE, "non-apparent column count changed between runs");
+    if (sc.nonapparent > cap || (keep_zero && sc.apparent_written > ap_cap))
+      return fail(VRPH_EDEVICE, "column counts changed between two runs of one dimension");
     const int64_t nna = (int64_t)sc.nonapparent;
     HIP_TRY(c->cols_tmp.ensure(std::max<int64_t>(nna, 1) * sizeof(Column)));
     HIP_TRY(c->sort_work.ensure(radix_sort_work_bytes(nna)));
