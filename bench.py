@@ -86,6 +86,10 @@ def batched_vs_plain(ctx, steps):
         out[f"{name}_ms"] = dt * 1e3
         out[f"{name}_clouds_per_s"] = len(clouds) / dt
     out["speedup"] = out["plain_ms"] / out["batched_ms"]
+    res = batch.forward(X.detach())
+    out["batched_graph_ms"] = res[0].stats["gpu_ms"][0]
+    out["batched_host_reduce_ms"] = res[0].stats["host_ms"][1]
+    out["batched_forward_total_ms"] = res[0].stats["total_ms"]
     out["workload"] = "64 noisy tori x 500 points in R^3 (sigma 0.1), dims 0-1, loss sum (death-birth)^2 over H1"
     batch.close()
     return out
@@ -98,7 +102,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (the reference for HBM counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)

@@ -54,6 +54,14 @@ typedef enum {
 /* flags */
 #define VRPH_KEEP_ZERO_PERSISTENCE 1u /* report every pair, also birth == death */
 #define VRPH_NO_ENCLOSING_RADIUS 2u   /* do not cut at the enclosing radius */
+/* Autotune: the first call that meets a (dimension, size bucket) not yet
+ * tuned times the enumeration + apparent-pairs kernel of that dimension at
+ * several tile sizes (simplices per workgroup; for dimension 1 the grid
+ * size), with HIP events, and keeps the fastest for the context. If
+ * the environment variable VRPH_TUNING_FILE names a file, tunings are read
+ * from it when the context is created and appended to it when found
+ * (lines "arch dimension size_bucket parameter"). */
+#define VRPH_AUTOTUNE 4u
 
 #define VRPH_MAX_DIM 6 /* largest supported max_dim */
 
@@ -91,7 +99,8 @@ typedef struct {
  *   gpu_ms          device time of dimension d's kernels (HIP events)
  *   apparent_ms     device time of the enumeration + apparent-pairs kernel
  *                   of dimension d alone (HIP events on the call's stream)
- *   host_ms         host time of dimension d's reduction                     */
+ *   host_ms         host time of dimension d's reduction
+ *   grid            workgroups launched by dimension d's enumeration kernel  */
 typedef struct {
   int64_t candidates[VRPH_MAX_DIM + 1];
   int64_t columns[VRPH_MAX_DIM + 1];
@@ -103,6 +112,8 @@ typedef struct {
   double gpu_ms[VRPH_MAX_DIM + 1];
   double apparent_ms[VRPH_MAX_DIM + 1];
   double host_ms[VRPH_MAX_DIM + 1];
+  int32_t grid[VRPH_MAX_DIM + 1];
+  int32_t pad_;
   float tau_eff;       /* the threshold actually applied */
   int32_t max_dim;
   double total_ms;     /* host wall time of the whole call */

@@ -130,6 +130,7 @@ __global__ __launch_bounds__(kBlock) void batch_pdist_kernel(const float* __rest
 hipError_t launch_batch_pdist(const float* X, int m, const Cloud* clouds, int count,
                               int64_t total_points, float* D, hipStream_t s) {
   if (total_points <= 0) return hipSuccess;
+  if (total_points > kMaxGroups) return hipErrorInvalidValue;
   batch_pdist_kernel<<<(unsigned)total_points, kBlock, 0, s>>>(X, m, clouds, count, D);
   return hipGetLastError();
 }
@@ -199,6 +200,7 @@ hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, in
                                          int64_t total_points, bool enclosing, uint32_t* W,
                                          CloudState* st, hipStream_t s) {
   if (total_points <= 0) return hipSuccess;
+  if (total_points > kMaxGroups) return hipErrorInvalidValue;
   batch_validate_kernel<<<(unsigned)total_points, kBlock, 0, s>>>(D, clouds, count, st);
   batch_weights_kernel<<<(unsigned)total_points, kBlock, 0, s>>>(D, clouds, count,
                                                                  enclosing ? 1 : 0, W, st);
@@ -208,9 +210,12 @@ hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, in
 // ---------------------------------------------------------------------------
 // H0 (Sec. 5.2.5): the pairs of dimension 0 are the merges of Kruskal's
 // algorithm over the edges in filtration order, i.e. the edges of the minimum
-// spanning forest under that total order. One workgroup per cloud:
-//   1. Prim's algorithm builds the forest (edge key = diameter bits, then
-//      reversed edge index, so the minimum key is the oldest edge);
+// spanning forest under that total order (unique, since the order is total).
+// One workgroup per cloud:
+//   1. Boruvka rounds build the forest: every component takes its minimum
+//      outgoing edge (key = diameter bits, then reversed edge index, so the
+//      minimum key is the oldest edge), components hook along those edges,
+//      pointer jumping relabels; at most log2(n) rounds;
 //   2. a bitonic sort in LDS puts the forest edges in filtration order;
 //   3. one lane runs union-find with the elder rule: each component is
 //      represented by its oldest vertex (the largest index); a merge kills
@@ -220,88 +225,91 @@ hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, in
 
 constexpr int kH0Threads = 256;
 
+__device__ __forceinline__ unsigned long long edge_key(uint32_t w, int a, int b) {
+  const uint64_t e = a > b ? edge_index(a, b) : edge_index(b, a);
+  return ((unsigned long long)w << 32) | (0xFFFFFFFFu - (uint32_t)e);
+}
+
 __global__ __launch_bounds__(kH0Threads) void batch_h0_kernel(const uint32_t* __restrict__ W,
                                                               const Cloud* __restrict__ clouds,
                                                               CloudState* __restrict__ st,
                                                               H0Pair* __restrict__ out,
                                                               int64_t out_stride,
                                                               uint32_t* __restrict__ bitmaps) {
-  __shared__ unsigned long long keyA[kMaxN];  // Prim keys, then parent/rep
+  __shared__ unsigned long long best[kMaxN];  // per component root: its minimum outgoing edge
   __shared__ unsigned long long mst[kMaxN];
-  __shared__ unsigned long long redk[2][kH0Threads / 64];
-  __shared__ int redv[2][kH0Threads / 64];
-  constexpr unsigned long long kDone = 0ull;  // marks a vertex already in the forest
-  constexpr unsigned long long kNone = ~0ull; // no edge to the forest yet
+  __shared__ int comp[kMaxN];                 // component root of every vertex
+  __shared__ int hookto[kMaxN];               // where a root moves this round
+  __shared__ int m_sh, changed;
+  constexpr unsigned long long kNone = ~0ull;
 
   const int c = blockIdx.x;
   const Cloud cl = clouds[c];
   const int n = cl.n;
   const uint32_t* Wc = W + cl.w_off;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
 
-  for (int v = tid; v < n; v += kH0Threads) keyA[v] = kNone;
+  for (int v = tid; v < n; v += kH0Threads) comp[v] = v;
+  if (tid == 0) m_sh = 0;
   __syncthreads();
 
-  int m = 0;  // forest edges so far (uniform across the workgroup)
-  for (int it = 0; it < n; ++it) {
-    // argmin over vertices not yet in the forest; among keys kNone (start of a
-    // new component) the largest vertex wins
-    unsigned long long bk = ~0ull;
-    int bv = -1;
-    for (int v = tid; v < n; v += kH0Threads) {
-      unsigned long long k = keyA[v];
-      if (k == kDone) continue;
-      if (bv < 0 || k < bk || (k == bk && v > bv)) {
-        bk = k;
-        bv = v;
+  for (;;) {
+    for (int v = tid; v < n; v += kH0Threads) best[v] = kNone;
+    if (tid == 0) changed = 0;
+    __syncthreads();
+    // minimum outgoing edge of every vertex, folded into its component
+    for (int u = tid; u < n; u += kH0Threads) {
+      const int cu = comp[u];
+      const uint32_t* Wu = Wc + (int64_t)u * n;
+      unsigned long long mk = kNone;
+      for (int v = 0; v < n; ++v) {
+        const uint32_t w = Wu[v];
+        if (w == kInf || comp[v] == cu) continue;
+        const unsigned long long k = edge_key(w, u, v);
+        mk = k < mk ? k : mk;
       }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      unsigned long long ok = shfl_xor_u64(bk, o);
-      int ov = __shfl_xor(bv, o);
-      if (ov >= 0 && (bv < 0 || ok < bk || (ok == bk && ov > bv))) {
-        bk = ok;
-        bv = ov;
-      }
-    }
-    const int buf = it & 1;
-    if (lane == 0) {
-      redk[buf][wave] = bk;
-      redv[buf][wave] = bv;
+      if (mk != kNone) atomicMin(&best[cu], mk);
     }
     __syncthreads();
-    bk = redk[buf][0];
-    bv = redv[buf][0];
-    for (int w = 1; w < kH0Threads / 64; ++w) {
-      unsigned long long ok = redk[buf][w];
-      int ov = redv[buf][w];
-      if (ov >= 0 && (bv < 0 || ok < bk || (ok == bk && ov > bv))) {
-        bk = ok;
-        bv = ov;
+    // every root decides, while best[] is read-only: its minimum edge goes to
+    // the forest (a mutual minimum edge, chosen by both components, is taken
+    // once, by the smaller root) and the root hooks to the other component
+    // (for a mutual edge only the larger root moves, so no cycle forms)
+    for (int r = tid; r < n; r += kH0Threads) {
+      hookto[r] = r;
+      if (comp[r] != r || best[r] == kNone) continue;
+      const unsigned long long k = best[r];
+      int a, b;
+      edge_vertices(0xFFFFFFFFu - (uint32_t)k, a, b);
+      const int other = comp[a] == r ? comp[b] : comp[a];
+      const bool mutual = best[other] == k;
+      if (!mutual || r < other) {
+        const int slot = atomicAdd(&m_sh, 1);
+        mst[slot] = k;
       }
+      if (!mutual || r > other) hookto[r] = other;
+      changed = 1;
     }
-    const int u = bv;
-    if (bk != kNone) {
-      if (tid == 0) mst[m] = bk;
-      ++m;
-    }
-    // u joins the forest; its owner marks it, every owner relaxes its vertices
-    const uint32_t* Wu = Wc + (int64_t)u * n;
-    for (int v = tid; v < n; v += kH0Threads) {
-      if (v == u) {
-        keyA[v] = kDone;
-        continue;
+    __syncthreads();
+    if (!changed) break;
+    for (int r = tid; r < n; r += kH0Threads)
+      if (comp[r] == r) comp[r] = hookto[r];
+    __syncthreads();
+    // relabel every vertex with its new root by pointer jumping
+    for (int it = 0; it < 32; ++it) {  // depth halves every step; 2^32 > n
+      int moved = 0;
+      for (int v = tid; v < n; v += kH0Threads) {
+        const int p = comp[v], pp = comp[p];
+        if (p != pp) {
+          comp[v] = pp;
+          moved = 1;
+        }
       }
-      unsigned long long k = keyA[v];
-      if (k == kDone) continue;
-      uint32_t w = Wu[v];
-      if (w == kInf) continue;
-      uint64_t e = u > v ? edge_index(u, v) : edge_index(v, u);
-      unsigned long long cand = ((unsigned long long)w << 32) | (0xFFFFFFFFu - (uint32_t)e);
-      if (cand < k) keyA[v] = cand;
+      __syncthreads();
+      if (!__syncthreads_or(moved)) break;
     }
   }
+  const int m = m_sh;
   __syncthreads();
 
   // bitonic sort of the m forest edges, ascending (padding with ~0)
@@ -333,12 +341,11 @@ __global__ __launch_bounds__(kH0Threads) void batch_h0_kernel(const uint32_t* __
     atomicOr(&bm[e >> 5], 1u << (e & 31));
   }
 
-  // union-find with the elder rule, one lane
-  int* parent = reinterpret_cast<int*>(keyA);
-  int* rep = parent + kMaxN;
+  // union-find with the elder rule, one lane (parent in comp[], rep in best[])
+  int* parent = comp;
   for (int v = tid; v < n; v += kH0Threads) {
     parent[v] = v;
-    rep[v] = v;
+    best[v] = (unsigned long long)v;
   }
   __syncthreads();
   if (tid == 0) {
@@ -358,10 +365,11 @@ __global__ __launch_bounds__(kH0Threads) void batch_h0_kernel(const uint32_t* __
         parent[rb] = parent[parent[rb]];
         rb = parent[rb];
       }
-      int young = rep[ra] < rep[rb] ? ra : rb;
+      const int rep_a = (int)best[ra], rep_b = (int)best[rb];
+      int young = rep_a < rep_b ? ra : rb;
       int old = young == ra ? rb : ra;
       o[k].death = e;
-      o[k].birth = (uint32_t)rep[young];
+      o[k].birth = (uint32_t)(young == ra ? rep_a : rep_b);
       o[k].diam = (uint32_t)(key >> 32);
       ++k;
       parent[young] = old;
@@ -369,7 +377,7 @@ __global__ __launch_bounds__(kH0Threads) void batch_h0_kernel(const uint32_t* __
     for (int v = 0; v < n; ++v)
       if (parent[v] == v) {
         o[k].death = ~0ull;
-        o[k].birth = (uint32_t)rep[v];
+        o[k].birth = (uint32_t)best[v];
         o[k].diam = kInf;
         ++k;
       }
@@ -475,10 +483,15 @@ __device__ __forceinline__ uint64_t wave_append(bool take, unsigned long long* c
 }
 
 // ---------------------------------------------------------------------------
-// Dimension-d enumeration + threshold + clearing + apparent test, one cloud.
-// Thread <-> candidate index c in [0, C(n, d+1)) (Alg. 17 launches one thread
-// per index). The candidate is decoded from Eq. 5.6 by binary search in the
-// LDS-resident binomial table, its diameter is the largest pairwise weight.
+// Dimension-d (d >= 2) enumeration + threshold + clearing + apparent test,
+// one cloud. The d-simplices (v_d > ... > v_0) are split into work units:
+// a unit fixes the prefix (v_d, ..., v_2) and covers a chunk of `chunk`
+// consecutive suffix indices k = C(v_1, 2) + v_0 < C(v_2, 2). The simplex
+// index (Eq. 5.6) is then base(prefix) + k, so consecutive lanes hold
+// consecutive indices and no lane decodes an index: the suffix follows from
+// one square root. Units are numbered with larger v_2 (more suffixes) first,
+// so the biggest units start first. unit_cum[i] counts the units of all
+// prefixes with v_2 > n-1-i (a table of n+1 entries built on the host).
 // Outputs: non-apparent columns (compacted, any order; the sort that follows
 // makes the order canonical), the clearing bits of the apparent cofacets for
 // dimension d+1, counts, and optionally every apparent pair.
@@ -486,66 +499,104 @@ __device__ __forceinline__ uint64_t wave_append(bool take, unsigned long long* c
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
-    const uint32_t* __restrict__ W, int n, const uint64_t* __restrict__ binom_g, int kmax,
-    uint64_t ncand, const uint32_t* __restrict__ clear_in, uint32_t* __restrict__ clear_out,
-    Column* __restrict__ cols, uint64_t cols_cap, ApparentPair* __restrict__ ap, uint64_t ap_cap,
-    Scalars* __restrict__ sc, int use_lds) {
-  extern __shared__ uint64_t lds_binom[];  // (D + 3) x (n + 1), k-major
+    const uint32_t* __restrict__ W, int n, const uint64_t* __restrict__ binom, int chunk,
+    const uint64_t* __restrict__ unit_cum, uint64_t units, const uint32_t* __restrict__ clear_in,
+    uint32_t* __restrict__ clear_out, Column* __restrict__ cols, uint64_t cols_cap,
+    ApparentPair* __restrict__ ap, uint64_t ap_cap, Scalars* __restrict__ sc) {
   const int np1 = n + 1;
-  const uint64_t* binom = binom_g;
-  if (use_lds) {
-    for (int i = threadIdx.x; i < (D + 3) * np1; i += blockDim.x) lds_binom[i] = binom_g[i];
-    __syncthreads();
-    binom = lds_binom;
-  }
-
+  auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
   unsigned long long n_cols = 0, n_app = 0, n_steps = 0;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < ncand; base += stride) {
-    const uint64_t c = base + threadIdx.x;
+
+  // units are strided over the workgroups (a dispatch holds < 2^32 work-items)
+  for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
+  // ---- the unit: prefix (v_d..v_2) and its suffix range (uniform) ----
+  int lo = 0, hi = n - 2;  // largest i with unit_cum[i] <= u; v_2 = n-1-i
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (unit_cum[mid] <= u)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int t = n - 1 - lo;
+  const uint64_t suffixes = (uint64_t)t * (uint64_t)(t - 1) / 2;
+  const uint64_t chunks = (suffixes + chunk - 1) / chunk;
+  const uint64_t q = u - unit_cum[lo];
+  uint64_t upper = q / chunks;  // rank of (v_d..v_3) among (d-2)-subsets of (t, n)
+  const uint64_t k_begin = (q % chunks) * (uint64_t)chunk;
+  const uint64_t k_end = min(k_begin + (uint64_t)chunk, suffixes);
+  int v[D + 1];
+  v[2] = t;
+  {
+    int top = n - 1 - (t + 1);  // decode in the shifted range [0, n-1-t)
+#pragma unroll
+    for (int i = D - 2; i >= 1; --i) {  // position i of the upper part -> v[i+2]
+      int a = i - 1, h = top;
+      while (a < h) {
+        int mid = (a + h + 1) >> 1;
+        if (C(mid, i) <= upper)
+          a = mid;
+        else
+          h = mid - 1;
+      }
+      v[i + 2] = a + t + 1;
+      upper -= C(a, i);
+      top = a - 1;
+    }
+  }
+  uint64_t base = 0;
+#pragma unroll
+  for (int i = 2; i <= D; ++i) base += C(v[i], i + 1);
+  uint32_t pmax = 0;  // largest weight among the prefix vertices
+#pragma unroll
+  for (int i = 3; i <= D; ++i)
+#pragma unroll
+    for (int j = 2; j < i; ++j) pmax = max(pmax, W[(int64_t)v[i] * n + v[j]]);
+  // a prefix with an edge above the threshold spans no simplex of the
+  // complex: the whole unit is skipped (uniform across the workgroup); this
+  // is what keeps a threshold far below the enclosing radius cheap
+  if (pmax == kInf) continue;
+
+  for (uint64_t kb = k_begin; kb < k_end; kb += kBlock) {
+    const uint64_t k = kb + threadIdx.x;
     bool is_col = false, is_app = false;
-    int v[D + 1];
     uint32_t pw[D + 1][D + 1];
     uint32_t diam = kInf;
-    uint64_t t = 0;
-    if (c < ncand) {
-      // decode: position i holds the largest v with C(v, i+1) <= remainder
-      uint64_t rem = c;
-      int hi = n - 1;
+    uint64_t c = 0, tcidx = 0;
+    int vv[D + 1];
 #pragma unroll
-      for (int i = D; i >= 1; --i) {
-        const uint64_t* col = binom + (i + 1) * np1;
-        int lo = i, h = hi;
-        while (lo < h) {
-          int mid = (lo + h + 1) >> 1;
-          if (col[mid] <= rem)
-            lo = mid;
-          else
-            h = mid - 1;
-        }
-        v[i] = lo;
-        rem -= col[lo];
-        hi = lo - 1;
-      }
-      v[0] = (int)rem;
-      diam = 0;
+    for (int i = 2; i <= D; ++i) vv[i] = v[i];
+    if (k < k_end) {
+      // suffix: largest v1 with C(v1, 2) <= k, then v0
+      int v1 = (int)((1.0f + sqrtf(8.0f * (float)k + 1.0f)) * 0.5f);
+      while ((uint64_t)v1 * (v1 - 1) / 2 > k) --v1;
+      while ((uint64_t)(v1 + 1) * v1 / 2 <= k) ++v1;
+      vv[1] = v1;
+      vv[0] = (int)(k - (uint64_t)v1 * (v1 - 1) / 2);
+      c = base + k;
+      diam = pmax;
 #pragma unroll
       for (int i = 1; i <= D; ++i)
 #pragma unroll
         for (int j = 0; j < i; ++j) {
-          pw[i][j] = W[(int64_t)v[i] * n + v[j]];
+          if (j >= 2) continue;  // prefix pairs are folded into pmax
+          pw[i][j] = W[(int64_t)vv[i] * n + vv[j]];
           diam = max(diam, pw[i][j]);
         }
+#pragma unroll
+      for (int i = 3; i <= D; ++i)
+#pragma unroll
+        for (int j = 2; j < i; ++j) pw[i][j] = W[(int64_t)vv[i] * n + vv[j]];
       const bool cleared = clear_in && ((clear_in[c >> 5] >> (c & 31)) & 1u);
       is_col = diam != kInf && !cleared;
       if (is_col) {
         ++n_cols;
-        const int x = apparent_cofacet<D>(W, n, v, pw, diam, n_steps);
+        const int x = apparent_cofacet<D>(W, n, vv, pw, diam, n_steps);
         if (x >= 0) {
           is_app = true;
           ++n_app;
-          t = cofacet_index<D>(v, x, binom, np1);
-          if (clear_out) atomicOr(&clear_out[t >> 5], 1u << (t & 31));
+          tcidx = cofacet_index<D>(vv, x, binom, np1);
+          if (clear_out) atomicOr(&clear_out[tcidx >> 5], 1u << (tcidx & 31));
         }
       }
     }
@@ -563,13 +614,14 @@ __global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
       if (is_app && as < ap_cap) {
         ApparentPair p;
         p.s = c;
-        p.t = t;
+        p.t = tcidx;
         p.diam = diam;
         p.cloud = 0;
         ap[as] = p;
       }
     }
   }
+  }  // units
   // workgroup totals, one atomic each
   __shared__ unsigned long long red[3][kBlock / 64];
   for (int o = 32; o > 0; o >>= 1) {
@@ -597,32 +649,31 @@ __global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
 }
 
 template <int D>
-static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom, int kmax,
-                                uint64_t ncand, const uint32_t* clear_in, uint32_t* clear_out,
-                                Column* cols, uint64_t cols_cap, ApparentPair* ap,
-                                uint64_t ap_cap, Scalars* sc, hipStream_t s, int grid) {
-  // the binomial columns 0..D+2 live in LDS when they fit in 48 KiB
-  size_t lds = (size_t)(D + 3) * (size_t)(n + 1) * sizeof(uint64_t);
-  const int use_lds = lds <= 48 * 1024;
-  enum_apparent_kernel<D><<<grid, kBlock, use_lds ? lds : 0, s>>>(
-      W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, use_lds);
+static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom, int chunk,
+                                const uint64_t* unit_cum, uint64_t units, unsigned grid,
+                                const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
+                                uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap, Scalars* sc,
+                                hipStream_t s) {
+  enum_apparent_kernel<D><<<grid, kBlock, 0, s>>>(W, n, binom, chunk, unit_cum, units, clear_in,
+                                                  clear_out, cols, cols_cap, ap, ap_cap, sc);
   return hipGetLastError();
 }
 
-hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int kmax,
-                                uint64_t ncand, const uint32_t* clear_in, uint32_t* clear_out,
-                                Column* cols, uint64_t cols_cap, ApparentPair* ap,
-                                uint64_t ap_cap, Scalars* sc, int grid, hipStream_t s) {
-  if (ncand == 0) return hipSuccess;
-  uint64_t need = (ncand + kBlock - 1) / kBlock;
-  if ((uint64_t)grid > need) grid = (int)need;
+hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,
+                                const uint64_t* unit_cum, uint64_t units,
+                                const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
+                                uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap, Scalars* sc,
+                                hipStream_t s) {
+  if (units == 0) return hipSuccess;
+  if (chunk < kBlock || chunk % kBlock) return hipErrorInvalidValue;
+  // at most kMaxGroups workgroups: the dispatch counts work-items in 32 bits
+  const unsigned grid = (unsigned)(units < (uint64_t)kMaxGroups ? units : (uint64_t)kMaxGroups);
   switch (d) {
-    case 1: return launch_enum_D<1>(W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s, grid);
-    case 2: return launch_enum_D<2>(W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s, grid);
-    case 3: return launch_enum_D<3>(W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s, grid);
-    case 4: return launch_enum_D<4>(W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s, grid);
-    case 5: return launch_enum_D<5>(W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s, grid);
-    case 6: return launch_enum_D<6>(W, n, binom, kmax, ncand, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s, grid);
+    case 2: return launch_enum_D<2>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
+    case 3: return launch_enum_D<3>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
+    case 4: return launch_enum_D<4>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
+    case 5: return launch_enum_D<5>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
+    case 6: return launch_enum_D<6>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -8,6 +8,8 @@
 #include "reduce.h"
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <unordered_map>
 
 namespace vrph {
@@ -276,17 +278,57 @@ static void push_coboundary(const HostComplex& H, const Keys<K>& ks, uint64_t c,
   }
 }
 
+// What a column needs before the sequential pass, independent of every other
+// column: its first pivot low(D_j) and, if that row is the cofacet of an
+// apparent pair, the apparent column.
+template <class K>
+struct FirstPivot {
+  K low;
+  uint64_t apparent;  // the apparent column owning `low`, if has_apparent
+  bool nonzero;
+  bool has_apparent;
+};
+
+template <class K>
+static void first_pivots(const HostComplex& H, const Keys<K>& ks, int d, const Column* cols,
+                         int64_t ncols, int threads, std::vector<FirstPivot<K>>& out) {
+  out.resize((size_t)ncols);
+  std::atomic<int64_t> next{0};
+  auto work = [&]() {
+    int v[kMaxDim + 3], sv[kMaxDim + 3];
+    for (;;) {
+      const int64_t j0 = next.fetch_add(256);
+      if (j0 >= ncols) return;
+      const int64_t j1 = std::min<int64_t>(ncols, j0 + 256);
+      for (int64_t j = j0; j < j1; ++j) {
+        FirstPivot<K>& f = out[(size_t)j];
+        decode_simplex(H, cols[j].cidx, d, v);
+        f.nonzero = oldest_cofacet(H, ks, v, d, ~cols[j].key_hi, &f.low);
+        f.has_apparent =
+            f.nonzero && apparent_partner(H, ks.index(f.low), ks.diam(f.low), d, &f.apparent, sv);
+      }
+    }
+  };
+  threads = (int)std::max<int64_t>(1, std::min<int64_t>(threads, ncols / 1024));
+  std::vector<std::thread> pool;
+  for (int i = 1; i < threads; ++i) pool.emplace_back(work);
+  work();
+  for (std::thread& t : pool) t.join();
+}
+
 template <class K>
 static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Column* cols,
-                        int64_t ncols, std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
-                        ReduceStats& stats) {
+                        int64_t ncols, int threads, std::vector<PairRec>& pairs,
+                        std::vector<uint64_t>& deaths, ReduceStats& stats) {
   std::unordered_map<uint64_t, Partner> pivots;  // row index -> column, this dimension
   pivots.reserve((size_t)ncols * 2 + 16);
   std::vector<std::vector<Simplex>> vstore;       // V columns of the reduced columns
   WorkColumn<K> work;
   std::vector<Simplex> vj;
   std::vector<uint32_t> reach_buf((size_t)H.n);
-  int v[kMaxDim + 3], pv[kMaxDim + 3];
+  int pv[kMaxDim + 3];
+  std::vector<FirstPivot<K>> first;
+  first_pivots(H, ks, d, cols, ncols, threads, first);
 
   // two-layer lookup (Fig. 5.10): pairs found by this reduction first, then
   // the apparent pairs, recognised from Def. 5.3.4 instead of a stored array
@@ -307,12 +349,25 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
   for (int64_t j = 0; j < ncols; ++j) {
     const uint64_t c = cols[j].cidx;
     const uint32_t diam = ~cols[j].key_hi;
-    decode_simplex(H, c, d, v);
-    K low;
+    const FirstPivot<K>& f = first[(size_t)j];
+    K low = f.low;
     Partner p;
-    bool nonzero = oldest_cofacet(H, ks, v, d, diam, &low);
+    bool nonzero = f.nonzero;
+    bool taken = false;
+    if (nonzero) {
+      if (f.has_apparent) {
+        p = Partner{f.apparent, ks.diam(low), -1};
+        taken = true;
+      } else {
+        auto it = pivots.find(ks.index(low));
+        if (it != pivots.end()) {
+          p = it->second;
+          taken = true;
+        }
+      }
+    }
     vj.clear();
-    if (nonzero && lookup(low, &p)) {
+    if (taken) {
       // Alg. 2 on column j: while its pivot is the pivot of an earlier column
       // k, add R_k = D_k + sum_{i in V_k} D_i (the pivot then moves up)
       work.clear();
@@ -360,7 +415,7 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
 }
 
 void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,
-                      std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
+                      int threads, std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
                       ReduceStats& stats) {
   // bits of the largest cofacet index, C(n, d+2) - 1
   const uint64_t top = H.C(H.n, d + 2);
@@ -368,9 +423,10 @@ void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t n
   int cbits = 1;
   while (cbits < 64 && (largest >> cbits)) ++cbits;
   if (31 + cbits <= 64)
-    reduce_keys<uint64_t>(H, Keys<uint64_t>{cbits}, d, cols, ncols, pairs, deaths, stats);
+    reduce_keys<uint64_t>(H, Keys<uint64_t>{cbits}, d, cols, ncols, threads, pairs, deaths,
+                          stats);
   else
-    reduce_keys<u128>(H, Keys<u128>{64}, d, cols, ncols, pairs, deaths, stats);
+    reduce_keys<u128>(H, Keys<u128>{64}, d, cols, ncols, threads, pairs, deaths, stats);
 }
 
 }  // namespace vrph

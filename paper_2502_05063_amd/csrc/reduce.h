@@ -34,10 +34,12 @@ struct ReduceStats {
 // column is a lazy max-heap). A column whose first pivot is free is paired
 // without building it (the emergent case of Sec. 5.2.11). Pivot lookups go to a hash map of the pairs found so far,
 // then to the apparent pairs, recognised on the fly from Def. 5.3.4 instead
-// of a stored array. Appends the pairs of dimension d
-// to `pairs` and the death indices to `deaths`.
+// of a stored array. The first pivot of every column, and whether it belongs
+// to an apparent pair, do not depend on the other columns: they are found
+// first, on `threads` host threads. Appends the pairs of dimension d to
+// `pairs` and the death indices to `deaths`.
 void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,
-                      std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
+                      int threads, std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
                       ReduceStats& stats);
 
 // Vertices v[d] > ... > v[0] of simplex `c` of dimension d (Eq. 5.6).

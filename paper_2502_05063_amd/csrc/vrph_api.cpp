@@ -9,7 +9,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <memory>
 #include <new>
 #include <string>
@@ -140,6 +144,11 @@ int bits_needed(uint64_t x) {
   return b;
 }
 
+int host_threads() {
+  const unsigned hc = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(16u, hc ? hc : 1u));
+}
+
 double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
@@ -160,7 +169,56 @@ struct vrph_ctx {
   HostPinned h_scal, h_cstate;
   std::vector<uint64_t> h_binom;
   int binom_n = -1, binom_k = -1;
+  std::string arch;
+  // (dimension, size bucket) -> tuned parameter: suffixes per workgroup for
+  // d >= 2, grid multiplier for d = 1
+  std::map<std::pair<int, int>, int> tuned;
+  DevBuf units;                    // unit table of the d >= 2 enumeration
+  std::vector<uint64_t> h_units;
 };
+
+// Work units of the d >= 2 enumeration kernel for tile `chunk`: cum[i] counts
+// the units of all prefixes (v_d..v_2) with v_2 > n-1-i; a prefix with v_2 = t
+// has C(n-1-t, d-2) choices of (v_d..v_3) and ceil(C(t,2)/chunk) chunks.
+static uint64_t enum_units(int n, int d, int chunk, const std::vector<uint64_t>& binom,
+                           std::vector<uint64_t>& cum) {
+  auto C = [&](int v, int k) -> uint64_t { return binom[(size_t)k * (n + 1) + v]; };
+  cum.assign((size_t)n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    const int t = n - 1 - i;
+    uint64_t u = 0;
+    if (t >= 2) {
+      const uint64_t suf = (uint64_t)t * (t - 1) / 2;
+      u = C(n - 1 - t, d - 2) * ((suf + chunk - 1) / chunk);
+    }
+    cum[i + 1] = cum[i] + u;
+  }
+  return cum[n];
+}
+
+// Autotuning of the enumeration kernels' grid (see VRPH_AUTOTUNE).
+static int size_bucket(int n) {
+  int b = 1;
+  while (b < n) b <<= 1;
+  return b;
+}
+
+static void load_tuning(vrph_ctx* c) {
+  const char* path = std::getenv("VRPH_TUNING_FILE");
+  if (!path) return;
+  std::ifstream f(path);
+  std::string arch;
+  int d, b, g;
+  while (f >> arch >> d >> b >> g)
+    if (arch == c->arch && g > 0 && g <= 256) c->tuned[{d, b}] = g;
+}
+
+static void save_tuning(vrph_ctx* c, int d, int b, int g) {
+  const char* path = std::getenv("VRPH_TUNING_FILE");
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << c->arch << " " << d << " " << b << " " << g << "\n";
+}
 
 struct vrph_barcode {
   std::vector<vrph_pair> pairs;  // canonical order
@@ -181,6 +239,9 @@ extern "C" vrph_status vrph_create(int device, vrph_ctx** out) {
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, device));
   c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->arch = prop.gcnArchName;
+  c->arch = c->arch.substr(0, c->arch.find(':'));
+  load_tuning(c.get());
   // a blocking stream: ordered against the legacy default stream, which is where
   // torch puts work when the caller passes stream 0
   HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamDefault));
@@ -197,7 +258,7 @@ extern "C" void vrph_destroy(vrph_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->D,   &c->W,     &c->binom,     &c->bitmaps, &c->cols,
                     &c->cols_tmp, &c->sort_work, &c->ap, &c->scal, &c->clouds,
-                    &c->cstate, &c->h0, &c->deaths};
+                    &c->cstate, &c->h0, &c->deaths, &c->units};
   for (DevBuf* b : bufs) b->release();
   c->h_scal.release();
   c->h_cstate.release();
@@ -400,23 +461,69 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       if (ap_cap < 4096) ap_cap = std::min<uint64_t>(ncand, 1 << 24) + 1;
     }
     Scalars sc;
+    Scalars* dsc = c->scal.as<Scalars>();
+    HIP_TRY(c->cols.ensure(cap * sizeof(Column)));
+    if (keep_zero) HIP_TRY(c->ap.ensure(std::max<uint64_t>(ap_cap, 1) * sizeof(ApparentPair)));
+    // the launch of dimension d with tuning parameter `param`: suffixes per
+    // workgroup (d >= 2) or grid multiplier (d = 1); returns the workgroups
+    uint64_t launched = 0;
+    auto launch_dim = [&](int param) -> hipError_t {
+      if (d == 1) {
+        launched = (uint64_t)c->num_cus * param;
+        return launch_batch_edges(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1, (int64_t)ncand,
+                                  clear_in, c->cols.as<Column>(), cap,
+                                  keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
+                                  clear_out, &dsc->columns, c->num_cus * param, s);
+      }
+      launched = enum_units(n, d, param, c->h_binom, c->h_units);
+      hipError_t e = c->units.ensure(c->h_units.size() * sizeof(uint64_t));
+      if (e != hipSuccess) return e;
+      e = hipMemcpyAsync(c->units.p, c->h_units.data(), c->h_units.size() * sizeof(uint64_t),
+                         hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) return e;
+      e = launch_enum_apparent(d, c->W.as<uint32_t>(), n, c->binom.as<uint64_t>(), param,
+                               c->units.as<uint64_t>(), launched, clear_in, clear_out,
+                               c->cols.as<Column>(), cap,
+                               keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap, dsc, s);
+      // the host table is consumed by the copy before the next launch reuses it
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      return e;
+    };
+    const std::pair<int, int> tkey{d, size_bucket(n)};
+    int param = d == 1 ? 8 : 1024;
+    auto it = c->tuned.find(tkey);
+    if (it != c->tuned.end()) {
+      param = it->second;
+    } else if (flags & VRPH_AUTOTUNE) {
+      // time each setting on this very input; outputs are rewritten by the run below
+      const std::vector<int> grid_mults = {1, 2, 4, 8, 16, 32, 64};
+      const std::vector<int> tiles = {256, 512, 1024, 2048, 4096, 8192};
+      float best = 0;
+      bool first = true;
+      for (int g : (d == 1 ? grid_mults : tiles)) {
+        HIP_TRY(hipMemsetAsync(c->scal.p, 0, sizeof(Scalars), s));
+        HIP_TRY(hipEventRecord(c->ev0, s));
+        HIP_TRY(launch_dim(g));
+        HIP_TRY(hipEventRecord(c->ev1, s));
+        HIP_TRY(hipEventSynchronize(c->ev1));
+        float t = 0;
+        HIP_TRY(hipEventElapsedTime(&t, c->ev0, c->ev1));
+        if (first || t < best) {
+          best = t;
+          param = g;
+          first = false;
+        }
+      }
+      c->tuned[tkey] = param;
+      save_tuning(c, d, tkey.second, param);
+    }
     for (int attempt = 0; attempt < 2; ++attempt) {
       HIP_TRY(c->cols.ensure(cap * sizeof(Column)));
       if (keep_zero) HIP_TRY(c->ap.ensure(std::max<uint64_t>(ap_cap, 1) * sizeof(ApparentPair)));
       HIP_TRY(hipMemsetAsync(c->scal.p, 0, sizeof(Scalars), s));
       HIP_TRY(hipEventRecord(c->ev0, s));
-      Scalars* dsc = c->scal.as<Scalars>();
-      if (d == 1) {
-        HIP_TRY(launch_batch_edges(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1, (int64_t)ncand,
-                                   clear_in, c->cols.as<Column>(), cap,
-                                   keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
-                                   clear_out, &dsc->columns, c->num_cus * 8, s));
-      } else {
-        HIP_TRY(launch_enum_apparent(d, c->W.as<uint32_t>(), n, c->binom.as<uint64_t>(), kmax,
-                                     ncand, clear_in, clear_out, c->cols.as<Column>(), cap,
-                                     keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap, dsc,
-                                     c->num_cus * 8, s));
-      }
+      HIP_TRY(launch_dim(param));
+      bc->stats.grid[d] = (int32_t)std::min<uint64_t>(launched, 0x7FFFFFFF);
       HIP_TRY(hipEventRecord(c->ev2, s));
       HIP_TRY(hipMemcpyAsync(c->h_scal.p, c->scal.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
@@ -456,7 +563,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     prs.clear();
     deaths.clear();
     ReduceStats rs;
-    reduce_dimension(H, d, hcols.data(), nna, prs, deaths, rs);
+    reduce_dimension(H, d, hcols.data(), nna, host_threads(), prs, deaths, rs);
     bc->stats.additions[d] = rs.additions;
     for (const PairRec& r : prs) bc->pairs.push_back(make_pair(d, r.birth, r.bdiam, r.death, r.ddiam));
     if (keep_zero)
@@ -546,12 +653,11 @@ struct vrph_batch {
   int64_t total_points = 0, total_w = 0, total_edges = 0, total_words = 0;
   int max_kmax = 0;
   DevBuf X, D, W, dclouds, cstate, h0, bitmaps, cols, cols_tmp, sort_work, ap, counters;
-  HostPinned h_cstate, h_counters;
+  HostPinned h_cstate, h_counters, h_W;  // h_W: every cloud's weights, read by the host reduction
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<std::vector<uint64_t>> binoms;  // per cloud, k-major (kmax+1) x (n+1)
   std::vector<vrph_barcode> results;
-  std::vector<uint32_t> hW;
   std::vector<H0Pair> hh0;
   std::vector<Column> hcols;
   std::vector<ApparentPair> hap;
@@ -614,6 +720,7 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
   HIP_TRY(b->counters.ensure(sizeof(Scalars)));
   HIP_TRY(b->h_cstate.ensure((size_t)count * sizeof(CloudState)));
   HIP_TRY(b->h_counters.ensure(sizeof(Scalars)));
+  HIP_TRY(b->h_W.ensure((size_t)b->total_w * 4));
   HIP_TRY(hipMemcpy(b->dclouds.p, b->clouds.data(), (size_t)count * sizeof(Cloud),
                     hipMemcpyHostToDevice));
   b->results.resize(count);
@@ -632,6 +739,7 @@ extern "C" void vrph_batch_destroy(vrph_batch* b) {
   for (DevBuf* d : bufs) d->release();
   b->h_cstate.release();
   b->h_counters.release();
+  b->h_W.release();
   delete b;
 }
 
@@ -723,10 +831,9 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
   // results of the device part
   const bool keep_zero = b->flags & VRPH_KEEP_ZERO_PERSISTENCE;
   const int64_t nna = (int64_t)sc.nonapparent;
-  b->hW.resize((size_t)b->total_w);
   b->hh0.resize((size_t)b->count * b->max_n);
   b->hcols.resize((size_t)nna);
-  HIP_TRY(hipMemcpyAsync(b->hW.data(), b->W.p, (size_t)b->total_w * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(b->h_W.p, b->W.p, (size_t)b->total_w * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(b->hh0.data(), b->h0.p, b->hh0.size() * sizeof(H0Pair),
                          hipMemcpyDeviceToHost, s));
   if (nna)
@@ -759,7 +866,7 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
       const Cloud& cl = b->clouds[i];
       HostComplex H;
       H.n = cl.n;
-      H.W = b->hW.data() + cl.w_off;
+      H.W = b->h_W.as<uint32_t>() + cl.w_off;
       H.binom = b->binoms[i].data();
       H.kmax = 3;
       vrph_barcode& r = b->results[i];
@@ -776,7 +883,7 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
         std::vector<uint64_t> deaths;
         ReduceStats rs;
         const int64_t cb = col_begin[i], ce = col_begin[i + 1];
-        reduce_dimension(H, 1, b->hcols.data() + cb, ce - cb, prs, deaths, rs);
+        reduce_dimension(H, 1, b->hcols.data() + cb, ce - cb, 1, prs, deaths, rs);
         for (const PairRec& q : prs) r.pairs.push_back(make_pair(1, q.birth, q.bdiam, q.death, q.ddiam));
         if (keep_zero)
           for (uint32_t j : ap_of[i]) {

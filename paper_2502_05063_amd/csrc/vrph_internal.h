@@ -15,6 +15,9 @@ constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr int kMaxDim = 6;        // largest max_dim
 constexpr int kMaxN = 2048;       // largest cloud the one-workgroup H0 kernel takes
 constexpr int kBlock = 256;       // threads per workgroup of the streaming kernels
+// A dispatch counts its work-items in 32 bits: launches of kBlock-thread
+// workgroups stay at or below this many workgroups and stride over the rest.
+constexpr int kMaxGroups = 1 << 22;
 
 // A non-apparent column of the coboundary matrix. Sorting ascending by
 // (cloud, key_hi, cidx) gives coboundary order within each cloud: diameter
@@ -78,10 +81,12 @@ hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, in
                                          CloudState* st, hipStream_t s);
 hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, CloudState* st,
                            H0Pair* out, int64_t out_stride, uint32_t* bitmaps, hipStream_t s);
-hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int kmax,
-                                uint64_t ncand, const uint32_t* clear_in, uint32_t* clear_out,
-                                Column* cols, uint64_t cols_cap, ApparentPair* ap,
-                                uint64_t ap_cap, Scalars* sc, int grid, hipStream_t s);
+// d >= 2; unit_cum (n+1 entries, device) and units from enum_units() on the host
+hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,
+                                const uint64_t* unit_cum, uint64_t units,
+                                const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
+                                uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap, Scalars* sc,
+                                hipStream_t s);
 hipError_t launch_batch_edges(const uint32_t* W, const Cloud* clouds, int count,
                               int64_t total_edges, const uint32_t* bitmaps, Column* cols,
                               uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libvrph.so")
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
 KEEP_ZERO_PERSISTENCE = 1
 NO_ENCLOSING_RADIUS = 2
+AUTOTUNE = 4
 MAX_DIM = 6
 
 PAIR_DTYPE = np.dtype(
@@ -46,6 +47,8 @@ class Stats(ctypes.Structure):
         ("gpu_ms", ctypes.c_double * (MAX_DIM + 1)),
         ("apparent_ms", ctypes.c_double * (MAX_DIM + 1)),
         ("host_ms", ctypes.c_double * (MAX_DIM + 1)),
+        ("grid", ctypes.c_int32 * (MAX_DIM + 1)),
+        ("pad_", ctypes.c_int32),
         ("tau_eff", ctypes.c_float),
         ("max_dim", ctypes.c_int32),
         ("total_ms", ctypes.c_double),
@@ -53,7 +56,7 @@ class Stats(ctypes.Structure):
 
     def to_dict(self):
         k = self.max_dim + 1
-        out = {f: list(getattr(self, f))[:k] for f, _ in self._fields_[:10]}
+        out = {f: list(getattr(self, f))[:k] for f, _ in self._fields_[:11]}
         out.update(tau_eff=self.tau_eff, max_dim=self.max_dim, total_ms=self.total_ms)
         return out
 
@@ -177,8 +180,9 @@ class Context:
         return D
 
     def barcode(self, *, X=None, D=None, max_dim=1, threshold=float("inf"), keep_zero=False,
-                no_enclosing=False):
-        flags = (KEEP_ZERO_PERSISTENCE if keep_zero else 0) | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
+                no_enclosing=False, autotune=False):
+        flags = ((KEEP_ZERO_PERSISTENCE if keep_zero else 0) | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
+                 | (AUTOTUNE if autotune else 0))
         out = ctypes.c_void_p()
         if X is not None:
             X = self._f32(X)

@@ -178,3 +178,13 @@ def test_index_overflow_is_reported(ctx):
     with pytest.raises(vrph.VrphError) as e:
         ctx.barcode(X=dev(X), max_dim=6)
     assert e.value.status == vrph.EOVERFLOW
+
+
+def test_autotune_keeps_results(ctx, tmp_path, monkeypatch):
+    X = synth.sphere(70, 3, seed=2)
+    ref = oracle.barcode(oracle.pdist(X), 2)
+    bc = ctx.barcode(X=dev(X), max_dim=2, keep_zero=True, autotune=True)
+    assert_same(bc.pairs, ref, "autotuned")
+    assert all(g > 0 for g in bc.stats["grid"][1:])
+    again = ctx.barcode(X=dev(X), max_dim=2, keep_zero=True)  # uses the tuned grid
+    assert np.array_equal(again.pairs, bc.pairs) and again.stats["grid"] == bc.stats["grid"]
