@@ -11,9 +11,11 @@ Prints one JSON line (see the design doc for every field).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -26,6 +28,30 @@ METRIC = "barcode wall time (ms) + simplices/sec and HBM GB/s; batched fwd+bwd c
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit integer / compare lane-ops per second
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+KERNEL_SRC = os.path.join(ROOT, "paper_2502_05063_amd", "csrc", "kernels.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "enum_apparent_sphere3_192.md")
+
+
+def measured_traffic(grid):
+    """HBM bytes per launch of the dominant kernel, from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy
+    calibration recorded there), or None unless that summary was taken on
+    the current kernel source with the same launch grid."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            text = f.read()
+        with open(KERNEL_SRC, "rb") as f:
+            src_hash = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    h = re.search(r"kernels_hip_sha256:\s*([0-9a-f]{64})", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9]+)", text)
+    g = re.search(r"grid_workgroups:\s*([0-9]+)", text)
+    if not (h and b and g) or h.group(1) != src_hash or int(g.group(1)) != grid:
+        return None
+    return int(b.group(1))
 
 
 def cpu_baseline(X, max_dim):
@@ -131,7 +157,9 @@ def main():
     Xd = torch.from_numpy(X).cuda()
     ctx = vrph.Context(0)
     for i in range(args.warmup):
-        bc = ctx.barcode(X=Xd, max_dim=max_dim)
+        # the first warm-up step runs the launch autotuner; its choice is cached
+        # in the context and reused by every later step
+        bc = ctx.barcode(X=Xd, max_dim=max_dim, autotune=(i == 0))
         print(f"warmup {i}: {bc.stats['total_ms']:.1f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     stats = []
@@ -155,6 +183,7 @@ def main():
     # diameter, d+1 per cofacet examined by the scans
     ops = cand * math.comb(d + 1, 2) + cof * (d + 1)
     achieved = ops / (k_ms / 1e3) / 1e12
+    traffic = measured_traffic(s0["grid"][d])
     out = {
         "metric": METRIC,
         "value": value,
@@ -178,9 +207,10 @@ def main():
         "apparent_per_dim": s0["apparent"],
         "reduced_per_dim": s0["reduced"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
                      "kernel": f"enum_apparent_kernel<{d}>", "kernel_ms": k_ms,
-                     "ops_per_launch": ops},
+                     "ops_per_launch": ops, "grid_workgroups": s0["grid"][d],
+                     "hbm_gbs": (traffic / (k_ms / 1e3) / 1e9) if traffic else None},
     }
     if not args.no_batched:
         out["batched_fwd_bwd"] = batched_vs_plain(ctx, max(2, min(args.steps, 5)))

@@ -55,12 +55,12 @@ typedef enum {
 #define VRPH_KEEP_ZERO_PERSISTENCE 1u /* report every pair, also birth == death */
 #define VRPH_NO_ENCLOSING_RADIUS 2u   /* do not cut at the enclosing radius */
 /* Autotune: the first call that meets a (dimension, size bucket) not yet
- * tuned times the enumeration + apparent-pairs kernel of that dimension at
- * several tile sizes (simplices per workgroup; for dimension 1 the grid
- * size), with HIP events, and keeps the fastest for the context. If
- * the environment variable VRPH_TUNING_FILE names a file, tunings are read
- * from it when the context is created and appended to it when found
- * (lines "arch dimension size_bucket parameter"). */
+ * tuned times the enumeration + apparent-pairs kernel of that dimension over
+ * its launch settings (workgroups per compute unit and, for dimension >= 2,
+ * simplices per work unit), with HIP events, and keeps the fastest for the
+ * context. If the environment variable VRPH_TUNING_FILE names a file,
+ * tunings are read from it when the context is created and appended to it
+ * when found (lines "arch dimension size_bucket units_size groups_per_cu"). */
 #define VRPH_AUTOTUNE 4u
 
 #define VRPH_MAX_DIM 6 /* largest supported max_dim */

@@ -410,27 +410,44 @@ __device__ __forceinline__ int apparent_cofacet(const uint32_t* __restrict__ W, 
                                                 const int (&v)[D + 1],
                                                 const uint32_t (&pw)[D + 1][D + 1],
                                                 uint32_t diam, unsigned long long& steps) {
-  uint32_t mv[D + 1];
-  int pos = D;
-  int x = n - 1;
-  for (; x >= 0; --x) {
-    if (pos >= 0 && x == v[pos]) {
-      --pos;
-      continue;
-    }
-    ++steps;
-    uint32_t mx = 0;
+  // Condition 1, kScan values of x per round trip: their loads are issued
+  // together instead of one dependent load-compare-branch per x. A vertex of
+  // s is never taken: its own row holds kInf on the diagonal. W is
+  // symmetric, so row x (the same for every lane of the wave, as x moves in
+  // lockstep) is read at the lanes' vertices; v[0] is consecutive across
+  // neighbouring lanes and the loads coalesce.
+  constexpr int kScan = 4;
+  int found = -1;
+  for (int x = n - 1; x >= 0 && found < 0; x -= kScan) {
+    uint32_t mx[kScan];
 #pragma unroll
-    for (int i = 0; i <= D; ++i) {
-      mv[i] = W[(int64_t)v[i] * n + x];
-      mx = max(mx, mv[i]);
+    for (int j = 0; j < kScan; ++j) {
+      const int xj = x - j;
+      const uint32_t* __restrict__ row = W + (int64_t)max(xj, 0) * n;
+      uint32_t m = 0;
+#pragma unroll
+      for (int i = 0; i <= D; ++i) m = max(m, row[v[i]]);
+      mx[j] = xj >= 0 ? m : kInf;
     }
-    if (mx <= diam) break;
+#pragma unroll
+    for (int j = kScan - 1; j >= 0; --j)  // the largest x with the diameter kept
+      if (mx[j] <= diam) found = x - j;
   }
-  if (x < 0) return -1;
+  // cofacets the definition examines: every non-vertex x from n-1 down to
+  // the one found (or all of them)
+  int above = 0;
+#pragma unroll
+  for (int i = 0; i <= D; ++i) above += v[i] > found;
+  steps += (unsigned long long)(found >= 0 ? n - found - above : n - (D + 1));
+  if (found < 0) return -1;
+  // Condition 2 on t = s + {x}
+  const uint32_t* __restrict__ row = W + (int64_t)found * n;
+  uint32_t mv[D + 1];
+#pragma unroll
+  for (int i = 0; i <= D; ++i) mv[i] = row[v[i]];
 #pragma unroll
   for (int u = 0; u <= D; ++u) {
-    if (v[u] < x) continue;
+    if (v[u] < found) continue;
     uint32_t mx = 0;
 #pragma unroll
     for (int i = 0; i <= D; ++i) {
@@ -442,7 +459,7 @@ __device__ __forceinline__ int apparent_cofacet(const uint32_t* __restrict__ W, 
     }
     if (mx == diam) return -1;
   }
-  return x;
+  return found;
 }
 
 // Index of the cofacet s + {x} (Eq. 5.6): vertices above x move up one position.
@@ -660,14 +677,19 @@ static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom,
 }
 
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,
-                                const uint64_t* unit_cum, uint64_t units,
+                                const uint64_t* unit_cum, uint64_t units, unsigned max_groups,
                                 const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
                                 uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap, Scalars* sc,
                                 hipStream_t s) {
   if (units == 0) return hipSuccess;
-  if (chunk < kBlock || chunk % kBlock) return hipErrorInvalidValue;
-  // at most kMaxGroups workgroups: the dispatch counts work-items in 32 bits
-  const unsigned grid = (unsigned)(units < (uint64_t)kMaxGroups ? units : (uint64_t)kMaxGroups);
+  if (chunk < kBlock || chunk % kBlock || max_groups == 0) return hipErrorInvalidValue;
+  // at most kMaxGroups workgroups: the dispatch counts work-items in 32 bits;
+  // a grid of a few workgroups per compute unit that loops over the units
+  // keeps the per-workgroup costs (dispatch, the counter atomics at its end)
+  // off the critical path
+  uint64_t g = units < (uint64_t)max_groups ? units : (uint64_t)max_groups;
+  if (g > (uint64_t)kMaxGroups) g = kMaxGroups;
+  const unsigned grid = (unsigned)g;
   switch (d) {
     case 2: return launch_enum_D<2>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
     case 3: return launch_enum_D<3>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);

@@ -1,52 +1,20 @@
 // Host submatrix reduction (Sec. 5.2.9, 5.5.1) over the columns the GPU
 // found non-apparent. Columns of the dimension-d coboundary matrix are
 // d-simplices in coboundary order (diameter descending, index ascending);
-// rows are (d+1)-simplices in the same order. A row is represented by a
-// 128-bit key (~diameter, index): increasing key = increasing row index, so
-// the lowest nonzero of a column (its pivot, the oldest cofacet) is the
-// largest key.
+// rows are (d+1)-simplices in the same order. A row is named by its
+// diameter rank and its index; the lowest nonzero of a column (its pivot) is
+// its oldest cofacet: the smallest rank, then the largest index.
 #include "reduce.h"
 
 #include <algorithm>
 #include <atomic>
+#include <cstring>
 #include <thread>
 #include <unordered_map>
 
 namespace vrph {
 
 using u128 = unsigned __int128;
-
-// Row keys. A diameter is a non-negative float, so its bit pattern has a
-// zero sign bit and fits in 31 bits; when 31 + (bits of the largest cofacet
-// index) <= 64 the key is a u64 ((2^31-1 - diameter) above the index),
-// otherwise a u128 with the diameter in the high word.
-template <class K>
-struct Keys;
-
-template <>
-struct Keys<uint64_t> {
-  int cbits;
-  uint64_t make(uint32_t diam, uint64_t c) const {
-    return ((uint64_t)(0x7FFFFFFFu - diam) << cbits) | c;
-  }
-  uint64_t index(uint64_t k) const { return k & ((cbits == 64) ? ~0ull : ((1ull << cbits) - 1)); }
-  uint32_t diam(uint64_t k) const { return 0x7FFFFFFFu - (uint32_t)(k >> cbits); }
-  static int high_bit(uint64_t x) { return 63 - __builtin_clzll(x); }
-  static constexpr int kBits = 64;
-};
-
-template <>
-struct Keys<u128> {
-  int cbits;
-  u128 make(uint32_t diam, uint64_t c) const { return ((u128)(uint32_t)~diam << 64) | (u128)c; }
-  uint64_t index(u128 k) const { return (uint64_t)k; }
-  uint32_t diam(u128 k) const { return ~(uint32_t)(k >> 64); }
-  static int high_bit(u128 x) {
-    const uint64_t hi = (uint64_t)(x >> 64), lo = (uint64_t)x;
-    return hi ? 127 - __builtin_clzll(hi) : 63 - __builtin_clzll(lo);
-  }
-  static constexpr int kBits = 128;
-};
 
 void decode_simplex(const HostComplex& H, uint64_t c, int d, int* v) {
   int hi = H.n - 1;
@@ -110,10 +78,18 @@ static uint64_t cofacet_index(const HostComplex& H, const int* v, int d, int x) 
   return c;
 }
 
-// max over the vertices of s of W(v_i, x); kInf if some edge is above tau_eff
+static uint32_t rank_of(const HostComplex& H, const int* v, int d) {
+  uint32_t m = 0;
+  for (int i = 1; i <= d; ++i)
+    for (int j = 0; j < i; ++j) m = std::max(m, H.wr(v[i], v[j]));
+  return m;
+}
+
+// max over the vertices of s of the rank of edge (v_i, x); kInf if some edge
+// is above tau_eff
 static inline uint32_t reach(const HostComplex& H, const int* v, int d, int x) {
   uint32_t m = 0;
-  for (int i = 0; i <= d; ++i) m = std::max(m, H.w(v[i], x));
+  for (int i = 0; i <= d; ++i) m = std::max(m, H.wr(v[i], x));
   return m;
 }
 
@@ -123,31 +99,51 @@ static inline bool contains(const int* v, int d, int x) {
   return false;
 }
 
-// low(D_s): the oldest cofacet = smallest diameter, then largest index. The
-// first x from the top whose cofacet keeps the diameter is it; otherwise the
-// largest key over all cofacets.
-template <class K>
-static bool oldest_cofacet(const HostComplex& H, const Keys<K>& ks, const int* v, int d,
-                           uint32_t diam, K* low) {
+// row (r, c) is older than row (r2, c2): smaller diameter, then larger index
+static inline bool older(uint32_t r, uint64_t c, uint32_t r2, uint64_t c2) {
+  return r < r2 || (r == r2 && c > c2);
+}
+
+// low(D_s): the oldest cofacet. The first x from the top whose cofacet keeps
+// the diameter is it; otherwise the oldest over all cofacets.
+static bool oldest_cofacet(const HostComplex& H, const int* v, int d, uint32_t dr, uint32_t* lr,
+                           uint64_t* lc) {
   bool found = false;
   for (int x = H.n - 1; x >= 0; --x) {
     if (contains(v, d, x)) continue;
-    uint32_t m = reach(H, v, d, x);
+    const uint32_t m = reach(H, v, d, x);
     if (m == kInf) continue;
-    K k = ks.make(std::max(diam, m), cofacet_index(H, v, d, x));
-    if (!found || k > *low) *low = k;
+    const uint32_t r = std::max(dr, m);
+    const uint64_t c = cofacet_index(H, v, d, x);
+    if (!found || older(r, c, *lr, *lc)) {
+      *lr = r;
+      *lc = c;
+    }
     found = true;
-    if (m <= diam) break;
+    if (m <= dr) break;
   }
   return found;
 }
 
-// If row t (a (d+1)-simplex) is the cofacet of an apparent pair (s, t),
-// return s. Def. 5.3.4: s is the youngest facet of t (largest diameter, then
-// smallest index: remove the largest vertex u whose removal keeps diam(t)),
-// and t is the oldest cofacet of s (no x > u outside s keeps the diameter).
-static bool apparent_partner(const HostComplex& H, uint64_t t, uint32_t dt, int d, uint64_t* s,
-                             int* sv) {
+// reach[x] = max_i rank(v_i, x) for every x: the elementwise max of d+1 rank
+// rows. The diagonal is kInf, so reach is kInf at the vertices of s.
+static void compute_reach(const HostComplex& H, const int* v, int d, uint32_t* reach) {
+  const int n = H.n;
+  const uint32_t* r0 = H.Wr + (size_t)v[0] * (size_t)n;
+  for (int x = 0; x < n; ++x) reach[x] = r0[x];
+  for (int i = 1; i <= d; ++i) {
+    const uint32_t* ri = H.Wr + (size_t)v[i] * (size_t)n;
+    for (int x = 0; x < n; ++x) reach[x] = std::max(reach[x], ri[x]);
+  }
+}
+
+// If row t (a (d+1)-simplex of diameter rank rt) is the cofacet of an
+// apparent pair (s, t), return s, its vertices in sv and its reach row.
+// Def. 5.3.4: s is the youngest facet of t (largest diameter, then smallest
+// index: remove the largest vertex u whose removal keeps diam(t)), and t is
+// the oldest cofacet of s (no x > u outside s keeps the diameter).
+static bool apparent_partner(const HostComplex& H, uint64_t t, uint32_t rt, int d, uint64_t* s,
+                             int* sv, uint32_t* reach) {
   int tv[kMaxDim + 3];
   decode_simplex(H, t, d + 1, tv);
   int drop = -1;
@@ -155,8 +151,8 @@ static bool apparent_partner(const HostComplex& H, uint64_t t, uint32_t dt, int 
     uint32_t m = 0;
     for (int i = 1; i <= d + 1; ++i)
       for (int j = 0; j < i; ++j)
-        if (i != r && j != r) m = std::max(m, H.w(tv[i], tv[j]));
-    if (m == dt) {
+        if (i != r && j != r) m = std::max(m, H.wr(tv[i], tv[j]));
+    if (m == rt) {
       drop = r;
       break;
     }
@@ -165,11 +161,10 @@ static bool apparent_partner(const HostComplex& H, uint64_t t, uint32_t dt, int 
   int k = 0;
   for (int i = 0; i <= d + 1; ++i)
     if (i != drop) sv[k++] = tv[i];
-  const int u = tv[drop];
-  for (int x = H.n - 1; x > u; --x) {
-    if (contains(sv, d, x)) continue;
-    if (reach(H, sv, d, x) <= dt) return false;
-  }
+  compute_reach(H, sv, d, reach);
+  bool older_cofacet = false;
+  for (int x = tv[drop] + 1; x < H.n; ++x) older_cofacet |= reach[x] <= rt;
+  if (older_cofacet) return false;
   uint64_t c = 0;
   for (int i = 0; i <= d; ++i) c += H.C(sv[i], i + 1);
   *s = c;
@@ -183,211 +178,387 @@ static bool apparent_partner(const HostComplex& H, uint64_t t, uint32_t dt, int 
 // is their coboundary (v = -1).
 struct Partner {
   uint64_t c;
-  uint32_t diam;
-  int32_t v;  // index into the stored V columns, -1 for none
+  uint32_t r;  // diameter rank
+  int32_t v;   // index into the stored V columns, -1 for none
 };
 
 struct Simplex {
   uint64_t c;
-  uint32_t diam;
+  uint32_t r;
   bool operator<(const Simplex& o) const { return c < o.c; }
   bool operator==(const Simplex& o) const { return c == o.c; }
 };
 
-// The working column: a monotone max-priority queue of row keys (a radix
-// heap). Every key pushed is <= the current pivot and pivots only decrease,
-// so a key lives in the bucket of the highest bit where it differs from the
-// last extracted maximum; bucket 0 holds copies of that maximum, and since
-// equal keys cancel in pairs over Z/2 the maximum survives iff bucket 0 has
-// odd size.
+// Row keys: a row (rank r, index c) is the integer (r << cbits) | (cmax - c),
+// so that a smaller key is an older row and the pivot of a column (its
+// oldest row) is its smallest key. cbits covers the largest cofacet index;
+// the key is a u64 when the rank fits above it, a u128 otherwise.
+template <class K>
+struct Keys {
+  int cbits;
+  K cmax;
+  K make(uint32_t r, uint64_t c) const { return ((K)r << cbits) | (cmax - (K)c); }
+  uint32_t rank(K k) const { return (uint32_t)(k >> cbits); }
+  uint64_t index(K k) const { return (uint64_t)(cmax - (k & cmax)); }
+};
+
+// The working column: a monotone min-priority queue of row keys. Rows pushed
+// are never older than the current pivot and the pivot only gets younger,
+// so the ranks in play only grow. Rows wait in a radix heap over their rank
+// (bucket = highest bit where the rank differs from the current one), where
+// a push is an append. When the pivot reaches a rank, that rank's rows are
+// sorted once into a run; rows pushed at the current rank later become runs
+// too (each is nearly sorted: a coboundary is enumerated in decreasing index
+// order).
+// Runs sit on a stack and the top two are merged while the upper one is at
+// least half the size of the one below, so there are few runs and a row is
+// merged O(log) times. Equal rows cancel in pairs (Z/2): the pivot is the
+// oldest row of odd multiplicity. Rows below the final pivot are appended
+// and at most moved between rank buckets, never sorted.
 template <class K>
 class WorkColumn {
  public:
+  explicit WorkColumn(const Keys<K>& ks) : ks_(ks) {}
+
   void clear() {
     for (auto& b : b_) b.clear();
-    last_ = ~(K)0;
+    for (Run& r : runs_) give(std::move(r.v));
+    runs_.clear();
+    cur_ = 0;
   }
-  void push(K k) { b_[bucket(k)].push_back(k); }
-  // the pivot (largest key of odd multiplicity), kept; false if zero
-  bool pivot(K* k) {
+
+  // bucket 0 holds the rows at the current rank that are not in a run yet
+  void push(K k) { b_[bucket(ks_.rank(k))].push_back(k); }
+
+  // the pivot (smallest key of odd multiplicity), kept in the column; false
+  // if the column is zero
+  bool pivot(K* out) {
     for (;;) {
-      if (b_[0].empty() && !refill()) return false;
-      if (b_[0].size() & 1) {
-        b_[0].resize(1);
-        *k = last_;
+      if (!b_[0].empty()) {
+        std::vector<K>& l = b_[0];
+        if (!std::is_sorted(l.begin(), l.end())) std::sort(l.begin(), l.end());
+        std::vector<K> v = take();
+        v.swap(l);
+        add_run(std::move(v));
+      }
+      K top = 0;
+      bool any = false;
+      for (size_t i = 0; i < runs_.size();) {
+        Run& r = runs_[i];
+        if (r.pos == r.v.size()) {  // spent
+          give(std::move(r.v));
+          runs_.erase(runs_.begin() + (std::ptrdiff_t)i);
+          continue;
+        }
+        if (!any || r.v[r.pos] < top) top = r.v[r.pos];
+        any = true;
+        ++i;
+      }
+      if (!any) {
+        if (!refill()) return false;
+        continue;
+      }
+      size_t k = 0, last = 0;
+      for (size_t i = 0; i < runs_.size(); ++i) {
+        Run& r = runs_[i];
+        const size_t p0 = r.pos;
+        while (r.pos < r.v.size() && r.v[r.pos] == top) ++r.pos;
+        if (r.pos != p0) {
+          k += r.pos - p0;
+          last = i;
+        }
+      }
+      if (k & 1) {
+        --runs_[last].pos;  // one copy stays
+        *out = top;
         return true;
       }
-      b_[0].clear();
     }
   }
 
  private:
-  int bucket(K k) const { return k == last_ ? 0 : Keys<K>::high_bit(k ^ last_) + 1; }
+  struct Run {
+    std::vector<K> v;
+    size_t pos = 0;
+    size_t left() const { return v.size() - pos; }
+  };
+
+  int bucket(uint32_t r) const { return r == cur_ ? 0 : 32 - __builtin_clz(r ^ cur_); }
+
+  std::vector<K> take() {
+    if (spare_.empty()) return {};
+    std::vector<K> v = std::move(spare_.back());
+    spare_.pop_back();
+    return v;
+  }
+  void give(std::vector<K>&& v) {
+    v.clear();
+    spare_.push_back(std::move(v));
+  }
+
+  void add_run(std::vector<K>&& v) {
+    runs_.push_back(Run{std::move(v), 0});
+    while (runs_.size() >= 2 && runs_.back().left() * 2 >= runs_[runs_.size() - 2].left()) {
+      Run& a = runs_[runs_.size() - 2];
+      Run& b = runs_.back();
+      std::vector<K> m = take();
+      m.resize(a.left() + b.left());
+      std::merge(a.v.begin() + (std::ptrdiff_t)a.pos, a.v.end(), b.v.begin() + (std::ptrdiff_t)b.pos,
+                 b.v.end(), m.begin());
+      give(std::move(a.v));
+      give(std::move(b.v));
+      runs_.pop_back();
+      runs_.back() = Run{std::move(m), 0};
+    }
+  }
+
+  // move to the next rank that holds rows: its rows land in bucket 0
   bool refill() {
     int i = 1;
-    while (i <= Keys<K>::kBits && b_[i].empty()) ++i;
-    if (i > Keys<K>::kBits) return false;
+    while (i < kBuckets && b_[i].empty()) ++i;
+    if (i == kBuckets) return false;
     std::vector<K>& src = b_[i];
-    K m = src[0];
-    for (K x : src) m = x > m ? x : m;
-    last_ = m;
-    std::vector<K> moved;
-    moved.swap(src);
-    for (K x : moved) b_[bucket(x)].push_back(x);
-    moved.clear();
-    moved.swap(src);  // keep the capacity
+    uint32_t m = ks_.rank(src[0]);
+    for (K x : src) m = std::min(m, ks_.rank(x));
+    cur_ = m;
+    moved_.clear();
+    moved_.swap(src);
+    for (K x : moved_) b_[bucket(ks_.rank(x))].push_back(x);
     return true;
   }
-  std::vector<K> b_[Keys<K>::kBits + 1];
-  K last_ = ~(K)0;
+
+  static constexpr int kBuckets = 33;
+  Keys<K> ks_;
+  std::vector<K> b_[kBuckets];
+  std::vector<Run> runs_;
+  std::vector<std::vector<K>> spare_;
+  std::vector<K> moved_;
+  uint32_t cur_ = 0;
 };
 
-// Push the cofacets of one column with row key <= limit. Used to add a
-// reduced column R_k whose pivot is `limit`: R_k is zero below its pivot, so
-// the parts of its summands below the pivot cancel and are not pushed.
-// Cofacets s + {x} come in decreasing index order as x goes down (Alg. 14);
-// the index is kept incrementally: vertices of s above x contribute
-// C(v_i, i+2) (they moved up one position), those below C(v_i, i+1), and x
-// itself C(x, j+1) with j the number of vertices below it.
+// Push the cofacets of simplex v (index c, diameter rank dr) that are not
+// older than the row `limit`; `reach` is its reach row, computed here unless
+// the caller has it. Used to add a reduced column R_k whose pivot is
+// `limit`: R_k is zero below its pivot, so the parts of its summands below
+// the pivot cancel and are not pushed. Cofacet s + {x} has index (Alg. 14)
+// high + C(x, j+2) + low with j+1 the number of vertices below x: vertices
+// above x contribute C(v_i, i+2) to `high` (they moved up one position),
+// those below C(v_i, i+1) to `low`. Between two vertices of s these sums are
+// constant, so the keys of a stretch of x are computed in one pass; pushes
+// then go out in decreasing index order.
 template <class K>
-static void push_coboundary(const HostComplex& H, const Keys<K>& ks, uint64_t c, uint32_t diam,
-                            int d, K limit, WorkColumn<K>& w, uint32_t* reach_buf) {
-  int v[kMaxDim + 3];
-  decode_simplex(H, c, d, v);
-  // reach_buf[x] = max_i W(v_i, x): elementwise max of d+1 weight rows
-  const size_t n = (size_t)H.n;
-  const uint32_t* r0 = H.W + (size_t)v[0] * n;
-  for (size_t x = 0; x < n; ++x) reach_buf[x] = r0[x];
-  for (int i = 1; i <= d; ++i) {
-    const uint32_t* ri = H.W + (size_t)v[i] * n;
-    for (size_t x = 0; x < n; ++x) reach_buf[x] = std::max(reach_buf[x], ri[x]);
-  }
+static void push_coboundary(const HostComplex& H, const Keys<K>& ks, const int* v, uint64_t c,
+                            uint32_t dr, int d, K limit, WorkColumn<K>& w, uint32_t* reach,
+                            bool have_reach, K* kb) {
+  const int n = H.n;
+  if (!have_reach) compute_reach(H, v, d, reach);
   uint64_t high = 0, low = c;
-  int pos = d;  // vertices v[pos+1..d] are above x
-  for (int x = H.n - 1; x >= 0; --x) {
-    if (pos >= 0 && x == v[pos]) {
+  int hi = n;  // the stretch is [lo, hi)
+  for (int pos = d; pos >= -1; --pos) {
+    const int lo = pos >= 0 ? v[pos] + 1 : 0;
+    const uint64_t base = high + low;
+    const uint64_t* row = H.binom + (size_t)(pos + 2) * (size_t)(n + 1);
+    for (int x = lo; x < hi; ++x) kb[x] = ks.make(std::max(dr, reach[x]), base + row[x]);
+    if (pos >= 0) {
       high += H.C(v[pos], pos + 2);
       low -= H.C(v[pos], pos + 1);
-      --pos;
-      continue;
+      hi = v[pos];
     }
-    const uint32_t m = reach_buf[x];
-    if (m == kInf) continue;
-    const K k = ks.make(std::max(diam, m), high + H.C(x, pos + 2) + low);
-    if (k <= limit) w.push(k);
   }
+  for (int x = n - 1; x >= 0; --x)
+    if (reach[x] != kInf && kb[x] >= limit) w.push(kb[x]);
 }
 
-// What a column needs before the sequential pass, independent of every other
-// column: its first pivot low(D_j) and, if that row is the cofacet of an
-// apparent pair, the apparent column.
-template <class K>
-struct FirstPivot {
-  K low;
-  uint64_t apparent;  // the apparent column owning `low`, if has_apparent
-  bool nonzero;
-  bool has_apparent;
+// Row index -> column of this dimension's reduced pivots: open addressing
+// with linear probing at load <= 1/2 (a row index is < 2^63, so ~0 marks an
+// empty slot).
+class PivotTable {
+ public:
+  explicit PivotTable(size_t n) {
+    size_t cap = 16;
+    int bits = 4;
+    while (cap < 2 * n + 2) {
+      cap <<= 1;
+      ++bits;
+    }
+    keys_.assign(cap, kEmpty);
+    vals_.resize(cap);
+    mask_ = cap - 1;
+    shift_ = 64 - bits;
+  }
+  const Partner* find(uint64_t k) const {
+    for (size_t i = slot(k);; i = (i + 1) & mask_) {
+      if (keys_[i] == k) return &vals_[i];
+      if (keys_[i] == kEmpty) return nullptr;
+    }
+  }
+  void insert(uint64_t k, const Partner& p) {
+    size_t i = slot(k);
+    while (keys_[i] != kEmpty) i = (i + 1) & mask_;
+    keys_[i] = k;
+    vals_[i] = p;
+  }
+
+ private:
+  static constexpr uint64_t kEmpty = ~0ull;
+  size_t slot(uint64_t k) const { return (size_t)((k * 0x9E3779B97F4A7C15ull) >> shift_); }
+  std::vector<uint64_t> keys_;
+  std::vector<Partner> vals_;
+  size_t mask_ = 0;
+  int shift_ = 0;
 };
 
+// The part of a column's reduction that does not depend on other columns.
+// While the pivot of a column is the cofacet of an apparent pair, Alg. 2
+// adds that apparent column: the pivot store of the other non-apparent
+// columns is never consulted for such a row, because the cofacet of an
+// apparent pair is the pivot of its own column only (pivots are unique).
+// So each column can follow its chain of apparent pivots on its own, in
+// parallel, until it reaches a row that is not an apparent cofacet; the
+// sequential pass then only continues the columns whose row is already
+// taken. The sequence of additions is exactly the sequential one.
+struct PreReduced {
+  uint64_t lc;      // pivot after the apparent chain (row index)
+  uint32_t lr;      // its rank
+  uint32_t dr;      // diameter rank of the column
+  uint32_t voff;    // apparent columns added: chain_v[j / kChunk][voff, voff + vcount)
+  uint32_t vcount;
+  bool nonzero;
+};
+
+constexpr int64_t kChunk = 256;
+
 template <class K>
-static void first_pivots(const HostComplex& H, const Keys<K>& ks, int d, const Column* cols,
-                         int64_t ncols, int threads, std::vector<FirstPivot<K>>& out) {
+static void pre_reduce(const HostComplex& H, const Keys<K>& ks, int d, const Column* cols,
+                       int64_t ncols, int threads, std::vector<PreReduced>& out,
+                       std::vector<std::vector<Simplex>>& chain_v, int64_t* additions) {
   out.resize((size_t)ncols);
-  std::atomic<int64_t> next{0};
-  auto work = [&]() {
+  chain_v.assign((size_t)((ncols + kChunk - 1) / kChunk), {});
+  std::atomic<int64_t> next{0}, adds{0};
+  auto worker = [&]() {
     int v[kMaxDim + 3], sv[kMaxDim + 3];
+    WorkColumn<K> work(ks);
+    std::vector<uint32_t> reach((size_t)H.n), areach((size_t)H.n);
+    std::vector<K> kb((size_t)H.n);
+    int64_t local_adds = 0;
     for (;;) {
-      const int64_t j0 = next.fetch_add(256);
-      if (j0 >= ncols) return;
-      const int64_t j1 = std::min<int64_t>(ncols, j0 + 256);
+      const int64_t j0 = next.fetch_add(kChunk);
+      if (j0 >= ncols) break;
+      const int64_t j1 = std::min<int64_t>(ncols, j0 + kChunk);
+      std::vector<Simplex>& cv = chain_v[(size_t)(j0 / kChunk)];
       for (int64_t j = j0; j < j1; ++j) {
-        FirstPivot<K>& f = out[(size_t)j];
-        decode_simplex(H, cols[j].cidx, d, v);
-        f.nonzero = oldest_cofacet(H, ks, v, d, ~cols[j].key_hi, &f.low);
-        f.has_apparent =
-            f.nonzero && apparent_partner(H, ks.index(f.low), ks.diam(f.low), d, &f.apparent, sv);
+        PreReduced& f = out[(size_t)j];
+        const uint64_t c = cols[j].cidx;
+        decode_simplex(H, c, d, v);
+        f.dr = rank_of(H, v, d);
+        f.voff = (uint32_t)cv.size();
+        f.vcount = 0;
+        f.nonzero = oldest_cofacet(H, v, d, f.dr, &f.lr, &f.lc);
+        uint64_t s;
+        if (!f.nonzero || !apparent_partner(H, f.lc, f.lr, d, &s, sv, areach.data())) continue;
+        K low = ks.make(f.lr, f.lc);
+        work.clear();
+        push_coboundary(H, ks, v, c, f.dr, d, low, work, reach.data(), false, kb.data());
+        for (;;) {
+          push_coboundary(H, ks, sv, s, f.lr, d, low, work, areach.data(), true, kb.data());
+          cv.push_back(Simplex{s, f.lr});
+          ++f.vcount;
+          ++local_adds;
+          if (!work.pivot(&low)) {
+            f.nonzero = false;
+            break;
+          }
+          f.lr = ks.rank(low);
+          f.lc = ks.index(low);
+          if (!apparent_partner(H, f.lc, f.lr, d, &s, sv, areach.data())) break;
+        }
       }
     }
+    adds += local_adds;
   };
   threads = (int)std::max<int64_t>(1, std::min<int64_t>(threads, ncols / 1024));
   std::vector<std::thread> pool;
-  for (int i = 1; i < threads; ++i) pool.emplace_back(work);
-  work();
+  for (int i = 1; i < threads; ++i) pool.emplace_back(worker);
+  worker();
   for (std::thread& t : pool) t.join();
+  *additions += adds.load();
 }
 
 template <class K>
 static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Column* cols,
                         int64_t ncols, int threads, std::vector<PairRec>& pairs,
                         std::vector<uint64_t>& deaths, ReduceStats& stats) {
-  std::unordered_map<uint64_t, Partner> pivots;  // row index -> column, this dimension
-  pivots.reserve((size_t)ncols * 2 + 16);
-  std::vector<std::vector<Simplex>> vstore;       // V columns of the reduced columns
-  WorkColumn<K> work;
+  PivotTable pivots((size_t)ncols);
+  std::vector<std::vector<Simplex>> vstore;  // V columns of the reduced columns
+  WorkColumn<K> work(ks);
   std::vector<Simplex> vj;
-  std::vector<uint32_t> reach_buf((size_t)H.n);
-  int pv[kMaxDim + 3];
-  std::vector<FirstPivot<K>> first;
-  first_pivots(H, ks, d, cols, ncols, threads, first);
-
-  // two-layer lookup (Fig. 5.10): pairs found by this reduction first, then
-  // the apparent pairs, recognised from Def. 5.3.4 instead of a stored array
-  auto lookup = [&](K row, Partner* p) -> bool {
-    auto it = pivots.find(ks.index(row));
-    if (it != pivots.end()) {
-      *p = it->second;
-      return true;
-    }
-    uint64_t s;
-    if (apparent_partner(H, ks.index(row), ks.diam(row), d, &s, pv)) {
-      *p = Partner{s, ks.diam(row), -1};
-      return true;
-    }
-    return false;
-  };
+  std::vector<uint32_t> reach((size_t)H.n), areach((size_t)H.n);
+  std::vector<K> kb((size_t)H.n);
+  int sv[kMaxDim + 3], pv[kMaxDim + 3];
+  std::vector<PreReduced> pre;
+  std::vector<std::vector<Simplex>> chain_v;
+  pre_reduce(H, ks, d, cols, ncols, threads, pre, chain_v, &stats.additions);
 
   for (int64_t j = 0; j < ncols; ++j) {
     const uint64_t c = cols[j].cidx;
-    const uint32_t diam = ~cols[j].key_hi;
-    const FirstPivot<K>& f = first[(size_t)j];
-    K low = f.low;
-    Partner p;
+    const PreReduced& f = pre[(size_t)j];
+    const Simplex* chain = chain_v[(size_t)(j / kChunk)].data() + f.voff;
+    const uint32_t dr = f.dr;
+    uint32_t lr = f.lr;
+    uint64_t lc = f.lc;
     bool nonzero = f.nonzero;
-    bool taken = false;
-    if (nonzero) {
-      if (f.has_apparent) {
-        p = Partner{f.apparent, ks.diam(low), -1};
-        taken = true;
-      } else {
-        auto it = pivots.find(ks.index(low));
-        if (it != pivots.end()) {
-          p = it->second;
-          taken = true;
-        }
-      }
-    }
-    vj.clear();
-    if (taken) {
-      // Alg. 2 on column j: while its pivot is the pivot of an earlier column
-      // k, add R_k = D_k + sum_{i in V_k} D_i (the pivot then moves up)
+    vj.assign(chain, chain + f.vcount);
+    const Partner* q = nonzero ? pivots.find(lc) : nullptr;
+    if (q) {
+      // Alg. 2 on column j, continued: while its pivot is the pivot of an
+      // earlier column k, add R_k = D_k + sum_{i in V_k} D_i (the pivot then
+      // moves up). Lookups are two-layer (Fig. 5.10): pairs found by this
+      // reduction first, then the apparent pairs, recognised from Def. 5.3.4
+      // instead of a stored array. The working column restarts from the
+      // column and the apparent columns its chain added.
+      Partner p = *q;
+      bool pv_known = false;  // pv holds the vertices of p.c
+      K low = ks.make(lr, lc);
       work.clear();
-      push_coboundary(H, ks, c, diam, d, low, work, reach_buf.data());
+      decode_simplex(H, c, d, sv);
+      push_coboundary(H, ks, sv, c, dr, d, low, work, reach.data(), false, kb.data());
+      for (uint32_t i = 0; i < f.vcount; ++i) {
+        decode_simplex(H, chain[i].c, d, sv);
+        push_coboundary(H, ks, sv, chain[i].c, chain[i].r, d, low, work, reach.data(), false,
+                        kb.data());
+      }
       for (;;) {
-        push_coboundary(H, ks, p.c, p.diam, d, low, work, reach_buf.data());
-        vj.push_back(Simplex{p.c, p.diam});
+        if (!pv_known) decode_simplex(H, p.c, d, pv);
+        if (pv_known)  // its reach row came with the lookup
+          push_coboundary(H, ks, pv, p.c, p.r, d, low, work, areach.data(), true, kb.data());
+        else
+          push_coboundary(H, ks, pv, p.c, p.r, d, low, work, reach.data(), false, kb.data());
+        vj.push_back(Simplex{p.c, p.r});
         if (p.v >= 0)
-          for (const Simplex& q : vstore[p.v]) {
-            push_coboundary(H, ks, q.c, q.diam, d, low, work, reach_buf.data());
-            vj.push_back(q);
+          for (const Simplex& r : vstore[p.v]) {
+            decode_simplex(H, r.c, d, sv);
+            push_coboundary(H, ks, sv, r.c, r.r, d, low, work, reach.data(), false, kb.data());
+            vj.push_back(r);
           }
         ++stats.additions;
         if (!work.pivot(&low)) {
           nonzero = false;
           break;
         }
-        if (!lookup(low, &p)) break;
+        lr = ks.rank(low);
+        lc = ks.index(low);
+        if (const Partner* q2 = pivots.find(lc)) {
+          p = *q2;
+          pv_known = false;
+        } else if (apparent_partner(H, lc, lr, d, &p.c, pv, areach.data())) {
+          p.r = lr;
+          p.v = -1;
+          pv_known = true;
+        } else {
+          break;
+        }
       }
-    } else if (nonzero) {
+    } else if (nonzero && f.vcount == 0) {
       ++stats.emergent;
     }
     if (nonzero) {
@@ -405,11 +576,11 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
         vi = (int32_t)vstore.size();
         vstore.push_back(std::move(red));
       }
-      pivots.emplace(ks.index(low), Partner{c, diam, vi});
-      pairs.push_back(PairRec{c, ks.index(low), diam, ks.diam(low)});
-      deaths.push_back(ks.index(low));
+      pivots.insert(lc, Partner{c, dr, vi});
+      pairs.push_back(PairRec{c, lc, H.rank_bits[dr], H.rank_bits[lr]});
+      deaths.push_back(lc);
     } else {
-      pairs.push_back(PairRec{c, ~0ull, diam, kInf});
+      pairs.push_back(PairRec{c, ~0ull, H.rank_bits[dr], kInf});
     }
   }
 }
@@ -417,16 +588,53 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
 void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,
                       int threads, std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
                       ReduceStats& stats) {
-  // bits of the largest cofacet index, C(n, d+2) - 1
+  if (ncols == 0) return;
+  // bits of the largest cofacet index C(n, d+2) - 1 and of the largest rank
   const uint64_t top = H.C(H.n, d + 2);
   const uint64_t largest = top ? top - 1 : 0;
-  int cbits = 1;
+  int cbits = 1, rbits = 1;
   while (cbits < 64 && (largest >> cbits)) ++cbits;
-  if (31 + cbits <= 64)
-    reduce_keys<uint64_t>(H, Keys<uint64_t>{cbits}, d, cols, ncols, threads, pairs, deaths,
-                          stats);
+  while (rbits < 32 && ((uint64_t)(H.nranks ? H.nranks - 1 : 0) >> rbits)) ++rbits;
+  const u128 cmax = cbits == 64 ? (u128)~0ull : (((u128)1 << cbits) - 1);
+  if (rbits + cbits <= 64)
+    reduce_keys<uint64_t>(H, Keys<uint64_t>{cbits, (uint64_t)cmax}, d, cols, ncols, threads,
+                          pairs, deaths, stats);
   else
-    reduce_keys<u128>(H, Keys<u128>{64}, d, cols, ncols, threads, pairs, deaths, stats);
+    reduce_keys<u128>(H, Keys<u128>{cbits, cmax}, d, cols, ncols, threads, pairs, deaths, stats);
+}
+
+// Dense ranks of the finite weights: the finite upper-triangle entries are
+// sorted by weight (a least-significant-digit radix sort on the 32-bit
+// pattern, which orders non-negative floats), and equal weights share a rank.
+void RankTable::build(int n, const uint32_t* W) {
+  const size_t nn = (size_t)n * (size_t)n;
+  Wr.assign(nn, kInf);
+  bits.clear();
+  std::vector<uint64_t> e, tmp;  // weight << 32 | position a*n + b
+  for (int a = 1; a < n; ++a)
+    for (int b = 0; b < a; ++b) {
+      const uint32_t w = W[(size_t)a * n + b];
+      if (w != kInf) e.push_back(((uint64_t)w << 32) | (uint32_t)((size_t)a * n + b));
+    }
+  tmp.resize(e.size());
+  for (int shift = 32; shift < 64; shift += 11) {
+    size_t cnt[2049] = {0};
+    for (uint64_t x : e) ++cnt[((x >> shift) & 2047) + 1];
+    bool trivial = false;
+    for (int k = 1; k <= 2048; ++k)
+      if (cnt[k] == e.size()) trivial = true;
+    if (trivial) continue;
+    for (int k = 1; k <= 2048; ++k) cnt[k] += cnt[k - 1];
+    for (uint64_t x : e) tmp[cnt[(x >> shift) & 2047]++] = x;
+    e.swap(tmp);
+  }
+  for (size_t k = 0; k < e.size(); ++k) {
+    const uint32_t w = (uint32_t)(e[k] >> 32);
+    if (bits.empty() || bits.back() != w) bits.push_back(w);
+    const uint32_t pos = (uint32_t)e[k];
+    const uint32_t a = pos / (uint32_t)n, b = pos % (uint32_t)n;
+    Wr[(size_t)a * n + b] = Wr[(size_t)b * n + a] = (uint32_t)(bits.size() - 1);
+  }
 }
 
 }  // namespace vrph

@@ -12,10 +12,32 @@ namespace vrph {
 struct HostComplex {
   int n = 0;
   const uint32_t* W = nullptr;      // n x n weights (float bits, kInf above tau_eff)
+  // Ranks of the same weights among the distinct finite ones (kInf stays
+  // kInf) and the weight of each rank; filled by build_ranks. Only the
+  // reduction reads them.
+  const uint32_t* Wr = nullptr;
+  const uint32_t* rank_bits = nullptr;
+  uint32_t nranks = 0;
   const uint64_t* binom = nullptr;  // k-major binomial table, (kmax + 1) x (n + 1)
   int kmax = 0;
   uint64_t C(int v, int k) const { return binom[(size_t)k * (size_t)(n + 1) + (size_t)v]; }
   uint32_t w(int a, int b) const { return W[(size_t)a * (size_t)n + (size_t)b]; }
+  uint32_t wr(int a, int b) const { return Wr[(size_t)a * (size_t)n + (size_t)b]; }
+};
+
+// Weight ranks for the host reduction. By the order invariance of the
+// barcode (Obs. 5.6.8) the pairs depend only on the order of the distances,
+// so the reduction compares dense ranks (equal weights share a rank) instead
+// of float bit patterns and maps ranks back to weights on output.
+struct RankTable {
+  std::vector<uint32_t> Wr;    // n x n, symmetric, kInf where W is kInf
+  std::vector<uint32_t> bits;  // weight (float bits) of each rank, increasing
+  void build(int n, const uint32_t* W);
+  void attach(HostComplex& H) const {
+    H.Wr = Wr.data();
+    H.rank_bits = bits.data();
+    H.nranks = (uint32_t)bits.size();
+  }
 };
 
 struct PairRec {
@@ -31,7 +53,8 @@ struct ReduceStats {
 // Reduce the non-apparent columns of dimension d, given in coboundary order,
 // with the reduction-matrix technique (Sec. 5.2.9: R = D V; a column adds the
 // reduced columns of earlier pivots, so its pivot only moves up; the working
-// column is a lazy max-heap). A column whose first pivot is free is paired
+// column is a monotone bucket queue over diameter ranks). H must carry a
+// RankTable. A column whose first pivot is free is paired
 // without building it (the emergent case of Sec. 5.2.11). Pivot lookups go to a hash map of the pairs found so far,
 // then to the apparent pairs, recognised on the fly from Def. 5.3.4 instead
 // of a stored array. The first pivot of every column, and whether it belongs

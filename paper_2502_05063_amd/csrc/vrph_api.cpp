@@ -45,6 +45,13 @@ static vrph_status fail(vrph_status st, const std::string& msg) {
                   std::string(#expr) + ": " + hipGetErrorString(e_));                     \
   } while (0)
 
+// inside helpers that return a hipError_t
+#define HIP_TRY_E(expr)             \
+  do {                              \
+    hipError_t e_ = (expr);         \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
 extern "C" const char* vrph_last_error(void) { return g_last_error.c_str(); }
 
 // ---------------------------------------------------------------------------
@@ -160,6 +167,13 @@ double now_ms() {
 // context and results
 // ---------------------------------------------------------------------------
 
+// Launch setting of an enumeration kernel: suffixes per work unit (d >= 2)
+// and workgroups per compute unit.
+struct Tune {
+  int chunk;
+  int mult;
+};
+
 struct vrph_ctx {
   int device = 0;
   int num_cus = 256;
@@ -170,9 +184,8 @@ struct vrph_ctx {
   std::vector<uint64_t> h_binom;
   int binom_n = -1, binom_k = -1;
   std::string arch;
-  // (dimension, size bucket) -> tuned parameter: suffixes per workgroup for
-  // d >= 2, grid multiplier for d = 1
-  std::map<std::pair<int, int>, int> tuned;
+  // (dimension, size bucket) -> tuned launch setting
+  std::map<std::pair<int, int>, Tune> tuned;
   DevBuf units;                    // unit table of the d >= 2 enumeration
   std::vector<uint64_t> h_units;
 };
@@ -196,7 +209,7 @@ static uint64_t enum_units(int n, int d, int chunk, const std::vector<uint64_t>&
   return cum[n];
 }
 
-// Autotuning of the enumeration kernels' grid (see VRPH_AUTOTUNE).
+// Autotuning of the enumeration kernels' launch (see VRPH_AUTOTUNE).
 static int size_bucket(int n) {
   int b = 1;
   while (b < n) b <<= 1;
@@ -208,16 +221,18 @@ static void load_tuning(vrph_ctx* c) {
   if (!path) return;
   std::ifstream f(path);
   std::string arch;
-  int d, b, g;
-  while (f >> arch >> d >> b >> g)
-    if (arch == c->arch && g > 0 && g <= 256) c->tuned[{d, b}] = g;
+  int d, b, chunk, mult;
+  while (f >> arch >> d >> b >> chunk >> mult)
+    if (arch == c->arch && d >= 1 && d <= kMaxDim && chunk >= kBlock && chunk <= (1 << 20) &&
+        chunk % kBlock == 0 && mult >= 1 && mult <= 1024)
+      c->tuned[{d, b}] = Tune{chunk, mult};
 }
 
-static void save_tuning(vrph_ctx* c, int d, int b, int g) {
+static void save_tuning(vrph_ctx* c, int d, int b, const Tune& t) {
   const char* path = std::getenv("VRPH_TUNING_FILE");
   if (!path) return;
   std::ofstream f(path, std::ios::app);
-  f << c->arch << " " << d << " " << b << " " << g << "\n";
+  f << c->arch << " " << d << " " << b << " " << t.chunk << " " << t.mult << "\n";
 }
 
 struct vrph_barcode {
@@ -424,6 +439,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
                                  ((cs.err & 4) ? " asymmetric" : "") +
                                  ((cs.err & 8) ? " nonzero diagonal" : ""));
   H.W = hW.data();
+  RankTable ranks;  // built when a dimension first has columns to reduce
 
   std::unique_ptr<vrph_barcode> bc(new (std::nothrow) vrph_barcode());
   if (!bc) return fail(VRPH_ENOMEM, "out of host memory");
@@ -464,55 +480,64 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     Scalars* dsc = c->scal.as<Scalars>();
     HIP_TRY(c->cols.ensure(cap * sizeof(Column)));
     if (keep_zero) HIP_TRY(c->ap.ensure(std::max<uint64_t>(ap_cap, 1) * sizeof(ApparentPair)));
-    // the launch of dimension d with tuning parameter `param`: suffixes per
-    // workgroup (d >= 2) or grid multiplier (d = 1); returns the workgroups
+    // the launch of dimension d with setting t (suffixes per work unit for
+    // d >= 2, workgroups per compute unit); `launched` = the workgroups.
+    // Events ev0 / ev2 bracket the kernel alone on the stream.
     uint64_t launched = 0;
-    auto launch_dim = [&](int param) -> hipError_t {
+    auto launch_dim = [&](const Tune& t) -> hipError_t {
+      const unsigned max_groups = (unsigned)c->num_cus * (unsigned)t.mult;
       if (d == 1) {
-        launched = (uint64_t)c->num_cus * param;
-        return launch_batch_edges(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1, (int64_t)ncand,
-                                  clear_in, c->cols.as<Column>(), cap,
-                                  keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
-                                  clear_out, &dsc->columns, c->num_cus * param, s);
+        launched = max_groups;
+        HIP_TRY_E(hipEventRecord(c->ev0, s));
+        HIP_TRY_E(launch_batch_edges(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1,
+                                     (int64_t)ncand, clear_in, c->cols.as<Column>(), cap,
+                                     keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
+                                     clear_out, &dsc->columns, (int)max_groups, s));
+        return hipEventRecord(c->ev2, s);
       }
-      launched = enum_units(n, d, param, c->h_binom, c->h_units);
+      const uint64_t units = enum_units(n, d, t.chunk, c->h_binom, c->h_units);
+      launched = std::min<uint64_t>(std::min<uint64_t>(units, max_groups), kMaxGroups);
       hipError_t e = c->units.ensure(c->h_units.size() * sizeof(uint64_t));
       if (e != hipSuccess) return e;
       e = hipMemcpyAsync(c->units.p, c->h_units.data(), c->h_units.size() * sizeof(uint64_t),
                          hipMemcpyHostToDevice, s);
       if (e != hipSuccess) return e;
-      e = launch_enum_apparent(d, c->W.as<uint32_t>(), n, c->binom.as<uint64_t>(), param,
-                               c->units.as<uint64_t>(), launched, clear_in, clear_out,
-                               c->cols.as<Column>(), cap,
-                               keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap, dsc, s);
+      HIP_TRY_E(hipEventRecord(c->ev0, s));
+      HIP_TRY_E(launch_enum_apparent(d, c->W.as<uint32_t>(), n, c->binom.as<uint64_t>(), t.chunk,
+                                     c->units.as<uint64_t>(), units, max_groups, clear_in,
+                                     clear_out, c->cols.as<Column>(), cap,
+                                     keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap, dsc,
+                                     s));
+      HIP_TRY_E(hipEventRecord(c->ev2, s));
       // the host table is consumed by the copy before the next launch reuses it
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      return e;
+      return hipStreamSynchronize(s);
     };
     const std::pair<int, int> tkey{d, size_bucket(n)};
-    int param = d == 1 ? 8 : 1024;
+    Tune param{4096, 8};
     auto it = c->tuned.find(tkey);
     if (it != c->tuned.end()) {
       param = it->second;
     } else if (flags & VRPH_AUTOTUNE) {
-      // time each setting on this very input; outputs are rewritten by the run below
-      const std::vector<int> grid_mults = {1, 2, 4, 8, 16, 32, 64};
-      const std::vector<int> tiles = {256, 512, 1024, 2048, 4096, 8192};
-      float best = 0;
-      bool first = true;
-      for (int g : (d == 1 ? grid_mults : tiles)) {
-        HIP_TRY(hipMemsetAsync(c->scal.p, 0, sizeof(Scalars), s));
-        HIP_TRY(hipEventRecord(c->ev0, s));
-        HIP_TRY(launch_dim(g));
-        HIP_TRY(hipEventRecord(c->ev1, s));
-        HIP_TRY(hipEventSynchronize(c->ev1));
-        float t = 0;
-        HIP_TRY(hipEventElapsedTime(&t, c->ev0, c->ev1));
-        if (first || t < best) {
-          best = t;
-          param = g;
-          first = false;
+      // time settings on this very input (outputs are rewritten by the run
+      // below): workgroups per compute unit first, then, for d >= 2, the
+      // work-unit size at the best of those
+      float best = -1;
+      auto trial = [&](const Tune& t) -> hipError_t {
+        HIP_TRY_E(hipMemsetAsync(c->scal.p, 0, sizeof(Scalars), s));
+        HIP_TRY_E(launch_dim(t));
+        HIP_TRY_E(hipEventSynchronize(c->ev2));
+        float ms = 0;
+        HIP_TRY_E(hipEventElapsedTime(&ms, c->ev0, c->ev2));
+        if (best < 0 || ms < best) {
+          best = ms;
+          param = t;
         }
+        return hipSuccess;
+      };
+      for (int mult : {1, 2, 4, 8, 16, 32, 64}) HIP_TRY(trial(Tune{param.chunk, mult}));
+      if (d >= 2) {
+        const int mult = param.mult;
+        for (int chunk : {1024, 2048, 8192, 16384, 32768}) HIP_TRY(trial(Tune{chunk, mult}));
       }
       c->tuned[tkey] = param;
       save_tuning(c, d, tkey.second, param);
@@ -521,10 +546,8 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       HIP_TRY(c->cols.ensure(cap * sizeof(Column)));
       if (keep_zero) HIP_TRY(c->ap.ensure(std::max<uint64_t>(ap_cap, 1) * sizeof(ApparentPair)));
       HIP_TRY(hipMemsetAsync(c->scal.p, 0, sizeof(Scalars), s));
-      HIP_TRY(hipEventRecord(c->ev0, s));
       HIP_TRY(launch_dim(param));
       bc->stats.grid[d] = (int32_t)std::min<uint64_t>(launched, 0x7FFFFFFF);
-      HIP_TRY(hipEventRecord(c->ev2, s));
       HIP_TRY(hipMemcpyAsync(c->h_scal.p, c->scal.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       std::memcpy(&sc, c->h_scal.p, sizeof(sc));
@@ -563,6 +586,10 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     prs.clear();
     deaths.clear();
     ReduceStats rs;
+    if (nna > 0 && !H.Wr) {
+      ranks.build(n, hW.data());
+      ranks.attach(H);
+    }
     reduce_dimension(H, d, hcols.data(), nna, host_threads(), prs, deaths, rs);
     bc->stats.additions[d] = rs.additions;
     for (const PairRec& r : prs) bc->pairs.push_back(make_pair(d, r.birth, r.bdiam, r.death, r.ddiam));
@@ -883,6 +910,11 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
         std::vector<uint64_t> deaths;
         ReduceStats rs;
         const int64_t cb = col_begin[i], ce = col_begin[i + 1];
+        RankTable ranks;
+        if (ce > cb) {
+          ranks.build(cl.n, H.W);
+          ranks.attach(H);
+        }
         reduce_dimension(H, 1, b->hcols.data() + cb, ce - cb, 1, prs, deaths, rs);
         for (const PairRec& q : prs) r.pairs.push_back(make_pair(1, q.birth, q.bdiam, q.death, q.ddiam));
         if (keep_zero)

@@ -81,9 +81,10 @@ hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, in
                                          CloudState* st, hipStream_t s);
 hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, CloudState* st,
                            H0Pair* out, int64_t out_stride, uint32_t* bitmaps, hipStream_t s);
-// d >= 2; unit_cum (n+1 entries, device) and units from enum_units() on the host
+// d >= 2; unit_cum (n+1 entries, device) and units from enum_units() on the
+// host; at most max_groups workgroups, which stride over the units
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,
-                                const uint64_t* unit_cum, uint64_t units,
+                                const uint64_t* unit_cum, uint64_t units, unsigned max_groups,
                                 const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
                                 uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap, Scalars* sc,
                                 hipStream_t s);

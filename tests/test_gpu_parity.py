@@ -180,11 +180,28 @@ def test_index_overflow_is_reported(ctx):
     assert e.value.status == vrph.EOVERFLOW
 
 
-def test_autotune_keeps_results(ctx, tmp_path, monkeypatch):
+def test_autotune_keeps_results(tmp_path, monkeypatch):
+    from paper_2502_05063_amd import vrph
+
+    tf = tmp_path / "tuning.txt"
+    monkeypatch.setenv("VRPH_TUNING_FILE", str(tf))
     X = synth.sphere(70, 3, seed=2)
     ref = oracle.barcode(oracle.pdist(X), 2)
-    bc = ctx.barcode(X=dev(X), max_dim=2, keep_zero=True, autotune=True)
-    assert_same(bc.pairs, ref, "autotuned")
-    assert all(g > 0 for g in bc.stats["grid"][1:])
-    again = ctx.barcode(X=dev(X), max_dim=2, keep_zero=True)  # uses the tuned grid
-    assert np.array_equal(again.pairs, bc.pairs) and again.stats["grid"] == bc.stats["grid"]
+    c1 = vrph.Context()
+    try:
+        bc = c1.barcode(X=dev(X), max_dim=2, keep_zero=True, autotune=True)
+        assert_same(bc.pairs, ref, "autotuned")
+        assert all(g > 0 for g in bc.stats["grid"][1:])
+        again = c1.barcode(X=dev(X), max_dim=2, keep_zero=True)  # the tuned launch, cached
+        assert np.array_equal(again.pairs, bc.pairs) and again.stats["grid"] == bc.stats["grid"]
+    finally:
+        c1.close()
+    # one line per tuned dimension: arch, dimension, size bucket, unit size, groups per CU
+    lines = [ln.split() for ln in tf.read_text().splitlines()]
+    assert sorted(int(f[1]) for f in lines) == [1, 2] and all(len(f) == 5 for f in lines)
+    c2 = vrph.Context()  # reads the file
+    try:
+        loaded = c2.barcode(X=dev(X), max_dim=2, keep_zero=True)
+        assert np.array_equal(loaded.pairs, bc.pairs) and loaded.stats["grid"] == bc.stats["grid"]
+    finally:
+        c2.close()
