@@ -393,6 +393,44 @@ hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, Cl
 }
 
 // ---------------------------------------------------------------------------
+// Reads of one cloud's weight matrix.
+// BufferRows: the whole wave works on one cloud. Raw buffer loads take the
+// row offset in a scalar register and the column offset per lane (32 bits
+// each), so a read is one instruction with no 64-bit address arithmetic;
+// `row` must be the same for every lane of the wave. The descriptor covers
+// exactly the n x n matrix (word 3 = 0x00020000, the raw 32-bit format of
+// the gfx9 family).
+// GlobalRows: lanes may belong to different clouds (batched edges).
+// ---------------------------------------------------------------------------
+
+struct BufferRows {
+  __amdgpu_buffer_rsrc_t rs;
+  int n;
+  __device__ BufferRows(const uint32_t* W, int n_)
+      : rs(__builtin_amdgcn_make_buffer_rsrc((void*)W, (short)0, n_ * n_ * 4, 0x00020000)),
+        n(n_) {}
+  // W[row][col], row uniform across the wave
+  __device__ __forceinline__ uint32_t row_at(int row, int col) const {
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, col * 4, row * n * 4, 0);
+  }
+  // W[row][col], both per lane
+  __device__ __forceinline__ uint32_t lane_at(int row, int col) const {
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, (row * n + col) * 4, 0, 0);
+  }
+};
+
+struct GlobalRows {
+  const uint32_t* __restrict__ W;
+  int n;
+  __device__ __forceinline__ uint32_t row_at(int row, int col) const {
+    return W[(int64_t)row * n + col];
+  }
+  __device__ __forceinline__ uint32_t lane_at(int row, int col) const {
+    return W[(int64_t)row * n + col];
+  }
+};
+
+// ---------------------------------------------------------------------------
 // The apparent-pairs test of one column (Lemma 5.3.6, Alg. 13).
 //
 // s has vertices v[D] > ... > v[0], pairwise weights pw and diameter diam.
@@ -405,9 +443,8 @@ hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, Cl
 // s is not apparent. Returns the added vertex x, or -1 if s is not apparent.
 // ---------------------------------------------------------------------------
 
-template <int D>
-__device__ __forceinline__ int apparent_cofacet(const uint32_t* __restrict__ W, int n,
-                                                const int (&v)[D + 1],
+template <int D, class Rows>
+__device__ __forceinline__ int apparent_cofacet(const Rows& rows, int n, const int (&v)[D + 1],
                                                 const uint32_t (&pw)[D + 1][D + 1],
                                                 uint32_t diam, unsigned long long& steps) {
   // Condition 1, kScan values of x per round trip: their loads are issued
@@ -415,7 +452,9 @@ __device__ __forceinline__ int apparent_cofacet(const uint32_t* __restrict__ W, 
   // s is never taken: its own row holds kInf on the diagonal. W is
   // symmetric, so row x (the same for every lane of the wave, as x moves in
   // lockstep) is read at the lanes' vertices; v[0] is consecutive across
-  // neighbouring lanes and the loads coalesce.
+  // neighbouring lanes and the loads coalesce. Rows below 0 are clamped to
+  // row 0 and their result forced to kInf (or-ing the sign of x - j), which
+  // keeps the loads unconditional.
   constexpr int kScan = 4;
   int found = -1;
   for (int x = n - 1; x >= 0 && found < 0; x -= kScan) {
@@ -423,11 +462,11 @@ __device__ __forceinline__ int apparent_cofacet(const uint32_t* __restrict__ W, 
 #pragma unroll
     for (int j = 0; j < kScan; ++j) {
       const int xj = x - j;
-      const uint32_t* __restrict__ row = W + (int64_t)max(xj, 0) * n;
+      const int r = max(xj, 0);
       uint32_t m = 0;
 #pragma unroll
-      for (int i = 0; i <= D; ++i) m = max(m, row[v[i]]);
-      mx[j] = xj >= 0 ? m : kInf;
+      for (int i = 0; i <= D; ++i) m = max(m, rows.row_at(r, v[i]));
+      mx[j] = m | (uint32_t)(xj >> 31);
     }
 #pragma unroll
     for (int j = kScan - 1; j >= 0; --j)  // the largest x with the diameter kept
@@ -441,10 +480,9 @@ __device__ __forceinline__ int apparent_cofacet(const uint32_t* __restrict__ W, 
   steps += (unsigned long long)(found >= 0 ? n - found - above : n - (D + 1));
   if (found < 0) return -1;
   // Condition 2 on t = s + {x}
-  const uint32_t* __restrict__ row = W + (int64_t)found * n;
   uint32_t mv[D + 1];
 #pragma unroll
-  for (int i = 0; i <= D; ++i) mv[i] = row[v[i]];
+  for (int i = 0; i <= D; ++i) mv[i] = rows.lane_at(found, v[i]);
 #pragma unroll
   for (int u = 0; u <= D; ++u) {
     if (v[u] < found) continue;
@@ -522,6 +560,7 @@ __global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
     ApparentPair* __restrict__ ap, uint64_t ap_cap, Scalars* __restrict__ sc) {
   const int np1 = n + 1;
   auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
+  const BufferRows rows(W, n);
   unsigned long long n_cols = 0, n_app = 0, n_steps = 0;
 
   // units are strided over the workgroups (a dispatch holds < 2^32 work-items)
@@ -568,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
 #pragma unroll
   for (int i = 3; i <= D; ++i)
 #pragma unroll
-    for (int j = 2; j < i; ++j) pmax = max(pmax, W[(int64_t)v[i] * n + v[j]]);
+    for (int j = 2; j < i; ++j) pmax = max(pmax, rows.row_at(v[i], v[j]));
   // a prefix with an edge above the threshold spans no simplex of the
   // complex: the whole unit is skipped (uniform across the workgroup); this
   // is what keeps a threshold far below the enclosing radius cheap
@@ -584,31 +623,36 @@ __global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
 #pragma unroll
     for (int i = 2; i <= D; ++i) vv[i] = v[i];
     if (k < k_end) {
-      // suffix: largest v1 with C(v1, 2) <= k, then v0
-      int v1 = (int)((1.0f + sqrtf(8.0f * (float)k + 1.0f)) * 0.5f);
-      while ((uint64_t)v1 * (v1 - 1) / 2 > k) --v1;
-      while ((uint64_t)(v1 + 1) * v1 / 2 <= k) ++v1;
+      // suffix: largest v1 with C(v1, 2) <= k, then v0. k < C(n, 2) < 2^22
+      // and 8k + 1 < 2^24 are exact in 32 bits and in a float; the square
+      // root is off by at most one, which the integer checks correct
+      const uint32_t k32 = (uint32_t)k;
+      int v1 = (int)((1.0f + sqrtf((float)(8u * k32 + 1u))) * 0.5f);
+      while ((uint32_t)v1 * (uint32_t)(v1 - 1) / 2u > k32) --v1;
+      while ((uint32_t)(v1 + 1) * (uint32_t)v1 / 2u <= k32) ++v1;
       vv[1] = v1;
-      vv[0] = (int)(k - (uint64_t)v1 * (v1 - 1) / 2);
+      vv[0] = (int)(k32 - (uint32_t)v1 * (uint32_t)(v1 - 1) / 2u);
       c = base + k;
       diam = pmax;
+      // rows of the prefix vertices are uniform; (v1, v0) is per lane
+      pw[1][0] = rows.lane_at(vv[1], vv[0]);
+      diam = max(diam, pw[1][0]);
 #pragma unroll
-      for (int i = 1; i <= D; ++i)
+      for (int i = 2; i <= D; ++i)
 #pragma unroll
-        for (int j = 0; j < i; ++j) {
-          if (j >= 2) continue;  // prefix pairs are folded into pmax
-          pw[i][j] = W[(int64_t)vv[i] * n + vv[j]];
+        for (int j = 0; j < 2; ++j) {
+          pw[i][j] = rows.row_at(vv[i], vv[j]);
           diam = max(diam, pw[i][j]);
         }
 #pragma unroll
       for (int i = 3; i <= D; ++i)
 #pragma unroll
-        for (int j = 2; j < i; ++j) pw[i][j] = W[(int64_t)vv[i] * n + vv[j]];
+        for (int j = 2; j < i; ++j) pw[i][j] = rows.row_at(vv[i], vv[j]);
       const bool cleared = clear_in && ((clear_in[c >> 5] >> (c & 31)) & 1u);
       is_col = diam != kInf && !cleared;
       if (is_col) {
         ++n_cols;
-        const int x = apparent_cofacet<D>(W, n, vv, pw, diam, n_steps);
+        const int x = apparent_cofacet<D>(rows, n, vv, pw, diam, n_steps);
         if (x >= 0) {
           is_app = true;
           ++n_app;
@@ -735,7 +779,7 @@ __global__ __launch_bounds__(kBlock) void batch_edges_kernel(
         int v[2] = {b, a};
         uint32_t pw[2][2];
         pw[1][0] = diam;
-        const int x = apparent_cofacet<1>(Wc, cl.n, v, pw, diam, n_steps);
+        const int x = apparent_cofacet<1>(GlobalRows{Wc, cl.n}, cl.n, v, pw, diam, n_steps);
         if (x >= 0) {
           is_app = true;
           ++n_app;

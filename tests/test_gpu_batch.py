@@ -130,3 +130,51 @@ def test_autograd_batch_matches_oracle_gradient(ctx):
     err = np.abs(Xt.grad.cpu().numpy() - G).max() / np.abs(G).max()
     assert err <= 1e-5, err
     b.close()
+
+
+def test_autograd_against_finite_differences(ctx):
+    """The GPU gradient against central differences of the same loss, along
+    random directions. The loss is evaluated in binary64 on the pairs the GPU
+    returns (each persistence is the length of the pair's diameter edge), and
+    the GPU pairing must be the same at both ends of the stencil."""
+    import torch
+
+    from paper_2502_05063_amd.autograd import cloud_persistence
+
+    rng = np.random.default_rng(11)
+    X = synth.torus(60, 2.0, 0.5, 0.1, rng)
+    Xt = torch.from_numpy(X).cuda().requires_grad_(True)
+    b, d = cloud_persistence(Xt, ctx, dim=1)
+    ((d - b) ** 2).sum().backward()
+    g = Xt.grad.cpu().numpy().astype(np.float64)
+
+    def h1_pairs(Xs):
+        bc = ctx.barcode(X=torch.from_numpy(np.ascontiguousarray(Xs, np.float32)).cuda(), max_dim=1)
+        h1 = bc.dim(1)
+        return h1[h1["essential"] == 0]
+
+    ref = h1_pairs(X)
+
+    def loss64(Xs, pairs):
+        Xd = Xs.astype(np.float64)
+        L = 0.0
+        for p in pairs:
+            bu, bv = p["birth_edge"]
+            du, dv = p["death_edge"]
+            L += (np.linalg.norm(Xd[du] - Xd[dv]) - np.linalg.norm(Xd[bu] - Xd[bv])) ** 2
+        return L
+
+    for _ in range(4):
+        U = rng.standard_normal(X.shape)
+        Xp = (X + 1e-4 * U).astype(np.float32)
+        Xm = (X - 1e-4 * U).astype(np.float32)
+        for Xs in (Xp, Xm):
+            ps = h1_pairs(Xs)
+            assert np.array_equal(ps["birth"], ref["birth"]) and np.array_equal(ps["death"], ref["death"])
+        step = Xp.astype(np.float64) - Xm.astype(np.float64)  # the exact perturbation taken
+        fd = loss64(Xp, ref) - loss64(Xm, ref)
+        an = float((g * step).sum())
+        # relative to the summed magnitudes: the float32 gradient carries
+        # ~1e-7 relative error per component, which can dominate a sum that
+        # happens to cancel
+        assert abs(fd - an) <= 1e-5 * float(np.abs(g * step).sum()), (fd, an)
