@@ -62,6 +62,12 @@ typedef enum {
  * tunings are read from it when the context is created and appended to it
  * when found (lines "arch dimension size_bucket units_size groups_per_cu"). */
 #define VRPH_AUTOTUNE 4u
+/* Use the global-memory enumeration kernels even when the cloud is small
+ * enough (n <= 200) for the kernels that read a 16-bit rank matrix from LDS.
+ * Results are identical; this exists to compare and test the two. */
+#define VRPH_NO_LDS 8u
+/* Unknown flag bits are rejected with VRPH_EINVAL; vrph_batch_plan accepts
+ * only VRPH_KEEP_ZERO_PERSISTENCE and VRPH_NO_ENCLOSING_RADIUS. */
 
 #define VRPH_MAX_DIM 6 /* largest supported max_dim */
 

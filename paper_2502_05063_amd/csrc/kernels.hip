@@ -404,6 +404,7 @@ hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, Cl
 // ---------------------------------------------------------------------------
 
 struct BufferRows {
+  static constexpr uint32_t kInfV = kInf;  // the weight of an edge above tau_eff
   __amdgpu_buffer_rsrc_t rs;
   int n;
   __device__ BufferRows(const uint32_t* W, int n_)
@@ -417,6 +418,22 @@ struct BufferRows {
   __device__ __forceinline__ uint32_t lane_at(int row, int col) const {
     return __builtin_amdgcn_raw_buffer_load_b32(rs, (row * n + col) * 4, 0, 0);
   }
+  // float bits of a weight
+  __device__ __forceinline__ uint32_t bits(uint32_t w) const { return w; }
+};
+
+// LdsRows: the cloud's weights replaced by their dense ranks (16 bits; the
+// order, which is all the filtration uses, is the same) and staged in LDS,
+// so the reads leave the vector-memory address path altogether; rank_bits
+// maps a rank back to its weight for the outputs.
+struct LdsRows {
+  static constexpr uint32_t kInfV = 0xFFFFu;
+  const uint16_t* s;
+  int n;
+  const uint32_t* __restrict__ rank_bits;
+  __device__ __forceinline__ uint32_t row_at(int row, int col) const { return s[row * n + col]; }
+  __device__ __forceinline__ uint32_t lane_at(int row, int col) const { return s[row * n + col]; }
+  __device__ __forceinline__ uint32_t bits(uint32_t w) const { return rank_bits[w]; }
 };
 
 struct GlobalRows {
@@ -552,15 +569,15 @@ __device__ __forceinline__ uint64_t wave_append(bool take, unsigned long long* c
 // dimension d+1, counts, and optionally every apparent pair.
 // ---------------------------------------------------------------------------
 
-template <int D>
-__global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
-    const uint32_t* __restrict__ W, int n, const uint64_t* __restrict__ binom, int chunk,
+template <int D, int BS, class Rows>
+__device__ __forceinline__ void enum_units(
+    const Rows& rows, int n, const uint64_t* __restrict__ binom, int chunk,
     const uint64_t* __restrict__ unit_cum, uint64_t units, const uint32_t* __restrict__ clear_in,
     uint32_t* __restrict__ clear_out, Column* __restrict__ cols, uint64_t cols_cap,
     ApparentPair* __restrict__ ap, uint64_t ap_cap, Scalars* __restrict__ sc) {
+  constexpr uint32_t kInfW = Rows::kInfV;
   const int np1 = n + 1;
   auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
-  const BufferRows rows(W, n);
   unsigned long long n_cols = 0, n_app = 0, n_steps = 0;
 
   // units are strided over the workgroups (a dispatch holds < 2^32 work-items)
@@ -611,13 +628,13 @@ __global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
   // a prefix with an edge above the threshold spans no simplex of the
   // complex: the whole unit is skipped (uniform across the workgroup); this
   // is what keeps a threshold far below the enclosing radius cheap
-  if (pmax == kInf) continue;
+  if (pmax == kInfW) continue;
 
-  for (uint64_t kb = k_begin; kb < k_end; kb += kBlock) {
+  for (uint64_t kb = k_begin; kb < k_end; kb += BS) {
     const uint64_t k = kb + threadIdx.x;
     bool is_col = false, is_app = false;
     uint32_t pw[D + 1][D + 1];
-    uint32_t diam = kInf;
+    uint32_t diam = kInfW;
     uint64_t c = 0, tcidx = 0;
     int vv[D + 1];
 #pragma unroll
@@ -649,7 +666,7 @@ __global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
 #pragma unroll
         for (int j = 2; j < i; ++j) pw[i][j] = rows.row_at(vv[i], vv[j]);
       const bool cleared = clear_in && ((clear_in[c >> 5] >> (c & 31)) & 1u);
-      is_col = diam != kInf && !cleared;
+      is_col = diam != kInfW && !cleared;
       if (is_col) {
         ++n_cols;
         const int x = apparent_cofacet<D>(rows, n, vv, pw, diam, n_steps);
@@ -665,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
     const uint64_t slot = wave_append(is_col && !is_app, &sc->nonapparent, any);
     if (is_col && !is_app && slot < cols_cap) {
       Column r;
-      r.key_hi = ~diam;
+      r.key_hi = ~rows.bits(diam);
       r.cloud = 0;
       r.cidx = c;
       cols[slot] = r;
@@ -676,7 +693,7 @@ __global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
         ApparentPair p;
         p.s = c;
         p.t = tcidx;
-        p.diam = diam;
+        p.diam = rows.bits(diam);
         p.cloud = 0;
         ap[as] = p;
       }
@@ -684,7 +701,7 @@ __global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
   }
   }  // units
   // workgroup totals, one atomic each
-  __shared__ unsigned long long red[3][kBlock / 64];
+  __shared__ unsigned long long red[3][BS / 64];
   for (int o = 32; o > 0; o >>= 1) {
     n_cols += shfl_xor_u64(n_cols, o);
     n_app += shfl_xor_u64(n_app, o);
@@ -710,6 +727,37 @@ __global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
 }
 
 template <int D>
+__global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
+    const uint32_t* __restrict__ W, int n, const uint64_t* __restrict__ binom, int chunk,
+    const uint64_t* __restrict__ unit_cum, uint64_t units, const uint32_t* __restrict__ clear_in,
+    uint32_t* __restrict__ clear_out, Column* __restrict__ cols, uint64_t cols_cap,
+    ApparentPair* __restrict__ ap, uint64_t ap_cap, Scalars* __restrict__ sc) {
+  const BufferRows rows(W, n);
+  enum_units<D, kBlock>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out, cols,
+                        cols_cap, ap, ap_cap, sc);
+}
+
+// The same with the rank matrix (n <= kLdsMaxN, 16-bit ranks, n*n entries
+// padded to an even count) staged in LDS once per workgroup: 2 workgroups of
+// kLdsBlock lanes fill a compute unit's 160 KB.
+template <int D>
+__global__ __launch_bounds__(kLdsBlock, 2) void enum_apparent_lds_kernel(
+    const uint16_t* __restrict__ Wr, const uint32_t* __restrict__ rank_bits, int n,
+    const uint64_t* __restrict__ binom, int chunk, const uint64_t* __restrict__ unit_cum,
+    uint64_t units, const uint32_t* __restrict__ clear_in, uint32_t* __restrict__ clear_out,
+    Column* __restrict__ cols, uint64_t cols_cap, ApparentPair* __restrict__ ap, uint64_t ap_cap,
+    Scalars* __restrict__ sc) {
+  __shared__ uint32_t sw[kLdsMaxN * kLdsMaxN / 2];
+  const int words = (n * n + 1) / 2;
+  const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(Wr);
+  for (int i = threadIdx.x; i < words; i += kLdsBlock) sw[i] = src[i];
+  __syncthreads();
+  const LdsRows rows{reinterpret_cast<const uint16_t*>(sw), n, rank_bits};
+  enum_units<D, kLdsBlock>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out, cols,
+                           cols_cap, ap, ap_cap, sc);
+}
+
+template <int D>
 static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom, int chunk,
                                 const uint64_t* unit_cum, uint64_t units, unsigned grid,
                                 const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
@@ -718,6 +766,41 @@ static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom,
   enum_apparent_kernel<D><<<grid, kBlock, 0, s>>>(W, n, binom, chunk, unit_cum, units, clear_in,
                                                   clear_out, cols, cols_cap, ap, ap_cap, sc);
   return hipGetLastError();
+}
+
+template <int D>
+static hipError_t launch_enum_lds_D(const uint16_t* Wr, const uint32_t* rank_bits, int n,
+                                    const uint64_t* binom, int chunk, const uint64_t* unit_cum,
+                                    uint64_t units, unsigned grid, const uint32_t* clear_in,
+                                    uint32_t* clear_out, Column* cols, uint64_t cols_cap,
+                                    ApparentPair* ap, uint64_t ap_cap, Scalars* sc,
+                                    hipStream_t s) {
+  enum_apparent_lds_kernel<D><<<grid, kLdsBlock, 0, s>>>(Wr, rank_bits, n, binom, chunk, unit_cum,
+                                                         units, clear_in, clear_out, cols, cols_cap,
+                                                         ap, ap_cap, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
+                                    const uint64_t* binom, int chunk, const uint64_t* unit_cum,
+                                    uint64_t units, unsigned max_groups,
+                                    const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
+                                    uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
+                                    Scalars* sc, hipStream_t s) {
+  if (units == 0) return hipSuccess;
+  if (n < 1 || n > kLdsMaxN || chunk < kLdsBlock || chunk % kLdsBlock || max_groups == 0)
+    return hipErrorInvalidValue;
+  uint64_t g = units < (uint64_t)max_groups ? units : (uint64_t)max_groups;
+  if (g > (uint64_t)kMaxGroups) g = kMaxGroups;
+  const unsigned grid = (unsigned)g;
+  switch (d) {
+    case 2: return launch_enum_lds_D<2>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
+    case 3: return launch_enum_lds_D<3>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
+    case 4: return launch_enum_lds_D<4>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
+    case 5: return launch_enum_lds_D<5>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
+    case 6: return launch_enum_lds_D<6>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <tuple>
 #include <sstream>
 #include <memory>
 #include <new>
@@ -180,12 +181,14 @@ struct vrph_ctx {
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
   DevBuf D, W, binom, bitmaps, cols, cols_tmp, sort_work, ap, scal, clouds, cstate, h0, deaths;
+  DevBuf wr16, rank_bits;  // 16-bit rank matrix and rank -> weight table (LDS kernels)
   HostPinned h_scal, h_cstate;
   std::vector<uint64_t> h_binom;
   int binom_n = -1, binom_k = -1;
   std::string arch;
   // (dimension, size bucket) -> tuned launch setting
-  std::map<std::pair<int, int>, Tune> tuned;
+  // (dimension, size bucket, kernel variant: 0 global, 1 LDS) -> setting
+  std::map<std::tuple<int, int, int>, Tune> tuned;
   DevBuf units;                    // unit table of the d >= 2 enumeration
   std::vector<uint64_t> h_units;
 };
@@ -221,18 +224,20 @@ static void load_tuning(vrph_ctx* c) {
   if (!path) return;
   std::ifstream f(path);
   std::string arch;
-  int d, b, chunk, mult;
-  while (f >> arch >> d >> b >> chunk >> mult)
-    if (arch == c->arch && d >= 1 && d <= kMaxDim && chunk >= kBlock && chunk <= (1 << 20) &&
-        chunk % kBlock == 0 && mult >= 1 && mult <= 1024)
-      c->tuned[{d, b}] = Tune{chunk, mult};
+  int d, b, var, chunk, mult;
+  while (f >> arch >> d >> b >> var >> chunk >> mult)
+    if (arch == c->arch && d >= 1 && d <= kMaxDim && (var == 0 || var == 1) &&
+        chunk >= (var ? kLdsBlock : kBlock) && chunk <= (1 << 20) &&
+        chunk % (var ? kLdsBlock : kBlock) == 0 && mult >= 1 && mult <= 1024)
+      c->tuned[{d, b, var}] = Tune{chunk, mult};
 }
 
-static void save_tuning(vrph_ctx* c, int d, int b, const Tune& t) {
+static void save_tuning(vrph_ctx* c, const std::tuple<int, int, int>& key, const Tune& t) {
   const char* path = std::getenv("VRPH_TUNING_FILE");
   if (!path) return;
   std::ofstream f(path, std::ios::app);
-  f << c->arch << " " << d << " " << b << " " << t.chunk << " " << t.mult << "\n";
+  f << c->arch << " " << std::get<0>(key) << " " << std::get<1>(key) << " " << std::get<2>(key)
+    << " " << t.chunk << " " << t.mult << "\n";
 }
 
 struct vrph_barcode {
@@ -439,7 +444,25 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
                                  ((cs.err & 4) ? " asymmetric" : "") +
                                  ((cs.err & 8) ? " nonzero diagonal" : ""));
   H.W = hW.data();
-  RankTable ranks;  // built when a dimension first has columns to reduce
+  // Weight ranks: needed by the host reduction and, for small clouds, by the
+  // LDS enumeration kernels (16-bit ranks: C(kLdsMaxN, 2) < 0xFFFF).
+  RankTable ranks;
+  std::vector<uint16_t> h_wr16;
+  const bool use_lds = max_dim >= 2 && n <= kLdsMaxN && !(flags & VRPH_NO_LDS);
+  if (use_lds) {
+    ranks.build(n, hW.data());
+    ranks.attach(H);
+    h_wr16.assign(((size_t)n * n + 1) & ~(size_t)1, 0xFFFF);
+    for (size_t i = 0; i < (size_t)n * n; ++i)
+      h_wr16[i] = ranks.Wr[i] == kInf ? (uint16_t)0xFFFF : (uint16_t)ranks.Wr[i];
+    HIP_TRY(c->wr16.ensure(h_wr16.size() * sizeof(uint16_t)));
+    HIP_TRY(c->rank_bits.ensure(std::max<size_t>(ranks.bits.size(), 1) * sizeof(uint32_t)));
+    HIP_TRY(hipMemcpyAsync(c->wr16.p, h_wr16.data(), h_wr16.size() * sizeof(uint16_t),
+                           hipMemcpyHostToDevice, s));
+    if (!ranks.bits.empty())
+      HIP_TRY(hipMemcpyAsync(c->rank_bits.p, ranks.bits.data(),
+                             ranks.bits.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  }
 
   std::unique_ptr<vrph_barcode> bc(new (std::nothrow) vrph_barcode());
   if (!bc) return fail(VRPH_ENOMEM, "out of host memory");
@@ -503,17 +526,26 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
                          hipMemcpyHostToDevice, s);
       if (e != hipSuccess) return e;
       HIP_TRY_E(hipEventRecord(c->ev0, s));
-      HIP_TRY_E(launch_enum_apparent(d, c->W.as<uint32_t>(), n, c->binom.as<uint64_t>(), t.chunk,
-                                     c->units.as<uint64_t>(), units, max_groups, clear_in,
-                                     clear_out, c->cols.as<Column>(), cap,
-                                     keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap, dsc,
-                                     s));
+      if (use_lds)
+        HIP_TRY_E(launch_enum_apparent_lds(
+            d, c->wr16.as<uint16_t>(), c->rank_bits.as<uint32_t>(), n, c->binom.as<uint64_t>(),
+            t.chunk, c->units.as<uint64_t>(), units, max_groups, clear_in, clear_out,
+            c->cols.as<Column>(), cap, keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
+            dsc, s));
+      else
+        HIP_TRY_E(launch_enum_apparent(d, c->W.as<uint32_t>(), n, c->binom.as<uint64_t>(),
+                                       t.chunk, c->units.as<uint64_t>(), units, max_groups,
+                                       clear_in, clear_out, c->cols.as<Column>(), cap,
+                                       keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
+                                       dsc, s));
       HIP_TRY_E(hipEventRecord(c->ev2, s));
       // the host table is consumed by the copy before the next launch reuses it
       return hipStreamSynchronize(s);
     };
-    const std::pair<int, int> tkey{d, size_bucket(n)};
-    Tune param{4096, 8};
+    const bool lds_dim = use_lds && d >= 2;
+    const std::tuple<int, int, int> tkey{d, size_bucket(n), lds_dim ? 1 : 0};
+    // LDS kernels: two workgroups of kLdsBlock lanes fill a compute unit
+    Tune param = lds_dim ? Tune{4096, 2} : Tune{4096, 8};
     auto it = c->tuned.find(tkey);
     if (it != c->tuned.end()) {
       param = it->second;
@@ -534,13 +566,14 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
         }
         return hipSuccess;
       };
-      for (int mult : {1, 2, 4, 8, 16, 32, 64}) HIP_TRY(trial(Tune{param.chunk, mult}));
+      for (int mult : {1, 2, 4, 8, 16, 32, 64})
+        if (!lds_dim || mult <= 4) HIP_TRY(trial(Tune{param.chunk, mult}));
       if (d >= 2) {
         const int mult = param.mult;
         for (int chunk : {1024, 2048, 8192, 16384, 32768}) HIP_TRY(trial(Tune{chunk, mult}));
       }
       c->tuned[tkey] = param;
-      save_tuning(c, d, tkey.second, param);
+      save_tuning(c, tkey, param);
     }
     for (int attempt = 0; attempt < 2; ++attempt) {
       HIP_TRY(c->cols.ensure(cap * sizeof(Column)));
@@ -586,7 +619,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     prs.clear();
     deaths.clear();
     ReduceStats rs;
-    if (nna > 0 && !H.Wr) {
+    if (nna > 0 && !H.Wr) {  // not built yet (no LDS kernel in this call)
       ranks.build(n, hW.data());
       ranks.attach(H);
     }
@@ -611,10 +644,14 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   return VRPH_OK;
 }
 
+constexpr uint32_t kKnownFlags =
+    VRPH_KEEP_ZERO_PERSISTENCE | VRPH_NO_ENCLOSING_RADIUS | VRPH_AUTOTUNE | VRPH_NO_LDS;
+
 static vrph_status check_common(vrph_ctx* c, int64_t n, int32_t max_dim, float threshold,
-                                vrph_barcode** out) {
+                                uint32_t flags, vrph_barcode** out) {
   if (!c || !out) return fail(VRPH_EINVAL, "NULL context or output");
   *out = nullptr;
+  if (flags & ~kKnownFlags) return fail(VRPH_EINVAL, "unknown flag bits");
   if (n < 1 || n > kMaxN) return fail(VRPH_EINVAL, "n must be in [1, 2048]");
   if (max_dim < 0 || max_dim > VRPH_MAX_DIM) return fail(VRPH_EINVAL, "max_dim out of range");
   if (std::isnan(threshold) || threshold < 0) return fail(VRPH_EINVAL, "threshold must be >= 0");
@@ -624,7 +661,7 @@ static vrph_status check_common(vrph_ctx* c, int64_t n, int32_t max_dim, float t
 extern "C" vrph_status vrph_barcode_from_dist(vrph_ctx* c, const float* D, int64_t n,
                                               int32_t max_dim, float threshold, uint32_t flags,
                                               void* hip_stream, vrph_barcode** out) {
-  vrph_status st = check_common(c, n, max_dim, threshold, out);
+  vrph_status st = check_common(c, n, max_dim, threshold, flags, out);
   if (st) return st;
   if (!D) return fail(VRPH_EINVAL, "D is NULL");
   HIP_TRY(hipSetDevice(c->device));
@@ -636,7 +673,7 @@ extern "C" vrph_status vrph_barcode_from_points(vrph_ctx* c, const float* X, int
                                                 int32_t m, int32_t max_dim, float threshold,
                                                 uint32_t flags, void* hip_stream,
                                                 vrph_barcode** out) {
-  vrph_status st = check_common(c, n, max_dim, threshold, out);
+  vrph_status st = check_common(c, n, max_dim, threshold, flags, out);
   if (st) return st;
   if (!X || m < 1) return fail(VRPH_EINVAL, "X is NULL or m < 1");
   HIP_TRY(hipSetDevice(c->device));
@@ -699,6 +736,8 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
     return fail(VRPH_EINVAL, "vrph_batch_plan: bad argument");
   *out = nullptr;
   if (max_dim < 0 || max_dim > 1) return fail(VRPH_EINVAL, "vrph_batch_plan: max_dim must be 0 or 1");
+  if (flags & ~(VRPH_KEEP_ZERO_PERSISTENCE | VRPH_NO_ENCLOSING_RADIUS))
+    return fail(VRPH_EINVAL, "vrph_batch_plan: unsupported flag bits");
   if (std::isnan(threshold) || threshold < 0) return fail(VRPH_EINVAL, "threshold must be >= 0");
   HIP_TRY(hipSetDevice(c->device));
   std::unique_ptr<vrph_batch> b(new (std::nothrow) vrph_batch());

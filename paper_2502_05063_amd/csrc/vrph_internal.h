@@ -15,6 +15,10 @@ constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr int kMaxDim = 6;        // largest max_dim
 constexpr int kMaxN = 2048;       // largest cloud the one-workgroup H0 kernel takes
 constexpr int kBlock = 256;       // threads per workgroup of the streaming kernels
+// clouds up to kLdsMaxN points enumerate from a 16-bit rank matrix in LDS
+// (kLdsMaxN^2 * 2 = 80,000 bytes, two workgroups of kLdsBlock per 160 KB CU)
+constexpr int kLdsMaxN = 200;
+constexpr int kLdsBlock = 1024;
 // A dispatch counts its work-items in 32 bits: launches of kBlock-thread
 // workgroups stay at or below this many workgroups and stride over the rest.
 constexpr int kMaxGroups = 1 << 22;
@@ -81,6 +85,16 @@ hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, in
                                          CloudState* st, hipStream_t s);
 hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, CloudState* st,
                            H0Pair* out, int64_t out_stride, uint32_t* bitmaps, hipStream_t s);
+// Rank-matrix variant of the same: Wr is the n x n matrix of 16-bit weight
+// ranks (0xFFFF above tau_eff), n <= kLdsMaxN, padded to an even number of
+// entries; rank_bits maps a rank to its weight. chunk is a multiple of
+// kLdsBlock.
+hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
+                                    const uint64_t* binom, int chunk, const uint64_t* unit_cum,
+                                    uint64_t units, unsigned max_groups,
+                                    const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
+                                    uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
+                                    Scalars* sc, hipStream_t s);
 // d >= 2; unit_cum (n+1 entries, device) and units from enum_units() on the
 // host; at most max_groups workgroups, which stride over the units
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,

@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
 KEEP_ZERO_PERSISTENCE = 1
 NO_ENCLOSING_RADIUS = 2
 AUTOTUNE = 4
+NO_LDS = 8
 MAX_DIM = 6
 
 PAIR_DTYPE = np.dtype(
@@ -180,9 +181,9 @@ class Context:
         return D
 
     def barcode(self, *, X=None, D=None, max_dim=1, threshold=float("inf"), keep_zero=False,
-                no_enclosing=False, autotune=False):
+                no_enclosing=False, autotune=False, lds=True):
         flags = ((KEEP_ZERO_PERSISTENCE if keep_zero else 0) | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
-                 | (AUTOTUNE if autotune else 0))
+                 | (AUTOTUNE if autotune else 0) | (0 if lds else NO_LDS))
         out = ctypes.c_void_p()
         if X is not None:
             X = self._f32(X)

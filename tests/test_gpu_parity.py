@@ -99,6 +99,23 @@ def test_random_sweep(ctx, seed):
     assert_same(bc.pairs, ref, f"seed {seed} n {n} d {max_dim}")
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_lds_and_global_kernels_agree(ctx, seed):
+    """The rank-matrix (LDS) and weight-matrix (global) enumeration kernels
+    give the same pairs, and both the oracle's; sizes straddle the LDS limit."""
+    rng = np.random.default_rng(500 + seed)
+    n = [12, 47, 64, 130, 199, 200][seed]
+    md = 3 if n <= 64 else 2
+    X = [synth.uniform_cube, synth.sphere][seed % 2](n, 3, seed=seed)
+    D = oracle.pdist(X)
+    thr = [INF, float(np.quantile(D[D > 0], 0.6))][seed % 3 == 2]
+    a = ctx.barcode(D=dev(D), max_dim=md, threshold=thr, keep_zero=True)
+    b = ctx.barcode(D=dev(D), max_dim=md, threshold=thr, keep_zero=True, lds=False)
+    assert np.array_equal(a.pairs, b.pairs)
+    if n <= 64 or md <= 2:
+        assert_same(a.pairs, oracle.barcode(D, md, thr), f"n {n}")
+
+
 def test_ragged_tile_sizes(ctx):
     """Sizes that leave ragged tails in every kernel's launch."""
     for n in (2, 3, 65, 129):
@@ -166,6 +183,13 @@ def test_invalid_inputs_are_rejected(ctx):
         ctx.barcode(D=dev(D), max_dim=7)
     with pytest.raises(vrph.VrphError):
         ctx.barcode(D=dev(D), max_dim=1, threshold=-1.0)
+    import ctypes
+
+    Dd = dev(D)
+    out = ctypes.c_void_p()
+    st = vrph.lib().vrph_barcode_from_dist(ctx.h, Dd.data_ptr(), D.shape[0], 1, float("inf"),
+                                           1 << 7, None, ctypes.byref(out))  # an unknown flag
+    assert st == vrph.EINVAL and not out.value
     # the context still works afterwards
     ref = oracle.barcode(D, 1)
     assert_same(ctx.barcode(D=dev(D), max_dim=1, keep_zero=True).pairs, ref, "after errors")
@@ -196,9 +220,10 @@ def test_autotune_keeps_results(tmp_path, monkeypatch):
         assert np.array_equal(again.pairs, bc.pairs) and again.stats["grid"] == bc.stats["grid"]
     finally:
         c1.close()
-    # one line per tuned dimension: arch, dimension, size bucket, unit size, groups per CU
+    # one line per tuned dimension: arch, dimension, size bucket, kernel variant, unit
+    # size, groups per CU
     lines = [ln.split() for ln in tf.read_text().splitlines()]
-    assert sorted(int(f[1]) for f in lines) == [1, 2] and all(len(f) == 5 for f in lines)
+    assert sorted(int(f[1]) for f in lines) == [1, 2] and all(len(f) == 6 for f in lines)
     c2 = vrph.Context()  # reads the file
     try:
         loaded = c2.barcode(X=dev(X), max_dim=2, keep_zero=True)
