@@ -31,7 +31,8 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2502_05063_amd", "csrc", "kernels.hip")
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "enum_apparent_sphere3_192.md")
+LDS_MAX_N = 200  # clouds up to this size enumerate from the LDS rank matrix
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "enum_apparent_lds_kernel_sphere3_192.md")
 
 
 def measured_traffic(grid):
@@ -178,10 +179,12 @@ def main():
     # dominant kernel: the dimension-3 enumeration + apparent-pairs kernel
     d = max_dim
     k_ms = float(np.mean([s["apparent_ms"][d] for s in stats]))
-    cand, cof, cols = s0["candidates"][d], s0["cofacets"][d], s0["columns"][d]
-    # algorithmic 32-bit weight comparisons: C(d+1,2) per candidate for its
-    # diameter, d+1 per cofacet examined by the scans
-    ops = cand * math.comb(d + 1, 2) + cof * (d + 1)
+    cand, cof, fac = s0["candidates"][d], s0["cofacets"][d], s0["facets"][d]
+    # algorithmic 32-bit weight comparisons of the apparent-pairs test
+    # (Lemma 5.3.6): C(d+1,2) per candidate for its diameter, d+1 per cofacet
+    # examined by the scan, C(d+1,2) per facet whose diameter the second
+    # condition computes
+    ops = cand * math.comb(d + 1, 2) + cof * (d + 1) + fac * math.comb(d + 1, 2)
     achieved = ops / (k_ms / 1e3) / 1e12
     traffic = measured_traffic(s0["grid"][d])
     out = {
@@ -208,7 +211,8 @@ def main():
         "reduced_per_dim": s0["reduced"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
-                     "kernel": f"enum_apparent_kernel<{d}>", "kernel_ms": k_ms,
+                     "kernel": (f"enum_apparent_lds_kernel<{d}>" if n <= LDS_MAX_N
+                                else f"enum_apparent_kernel<{d}>"), "kernel_ms": k_ms,
                      "ops_per_launch": ops, "grid_workgroups": s0["grid"][d],
                      "hbm_gbs": (traffic / (k_ms / 1e3) / 1e9) if traffic else None},
     }

@@ -102,6 +102,8 @@ typedef struct {
  *   additions       column additions made by that reduction
  *   pairs           pairs of dimension d, all of them (also zero persistence)
  *   cofacets        cofacets examined by the apparent-pairs scans
+ *   facets          facets of a found cofacet whose diameter the second
+ *                   condition of the apparent-pairs test computed
  *   gpu_ms          device time of dimension d's kernels (HIP events)
  *   apparent_ms     device time of the enumeration + apparent-pairs kernel
  *                   of dimension d alone (HIP events on the call's stream)
@@ -115,6 +117,7 @@ typedef struct {
   int64_t additions[VRPH_MAX_DIM + 1];
   int64_t pairs[VRPH_MAX_DIM + 1];
   int64_t cofacets[VRPH_MAX_DIM + 1];
+  int64_t facets[VRPH_MAX_DIM + 1];
   double gpu_ms[VRPH_MAX_DIM + 1];
   double apparent_ms[VRPH_MAX_DIM + 1];
   double host_ms[VRPH_MAX_DIM + 1];

@@ -463,7 +463,8 @@ struct GlobalRows {
 template <int D, class Rows>
 __device__ __forceinline__ int apparent_cofacet(const Rows& rows, int n, const int (&v)[D + 1],
                                                 const uint32_t (&pw)[D + 1][D + 1],
-                                                uint32_t diam, unsigned long long& steps) {
+                                                uint32_t diam, unsigned long long& steps,
+                                                unsigned long long& facets) {
   // Condition 1, kScan values of x per round trip: their loads are issued
   // together instead of one dependent load-compare-branch per x. A vertex of
   // s is never taken: its own row holds kInf on the diagonal. W is
@@ -503,6 +504,7 @@ __device__ __forceinline__ int apparent_cofacet(const Rows& rows, int n, const i
 #pragma unroll
   for (int u = 0; u <= D; ++u) {
     if (v[u] < found) continue;
+    ++facets;
     uint32_t mx = 0;
 #pragma unroll
     for (int i = 0; i <= D; ++i) {
@@ -554,6 +556,28 @@ __device__ __forceinline__ uint64_t wave_append(bool take, unsigned long long* c
   return base + (uint64_t)__popcll(below);
 }
 
+// Sum per-lane counters over the workgroup and add each total to its global
+// counter with one atomic (thread 0). All threads of the workgroup call it.
+template <int BS, int N>
+__device__ __forceinline__ void add_block_counters(unsigned long long (&v)[N],
+                                                   unsigned long long* const (&dst)[N]) {
+  __shared__ unsigned long long red[N][BS / 64];
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += shfl_xor_u64(v[i], o);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < N; ++i) red[i][threadIdx.x >> 6] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      unsigned long long t = 0;
+      for (int w = 0; w < BS / 64; ++w) t += red[i][w];
+      atomicAdd(dst[i], t);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Dimension-d (d >= 2) enumeration + threshold + clearing + apparent test,
 // one cloud. The d-simplices (v_d > ... > v_0) are split into work units:
@@ -578,7 +602,7 @@ __device__ __forceinline__ void enum_units(
   constexpr uint32_t kInfW = Rows::kInfV;
   const int np1 = n + 1;
   auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
-  unsigned long long n_cols = 0, n_app = 0, n_steps = 0;
+  unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0;
 
   // units are strided over the workgroups (a dispatch holds < 2^32 work-items)
   for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
@@ -669,7 +693,7 @@ __device__ __forceinline__ void enum_units(
       is_col = diam != kInfW && !cleared;
       if (is_col) {
         ++n_cols;
-        const int x = apparent_cofacet<D>(rows, n, vv, pw, diam, n_steps);
+        const int x = apparent_cofacet<D>(rows, n, vv, pw, diam, n_steps, n_facets);
         if (x >= 0) {
           is_app = true;
           ++n_app;
@@ -701,29 +725,10 @@ __device__ __forceinline__ void enum_units(
   }
   }  // units
   // workgroup totals, one atomic each
-  __shared__ unsigned long long red[3][BS / 64];
-  for (int o = 32; o > 0; o >>= 1) {
-    n_cols += shfl_xor_u64(n_cols, o);
-    n_app += shfl_xor_u64(n_app, o);
-    n_steps += shfl_xor_u64(n_steps, o);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = n_cols;
-    red[1][threadIdx.x >> 6] = n_app;
-    red[2][threadIdx.x >> 6] = n_steps;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long a = 0, b = 0, c3 = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      a += red[0][w];
-      b += red[1][w];
-      c3 += red[2][w];
-    }
-    atomicAdd(&sc->columns, a);
-    atomicAdd(&sc->apparent, b);
-    atomicAdd(&sc->scan_steps, c3);
-  }
+  unsigned long long tot[4] = {n_cols, n_app, n_steps, n_facets};
+  unsigned long long* const dst[4] = {&sc->columns, &sc->apparent, &sc->scan_steps,
+                                      &sc->facet_steps};
+  add_block_counters<BS, 4>(tot, dst);
 }
 
 template <int D>
@@ -838,7 +843,7 @@ __global__ __launch_bounds__(kBlock) void batch_edges_kernel(
     int64_t total_edges, const uint32_t* __restrict__ bitmaps, Column* __restrict__ cols,
     uint64_t cols_cap, ApparentPair* __restrict__ ap, uint64_t ap_cap, uint32_t* __restrict__ clear_out,
     const uint64_t* __restrict__ binom_g, int np1, unsigned long long* __restrict__ counters) {
-  unsigned long long n_cols = 0, n_app = 0, n_steps = 0;
+  unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total_edges; base += stride) {
     const int64_t e = base + threadIdx.x;
@@ -862,7 +867,8 @@ __global__ __launch_bounds__(kBlock) void batch_edges_kernel(
         int v[2] = {b, a};
         uint32_t pw[2][2];
         pw[1][0] = diam;
-        const int x = apparent_cofacet<1>(GlobalRows{Wc, cl.n}, cl.n, v, pw, diam, n_steps);
+        const int x =
+            apparent_cofacet<1>(GlobalRows{Wc, cl.n}, cl.n, v, pw, diam, n_steps, n_facets);
         if (x >= 0) {
           is_app = true;
           ++n_app;
@@ -894,29 +900,11 @@ __global__ __launch_bounds__(kBlock) void batch_edges_kernel(
       }
     }
   }
-  __shared__ unsigned long long red[3][kBlock / 64];
-  for (int o = 32; o > 0; o >>= 1) {
-    n_cols += shfl_xor_u64(n_cols, o);
-    n_app += shfl_xor_u64(n_app, o);
-    n_steps += shfl_xor_u64(n_steps, o);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = n_cols;
-    red[1][threadIdx.x >> 6] = n_app;
-    red[2][threadIdx.x >> 6] = n_steps;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long a = 0, b = 0, c3 = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      a += red[0][w];
-      b += red[1][w];
-      c3 += red[2][w];
-    }
-    atomicAdd(&counters[0], a);
-    atomicAdd(&counters[1], b);
-    atomicAdd(&counters[5], c3);
-  }
+  // counters[] = &Scalars::columns: columns, apparent, nonapparent, candidates,
+  // apparent_written, scan_steps, facet_steps
+  unsigned long long tot[4] = {n_cols, n_app, n_steps, n_facets};
+  unsigned long long* const dst[4] = {&counters[0], &counters[1], &counters[5], &counters[6]};
+  add_block_counters<kBlock, 4>(tot, dst);
   (void)binom_g;
   (void)np1;
 }

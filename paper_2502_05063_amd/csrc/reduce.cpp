@@ -202,6 +202,27 @@ struct Keys {
   uint64_t index(K k) const { return (uint64_t)(cmax - (k & cmax)); }
 };
 
+// A vector that grows without zero-filling (default-initialised elements),
+// so a batch of keys can be appended by resizing and writing in place.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new ((void*)p) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+};
+
 // The working column: a monotone min-priority queue of row keys. Rows pushed
 // are never older than the current pivot and the pivot only gets younger,
 // so the ranks in play only grow. Rows wait in a radix heap over their rank
@@ -217,6 +238,8 @@ struct Keys {
 // and at most moved between rank buckets, never sorted.
 template <class K>
 class WorkColumn {
+  using KVec = std::vector<K, NoInitAlloc<K>>;
+
  public:
   explicit WorkColumn(const Keys<K>& ks) : ks_(ks) {}
 
@@ -227,17 +250,35 @@ class WorkColumn {
     cur_ = 0;
   }
 
-  // bucket 0 holds the rows at the current rank that are not in a run yet
-  void push(K k) { b_[bucket(ks_.rank(k))].push_back(k); }
+  // Append m keys to their buckets: bucket indices first, then one resize
+  // per touched bucket and direct writes (keys keep their order within a
+  // bucket). Bucket 0 holds the rows at the current rank not yet in a run.
+  void push_many(const K* k, size_t m) {
+    if (bk_.size() < m) bk_.resize(m);
+    size_t cnt[kBuckets] = {0};
+    for (size_t i = 0; i < m; ++i) {
+      const uint8_t b = (uint8_t)bucket(ks_.rank(k[i]));
+      bk_[i] = b;
+      ++cnt[b];
+    }
+    K* wp[kBuckets];
+    for (int b = 0; b < kBuckets; ++b)
+      if (cnt[b]) {
+        const size_t o = b_[b].size();
+        b_[b].resize(o + cnt[b]);
+        wp[b] = b_[b].data() + o;
+      }
+    for (size_t i = 0; i < m; ++i) *wp[bk_[i]]++ = k[i];
+  }
 
   // the pivot (smallest key of odd multiplicity), kept in the column; false
   // if the column is zero
   bool pivot(K* out) {
     for (;;) {
       if (!b_[0].empty()) {
-        std::vector<K>& l = b_[0];
+        KVec& l = b_[0];
         if (!std::is_sorted(l.begin(), l.end())) std::sort(l.begin(), l.end());
-        std::vector<K> v = take();
+        KVec v = take();
         v.swap(l);
         add_run(std::move(v));
       }
@@ -278,30 +319,30 @@ class WorkColumn {
 
  private:
   struct Run {
-    std::vector<K> v;
+    KVec v;
     size_t pos = 0;
     size_t left() const { return v.size() - pos; }
   };
 
   int bucket(uint32_t r) const { return r == cur_ ? 0 : 32 - __builtin_clz(r ^ cur_); }
 
-  std::vector<K> take() {
+  KVec take() {
     if (spare_.empty()) return {};
-    std::vector<K> v = std::move(spare_.back());
+    KVec v = std::move(spare_.back());
     spare_.pop_back();
     return v;
   }
-  void give(std::vector<K>&& v) {
+  void give(KVec&& v) {
     v.clear();
     spare_.push_back(std::move(v));
   }
 
-  void add_run(std::vector<K>&& v) {
+  void add_run(KVec&& v) {
     runs_.push_back(Run{std::move(v), 0});
     while (runs_.size() >= 2 && runs_.back().left() * 2 >= runs_[runs_.size() - 2].left()) {
       Run& a = runs_[runs_.size() - 2];
       Run& b = runs_.back();
-      std::vector<K> m = take();
+      KVec m = take();
       m.resize(a.left() + b.left());
       std::merge(a.v.begin() + (std::ptrdiff_t)a.pos, a.v.end(), b.v.begin() + (std::ptrdiff_t)b.pos,
                  b.v.end(), m.begin());
@@ -317,28 +358,29 @@ class WorkColumn {
     int i = 1;
     while (i < kBuckets && b_[i].empty()) ++i;
     if (i == kBuckets) return false;
-    std::vector<K>& src = b_[i];
+    KVec& src = b_[i];
     uint32_t m = ks_.rank(src[0]);
     for (K x : src) m = std::min(m, ks_.rank(x));
     cur_ = m;
     moved_.clear();
     moved_.swap(src);
-    for (K x : moved_) b_[bucket(ks_.rank(x))].push_back(x);
+    push_many(moved_.data(), moved_.size());
     return true;
   }
 
   static constexpr int kBuckets = 33;
   Keys<K> ks_;
-  std::vector<K> b_[kBuckets];
+  KVec b_[kBuckets];
   std::vector<Run> runs_;
-  std::vector<std::vector<K>> spare_;
-  std::vector<K> moved_;
+  std::vector<KVec> spare_;
+  KVec moved_;
+  std::vector<uint8_t> bk_;  // bucket of each key of a push_many
   uint32_t cur_ = 0;
 };
 
 // Push the cofacets of simplex v (index c, diameter rank dr) that are not
 // older than the row `limit`; `reach` is its reach row, computed here unless
-// the caller has it. Used to add a reduced column R_k whose pivot is
+// the caller has it; kb is scratch for 2n keys. Used to add a reduced column R_k whose pivot is
 // `limit`: R_k is zero below its pivot, so the parts of its summands below
 // the pivot cancel and are not pushed. Cofacet s + {x} has index (Alg. 14)
 // high + C(x, j+2) + low with j+1 the number of vertices below x: vertices
@@ -365,8 +407,16 @@ static void push_coboundary(const HostComplex& H, const Keys<K>& ks, const int* 
       hi = v[pos];
     }
   }
-  for (int x = n - 1; x >= 0; --x)
-    if (reach[x] != kInf && kb[x] >= limit) w.push(kb[x]);
+  // the cofacets to push, in decreasing index order, compacted into the
+  // second half of kb
+  K* out = kb + n;
+  size_t m = 0;
+  for (int x = n - 1; x >= 0; --x) {
+    const K k = kb[x];
+    out[m] = k;
+    m += (reach[x] != kInf) & (k >= limit);
+  }
+  w.push_many(out, m);
 }
 
 // Row index -> column of this dimension's reduced pivots: open addressing
@@ -439,7 +489,7 @@ static void pre_reduce(const HostComplex& H, const Keys<K>& ks, int d, const Col
     int v[kMaxDim + 3], sv[kMaxDim + 3];
     WorkColumn<K> work(ks);
     std::vector<uint32_t> reach((size_t)H.n), areach((size_t)H.n);
-    std::vector<K> kb((size_t)H.n);
+    std::vector<K> kb(2 * (size_t)H.n);
     int64_t local_adds = 0;
     for (;;) {
       const int64_t j0 = next.fetch_add(kChunk);
@@ -493,7 +543,7 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
   WorkColumn<K> work(ks);
   std::vector<Simplex> vj;
   std::vector<uint32_t> reach((size_t)H.n), areach((size_t)H.n);
-  std::vector<K> kb((size_t)H.n);
+  std::vector<K> kb(2 * (size_t)H.n);
   int sv[kMaxDim + 3], pv[kMaxDim + 3];
   std::vector<PreReduced> pre;
   std::vector<std::vector<Simplex>> chain_v;

@@ -610,6 +610,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev2));
     bc->stats.apparent_ms[d] = ms;
     bc->stats.cofacets[d] = (int64_t)sc.scan_steps;
+    bc->stats.facets[d] = (int64_t)sc.facet_steps;
     bc->stats.candidates[d] = (int64_t)ncand;
     bc->stats.columns[d] = (int64_t)sc.columns;
     bc->stats.apparent[d] = (int64_t)sc.apparent;

@@ -57,6 +57,7 @@ struct Scalars {
   uint32_t tau_bits;  // effective threshold
   uint32_t h0_count;  // H0 pairs written
   unsigned long long columns, apparent, nonapparent, candidates, apparent_written, scan_steps;
+  unsigned long long facet_steps;  // facets of t whose diameter Condition 2 computed
 };
 
 // Per-cloud description for the batched kernels.

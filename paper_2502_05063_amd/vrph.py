@@ -45,6 +45,7 @@ class Stats(ctypes.Structure):
         ("additions", ctypes.c_int64 * (MAX_DIM + 1)),
         ("pairs", ctypes.c_int64 * (MAX_DIM + 1)),
         ("cofacets", ctypes.c_int64 * (MAX_DIM + 1)),
+        ("facets", ctypes.c_int64 * (MAX_DIM + 1)),
         ("gpu_ms", ctypes.c_double * (MAX_DIM + 1)),
         ("apparent_ms", ctypes.c_double * (MAX_DIM + 1)),
         ("host_ms", ctypes.c_double * (MAX_DIM + 1)),
@@ -57,7 +58,7 @@ class Stats(ctypes.Structure):
 
     def to_dict(self):
         k = self.max_dim + 1
-        out = {f: list(getattr(self, f))[:k] for f, _ in self._fields_[:11]}
+        out = {f: list(getattr(self, f))[:k] for f, _ in self._fields_[:12]}
         out.update(tau_eff=self.tau_eff, max_dim=self.max_dim, total_ms=self.total_ms)
         return out
 

@@ -178,3 +178,76 @@ def test_autograd_against_finite_differences(ctx):
         # ~1e-7 relative error per component, which can dominate a sum that
         # happens to cancel
         assert abs(fd - an) <= 1e-5 * float(np.abs(g * step).sum()), (fd, an)
+
+
+# ---------------------------------------------------------------------------
+# full-size batched workloads against values written by the oracle alone
+# (tests/golden/make_golden.py)
+
+GOLD = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    import json
+    import os
+
+    with open(os.path.join(GOLD, f"{name}.json")) as f:
+        return json.load(f)
+
+
+def _batch_inputs(name):
+    if name == "c4_batch256":
+        return synth.circle_or_torus_batch(256, 50, 400, 0.05, seed=0)
+    return synth.torus_batch(64, 500, 0.1, seed=0)
+
+
+@pytest.mark.parametrize("name", ["c4_batch256", "c5_torus64x500"])
+def test_batch_full_size_against_oracle_golden(ctx, name):
+    import hashlib
+
+    g = _golden(name)
+    clouds = _batch_inputs(name)
+    assert [len(c) for c in clouds] == [r["n"] for r in g["clouds"]]
+    b = ctx.batch([len(c) for c in clouds], 3, max_dim=1, keep_zero=True)
+    try:
+        res = b.forward(packed(clouds))
+        for i, rec in enumerate(g["clouds"]):
+            P = np.ascontiguousarray(strip(res[i].pairs), dtype=oracle.PAIR_DTYPE)
+            counts = [int((P["dim"] == d).sum()) for d in range(2)]
+            assert counts == rec["pairs_per_dim"], (name, i)
+            assert hashlib.sha256(P.tobytes()).hexdigest() == rec["full_list_sha256"], (name, i)
+    finally:
+        b.close()
+
+
+def test_c5_full_gradient_against_oracle(ctx):
+    """The differentiable workload at full size (64 tori x 500 points): the
+    batched autograd gradient against the binary64 gradient oracle evaluated
+    on the oracle's own H1 pairs (from the golden file)."""
+    import torch
+
+    from paper_2502_05063_amd.autograd import batch_persistence
+
+    g = _golden("c5_torus64x500")
+    clouds = _batch_inputs("c5_torus64x500")
+    b = ctx.batch([len(c) for c in clouds], 3, max_dim=1)
+    try:
+        Xt = packed(clouds).requires_grad_(True)
+        births, deaths, _ = batch_persistence(Xt, b, dim=1)
+        ((deaths - births) ** 2).sum().backward()
+        G = np.zeros((Xt.shape[0], 3))
+        off = 0
+        for X, rec in zip(clouds, g["clouds"]):
+            D = oracle.pdist(X)
+            pairs = np.zeros(len(rec["h1_nonzero"]), oracle.PAIR_DTYPE)
+            for k, (bi, di) in enumerate(rec["h1_nonzero"]):
+                bu, bv = oracle.diameter_edge(D, 1, bi)
+                du, dv = oracle.diameter_edge(D, 2, di)
+                pairs[k] = (1, 0, bi, di, D[bu, bv], D[du, dv])
+            pers = (pairs["death_diam"] - pairs["birth_diam"]).astype(np.float32)
+            G[off:off + len(X)] = oracle.gradient(X, D, pairs, -2 * pers, 2 * pers)
+            off += len(X)
+        err = np.abs(Xt.grad.cpu().numpy() - G).max() / np.abs(G).max()
+        assert err <= 1e-5, err
+    finally:
+        b.close()
