@@ -60,7 +60,8 @@ typedef enum {
  * simplices per work unit), with HIP events, and keeps the fastest for the
  * context. If the environment variable VRPH_TUNING_FILE names a file,
  * tunings are read from it when the context is created and appended to it
- * when found (lines "arch dimension size_bucket units_size groups_per_cu"). */
+ * when found (lines "arch dimension size_bucket variant unit_size
+ * groups_per_cu", variant 0 for the global-memory kernel, 1 for the LDS one). */
 #define VRPH_AUTOTUNE 4u
 /* Use the global-memory enumeration kernels even when the cloud is small
  * enough (n <= 200) for the kernels that read a 16-bit rank matrix from LDS.

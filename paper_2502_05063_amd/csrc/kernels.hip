@@ -223,7 +223,7 @@ hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, in
 // The forest edges are the deaths of H0 pairs and are cleared for dim 1.
 // ---------------------------------------------------------------------------
 
-constexpr int kH0Threads = 256;
+constexpr int kH0Threads = 1024;
 
 __device__ __forceinline__ unsigned long long edge_key(uint32_t w, int a, int b) {
   const uint64_t e = a > b ? edge_index(a, b) : edge_index(b, a);
@@ -257,18 +257,28 @@ __global__ __launch_bounds__(kH0Threads) void batch_h0_kernel(const uint32_t* __
     for (int v = tid; v < n; v += kH0Threads) best[v] = kNone;
     if (tid == 0) changed = 0;
     __syncthreads();
-    // minimum outgoing edge of every vertex, folded into its component
-    for (int u = tid; u < n; u += kH0Threads) {
-      const int cu = comp[u];
-      const uint32_t* Wu = Wc + (int64_t)u * n;
-      unsigned long long mk = kNone;
-      for (int v = 0; v < n; ++v) {
-        const uint32_t w = Wu[v];
-        if (w == kInf || comp[v] == cu) continue;
-        const unsigned long long k = edge_key(w, u, v);
-        mk = k < mk ? k : mk;
+    // minimum outgoing edge of every vertex, folded into its component: a
+    // wave takes a row, its lanes stride along it (coalesced, several loads
+    // in flight), then a wave minimum and one LDS atomic per row
+    {
+      const int wave = tid >> 6, lane = tid & 63;
+      for (int u = wave; u < n; u += kH0Threads / 64) {
+        const int cu = comp[u];
+        const uint32_t* Wu = Wc + (int64_t)u * n;
+        unsigned long long mk = kNone;
+        for (int v = lane; v < n; v += 64) {
+          const uint32_t w = Wu[v];
+          if (w != kInf && comp[v] != cu) {
+            const unsigned long long k = edge_key(w, u, v);
+            mk = k < mk ? k : mk;
+          }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          const unsigned long long t = shfl_xor_u64(mk, o);
+          mk = t < mk ? t : mk;
+        }
+        if (lane == 0 && mk != kNone) atomicMin(&best[cu], mk);
       }
-      if (mk != kNone) atomicMin(&best[cu], mk);
     }
     __syncthreads();
     // every root decides, while best[] is read-only: its minimum edge goes to

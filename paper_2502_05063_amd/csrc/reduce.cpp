@@ -8,9 +8,7 @@
 
 #include <algorithm>
 #include <atomic>
-#include <cstring>
 #include <thread>
-#include <unordered_map>
 
 namespace vrph {
 
@@ -87,7 +85,7 @@ static uint32_t rank_of(const HostComplex& H, const int* v, int d) {
 
 // max over the vertices of s of the rank of edge (v_i, x); kInf if some edge
 // is above tau_eff
-static inline uint32_t reach(const HostComplex& H, const int* v, int d, int x) {
+static inline uint32_t reach_of(const HostComplex& H, const int* v, int d, int x) {
   uint32_t m = 0;
   for (int i = 0; i <= d; ++i) m = std::max(m, H.wr(v[i], x));
   return m;
@@ -97,6 +95,30 @@ static inline bool contains(const int* v, int d, int x) {
   for (int i = 0; i <= d; ++i)
     if (v[i] == x) return true;
   return false;
+}
+
+// mask = the vertices adjacent within tau_eff to every vertex of s, i.e. the
+// x whose cofacet s + {x} is in the complex (the vertices of s are not in
+// it: no vertex is its own neighbour)
+static void common_neighbors(const HostComplex& H, const int* v, int d, uint64_t* mask) {
+  const uint64_t* r0 = H.nb + (size_t)v[0] * (size_t)H.nbw;
+  for (int w = 0; w < H.nbw; ++w) mask[w] = r0[w];
+  for (int i = 1; i <= d; ++i) {
+    const uint64_t* ri = H.nb + (size_t)v[i] * (size_t)H.nbw;
+    for (int w = 0; w < H.nbw; ++w) mask[w] &= ri[w];
+  }
+}
+
+// Calls f(x) for the set bits x of mask from the largest down; stops when f
+// returns false.
+template <class F>
+static void for_each_desc(const uint64_t* mask, int words, F f) {
+  for (int w = words - 1; w >= 0; --w)
+    for (uint64_t m = mask[w]; m;) {
+      const int b = 63 - __builtin_clzll(m);
+      m &= ~(1ull << b);
+      if (!f(w * 64 + b)) return;
+    }
 }
 
 // row (r, c) is older than row (r2, c2): smaller diameter, then larger index
@@ -109,9 +131,25 @@ static inline bool older(uint32_t r, uint64_t c, uint32_t r2, uint64_t c2) {
 static bool oldest_cofacet(const HostComplex& H, const int* v, int d, uint32_t dr, uint32_t* lr,
                            uint64_t* lc) {
   bool found = false;
+  if (H.sparse) {
+    uint64_t mask[kMaxN / 64];
+    common_neighbors(H, v, d, mask);
+    for_each_desc(mask, H.nbw, [&](int x) {
+      const uint32_t m = reach_of(H, v, d, x);
+      const uint32_t r = std::max(dr, m);
+      const uint64_t c = cofacet_index(H, v, d, x);
+      if (!found || older(r, c, *lr, *lc)) {
+        *lr = r;
+        *lc = c;
+      }
+      found = true;
+      return m > dr;
+    });
+    return found;
+  }
   for (int x = H.n - 1; x >= 0; --x) {
     if (contains(v, d, x)) continue;
-    const uint32_t m = reach(H, v, d, x);
+    const uint32_t m = reach_of(H, v, d, x);
     if (m == kInf) continue;
     const uint32_t r = std::max(dr, m);
     const uint64_t c = cofacet_index(H, v, d, x);
@@ -161,9 +199,20 @@ static bool apparent_partner(const HostComplex& H, uint64_t t, uint32_t rt, int 
   int k = 0;
   for (int i = 0; i <= d + 1; ++i)
     if (i != drop) sv[k++] = tv[i];
-  compute_reach(H, sv, d, reach);
   bool older_cofacet = false;
-  for (int x = tv[drop] + 1; x < H.n; ++x) older_cofacet |= reach[x] <= rt;
+  if (H.sparse) {  // the caller's coboundary push walks the neighbours itself
+    uint64_t mask[kMaxN / 64];
+    common_neighbors(H, sv, d, mask);
+    const int u = tv[drop];
+    for_each_desc(mask, H.nbw, [&](int x) {
+      if (x <= u) return false;
+      older_cofacet |= reach_of(H, sv, d, x) <= rt;
+      return !older_cofacet;
+    });
+  } else {
+    compute_reach(H, sv, d, reach);
+    for (int x = tv[drop] + 1; x < H.n; ++x) older_cofacet |= reach[x] <= rt;
+  }
   if (older_cofacet) return false;
   uint64_t c = 0;
   for (int i = 0; i <= d; ++i) c += H.C(sv[i], i + 1);
@@ -202,8 +251,8 @@ struct Keys {
   uint64_t index(K k) const { return (uint64_t)(cmax - (k & cmax)); }
 };
 
-// A vector that grows without zero-filling (default-initialised elements),
-// so a batch of keys can be appended by resizing and writing in place.
+// A vector that grows without zero-filling (default-initialised elements):
+// a merge resizes its output and then writes every element.
 template <class T>
 struct NoInitAlloc : std::allocator<T> {
   template <class U>
@@ -250,26 +299,8 @@ class WorkColumn {
     cur_ = 0;
   }
 
-  // Append m keys to their buckets: bucket indices first, then one resize
-  // per touched bucket and direct writes (keys keep their order within a
-  // bucket). Bucket 0 holds the rows at the current rank not yet in a run.
-  void push_many(const K* k, size_t m) {
-    if (bk_.size() < m) bk_.resize(m);
-    size_t cnt[kBuckets] = {0};
-    for (size_t i = 0; i < m; ++i) {
-      const uint8_t b = (uint8_t)bucket(ks_.rank(k[i]));
-      bk_[i] = b;
-      ++cnt[b];
-    }
-    K* wp[kBuckets];
-    for (int b = 0; b < kBuckets; ++b)
-      if (cnt[b]) {
-        const size_t o = b_[b].size();
-        b_[b].resize(o + cnt[b]);
-        wp[b] = b_[b].data() + o;
-      }
-    for (size_t i = 0; i < m; ++i) *wp[bk_[i]]++ = k[i];
-  }
+  // bucket 0 holds the rows at the current rank that are not in a run yet
+  void push(K k) { b_[bucket(ks_.rank(k))].push_back(k); }
 
   // the pivot (smallest key of odd multiplicity), kept in the column; false
   // if the column is zero
@@ -364,7 +395,7 @@ class WorkColumn {
     cur_ = m;
     moved_.clear();
     moved_.swap(src);
-    push_many(moved_.data(), moved_.size());
+    for (K x : moved_) push(x);
     return true;
   }
 
@@ -374,13 +405,12 @@ class WorkColumn {
   std::vector<Run> runs_;
   std::vector<KVec> spare_;
   KVec moved_;
-  std::vector<uint8_t> bk_;  // bucket of each key of a push_many
   uint32_t cur_ = 0;
 };
 
 // Push the cofacets of simplex v (index c, diameter rank dr) that are not
 // older than the row `limit`; `reach` is its reach row, computed here unless
-// the caller has it; kb is scratch for 2n keys. Used to add a reduced column R_k whose pivot is
+// the caller has it; kb is scratch for n keys. Used to add a reduced column R_k whose pivot is
 // `limit`: R_k is zero below its pivot, so the parts of its summands below
 // the pivot cancel and are not pushed. Cofacet s + {x} has index (Alg. 14)
 // high + C(x, j+2) + low with j+1 the number of vertices below x: vertices
@@ -393,6 +423,25 @@ static void push_coboundary(const HostComplex& H, const Keys<K>& ks, const int* 
                             uint32_t dr, int d, K limit, WorkColumn<K>& w, uint32_t* reach,
                             bool have_reach, K* kb) {
   const int n = H.n;
+  if (H.sparse) {
+    // only the common neighbours have cofacets in the complex; the index
+    // sums move past a vertex of s when x drops below it
+    uint64_t mask[kMaxN / 64];
+    common_neighbors(H, v, d, mask);
+    uint64_t high = 0, low = c;
+    int pos = d;
+    for_each_desc(mask, H.nbw, [&](int x) {
+      while (pos >= 0 && v[pos] > x) {
+        high += H.C(v[pos], pos + 2);
+        low -= H.C(v[pos], pos + 1);
+        --pos;
+      }
+      const K k = ks.make(std::max(dr, reach_of(H, v, d, x)), high + H.C(x, pos + 2) + low);
+      if (k >= limit) w.push(k);
+      return true;
+    });
+    return;
+  }
   if (!have_reach) compute_reach(H, v, d, reach);
   uint64_t high = 0, low = c;
   int hi = n;  // the stretch is [lo, hi)
@@ -407,16 +456,9 @@ static void push_coboundary(const HostComplex& H, const Keys<K>& ks, const int* 
       hi = v[pos];
     }
   }
-  // the cofacets to push, in decreasing index order, compacted into the
-  // second half of kb
-  K* out = kb + n;
-  size_t m = 0;
-  for (int x = n - 1; x >= 0; --x) {
-    const K k = kb[x];
-    out[m] = k;
-    m += (reach[x] != kInf) & (k >= limit);
-  }
-  w.push_many(out, m);
+  // push in decreasing index order
+  for (int x = n - 1; x >= 0; --x)
+    if (reach[x] != kInf && kb[x] >= limit) w.push(kb[x]);
 }
 
 // Row index -> column of this dimension's reduced pivots: open addressing
@@ -489,7 +531,7 @@ static void pre_reduce(const HostComplex& H, const Keys<K>& ks, int d, const Col
     int v[kMaxDim + 3], sv[kMaxDim + 3];
     WorkColumn<K> work(ks);
     std::vector<uint32_t> reach((size_t)H.n), areach((size_t)H.n);
-    std::vector<K> kb(2 * (size_t)H.n);
+    std::vector<K> kb((size_t)H.n);
     int64_t local_adds = 0;
     for (;;) {
       const int64_t j0 = next.fetch_add(kChunk);
@@ -543,7 +585,7 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
   WorkColumn<K> work(ks);
   std::vector<Simplex> vj;
   std::vector<uint32_t> reach((size_t)H.n), areach((size_t)H.n);
-  std::vector<K> kb(2 * (size_t)H.n);
+  std::vector<K> kb((size_t)H.n);
   int sv[kMaxDim + 3], pv[kMaxDim + 3];
   std::vector<PreReduced> pre;
   std::vector<std::vector<Simplex>> chain_v;
@@ -678,13 +720,18 @@ void RankTable::build(int n, const uint32_t* W) {
     for (uint64_t x : e) tmp[cnt[(x >> shift) & 2047]++] = x;
     e.swap(tmp);
   }
+  nbw = (n + 63) / 64;
+  nb.assign((size_t)n * (size_t)nbw, 0);
   for (size_t k = 0; k < e.size(); ++k) {
     const uint32_t w = (uint32_t)(e[k] >> 32);
     if (bits.empty() || bits.back() != w) bits.push_back(w);
     const uint32_t pos = (uint32_t)e[k];
     const uint32_t a = pos / (uint32_t)n, b = pos % (uint32_t)n;
     Wr[(size_t)a * n + b] = Wr[(size_t)b * n + a] = (uint32_t)(bits.size() - 1);
+    nb[(size_t)a * nbw + (b >> 6)] |= 1ull << (b & 63);
+    nb[(size_t)b * nbw + (a >> 6)] |= 1ull << (a & 63);
   }
+  sparse = (uint64_t)e.size() * 4 < (uint64_t)n * (uint64_t)(n - 1) / 2;
 }
 
 }  // namespace vrph

@@ -18,6 +18,12 @@ struct HostComplex {
   const uint32_t* Wr = nullptr;
   const uint32_t* rank_bits = nullptr;
   uint32_t nranks = 0;
+  // Neighbour bitmaps (row v: bit x set iff edge (v, x) is within tau_eff;
+  // nbw 64-bit words per row) and whether the complex is sparse enough for
+  // the reduction to walk them instead of every vertex.
+  const uint64_t* nb = nullptr;
+  int nbw = 0;
+  bool sparse = false;
   const uint64_t* binom = nullptr;  // k-major binomial table, (kmax + 1) x (n + 1)
   int kmax = 0;
   uint64_t C(int v, int k) const { return binom[(size_t)k * (size_t)(n + 1) + (size_t)v]; }
@@ -32,11 +38,17 @@ struct HostComplex {
 struct RankTable {
   std::vector<uint32_t> Wr;    // n x n, symmetric, kInf where W is kInf
   std::vector<uint32_t> bits;  // weight (float bits) of each rank, increasing
+  std::vector<uint64_t> nb;    // neighbour bitmaps, n rows of nbw words
+  int nbw = 0;
+  bool sparse = false;         // fewer than a quarter of the edges are finite
   void build(int n, const uint32_t* W);
   void attach(HostComplex& H) const {
     H.Wr = Wr.data();
     H.rank_bits = bits.data();
     H.nranks = (uint32_t)bits.size();
+    H.nb = nb.data();
+    H.nbw = nbw;
+    H.sparse = sparse;
   }
 };
 
@@ -47,19 +59,22 @@ struct PairRec {
 
 struct ReduceStats {
   int64_t additions = 0;
-  int64_t emergent = 0;  // columns paired without building them (their first pivot was free)
+  int64_t emergent = 0;  // columns paired at their first pivot, with no addition
 };
 
 // Reduce the non-apparent columns of dimension d, given in coboundary order,
 // with the reduction-matrix technique (Sec. 5.2.9: R = D V; a column adds the
-// reduced columns of earlier pivots, so its pivot only moves up; the working
-// column is a monotone bucket queue over diameter ranks). H must carry a
-// RankTable. A column whose first pivot is free is paired
-// without building it (the emergent case of Sec. 5.2.11). Pivot lookups go to a hash map of the pairs found so far,
-// then to the apparent pairs, recognised on the fly from Def. 5.3.4 instead
-// of a stored array. The first pivot of every column, and whether it belongs
-// to an apparent pair, do not depend on the other columns: they are found
-// first, on `threads` host threads. Appends the pairs of dimension d to
+// reduced columns of earlier pivots, so its pivot only moves up). H must
+// carry a RankTable: rows are compared by weight rank. The working column is
+// a radix heap over ranks with sorted runs for the rank the pivot is in.
+// Pivot lookups go to a table of the pairs found so far, then to the apparent
+// pairs, recognised on the fly from Def. 5.3.4 instead of a stored array.
+// While a column's pivot is the cofacet of an apparent pair, the addition it
+// makes depends on no other non-apparent column; every column follows that
+// chain on its own, on `threads` host threads, before the sequential pass,
+// which continues only the columns whose pivot an earlier column already
+// took. A column whose first pivot is free is paired without building it
+// (the emergent case of Sec. 5.2.11). Appends the pairs of dimension d to
 // `pairs` and the death indices to `deaths`.
 void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,
                       int threads, std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,

@@ -13,12 +13,12 @@
 #include <cstring>
 #include <fstream>
 #include <map>
-#include <tuple>
-#include <sstream>
 #include <memory>
 #include <new>
+#include <sstream>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "reduce.h"
@@ -186,7 +186,6 @@ struct vrph_ctx {
   std::vector<uint64_t> h_binom;
   int binom_n = -1, binom_k = -1;
   std::string arch;
-  // (dimension, size bucket) -> tuned launch setting
   // (dimension, size bucket, kernel variant: 0 global, 1 LDS) -> setting
   std::map<std::tuple<int, int, int>, Tune> tuned;
   DevBuf units;                    // unit table of the d >= 2 enumeration
@@ -276,9 +275,10 @@ extern "C" void vrph_destroy(vrph_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  DevBuf* bufs[] = {&c->D,   &c->W,     &c->binom,     &c->bitmaps, &c->cols,
-                    &c->cols_tmp, &c->sort_work, &c->ap, &c->scal, &c->clouds,
-                    &c->cstate, &c->h0, &c->deaths, &c->units};
+  DevBuf* bufs[] = {&c->D,      &c->W,     &c->binom,  &c->bitmaps, &c->cols,
+                    &c->cols_tmp, &c->sort_work, &c->ap, &c->scal,  &c->clouds,
+                    &c->cstate,  &c->h0,    &c->deaths, &c->units,   &c->wr16,
+                    &c->rank_bits};
   for (DevBuf* b : bufs) b->release();
   c->h_scal.release();
   c->h_cstate.release();

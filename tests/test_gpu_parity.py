@@ -127,6 +127,33 @@ def test_ragged_tile_sizes(ctx):
         assert_same(bc.pairs, ref, f"n {n}")
 
 
+def test_degenerate_inputs(ctx):
+    """Edge cases the method has: one point, max_dim beyond the complex,
+    threshold 0, a threshold equal to an edge length (inclusive, Eq. 5.3),
+    duplicate points (zero off-diagonal distances) and no edge below the
+    threshold; every one against the oracle, all pairs included."""
+    cases = []
+    cases.append((oracle.pdist(np.zeros((1, 3), np.float32)), 2, INF))
+    X = synth.uniform_cube(5, 3, seed=7)
+    cases.append((oracle.pdist(X), 4, INF))
+    cases.append((oracle.pdist(X), 2, 0.0))
+    D = oracle.pdist(synth.uniform_cube(20, 3, seed=8))
+    edge = float(np.sort(D[np.triu_indices(20, 1)])[60])
+    cases.append((D, 2, edge))
+    Xd = synth.uniform_cube(12, 3, seed=9)
+    Xd[6:] = Xd[:6]  # every point twice
+    cases.append((oracle.pdist(Xd), 2, INF))
+    cases.append((oracle.pdist(synth.uniform_cube(15, 3, seed=10)), 2,
+                  float(np.min(oracle.pdist(synth.uniform_cube(15, 3, seed=10))[np.triu_indices(15, 1)])) / 2))
+    for i, (D, md, thr) in enumerate(cases):
+        ref = oracle.barcode(D, md, thr)
+        bc = ctx.barcode(D=dev(D), max_dim=md, threshold=thr, keep_zero=True)
+        assert_same(bc.pairs, ref, f"case {i}")
+        if md >= 2:
+            assert_same(ctx.barcode(D=dev(D), max_dim=md, threshold=thr, keep_zero=True,
+                                    lds=False).pairs, ref, f"case {i} global")
+
+
 def test_all_equal_distances_thm_5_4_2(ctx):
     for n0, d in ((9, 1), (9, 2), (8, 3)):
         D = np.ones((n0, n0), np.float32) - np.eye(n0, dtype=np.float32)
