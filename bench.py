@@ -180,12 +180,22 @@ def main():
     d = max_dim
     k_ms = float(np.mean([s["apparent_ms"][d] for s in stats]))
     cand, cof, fac = s0["candidates"][d], s0["cofacets"][d], s0["facets"][d]
-    # algorithmic 32-bit weight comparisons of the apparent-pairs test
+    cols, app, nonapp = s0["columns"][d], s0["apparent"][d], s0["reduced"][d]
+    # algorithmic bytes of the enumeration (a4) and apparent-pairs (a6) steps
+    # this launch performs, at the method's per-unit data movement: 1 bit of
+    # clearing bitmap read per candidate, an 8-byte key written (a4) and read
+    # back (a6) per column, 16 bytes per apparent pair, 8 bytes per
+    # non-apparent column and, when a next dimension exists, 1 clearing bit
+    # per apparent pair
+    alg_bytes = (cand / 8 + cols * 8 + cols * 8 + app * 16 + nonapp * 8
+                 + (app / 8 if d < max_dim else 0))
+    achieved_gbs = alg_bytes / (k_ms / 1e3) / 1e9
+    # the same launch as integer compares of the apparent-pairs test
     # (Lemma 5.3.6): C(d+1,2) per candidate for its diameter, d+1 per cofacet
     # examined by the scan, C(d+1,2) per facet whose diameter the second
     # condition computes
     ops = cand * math.comb(d + 1, 2) + cof * (d + 1) + fac * math.comb(d + 1, 2)
-    achieved = ops / (k_ms / 1e3) / 1e12
+    achieved_tops = ops / (k_ms / 1e3) / 1e12
     traffic = measured_traffic(s0["grid"][d])
     out = {
         "metric": METRIC,
@@ -209,12 +219,15 @@ def main():
         "columns_per_dim": s0["columns"],
         "apparent_per_dim": s0["apparent"],
         "reduced_per_dim": s0["reduced"],
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": (f"enum_apparent_lds_kernel<{d}>" if n <= LDS_MAX_N
                                 else f"enum_apparent_kernel<{d}>"), "kernel_ms": k_ms,
-                     "ops_per_launch": ops, "grid_workgroups": s0["grid"][d],
-                     "hbm_gbs": (traffic / (k_ms / 1e3) / 1e9) if traffic else None},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "grid_workgroups": s0["grid"][d],
+                     "measured_gbs": (traffic / (k_ms / 1e3) / 1e9) if traffic else None,
+                     "alu": {"achieved": achieved_tops, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                             "frac": achieved_tops / ALU_PEAK_TOPS, "ops_per_launch": ops}},
     }
     if not args.no_batched:
         out["batched_fwd_bwd"] = batched_vs_plain(ctx, max(2, min(args.steps, 5)))
