@@ -6,7 +6,8 @@ host submatrix reduction, result assembly) of 192 points on S^3 in R^4
 (normalised Gaussians, seed 0), dimensions 0..3, full threshold; the points
 are resident in HBM before the timed region starts.
 
-Prints one JSON line (see the design doc for every field).
+Prints one JSON line: the measured step, the roofline view of the dominant
+kernel, the oracle baseline and the batched forward+backward comparison.
 """
 from __future__ import annotations
 
@@ -144,8 +145,9 @@ def main():
                           "copies": 3}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; "
+              "clouds, or the index ranges of one cloud's dimensions, would be split "
+              "across GPUs with one process per GPU.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -29,7 +29,7 @@
  *                       up; V_j is kept. The working column is a binary heap
  *                       in which equal row keys cancel in pairs.
  *
- * Readings where the paper is silent (each also listed in the design doc):
+ * Readings where the paper is silent:
  *   - tau_eff = min(tau, R), R = min_i max_j D_ij the enclosing radius
  *     (Sec. 5.2.12, Prop. 5.2.13), unless ORC_FLAG_NO_ENCLOSING is given.
  *   - the threshold is inclusive (Eq. 5.3).

@@ -433,18 +433,36 @@ struct BufferRows {
 };
 
 // LdsRows: the cloud's weights replaced by their dense ranks (16 bits; the
-// order, which is all the filtration uses, is the same) and staged in LDS,
-// so the reads leave the vector-memory address path altogether; rank_bits
-// maps a rank back to its weight for the outputs.
+// order, which is all the filtration uses, is the same) and staged in LDS
+// in rows of lds_stride(n) entries, so the reads leave the vector-memory
+// address path altogether; rank_bits maps a rank back to its weight for
+// the outputs.
 struct LdsRows {
   static constexpr uint32_t kInfV = 0xFFFFu;
   const uint16_t* s;
   int n;
+  int stride;
   const uint32_t* __restrict__ rank_bits;
-  __device__ __forceinline__ uint32_t row_at(int row, int col) const { return s[row * n + col]; }
-  __device__ __forceinline__ uint32_t lane_at(int row, int col) const { return s[row * n + col]; }
+  __device__ __forceinline__ uint32_t row_at(int row, int col) const {
+    return s[row * stride + col];
+  }
+  __device__ __forceinline__ uint32_t lane_at(int row, int col) const {
+    return s[row * stride + col];
+  }
+  // entries col .. col+7 of a row (col a multiple of 8) as 4 words, two
+  // 16-bit ranks each, the lower column in the low half
+  __device__ __forceinline__ uint4 row8(int row, int col) const {
+    return *reinterpret_cast<const uint4*>(s + row * stride + col);
+  }
   __device__ __forceinline__ uint32_t bits(uint32_t w) const { return rank_bits[w]; }
 };
+
+// max of two pairs of unsigned 16-bit values packed in 32 bits
+__device__ __forceinline__ uint32_t max_u16x2(uint32_t a, uint32_t b) {
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                __builtin_bit_cast(u16x2, b)));
+}
 
 struct GlobalRows {
   const uint32_t* __restrict__ W;
@@ -529,6 +547,61 @@ __device__ __forceinline__ int apparent_cofacet(const Rows& rows, int n, const i
   return found;
 }
 
+// The same test on the rank matrix in LDS. Condition 1 reads 8 values of x
+// per round: the entries x-7..x of the row of each vertex of s (W is
+// symmetric) come as one 128-bit read per vertex, and their maximum over
+// the vertices is taken two ranks at a time. Rounds start at multiples of
+// 8; columns past n-1 are padding that holds the 0xFFFF of an edge above
+// the threshold, as do the diagonal entries, so neither a padding column
+// nor a vertex of s is ever taken.
+template <int D>
+__device__ __forceinline__ int apparent_cofacet_lds(const LdsRows& rows, int n,
+                                                    const int (&v)[D + 1],
+                                                    const uint32_t (&pw)[D + 1][D + 1],
+                                                    uint32_t diam, unsigned long long& steps,
+                                                    unsigned long long& facets) {
+  int found = -1;
+  for (int g = (n - 1) & ~7; g >= 0 && found < 0; g -= 8) {
+    uint4 m = rows.row8(v[0], g);
+#pragma unroll
+    for (int i = 1; i <= D; ++i) {
+      const uint4 r = rows.row8(v[i], g);
+      m.x = max_u16x2(m.x, r.x);
+      m.y = max_u16x2(m.y, r.y);
+      m.z = max_u16x2(m.z, r.z);
+      m.w = max_u16x2(m.w, r.w);
+    }
+    const uint32_t w[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j)  // the largest x with the diameter kept
+      if (((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu) <= diam) found = g + j;
+  }
+  int above = 0;
+#pragma unroll
+  for (int i = 0; i <= D; ++i) above += v[i] > found;
+  steps += (unsigned long long)(found >= 0 ? n - found - above : n - (D + 1));
+  if (found < 0) return -1;
+  uint32_t mv[D + 1];
+#pragma unroll
+  for (int i = 0; i <= D; ++i) mv[i] = rows.lane_at(v[i], found);
+#pragma unroll
+  for (int u = 0; u <= D; ++u) {
+    if (v[u] < found) continue;
+    ++facets;
+    uint32_t mx = 0;
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+      if (i == u) continue;
+      mx = max(mx, mv[i]);
+#pragma unroll
+      for (int j = 0; j < i; ++j)
+        if (j != u) mx = max(mx, pw[i][j]);
+    }
+    if (mx == diam) return -1;
+  }
+  return found;
+}
+
 // Index of the cofacet s + {x} (Eq. 5.6): vertices above x move up one position.
 template <int D>
 __device__ __forceinline__ uint64_t cofacet_index(const int (&v)[D + 1], int x,
@@ -565,6 +638,60 @@ __device__ __forceinline__ uint64_t wave_append(bool take, unsigned long long* c
   const unsigned long long below = lane ? (mask & ((~0ull) >> (64 - lane))) : 0ull;
   return base + (uint64_t)__popcll(below);
 }
+
+// Wave-aggregated append of Column records into a ColumnSink, in two
+// steps: reserve() takes the slots of the lanes with `take` in the wave's
+// region (one atomic per wave) and keeps the records; flush() writes them
+// once the atomic's result is back, the wave having done other work in
+// between. Slots past the region's end go to the overflow region (a second
+// atomic, only then). All lanes of the wave call both together.
+struct DeferredAppend {
+  bool any = false;   // the last reserve() had a taking lane (uniform)
+  bool take = false;
+  int leader = 0;     // lane that holds the reserved base (uniform)
+  uint32_t cnt = 0;   // taking lanes (uniform)
+  uint32_t below = 0; // taking lanes below this one
+  unsigned long long base = 0;
+  Column rec;
+  __device__ __forceinline__ void reserve(bool t, unsigned long long* counter, uint32_t key_hi,
+                                          uint64_t cidx) {
+    const unsigned long long mask = __ballot(t);
+    any = mask != 0;
+    if (!any) return;
+    const int lane = threadIdx.x & 63;
+    leader = __ffsll((long long)mask) - 1;
+    cnt = (uint32_t)__popcll(mask);
+    if (lane == leader) base = atomicAdd(counter, (unsigned long long)cnt);
+    below = (uint32_t)__popcll(lane ? (mask & ((~0ull) >> (64 - lane))) : 0ull);
+    take = t;
+    rec.key_hi = key_hi;
+    rec.cloud = 0;
+    rec.cidx = cidx;
+  }
+  // region r of the sink
+  __device__ __forceinline__ void flush(const ColumnSink& k, int r) {
+    if (!any) return;
+    any = false;
+    const uint64_t b = shfl_u64(base, leader);
+    const uint64_t slot = b + below;
+    Column* const region = k.cols + (uint64_t)r * k.seg;
+    if (b + cnt <= k.seg) {  // uniform
+      if (take) region[slot] = rec;
+      return;
+    }
+    const uint64_t first = b > k.seg ? b : k.seg;  // first slot past the region
+    unsigned long long ob = 0;
+    if ((int)(threadIdx.x & 63) == leader)
+      ob = atomicAdd(k.ctr + (size_t)kSinkBuckets * kSinkStride, (unsigned long long)(b + cnt - first));
+    ob = shfl_u64(ob, leader);
+    if (take) {
+      if (slot < k.seg)
+        region[slot] = rec;
+      else if (ob + (slot - first) < k.ovf_cap)
+        k.cols[(uint64_t)kSinkBuckets * k.seg + ob + (slot - first)] = rec;
+    }
+  }
+};
 
 // Sum per-lane counters over the workgroup and add each total to its global
 // counter with one atomic (thread 0). All threads of the workgroup call it.
@@ -607,12 +734,15 @@ template <int D, int BS, class Rows>
 __device__ __forceinline__ void enum_units(
     const Rows& rows, int n, const uint64_t* __restrict__ binom, int chunk,
     const uint64_t* __restrict__ unit_cum, uint64_t units, const uint32_t* __restrict__ clear_in,
-    uint32_t* __restrict__ clear_out, Column* __restrict__ cols, uint64_t cols_cap,
-    ApparentPair* __restrict__ ap, uint64_t ap_cap, Scalars* __restrict__ sc) {
+    uint32_t* __restrict__ clear_out, const ColumnSink& sink, ApparentPair* __restrict__ ap,
+    uint64_t ap_cap, Scalars* __restrict__ sc) {
   constexpr uint32_t kInfW = Rows::kInfV;
   const int np1 = n + 1;
   auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
   unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0;
+  DeferredAppend pend;
+  const int bucket = (int)((blockIdx.x * (BS / 64) + (threadIdx.x >> 6)) % kSinkBuckets);
+  unsigned long long* const bucket_ctr = sink.ctr + (size_t)bucket * kSinkStride;
 
   // units are strided over the workgroups (a dispatch holds < 2^32 work-items)
   for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
@@ -664,8 +794,15 @@ __device__ __forceinline__ void enum_units(
   // is what keeps a threshold far below the enclosing radius cheap
   if (pmax == kInfW) continue;
 
+  // the clearing words of a lane's next candidate are read one round ahead,
+  // so their latency overlaps the current candidate's work
+  uint32_t cw_next = 0;
+  if (clear_in && k_begin + threadIdx.x < k_end)
+    cw_next = clear_in[(base + k_begin + threadIdx.x) >> 5];
   for (uint64_t kb = k_begin; kb < k_end; kb += BS) {
     const uint64_t k = kb + threadIdx.x;
+    const uint32_t cw = cw_next;
+    if (clear_in && k + BS < k_end) cw_next = clear_in[(base + k + BS) >> 5];
     bool is_col = false, is_app = false;
     uint32_t pw[D + 1][D + 1];
     uint32_t diam = kInfW;
@@ -674,13 +811,18 @@ __device__ __forceinline__ void enum_units(
 #pragma unroll
     for (int i = 2; i <= D; ++i) vv[i] = v[i];
     if (k < k_end) {
-      // suffix: largest v1 with C(v1, 2) <= k, then v0. k < C(n, 2) < 2^22
-      // and 8k + 1 < 2^24 are exact in 32 bits and in a float; the square
-      // root is off by at most one, which the integer checks correct
+      // suffix: largest v1 with C(v1, 2) <= k, i.e. floor((1 + sqrt(8k+1))/2),
+      // then v0. k < C(n, 2) < 2^21 and 8k + 1 < 2^24 are exact in 32 bits
+      // and in a float. The hardware square root is within 1 ulp (2^-11 at
+      // 4096), so the estimate is within 1e-3 of the exact quotient and its
+      // floor is off by at most one either way: one exact integer step
+      // corrects it.
       const uint32_t k32 = (uint32_t)k;
-      int v1 = (int)((1.0f + sqrtf((float)(8u * k32 + 1u))) * 0.5f);
-      while ((uint32_t)v1 * (uint32_t)(v1 - 1) / 2u > k32) --v1;
-      while ((uint32_t)(v1 + 1) * (uint32_t)v1 / 2u <= k32) ++v1;
+      int v1 = (int)((1.0f + __builtin_amdgcn_sqrtf((float)(8u * k32 + 1u))) * 0.5f);
+      if ((uint32_t)v1 * (uint32_t)(v1 - 1) / 2u > k32)
+        --v1;
+      else if ((uint32_t)(v1 + 1) * (uint32_t)v1 / 2u <= k32)
+        ++v1;
       vv[1] = v1;
       vv[0] = (int)(k32 - (uint32_t)v1 * (uint32_t)(v1 - 1) / 2u);
       c = base + k;
@@ -699,11 +841,15 @@ __device__ __forceinline__ void enum_units(
       for (int i = 3; i <= D; ++i)
 #pragma unroll
         for (int j = 2; j < i; ++j) pw[i][j] = rows.row_at(vv[i], vv[j]);
-      const bool cleared = clear_in && ((clear_in[c >> 5] >> (c & 31)) & 1u);
+      const bool cleared = (cw >> (c & 31)) & 1u;
       is_col = diam != kInfW && !cleared;
       if (is_col) {
         ++n_cols;
-        const int x = apparent_cofacet<D>(rows, n, vv, pw, diam, n_steps, n_facets);
+        int x;
+        if constexpr (__is_same(Rows, LdsRows))
+          x = apparent_cofacet_lds<D>(rows, n, vv, pw, diam, n_steps, n_facets);
+        else
+          x = apparent_cofacet<D>(rows, n, vv, pw, diam, n_steps, n_facets);
         if (x >= 0) {
           is_app = true;
           ++n_app;
@@ -712,15 +858,14 @@ __device__ __forceinline__ void enum_units(
         }
       }
     }
+    // non-apparent columns: the slots are reserved now and the records
+    // written one round later, once the reserving atomic has returned
+    pend.flush(sink, bucket);
+    const bool nonapp = is_col && !is_app;
+    uint32_t key_hi = 0;
+    if (nonapp) key_hi = ~rows.bits(diam);
+    pend.reserve(nonapp, bucket_ctr, key_hi, c);
     bool any;
-    const uint64_t slot = wave_append(is_col && !is_app, &sc->nonapparent, any);
-    if (is_col && !is_app && slot < cols_cap) {
-      Column r;
-      r.key_hi = ~rows.bits(diam);
-      r.cloud = 0;
-      r.cidx = c;
-      cols[slot] = r;
-    }
     if (ap) {
       const uint64_t as = wave_append(is_app, &sc->apparent_written, any);
       if (is_app && as < ap_cap) {
@@ -734,6 +879,7 @@ __device__ __forceinline__ void enum_units(
     }
   }
   }  // units
+  pend.flush(sink, bucket);
   // workgroup totals, one atomic each
   unsigned long long tot[4] = {n_cols, n_app, n_steps, n_facets};
   unsigned long long* const dst[4] = {&sc->columns, &sc->apparent, &sc->scan_steps,
@@ -741,45 +887,50 @@ __device__ __forceinline__ void enum_units(
   add_block_counters<BS, 4>(tot, dst);
 }
 
+// 8 waves per SIMD (64 vector, 96 scalar registers) for D <= 3
 template <int D>
-__global__ __launch_bounds__(kBlock) void enum_apparent_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D <= 3 ? 8 : 4)))
+void enum_apparent_kernel(
     const uint32_t* __restrict__ W, int n, const uint64_t* __restrict__ binom, int chunk,
     const uint64_t* __restrict__ unit_cum, uint64_t units, const uint32_t* __restrict__ clear_in,
-    uint32_t* __restrict__ clear_out, Column* __restrict__ cols, uint64_t cols_cap,
-    ApparentPair* __restrict__ ap, uint64_t ap_cap, Scalars* __restrict__ sc) {
+    uint32_t* __restrict__ clear_out, ColumnSink sink, ApparentPair* __restrict__ ap,
+    uint64_t ap_cap, Scalars* __restrict__ sc) {
   const BufferRows rows(W, n);
-  enum_units<D, kBlock>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out, cols,
-                        cols_cap, ap, ap_cap, sc);
+  enum_units<D, kBlock>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out, sink, ap,
+                        ap_cap, sc);
 }
 
-// The same with the rank matrix (n <= kLdsMaxN, 16-bit ranks, n*n entries
-// padded to an even count) staged in LDS once per workgroup: 2 workgroups of
-// kLdsBlock lanes fill a compute unit's 160 KB.
+// The same with the rank matrix (n <= kLdsMaxN, 16-bit ranks, n rows of
+// lds_stride(n) entries) staged in LDS once per workgroup: 2 workgroups of
+// kLdsBlock lanes fill a compute unit's 160 KB. Two of them are resident
+// only at 8 waves per SIMD, which caps a wave at 64 vector and 96 scalar
+// registers; the compiler is held to that for D <= 3 (above, the registers
+// a wave needs leave room for one workgroup per compute unit).
 template <int D>
-__global__ __launch_bounds__(kLdsBlock, 2) void enum_apparent_lds_kernel(
+__global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(D <= 3 ? 8 : 4)))
+void enum_apparent_lds_kernel(
     const uint16_t* __restrict__ Wr, const uint32_t* __restrict__ rank_bits, int n,
     const uint64_t* __restrict__ binom, int chunk, const uint64_t* __restrict__ unit_cum,
     uint64_t units, const uint32_t* __restrict__ clear_in, uint32_t* __restrict__ clear_out,
-    Column* __restrict__ cols, uint64_t cols_cap, ApparentPair* __restrict__ ap, uint64_t ap_cap,
-    Scalars* __restrict__ sc) {
-  __shared__ uint32_t sw[kLdsMaxN * kLdsMaxN / 2];
-  const int words = (n * n + 1) / 2;
-  const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(Wr);
+    ColumnSink sink, ApparentPair* __restrict__ ap, uint64_t ap_cap, Scalars* __restrict__ sc) {
+  __shared__ uint4 sw[kLdsMaxN * kLdsMaxN / 8];
+  const int stride = lds_stride(n);
+  const int words = n * stride / 8;  // 16-byte words; stride is a multiple of 8
+  const uint4* __restrict__ src = reinterpret_cast<const uint4*>(Wr);
   for (int i = threadIdx.x; i < words; i += kLdsBlock) sw[i] = src[i];
   __syncthreads();
-  const LdsRows rows{reinterpret_cast<const uint16_t*>(sw), n, rank_bits};
-  enum_units<D, kLdsBlock>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out, cols,
-                           cols_cap, ap, ap_cap, sc);
+  const LdsRows rows{reinterpret_cast<const uint16_t*>(sw), n, stride, rank_bits};
+  enum_units<D, kLdsBlock>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out, sink,
+                           ap, ap_cap, sc);
 }
 
 template <int D>
 static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom, int chunk,
                                 const uint64_t* unit_cum, uint64_t units, unsigned grid,
-                                const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
-                                uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap, Scalars* sc,
-                                hipStream_t s) {
+                                const uint32_t* clear_in, uint32_t* clear_out, ColumnSink sink,
+                                ApparentPair* ap, uint64_t ap_cap, Scalars* sc, hipStream_t s) {
   enum_apparent_kernel<D><<<grid, kBlock, 0, s>>>(W, n, binom, chunk, unit_cum, units, clear_in,
-                                                  clear_out, cols, cols_cap, ap, ap_cap, sc);
+                                                  clear_out, sink, ap, ap_cap, sc);
   return hipGetLastError();
 }
 
@@ -787,20 +938,19 @@ template <int D>
 static hipError_t launch_enum_lds_D(const uint16_t* Wr, const uint32_t* rank_bits, int n,
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
                                     uint64_t units, unsigned grid, const uint32_t* clear_in,
-                                    uint32_t* clear_out, Column* cols, uint64_t cols_cap,
-                                    ApparentPair* ap, uint64_t ap_cap, Scalars* sc,
-                                    hipStream_t s) {
+                                    uint32_t* clear_out, ColumnSink sink, ApparentPair* ap,
+                                    uint64_t ap_cap, Scalars* sc, hipStream_t s) {
   enum_apparent_lds_kernel<D><<<grid, kLdsBlock, 0, s>>>(Wr, rank_bits, n, binom, chunk, unit_cum,
-                                                         units, clear_in, clear_out, cols, cols_cap,
-                                                         ap, ap_cap, sc);
+                                                         units, clear_in, clear_out, sink, ap,
+                                                         ap_cap, sc);
   return hipGetLastError();
 }
 
 hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
                                     uint64_t units, unsigned max_groups,
-                                    const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
-                                    uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
+                                    const uint32_t* clear_in, uint32_t* clear_out,
+                                    ColumnSink sink, ApparentPair* ap, uint64_t ap_cap,
                                     Scalars* sc, hipStream_t s) {
   if (units == 0) return hipSuccess;
   if (n < 1 || n > kLdsMaxN || chunk < kLdsBlock || chunk % kLdsBlock || max_groups == 0)
@@ -809,20 +959,19 @@ hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* r
   if (g > (uint64_t)kMaxGroups) g = kMaxGroups;
   const unsigned grid = (unsigned)g;
   switch (d) {
-    case 2: return launch_enum_lds_D<2>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
-    case 3: return launch_enum_lds_D<3>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
-    case 4: return launch_enum_lds_D<4>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
-    case 5: return launch_enum_lds_D<5>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
-    case 6: return launch_enum_lds_D<6>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
+    case 2: return launch_enum_lds_D<2>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
+    case 3: return launch_enum_lds_D<3>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
+    case 4: return launch_enum_lds_D<4>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
+    case 5: return launch_enum_lds_D<5>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
+    case 6: return launch_enum_lds_D<6>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,
                                 const uint64_t* unit_cum, uint64_t units, unsigned max_groups,
-                                const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
-                                uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap, Scalars* sc,
-                                hipStream_t s) {
+                                const uint32_t* clear_in, uint32_t* clear_out, ColumnSink sink,
+                                ApparentPair* ap, uint64_t ap_cap, Scalars* sc, hipStream_t s) {
   if (units == 0) return hipSuccess;
   if (chunk < kBlock || chunk % kBlock || max_groups == 0) return hipErrorInvalidValue;
   // at most kMaxGroups workgroups: the dispatch counts work-items in 32 bits;
@@ -833,13 +982,50 @@ hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t*
   if (g > (uint64_t)kMaxGroups) g = kMaxGroups;
   const unsigned grid = (unsigned)g;
   switch (d) {
-    case 2: return launch_enum_D<2>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
-    case 3: return launch_enum_D<3>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
-    case 4: return launch_enum_D<4>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
-    case 5: return launch_enum_D<5>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
-    case 6: return launch_enum_D<6>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, cols, cols_cap, ap, ap_cap, sc, s);
+    case 2: return launch_enum_D<2>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
+    case 3: return launch_enum_D<3>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
+    case 4: return launch_enum_D<4>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
+    case 5: return launch_enum_D<5>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
+    case 6: return launch_enum_D<6>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Packing of a ColumnSink: workgroup r < kSinkBuckets copies region r, the
+// last one the overflow region; each adds up the kept counts of the regions
+// before its own for its offset.
+// ---------------------------------------------------------------------------
+
+constexpr int kGatherThreads = 256;
+
+__global__ __launch_bounds__(kGatherThreads) void gather_columns_kernel(
+    ColumnSink k, Column* __restrict__ out, uint64_t out_cap, Scalars* __restrict__ sc) {
+  __shared__ unsigned long long part[kGatherThreads / 64];
+  const int r = blockIdx.x;
+  unsigned long long off = 0;
+  for (int q = threadIdx.x; q < r; q += kGatherThreads) {
+    const unsigned long long c = k.ctr[(size_t)q * kSinkStride];
+    off += c < k.seg ? c : k.seg;
+  }
+  for (int o = 32; o > 0; o >>= 1) off += shfl_xor_u64(off, o);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = off;
+  __syncthreads();
+  off = 0;
+  for (int w = 0; w < kGatherThreads / 64; ++w) off += part[w];
+  const unsigned long long have = k.ctr[(size_t)r * kSinkStride];
+  const uint64_t lim = r < kSinkBuckets ? k.seg : k.ovf_cap;
+  const uint64_t count = have < lim ? have : lim;
+  const Column* __restrict__ src = k.cols + (uint64_t)r * k.seg;
+  for (uint64_t i = threadIdx.x; i < count && off + i < out_cap; i += kGatherThreads)
+    out[off + i] = src[i];
+  if (r == kSinkBuckets && threadIdx.x == 0) sc->nonapparent = off + have;
+}
+
+hipError_t launch_gather_columns(ColumnSink sink, Column* out, uint64_t out_cap, Scalars* sc,
+                                 hipStream_t s) {
+  gather_columns_kernel<<<kSinkBuckets + 1, kGatherThreads, 0, s>>>(sink, out, out_cap, sc);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

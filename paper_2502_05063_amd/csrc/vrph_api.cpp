@@ -182,6 +182,8 @@ struct vrph_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
   DevBuf D, W, binom, bitmaps, cols, cols_tmp, sort_work, ap, scal, clouds, cstate, h0, deaths;
   DevBuf wr16, rank_bits;  // 16-bit rank matrix and rank -> weight table (LDS kernels)
+  DevBuf sink_ctr;         // region counters of the d >= 2 column sink
+  uint64_t col_cap = 0;    // non-apparent columns the buffers are sized for
   HostPinned h_scal, h_cstate;
   std::vector<uint64_t> h_binom;
   int binom_n = -1, binom_k = -1;
@@ -278,7 +280,7 @@ extern "C" void vrph_destroy(vrph_ctx* c) {
   DevBuf* bufs[] = {&c->D,      &c->W,     &c->binom,  &c->bitmaps, &c->cols,
                     &c->cols_tmp, &c->sort_work, &c->ap, &c->scal,  &c->clouds,
                     &c->cstate,  &c->h0,    &c->deaths, &c->units,   &c->wr16,
-                    &c->rank_bits};
+                    &c->rank_bits, &c->sink_ctr};
   for (DevBuf* b : bufs) b->release();
   c->h_scal.release();
   c->h_cstate.release();
@@ -452,9 +454,13 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   if (use_lds) {
     ranks.build(n, hW.data());
     ranks.attach(H);
-    h_wr16.assign(((size_t)n * n + 1) & ~(size_t)1, 0xFFFF);
-    for (size_t i = 0; i < (size_t)n * n; ++i)
-      h_wr16[i] = ranks.Wr[i] == kInf ? (uint16_t)0xFFFF : (uint16_t)ranks.Wr[i];
+    const size_t stride = (size_t)lds_stride((int)n);
+    h_wr16.assign((size_t)n * stride, 0xFFFF);
+    for (size_t a = 0; a < (size_t)n; ++a)
+      for (size_t b = 0; b < (size_t)n; ++b) {
+        const uint32_t r = ranks.Wr[a * (size_t)n + b];
+        h_wr16[a * stride + b] = r == kInf ? (uint16_t)0xFFFF : (uint16_t)r;
+      }
     HIP_TRY(c->wr16.ensure(h_wr16.size() * sizeof(uint16_t)));
     HIP_TRY(c->rank_bits.ensure(std::max<size_t>(ranks.bits.size(), 1) * sizeof(uint32_t)));
     HIP_TRY(hipMemcpyAsync(c->wr16.p, h_wr16.data(), h_wr16.size() * sizeof(uint16_t),
@@ -492,8 +498,15 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     uint32_t* clear_out = d < max_dim ? bm + bm_off[d + 1] : nullptr;
     // output capacities grow on demand: the kernel counts past the end
     // without writing, and the dimension runs again with the exact need
-    uint64_t cap = c->cols.cap / sizeof(Column);
+    uint64_t cap = c->col_cap;
     if (cap < 4096) cap = std::min<uint64_t>(ncand, 1 << 16) + 1;
+    // d >= 2: the kernel fills a ColumnSink in `cols`, which gather_columns
+    // packs into `cols_tmp`; d = 1 appends to `cols` directly
+    auto ensure_cols = [&]() -> hipError_t {
+      hipError_t e = c->cols.ensure((d >= 2 ? sink_records(cap) : cap) * sizeof(Column));
+      if (e == hipSuccess) e = c->cols_tmp.ensure(cap * sizeof(Column));
+      return e;
+    };
     uint64_t ap_cap = 0;
     if (keep_zero) {
       ap_cap = c->ap.cap / sizeof(ApparentPair);
@@ -501,7 +514,8 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     }
     Scalars sc;
     Scalars* dsc = c->scal.as<Scalars>();
-    HIP_TRY(c->cols.ensure(cap * sizeof(Column)));
+    HIP_TRY(ensure_cols());
+    HIP_TRY(c->sink_ctr.ensure(kSinkCounters * sizeof(unsigned long long)));
     if (keep_zero) HIP_TRY(c->ap.ensure(std::max<uint64_t>(ap_cap, 1) * sizeof(ApparentPair)));
     // the launch of dimension d with setting t (suffixes per work unit for
     // d >= 2, workgroups per compute unit); `launched` = the workgroups.
@@ -525,20 +539,23 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       e = hipMemcpyAsync(c->units.p, c->h_units.data(), c->h_units.size() * sizeof(uint64_t),
                          hipMemcpyHostToDevice, s);
       if (e != hipSuccess) return e;
+      HIP_TRY_E(hipMemsetAsync(c->sink_ctr.p, 0, kSinkCounters * sizeof(unsigned long long), s));
+      const ColumnSink sink{c->cols.as<Column>(), c->sink_ctr.as<unsigned long long>(),
+                            sink_seg(cap), cap};
       HIP_TRY_E(hipEventRecord(c->ev0, s));
       if (use_lds)
         HIP_TRY_E(launch_enum_apparent_lds(
             d, c->wr16.as<uint16_t>(), c->rank_bits.as<uint32_t>(), n, c->binom.as<uint64_t>(),
-            t.chunk, c->units.as<uint64_t>(), units, max_groups, clear_in, clear_out,
-            c->cols.as<Column>(), cap, keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
-            dsc, s));
+            t.chunk, c->units.as<uint64_t>(), units, max_groups, clear_in, clear_out, sink,
+            keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap, dsc, s));
       else
         HIP_TRY_E(launch_enum_apparent(d, c->W.as<uint32_t>(), n, c->binom.as<uint64_t>(),
                                        t.chunk, c->units.as<uint64_t>(), units, max_groups,
-                                       clear_in, clear_out, c->cols.as<Column>(), cap,
+                                       clear_in, clear_out, sink,
                                        keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
                                        dsc, s));
       HIP_TRY_E(hipEventRecord(c->ev2, s));
+      HIP_TRY_E(launch_gather_columns(sink, c->cols_tmp.as<Column>(), cap, dsc, s));
       // the host table is consumed by the copy before the next launch reuses it
       return hipStreamSynchronize(s);
     };
@@ -576,7 +593,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       save_tuning(c, tkey, param);
     }
     for (int attempt = 0; attempt < 2; ++attempt) {
-      HIP_TRY(c->cols.ensure(cap * sizeof(Column)));
+      HIP_TRY(ensure_cols());
       if (keep_zero) HIP_TRY(c->ap.ensure(std::max<uint64_t>(ap_cap, 1) * sizeof(ApparentPair)));
       HIP_TRY(hipMemsetAsync(c->scal.p, 0, sizeof(Scalars), s));
       HIP_TRY(launch_dim(param));
@@ -590,14 +607,15 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     }
     if (sc.nonapparent > cap || (keep_zero && sc.apparent_written > ap_cap))
       return fail(VRPH_EDEVICE, "column counts changed between two runs of one dimension");
+    c->col_cap = std::max(c->col_cap, cap);
     const int64_t nna = (int64_t)sc.nonapparent;
-    HIP_TRY(c->cols_tmp.ensure(std::max<int64_t>(nna, 1) * sizeof(Column)));
+    Column* const packed = d >= 2 ? c->cols_tmp.as<Column>() : c->cols.as<Column>();
+    Column* const spare = d >= 2 ? c->cols.as<Column>() : c->cols_tmp.as<Column>();
     HIP_TRY(c->sort_work.ensure(radix_sort_work_bytes(nna)));
-    HIP_TRY(radix_sort_columns(c->cols.as<Column>(), c->cols_tmp.as<Column>(), nna,
-                               bits_needed(ncand), 0, c->sort_work.p, s));
+    HIP_TRY(radix_sort_columns(packed, spare, nna, bits_needed(ncand), 0, c->sort_work.p, s));
     HIP_TRY(hipEventRecord(c->ev1, s));
     hcols.resize(nna);
-    if (nna) HIP_TRY(hipMemcpyAsync(hcols.data(), c->cols.p, nna * sizeof(Column), hipMemcpyDeviceToHost, s));
+    if (nna) HIP_TRY(hipMemcpyAsync(hcols.data(), packed, nna * sizeof(Column), hipMemcpyDeviceToHost, s));
     if (keep_zero) {
       hap.resize(sc.apparent_written);
       if (sc.apparent_written)

@@ -16,9 +16,19 @@ constexpr int kMaxDim = 6;        // largest max_dim
 constexpr int kMaxN = 2048;       // largest cloud the one-workgroup H0 kernel takes
 constexpr int kBlock = 256;       // threads per workgroup of the streaming kernels
 // clouds up to kLdsMaxN points enumerate from a 16-bit rank matrix in LDS
-// (kLdsMaxN^2 * 2 = 80,000 bytes, two workgroups of kLdsBlock per 160 KB CU)
+// (at most 80,000 bytes, two workgroups of kLdsBlock per 160 KB CU)
 constexpr int kLdsMaxN = 200;
 constexpr int kLdsBlock = 1024;
+// Row stride, in 16-bit entries, of the rank matrix in LDS: 8q >= n with q
+// odd. Rows start on 16-byte boundaries, so 8 consecutive entries of a row
+// are one 128-bit read; with q odd, the rows of 8 (32 banks) or 16 (64
+// banks) consecutive vertices start on distinct 4-bank groups, so lanes that
+// read the rows of consecutive vertices do not conflict. For n <= kLdsMaxN
+// the stride is at most kLdsMaxN.
+__host__ __device__ constexpr int lds_stride(int n) {
+  return 8 * ((((n + 7) / 8) & 1) ? (n + 7) / 8 : (n + 7) / 8 + 1);
+}
+static_assert(lds_stride(kLdsMaxN) <= kLdsMaxN, "rank matrix of kLdsMaxN points fits its LDS");
 // A dispatch counts its work-items in 32 bits: launches of kBlock-thread
 // workgroups stay at or below this many workgroups and stride over the rest.
 constexpr int kMaxGroups = 1 << 22;
@@ -60,6 +70,26 @@ struct Scalars {
   unsigned long long facet_steps;  // facets of t whose diameter Condition 2 computed
 };
 
+// Where the enumeration kernels (d >= 2) put their non-apparent columns.
+// Every wave appends to one of kSinkBuckets regions of `seg` records, each
+// with its own counter (counters 128 bytes apart): one shared counter would
+// serialise the appends of the whole device on one address. A region that
+// fills up spills into the overflow region (ovf_cap records, its counter
+// after the region counters). gather_columns then packs everything into one
+// array and stores the total in Scalars::nonapparent.
+constexpr int kSinkBuckets = 256;
+constexpr int kSinkStride = 16;  // 64-bit counters per 128 bytes
+constexpr size_t kSinkCounters = (size_t)(kSinkBuckets + 1) * kSinkStride;
+struct ColumnSink {
+  Column* cols;               // kSinkBuckets * seg region records, then ovf_cap
+  unsigned long long* ctr;    // kSinkCounters entries, zeroed before a launch
+  uint64_t seg;
+  uint64_t ovf_cap;
+};
+// a sink for up to `cap` columns: region size and records of its buffer
+inline uint64_t sink_seg(uint64_t cap) { return (cap + kSinkBuckets - 1) / kSinkBuckets; }
+inline uint64_t sink_records(uint64_t cap) { return sink_seg(cap) * kSinkBuckets + cap; }
+
 // Per-cloud description for the batched kernels.
 struct Cloud {
   int64_t x_off;    // first point of the cloud in the packed point array
@@ -86,23 +116,26 @@ hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, in
                                          CloudState* st, hipStream_t s);
 hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, CloudState* st,
                            H0Pair* out, int64_t out_stride, uint32_t* bitmaps, hipStream_t s);
-// Rank-matrix variant of the same: Wr is the n x n matrix of 16-bit weight
-// ranks (0xFFFF above tau_eff), n <= kLdsMaxN, padded to an even number of
-// entries; rank_bits maps a rank to its weight. chunk is a multiple of
-// kLdsBlock.
+// Rank-matrix variant of the same: Wr holds n rows of lds_stride(n) 16-bit
+// weight ranks (0xFFFF above tau_eff, on the diagonal and in the padding
+// past column n-1), n <= kLdsMaxN; rank_bits maps a rank to its weight.
+// chunk is a multiple of kLdsBlock.
 hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
                                     uint64_t units, unsigned max_groups,
-                                    const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
-                                    uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
+                                    const uint32_t* clear_in, uint32_t* clear_out,
+                                    ColumnSink sink, ApparentPair* ap, uint64_t ap_cap,
                                     Scalars* sc, hipStream_t s);
 // d >= 2; unit_cum (n+1 entries, device) and units from enum_units() on the
 // host; at most max_groups workgroups, which stride over the units
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,
                                 const uint64_t* unit_cum, uint64_t units, unsigned max_groups,
-                                const uint32_t* clear_in, uint32_t* clear_out, Column* cols,
-                                uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap, Scalars* sc,
-                                hipStream_t s);
+                                const uint32_t* clear_in, uint32_t* clear_out, ColumnSink sink,
+                                ApparentPair* ap, uint64_t ap_cap, Scalars* sc, hipStream_t s);
+// Packs a sink's columns into out (at most out_cap of them) and stores their
+// total count in sc->nonapparent (more than out_cap: some were not kept).
+hipError_t launch_gather_columns(ColumnSink sink, Column* out, uint64_t out_cap, Scalars* sc,
+                                 hipStream_t s);
 hipError_t launch_batch_edges(const uint32_t* W, const Cloud* clouds, int count,
                               int64_t total_edges, const uint32_t* bitmaps, Column* cols,
                               uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
