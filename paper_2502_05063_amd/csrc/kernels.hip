@@ -443,25 +443,39 @@ struct LdsRows {
   int n;
   int stride;
   const uint32_t* __restrict__ rank_bits;
+  // row * stride < 2^16: a 24-bit multiply
   __device__ __forceinline__ uint32_t row_at(int row, int col) const {
-    return s[row * stride + col];
+    return s[__umul24(row, stride) + col];
   }
   __device__ __forceinline__ uint32_t lane_at(int row, int col) const {
-    return s[row * stride + col];
+    return s[__umul24(row, stride) + col];
   }
   // entries col .. col+7 of a row (col a multiple of 8) as 4 words, two
   // 16-bit ranks each, the lower column in the low half
   __device__ __forceinline__ uint4 row8(int row, int col) const {
-    return *reinterpret_cast<const uint4*>(s + row * stride + col);
+    return *reinterpret_cast<const uint4*>(s + __umul24(row, stride) + col);
   }
   __device__ __forceinline__ uint32_t bits(uint32_t w) const { return rank_bits[w]; }
 };
 
-// max of two pairs of unsigned 16-bit values packed in 32 bits
+// Two unsigned 16-bit values packed in 32 bits: elementwise max, min and
+// saturating difference.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t max_u16x2(uint32_t a, uint32_t b) {
-  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
   return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
                                                                 __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t min_u16x2(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
+                                                                __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t addsat_u16x2(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_add_sat(__builtin_bit_cast(u16x2, a),
+                                                                    __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t subsat_u16x2(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, a),
+                                                                    __builtin_bit_cast(u16x2, b)));
 }
 
 struct GlobalRows {
@@ -474,6 +488,39 @@ struct GlobalRows {
     return W[(int64_t)row * n + col];
   }
 };
+
+// Condition 2 of the apparent-pairs test for the cofacet t = s + {x}: the
+// facets of t with a smaller index than s are t minus a vertex u > x; taking
+// them in the order of increasing u, the first one whose diameter equals
+// diam(s) makes s not apparent. The facets looked at (up
+// to the deciding one) are counted. Usually x lies above every vertex of s
+// and there is nothing to look at: the branches then skip the whole test,
+// loads included, for the wave.
+template <int D, class Rows>
+__device__ __forceinline__ bool no_equal_facet_below(const Rows& rows, const int (&v)[D + 1], int x,
+                                                     const uint32_t (&pw)[D + 1][D + 1],
+                                                     uint32_t diam, uint32_t& facets) {
+  if (v[D] < x) return true;  // x above every vertex of s
+  uint32_t mv[D + 1];
+#pragma unroll
+  for (int i = 0; i <= D; ++i) mv[i] = rows.lane_at(x, v[i]);
+#pragma unroll
+  for (int u = 0; u <= D; ++u) {
+    if (v[u] < x) continue;
+    ++facets;
+    uint32_t mx = 0;
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+      if (i == u) continue;
+      mx = max(mx, mv[i]);
+#pragma unroll
+      for (int j = 0; j < i; ++j)
+        if (j != u) mx = max(mx, pw[i][j]);
+    }
+    if (mx == diam) return false;
+  }
+  return true;
+}
 
 // ---------------------------------------------------------------------------
 // The apparent-pairs test of one column (Lemma 5.3.6, Alg. 13).
@@ -491,8 +538,8 @@ struct GlobalRows {
 template <int D, class Rows>
 __device__ __forceinline__ int apparent_cofacet(const Rows& rows, int n, const int (&v)[D + 1],
                                                 const uint32_t (&pw)[D + 1][D + 1],
-                                                uint32_t diam, unsigned long long& steps,
-                                                unsigned long long& facets) {
+                                                uint32_t diam, uint32_t& steps,
+                                                uint32_t& facets) {
   // Condition 1, kScan values of x per round trip: their loads are issued
   // together instead of one dependent load-compare-branch per x. A vertex of
   // s is never taken: its own row holds kInf on the diagonal. W is
@@ -523,28 +570,10 @@ __device__ __forceinline__ int apparent_cofacet(const Rows& rows, int n, const i
   int above = 0;
 #pragma unroll
   for (int i = 0; i <= D; ++i) above += v[i] > found;
-  steps += (unsigned long long)(found >= 0 ? n - found - above : n - (D + 1));
+  steps += (uint32_t)(found >= 0 ? n - found - above : n - (D + 1));
   if (found < 0) return -1;
   // Condition 2 on t = s + {x}
-  uint32_t mv[D + 1];
-#pragma unroll
-  for (int i = 0; i <= D; ++i) mv[i] = rows.lane_at(found, v[i]);
-#pragma unroll
-  for (int u = 0; u <= D; ++u) {
-    if (v[u] < found) continue;
-    ++facets;
-    uint32_t mx = 0;
-#pragma unroll
-    for (int i = 0; i <= D; ++i) {
-      if (i == u) continue;
-      mx = max(mx, mv[i]);
-#pragma unroll
-      for (int j = 0; j < i; ++j)
-        if (j != u) mx = max(mx, pw[i][j]);
-    }
-    if (mx == diam) return -1;
-  }
-  return found;
+  return no_equal_facet_below<D>(rows, v, found, pw, diam, facets) ? found : -1;
 }
 
 // The same test on the rank matrix in LDS. Condition 1 reads 8 values of x
@@ -558,8 +587,12 @@ template <int D>
 __device__ __forceinline__ int apparent_cofacet_lds(const LdsRows& rows, int n,
                                                     const int (&v)[D + 1],
                                                     const uint32_t (&pw)[D + 1][D + 1],
-                                                    uint32_t diam, unsigned long long& steps,
-                                                    unsigned long long& facets) {
+                                                    uint32_t diam, uint32_t& steps,
+                                                    uint32_t& facets) {
+  // per 16-bit half: max over the vertices minus diam, saturated at 0, is 0
+  // exactly where the diameter is kept; the halves' "above" flags are folded
+  // into one byte, bit j for x = g + j, and the highest clear bit wins
+  const uint32_t d2 = diam * 0x00010001u;  // diam < 0xFFFF
   int found = -1;
   for (int g = (n - 1) & ~7; g >= 0 && found < 0; g -= 8) {
     uint4 m = rows.row8(v[0], g);
@@ -571,35 +604,24 @@ __device__ __forceinline__ int apparent_cofacet_lds(const LdsRows& rows, int n,
       m.z = max_u16x2(m.z, r.z);
       m.w = max_u16x2(m.w, r.w);
     }
-    const uint32_t w[4] = {m.x, m.y, m.z, m.w};
-#pragma unroll
-    for (int j = 0; j < 8; ++j)  // the largest x with the diameter kept
-      if (((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu) <= diam) found = g + j;
+    // bit 15 of a half: set iff that x's maximum is above diam
+    const uint32_t h = 0x7FFF7FFFu;
+    const uint32_t a0 = addsat_u16x2(subsat_u16x2(m.x, d2), h);  // x = g, g+1
+    const uint32_t a1 = addsat_u16x2(subsat_u16x2(m.y, d2), h);  // g+2, g+3
+    const uint32_t a2 = addsat_u16x2(subsat_u16x2(m.z, d2), h);
+    const uint32_t a3 = addsat_u16x2(subsat_u16x2(m.w, d2), h);
+    // g+2k at bit 2k, g+2k+1 at bit 16+2k
+    const uint32_t f = 0x80008000u;
+    const uint32_t word = ((a0 & f) >> 15) | ((a1 & f) >> 13) | ((a2 & f) >> 11) | ((a3 & f) >> 9);
+    const uint32_t kept = ~(word | (word >> 15)) & 0xFFu;
+    if (kept) found = g + 31 - __clz(kept);
   }
   int above = 0;
 #pragma unroll
   for (int i = 0; i <= D; ++i) above += v[i] > found;
-  steps += (unsigned long long)(found >= 0 ? n - found - above : n - (D + 1));
+  steps += (uint32_t)(found >= 0 ? n - found - above : n - (D + 1));
   if (found < 0) return -1;
-  uint32_t mv[D + 1];
-#pragma unroll
-  for (int i = 0; i <= D; ++i) mv[i] = rows.lane_at(v[i], found);
-#pragma unroll
-  for (int u = 0; u <= D; ++u) {
-    if (v[u] < found) continue;
-    ++facets;
-    uint32_t mx = 0;
-#pragma unroll
-    for (int i = 0; i <= D; ++i) {
-      if (i == u) continue;
-      mx = max(mx, mv[i]);
-#pragma unroll
-      for (int j = 0; j < i; ++j)
-        if (j != u) mx = max(mx, pw[i][j]);
-    }
-    if (mx == diam) return -1;
-  }
-  return found;
+  return no_equal_facet_below<D>(rows, v, found, pw, diam, facets) ? found : -1;
 }
 
 // Index of the cofacet s + {x} (Eq. 5.6): vertices above x move up one position.
@@ -741,6 +763,7 @@ __device__ __forceinline__ void enum_units(
   auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
   unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0;
   DeferredAppend pend;
+  const bool need_t = clear_out != nullptr || ap != nullptr;
   const int bucket = (int)((blockIdx.x * (BS / 64) + (threadIdx.x >> 6)) % kSinkBuckets);
   unsigned long long* const bucket_ctr = sink.ctr + (size_t)bucket * kSinkStride;
 
@@ -793,6 +816,7 @@ __device__ __forceinline__ void enum_units(
   // complex: the whole unit is skipped (uniform across the workgroup); this
   // is what keeps a threshold far below the enclosing radius cheap
   if (pmax == kInfW) continue;
+  uint32_t u_steps = 0, u_facets = 0;
 
   // the clearing words of a lane's next candidate are read one round ahead,
   // so their latency overlaps the current candidate's work
@@ -819,12 +843,16 @@ __device__ __forceinline__ void enum_units(
       // corrects it.
       const uint32_t k32 = (uint32_t)k;
       int v1 = (int)((1.0f + __builtin_amdgcn_sqrtf((float)(8u * k32 + 1u))) * 0.5f);
-      if ((uint32_t)v1 * (uint32_t)(v1 - 1) / 2u > k32)
+      uint32_t t1 = __umul24(v1, v1 - 1) >> 1;  // C(v1, 2); v1 <= n < 2^12
+      if (t1 > k32) {
         --v1;
-      else if ((uint32_t)(v1 + 1) * (uint32_t)v1 / 2u <= k32)
+        t1 -= v1;
+      } else if (t1 + v1 <= k32) {
+        t1 += v1;
         ++v1;
+      }
       vv[1] = v1;
-      vv[0] = (int)(k32 - (uint32_t)v1 * (uint32_t)(v1 - 1) / 2u);
+      vv[0] = (int)(k32 - t1);
       c = base + k;
       diam = pmax;
       // rows of the prefix vertices are uniform; (v1, v0) is per lane
@@ -847,14 +875,18 @@ __device__ __forceinline__ void enum_units(
         ++n_cols;
         int x;
         if constexpr (__is_same(Rows, LdsRows))
-          x = apparent_cofacet_lds<D>(rows, n, vv, pw, diam, n_steps, n_facets);
+          x = apparent_cofacet_lds<D>(rows, n, vv, pw, diam, u_steps, u_facets);
         else
-          x = apparent_cofacet<D>(rows, n, vv, pw, diam, n_steps, n_facets);
+          x = apparent_cofacet<D>(rows, n, vv, pw, diam, u_steps, u_facets);
         if (x >= 0) {
           is_app = true;
           ++n_app;
-          tcidx = cofacet_index<D>(vv, x, binom, np1);
-          if (clear_out) atomicOr(&clear_out[tcidx >> 5], 1u << (tcidx & 31));
+          // the cofacet's index is needed only to clear it in the next
+          // dimension or to report the pair
+          if (need_t) {
+            tcidx = cofacet_index<D>(vv, x, binom, np1);
+            if (clear_out) atomicOr(&clear_out[tcidx >> 5], 1u << (tcidx & 31));
+          }
         }
       }
     }
@@ -878,6 +910,10 @@ __device__ __forceinline__ void enum_units(
       }
     }
   }
+  // a unit's counts fit 32 bits: at most chunk / BS candidates per lane,
+  // fewer than n cofacets and D + 1 facets each
+  n_steps += u_steps;
+  n_facets += u_facets;
   }  // units
   pend.flush(sink, bucket);
   // workgroup totals, one atomic each
@@ -1063,8 +1099,10 @@ __global__ __launch_bounds__(kBlock) void batch_edges_kernel(
         int v[2] = {b, a};
         uint32_t pw[2][2];
         pw[1][0] = diam;
-        const int x =
-            apparent_cofacet<1>(GlobalRows{Wc, cl.n}, cl.n, v, pw, diam, n_steps, n_facets);
+        uint32_t st = 0, fa = 0;
+        const int x = apparent_cofacet<1>(GlobalRows{Wc, cl.n}, cl.n, v, pw, diam, st, fa);
+        n_steps += st;
+        n_facets += fa;
         if (x >= 0) {
           is_app = true;
           ++n_app;
