@@ -589,10 +589,6 @@ __device__ __forceinline__ int apparent_cofacet_lds(const LdsRows& rows, int n,
                                                     const uint32_t (&pw)[D + 1][D + 1],
                                                     uint32_t diam, uint32_t& steps,
                                                     uint32_t& facets) {
-  // per 16-bit half: max over the vertices minus diam, saturated at 0, is 0
-  // exactly where the diameter is kept; the halves' "above" flags are folded
-  // into one byte, bit j for x = g + j, and the highest clear bit wins
-  const uint32_t d2 = diam * 0x00010001u;  // diam < 0xFFFF
   int found = -1;
   for (int g = (n - 1) & ~7; g >= 0 && found < 0; g -= 8) {
     uint4 m = rows.row8(v[0], g);
@@ -604,17 +600,14 @@ __device__ __forceinline__ int apparent_cofacet_lds(const LdsRows& rows, int n,
       m.z = max_u16x2(m.z, r.z);
       m.w = max_u16x2(m.w, r.w);
     }
-    // bit 15 of a half: set iff that x's maximum is above diam
-    const uint32_t h = 0x7FFF7FFFu;
-    const uint32_t a0 = addsat_u16x2(subsat_u16x2(m.x, d2), h);  // x = g, g+1
-    const uint32_t a1 = addsat_u16x2(subsat_u16x2(m.y, d2), h);  // g+2, g+3
-    const uint32_t a2 = addsat_u16x2(subsat_u16x2(m.z, d2), h);
-    const uint32_t a3 = addsat_u16x2(subsat_u16x2(m.w, d2), h);
-    // g+2k at bit 2k, g+2k+1 at bit 16+2k
-    const uint32_t f = 0x80008000u;
-    const uint32_t word = ((a0 & f) >> 15) | ((a1 & f) >> 13) | ((a2 & f) >> 11) | ((a3 & f) >> 9);
-    const uint32_t kept = ~(word | (word >> 15)) & 0xFFu;
-    if (kept) found = g + 31 - __clz(kept);
+    // the largest x = g + j with the diameter kept; j is an inline
+    // constant of the selects and g is added once
+    const uint32_t w[4] = {m.x, m.y, m.z, m.w};
+    int j_kept = -1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu) <= diam) j_kept = j;
+    if (j_kept >= 0) found = g + j_kept;
   }
   int above = 0;
 #pragma unroll
