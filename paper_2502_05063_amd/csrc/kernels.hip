@@ -745,7 +745,7 @@ __device__ __forceinline__ void add_block_counters(unsigned long long (&v)[N],
 // dimension d+1, counts, and optionally every apparent pair.
 // ---------------------------------------------------------------------------
 
-template <int D, int BS, class Rows>
+template <int D, int BS, int UL, class Rows>
 __device__ __forceinline__ void enum_units(
     const Rows& rows, int n, const uint64_t* __restrict__ binom, int chunk,
     const uint64_t* __restrict__ unit_cum, uint64_t units, const uint32_t* __restrict__ clear_in,
@@ -757,11 +757,25 @@ __device__ __forceinline__ void enum_units(
   unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0;
   DeferredAppend pend;
   const bool need_t = clear_out != nullptr || ap != nullptr;
-  const int bucket = (int)((blockIdx.x * (BS / 64) + (threadIdx.x >> 6)) % kSinkBuckets);
+  const int bucket = (int)((blockIdx.x * (BS / 64) +
+                            (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))) %
+                           kSinkBuckets);
   unsigned long long* const bucket_ctr = sink.ctr + (size_t)bucket * kSinkStride;
 
-  // units are strided over the workgroups (a dispatch holds < 2^32 work-items)
-  for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
+  // units are strided over groups of UL lanes (a dispatch holds < 2^32
+  // work-items). UL = 64: a wave takes a unit on its own, so the unit's
+  // prefix is decoded once and its last round of 64 candidates is the only
+  // partial one. UL = BS: the waves of a workgroup share a unit, and with it
+  // the rows of W it reads from the caches.
+  // The group number is read from the first lane so that the compiler
+  // knows it, and everything derived from it (the unit's decode), to be
+  // uniform across the wave: scalar registers and scalar loads.
+  static_assert(UL % 64 == 0 && BS % UL == 0, "unit groups are whole waves of a workgroup");
+  const int lane = (int)(threadIdx.x % UL);
+  const int group_in_block = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / UL));
+  const uint64_t group0 = (uint64_t)blockIdx.x * (BS / UL) + (uint64_t)group_in_block;
+  const uint64_t ngroups = (uint64_t)gridDim.x * (BS / UL);
+  for (uint64_t u = group0; u < units; u += ngroups) {
   // ---- the unit: prefix (v_d..v_2) and its suffix range (uniform) ----
   int lo = 0, hi = n - 2;  // largest i with unit_cum[i] <= u; v_2 = n-1-i
   while (lo < hi) {
@@ -806,7 +820,7 @@ __device__ __forceinline__ void enum_units(
 #pragma unroll
     for (int j = 2; j < i; ++j) pmax = max(pmax, rows.row_at(v[i], v[j]));
   // a prefix with an edge above the threshold spans no simplex of the
-  // complex: the whole unit is skipped (uniform across the workgroup); this
+  // complex: the whole unit is skipped (uniform across the wave); this
   // is what keeps a threshold far below the enclosing radius cheap
   if (pmax == kInfW) continue;
   uint32_t u_steps = 0, u_facets = 0;
@@ -814,12 +828,11 @@ __device__ __forceinline__ void enum_units(
   // the clearing words of a lane's next candidate are read one round ahead,
   // so their latency overlaps the current candidate's work
   uint32_t cw_next = 0;
-  if (clear_in && k_begin + threadIdx.x < k_end)
-    cw_next = clear_in[(base + k_begin + threadIdx.x) >> 5];
-  for (uint64_t kb = k_begin; kb < k_end; kb += BS) {
-    const uint64_t k = kb + threadIdx.x;
+  if (clear_in && k_begin + lane < k_end) cw_next = clear_in[(base + k_begin + lane) >> 5];
+  for (uint64_t kb = k_begin; kb < k_end; kb += UL) {
+    const uint64_t k = kb + lane;
     const uint32_t cw = cw_next;
-    if (clear_in && k + BS < k_end) cw_next = clear_in[(base + k + BS) >> 5];
+    if (clear_in && k + UL < k_end) cw_next = clear_in[(base + k + UL) >> 5];
     bool is_col = false, is_app = false;
     uint32_t pw[D + 1][D + 1];
     uint32_t diam = kInfW;
@@ -925,8 +938,8 @@ void enum_apparent_kernel(
     uint32_t* __restrict__ clear_out, ColumnSink sink, ApparentPair* __restrict__ ap,
     uint64_t ap_cap, Scalars* __restrict__ sc) {
   const BufferRows rows(W, n);
-  enum_units<D, kBlock>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out, sink, ap,
-                        ap_cap, sc);
+  enum_units<D, kBlock, kBlock>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out,
+                                sink, ap, ap_cap, sc);
 }
 
 // The same with the rank matrix (n <= kLdsMaxN, 16-bit ranks, n rows of
@@ -949,8 +962,8 @@ void enum_apparent_lds_kernel(
   for (int i = threadIdx.x; i < words; i += kLdsBlock) sw[i] = src[i];
   __syncthreads();
   const LdsRows rows{reinterpret_cast<const uint16_t*>(sw), n, stride, rank_bits};
-  enum_units<D, kLdsBlock>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out, sink,
-                           ap, ap_cap, sc);
+  enum_units<D, kLdsBlock, 64>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out,
+                               sink, ap, ap_cap, sc);
 }
 
 template <int D>
@@ -982,9 +995,10 @@ hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* r
                                     ColumnSink sink, ApparentPair* ap, uint64_t ap_cap,
                                     Scalars* sc, hipStream_t s) {
   if (units == 0) return hipSuccess;
-  if (n < 1 || n > kLdsMaxN || chunk < kLdsBlock || chunk % kLdsBlock || max_groups == 0)
+  if (n < 1 || n > kLdsMaxN || chunk < 64 || chunk % 64 || max_groups == 0)
     return hipErrorInvalidValue;
-  uint64_t g = units < (uint64_t)max_groups ? units : (uint64_t)max_groups;
+  const uint64_t need = (units + kLdsBlock / 64 - 1) / (kLdsBlock / 64);  // a unit per wave
+  uint64_t g = need < (uint64_t)max_groups ? need : (uint64_t)max_groups;
   if (g > (uint64_t)kMaxGroups) g = kMaxGroups;
   const unsigned grid = (unsigned)g;
   switch (d) {
@@ -1002,12 +1016,12 @@ hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t*
                                 const uint32_t* clear_in, uint32_t* clear_out, ColumnSink sink,
                                 ApparentPair* ap, uint64_t ap_cap, Scalars* sc, hipStream_t s) {
   if (units == 0) return hipSuccess;
-  if (chunk < kBlock || chunk % kBlock || max_groups == 0) return hipErrorInvalidValue;
+  if (chunk < 64 || chunk % 64 || max_groups == 0) return hipErrorInvalidValue;
   // at most kMaxGroups workgroups: the dispatch counts work-items in 32 bits;
   // a grid of a few workgroups per compute unit that loops over the units
   // keeps the per-workgroup costs (dispatch, the counter atomics at its end)
   // off the critical path
-  uint64_t g = units < (uint64_t)max_groups ? units : (uint64_t)max_groups;
+  uint64_t g = units < (uint64_t)max_groups ? units : (uint64_t)max_groups;  // a unit per group
   if (g > (uint64_t)kMaxGroups) g = kMaxGroups;
   const unsigned grid = (unsigned)g;
   switch (d) {

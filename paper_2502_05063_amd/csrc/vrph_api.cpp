@@ -170,6 +170,10 @@ double now_ms() {
 
 // Launch setting of an enumeration kernel: suffixes per work unit (d >= 2)
 // and workgroups per compute unit.
+// largest work unit (suffixes) the defaults and the autotuner use; large
+// units pay off where a threshold skips most prefixes
+constexpr int kMaxChunk = 1 << 17;
+
 struct Tune {
   int chunk;
   int mult;
@@ -228,8 +232,7 @@ static void load_tuning(vrph_ctx* c) {
   int d, b, var, chunk, mult;
   while (f >> arch >> d >> b >> var >> chunk >> mult)
     if (arch == c->arch && d >= 1 && d <= kMaxDim && (var == 0 || var == 1) &&
-        chunk >= (var ? kLdsBlock : kBlock) && chunk <= (1 << 20) &&
-        chunk % (var ? kLdsBlock : kBlock) == 0 && mult >= 1 && mult <= 1024)
+        chunk >= 64 && chunk <= (1 << 20) && chunk % 64 == 0 && mult >= 1 && mult <= 1024)
       c->tuned[{d, b, var}] = Tune{chunk, mult};
 }
 
@@ -533,7 +536,11 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
         return hipEventRecord(c->ev2, s);
       }
       const uint64_t units = enum_units(n, d, t.chunk, c->h_binom, c->h_units);
-      launched = std::min<uint64_t>(std::min<uint64_t>(units, max_groups), kMaxGroups);
+      // LDS kernel: a unit per wave; global-memory kernel: a unit per workgroup
+      const uint64_t units_per_group = use_lds ? kLdsBlock / 64 : 1;
+      launched = std::min<uint64_t>(
+          std::min<uint64_t>((units + units_per_group - 1) / units_per_group, max_groups),
+          kMaxGroups);
       hipError_t e = c->units.ensure(c->h_units.size() * sizeof(uint64_t));
       if (e != hipSuccess) return e;
       e = hipMemcpyAsync(c->units.p, c->h_units.data(), c->h_units.size() * sizeof(uint64_t),
@@ -561,15 +568,34 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     };
     const bool lds_dim = use_lds && d >= 2;
     const std::tuple<int, int, int> tkey{d, size_bucket(n), lds_dim ? 1 : 0};
-    // LDS kernels: two workgroups of kLdsBlock lanes fill a compute unit
-    Tune param = lds_dim ? Tune{4096, 2} : Tune{4096, 8};
+    // LDS kernels: two workgroups of kLdsBlock lanes fill a compute unit.
+    // Default work-unit size: the power of two in [64, 2^17] that gives the
+    // unit takers of the default grid (waves of the LDS kernel, workgroups of
+    // the other) about four units each.
+    Tune param{64, lds_dim ? 2 : 8};
+    {
+      const uint64_t takers = (uint64_t)c->num_cus * (uint64_t)param.mult *
+                              (uint64_t)(lds_dim ? kLdsBlock / 64 : 1);
+      const uint64_t per = ncand / std::max<uint64_t>(4 * takers, 1);
+      while (param.chunk < kMaxChunk && (uint64_t)param.chunk * 2 <= per) param.chunk *= 2;
+    }
     auto it = c->tuned.find(tkey);
     if (it != c->tuned.end()) {
       param = it->second;
     } else if (flags & VRPH_AUTOTUNE) {
       // time settings on this very input (outputs are rewritten by the run
-      // below): workgroups per compute unit first, then, for d >= 2, the
-      // work-unit size at the best of those
+      // below): for d >= 2 the work-unit size and the workgroups per compute
+      // unit, by coordinate search. One launch first sizes the outputs, so
+      // that no trial runs with overfull column regions.
+      HIP_TRY(hipMemsetAsync(c->scal.p, 0, sizeof(Scalars), s));
+      HIP_TRY(launch_dim(param));
+      HIP_TRY(hipMemcpyAsync(c->h_scal.p, c->scal.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      std::memcpy(&sc, c->h_scal.p, sizeof(sc));
+      if (sc.nonapparent > cap) cap = sc.nonapparent + 1024;
+      if (keep_zero && sc.apparent_written > ap_cap) ap_cap = sc.apparent_written + 1024;
+      HIP_TRY(ensure_cols());
+      if (keep_zero) HIP_TRY(c->ap.ensure(std::max<uint64_t>(ap_cap, 1) * sizeof(ApparentPair)));
       float best = -1;
       auto trial = [&](const Tune& t) -> hipError_t {
         HIP_TRY_E(hipMemsetAsync(c->scal.p, 0, sizeof(Scalars), s));
@@ -583,11 +609,17 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
         }
         return hipSuccess;
       };
-      for (int mult : {1, 2, 4, 8, 16, 32, 64})
-        if (!lds_dim || mult <= 4) HIP_TRY(trial(Tune{param.chunk, mult}));
-      if (d >= 2) {
-        const int mult = param.mult;
-        for (int chunk : {1024, 2048, 8192, 16384, 32768}) HIP_TRY(trial(Tune{chunk, mult}));
+      // two rounds of coordinate search: unit sizes at the current grid,
+      // then grids at the current unit size
+      for (int round = 0; round < 2; ++round) {
+        if (d >= 2) {
+          const int mult = param.mult;
+          for (int chunk = 64; chunk <= kMaxChunk; chunk *= 2) HIP_TRY(trial(Tune{chunk, mult}));
+        }
+        const int chunk = param.chunk;
+        for (int mult : {1, 2, 4, 8, 16, 32, 64})
+          if (!lds_dim || mult <= 4) HIP_TRY(trial(Tune{chunk, mult}));
+        if (d < 2) break;
       }
       c->tuned[tkey] = param;
       save_tuning(c, tkey, param);

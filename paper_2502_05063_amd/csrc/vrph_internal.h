@@ -86,8 +86,9 @@ struct ColumnSink {
   uint64_t seg;
   uint64_t ovf_cap;
 };
-// a sink for up to `cap` columns: region size and records of its buffer
-inline uint64_t sink_seg(uint64_t cap) { return (cap + kSinkBuckets - 1) / kSinkBuckets; }
+// a sink for up to `cap` columns: region size (a quarter above the mean
+// load, so that regions seldom spill) and records of its buffer
+inline uint64_t sink_seg(uint64_t cap) { return (cap + cap / 4) / kSinkBuckets + 64; }
 inline uint64_t sink_records(uint64_t cap) { return sink_seg(cap) * kSinkBuckets + cap; }
 
 // Per-cloud description for the batched kernels.
@@ -119,7 +120,7 @@ hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, Cl
 // Rank-matrix variant of the same: Wr holds n rows of lds_stride(n) 16-bit
 // weight ranks (0xFFFF above tau_eff, on the diagonal and in the padding
 // past column n-1), n <= kLdsMaxN; rank_bits maps a rank to its weight.
-// chunk is a multiple of kLdsBlock.
+// chunk (suffixes per work unit, one wave each) is a positive multiple of 64.
 hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
                                     uint64_t units, unsigned max_groups,
