@@ -654,12 +654,55 @@ __device__ __forceinline__ uint64_t wave_append(bool take, unsigned long long* c
   return base + (uint64_t)__popcll(below);
 }
 
-// Wave-aggregated append of Column records into a ColumnSink, in two
-// steps: reserve() takes the slots of the lanes with `take` in the wave's
-// region (one atomic per wave) and keeps the records; flush() writes them
-// once the atomic's result is back, the wave having done other work in
-// between. Slots past the region's end go to the overflow region (a second
-// atomic, only then). All lanes of the wave call both together.
+// Place the records of one wave-aggregated reservation into a RecordSink:
+// the wave holds slots b .. b+cnt-1 of region r (b from the region counter;
+// this lane's slot is b + below). Slots past the region's end go to the
+// overflow region, for which one more atomic is taken only then. All lanes
+// of the wave call it together; b, cnt and leader are uniform.
+template <class T>
+__device__ __forceinline__ void sink_place(const RecordSink<T>& k, int r, uint64_t b,
+                                           uint32_t cnt, uint32_t below, int leader, bool take,
+                                           const T& rec) {
+  const uint64_t slot = b + below;
+  T* const region = k.recs + (uint64_t)r * k.seg;
+  if (b + cnt <= k.seg) {  // uniform
+    if (take) region[slot] = rec;
+    return;
+  }
+  const uint64_t first = b > k.seg ? b : k.seg;  // first slot past the region
+  unsigned long long ob = 0;
+  if ((int)(threadIdx.x & 63) == leader)
+    ob = atomicAdd(k.ctr + (size_t)kSinkBuckets * kSinkStride, (unsigned long long)(b + cnt - first));
+  ob = shfl_u64(ob, leader);
+  if (take) {
+    if (slot < k.seg)
+      region[slot] = rec;
+    else if (ob + (slot - first) < k.ovf_cap)
+      k.recs[(uint64_t)kSinkBuckets * k.seg + ob + (slot - first)] = rec;
+  }
+}
+
+// Wave-aggregated append into region r of a RecordSink, at once: one atomic
+// per wave on the region's counter, then the writes.
+template <class T>
+__device__ __forceinline__ void sink_append(const RecordSink<T>& k, int r, bool take,
+                                            const T& rec) {
+  const unsigned long long mask = __ballot(take);
+  if (!mask) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  const uint32_t cnt = (uint32_t)__popcll(mask);
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(k.ctr + (size_t)r * kSinkStride, (unsigned long long)cnt);
+  base = shfl_u64(base, leader);
+  const uint32_t below = (uint32_t)__popcll(lane ? (mask & ((~0ull) >> (64 - lane))) : 0ull);
+  sink_place(k, r, base, cnt, below, leader, take, rec);
+}
+
+// The same in two steps, for Column records: reserve() takes the slots of
+// the lanes with `take` (one atomic per wave) and keeps the records; flush()
+// writes them once the atomic's result is back, the wave having done other
+// work in between. All lanes of the wave call both together.
 struct DeferredAppend {
   bool any = false;   // the last reserve() had a taking lane (uniform)
   bool take = false;
@@ -683,28 +726,10 @@ struct DeferredAppend {
     rec.cloud = 0;
     rec.cidx = cidx;
   }
-  // region r of the sink
   __device__ __forceinline__ void flush(const ColumnSink& k, int r) {
     if (!any) return;
     any = false;
-    const uint64_t b = shfl_u64(base, leader);
-    const uint64_t slot = b + below;
-    Column* const region = k.cols + (uint64_t)r * k.seg;
-    if (b + cnt <= k.seg) {  // uniform
-      if (take) region[slot] = rec;
-      return;
-    }
-    const uint64_t first = b > k.seg ? b : k.seg;  // first slot past the region
-    unsigned long long ob = 0;
-    if ((int)(threadIdx.x & 63) == leader)
-      ob = atomicAdd(k.ctr + (size_t)kSinkBuckets * kSinkStride, (unsigned long long)(b + cnt - first));
-    ob = shfl_u64(ob, leader);
-    if (take) {
-      if (slot < k.seg)
-        region[slot] = rec;
-      else if (ob + (slot - first) < k.ovf_cap)
-        k.cols[(uint64_t)kSinkBuckets * k.seg + ob + (slot - first)] = rec;
-    }
+    sink_place(k, r, shfl_u64(base, leader), cnt, below, leader, take, rec);
   }
 };
 
@@ -749,14 +774,14 @@ template <int D, int BS, int UL, class Rows>
 __device__ __forceinline__ void enum_units(
     const Rows& rows, int n, const uint64_t* __restrict__ binom, int chunk,
     const uint64_t* __restrict__ unit_cum, uint64_t units, const uint32_t* __restrict__ clear_in,
-    uint32_t* __restrict__ clear_out, const ColumnSink& sink, ApparentPair* __restrict__ ap,
-    uint64_t ap_cap, Scalars* __restrict__ sc) {
+    uint32_t* __restrict__ clear_out, const ColumnSink& sink, const PairSink& aps,
+    Scalars* __restrict__ sc) {
   constexpr uint32_t kInfW = Rows::kInfV;
   const int np1 = n + 1;
   auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
   unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0;
   DeferredAppend pend;
-  const bool need_t = clear_out != nullptr || ap != nullptr;
+  const bool need_t = clear_out != nullptr || aps.recs != nullptr;
   const int bucket = (int)((blockIdx.x * (BS / 64) +
                             (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))) %
                            kSinkBuckets);
@@ -904,16 +929,13 @@ __device__ __forceinline__ void enum_units(
     if (nonapp) key_hi = ~rows.bits(diam);
     pend.reserve(nonapp, bucket_ctr, key_hi, c);
     bool any;
-    if (ap) {
-      const uint64_t as = wave_append(is_app, &sc->apparent_written, any);
-      if (is_app && as < ap_cap) {
-        ApparentPair p;
-        p.s = c;
-        p.t = tcidx;
-        p.diam = rows.bits(diam);
-        p.cloud = 0;
-        ap[as] = p;
-      }
+    if (aps.recs) {
+      ApparentPair p;
+      p.s = c;
+      p.t = tcidx;
+      p.diam = is_app ? rows.bits(diam) : 0u;
+      p.cloud = 0;
+      sink_append(aps, bucket, is_app, p);
     }
   }
   // a unit's counts fit 32 bits: at most chunk / BS candidates per lane,
@@ -935,11 +957,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D <= 3 ?
 void enum_apparent_kernel(
     const uint32_t* __restrict__ W, int n, const uint64_t* __restrict__ binom, int chunk,
     const uint64_t* __restrict__ unit_cum, uint64_t units, const uint32_t* __restrict__ clear_in,
-    uint32_t* __restrict__ clear_out, ColumnSink sink, ApparentPair* __restrict__ ap,
-    uint64_t ap_cap, Scalars* __restrict__ sc) {
+    uint32_t* __restrict__ clear_out, ColumnSink sink, PairSink aps, Scalars* __restrict__ sc) {
   const BufferRows rows(W, n);
   enum_units<D, kBlock, kBlock>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out,
-                                sink, ap, ap_cap, sc);
+                                sink, aps, sc);
 }
 
 // The same with the rank matrix (n <= kLdsMaxN, 16-bit ranks, n rows of
@@ -954,7 +975,7 @@ void enum_apparent_lds_kernel(
     const uint16_t* __restrict__ Wr, const uint32_t* __restrict__ rank_bits, int n,
     const uint64_t* __restrict__ binom, int chunk, const uint64_t* __restrict__ unit_cum,
     uint64_t units, const uint32_t* __restrict__ clear_in, uint32_t* __restrict__ clear_out,
-    ColumnSink sink, ApparentPair* __restrict__ ap, uint64_t ap_cap, Scalars* __restrict__ sc) {
+    ColumnSink sink, PairSink aps, Scalars* __restrict__ sc) {
   __shared__ uint4 sw[kLdsMaxN * kLdsMaxN / 8];
   const int stride = lds_stride(n);
   const int words = n * stride / 8;  // 16-byte words; stride is a multiple of 8
@@ -963,16 +984,16 @@ void enum_apparent_lds_kernel(
   __syncthreads();
   const LdsRows rows{reinterpret_cast<const uint16_t*>(sw), n, stride, rank_bits};
   enum_units<D, kLdsBlock, 64>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out,
-                               sink, ap, ap_cap, sc);
+                               sink, aps, sc);
 }
 
 template <int D>
 static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom, int chunk,
                                 const uint64_t* unit_cum, uint64_t units, unsigned grid,
                                 const uint32_t* clear_in, uint32_t* clear_out, ColumnSink sink,
-                                ApparentPair* ap, uint64_t ap_cap, Scalars* sc, hipStream_t s) {
+                                PairSink aps, Scalars* sc, hipStream_t s) {
   enum_apparent_kernel<D><<<grid, kBlock, 0, s>>>(W, n, binom, chunk, unit_cum, units, clear_in,
-                                                  clear_out, sink, ap, ap_cap, sc);
+                                                  clear_out, sink, aps, sc);
   return hipGetLastError();
 }
 
@@ -980,11 +1001,11 @@ template <int D>
 static hipError_t launch_enum_lds_D(const uint16_t* Wr, const uint32_t* rank_bits, int n,
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
                                     uint64_t units, unsigned grid, const uint32_t* clear_in,
-                                    uint32_t* clear_out, ColumnSink sink, ApparentPair* ap,
-                                    uint64_t ap_cap, Scalars* sc, hipStream_t s) {
+                                    uint32_t* clear_out, ColumnSink sink, PairSink aps,
+                                    Scalars* sc, hipStream_t s) {
   enum_apparent_lds_kernel<D><<<grid, kLdsBlock, 0, s>>>(Wr, rank_bits, n, binom, chunk, unit_cum,
-                                                         units, clear_in, clear_out, sink, ap,
-                                                         ap_cap, sc);
+                                                         units, clear_in, clear_out, sink, aps,
+                                                         sc);
   return hipGetLastError();
 }
 
@@ -992,8 +1013,7 @@ hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* r
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
                                     uint64_t units, unsigned max_groups,
                                     const uint32_t* clear_in, uint32_t* clear_out,
-                                    ColumnSink sink, ApparentPair* ap, uint64_t ap_cap,
-                                    Scalars* sc, hipStream_t s) {
+                                    ColumnSink sink, PairSink aps, Scalars* sc, hipStream_t s) {
   if (units == 0) return hipSuccess;
   if (n < 1 || n > kLdsMaxN || chunk < 64 || chunk % 64 || max_groups == 0)
     return hipErrorInvalidValue;
@@ -1002,11 +1022,11 @@ hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* r
   if (g > (uint64_t)kMaxGroups) g = kMaxGroups;
   const unsigned grid = (unsigned)g;
   switch (d) {
-    case 2: return launch_enum_lds_D<2>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
-    case 3: return launch_enum_lds_D<3>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
-    case 4: return launch_enum_lds_D<4>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
-    case 5: return launch_enum_lds_D<5>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
-    case 6: return launch_enum_lds_D<6>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
+    case 2: return launch_enum_lds_D<2>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 3: return launch_enum_lds_D<3>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 4: return launch_enum_lds_D<4>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 5: return launch_enum_lds_D<5>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 6: return launch_enum_lds_D<6>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1014,7 +1034,7 @@ hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* r
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,
                                 const uint64_t* unit_cum, uint64_t units, unsigned max_groups,
                                 const uint32_t* clear_in, uint32_t* clear_out, ColumnSink sink,
-                                ApparentPair* ap, uint64_t ap_cap, Scalars* sc, hipStream_t s) {
+                                PairSink aps, Scalars* sc, hipStream_t s) {
   if (units == 0) return hipSuccess;
   if (chunk < 64 || chunk % 64 || max_groups == 0) return hipErrorInvalidValue;
   // at most kMaxGroups workgroups: the dispatch counts work-items in 32 bits;
@@ -1025,25 +1045,26 @@ hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t*
   if (g > (uint64_t)kMaxGroups) g = kMaxGroups;
   const unsigned grid = (unsigned)g;
   switch (d) {
-    case 2: return launch_enum_D<2>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
-    case 3: return launch_enum_D<3>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
-    case 4: return launch_enum_D<4>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
-    case 5: return launch_enum_D<5>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
-    case 6: return launch_enum_D<6>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, ap, ap_cap, sc, s);
+    case 2: return launch_enum_D<2>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 3: return launch_enum_D<3>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 4: return launch_enum_D<4>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 5: return launch_enum_D<5>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 6: return launch_enum_D<6>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Packing of a ColumnSink: workgroup r < kSinkBuckets copies region r, the
+// Packing of a RecordSink: workgroup r < kSinkBuckets copies region r, the
 // last one the overflow region; each adds up the kept counts of the regions
 // before its own for its offset.
 // ---------------------------------------------------------------------------
 
 constexpr int kGatherThreads = 256;
 
-__global__ __launch_bounds__(kGatherThreads) void gather_columns_kernel(
-    ColumnSink k, Column* __restrict__ out, uint64_t out_cap, Scalars* __restrict__ sc) {
+template <class T>
+__global__ __launch_bounds__(kGatherThreads) void gather_kernel(
+    RecordSink<T> k, T* __restrict__ out, uint64_t out_cap, unsigned long long* __restrict__ total) {
   __shared__ unsigned long long part[kGatherThreads / 64];
   const int r = blockIdx.x;
   unsigned long long off = 0;
@@ -1059,15 +1080,22 @@ __global__ __launch_bounds__(kGatherThreads) void gather_columns_kernel(
   const unsigned long long have = k.ctr[(size_t)r * kSinkStride];
   const uint64_t lim = r < kSinkBuckets ? k.seg : k.ovf_cap;
   const uint64_t count = have < lim ? have : lim;
-  const Column* __restrict__ src = k.cols + (uint64_t)r * k.seg;
+  const T* __restrict__ src = k.recs + (uint64_t)r * k.seg;
   for (uint64_t i = threadIdx.x; i < count && off + i < out_cap; i += kGatherThreads)
     out[off + i] = src[i];
-  if (r == kSinkBuckets && threadIdx.x == 0) sc->nonapparent = off + have;
+  if (r == kSinkBuckets && threadIdx.x == 0) *total = off + have;
 }
 
-hipError_t launch_gather_columns(ColumnSink sink, Column* out, uint64_t out_cap, Scalars* sc,
-                                 hipStream_t s) {
-  gather_columns_kernel<<<kSinkBuckets + 1, kGatherThreads, 0, s>>>(sink, out, out_cap, sc);
+hipError_t launch_gather_columns(ColumnSink sink, Column* out, uint64_t out_cap,
+                                 unsigned long long* total, hipStream_t s) {
+  gather_kernel<Column><<<kSinkBuckets + 1, kGatherThreads, 0, s>>>(sink, out, out_cap, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_pairs(PairSink sink, ApparentPair* out, uint64_t out_cap,
+                               unsigned long long* total, hipStream_t s) {
+  gather_kernel<ApparentPair><<<kSinkBuckets + 1, kGatherThreads, 0, s>>>(sink, out, out_cap,
+                                                                          total);
   return hipGetLastError();
 }
 

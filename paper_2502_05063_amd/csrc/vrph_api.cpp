@@ -187,7 +187,9 @@ struct vrph_ctx {
   DevBuf D, W, binom, bitmaps, cols, cols_tmp, sort_work, ap, scal, clouds, cstate, h0, deaths;
   DevBuf wr16, rank_bits;  // 16-bit rank matrix and rank -> weight table (LDS kernels)
   DevBuf sink_ctr;         // region counters of the d >= 2 column sink
+  DevBuf ap_ctr, ap_tmp;   // region counters and packed output of the pair sink
   uint64_t col_cap = 0;    // non-apparent columns the buffers are sized for
+  uint64_t pair_cap = 0;   // apparent pairs the buffers are sized for
   HostPinned h_scal, h_cstate;
   std::vector<uint64_t> h_binom;
   int binom_n = -1, binom_k = -1;
@@ -283,7 +285,7 @@ extern "C" void vrph_destroy(vrph_ctx* c) {
   DevBuf* bufs[] = {&c->D,      &c->W,     &c->binom,  &c->bitmaps, &c->cols,
                     &c->cols_tmp, &c->sort_work, &c->ap, &c->scal,  &c->clouds,
                     &c->cstate,  &c->h0,    &c->deaths, &c->units,   &c->wr16,
-                    &c->rank_bits, &c->sink_ctr};
+                    &c->rank_bits, &c->sink_ctr, &c->ap_ctr, &c->ap_tmp};
   for (DevBuf* b : bufs) b->release();
   c->h_scal.release();
   c->h_cstate.release();
@@ -512,14 +514,25 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     };
     uint64_t ap_cap = 0;
     if (keep_zero) {
-      ap_cap = c->ap.cap / sizeof(ApparentPair);
+      ap_cap = c->pair_cap;
       if (ap_cap < 4096) ap_cap = std::min<uint64_t>(ncand, 1 << 24) + 1;
     }
+    // d >= 2: the pairs go to a sink in `ap`, packed into `ap_tmp`; d = 1
+    // appends them to `ap` directly
+    auto ensure_pairs = [&]() -> hipError_t {
+      if (!keep_zero) return hipSuccess;
+      hipError_t e = c->ap.ensure((d >= 2 ? sink_records(ap_cap) : std::max<uint64_t>(ap_cap, 1)) *
+                                  sizeof(ApparentPair));
+      if (e == hipSuccess && d >= 2) e = c->ap_tmp.ensure(ap_cap * sizeof(ApparentPair));
+      if (e == hipSuccess && d >= 2)
+        e = c->ap_ctr.ensure(kSinkCounters * sizeof(unsigned long long));
+      return e;
+    };
     Scalars sc;
     Scalars* dsc = c->scal.as<Scalars>();
     HIP_TRY(ensure_cols());
     HIP_TRY(c->sink_ctr.ensure(kSinkCounters * sizeof(unsigned long long)));
-    if (keep_zero) HIP_TRY(c->ap.ensure(std::max<uint64_t>(ap_cap, 1) * sizeof(ApparentPair)));
+    HIP_TRY(ensure_pairs());
     // the launch of dimension d with setting t (suffixes per work unit for
     // d >= 2, workgroups per compute unit); `launched` = the workgroups.
     // Events ev0 / ev2 bracket the kernel alone on the stream.
@@ -549,20 +562,27 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       HIP_TRY_E(hipMemsetAsync(c->sink_ctr.p, 0, kSinkCounters * sizeof(unsigned long long), s));
       const ColumnSink sink{c->cols.as<Column>(), c->sink_ctr.as<unsigned long long>(),
                             sink_seg(cap), cap};
+      PairSink aps{nullptr, nullptr, 0, 0};
+      if (keep_zero) {
+        HIP_TRY_E(hipMemsetAsync(c->ap_ctr.p, 0, kSinkCounters * sizeof(unsigned long long), s));
+        aps = PairSink{c->ap.as<ApparentPair>(), c->ap_ctr.as<unsigned long long>(),
+                       sink_seg(ap_cap), ap_cap};
+      }
       HIP_TRY_E(hipEventRecord(c->ev0, s));
       if (use_lds)
         HIP_TRY_E(launch_enum_apparent_lds(
             d, c->wr16.as<uint16_t>(), c->rank_bits.as<uint32_t>(), n, c->binom.as<uint64_t>(),
-            t.chunk, c->units.as<uint64_t>(), units, max_groups, clear_in, clear_out, sink,
-            keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap, dsc, s));
+            t.chunk, c->units.as<uint64_t>(), units, max_groups, clear_in, clear_out, sink, aps,
+            dsc, s));
       else
         HIP_TRY_E(launch_enum_apparent(d, c->W.as<uint32_t>(), n, c->binom.as<uint64_t>(),
                                        t.chunk, c->units.as<uint64_t>(), units, max_groups,
-                                       clear_in, clear_out, sink,
-                                       keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
-                                       dsc, s));
+                                       clear_in, clear_out, sink, aps, dsc, s));
       HIP_TRY_E(hipEventRecord(c->ev2, s));
-      HIP_TRY_E(launch_gather_columns(sink, c->cols_tmp.as<Column>(), cap, dsc, s));
+      HIP_TRY_E(launch_gather_columns(sink, c->cols_tmp.as<Column>(), cap, &dsc->nonapparent, s));
+      if (keep_zero)
+        HIP_TRY_E(launch_gather_pairs(aps, c->ap_tmp.as<ApparentPair>(), ap_cap,
+                                      &dsc->apparent_written, s));
       // the host table is consumed by the copy before the next launch reuses it
       return hipStreamSynchronize(s);
     };
@@ -595,7 +615,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       if (sc.nonapparent > cap) cap = sc.nonapparent + 1024;
       if (keep_zero && sc.apparent_written > ap_cap) ap_cap = sc.apparent_written + 1024;
       HIP_TRY(ensure_cols());
-      if (keep_zero) HIP_TRY(c->ap.ensure(std::max<uint64_t>(ap_cap, 1) * sizeof(ApparentPair)));
+      HIP_TRY(ensure_pairs());
       float best = -1;
       auto trial = [&](const Tune& t) -> hipError_t {
         HIP_TRY_E(hipMemsetAsync(c->scal.p, 0, sizeof(Scalars), s));
@@ -626,7 +646,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     }
     for (int attempt = 0; attempt < 2; ++attempt) {
       HIP_TRY(ensure_cols());
-      if (keep_zero) HIP_TRY(c->ap.ensure(std::max<uint64_t>(ap_cap, 1) * sizeof(ApparentPair)));
+      HIP_TRY(ensure_pairs());
       HIP_TRY(hipMemsetAsync(c->scal.p, 0, sizeof(Scalars), s));
       HIP_TRY(launch_dim(param));
       bc->stats.grid[d] = (int32_t)std::min<uint64_t>(launched, 0x7FFFFFFF);
@@ -640,6 +660,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     if (sc.nonapparent > cap || (keep_zero && sc.apparent_written > ap_cap))
       return fail(VRPH_EDEVICE, "column counts changed between two runs of one dimension");
     c->col_cap = std::max(c->col_cap, cap);
+    if (keep_zero) c->pair_cap = std::max(c->pair_cap, ap_cap);
     const int64_t nna = (int64_t)sc.nonapparent;
     Column* const packed = d >= 2 ? c->cols_tmp.as<Column>() : c->cols.as<Column>();
     Column* const spare = d >= 2 ? c->cols.as<Column>() : c->cols_tmp.as<Column>();
@@ -651,7 +672,8 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     if (keep_zero) {
       hap.resize(sc.apparent_written);
       if (sc.apparent_written)
-        HIP_TRY(hipMemcpyAsync(hap.data(), c->ap.p, sc.apparent_written * sizeof(ApparentPair),
+        HIP_TRY(hipMemcpyAsync(hap.data(), d >= 2 ? c->ap_tmp.p : c->ap.p,
+                               sc.apparent_written * sizeof(ApparentPair),
                                hipMemcpyDeviceToHost, s));
     }
     HIP_TRY(hipStreamSynchronize(s));

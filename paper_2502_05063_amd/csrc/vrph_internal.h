@@ -70,23 +70,27 @@ struct Scalars {
   unsigned long long facet_steps;  // facets of t whose diameter Condition 2 computed
 };
 
-// Where the enumeration kernels (d >= 2) put their non-apparent columns.
-// Every wave appends to one of kSinkBuckets regions of `seg` records, each
-// with its own counter (counters 128 bytes apart): one shared counter would
-// serialise the appends of the whole device on one address. A region that
-// fills up spills into the overflow region (ovf_cap records, its counter
-// after the region counters). gather_columns then packs everything into one
-// array and stores the total in Scalars::nonapparent.
+// Where the enumeration kernels (d >= 2) put their records (non-apparent
+// columns; apparent pairs when every pair is requested). Every wave appends
+// to one of kSinkBuckets regions of `seg` records, each with its own counter
+// (counters 128 bytes apart): one shared counter would serialise the appends
+// of the whole device on one address. A region that fills up spills into
+// the overflow region (ovf_cap records, its counter after the region
+// counters). A gather kernel then packs everything into one array and
+// stores the total.
 constexpr int kSinkBuckets = 256;
 constexpr int kSinkStride = 16;  // 64-bit counters per 128 bytes
 constexpr size_t kSinkCounters = (size_t)(kSinkBuckets + 1) * kSinkStride;
-struct ColumnSink {
-  Column* cols;               // kSinkBuckets * seg region records, then ovf_cap
+template <class T>
+struct RecordSink {
+  T* recs;                    // kSinkBuckets * seg region records, then ovf_cap
   unsigned long long* ctr;    // kSinkCounters entries, zeroed before a launch
   uint64_t seg;
   uint64_t ovf_cap;
 };
-// a sink for up to `cap` columns: region size (a quarter above the mean
+using ColumnSink = RecordSink<Column>;
+using PairSink = RecordSink<ApparentPair>;
+// a sink for up to `cap` records: region size (a quarter above the mean
 // load, so that regions seldom spill) and records of its buffer
 inline uint64_t sink_seg(uint64_t cap) { return (cap + cap / 4) / kSinkBuckets + 64; }
 inline uint64_t sink_records(uint64_t cap) { return sink_seg(cap) * kSinkBuckets + cap; }
@@ -125,18 +129,19 @@ hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* r
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
                                     uint64_t units, unsigned max_groups,
                                     const uint32_t* clear_in, uint32_t* clear_out,
-                                    ColumnSink sink, ApparentPair* ap, uint64_t ap_cap,
-                                    Scalars* sc, hipStream_t s);
+                                    ColumnSink sink, PairSink aps, Scalars* sc, hipStream_t s);
 // d >= 2; unit_cum (n+1 entries, device) and units from enum_units() on the
 // host; at most max_groups workgroups, which stride over the units
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,
                                 const uint64_t* unit_cum, uint64_t units, unsigned max_groups,
                                 const uint32_t* clear_in, uint32_t* clear_out, ColumnSink sink,
-                                ApparentPair* ap, uint64_t ap_cap, Scalars* sc, hipStream_t s);
-// Packs a sink's columns into out (at most out_cap of them) and stores their
-// total count in sc->nonapparent (more than out_cap: some were not kept).
-hipError_t launch_gather_columns(ColumnSink sink, Column* out, uint64_t out_cap, Scalars* sc,
-                                 hipStream_t s);
+                                PairSink aps, Scalars* sc, hipStream_t s);
+// Pack a sink's records into out (at most out_cap of them) and store their
+// total count in *total (more than out_cap: some were not kept).
+hipError_t launch_gather_columns(ColumnSink sink, Column* out, uint64_t out_cap,
+                                 unsigned long long* total, hipStream_t s);
+hipError_t launch_gather_pairs(PairSink sink, ApparentPair* out, uint64_t out_cap,
+                               unsigned long long* total, hipStream_t s);
 hipError_t launch_batch_edges(const uint32_t* W, const Cloud* clouds, int count,
                               int64_t total_edges, const uint32_t* bitmaps, Column* cols,
                               uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
