@@ -156,6 +156,22 @@ vrph_status vrph_barcode_from_points(vrph_ctx* ctx, const float* X, int64_t n, i
                                      int32_t max_dim, float threshold, uint32_t flags,
                                      void* hip_stream, vrph_barcode** out);
 
+/* Same from a sparse distance matrix (the paper's sparse input, Sec. 5.6.6
+ * and the o3 experiment of Table 5.2): nnz entries (row[k], col[k], val[k]),
+ * each an unordered pair of distinct points 0 <= row, col < n given once, in
+ * either orientation, with val finite and >= 0. Pairs that are not given are
+ * not edges (an infinite distance): no simplex containing them is in the
+ * filtration. row, col (int32) and val (float32) are DEVICE arrays of nnz
+ * entries. The enclosing radius (unless VRPH_NO_ENCLOSING_RADIUS) is
+ * min_i max_j D_ij with the missing entries infinite, i.e. it only cuts
+ * where some point has all its n-1 distances given. VRPH_EINVAL for an
+ * index out of range, a diagonal entry, a repeated pair, or a value that is
+ * negative or not finite. 1 <= n <= 2048, 0 <= nnz <= n(n-1)/2. */
+vrph_status vrph_barcode_from_sparse(vrph_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row,
+                                     const int32_t* col, const float* val, int32_t max_dim,
+                                     float threshold, uint32_t flags, void* hip_stream,
+                                     vrph_barcode** out);
+
 /* Pairs of dimension dim (dim = -1: all dimensions), canonical order: by
  * dimension, then birth index, then death index. Without
  * VRPH_KEEP_ZERO_PERSISTENCE, pairs with birth_diam == death_diam are left

@@ -143,7 +143,8 @@ hipError_t launch_batch_pdist(const float* X, int m, const Cloud* clouds, int co
 __global__ __launch_bounds__(kBlock) void batch_validate_kernel(const float* __restrict__ D,
                                                                 const Cloud* __restrict__ clouds,
                                                                 int count,
-                                                                CloudState* __restrict__ st) {
+                                                                CloudState* __restrict__ st,
+                                                                int allow_inf) {
   __shared__ uint32_t red[kBlock / 64];
   __shared__ uint32_t errs;
   const int64_t row = blockIdx.x;
@@ -156,12 +157,14 @@ __global__ __launch_bounds__(kBlock) void batch_validate_kernel(const float* __r
   uint32_t mx = 0, err = 0;
   for (int j = threadIdx.x; j < cl.n; j += blockDim.x) {
     float x = Drow[j];
-    if (!isfinite(x)) err |= 1u;
+    // a sparse matrix holds +inf where a pair is not an edge; it then also
+    // takes part in the row maximum of the enclosing radius
+    if (!isfinite(x) && !(allow_inf && x == INFINITY)) err |= 1u;
     if (x < 0.0f) err |= 2u;
     if (x != D[cl.w_off + (int64_t)j * cl.n + i]) err |= 4u;
     if (j == i && x != 0.0f) err |= 8u;
     uint32_t k = float_key(x);
-    if (isfinite(x) && x >= 0.0f && k > mx) mx = k;
+    if (!isnan(x) && x >= 0.0f && k > mx) mx = k;
   }
   for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
@@ -192,18 +195,77 @@ __global__ __launch_bounds__(kBlock) void batch_weights_kernel(const float* __re
   uint32_t* Wrow = W + cl.w_off + (int64_t)i * cl.n;
   for (int j = threadIdx.x; j < cl.n; j += blockDim.x) {
     uint32_t k = float_key(Drow[j]);
-    Wrow[j] = (j != i && k <= tau) ? k : kInf;
+    // +inf (a pair that is not an edge of a sparse matrix) is never an edge
+    Wrow[j] = (j != i && k <= tau && k < 0x7F800000u) ? k : kInf;
   }
 }
 
 hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, int count,
                                          int64_t total_points, bool enclosing, uint32_t* W,
-                                         CloudState* st, hipStream_t s) {
+                                         CloudState* st, hipStream_t s, bool allow_inf) {
   if (total_points <= 0) return hipSuccess;
   if (total_points > kMaxGroups) return hipErrorInvalidValue;
-  batch_validate_kernel<<<(unsigned)total_points, kBlock, 0, s>>>(D, clouds, count, st);
+  batch_validate_kernel<<<(unsigned)total_points, kBlock, 0, s>>>(D, clouds, count, st,
+                                                                  allow_inf ? 1 : 0);
   batch_weights_kernel<<<(unsigned)total_points, kBlock, 0, s>>>(D, clouds, count,
                                                                  enclosing ? 1 : 0, W, st);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sparse input: the n x n matrix with +inf where a pair is not given and 0 on
+// the diagonal, then the given entries in both orientations. A repeated pair
+// finds a finite value already in one of its two cells (both writes are
+// exchanges, so of two writers to a cell the second sees the first). Errors
+// go to st->err: bit 0 a value that is not finite, bit 1 a negative value,
+// bit 4 an index out of range or on the diagonal, bit 5 a repeated pair.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void sparse_init_kernel(float* __restrict__ D, int n) {
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nn;
+       q += (int64_t)gridDim.x * kBlock)
+    D[q] = (q / n == q % n) ? 0.0f : INFINITY;
+}
+
+__global__ __launch_bounds__(kBlock) void sparse_fill_kernel(const int32_t* __restrict__ row,
+                                                             const int32_t* __restrict__ col,
+                                                             const float* __restrict__ val,
+                                                             int64_t nnz, int n,
+                                                             float* __restrict__ D,
+                                                             CloudState* __restrict__ st) {
+  const uint32_t inf_bits = 0x7F800000u;
+  uint32_t* const Db = reinterpret_cast<uint32_t*>(D);
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nnz;
+       q += (int64_t)gridDim.x * kBlock) {
+    const int i = row[q], j = col[q];
+    const float v = val[q];
+    uint32_t err = 0;
+    if (i < 0 || i >= n || j < 0 || j >= n || i == j) err |= 16u;
+    if (!isfinite(v)) err |= 1u;
+    if (v < 0.0f) err |= 2u;
+    if (!err) {
+      const uint32_t b = __float_as_uint(v == 0.0f ? 0.0f : v);  // -0 stored as +0
+      const uint32_t p1 = atomicExch(&Db[(int64_t)i * n + j], b);
+      const uint32_t p2 = atomicExch(&Db[(int64_t)j * n + i], b);
+      if (p1 != inf_bits || p2 != inf_bits) err |= 32u;
+    }
+    if (err) atomicOr(&st->err, err);
+  }
+}
+
+hipError_t launch_sparse_matrix(const int32_t* row, const int32_t* col, const float* val,
+                                int64_t nnz, int n, float* D, CloudState* st, hipStream_t s) {
+  if (n < 1) return hipErrorInvalidValue;
+  const int64_t nn = (int64_t)n * n;
+  const int64_t bi = (nn + kBlock - 1) / kBlock;
+  const unsigned gi = (unsigned)(bi < 4096 ? bi : 4096);
+  sparse_init_kernel<<<gi, kBlock, 0, s>>>(D, n);
+  if (nnz > 0) {
+    const int64_t bf = (nnz + kBlock - 1) / kBlock;
+    const unsigned gf = (unsigned)(bf < 4096 ? bf : 4096);
+    sparse_fill_kernel<<<gf, kBlock, 0, s>>>(row, col, val, nnz, n, D, st);
+  }
   return hipGetLastError();
 }
 

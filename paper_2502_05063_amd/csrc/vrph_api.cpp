@@ -360,23 +360,73 @@ extern "C" vrph_status vrph_pdist(vrph_ctx* c, const float* X, int64_t n, int32_
 // the single-cloud pipeline
 // ---------------------------------------------------------------------------
 
-static void finish_pairs(vrph_barcode* bc, const HostComplex& H, int max_dim, bool keep_zero) {
+// Run f(begin, end) over [0, count) split into contiguous ranges on up to
+// `threads` host threads (one when the range is small).
+template <class F>
+static void parallel_ranges(size_t count, int threads, F f) {
+  const size_t min_per = 1 << 16;
+  size_t t = std::min<size_t>((size_t)std::max(threads, 1), (count + min_per - 1) / min_per);
+  if (t <= 1) {
+    f((size_t)0, count);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (size_t i = 0; i < t; ++i)
+    pool.emplace_back([&, i]() { f(count * i / t, count * (i + 1) / t); });
+  for (std::thread& th : pool) th.join();
+}
+
+// std::sort of [first, last) on up to `threads` threads: sorted blocks,
+// then rounds of pairwise merges.
+template <class It, class Cmp>
+static void parallel_sort(It first, It last, Cmp cmp, int threads) {
+  const size_t n = (size_t)(last - first);
+  size_t blocks = std::min<size_t>((size_t)std::max(threads, 1), n / (1 << 16));
+  if (blocks <= 1) {
+    std::sort(first, last, cmp);
+    return;
+  }
+  std::vector<size_t> cut(blocks + 1);
+  for (size_t i = 0; i <= blocks; ++i) cut[i] = n * i / blocks;
+  {
+    std::vector<std::thread> pool;
+    for (size_t i = 0; i < blocks; ++i)
+      pool.emplace_back([&, i]() { std::sort(first + cut[i], first + cut[i + 1], cmp); });
+    for (std::thread& th : pool) th.join();
+  }
+  for (size_t width = 1; width < blocks; width *= 2) {
+    std::vector<std::thread> pool;
+    for (size_t i = 0; i + width < blocks; i += 2 * width) {
+      const size_t lo = cut[i], mid = cut[i + width], hi = cut[std::min(i + 2 * width, blocks)];
+      pool.emplace_back([=]() { std::inplace_merge(first + lo, first + mid, first + hi, cmp); });
+    }
+    for (std::thread& th : pool) th.join();
+  }
+}
+
+// threads: host threads for the edge lookups and the sort (1 where the
+// caller already runs one cloud per thread)
+static void finish_pairs(vrph_barcode* bc, const HostComplex& H, int max_dim, bool keep_zero,
+                         int threads) {
   std::vector<vrph_pair>& P = bc->pairs;
   if (!keep_zero)
     P.erase(std::remove_if(P.begin(), P.end(),
                            [](const vrph_pair& p) { return !p.essential && p.birth_diam == p.death_diam; }),
             P.end());
-  for (vrph_pair& p : P) {
-    p.birth_edge[0] = p.birth_edge[1] = -1;
-    p.death_edge[0] = p.death_edge[1] = -1;
-    if (p.dim >= 1) diameter_edge(H, p.birth, p.dim, &p.birth_edge[0], &p.birth_edge[1]);
-    if (!p.essential) diameter_edge(H, p.death, p.dim + 1, &p.death_edge[0], &p.death_edge[1]);
-  }
-  std::sort(P.begin(), P.end(), [](const vrph_pair& a, const vrph_pair& b) {
+  parallel_ranges(P.size(), threads, [&](size_t b, size_t e) {
+    for (size_t i = b; i < e; ++i) {
+      vrph_pair& p = P[i];
+      p.birth_edge[0] = p.birth_edge[1] = -1;
+      p.death_edge[0] = p.death_edge[1] = -1;
+      if (p.dim >= 1) diameter_edge(H, p.birth, p.dim, &p.birth_edge[0], &p.birth_edge[1]);
+      if (!p.essential) diameter_edge(H, p.death, p.dim + 1, &p.death_edge[0], &p.death_edge[1]);
+    }
+  });
+  parallel_sort(P.begin(), P.end(), [](const vrph_pair& a, const vrph_pair& b) {
     if (a.dim != b.dim) return a.dim < b.dim;
     if (a.birth != b.birth) return a.birth < b.birth;
     return a.death < b.death;
-  });
+  }, threads);
   for (int d = 0; d <= VRPH_MAX_DIM + 1; ++d) bc->off[d] = 0;
   for (const vrph_pair& p : P) bc->off[p.dim + 1]++;
   for (int d = 1; d <= VRPH_MAX_DIM + 2; ++d) bc->off[d] += bc->off[d - 1];
@@ -395,8 +445,19 @@ static vrph_pair make_pair(int dim, uint64_t b, uint32_t bd, uint64_t d, uint32_
   return p;
 }
 
+// A sparse distance matrix as given to vrph_barcode_from_sparse (device arrays).
+struct SparseInput {
+  const int32_t* row;
+  const int32_t* col;
+  const float* val;
+  int64_t nnz;
+};
+
+// D: the dense n x n matrix, or, with sp, the context's buffer that the
+// sparse entries are written into first (+inf where a pair is not given).
 static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim, float threshold,
-                                uint32_t flags, hipStream_t s, vrph_barcode** out) {
+                                uint32_t flags, hipStream_t s, vrph_barcode** out,
+                                const SparseInput* sp = nullptr) {
   const double t_start = now_ms();
   const bool keep_zero = flags & VRPH_KEEP_ZERO_PERSISTENCE;
   const int kmax = max_dim + 2;
@@ -430,10 +491,13 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   if (st) return st;
   HIP_TRY(c->W.ensure((size_t)n * n * 4));
   HIP_TRY(c->h0.ensure((size_t)n * sizeof(H0Pair)));
+  if (sp)
+    HIP_TRY(launch_sparse_matrix(sp->row, sp->col, sp->val, sp->nnz, n, const_cast<float*>(D),
+                                 c->cstate.as<CloudState>(), s));
   HIP_TRY(hipEventRecord(c->ev0, s));
   HIP_TRY(launch_batch_validate_weights(D, c->clouds.as<Cloud>(), 1, n,
                                         !(flags & VRPH_NO_ENCLOSING_RADIUS), c->W.as<uint32_t>(),
-                                        c->cstate.as<CloudState>(), s));
+                                        c->cstate.as<CloudState>(), s, sp != nullptr));
   HIP_TRY(launch_batch_h0(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1,
                           c->cstate.as<CloudState>(), c->h0.as<H0Pair>(), n, bm + bm_off[1], s));
   HIP_TRY(hipEventRecord(c->ev1, s));
@@ -449,7 +513,9 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     return fail(VRPH_EINVAL, std::string("invalid distance matrix:") +
                                  ((cs.err & 1) ? " non-finite" : "") + ((cs.err & 2) ? " negative" : "") +
                                  ((cs.err & 4) ? " asymmetric" : "") +
-                                 ((cs.err & 8) ? " nonzero diagonal" : ""));
+                                 ((cs.err & 8) ? " nonzero diagonal" : "") +
+                                 ((cs.err & 16) ? " entry index out of range or on the diagonal" : "") +
+                                 ((cs.err & 32) ? " repeated pair" : ""));
   H.W = hW.data();
   // Weight ranks: needed by the host reduction and, for small clouds, by the
   // LDS enumeration kernels (16-bit ranks: C(kLdsMaxN, 2) < 0xFFFF).
@@ -698,9 +764,16 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     }
     reduce_dimension(H, d, hcols.data(), nna, host_threads(), prs, deaths, rs);
     bc->stats.additions[d] = rs.additions;
+    bc->pairs.reserve(bc->pairs.size() + prs.size() + (keep_zero ? hap.size() : 0));
     for (const PairRec& r : prs) bc->pairs.push_back(make_pair(d, r.birth, r.bdiam, r.death, r.ddiam));
-    if (keep_zero)
-      for (const ApparentPair& a : hap) bc->pairs.push_back(make_pair(d, a.s, a.diam, a.t, a.diam));
+    if (keep_zero) {
+      const size_t base = bc->pairs.size();
+      bc->pairs.resize(base + hap.size());
+      parallel_ranges(hap.size(), host_threads(), [&](size_t b, size_t e) {
+        for (size_t i = b; i < e; ++i)
+          bc->pairs[base + i] = make_pair(d, hap[i].s, hap[i].diam, hap[i].t, hap[i].diam);
+      });
+    }
     bc->stats.pairs[d] = (int64_t)prs.size() + (int64_t)sc.apparent;
     bc->stats.host_ms[d] = now_ms() - h0t;
     if (clear_out && !deaths.empty()) {
@@ -711,7 +784,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       HIP_TRY(hipStreamSynchronize(s));  // `deaths` is reused by the next dimension
     }
   }
-  finish_pairs(bc.get(), H, max_dim, keep_zero);
+  finish_pairs(bc.get(), H, max_dim, keep_zero, host_threads());
   bc->stats.total_ms = now_ms() - t_start;
   *out = bc.release();
   return VRPH_OK;
@@ -756,6 +829,23 @@ extern "C" vrph_status vrph_barcode_from_points(vrph_ctx* c, const float* X, int
   if (st) return st;
   HIP_TRY(launch_batch_pdist(X, m, c->clouds.as<Cloud>(), 1, n, c->D.as<float>(), s));
   return barcode_impl(c, c->D.as<float>(), (int)n, max_dim, threshold, flags, s, out);
+}
+
+extern "C" vrph_status vrph_barcode_from_sparse(vrph_ctx* c, int64_t n, int64_t nnz,
+                                                const int32_t* row, const int32_t* col,
+                                                const float* val, int32_t max_dim,
+                                                float threshold, uint32_t flags,
+                                                void* hip_stream, vrph_barcode** out) {
+  vrph_status st = check_common(c, n, max_dim, threshold, flags, out);
+  if (st) return st;
+  if (nnz < 0 || nnz > n * (n - 1) / 2)
+    return fail(VRPH_EINVAL, "nnz must be in [0, n(n-1)/2]");
+  if (nnz > 0 && (!row || !col || !val)) return fail(VRPH_EINVAL, "row, col or val is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  HIP_TRY(c->D.ensure((size_t)n * n * 4));
+  const SparseInput sp{row, col, val, nnz};
+  return barcode_impl(c, c->D.as<float>(), (int)n, max_dim, threshold, flags, s, out, &sp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1037,7 +1127,7 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
         r.stats.reduced[1] = ce - cb;
         r.stats.additions[1] = rs.additions;
       }
-      finish_pairs(&r, H, b->max_dim, keep_zero);
+      finish_pairs(&r, H, b->max_dim, keep_zero, 1);
     }
   };
   const int nthreads = std::max(1, std::min<int>(b->count, std::min<int>(16, (int)std::thread::hardware_concurrency())));

@@ -118,7 +118,12 @@ hipError_t launch_batch_pdist(const float* X, int m, const Cloud* clouds, int co
                               int64_t total_points, float* D, hipStream_t s);
 hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, int count,
                                          int64_t total_points, bool enclosing, uint32_t* W,
-                                         CloudState* st, hipStream_t s);
+                                         CloudState* st, hipStream_t s,
+                                         bool allow_inf = false);
+// Sparse input: D (n x n) <- +inf off the diagonal, 0 on it, then the nnz
+// given entries in both orientations; input errors are or-ed into st->err.
+hipError_t launch_sparse_matrix(const int32_t* row, const int32_t* col, const float* val,
+                                int64_t nnz, int n, float* D, CloudState* st, hipStream_t s);
 hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, CloudState* st,
                            H0Pair* out, int64_t out_stride, uint32_t* bitmaps, hipStream_t s);
 // Rank-matrix variant of the same: Wr holds n rows of lds_stride(n) 16-bit

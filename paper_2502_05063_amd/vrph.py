@@ -89,6 +89,7 @@ def lib():
         "vrph_pdist": (i32, [vp, vp, i64, i32, vp, vp]),
         "vrph_barcode_from_dist": (i32, [vp, vp, i64, i32, f32, u32, vp, P(vp)]),
         "vrph_barcode_from_points": (i32, [vp, vp, i64, i32, i32, f32, u32, vp, P(vp)]),
+        "vrph_barcode_from_sparse": (i32, [vp, i64, i64, vp, vp, vp, i32, f32, u32, vp, P(vp)]),
         "vrph_barcode_count": (i64, [vp, i32]),
         "vrph_barcode_pairs": (vp, [vp, i32]),
         "vrph_barcode_stats": (P(Stats), [vp]),
@@ -195,6 +196,26 @@ class Context:
             D = self._f32(D)
             _check(lib().vrph_barcode_from_dist(self.h, _dev_ptr(D), D.shape[0], max_dim,
                                                 threshold, flags, _stream_ptr(), ctypes.byref(out)))
+        return Barcode(out)
+
+    def barcode_sparse(self, n, row, col, val, *, max_dim=1, threshold=float("inf"),
+                       keep_zero=False, no_enclosing=False, autotune=False, lds=True):
+        """Barcode of a sparse distance matrix: entries (row[k], col[k], val[k]) on the
+        device (int32, int32, float32); pairs not given are not edges."""
+        import torch
+
+        flags = ((KEEP_ZERO_PERSISTENCE if keep_zero else 0) | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
+                 | (AUTOTUNE if autotune else 0) | (0 if lds else NO_LDS))
+        for t, dt in ((row, torch.int32), (col, torch.int32), (val, torch.float32)):
+            if not t.is_cuda or t.dtype != dt or t.dim() != 1:
+                raise ValueError("row, col: 1-D int32 CUDA tensors; val: 1-D float32 CUDA tensor")
+        if not (row.numel() == col.numel() == val.numel()):
+            raise ValueError("row, col and val must have the same length")
+        row, col, val = row.contiguous(), col.contiguous(), val.contiguous()
+        out = ctypes.c_void_p()
+        _check(lib().vrph_barcode_from_sparse(self.h, n, row.numel(), _dev_ptr(row), _dev_ptr(col),
+                                              _dev_ptr(val), max_dim, threshold, flags,
+                                              _stream_ptr(), ctypes.byref(out)))
         return Barcode(out)
 
     def backward(self, X, edges, g_birth, g_death, gX):
