@@ -156,8 +156,9 @@ vrph_status vrph_barcode_from_points(vrph_ctx* ctx, const float* X, int64_t n, i
                                      int32_t max_dim, float threshold, uint32_t flags,
                                      void* hip_stream, vrph_barcode** out);
 
-/* Same from a sparse distance matrix (the paper's sparse input, Sec. 5.6.6
- * and the o3 experiment of Table 5.2): nnz entries (row[k], col[k], val[k]),
+/* Same from a sparse distance matrix (Sec. 5.3.12: the distances not given
+ * are infinite, so no simplex with such an edge has a finite diameter; the
+ * o3 run of Table 5.2 uses this input): nnz entries (row[k], col[k], val[k]),
  * each an unordered pair of distinct points 0 <= row, col < n given once, in
  * either orientation, with val finite and >= 0. Pairs that are not given are
  * not edges (an infinite distance): no simplex containing them is in the
