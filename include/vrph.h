@@ -67,6 +67,12 @@ typedef enum {
  * enough (n <= 200) for the kernels that read a 16-bit rank matrix from LDS.
  * Results are identical; this exists to compare and test the two. */
 #define VRPH_NO_LDS 8u
+/* Keep the cleared columns of every dimension >= 2 (Alg. 17: deaths and
+ * apparent cofacets of the dimension below) in a hash set of their indices
+ * instead of a bitmap over all C(n, d+1) indices. The library does this by
+ * itself where a bitmap would exceed 8 GB (e.g. dimension 3 of 4096
+ * points); the flag forces it, for testing. Results are identical. */
+#define VRPH_HASHED_CLEARING 16u
 /* Unknown flag bits are rejected with VRPH_EINVAL; vrph_batch_plan accepts
  * only VRPH_KEEP_ZERO_PERSISTENCE and VRPH_NO_ENCLOSING_RADIUS. */
 
@@ -145,7 +151,7 @@ vrph_status vrph_pdist(vrph_ctx* ctx, const float* X, int64_t n, int32_t m, floa
 
 /* Barcode of a distance matrix. D: n x n float32, finite, >= 0, symmetric,
  * zero diagonal (VRPH_EINVAL otherwise; the triangle inequality is not
- * required, Sec. 5.6.6). 1 <= n <= 2048, 0 <= max_dim <= VRPH_MAX_DIM,
+ * required, Sec. 5.6.6). 1 <= n <= 4096, 0 <= max_dim <= VRPH_MAX_DIM,
  * threshold >= 0 or +inf. */
 vrph_status vrph_barcode_from_dist(vrph_ctx* ctx, const float* D, int64_t n, int32_t max_dim,
                                    float threshold, uint32_t flags, void* hip_stream,
@@ -167,7 +173,7 @@ vrph_status vrph_barcode_from_points(vrph_ctx* ctx, const float* X, int64_t n, i
  * min_i max_j D_ij with the missing entries infinite, i.e. it only cuts
  * where some point has all its n-1 distances given. VRPH_EINVAL for an
  * index out of range, a diagonal entry, a repeated pair, or a value that is
- * negative or not finite. 1 <= n <= 2048, 0 <= nnz <= n(n-1)/2. */
+ * negative or not finite. 1 <= n <= 4096, 0 <= nnz <= n(n-1)/2. */
 vrph_status vrph_barcode_from_sparse(vrph_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row,
                                      const int32_t* col, const float* val, int32_t max_dim,
                                      float threshold, uint32_t flags, void* hip_stream,
@@ -189,7 +195,7 @@ void vrph_barcode_free(vrph_barcode* bc);
  * (sum(sizes) x m floats). vrph_batch_forward replays one captured HIP graph
  * over all clouds (distances, enclosing radii, H0, enumeration and the
  * apparent-pairs test), then reduces the few non-apparent columns of every
- * cloud on host threads. Each size must satisfy 2 <= size <= 2048 and every
+ * cloud on host threads. Each size must satisfy 2 <= size <= 4096 and every
  * cloud uses the same max_dim (<= 1). */
 vrph_status vrph_batch_plan(vrph_ctx* ctx, const int64_t* sizes, int32_t count, int32_t m,
                             int32_t max_dim, float threshold, uint32_t flags, vrph_batch** out);

@@ -55,6 +55,35 @@ __device__ __forceinline__ void edge_vertices(uint64_t c, int& a, int& b) {
   b = (int)(c - (uint64_t)x * (uint64_t)(x - 1) / 2);
 }
 
+// ---- clearing sets (bitmap or hash, see ClearSet) ----
+__device__ __forceinline__ uint64_t clear_slot(const ClearSet& cs, uint64_t c) {
+  return (c * 0x9E3779B97F4A7C15ull) >> 20 & cs.mask;  // multiplicative hash
+}
+__device__ __forceinline__ bool clear_contains(const ClearSet& cs, uint64_t c) {
+  if (cs.bits) return (cs.bits[c >> 5] >> (c & 31)) & 1u;
+  if (!cs.keys) return false;
+  uint64_t sl = clear_slot(cs, c);
+  for (int i = 0; i < kClearProbes; ++i, sl = (sl + 1) & cs.mask) {
+    const unsigned long long k = cs.keys[sl];
+    if (k == c) return true;
+    if (k == kClearEmpty) return false;
+  }
+  return false;  // never inserted: an insert stays within kClearProbes slots
+}
+__device__ __forceinline__ void clear_insert(const ClearSet& cs, uint64_t c) {
+  if (cs.bits) {
+    atomicOr(&cs.bits[c >> 5], 1u << (c & 31));
+    return;
+  }
+  if (!cs.keys) return;
+  uint64_t sl = clear_slot(cs, c);
+  for (int i = 0; i < kClearProbes; ++i, sl = (sl + 1) & cs.mask) {
+    const unsigned long long prev = atomicCAS(&cs.keys[sl], kClearEmpty, (unsigned long long)c);
+    if (prev == kClearEmpty || prev == c) return;
+  }
+  atomicExch(cs.overflow, 1u);
+}
+
 __device__ __forceinline__ int find_cloud(const Cloud* clouds, int count, int64_t key,
                                           int64_t Cloud::*field) {
   int lo = 0, hi = count - 1;
@@ -835,15 +864,15 @@ __device__ __forceinline__ void add_block_counters(unsigned long long (&v)[N],
 template <int D, int BS, int UL, class Rows>
 __device__ __forceinline__ void enum_units(
     const Rows& rows, int n, const uint64_t* __restrict__ binom, int chunk,
-    const uint64_t* __restrict__ unit_cum, uint64_t units, const uint32_t* __restrict__ clear_in,
-    uint32_t* __restrict__ clear_out, const ColumnSink& sink, const PairSink& aps,
+    const uint64_t* __restrict__ unit_cum, uint64_t units, const ClearSet& clear_in,
+    const ClearSet& clear_out, const ColumnSink& sink, const PairSink& aps,
     Scalars* __restrict__ sc) {
   constexpr uint32_t kInfW = Rows::kInfV;
   const int np1 = n + 1;
   auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
   unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0;
   DeferredAppend pend;
-  const bool need_t = clear_out != nullptr || aps.recs != nullptr;
+  const bool need_t = clear_out.bits || clear_out.keys || aps.recs;
   const int bucket = (int)((blockIdx.x * (BS / 64) +
                             (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))) %
                            kSinkBuckets);
@@ -915,11 +944,12 @@ __device__ __forceinline__ void enum_units(
   // the clearing words of a lane's next candidate are read one round ahead,
   // so their latency overlaps the current candidate's work
   uint32_t cw_next = 0;
-  if (clear_in && k_begin + lane < k_end) cw_next = clear_in[(base + k_begin + lane) >> 5];
+  const uint32_t* __restrict__ clear_bits = clear_in.bits;
+  if (clear_bits && k_begin + lane < k_end) cw_next = clear_bits[(base + k_begin + lane) >> 5];
   for (uint64_t kb = k_begin; kb < k_end; kb += UL) {
     const uint64_t k = kb + lane;
     const uint32_t cw = cw_next;
-    if (clear_in && k + UL < k_end) cw_next = clear_in[(base + k + UL) >> 5];
+    if (clear_bits && k + UL < k_end) cw_next = clear_bits[(base + k + UL) >> 5];
     bool is_col = false, is_app = false;
     uint32_t pw[D + 1][D + 1];
     uint32_t diam = kInfW;
@@ -929,14 +959,14 @@ __device__ __forceinline__ void enum_units(
     for (int i = 2; i <= D; ++i) vv[i] = v[i];
     if (k < k_end) {
       // suffix: largest v1 with C(v1, 2) <= k, i.e. floor((1 + sqrt(8k+1))/2),
-      // then v0. k < C(n, 2) < 2^21 and 8k + 1 < 2^24 are exact in 32 bits
-      // and in a float. The hardware square root is within 1 ulp (2^-11 at
-      // 4096), so the estimate is within 1e-3 of the exact quotient and its
-      // floor is off by at most one either way: one exact integer step
-      // corrects it.
+      // then v0. k < C(n, 2) < 2^23, so 8k + 1 < 2^26 is exact in 32 bits and
+      // within a relative 2^-24 as a float; the hardware square root adds at
+      // most 1 ulp (2^-10 at 8192). The estimate is then within 3e-3 of the
+      // exact quotient and its floor is off by at most one either way: one
+      // exact integer step corrects it.
       const uint32_t k32 = (uint32_t)k;
       int v1 = (int)((1.0f + __builtin_amdgcn_sqrtf((float)(8u * k32 + 1u))) * 0.5f);
-      uint32_t t1 = __umul24(v1, v1 - 1) >> 1;  // C(v1, 2); v1 <= n < 2^12
+      uint32_t t1 = __umul24(v1, v1 - 1) >> 1;  // C(v1, 2); v1 <= n <= 2^12
       if (t1 > k32) {
         --v1;
         t1 -= v1;
@@ -962,7 +992,9 @@ __device__ __forceinline__ void enum_units(
       for (int i = 3; i <= D; ++i)
 #pragma unroll
         for (int j = 2; j < i; ++j) pw[i][j] = rows.row_at(vv[i], vv[j]);
-      const bool cleared = (cw >> (c & 31)) & 1u;
+      // a hashed set is probed only for simplices of the complex
+      const bool cleared =
+          clear_bits ? ((cw >> (c & 31)) & 1u) : (diam != kInfW && clear_contains(clear_in, c));
       is_col = diam != kInfW && !cleared;
       if (is_col) {
         ++n_cols;
@@ -978,7 +1010,7 @@ __device__ __forceinline__ void enum_units(
           // dimension or to report the pair
           if (need_t) {
             tcidx = cofacet_index<D>(vv, x, binom, np1);
-            if (clear_out) atomicOr(&clear_out[tcidx >> 5], 1u << (tcidx & 31));
+            clear_insert(clear_out, tcidx);
           }
         }
       }
@@ -1018,8 +1050,8 @@ template <int D>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D <= 3 ? 8 : 4)))
 void enum_apparent_kernel(
     const uint32_t* __restrict__ W, int n, const uint64_t* __restrict__ binom, int chunk,
-    const uint64_t* __restrict__ unit_cum, uint64_t units, const uint32_t* __restrict__ clear_in,
-    uint32_t* __restrict__ clear_out, ColumnSink sink, PairSink aps, Scalars* __restrict__ sc) {
+    const uint64_t* __restrict__ unit_cum, uint64_t units, ClearSet clear_in, ClearSet clear_out,
+    ColumnSink sink, PairSink aps, Scalars* __restrict__ sc) {
   const BufferRows rows(W, n);
   enum_units<D, kBlock, kBlock>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out,
                                 sink, aps, sc);
@@ -1036,8 +1068,8 @@ __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(D <= 
 void enum_apparent_lds_kernel(
     const uint16_t* __restrict__ Wr, const uint32_t* __restrict__ rank_bits, int n,
     const uint64_t* __restrict__ binom, int chunk, const uint64_t* __restrict__ unit_cum,
-    uint64_t units, const uint32_t* __restrict__ clear_in, uint32_t* __restrict__ clear_out,
-    ColumnSink sink, PairSink aps, Scalars* __restrict__ sc) {
+    uint64_t units, ClearSet clear_in, ClearSet clear_out, ColumnSink sink, PairSink aps,
+    Scalars* __restrict__ sc) {
   __shared__ uint4 sw[kLdsMaxN * kLdsMaxN / 8];
   const int stride = lds_stride(n);
   const int words = n * stride / 8;  // 16-byte words; stride is a multiple of 8
@@ -1052,7 +1084,7 @@ void enum_apparent_lds_kernel(
 template <int D>
 static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom, int chunk,
                                 const uint64_t* unit_cum, uint64_t units, unsigned grid,
-                                const uint32_t* clear_in, uint32_t* clear_out, ColumnSink sink,
+                                ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
                                 PairSink aps, Scalars* sc, hipStream_t s) {
   enum_apparent_kernel<D><<<grid, kBlock, 0, s>>>(W, n, binom, chunk, unit_cum, units, clear_in,
                                                   clear_out, sink, aps, sc);
@@ -1062,8 +1094,8 @@ static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom,
 template <int D>
 static hipError_t launch_enum_lds_D(const uint16_t* Wr, const uint32_t* rank_bits, int n,
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
-                                    uint64_t units, unsigned grid, const uint32_t* clear_in,
-                                    uint32_t* clear_out, ColumnSink sink, PairSink aps,
+                                    uint64_t units, unsigned grid, ClearSet clear_in,
+                                    ClearSet clear_out, ColumnSink sink, PairSink aps,
                                     Scalars* sc, hipStream_t s) {
   enum_apparent_lds_kernel<D><<<grid, kLdsBlock, 0, s>>>(Wr, rank_bits, n, binom, chunk, unit_cum,
                                                          units, clear_in, clear_out, sink, aps,
@@ -1073,9 +1105,9 @@ static hipError_t launch_enum_lds_D(const uint16_t* Wr, const uint32_t* rank_bit
 
 hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
-                                    uint64_t units, unsigned max_groups,
-                                    const uint32_t* clear_in, uint32_t* clear_out,
-                                    ColumnSink sink, PairSink aps, Scalars* sc, hipStream_t s) {
+                                    uint64_t units, unsigned max_groups, ClearSet clear_in,
+                                    ClearSet clear_out, ColumnSink sink, PairSink aps,
+                                    Scalars* sc, hipStream_t s) {
   if (units == 0) return hipSuccess;
   if (n < 1 || n > kLdsMaxN || chunk < 64 || chunk % 64 || max_groups == 0)
     return hipErrorInvalidValue;
@@ -1095,7 +1127,7 @@ hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* r
 
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,
                                 const uint64_t* unit_cum, uint64_t units, unsigned max_groups,
-                                const uint32_t* clear_in, uint32_t* clear_out, ColumnSink sink,
+                                ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
                                 PairSink aps, Scalars* sc, hipStream_t s) {
   if (units == 0) return hipSuccess;
   if (chunk < 64 || chunk % 64 || max_groups == 0) return hipErrorInvalidValue;
@@ -1170,7 +1202,7 @@ hipError_t launch_gather_pairs(PairSink sink, ApparentPair* out, uint64_t out_ca
 __global__ __launch_bounds__(kBlock) void batch_edges_kernel(
     const uint32_t* __restrict__ W, const Cloud* __restrict__ clouds, int count,
     int64_t total_edges, const uint32_t* __restrict__ bitmaps, Column* __restrict__ cols,
-    uint64_t cols_cap, ApparentPair* __restrict__ ap, uint64_t ap_cap, uint32_t* __restrict__ clear_out,
+    uint64_t cols_cap, ApparentPair* __restrict__ ap, uint64_t ap_cap, ClearSet clear_out,
     const uint64_t* __restrict__ binom_g, int np1, unsigned long long* __restrict__ counters) {
   unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1206,7 +1238,7 @@ __global__ __launch_bounds__(kBlock) void batch_edges_kernel(
           // triangle index of {x, a, b} (Eq. 5.6)
           int hi = max(x, a), lo = min(x, b), mid = x + a + b - hi - lo;
           t = (uint64_t)hi * (hi - 1) * (hi - 2) / 6 + (uint64_t)mid * (mid - 1) / 2 + (uint64_t)lo;
-          if (clear_out) atomicOr(&clear_out[t >> 5], 1u << (t & 31));
+          clear_insert(clear_out, t);
         }
       }
     }
@@ -1243,7 +1275,7 @@ __global__ __launch_bounds__(kBlock) void batch_edges_kernel(
 hipError_t launch_batch_edges(const uint32_t* W, const Cloud* clouds, int count,
                               int64_t total_edges, const uint32_t* bitmaps, Column* cols,
                               uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
-                              uint32_t* clear_out, unsigned long long* counters, int grid,
+                              ClearSet clear_out, unsigned long long* counters, int grid,
                               hipStream_t s) {
   if (total_edges <= 0) return hipSuccess;
   int64_t need = (total_edges + kBlock - 1) / kBlock;
@@ -1265,6 +1297,21 @@ __global__ void set_bits_kernel(const uint64_t* __restrict__ idx, int64_t count,
     uint64_t t = idx[i];
     atomicOr(&bitmap[t >> 5], 1u << (t & 31));
   }
+}
+
+__global__ void clear_insert_kernel(const uint64_t* __restrict__ idx, int64_t count,
+                                    ClearSet set) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    clear_insert(set, idx[i]);
+}
+
+hipError_t launch_clear_insert(const uint64_t* idx, int64_t count, ClearSet set, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + kBlock - 1) / kBlock;
+  if (blocks > 1024) blocks = 1024;
+  clear_insert_kernel<<<(int)blocks, kBlock, 0, s>>>(idx, count, set);
+  return hipGetLastError();
 }
 
 hipError_t launch_set_bits(const uint64_t* idx, int64_t count, uint32_t* bitmap, hipStream_t s) {

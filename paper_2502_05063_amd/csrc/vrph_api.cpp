@@ -187,6 +187,9 @@ struct vrph_ctx {
   DevBuf D, W, binom, bitmaps, cols, cols_tmp, sort_work, ap, scal, clouds, cstate, h0, deaths;
   DevBuf wr16, rank_bits;  // 16-bit rank matrix and rank -> weight table (LDS kernels)
   DevBuf sink_ctr;         // region counters of the d >= 2 column sink
+  DevBuf hset[kMaxDim + 2];  // hashed clearing sets, per dimension
+  DevBuf hflag;              // their overflow flags
+  uint64_t hslots[kMaxDim + 2] = {};  // slots the hashed sets last needed
   DevBuf ap_ctr, ap_tmp;   // region counters and packed output of the pair sink
   uint64_t col_cap = 0;    // non-apparent columns the buffers are sized for
   uint64_t pair_cap = 0;   // apparent pairs the buffers are sized for
@@ -285,8 +288,9 @@ extern "C" void vrph_destroy(vrph_ctx* c) {
   DevBuf* bufs[] = {&c->D,      &c->W,     &c->binom,  &c->bitmaps, &c->cols,
                     &c->cols_tmp, &c->sort_work, &c->ap, &c->scal,  &c->clouds,
                     &c->cstate,  &c->h0,    &c->deaths, &c->units,   &c->wr16,
-                    &c->rank_bits, &c->sink_ctr, &c->ap_ctr, &c->ap_tmp};
+                    &c->rank_bits, &c->sink_ctr, &c->ap_ctr, &c->ap_tmp, &c->hflag};
   for (DevBuf* b : bufs) b->release();
+  for (DevBuf& b : c->hset) b.release();
   c->h_scal.release();
   c->h_cstate.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -475,17 +479,47 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   H.binom = c->h_binom.data();
   H.kmax = kmax;
 
-  // clearing bitmaps: dimension d columns are C(n, d+1) bits
-  // (dimension 1 always: the H0 kernel marks the forest edges there)
+  // clearing sets: dimension d's columns are C(n, d+1) indices. A bitmap
+  // while it takes at most kBitmapBudget bytes, otherwise a hash set (with
+  // VRPH_HASHED_CLEARING from dimension 2 on). Dimension 1 is always a
+  // bitmap: the H0 kernel marks the forest edges there.
+  constexpr uint64_t kBitmapBudget = 8ull << 30;
   std::vector<int64_t> bm_off(max_dim + 3, 0);
+  std::vector<char> hashed(max_dim + 3, 0);
   int64_t words = 0;
   for (int d = 1; d <= max_dim + 1; ++d) {
     bm_off[d] = words;
-    if (d <= std::max(max_dim, 1)) words += (int64_t)((H.C(n, d + 1) + 31) / 32);
+    if (d > std::max(max_dim, 1)) continue;
+    const uint64_t bits = H.C(n, d + 1);
+    hashed[d] = d >= 2 && ((flags & VRPH_HASHED_CLEARING) || bits / 8 > kBitmapBudget);
+    if (!hashed[d]) words += (int64_t)((bits + 31) / 32);
   }
   HIP_TRY(c->bitmaps.ensure((size_t)std::max<int64_t>(words, 1) * 4));
   uint32_t* bm = c->bitmaps.as<uint32_t>();
   HIP_TRY(launch_fill_u32(bm, words, 0u, s));
+  HIP_TRY(c->hflag.ensure((kMaxDim + 2) * sizeof(uint32_t)));
+  // (re)allocate and empty the hashed set of dimension d with `slots` slots
+  auto make_hashed = [&](int d, uint64_t slots) -> hipError_t {
+    hipError_t e = c->hset[d].ensure(slots * sizeof(unsigned long long));
+    if (e == hipSuccess) e = launch_fill_u32(c->hset[d].as<uint32_t>(), (int64_t)(2 * slots), ~0u, s);
+    if (e == hipSuccess) e = launch_fill_u32(c->hflag.as<uint32_t>() + d, 1, 0u, s);
+    c->hslots[d] = slots;
+    return e;
+  };
+  auto clear_set = [&](int d) -> ClearSet {
+    ClearSet cs{nullptr, nullptr, 0, nullptr};
+    if (d < 1 || d > max_dim) return cs;
+    if (!hashed[d]) {
+      cs.bits = bm + bm_off[d];
+    } else {
+      cs.keys = c->hset[d].as<unsigned long long>();
+      cs.mask = c->hslots[d] - 1;
+      cs.overflow = c->hflag.as<uint32_t>() + d;
+    }
+    return cs;
+  };
+  for (int d = 2; d <= max_dim; ++d)
+    if (hashed[d]) HIP_TRY(make_hashed(d, std::max<uint64_t>(c->hslots[d], 1u << 20)));
 
   vrph_status st = upload_single_cloud(c, n, threshold, s);
   if (st) return st;
@@ -565,8 +599,8 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   std::vector<uint64_t> deaths;
   for (int d = 1; d <= max_dim; ++d) {
     const uint64_t ncand = H.C(n, d + 1);
-    uint32_t* clear_in = bm + bm_off[d];
-    uint32_t* clear_out = d < max_dim ? bm + bm_off[d + 1] : nullptr;
+    const ClearSet clear_in = clear_set(d);
+    ClearSet clear_out = clear_set(d + 1);
     // output capacities grow on demand: the kernel counts past the end
     // without writing, and the dimension runs again with the exact need
     uint64_t cap = c->col_cap;
@@ -609,7 +643,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
         launched = max_groups;
         HIP_TRY_E(hipEventRecord(c->ev0, s));
         HIP_TRY_E(launch_batch_edges(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1,
-                                     (int64_t)ncand, clear_in, c->cols.as<Column>(), cap,
+                                     (int64_t)ncand, clear_in.bits, c->cols.as<Column>(), cap,
                                      keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
                                      clear_out, &dsc->columns, (int)max_groups, s));
         return hipEventRecord(c->ev2, s);
@@ -710,21 +744,39 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       c->tuned[tkey] = param;
       save_tuning(c, tkey, param);
     }
-    for (int attempt = 0; attempt < 2; ++attempt) {
+    // A hashed set of dimension d+1 receives at most one index per column
+    // of dimension d (its apparent cofacet or its death); it is kept at four
+    // slots per column or more (load <= 1/4).
+    auto hashed_out_ok = [&](uint32_t overflow) {
+      return !clear_out.keys || (!overflow && c->hslots[d + 1] >= 4 * sc.columns);
+    };
+    for (int attempt = 0; attempt < 3; ++attempt) {
       HIP_TRY(ensure_cols());
       HIP_TRY(ensure_pairs());
       HIP_TRY(hipMemsetAsync(c->scal.p, 0, sizeof(Scalars), s));
       HIP_TRY(launch_dim(param));
       bc->stats.grid[d] = (int32_t)std::min<uint64_t>(launched, 0x7FFFFFFF);
       HIP_TRY(hipMemcpyAsync(c->h_scal.p, c->scal.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+      uint32_t hov = 0;
+      if (clear_out.keys)
+        HIP_TRY(hipMemcpyAsync(&hov, clear_out.overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       std::memcpy(&sc, c->h_scal.p, sizeof(sc));
-      if (sc.nonapparent <= cap && (!keep_zero || sc.apparent_written <= ap_cap)) break;
+      const bool sets_ok = hashed_out_ok(hov);
+      if (sc.nonapparent <= cap && (!keep_zero || sc.apparent_written <= ap_cap) && sets_ok) break;
       cap = std::max<uint64_t>(cap, sc.nonapparent + 1024);
       if (keep_zero) ap_cap = std::max<uint64_t>(ap_cap, sc.apparent_written + 1024);
+      if (!sets_ok) {
+        uint64_t slots = 1u << 20;
+        while (slots < 4 * sc.columns) slots <<= 1;
+        HIP_TRY(make_hashed(d + 1, slots));
+        clear_out = clear_set(d + 1);
+      }
     }
     if (sc.nonapparent > cap || (keep_zero && sc.apparent_written > ap_cap))
       return fail(VRPH_EDEVICE, "column counts changed between two runs of one dimension");
+    if (!hashed_out_ok(0))
+      return fail(VRPH_EDEVICE, "clearing set of the next dimension overflowed");
     c->col_cap = std::max(c->col_cap, cap);
     if (keep_zero) c->pair_cap = std::max(c->pair_cap, ap_cap);
     const int64_t nna = (int64_t)sc.nonapparent;
@@ -776,12 +828,16 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     }
     bc->stats.pairs[d] = (int64_t)prs.size() + (int64_t)sc.apparent;
     bc->stats.host_ms[d] = now_ms() - h0t;
-    if (clear_out && !deaths.empty()) {
+    if ((clear_out.bits || clear_out.keys) && !deaths.empty()) {
       HIP_TRY(c->deaths.ensure(deaths.size() * sizeof(uint64_t)));
       HIP_TRY(hipMemcpyAsync(c->deaths.p, deaths.data(), deaths.size() * sizeof(uint64_t),
                              hipMemcpyHostToDevice, s));
-      HIP_TRY(launch_set_bits(c->deaths.as<uint64_t>(), (int64_t)deaths.size(), clear_out, s));
+      HIP_TRY(launch_clear_insert(c->deaths.as<uint64_t>(), (int64_t)deaths.size(), clear_out, s));
+      uint32_t hov = 0;
+      if (clear_out.keys)
+        HIP_TRY(hipMemcpyAsync(&hov, clear_out.overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));  // `deaths` is reused by the next dimension
+      if (hov) return fail(VRPH_EDEVICE, "clearing set of the next dimension overflowed");
     }
   }
   finish_pairs(bc.get(), H, max_dim, keep_zero, host_threads());
@@ -790,15 +846,15 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   return VRPH_OK;
 }
 
-constexpr uint32_t kKnownFlags =
-    VRPH_KEEP_ZERO_PERSISTENCE | VRPH_NO_ENCLOSING_RADIUS | VRPH_AUTOTUNE | VRPH_NO_LDS;
+constexpr uint32_t kKnownFlags = VRPH_KEEP_ZERO_PERSISTENCE | VRPH_NO_ENCLOSING_RADIUS |
+                                 VRPH_AUTOTUNE | VRPH_NO_LDS | VRPH_HASHED_CLEARING;
 
 static vrph_status check_common(vrph_ctx* c, int64_t n, int32_t max_dim, float threshold,
                                 uint32_t flags, vrph_barcode** out) {
   if (!c || !out) return fail(VRPH_EINVAL, "NULL context or output");
   *out = nullptr;
   if (flags & ~kKnownFlags) return fail(VRPH_EINVAL, "unknown flag bits");
-  if (n < 1 || n > kMaxN) return fail(VRPH_EINVAL, "n must be in [1, 2048]");
+  if (n < 1 || n > kMaxN) return fail(VRPH_EINVAL, "n must be in [1, 4096]");
   if (max_dim < 0 || max_dim > VRPH_MAX_DIM) return fail(VRPH_EINVAL, "max_dim out of range");
   if (std::isnan(threshold) || threshold < 0) return fail(VRPH_EINVAL, "threshold must be >= 0");
   return VRPH_OK;
@@ -916,7 +972,7 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
   b->binoms.resize(count);
   for (int i = 0; i < count; ++i) {
     const int64_t n = sizes[i];
-    if (n < 2 || n > kMaxN) return fail(VRPH_EINVAL, "vrph_batch_plan: cloud size out of [2, 2048]");
+    if (n < 2 || n > kMaxN) return fail(VRPH_EINVAL, "vrph_batch_plan: cloud size out of [2, 4096]");
     Cloud& cl = b->clouds[i];
     cl.x_off = b->total_points;
     cl.w_off = b->total_w;
@@ -1001,7 +1057,8 @@ static hipError_t batch_record(vrph_batch* b, hipStream_t s) {
     if ((e = launch_batch_edges(b->W.as<uint32_t>(), b->dclouds.as<Cloud>(), b->count,
                                 b->total_edges, b->bitmaps.as<uint32_t>(), b->cols.as<Column>(),
                                 cap, keep_zero ? b->ap.as<ApparentPair>() : nullptr,
-                                keep_zero ? cap : 0, nullptr, &sc->columns,
+                                keep_zero ? cap : 0, ClearSet{nullptr, nullptr, 0, nullptr},
+                                &sc->columns,
                                 b->ctx->num_cus * 8, s)))
       return e;
     int max_edges_bits = 0;

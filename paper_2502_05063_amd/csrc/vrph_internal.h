@@ -13,7 +13,7 @@ namespace vrph {
 // threshold (and the diagonal) hold kInf, larger than any finite pattern.
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr int kMaxDim = 6;        // largest max_dim
-constexpr int kMaxN = 2048;       // largest cloud the one-workgroup H0 kernel takes
+constexpr int kMaxN = 4096;       // largest cloud the one-workgroup H0 kernel takes
 constexpr int kBlock = 256;       // threads per workgroup of the streaming kernels
 // clouds up to kLdsMaxN points enumerate from a 16-bit rank matrix in LDS
 // (at most 80,000 bytes, two workgroups of kLdsBlock per 160 KB CU)
@@ -95,6 +95,22 @@ using PairSink = RecordSink<ApparentPair>;
 inline uint64_t sink_seg(uint64_t cap) { return (cap + cap / 4) / kSinkBuckets + 64; }
 inline uint64_t sink_records(uint64_t cap) { return sink_seg(cap) * kSinkBuckets + cap; }
 
+// The clearing set of one dimension (Alg. 17's cleared columns: deaths and
+// apparent cofacets of the dimension below). A bitmap over all C(n, d+1)
+// indices where that fits the budget, otherwise an open-addressing hash set
+// of the indices (linear probing, at most kClearProbes slots per index; an
+// insert that finds no free slot within them sets *overflow and the
+// dimension below runs again with a larger table). Exactly one of bits and
+// keys is non-null, or neither (nothing cleared).
+constexpr unsigned long long kClearEmpty = ~0ull;
+constexpr int kClearProbes = 64;
+struct ClearSet {
+  uint32_t* bits;
+  unsigned long long* keys;
+  uint64_t mask;        // slots - 1, slots a power of two
+  uint32_t* overflow;
+};
+
 // Per-cloud description for the batched kernels.
 struct Cloud {
   int64_t x_off;    // first point of the cloud in the packed point array
@@ -132,14 +148,14 @@ hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, Cl
 // chunk (suffixes per work unit, one wave each) is a positive multiple of 64.
 hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
-                                    uint64_t units, unsigned max_groups,
-                                    const uint32_t* clear_in, uint32_t* clear_out,
-                                    ColumnSink sink, PairSink aps, Scalars* sc, hipStream_t s);
+                                    uint64_t units, unsigned max_groups, ClearSet clear_in,
+                                    ClearSet clear_out, ColumnSink sink, PairSink aps,
+                                    Scalars* sc, hipStream_t s);
 // d >= 2; unit_cum (n+1 entries, device) and units from enum_units() on the
 // host; at most max_groups workgroups, which stride over the units
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,
                                 const uint64_t* unit_cum, uint64_t units, unsigned max_groups,
-                                const uint32_t* clear_in, uint32_t* clear_out, ColumnSink sink,
+                                ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
                                 PairSink aps, Scalars* sc, hipStream_t s);
 // Pack a sink's records into out (at most out_cap of them) and store their
 // total count in *total (more than out_cap: some were not kept).
@@ -150,9 +166,11 @@ hipError_t launch_gather_pairs(PairSink sink, ApparentPair* out, uint64_t out_ca
 hipError_t launch_batch_edges(const uint32_t* W, const Cloud* clouds, int count,
                               int64_t total_edges, const uint32_t* bitmaps, Column* cols,
                               uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
-                              uint32_t* clear_out, unsigned long long* counters, int grid,
+                              ClearSet clear_out, unsigned long long* counters, int grid,
                               hipStream_t s);
 hipError_t launch_set_bits(const uint64_t* idx, int64_t count, uint32_t* bitmap, hipStream_t s);
+// Insert count indices into a clearing set (bitmap or hash).
+hipError_t launch_clear_insert(const uint64_t* idx, int64_t count, ClearSet set, hipStream_t s);
 hipError_t launch_backward(const float* X, int m, const int32_t* edges, int64_t npairs,
                            const float* g_birth, const float* g_death, float* gX, hipStream_t s);
 

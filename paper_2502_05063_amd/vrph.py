@@ -19,6 +19,7 @@ KEEP_ZERO_PERSISTENCE = 1
 NO_ENCLOSING_RADIUS = 2
 AUTOTUNE = 4
 NO_LDS = 8
+HASHED_CLEARING = 16
 MAX_DIM = 6
 
 PAIR_DTYPE = np.dtype(
@@ -183,9 +184,10 @@ class Context:
         return D
 
     def barcode(self, *, X=None, D=None, max_dim=1, threshold=float("inf"), keep_zero=False,
-                no_enclosing=False, autotune=False, lds=True):
+                no_enclosing=False, autotune=False, lds=True, hashed_clearing=False):
         flags = ((KEEP_ZERO_PERSISTENCE if keep_zero else 0) | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
-                 | (AUTOTUNE if autotune else 0) | (0 if lds else NO_LDS))
+                 | (AUTOTUNE if autotune else 0) | (0 if lds else NO_LDS)
+                 | (HASHED_CLEARING if hashed_clearing else 0))
         out = ctypes.c_void_p()
         if X is not None:
             X = self._f32(X)
@@ -199,13 +201,15 @@ class Context:
         return Barcode(out)
 
     def barcode_sparse(self, n, row, col, val, *, max_dim=1, threshold=float("inf"),
-                       keep_zero=False, no_enclosing=False, autotune=False, lds=True):
+                       keep_zero=False, no_enclosing=False, autotune=False, lds=True,
+                       hashed_clearing=False):
         """Barcode of a sparse distance matrix: entries (row[k], col[k], val[k]) on the
         device (int32, int32, float32); pairs not given are not edges."""
         import torch
 
         flags = ((KEEP_ZERO_PERSISTENCE if keep_zero else 0) | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
-                 | (AUTOTUNE if autotune else 0) | (0 if lds else NO_LDS))
+                 | (AUTOTUNE if autotune else 0) | (0 if lds else NO_LDS)
+                 | (HASHED_CLEARING if hashed_clearing else 0))
         for t, dt in ((row, torch.int32), (col, torch.int32), (val, torch.float32)):
             if not t.is_cuda or t.dtype != dt or t.dim() != 1:
                 raise ValueError("row, col: 1-D int32 CUDA tensors; val: 1-D float32 CUDA tensor")
