@@ -101,7 +101,9 @@ typedef struct {
 } vrph_pair;
 
 /* Counts per dimension d (index d), in the terms of Ch. 5:
- *   candidates      simplices examined by the enumeration
+ *   candidates      simplices examined by the enumeration (all C(n, d+1)
+ *                   indices; for a sparse dimension 3, the suffixes of the
+ *                   edges within the threshold)
  *   columns         columns of the coboundary matrix after the threshold and
  *                   clearing (Alg. 17)
  *   apparent        columns found apparent (Lemma 5.3.6)

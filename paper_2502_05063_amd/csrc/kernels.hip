@@ -864,9 +864,9 @@ __device__ __forceinline__ void add_block_counters(unsigned long long (&v)[N],
 template <int D, int BS, int UL, class Rows>
 __device__ __forceinline__ void enum_units(
     const Rows& rows, int n, const uint64_t* __restrict__ binom, int chunk,
-    const uint64_t* __restrict__ unit_cum, uint64_t units, const ClearSet& clear_in,
-    const ClearSet& clear_out, const ColumnSink& sink, const PairSink& aps,
-    Scalars* __restrict__ sc) {
+    const uint64_t* __restrict__ unit_cum, uint64_t units, const PrefixList& pl,
+    const ClearSet& clear_in, const ClearSet& clear_out, const ColumnSink& sink,
+    const PairSink& aps, Scalars* __restrict__ sc) {
   constexpr uint32_t kInfW = Rows::kInfV;
   const int np1 = n + 1;
   auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
@@ -893,6 +893,29 @@ __device__ __forceinline__ void enum_units(
   const uint64_t ngroups = (uint64_t)gridDim.x * (BS / UL);
   for (uint64_t u = group0; u < units; u += ngroups) {
   // ---- the unit: prefix (v_d..v_2) and its suffix range (uniform) ----
+  int v[D + 1];
+  uint64_t k_begin = 0, k_end = 0;
+  bool listed = false;
+  if constexpr (D == 3) {
+    if (pl.v) {  // listed prefixes: the p with cum[p] <= u < cum[p+1]
+      listed = true;
+      uint32_t lo = 0, hi = pl.count - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (pl.cum[mid] <= u)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      const uint32_t pv = pl.v[lo];
+      v[3] = (int)(pv >> 16);
+      v[2] = (int)(pv & 0xFFFFu);
+      const uint64_t suffixes = (uint64_t)v[2] * (uint64_t)(v[2] - 1) / 2;
+      k_begin = (u - pl.cum[lo]) * (uint64_t)chunk;
+      k_end = min(k_begin + (uint64_t)chunk, suffixes);
+    }
+  }
+  if (!listed) {
   int lo = 0, hi = n - 2;  // largest i with unit_cum[i] <= u; v_2 = n-1-i
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
@@ -906,11 +929,9 @@ __device__ __forceinline__ void enum_units(
   const uint64_t chunks = (suffixes + chunk - 1) / chunk;
   const uint64_t q = u - unit_cum[lo];
   uint64_t upper = q / chunks;  // rank of (v_d..v_3) among (d-2)-subsets of (t, n)
-  const uint64_t k_begin = (q % chunks) * (uint64_t)chunk;
-  const uint64_t k_end = min(k_begin + (uint64_t)chunk, suffixes);
-  int v[D + 1];
+  k_begin = (q % chunks) * (uint64_t)chunk;
+  k_end = min(k_begin + (uint64_t)chunk, suffixes);
   v[2] = t;
-  {
     int top = n - 1 - (t + 1);  // decode in the shifted range [0, n-1-t)
 #pragma unroll
     for (int i = D - 2; i >= 1; --i) {  // position i of the upper part -> v[i+2]
@@ -926,7 +947,7 @@ __device__ __forceinline__ void enum_units(
       upper -= C(a, i);
       top = a - 1;
     }
-  }
+  }  // dense unit table
   uint64_t base = 0;
 #pragma unroll
   for (int i = 2; i <= D; ++i) base += C(v[i], i + 1);
@@ -1050,10 +1071,10 @@ template <int D>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D <= 3 ? 8 : 4)))
 void enum_apparent_kernel(
     const uint32_t* __restrict__ W, int n, const uint64_t* __restrict__ binom, int chunk,
-    const uint64_t* __restrict__ unit_cum, uint64_t units, ClearSet clear_in, ClearSet clear_out,
-    ColumnSink sink, PairSink aps, Scalars* __restrict__ sc) {
+    const uint64_t* __restrict__ unit_cum, uint64_t units, PrefixList pl, ClearSet clear_in,
+    ClearSet clear_out, ColumnSink sink, PairSink aps, Scalars* __restrict__ sc) {
   const BufferRows rows(W, n);
-  enum_units<D, kBlock, kBlock>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out,
+  enum_units<D, kBlock, kBlock>(rows, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out,
                                 sink, aps, sc);
 }
 
@@ -1068,8 +1089,8 @@ __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(D <= 
 void enum_apparent_lds_kernel(
     const uint16_t* __restrict__ Wr, const uint32_t* __restrict__ rank_bits, int n,
     const uint64_t* __restrict__ binom, int chunk, const uint64_t* __restrict__ unit_cum,
-    uint64_t units, ClearSet clear_in, ClearSet clear_out, ColumnSink sink, PairSink aps,
-    Scalars* __restrict__ sc) {
+    uint64_t units, PrefixList pl, ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
+    PairSink aps, Scalars* __restrict__ sc) {
   __shared__ uint4 sw[kLdsMaxN * kLdsMaxN / 8];
   const int stride = lds_stride(n);
   const int words = n * stride / 8;  // 16-byte words; stride is a multiple of 8
@@ -1077,37 +1098,37 @@ void enum_apparent_lds_kernel(
   for (int i = threadIdx.x; i < words; i += kLdsBlock) sw[i] = src[i];
   __syncthreads();
   const LdsRows rows{reinterpret_cast<const uint16_t*>(sw), n, stride, rank_bits};
-  enum_units<D, kLdsBlock, 64>(rows, n, binom, chunk, unit_cum, units, clear_in, clear_out,
+  enum_units<D, kLdsBlock, 64>(rows, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out,
                                sink, aps, sc);
 }
 
 template <int D>
 static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom, int chunk,
-                                const uint64_t* unit_cum, uint64_t units, unsigned grid,
-                                ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
-                                PairSink aps, Scalars* sc, hipStream_t s) {
-  enum_apparent_kernel<D><<<grid, kBlock, 0, s>>>(W, n, binom, chunk, unit_cum, units, clear_in,
-                                                  clear_out, sink, aps, sc);
+                                const uint64_t* unit_cum, uint64_t units, PrefixList pl,
+                                unsigned grid, ClearSet clear_in, ClearSet clear_out,
+                                ColumnSink sink, PairSink aps, Scalars* sc, hipStream_t s) {
+  enum_apparent_kernel<D><<<grid, kBlock, 0, s>>>(W, n, binom, chunk, unit_cum, units, pl,
+                                                  clear_in, clear_out, sink, aps, sc);
   return hipGetLastError();
 }
 
 template <int D>
 static hipError_t launch_enum_lds_D(const uint16_t* Wr, const uint32_t* rank_bits, int n,
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
-                                    uint64_t units, unsigned grid, ClearSet clear_in,
-                                    ClearSet clear_out, ColumnSink sink, PairSink aps,
-                                    Scalars* sc, hipStream_t s) {
+                                    uint64_t units, PrefixList pl, unsigned grid,
+                                    ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
+                                    PairSink aps, Scalars* sc, hipStream_t s) {
   enum_apparent_lds_kernel<D><<<grid, kLdsBlock, 0, s>>>(Wr, rank_bits, n, binom, chunk, unit_cum,
-                                                         units, clear_in, clear_out, sink, aps,
-                                                         sc);
+                                                         units, pl, clear_in, clear_out, sink,
+                                                         aps, sc);
   return hipGetLastError();
 }
 
 hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
-                                    uint64_t units, unsigned max_groups, ClearSet clear_in,
-                                    ClearSet clear_out, ColumnSink sink, PairSink aps,
-                                    Scalars* sc, hipStream_t s) {
+                                    uint64_t units, PrefixList pl, unsigned max_groups,
+                                    ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
+                                    PairSink aps, Scalars* sc, hipStream_t s) {
   if (units == 0) return hipSuccess;
   if (n < 1 || n > kLdsMaxN || chunk < 64 || chunk % 64 || max_groups == 0)
     return hipErrorInvalidValue;
@@ -1116,19 +1137,19 @@ hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* r
   if (g > (uint64_t)kMaxGroups) g = kMaxGroups;
   const unsigned grid = (unsigned)g;
   switch (d) {
-    case 2: return launch_enum_lds_D<2>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
-    case 3: return launch_enum_lds_D<3>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
-    case 4: return launch_enum_lds_D<4>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
-    case 5: return launch_enum_lds_D<5>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
-    case 6: return launch_enum_lds_D<6>(Wr, rank_bits, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 2: return launch_enum_lds_D<2>(Wr, rank_bits, n, binom, chunk, unit_cum, units, pl, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 3: return launch_enum_lds_D<3>(Wr, rank_bits, n, binom, chunk, unit_cum, units, pl, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 4: return launch_enum_lds_D<4>(Wr, rank_bits, n, binom, chunk, unit_cum, units, pl, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 5: return launch_enum_lds_D<5>(Wr, rank_bits, n, binom, chunk, unit_cum, units, pl, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 6: return launch_enum_lds_D<6>(Wr, rank_bits, n, binom, chunk, unit_cum, units, pl, grid, clear_in, clear_out, sink, aps, sc, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,
-                                const uint64_t* unit_cum, uint64_t units, unsigned max_groups,
-                                ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
-                                PairSink aps, Scalars* sc, hipStream_t s) {
+                                const uint64_t* unit_cum, uint64_t units, PrefixList pl,
+                                unsigned max_groups, ClearSet clear_in, ClearSet clear_out,
+                                ColumnSink sink, PairSink aps, Scalars* sc, hipStream_t s) {
   if (units == 0) return hipSuccess;
   if (chunk < 64 || chunk % 64 || max_groups == 0) return hipErrorInvalidValue;
   // at most kMaxGroups workgroups: the dispatch counts work-items in 32 bits;
@@ -1139,11 +1160,11 @@ hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t*
   if (g > (uint64_t)kMaxGroups) g = kMaxGroups;
   const unsigned grid = (unsigned)g;
   switch (d) {
-    case 2: return launch_enum_D<2>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
-    case 3: return launch_enum_D<3>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
-    case 4: return launch_enum_D<4>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
-    case 5: return launch_enum_D<5>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
-    case 6: return launch_enum_D<6>(W, n, binom, chunk, unit_cum, units, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 2: return launch_enum_D<2>(W, n, binom, chunk, unit_cum, units, pl, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 3: return launch_enum_D<3>(W, n, binom, chunk, unit_cum, units, pl, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 4: return launch_enum_D<4>(W, n, binom, chunk, unit_cum, units, pl, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 5: return launch_enum_D<5>(W, n, binom, chunk, unit_cum, units, pl, grid, clear_in, clear_out, sink, aps, sc, s);
+    case 6: return launch_enum_D<6>(W, n, binom, chunk, unit_cum, units, pl, grid, clear_in, clear_out, sink, aps, sc, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -200,6 +200,8 @@ struct vrph_ctx {
   // (dimension, size bucket, kernel variant: 0 global, 1 LDS) -> setting
   std::map<std::tuple<int, int, int>, Tune> tuned;
   DevBuf units;                    // unit table of the d >= 2 enumeration
+  DevBuf pfx_v, pfx_cum;           // listed prefixes of a sparse dimension-3 enumeration
+  std::vector<uint64_t> h_pfx_cum;
   std::vector<uint64_t> h_units;
 };
 
@@ -220,6 +222,18 @@ static uint64_t enum_units(int n, int d, int chunk, const std::vector<uint64_t>&
     cum[i + 1] = cum[i] + u;
   }
   return cum[n];
+}
+
+// Work units over listed dimension-3 prefixes (edges v3 > v2, packed
+// v3 << 16 | v2): cum[p] counts the units of the prefixes before p.
+static uint64_t listed_units(const std::vector<uint32_t>& pv, int chunk, std::vector<uint64_t>& cum) {
+  cum.assign(pv.size() + 1, 0);
+  for (size_t p = 0; p < pv.size(); ++p) {
+    const uint64_t v2 = pv[p] & 0xFFFFu;
+    const uint64_t suf = v2 * (v2 - 1) / 2;
+    cum[p + 1] = cum[p] + (suf + chunk - 1) / chunk;
+  }
+  return cum.back();
 }
 
 // Autotuning of the enumeration kernels' launch (see VRPH_AUTOTUNE).
@@ -575,6 +589,28 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
                              ranks.bits.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
   }
 
+  // Dimension 3 over a sparse edge set: list its prefixes, the edges
+  // (v3 > v2 >= 2) within the threshold, largest v2 first, so that no work
+  // unit is spent on a vertex pair that is not an edge (see PrefixList).
+  std::vector<uint32_t> pfx;
+  if (max_dim >= 3 && n >= 4) {
+    uint64_t valid = 0, total = 0;
+    for (int v2 = 2; v2 < n - 1; ++v2)
+      for (int v3 = v2 + 1; v3 < n; ++v3) {
+        ++total;
+        valid += hW[(size_t)v3 * n + v2] != kInf;
+      }
+    if (valid > 0 && 2 * valid < total) {
+      pfx.reserve(valid);
+      for (int v2 = n - 2; v2 >= 2; --v2)
+        for (int v3 = v2 + 1; v3 < n; ++v3)
+          if (hW[(size_t)v3 * n + v2] != kInf) pfx.push_back(((uint32_t)v3 << 16) | (uint32_t)v2);
+      HIP_TRY(c->pfx_v.ensure(pfx.size() * sizeof(uint32_t)));
+      HIP_TRY(hipMemcpyAsync(c->pfx_v.p, pfx.data(), pfx.size() * sizeof(uint32_t),
+                             hipMemcpyHostToDevice, s));
+    }
+  }
+
   std::unique_ptr<vrph_barcode> bc(new (std::nothrow) vrph_barcode());
   if (!bc) return fail(VRPH_ENOMEM, "out of host memory");
   std::memset(&bc->stats, 0, sizeof(bc->stats));
@@ -599,6 +635,16 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   std::vector<uint64_t> deaths;
   for (int d = 1; d <= max_dim; ++d) {
     const uint64_t ncand = H.C(n, d + 1);
+    // the candidates the enumeration examines: all d-simplex indices, or,
+    // over listed prefixes, the suffixes of the listed edges
+    uint64_t examined = ncand;
+    if (d == 3 && !pfx.empty()) {
+      examined = 0;
+      for (uint32_t pv : pfx) {
+        const uint64_t v2 = pv & 0xFFFFu;
+        examined += v2 * (v2 - 1) / 2;
+      }
+    }
     const ClearSet clear_in = clear_set(d);
     ClearSet clear_out = clear_set(d + 1);
     // output capacities grow on demand: the kernel counts past the end
@@ -648,7 +694,20 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
                                      clear_out, &dsc->columns, (int)max_groups, s));
         return hipEventRecord(c->ev2, s);
       }
-      const uint64_t units = enum_units(n, d, t.chunk, c->h_binom, c->h_units);
+      // dimension 3 over a sparse edge set: list the prefixes (edges) instead
+      PrefixList pl{nullptr, nullptr, 0};
+      uint64_t units = 0;
+      if (d == 3 && !pfx.empty()) {
+        units = listed_units(pfx, t.chunk, c->h_pfx_cum);
+        hipError_t e2 = c->pfx_cum.ensure(c->h_pfx_cum.size() * sizeof(uint64_t));
+        if (e2 != hipSuccess) return e2;
+        e2 = hipMemcpyAsync(c->pfx_cum.p, c->h_pfx_cum.data(),
+                            c->h_pfx_cum.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+        if (e2 != hipSuccess) return e2;
+        pl = PrefixList{c->pfx_cum.as<uint64_t>(), c->pfx_v.as<uint32_t>(), (uint32_t)pfx.size()};
+      } else {
+        units = enum_units(n, d, t.chunk, c->h_binom, c->h_units);
+      }
       // LDS kernel: a unit per wave; global-memory kernel: a unit per workgroup
       const uint64_t units_per_group = use_lds ? kLdsBlock / 64 : 1;
       launched = std::min<uint64_t>(
@@ -672,12 +731,12 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       if (use_lds)
         HIP_TRY_E(launch_enum_apparent_lds(
             d, c->wr16.as<uint16_t>(), c->rank_bits.as<uint32_t>(), n, c->binom.as<uint64_t>(),
-            t.chunk, c->units.as<uint64_t>(), units, max_groups, clear_in, clear_out, sink, aps,
-            dsc, s));
+            t.chunk, c->units.as<uint64_t>(), units, pl, max_groups, clear_in, clear_out, sink,
+            aps, dsc, s));
       else
         HIP_TRY_E(launch_enum_apparent(d, c->W.as<uint32_t>(), n, c->binom.as<uint64_t>(),
-                                       t.chunk, c->units.as<uint64_t>(), units, max_groups,
-                                       clear_in, clear_out, sink, aps, dsc, s));
+                                       t.chunk, c->units.as<uint64_t>(), units, pl,
+                                       max_groups, clear_in, clear_out, sink, aps, dsc, s));
       HIP_TRY_E(hipEventRecord(c->ev2, s));
       HIP_TRY_E(launch_gather_columns(sink, c->cols_tmp.as<Column>(), cap, &dsc->nonapparent, s));
       if (keep_zero)
@@ -696,7 +755,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     {
       const uint64_t takers = (uint64_t)c->num_cus * (uint64_t)param.mult *
                               (uint64_t)(lds_dim ? kLdsBlock / 64 : 1);
-      const uint64_t per = ncand / std::max<uint64_t>(4 * takers, 1);
+      const uint64_t per = examined / std::max<uint64_t>(4 * takers, 1);
       while (param.chunk < kMaxChunk && (uint64_t)param.chunk * 2 <= per) param.chunk *= 2;
     }
     auto it = c->tuned.find(tkey);
@@ -731,10 +790,19 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       };
       // two rounds of coordinate search: unit sizes at the current grid,
       // then grids at the current unit size
+      // unit sizes that would give far more units than the default are not
+      // tried: each unit costs a decode even where its prefix is skipped
+      std::vector<uint64_t> scratch;
+      auto units_for = [&](int chunk) -> uint64_t {
+        return d == 3 && !pfx.empty() ? listed_units(pfx, chunk, scratch)
+                                      : enum_units(n, d, chunk, c->h_binom, scratch);
+      };
+      const uint64_t unit_limit = std::max<uint64_t>(4 * units_for(param.chunk), 1u << 24);
       for (int round = 0; round < 2; ++round) {
         if (d >= 2) {
           const int mult = param.mult;
-          for (int chunk = 64; chunk <= kMaxChunk; chunk *= 2) HIP_TRY(trial(Tune{chunk, mult}));
+          for (int chunk = 64; chunk <= kMaxChunk; chunk *= 2)
+            if (units_for(chunk) <= unit_limit) HIP_TRY(trial(Tune{chunk, mult}));
         }
         const int chunk = param.chunk;
         for (int mult : {1, 2, 4, 8, 16, 32, 64})
@@ -801,7 +869,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     bc->stats.apparent_ms[d] = ms;
     bc->stats.cofacets[d] = (int64_t)sc.scan_steps;
     bc->stats.facets[d] = (int64_t)sc.facet_steps;
-    bc->stats.candidates[d] = (int64_t)ncand;
+    bc->stats.candidates[d] = (int64_t)examined;
     bc->stats.columns[d] = (int64_t)sc.columns;
     bc->stats.apparent[d] = (int64_t)sc.apparent;
     bc->stats.reduced[d] = nna;

@@ -111,6 +111,18 @@ struct ClearSet {
   uint32_t* overflow;
 };
 
+// The prefixes of a dimension-3 enumeration listed explicitly: the edges
+// (v_3 > v_2) within the threshold, packed v_3 << 16 | v_2, with cum[p] the
+// work units of the prefixes before p (cum has count + 1 entries). Used where
+// most vertex pairs are not edges, so that no unit is spent on a prefix that
+// spans no simplex. v == nullptr: every prefix, numbered as in the dense
+// unit table.
+struct PrefixList {
+  const uint64_t* cum;
+  const uint32_t* v;
+  uint32_t count;
+};
+
 // Per-cloud description for the batched kernels.
 struct Cloud {
   int64_t x_off;    // first point of the cloud in the packed point array
@@ -148,15 +160,15 @@ hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, Cl
 // chunk (suffixes per work unit, one wave each) is a positive multiple of 64.
 hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
                                     const uint64_t* binom, int chunk, const uint64_t* unit_cum,
-                                    uint64_t units, unsigned max_groups, ClearSet clear_in,
-                                    ClearSet clear_out, ColumnSink sink, PairSink aps,
-                                    Scalars* sc, hipStream_t s);
+                                    uint64_t units, PrefixList pl, unsigned max_groups,
+                                    ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
+                                    PairSink aps, Scalars* sc, hipStream_t s);
 // d >= 2; unit_cum (n+1 entries, device) and units from enum_units() on the
 // host; at most max_groups workgroups, which stride over the units
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,
-                                const uint64_t* unit_cum, uint64_t units, unsigned max_groups,
-                                ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
-                                PairSink aps, Scalars* sc, hipStream_t s);
+                                const uint64_t* unit_cum, uint64_t units, PrefixList pl,
+                                unsigned max_groups, ClearSet clear_in, ClearSet clear_out,
+                                ColumnSink sink, PairSink aps, Scalars* sc, hipStream_t s);
 // Pack a sink's records into out (at most out_cap of them) and store their
 // total count in *total (more than out_cap: some were not kept).
 hipError_t launch_gather_columns(ColumnSink sink, Column* out, uint64_t out_cap,
