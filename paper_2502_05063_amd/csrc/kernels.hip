@@ -870,7 +870,7 @@ __device__ __forceinline__ void enum_units(
   constexpr uint32_t kInfW = Rows::kInfV;
   const int np1 = n + 1;
   auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
-  unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0;
+  unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0, n_cand = 0;
   DeferredAppend pend;
   const bool need_t = clear_out.bits || clear_out.keys || aps.recs;
   const int bucket = (int)((blockIdx.x * (BS / 64) +
@@ -962,10 +962,47 @@ __device__ __forceinline__ void enum_units(
   if (pmax == kInfW) continue;
   uint32_t u_steps = 0, u_facets = 0;
 
+  // Neighbour mode (listed dimension-3 prefixes in the global-memory
+  // kernel, Sec. 5.3.13): the suffixes (v1 > v0) of a prefix (v3, v2) that
+  // can span a simplex are the pairs of common neighbours of v3 and v2 below
+  // v2. The workgroup lists them in LDS in increasing order, and suffix k
+  // below is then the k-th pair (i > j) of that list instead of the k-th
+  // pair of all vertices below v2.
+  constexpr bool kNeighbours = D == 3 && !__is_same(Rows, LdsRows);
+  const uint16_t* nb = nullptr;
+  if constexpr (kNeighbours) {
+    if (listed) {
+      __shared__ uint16_t cn[kMaxN];
+      __shared__ uint32_t wcount[BS / 64];
+      const int wave = (int)(threadIdx.x >> 6), l64 = (int)(threadIdx.x & 63);
+      uint32_t cnt = 0;
+      for (int x0 = 0; x0 < v[2]; x0 += BS) {
+        const int x = x0 + (int)threadIdx.x;
+        const bool in = x < v[2] && rows.row_at(v[3], x) != kInfW && rows.row_at(v[2], x) != kInfW;
+        const unsigned long long m = __ballot(in);
+        if (l64 == 0) wcount[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t off = cnt, all = 0;
+        for (int w = 0; w < BS / 64; ++w) {
+          if (w < wave) off += wcount[w];
+          all += wcount[w];
+        }
+        if (in) cn[off + (uint32_t)__popcll(l64 ? (m & ((~0ull) >> (64 - l64))) : 0ull)] = (uint16_t)x;
+        cnt += all;
+        __syncthreads();
+      }
+      nb = cn;
+      k_begin = 0;
+      k_end = (uint64_t)cnt * (cnt - 1) / 2;
+      if (threadIdx.x == 0) n_cand += k_end;
+    }
+  }
+
   // the clearing words of a lane's next candidate are read one round ahead,
-  // so their latency overlaps the current candidate's work
+  // so their latency overlaps the current candidate's work (dense suffixes
+  // only: in neighbour mode consecutive k are not consecutive indices)
   uint32_t cw_next = 0;
-  const uint32_t* __restrict__ clear_bits = clear_in.bits;
+  const uint32_t* __restrict__ clear_bits = nb ? nullptr : clear_in.bits;
   if (clear_bits && k_begin + lane < k_end) cw_next = clear_bits[(base + k_begin + lane) >> 5];
   for (uint64_t kb = k_begin; kb < k_end; kb += UL) {
     const uint64_t k = kb + lane;
@@ -998,6 +1035,13 @@ __device__ __forceinline__ void enum_units(
       vv[1] = v1;
       vv[0] = (int)(k32 - t1);
       c = base + k;
+      if constexpr (kNeighbours) {
+        if (nb) {  // the k-th pair of common neighbours
+          vv[1] = nb[v1];
+          vv[0] = nb[k32 - t1];
+          c = base + (uint64_t)vv[1] * (uint64_t)(vv[1] - 1) / 2 + (uint64_t)vv[0];
+        }
+      }
       diam = pmax;
       // rows of the prefix vertices are uniform; (v1, v0) is per lane
       pw[1][0] = rows.lane_at(vv[1], vv[0]);
@@ -1057,13 +1101,15 @@ __device__ __forceinline__ void enum_units(
   // fewer than n cofacets and D + 1 facets each
   n_steps += u_steps;
   n_facets += u_facets;
+  if constexpr (kNeighbours)
+    if (nb) __syncthreads();  // the next unit rewrites the neighbour list
   }  // units
   pend.flush(sink, bucket);
   // workgroup totals, one atomic each
-  unsigned long long tot[4] = {n_cols, n_app, n_steps, n_facets};
-  unsigned long long* const dst[4] = {&sc->columns, &sc->apparent, &sc->scan_steps,
-                                      &sc->facet_steps};
-  add_block_counters<BS, 4>(tot, dst);
+  unsigned long long tot[5] = {n_cols, n_app, n_steps, n_facets, n_cand};
+  unsigned long long* const dst[5] = {&sc->columns, &sc->apparent, &sc->scan_steps,
+                                      &sc->facet_steps, &sc->candidates};
+  add_block_counters<BS, 5>(tot, dst);
 }
 
 // 8 waves per SIMD (64 vector, 96 scalar registers) for D <= 3

@@ -225,15 +225,13 @@ static uint64_t enum_units(int n, int d, int chunk, const std::vector<uint64_t>&
 }
 
 // Work units over listed dimension-3 prefixes (edges v3 > v2, packed
-// v3 << 16 | v2): cum[p] counts the units of the prefixes before p.
-static uint64_t listed_units(const std::vector<uint32_t>& pv, int chunk, std::vector<uint64_t>& cum) {
-  cum.assign(pv.size() + 1, 0);
-  for (size_t p = 0; p < pv.size(); ++p) {
-    const uint64_t v2 = pv[p] & 0xFFFFu;
-    const uint64_t suf = v2 * (v2 - 1) / 2;
-    cum[p + 1] = cum[p] + (suf + chunk - 1) / chunk;
-  }
-  return cum.back();
+// v3 << 16 | v2): cum[p] counts the units of the prefixes before p. The
+// global-memory kernel enumerates a listed prefix's suffixes over the common
+// neighbours of v3 and v2, one unit per prefix.
+static uint64_t listed_units(const std::vector<uint32_t>& pv, std::vector<uint64_t>& cum) {
+  cum.resize(pv.size() + 1);
+  for (size_t p = 0; p <= pv.size(); ++p) cum[p] = p;
+  return pv.size();
 }
 
 // Autotuning of the enumeration kernels' launch (see VRPH_AUTOTUNE).
@@ -593,7 +591,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   // (v3 > v2 >= 2) within the threshold, largest v2 first, so that no work
   // unit is spent on a vertex pair that is not an edge (see PrefixList).
   std::vector<uint32_t> pfx;
-  if (max_dim >= 3 && n >= 4) {
+  if (max_dim >= 3 && n >= 4 && !use_lds) {
     uint64_t valid = 0, total = 0;
     for (int v2 = 2; v2 < n - 1; ++v2)
       for (int v3 = v2 + 1; v3 < n; ++v3) {
@@ -698,7 +696,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       PrefixList pl{nullptr, nullptr, 0};
       uint64_t units = 0;
       if (d == 3 && !pfx.empty()) {
-        units = listed_units(pfx, t.chunk, c->h_pfx_cum);
+        units = listed_units(pfx, c->h_pfx_cum);
         hipError_t e2 = c->pfx_cum.ensure(c->h_pfx_cum.size() * sizeof(uint64_t));
         if (e2 != hipSuccess) return e2;
         e2 = hipMemcpyAsync(c->pfx_cum.p, c->h_pfx_cum.data(),
@@ -793,13 +791,13 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       // unit sizes that would give far more units than the default are not
       // tried: each unit costs a decode even where its prefix is skipped
       std::vector<uint64_t> scratch;
+      const bool listed = d == 3 && !pfx.empty();  // unit size has no effect then
       auto units_for = [&](int chunk) -> uint64_t {
-        return d == 3 && !pfx.empty() ? listed_units(pfx, chunk, scratch)
-                                      : enum_units(n, d, chunk, c->h_binom, scratch);
+        return listed ? listed_units(pfx, scratch) : enum_units(n, d, chunk, c->h_binom, scratch);
       };
       const uint64_t unit_limit = std::max<uint64_t>(4 * units_for(param.chunk), 1u << 24);
       for (int round = 0; round < 2; ++round) {
-        if (d >= 2) {
+        if (d >= 2 && !listed) {
           const int mult = param.mult;
           for (int chunk = 64; chunk <= kMaxChunk; chunk *= 2)
             if (units_for(chunk) <= unit_limit) HIP_TRY(trial(Tune{chunk, mult}));
@@ -869,7 +867,8 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     bc->stats.apparent_ms[d] = ms;
     bc->stats.cofacets[d] = (int64_t)sc.scan_steps;
     bc->stats.facets[d] = (int64_t)sc.facet_steps;
-    bc->stats.candidates[d] = (int64_t)examined;
+    // over listed prefixes the kernel counts the suffixes it enumerated
+    bc->stats.candidates[d] = d == 3 && !pfx.empty() ? (int64_t)sc.candidates : (int64_t)examined;
     bc->stats.columns[d] = (int64_t)sc.columns;
     bc->stats.apparent[d] = (int64_t)sc.apparent;
     bc->stats.reduced[d] = nna;
