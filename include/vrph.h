@@ -102,8 +102,9 @@ typedef struct {
 
 /* Counts per dimension d (index d), in the terms of Ch. 5:
  *   candidates      simplices examined by the enumeration (all C(n, d+1)
- *                   indices; for a sparse dimension 3, the suffixes of the
- *                   edges within the threshold)
+ *                   indices; where at most half the vertex pairs are edges
+ *                   and n > 200, dimensions 2 and 3 enumerate only vertex
+ *                   sets over common neighbours, and this counts those)
  *   columns         columns of the coboundary matrix after the threshold and
  *                   clearing (Alg. 17)
  *   apparent        columns found apparent (Lemma 5.3.6)

@@ -896,7 +896,7 @@ __device__ __forceinline__ void enum_units(
   int v[D + 1];
   uint64_t k_begin = 0, k_end = 0;
   bool listed = false;
-  if constexpr (D == 3) {
+  if constexpr (D == 2 || D == 3) {
     if (pl.v) {  // listed prefixes: the p with cum[p] <= u < cum[p+1]
       listed = true;
       uint32_t lo = 0, hi = pl.count - 1;
@@ -908,7 +908,7 @@ __device__ __forceinline__ void enum_units(
           hi = mid - 1;
       }
       const uint32_t pv = pl.v[lo];
-      v[3] = (int)(pv >> 16);
+      if constexpr (D == 3) v[3] = (int)(pv >> 16);
       v[2] = (int)(pv & 0xFFFFu);
       const uint64_t suffixes = (uint64_t)v[2] * (uint64_t)(v[2] - 1) / 2;
       k_begin = (u - pl.cum[lo]) * (uint64_t)chunk;
@@ -962,13 +962,13 @@ __device__ __forceinline__ void enum_units(
   if (pmax == kInfW) continue;
   uint32_t u_steps = 0, u_facets = 0;
 
-  // Neighbour mode (listed dimension-3 prefixes in the global-memory
-  // kernel, Sec. 5.3.13): the suffixes (v1 > v0) of a prefix (v3, v2) that
-  // can span a simplex are the pairs of common neighbours of v3 and v2 below
-  // v2. The workgroup lists them in LDS in increasing order, and suffix k
-  // below is then the k-th pair (i > j) of that list instead of the k-th
-  // pair of all vertices below v2.
-  constexpr bool kNeighbours = D == 3 && !__is_same(Rows, LdsRows);
+  // Neighbour mode (listed prefixes of dimension 2 or 3 in the
+  // global-memory kernel, Sec. 5.3.13): the suffixes (v1 > v0) of a prefix
+  // (v3, v2), or (v2), that can span a simplex are the pairs of common
+  // neighbours of the prefix vertices below v2. The workgroup lists them in
+  // LDS in increasing order, and suffix k below is then the k-th pair
+  // (i > j) of that list instead of the k-th pair of all vertices below v2.
+  constexpr bool kNeighbours = (D == 2 || D == 3) && !__is_same(Rows, LdsRows);
   const uint16_t* nb = nullptr;
   if constexpr (kNeighbours) {
     if (listed) {
@@ -978,7 +978,8 @@ __device__ __forceinline__ void enum_units(
       uint32_t cnt = 0;
       for (int x0 = 0; x0 < v[2]; x0 += BS) {
         const int x = x0 + (int)threadIdx.x;
-        const bool in = x < v[2] && rows.row_at(v[3], x) != kInfW && rows.row_at(v[2], x) != kInfW;
+        bool in = x < v[2] && rows.row_at(v[2], x) != kInfW;
+        if constexpr (D == 3) in = in && rows.row_at(v[3], x) != kInfW;
         const unsigned long long m = __ballot(in);
         if (l64 == 0) wcount[wave] = (uint32_t)__popcll(m);
         __syncthreads();

@@ -200,7 +200,7 @@ struct vrph_ctx {
   // (dimension, size bucket, kernel variant: 0 global, 1 LDS) -> setting
   std::map<std::tuple<int, int, int>, Tune> tuned;
   DevBuf units;                    // unit table of the d >= 2 enumeration
-  DevBuf pfx_v, pfx_cum;           // listed prefixes of a sparse dimension-3 enumeration
+  DevBuf pfx_v, pfx_cum;           // listed prefixes of sparse dimension-2 and 3 enumerations
   std::vector<uint64_t> h_pfx_cum;
   std::vector<uint64_t> h_units;
 };
@@ -587,27 +587,39 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
                              ranks.bits.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
   }
 
-  // Dimension 3 over a sparse edge set: list its prefixes, the edges
-  // (v3 > v2 >= 2) within the threshold, largest v2 first, so that no work
-  // unit is spent on a vertex pair that is not an edge (see PrefixList).
-  std::vector<uint32_t> pfx;
-  if (max_dim >= 3 && n >= 4 && !use_lds) {
+  // Dimensions 2 and 3 over a sparse edge set (at most half the vertex
+  // pairs within the threshold): list the prefixes, the vertices v2 >= 2 and
+  // the edges (v3 > v2 >= 2) within the threshold, largest v2 first; the
+  // global-memory kernel then enumerates their suffixes over common
+  // neighbours (see PrefixList).
+  std::vector<uint32_t> pfx2, pfx3;
+  if (max_dim >= 2 && n >= 3 && !use_lds) {
     uint64_t valid = 0, total = 0;
-    for (int v2 = 2; v2 < n - 1; ++v2)
-      for (int v3 = v2 + 1; v3 < n; ++v3) {
+    for (int a = 1; a < n; ++a)
+      for (int b = 0; b < a; ++b) {
         ++total;
-        valid += hW[(size_t)v3 * n + v2] != kInf;
+        valid += hW[(size_t)a * n + b] != kInf;
       }
-    if (valid > 0 && 2 * valid < total) {
-      pfx.reserve(valid);
-      for (int v2 = n - 2; v2 >= 2; --v2)
-        for (int v3 = v2 + 1; v3 < n; ++v3)
-          if (hW[(size_t)v3 * n + v2] != kInf) pfx.push_back(((uint32_t)v3 << 16) | (uint32_t)v2);
-      HIP_TRY(c->pfx_v.ensure(pfx.size() * sizeof(uint32_t)));
-      HIP_TRY(hipMemcpyAsync(c->pfx_v.p, pfx.data(), pfx.size() * sizeof(uint32_t),
-                             hipMemcpyHostToDevice, s));
+    if (2 * valid < total) {
+      for (int v2 = n - 1; v2 >= 2; --v2) pfx2.push_back((uint32_t)v2);
+      if (max_dim >= 3)
+        for (int v2 = n - 2; v2 >= 2; --v2)
+          for (int v3 = v2 + 1; v3 < n; ++v3)
+            if (hW[(size_t)v3 * n + v2] != kInf) pfx3.push_back(((uint32_t)v3 << 16) | (uint32_t)v2);
+      HIP_TRY(c->pfx_v.ensure(std::max<size_t>(pfx2.size() + pfx3.size(), 1) * sizeof(uint32_t)));
+      if (!pfx2.empty())
+        HIP_TRY(hipMemcpyAsync(c->pfx_v.p, pfx2.data(), pfx2.size() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, s));
+      if (!pfx3.empty())
+        HIP_TRY(hipMemcpyAsync(c->pfx_v.as<uint32_t>() + pfx2.size(), pfx3.data(),
+                               pfx3.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     }
   }
+  // the listed prefixes of dimension d (empty: dense enumeration)
+  auto prefixes = [&](int d) -> const std::vector<uint32_t>& {
+    static const std::vector<uint32_t> none;
+    return d == 2 ? pfx2 : d == 3 ? pfx3 : none;
+  };
 
   std::unique_ptr<vrph_barcode> bc(new (std::nothrow) vrph_barcode());
   if (!bc) return fail(VRPH_ENOMEM, "out of host memory");
@@ -635,8 +647,10 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     const uint64_t ncand = H.C(n, d + 1);
     // the candidates the enumeration examines: all d-simplex indices, or,
     // over listed prefixes, the suffixes of the listed edges
+    const std::vector<uint32_t>& pfx = prefixes(d);
+    const uint32_t* const pfx_dev = c->pfx_v.as<uint32_t>() + (d == 3 ? pfx2.size() : 0);
     uint64_t examined = ncand;
-    if (d == 3 && !pfx.empty()) {
+    if (!pfx.empty()) {
       examined = 0;
       for (uint32_t pv : pfx) {
         const uint64_t v2 = pv & 0xFFFFu;
@@ -695,14 +709,14 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       // dimension 3 over a sparse edge set: list the prefixes (edges) instead
       PrefixList pl{nullptr, nullptr, 0};
       uint64_t units = 0;
-      if (d == 3 && !pfx.empty()) {
+      if (!pfx.empty()) {
         units = listed_units(pfx, c->h_pfx_cum);
         hipError_t e2 = c->pfx_cum.ensure(c->h_pfx_cum.size() * sizeof(uint64_t));
         if (e2 != hipSuccess) return e2;
         e2 = hipMemcpyAsync(c->pfx_cum.p, c->h_pfx_cum.data(),
                             c->h_pfx_cum.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s);
         if (e2 != hipSuccess) return e2;
-        pl = PrefixList{c->pfx_cum.as<uint64_t>(), c->pfx_v.as<uint32_t>(), (uint32_t)pfx.size()};
+        pl = PrefixList{c->pfx_cum.as<uint64_t>(), pfx_dev, (uint32_t)pfx.size()};
       } else {
         units = enum_units(n, d, t.chunk, c->h_binom, c->h_units);
       }
@@ -791,7 +805,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       // unit sizes that would give far more units than the default are not
       // tried: each unit costs a decode even where its prefix is skipped
       std::vector<uint64_t> scratch;
-      const bool listed = d == 3 && !pfx.empty();  // unit size has no effect then
+      const bool listed = !pfx.empty();  // unit size has no effect then
       auto units_for = [&](int chunk) -> uint64_t {
         return listed ? listed_units(pfx, scratch) : enum_units(n, d, chunk, c->h_binom, scratch);
       };
@@ -868,7 +882,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     bc->stats.cofacets[d] = (int64_t)sc.scan_steps;
     bc->stats.facets[d] = (int64_t)sc.facet_steps;
     // over listed prefixes the kernel counts the suffixes it enumerated
-    bc->stats.candidates[d] = d == 3 && !pfx.empty() ? (int64_t)sc.candidates : (int64_t)examined;
+    bc->stats.candidates[d] = !pfx.empty() ? (int64_t)sc.candidates : (int64_t)examined;
     bc->stats.columns[d] = (int64_t)sc.columns;
     bc->stats.apparent[d] = (int64_t)sc.apparent;
     bc->stats.reduced[d] = nna;

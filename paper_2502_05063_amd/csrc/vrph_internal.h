@@ -111,12 +111,13 @@ struct ClearSet {
   uint32_t* overflow;
 };
 
-// The prefixes of a dimension-3 enumeration listed explicitly: the edges
-// (v_3 > v_2) within the threshold, packed v_3 << 16 | v_2, with cum[p] the
-// work units of the prefixes before p (cum has count + 1 entries). Used where
-// most vertex pairs are not edges, so that no unit is spent on a prefix that
-// spans no simplex. v == nullptr: every prefix, numbered as in the dense
-// unit table.
+// The prefixes of a dimension-3 (or 2) enumeration listed explicitly: the
+// edges (v_3 > v_2) within the threshold packed v_3 << 16 | v_2 (or the
+// vertices v_2), with cum[p] the work units of the prefixes before p (cum has
+// count + 1 entries). Used where most vertex pairs are not edges: the
+// global-memory kernel then enumerates each prefix's suffixes over common
+// neighbours. v == nullptr: every prefix, numbered as in the dense unit
+// table.
 struct PrefixList {
   const uint64_t* cum;
   const uint32_t* v;
