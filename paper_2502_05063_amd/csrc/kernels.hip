@@ -708,6 +708,35 @@ __device__ __forceinline__ int apparent_cofacet_lds(const LdsRows& rows, int n,
   return no_equal_facet_below<D>(rows, v, found, pw, diam, facets) ? found : -1;
 }
 
+// The same test in neighbour mode: condition 1 walks the prefix's common
+// neighbours nb[0..count) from the top instead of every x from n-1 down (a
+// vertex outside them keeps no diameter). The walk is in lockstep across the
+// lanes, so nb[i] and its row are the same for the whole wave; the lane's own
+// vertices are skipped. The cofacets counted are those of the definition, as
+// in the full scan.
+template <int D, class Rows>
+__device__ __forceinline__ int apparent_cofacet_nb(const Rows& rows, int n, const int (&v)[D + 1],
+                                                   const uint32_t (&pw)[D + 1][D + 1],
+                                                   uint32_t diam, const uint16_t* nb,
+                                                   uint32_t count, uint32_t& steps,
+                                                   uint32_t& facets) {
+  int found = -1;
+  for (int i = (int)count - 1; i >= 0 && found < 0; --i) {
+    const int x = nb[i];
+    if (x == v[0] || x == v[1]) continue;
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j <= D; ++j) m = max(m, rows.row_at(x, v[j]));
+    if (m <= diam) found = x;
+  }
+  int above = 0;
+#pragma unroll
+  for (int i = 0; i <= D; ++i) above += v[i] > found;
+  steps += (uint32_t)(found >= 0 ? n - found - above : n - (D + 1));
+  if (found < 0) return -1;
+  return no_equal_facet_below<D>(rows, v, found, pw, diam, facets) ? found : -1;
+}
+
 // Index of the cofacet s + {x} (Eq. 5.6): vertices above x move up one position.
 template <int D>
 __device__ __forceinline__ uint64_t cofacet_index(const int (&v)[D + 1], int x,
@@ -963,22 +992,27 @@ __device__ __forceinline__ void enum_units(
   uint32_t u_steps = 0, u_facets = 0;
 
   // Neighbour mode (listed prefixes of dimension 2 or 3 in the
-  // global-memory kernel, Sec. 5.3.13): the suffixes (v1 > v0) of a prefix
-  // (v3, v2), or (v2), that can span a simplex are the pairs of common
-  // neighbours of the prefix vertices below v2. The workgroup lists them in
-  // LDS in increasing order, and suffix k below is then the k-th pair
-  // (i > j) of that list instead of the k-th pair of all vertices below v2.
+  // global-memory kernel, Sec. 5.3.12-5.3.13): the suffixes (v1 > v0) of a
+  // prefix (v3, v2), or (v2), that can span a simplex are the pairs of
+  // common neighbours of the prefix vertices below v2. The workgroup lists
+  // the common neighbours in LDS in increasing order, and suffix k below is
+  // then the k-th pair (i > j) of those below v2 instead of the k-th pair of
+  // all vertices below v2.
   constexpr bool kNeighbours = (D == 2 || D == 3) && !__is_same(Rows, LdsRows);
+  // The list holds every common neighbour (below and above v2), so that the
+  // cofacet scan can walk it too: a vertex outside it is not a neighbour of
+  // some vertex of s, so no cofacet with it keeps the diameter.
   const uint16_t* nb = nullptr;
+  uint32_t nb_all = 0;  // common neighbours; the first nb_below are below v2
   if constexpr (kNeighbours) {
     if (listed) {
       __shared__ uint16_t cn[kMaxN];
       __shared__ uint32_t wcount[BS / 64];
       const int wave = (int)(threadIdx.x >> 6), l64 = (int)(threadIdx.x & 63);
       uint32_t cnt = 0;
-      for (int x0 = 0; x0 < v[2]; x0 += BS) {
+      for (int x0 = 0; x0 < n; x0 += BS) {
         const int x = x0 + (int)threadIdx.x;
-        bool in = x < v[2] && rows.row_at(v[2], x) != kInfW;
+        bool in = x < n && rows.row_at(v[2], x) != kInfW;  // the diagonal is kInf
         if constexpr (D == 3) in = in && rows.row_at(v[3], x) != kInfW;
         const unsigned long long m = __ballot(in);
         if (l64 == 0) wcount[wave] = (uint32_t)__popcll(m);
@@ -992,9 +1026,19 @@ __device__ __forceinline__ void enum_units(
         cnt += all;
         __syncthreads();
       }
+      // the list is increasing: its entries below v2 come first
+      uint32_t lo = 0, hi = cnt;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (cn[mid] < v[2])
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
       nb = cn;
+      nb_all = cnt;
       k_begin = 0;
-      k_end = (uint64_t)cnt * (cnt - 1) / 2;
+      k_end = (uint64_t)lo * (lo - 1) / 2;  // pairs of the neighbours below v2
       if (threadIdx.x == 0) n_cand += k_end;
     }
   }
@@ -1067,6 +1111,8 @@ __device__ __forceinline__ void enum_units(
         int x;
         if constexpr (__is_same(Rows, LdsRows))
           x = apparent_cofacet_lds<D>(rows, n, vv, pw, diam, u_steps, u_facets);
+        else if (nb)
+          x = apparent_cofacet_nb<D>(rows, n, vv, pw, diam, nb, nb_all, u_steps, u_facets);
         else
           x = apparent_cofacet<D>(rows, n, vv, pw, diam, u_steps, u_facets);
         if (x >= 0) {
