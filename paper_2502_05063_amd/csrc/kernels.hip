@@ -890,18 +890,26 @@ __device__ __forceinline__ void add_block_counters(unsigned long long (&v)[N],
 // dimension d+1, counts, and optionally every apparent pair.
 // ---------------------------------------------------------------------------
 
-template <int D, int BS, int UL, class Rows>
+// Kernel variants (Mode bits): kModeHashed when a clearing set is hashed
+// (the bitmap variant keeps the probe loops out of its hot loop),
+// kModeListed when the units are listed prefixes (dimensions 2 and 3 only).
+constexpr int kModeHashed = 1, kModeListed = 2;
+
+template <int D, int BS, int UL, int Mode, class Rows>
 __device__ __forceinline__ void enum_units(
     const Rows& rows, int n, const uint64_t* __restrict__ binom, int chunk,
     const uint64_t* __restrict__ unit_cum, uint64_t units, const PrefixList& pl,
     const ClearSet& clear_in, const ClearSet& clear_out, const ColumnSink& sink,
     const PairSink& aps, Scalars* __restrict__ sc) {
   constexpr uint32_t kInfW = Rows::kInfV;
+  constexpr bool kHashed = (Mode & kModeHashed) != 0;
+  constexpr bool kListed = (Mode & kModeListed) != 0;
+  static_assert(!kListed || D == 2 || D == 3, "listed prefixes are pairs or single vertices");
   const int np1 = n + 1;
   auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
   unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0, n_cand = 0;
   DeferredAppend pend;
-  const bool need_t = clear_out.bits || clear_out.keys || aps.recs;
+  const bool need_t = clear_out.bits || (kHashed && clear_out.keys) || aps.recs;
   const int bucket = (int)((blockIdx.x * (BS / 64) +
                             (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))) %
                            kSinkBuckets);
@@ -925,8 +933,8 @@ __device__ __forceinline__ void enum_units(
   int v[D + 1];
   uint64_t k_begin = 0, k_end = 0;
   bool listed = false;
-  if constexpr (D == 2 || D == 3) {
-    if (pl.v) {  // listed prefixes: the p with cum[p] <= u < cum[p+1]
+  if constexpr (kListed) {
+    {  // listed prefixes: the p with cum[p] <= u < cum[p+1]
       listed = true;
       uint32_t lo = 0, hi = pl.count - 1;
       while (lo < hi) {
@@ -998,7 +1006,7 @@ __device__ __forceinline__ void enum_units(
   // the common neighbours in LDS in increasing order, and suffix k below is
   // then the k-th pair (i > j) of those below v2 instead of the k-th pair of
   // all vertices below v2.
-  constexpr bool kNeighbours = (D == 2 || D == 3) && !__is_same(Rows, LdsRows);
+  constexpr bool kNeighbours = kListed && !__is_same(Rows, LdsRows);
   // The list holds every common neighbour (below and above v2), so that the
   // cofacet scan can walk it too: a vertex outside it is not a neighbour of
   // some vertex of s, so no cofacet with it keeps the diameter.
@@ -1047,7 +1055,7 @@ __device__ __forceinline__ void enum_units(
   // so their latency overlaps the current candidate's work (dense suffixes
   // only: in neighbour mode consecutive k are not consecutive indices)
   uint32_t cw_next = 0;
-  const uint32_t* __restrict__ clear_bits = nb ? nullptr : clear_in.bits;
+  const uint32_t* __restrict__ clear_bits = kNeighbours ? nullptr : clear_in.bits;
   if (clear_bits && k_begin + lane < k_end) cw_next = clear_bits[(base + k_begin + lane) >> 5];
   for (uint64_t kb = k_begin; kb < k_end; kb += UL) {
     const uint64_t k = kb + lane;
@@ -1102,9 +1110,14 @@ __device__ __forceinline__ void enum_units(
       for (int i = 3; i <= D; ++i)
 #pragma unroll
         for (int j = 2; j < i; ++j) pw[i][j] = rows.row_at(vv[i], vv[j]);
-      // a hashed set is probed only for simplices of the complex
-      const bool cleared =
-          clear_bits ? ((cw >> (c & 31)) & 1u) : (diam != kInfW && clear_contains(clear_in, c));
+      // a hashed set (or a bitmap in neighbour mode) is probed only for
+      // simplices of the complex
+      bool cleared;
+      if constexpr (kHashed || kNeighbours)
+        cleared = clear_bits ? ((cw >> (c & 31)) & 1u)
+                             : (diam != kInfW && clear_contains(clear_in, c));
+      else
+        cleared = (cw >> (c & 31)) & 1u;
       is_col = diam != kInfW && !cleared;
       if (is_col) {
         ++n_cols;
@@ -1122,7 +1135,10 @@ __device__ __forceinline__ void enum_units(
           // dimension or to report the pair
           if (need_t) {
             tcidx = cofacet_index<D>(vv, x, binom, np1);
-            clear_insert(clear_out, tcidx);
+            if constexpr (kHashed)
+              clear_insert(clear_out, tcidx);
+            else if (clear_out.bits)
+              atomicOr(&clear_out.bits[tcidx >> 5], 1u << (tcidx & 31));
           }
         }
       }
@@ -1160,14 +1176,14 @@ __device__ __forceinline__ void enum_units(
 }
 
 // 8 waves per SIMD (64 vector, 96 scalar registers) for D <= 3
-template <int D>
+template <int D, int Mode>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D <= 3 ? 8 : 4)))
 void enum_apparent_kernel(
     const uint32_t* __restrict__ W, int n, const uint64_t* __restrict__ binom, int chunk,
     const uint64_t* __restrict__ unit_cum, uint64_t units, PrefixList pl, ClearSet clear_in,
     ClearSet clear_out, ColumnSink sink, PairSink aps, Scalars* __restrict__ sc) {
   const BufferRows rows(W, n);
-  enum_units<D, kBlock, kBlock>(rows, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out,
+  enum_units<D, kBlock, kBlock, Mode>(rows, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out,
                                 sink, aps, sc);
 }
 
@@ -1177,7 +1193,7 @@ void enum_apparent_kernel(
 // only at 8 waves per SIMD, which caps a wave at 64 vector and 96 scalar
 // registers; the compiler is held to that for D <= 3 (above, the registers
 // a wave needs leave room for one workgroup per compute unit).
-template <int D>
+template <int D, int Mode>
 __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(D <= 3 ? 8 : 4)))
 void enum_apparent_lds_kernel(
     const uint16_t* __restrict__ Wr, const uint32_t* __restrict__ rank_bits, int n,
@@ -1191,7 +1207,7 @@ void enum_apparent_lds_kernel(
   for (int i = threadIdx.x; i < words; i += kLdsBlock) sw[i] = src[i];
   __syncthreads();
   const LdsRows rows{reinterpret_cast<const uint16_t*>(sw), n, stride, rank_bits};
-  enum_units<D, kLdsBlock, 64>(rows, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out,
+  enum_units<D, kLdsBlock, 64, Mode>(rows, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out,
                                sink, aps, sc);
 }
 
@@ -1200,8 +1216,26 @@ static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom,
                                 const uint64_t* unit_cum, uint64_t units, PrefixList pl,
                                 unsigned grid, ClearSet clear_in, ClearSet clear_out,
                                 ColumnSink sink, PairSink aps, Scalars* sc, hipStream_t s) {
-  enum_apparent_kernel<D><<<grid, kBlock, 0, s>>>(W, n, binom, chunk, unit_cum, units, pl,
-                                                  clear_in, clear_out, sink, aps, sc);
+  const bool hashed = clear_in.keys || clear_out.keys;
+  if constexpr (D == 2 || D == 3) {
+    if (pl.v) {
+      if (hashed)
+        enum_apparent_kernel<D, kModeListed | kModeHashed><<<grid, kBlock, 0, s>>>(
+            W, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out, sink, aps, sc);
+      else
+        enum_apparent_kernel<D, kModeListed><<<grid, kBlock, 0, s>>>(
+            W, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out, sink, aps, sc);
+      return hipGetLastError();
+    }
+  } else {
+    if (pl.v) return hipErrorInvalidValue;  // prefixes are listed for d = 2, 3 only
+  }
+  if (hashed)
+    enum_apparent_kernel<D, kModeHashed><<<grid, kBlock, 0, s>>>(
+        W, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out, sink, aps, sc);
+  else
+    enum_apparent_kernel<D, 0><<<grid, kBlock, 0, s>>>(W, n, binom, chunk, unit_cum, units, pl,
+                                                       clear_in, clear_out, sink, aps, sc);
   return hipGetLastError();
 }
 
@@ -1211,9 +1245,13 @@ static hipError_t launch_enum_lds_D(const uint16_t* Wr, const uint32_t* rank_bit
                                     uint64_t units, PrefixList pl, unsigned grid,
                                     ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
                                     PairSink aps, Scalars* sc, hipStream_t s) {
-  enum_apparent_lds_kernel<D><<<grid, kLdsBlock, 0, s>>>(Wr, rank_bits, n, binom, chunk, unit_cum,
-                                                         units, pl, clear_in, clear_out, sink,
-                                                         aps, sc);
+  if (pl.v) return hipErrorInvalidValue;  // the LDS kernel takes dense unit tables only
+  if (clear_in.keys || clear_out.keys)
+    enum_apparent_lds_kernel<D, kModeHashed><<<grid, kLdsBlock, 0, s>>>(
+        Wr, rank_bits, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out, sink, aps, sc);
+  else
+    enum_apparent_lds_kernel<D, 0><<<grid, kLdsBlock, 0, s>>>(
+        Wr, rank_bits, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out, sink, aps, sc);
   return hipGetLastError();
 }
 
