@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <memory>
 #include <thread>
 
 namespace vrph {
@@ -220,22 +222,50 @@ static bool apparent_partner(const HostComplex& H, uint64_t t, uint32_t rt, int 
   return true;
 }
 
-// A column in the pivot store: its simplex and, for a column reduced here,
-// the other columns whose sum with it is its reduced column (the V column of
-// the reduction-matrix technique, R = D V, Sec. 5.2.9). Apparent columns and
-// columns paired at their first pivot need no additions: their reduced column
-// is their coboundary (v = -1).
-struct Partner {
-  uint64_t c;
-  uint32_t r;  // diameter rank
-  int32_t v;   // index into the stored V columns, -1 for none
-};
-
 struct Simplex {
   uint64_t c;
   uint32_t r;
   bool operator<(const Simplex& o) const { return c < o.c; }
   bool operator==(const Simplex& o) const { return c == o.c; }
+};
+
+// A column in the pivot store: its simplex and, for a column reduced here,
+// the other columns whose sum with it is its reduced column (the V column of
+// the reduction-matrix technique, R = D V, Sec. 5.2.9), stored elsewhere.
+// Apparent columns and columns paired at their first pivot need no
+// additions: their reduced column is their coboundary (vlen = 0).
+struct Partner {
+  uint64_t c;
+  uint32_t r;     // diameter rank
+  uint32_t vlen;  // length of the V column
+  const Simplex* v;
+};
+
+// Append-only storage of V columns: chunks never move, so a column stored
+// by one thread can be read by others once published.
+class VArena {
+ public:
+  const Simplex* put(const Simplex* src, size_t len) {
+    Simplex* dst;
+    if (len > kChunk / 4) {
+      big_.emplace_back(new Simplex[len]);
+      dst = big_.back().get();
+    } else {
+      if (chunks_.empty() || used_ + len > kChunk) {
+        chunks_.emplace_back(new Simplex[kChunk]);
+        used_ = 0;
+      }
+      dst = chunks_.back().get() + used_;
+      used_ += len;
+    }
+    std::copy(src, src + len, dst);
+    return dst;
+  }
+
+ private:
+  static constexpr size_t kChunk = 1 << 16;
+  std::vector<std::unique_ptr<Simplex[]>> chunks_, big_;
+  size_t used_ = 0;
 };
 
 // Row keys: a row (rank r, index c) is the integer (r << cbits) | (cmax - c),
@@ -249,6 +279,15 @@ struct Keys {
   K make(uint32_t r, uint64_t c) const { return ((K)r << cbits) | (cmax - (K)c); }
   uint32_t rank(K k) const { return (uint32_t)(k >> cbits); }
   uint64_t index(K k) const { return (uint64_t)(cmax - (k & cmax)); }
+  // a 64-bit key that never decreases as the key grows: the key itself, or
+  // its top 64 bits when it is wider (then rank << 32 and the top 32 bits of
+  // the index part; cbits >= 32 there since a rank has at most 32 bits)
+  uint64_t coarse(K k) const {
+    if constexpr (sizeof(K) == 8)
+      return (uint64_t)k;
+    else
+      return (uint64_t)(k >> (cbits - 32));
+  }
 };
 
 // A vector that grows without zero-filling (default-initialised elements):
@@ -461,9 +500,12 @@ static void push_coboundary(const HostComplex& H, const Keys<K>& ks, const int* 
     if (reach[x] != kInf && kb[x] >= limit) w.push(kb[x]);
 }
 
-// Row index -> column of this dimension's reduced pivots: open addressing
-// with linear probing at load <= 1/2 (a row index is < 2^63, so ~0 marks an
-// empty slot).
+// Row index -> column of this dimension's reduced pivots, shared by the
+// reduction threads: open addressing with linear probing at load <= 1/2 (a
+// row index is < 2^63, so ~0 and ~1 are free to mark an empty slot and one
+// being filled). An inserter claims an empty slot, writes the value, then
+// publishes the key (release); a reader that meets a slot being filled waits
+// for it. Entries are never removed.
 class PivotTable {
  public:
   explicit PivotTable(size_t n) {
@@ -473,29 +515,43 @@ class PivotTable {
       cap <<= 1;
       ++bits;
     }
-    keys_.assign(cap, kEmpty);
-    vals_.resize(cap);
+    keys_.reset(new std::atomic<uint64_t>[cap]);
+    for (size_t i = 0; i < cap; ++i) keys_[i].store(kEmpty, std::memory_order_relaxed);
+    vals_.reset(new Partner[cap]);
     mask_ = cap - 1;
     shift_ = 64 - bits;
   }
-  const Partner* find(uint64_t k) const {
+  bool find(uint64_t k, Partner* out) const {
     for (size_t i = slot(k);; i = (i + 1) & mask_) {
-      if (keys_[i] == k) return &vals_[i];
-      if (keys_[i] == kEmpty) return nullptr;
+      uint64_t s = keys_[i].load(std::memory_order_acquire);
+      while (s == kBusy) {
+        std::this_thread::yield();
+        s = keys_[i].load(std::memory_order_acquire);
+      }
+      if (s == k) {
+        *out = vals_[i];
+        return true;
+      }
+      if (s == kEmpty) return false;
     }
   }
   void insert(uint64_t k, const Partner& p) {
-    size_t i = slot(k);
-    while (keys_[i] != kEmpty) i = (i + 1) & mask_;
-    keys_[i] = k;
-    vals_[i] = p;
+    for (size_t i = slot(k);; i = (i + 1) & mask_) {
+      uint64_t e = kEmpty;
+      if (keys_[i].load(std::memory_order_relaxed) == kEmpty &&
+          keys_[i].compare_exchange_strong(e, kBusy, std::memory_order_acq_rel)) {
+        vals_[i] = p;
+        keys_[i].store(k, std::memory_order_release);
+        return;
+      }
+    }
   }
 
  private:
-  static constexpr uint64_t kEmpty = ~0ull;
+  static constexpr uint64_t kEmpty = ~0ull, kBusy = ~0ull - 1;
   size_t slot(uint64_t k) const { return (size_t)((k * 0x9E3779B97F4A7C15ull) >> shift_); }
-  std::vector<uint64_t> keys_;
-  std::vector<Partner> vals_;
+  std::unique_ptr<std::atomic<uint64_t>[]> keys_;
+  std::unique_ptr<Partner[]> vals_;
   size_t mask_ = 0;
   int shift_ = 0;
 };
@@ -576,105 +632,265 @@ static void pre_reduce(const HostComplex& H, const Keys<K>& ks, int d, const Col
   *additions += adds.load();
 }
 
+// The columns that the apparent chains leave with a pivot taken by another
+// column are reduced on `threads` threads at once, with the same result as
+// the column-by-column pass of Alg. 2. Column j adds R_k whenever its pivot
+// is the pivot of an earlier column k; it may stop at a pivot l only once no
+// earlier column can still end at l. A column's pivot only gets younger
+// while it is reduced (its key only grows), so an earlier column whose
+// current pivot key is above l's can no longer end at l, and a finished one
+// has its pivot in the table. Each thread publishes the column it holds and
+// that column's current pivot key (coarsened to 64 bits, which only makes
+// the test more cautious). Columns are taken in order, under a lock that
+// also publishes the new column, so every earlier column that is not
+// finished is held by a thread. Column j waits while an earlier held
+// column's key is <= l's, then looks l up again (a finished column's pivot
+// is in the table before its thread takes another column). The earliest
+// unfinished column never waits, so the pass always progresses; the
+// additions each column makes are exactly those of the sequential pass. A
+// finished column's V column is stored before its pivot is published, so a
+// column found in the table can be added at once.
+// The bookkeeping costs a few hundred nanoseconds per column and waits are
+// common among columns of equal diameter, so the pass runs in blocks: a
+// block goes to all threads only when the columns of the block before took
+// more than kParallelNs each on one thread (long columns: many additions,
+// or large coboundaries), and wide blocks continue while their columns stay
+// that long and the threads' busy time (their time outside waits) is at
+// least kMinSpeedup times the block's wall time.
 template <class K>
 static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Column* cols,
                         int64_t ncols, int threads, std::vector<PairRec>& pairs,
                         std::vector<uint64_t>& deaths, ReduceStats& stats) {
   PivotTable pivots((size_t)ncols);
-  std::vector<std::vector<Simplex>> vstore;  // V columns of the reduced columns
-  WorkColumn<K> work(ks);
-  std::vector<Simplex> vj;
-  std::vector<uint32_t> reach((size_t)H.n), areach((size_t)H.n);
-  std::vector<K> kb((size_t)H.n);
-  int sv[kMaxDim + 3], pv[kMaxDim + 3];
   std::vector<PreReduced> pre;
   std::vector<std::vector<Simplex>> chain_v;
   pre_reduce(H, ks, d, cols, ncols, threads, pre, chain_v, &stats.additions);
 
-  for (int64_t j = 0; j < ncols; ++j) {
-    const uint64_t c = cols[j].cidx;
-    const PreReduced& f = pre[(size_t)j];
-    const Simplex* chain = chain_v[(size_t)(j / kChunk)].data() + f.voff;
-    const uint32_t dr = f.dr;
-    uint32_t lr = f.lr;
-    uint64_t lc = f.lc;
-    bool nonzero = f.nonzero;
-    vj.assign(chain, chain + f.vcount);
-    const Partner* q = nonzero ? pivots.find(lc) : nullptr;
-    if (q) {
-      // Alg. 2 on column j, continued: while its pivot is the pivot of an
-      // earlier column k, add R_k = D_k + sum_{i in V_k} D_i (the pivot then
-      // moves up). Lookups are two-layer (Fig. 5.10): pairs found by this
-      // reduction first, then the apparent pairs, recognised from Def. 5.3.4
-      // instead of a stored array. The working column restarts from the
-      // column and the apparent columns its chain added.
-      Partner p = *q;
-      bool pv_known = false;  // pv holds the vertices of p.c
-      K low = ks.make(lr, lc);
-      work.clear();
-      decode_simplex(H, c, d, sv);
-      push_coboundary(H, ks, sv, c, dr, d, low, work, reach.data(), false, kb.data());
-      for (uint32_t i = 0; i < f.vcount; ++i) {
-        decode_simplex(H, chain[i].c, d, sv);
-        push_coboundary(H, ks, sv, chain[i].c, chain[i].r, d, low, work, reach.data(), false,
-                        kb.data());
+  // column j's pair goes to pairs[first + j]
+  const size_t first = pairs.size();
+  pairs.resize(first + (size_t)ncols);
+
+  threads = std::max(threads, 1);
+  // per thread: the column it holds (-1: none) and that column's current
+  // pivot key, coarsened
+  std::unique_ptr<std::atomic<int64_t>[]> held_col(new std::atomic<int64_t>[threads]);
+  std::unique_ptr<std::atomic<uint64_t>[]> held_key(new std::atomic<uint64_t>[threads]);
+  for (int t = 0; t < threads; ++t) {
+    held_col[t].store(-1, std::memory_order_relaxed);
+    held_key[t].store(0, std::memory_order_relaxed);
+  }
+  std::atomic_flag take_lock = ATOMIC_FLAG_INIT;
+  int64_t next = 0, end = 0;
+  int nthr = 1;  // threads of the current block
+  std::atomic<int64_t> adds{0}, emergent{0}, busy_ns{0};
+  // waits that last: a few yields, then short sleeps, so that waiting
+  // threads leave the cores to the columns they wait for
+  auto backoff = [](int& spins) {
+    if (++spins < 64)
+      std::this_thread::yield();
+    else
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+  };
+
+  // per-thread scratch, kept across blocks
+  struct Scratch {
+    WorkColumn<K> work;
+    std::vector<Simplex> vj, red;
+    VArena arena;
+    std::vector<uint32_t> reach, areach;
+    std::vector<K> kb;
+    Scratch(const Keys<K>& k, int n) : work(k), reach((size_t)n), areach((size_t)n), kb((size_t)n) {}
+  };
+  std::vector<std::unique_ptr<Scratch>> scratch((size_t)threads);
+  auto worker = [&](int self) {
+    const auto w0 = std::chrono::steady_clock::now();
+    double waited = 0;
+    if (!scratch[(size_t)self]) scratch[(size_t)self].reset(new Scratch(ks, H.n));
+    Scratch& sc = *scratch[(size_t)self];
+    WorkColumn<K>& work = sc.work;
+    std::vector<Simplex>& vj = sc.vj;
+    std::vector<Simplex>& red = sc.red;
+    std::vector<uint32_t>& reach = sc.reach;
+    std::vector<uint32_t>& areach = sc.areach;
+    std::vector<K>& kb = sc.kb;
+    int sv[kMaxDim + 3], pv[kMaxDim + 3];
+    int64_t local_adds = 0, local_emergent = 0;
+    // returns once no earlier column held by another thread can still end
+    // at row l (key coarsened to lq)
+    auto settle = [&](int64_t j, uint64_t lq) {
+      for (int t = 0; t < nthr; ++t) {
+        if (t == self) continue;
+        std::chrono::steady_clock::time_point s0;
+        for (int spins = 0;; backoff(spins)) {
+          const int64_t k = held_col[t].load(std::memory_order_acquire);
+          if (k < 0 || k >= j || held_key[t].load(std::memory_order_acquire) > lq) {
+            if (spins > 0)
+              waited += std::chrono::duration<double, std::nano>(
+                            std::chrono::steady_clock::now() - s0).count();
+            break;
+          }
+          if (spins == 0) s0 = std::chrono::steady_clock::now();
+        }
       }
-      for (;;) {
-        if (!pv_known) decode_simplex(H, p.c, d, pv);
-        if (pv_known)  // its reach row came with the lookup
-          push_coboundary(H, ks, pv, p.c, p.r, d, low, work, areach.data(), true, kb.data());
-        else
-          push_coboundary(H, ks, pv, p.c, p.r, d, low, work, reach.data(), false, kb.data());
-        vj.push_back(Simplex{p.c, p.r});
-        if (p.v >= 0)
-          for (const Simplex& r : vstore[p.v]) {
+    };
+    for (;;) {
+      int64_t j;
+      if (nthr == 1) {  // alone: nothing to publish
+        if (next >= end) break;
+        j = next++;
+      } else {
+        for (int spins = 0; take_lock.test_and_set(std::memory_order_acquire); backoff(spins)) {
+        }
+        if (next >= end) {
+          take_lock.clear(std::memory_order_release);
+          break;
+        }
+        j = next++;
+        held_key[self].store(ks.coarse(ks.make(pre[(size_t)j].lr, pre[(size_t)j].lc)),
+                             std::memory_order_release);
+        held_col[self].store(j, std::memory_order_release);
+        take_lock.clear(std::memory_order_release);
+      }
+      const uint64_t c = cols[j].cidx;
+      const PreReduced& f = pre[(size_t)j];
+      const Simplex* chain = chain_v[(size_t)(j / kChunk)].data() + f.voff;
+      const uint32_t dr = f.dr;
+      uint32_t lr = f.lr;
+      uint64_t lc = f.lc;
+      bool nonzero = f.nonzero;
+      vj.assign(chain, chain + f.vcount);
+      Partner p{};
+      bool have_p = false;
+      if (nonzero) {
+        have_p = pivots.find(lc, &p);
+        if (!have_p) {
+          settle(j, ks.coarse(ks.make(lr, lc)));
+          have_p = pivots.find(lc, &p);
+        }
+      }
+      if (have_p) {
+        // Alg. 2 on column j, continued: while its pivot is the pivot of an
+        // earlier column k, add R_k = D_k + sum_{i in V_k} D_i (the pivot
+        // then moves up). Lookups are two-layer (Fig. 5.10): pairs found by
+        // this reduction first, then the apparent pairs, recognised from
+        // Def. 5.3.4 instead of a stored array. The working column restarts
+        // from the column and the apparent columns its chain added.
+        bool pv_known = false;  // pv holds the vertices of p.c
+        K low = ks.make(lr, lc);
+        work.clear();
+        decode_simplex(H, c, d, sv);
+        push_coboundary(H, ks, sv, c, dr, d, low, work, reach.data(), false, kb.data());
+        for (uint32_t i = 0; i < f.vcount; ++i) {
+          decode_simplex(H, chain[i].c, d, sv);
+          push_coboundary(H, ks, sv, chain[i].c, chain[i].r, d, low, work, reach.data(), false,
+                          kb.data());
+        }
+        for (;;) {
+          if (!pv_known) decode_simplex(H, p.c, d, pv);
+          if (pv_known)  // its reach row came with the lookup
+            push_coboundary(H, ks, pv, p.c, p.r, d, low, work, areach.data(), true, kb.data());
+          else
+            push_coboundary(H, ks, pv, p.c, p.r, d, low, work, reach.data(), false, kb.data());
+          vj.push_back(Simplex{p.c, p.r});
+          for (uint32_t i = 0; i < p.vlen; ++i) {
+            const Simplex& r = p.v[i];
             decode_simplex(H, r.c, d, sv);
             push_coboundary(H, ks, sv, r.c, r.r, d, low, work, reach.data(), false, kb.data());
             vj.push_back(r);
           }
-        ++stats.additions;
-        if (!work.pivot(&low)) {
-          nonzero = false;
-          break;
+          ++local_adds;
+          if (!work.pivot(&low)) {
+            nonzero = false;
+            break;
+          }
+          lr = ks.rank(low);
+          lc = ks.index(low);
+          held_key[self].store(ks.coarse(low), std::memory_order_release);
+          if (pivots.find(lc, &p)) {
+            pv_known = false;
+          } else if (apparent_partner(H, lc, lr, d, &p.c, pv, areach.data())) {
+            p.r = lr;
+            p.vlen = 0;
+            pv_known = true;
+          } else {
+            settle(j, ks.coarse(low));
+            if (pivots.find(lc, &p))
+              pv_known = false;
+            else
+              break;
+          }
         }
-        lr = ks.rank(low);
-        lc = ks.index(low);
-        if (const Partner* q2 = pivots.find(lc)) {
-          p = *q2;
-          pv_known = false;
-        } else if (apparent_partner(H, lc, lr, d, &p.c, pv, areach.data())) {
-          p.r = lr;
-          p.v = -1;
-          pv_known = true;
-        } else {
-          break;
-        }
+      } else if (nonzero && f.vcount == 0) {
+        ++local_emergent;
       }
-    } else if (nonzero && f.vcount == 0) {
-      ++stats.emergent;
+      if (nonzero) {
+        Partner mine{c, dr, 0, nullptr};
+        if (!vj.empty()) {
+          // V over Z/2: a column added twice cancels
+          std::sort(vj.begin(), vj.end());
+          red.clear();
+          for (size_t a = 0; a < vj.size();) {
+            size_t b = a;
+            while (b < vj.size() && vj[b] == vj[a]) ++b;
+            if ((b - a) & 1) red.push_back(vj[a]);
+            a = b;
+          }
+          mine.vlen = (uint32_t)red.size();
+          mine.v = sc.arena.put(red.data(), red.size());
+        }
+        pivots.insert(lc, mine);
+        pairs[first + (size_t)j] = PairRec{c, lc, H.rank_bits[dr], H.rank_bits[lr]};
+      } else {
+        pairs[first + (size_t)j] = PairRec{c, ~0ull, H.rank_bits[dr], kInf};
+      }
     }
-    if (nonzero) {
-      int32_t vi = -1;
-      if (!vj.empty()) {
-        // V over Z/2: a column added twice cancels
-        std::sort(vj.begin(), vj.end());
-        std::vector<Simplex> red;
-        for (size_t a = 0; a < vj.size();) {
-          size_t b = a;
-          while (b < vj.size() && vj[b] == vj[a]) ++b;
-          if ((b - a) & 1) red.push_back(vj[a]);
-          a = b;
-        }
-        vi = (int32_t)vstore.size();
-        vstore.push_back(std::move(red));
+    held_col[self].store(-1, std::memory_order_release);
+    busy_ns += (int64_t)(std::chrono::duration<double, std::nano>(
+                             std::chrono::steady_clock::now() - w0).count() - waited);
+    adds += local_adds;
+    emergent += local_emergent;
+  };
+  constexpr double kParallelNs = 2000.0, kMinSpeedup = 2.0;
+  constexpr int64_t kProbeBlock = 256, kMaxNarrowBlock = 8192, kParallelBlock = 8192;
+  constexpr int kCooldown = 16;  // one-thread blocks after a wide one that did not pay
+  bool wide = false;
+  int cooldown = 0;
+  int64_t narrow_block = kProbeBlock;  // grows while the columns stay short
+  while (next < ncols) {
+    const int64_t j0 = next;
+    end = std::min<int64_t>(ncols, j0 + (wide ? kParallelBlock : narrow_block));
+    nthr = wide ? (int)std::min<int64_t>(threads, end - j0) : 1;
+    busy_ns = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthr; ++t) pool.emplace_back(worker, t);
+    worker(0);
+    for (std::thread& t : pool) t.join();
+    const double wall =
+        std::chrono::duration<double, std::nano>(std::chrono::steady_clock::now() - t0).count();
+    const double per_col = (double)busy_ns.load() / (double)(end - j0);
+    if (wide) {
+      if ((double)busy_ns.load() < kMinSpeedup * wall) {
+        wide = false;
+        cooldown = kCooldown;
+      } else {
+        wide = per_col > kParallelNs;
       }
-      pivots.insert(lc, Partner{c, dr, vi});
-      pairs.push_back(PairRec{c, lc, H.rank_bits[dr], H.rank_bits[lr]});
-      deaths.push_back(lc);
+      narrow_block = kProbeBlock;
     } else {
-      pairs.push_back(PairRec{c, ~0ull, H.rank_bits[dr], kInf});
+      narrow_block = per_col < 0.25 * kParallelNs ? std::min(2 * narrow_block, kMaxNarrowBlock)
+                                                  : kProbeBlock;
+      if (cooldown > 0)
+        --cooldown;
+      else
+        wide = threads > 1 && per_col > kParallelNs;
     }
   }
+  stats.additions += adds.load();
+  stats.emergent += emergent.load();
+
+  for (size_t i = first; i < pairs.size(); ++i)
+    if (pairs[i].death != ~0ull) deaths.push_back(pairs[i].death);
 }
 
 void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,
