@@ -223,8 +223,9 @@ def main():
         "reduced_per_dim": s0["reduced"],
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": (f"enum_apparent_lds_kernel<{d}>" if n <= LDS_MAX_N
-                                else f"enum_apparent_kernel<{d}>"), "kernel_ms": k_ms,
+                     # the variant with bitmap clearing sets and dense unit tables
+                     "kernel": (f"enum_apparent_lds_kernel<{d}, 0>" if n <= LDS_MAX_N
+                                else f"enum_apparent_kernel<{d}, 0>"), "kernel_ms": k_ms,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "grid_workgroups": s0["grid"][d],
                      "measured_gbs": (traffic / (k_ms / 1e3) / 1e9) if traffic else None,
