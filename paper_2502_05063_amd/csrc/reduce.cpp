@@ -660,7 +660,7 @@ static void pre_reduce(const HostComplex& H, const Keys<K>& ks, int d, const Col
 template <class K>
 static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Column* cols,
                         int64_t ncols, int threads, std::vector<PairRec>& pairs,
-                        std::vector<uint64_t>& deaths, ReduceStats& stats) {
+                        std::vector<uint64_t>& deaths, ReduceStats& stats, bool always_wide) {
   PivotTable pivots((size_t)ncols);
   std::vector<PreReduced> pre;
   std::vector<std::vector<Simplex>> chain_v;
@@ -853,7 +853,7 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
   constexpr double kParallelNs = 2000.0, kMinSpeedup = 2.0;
   constexpr int64_t kProbeBlock = 256, kMaxNarrowBlock = 8192, kParallelBlock = 8192;
   constexpr int kCooldown = 16;  // one-thread blocks after a wide one that did not pay
-  bool wide = false;
+  bool wide = always_wide && threads > 1;
   int cooldown = 0;
   int64_t narrow_block = kProbeBlock;  // grows while the columns stay short
   while (next < ncols) {
@@ -869,7 +869,9 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
     const double wall =
         std::chrono::duration<double, std::nano>(std::chrono::steady_clock::now() - t0).count();
     const double per_col = (double)busy_ns.load() / (double)(end - j0);
-    if (wide) {
+    if (always_wide) {
+      wide = threads > 1;
+    } else if (wide) {
       if ((double)busy_ns.load() < kMinSpeedup * wall) {
         wide = false;
         cooldown = kCooldown;
@@ -895,7 +897,7 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
 
 void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,
                       int threads, std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
-                      ReduceStats& stats) {
+                      ReduceStats& stats, bool always_wide) {
   if (ncols == 0) return;
   // bits of the largest cofacet index C(n, d+2) - 1 and of the largest rank
   const uint64_t top = H.C(H.n, d + 2);
@@ -906,9 +908,10 @@ void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t n
   const u128 cmax = cbits == 64 ? (u128)~0ull : (((u128)1 << cbits) - 1);
   if (rbits + cbits <= 64)
     reduce_keys<uint64_t>(H, Keys<uint64_t>{cbits, (uint64_t)cmax}, d, cols, ncols, threads,
-                          pairs, deaths, stats);
+                          pairs, deaths, stats, always_wide);
   else
-    reduce_keys<u128>(H, Keys<u128>{cbits, cmax}, d, cols, ncols, threads, pairs, deaths, stats);
+    reduce_keys<u128>(H, Keys<u128>{cbits, cmax}, d, cols, ncols, threads, pairs, deaths, stats,
+                      always_wide);
 }
 
 // Dense ranks of the finite weights: the finite upper-triangle entries are

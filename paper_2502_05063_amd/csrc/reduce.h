@@ -71,14 +71,18 @@ struct ReduceStats {
 // pairs, recognised on the fly from Def. 5.3.4 instead of a stored array.
 // While a column's pivot is the cofacet of an apparent pair, the addition it
 // makes depends on no other non-apparent column; every column follows that
-// chain on its own, on `threads` host threads, before the sequential pass,
-// which continues only the columns whose pivot an earlier column already
-// took. A column whose first pivot is free is paired without building it
-// (the emergent case of Sec. 5.2.11). Appends the pairs of dimension d to
-// `pairs` and the death indices to `deaths`.
+// chain on its own, on `threads` host threads, first. The columns left with
+// a pivot that another column took are then reduced in order, in blocks:
+// blocks of long columns on all `threads` threads, with the same additions
+// as the sequential pass (a column stops at a pivot only once every earlier
+// unfinished column's pivot has moved past it), blocks of short columns on
+// one thread; `always_wide` puts every block on all threads (for tests). A
+// column whose first pivot is free is paired without building it (the
+// emergent case of Sec. 5.2.11). Appends the pairs of dimension d to `pairs`
+// in column order and the death indices to `deaths`.
 void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,
                       int threads, std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
-                      ReduceStats& stats);
+                      ReduceStats& stats, bool always_wide = false);
 
 // Vertices v[d] > ... > v[0] of simplex `c` of dimension d (Eq. 5.6).
 void decode_simplex(const HostComplex& H, uint64_t c, int d, int* v);

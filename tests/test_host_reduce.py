@@ -1,0 +1,97 @@
+"""The host submatrix reduction on its own (no GPU): host_reduce_driver.cpp
+runs the product's reduce_dimension on columns it selects on the host, on
+one thread and on several with every block forced onto all threads. The
+pairs must be the same, in the same order, on any thread count (the
+parallel pass makes exactly the sequential additions), and together with
+the apparent pairs they must be the oracle's pairs of dimensions >= 1.
+"""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_05063_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_2502_05063_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("drv") / "host_reduce_driver")
+    cmd = [hipcc, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           os.path.join(HERE, "host_reduce_driver.cpp"), os.path.join(CSRC, "reduce.cpp"),
+           "-lpthread", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return exe
+
+
+def run(driver, path, max_dim, tau, threads, wide):
+    r = subprocess.run([driver, path, str(max_dim), repr(float(tau)), str(threads),
+                        "1" if wide else "0"], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    return r.stdout
+
+
+def as_set(text):
+    out = set()
+    for line in text.splitlines():
+        d, b, t, bb, tb = (int(x) for x in line.split())
+        ess = t == 2**64 - 1
+        out.add((d, b, -1 if ess else t, bb, -1 if ess else tb))
+    return out
+
+
+def oracle_set(D, max_dim, thr):
+    out = set()
+    for p in oracle.barcode(D, max_dim, threshold=thr):
+        if p["dim"] == 0:
+            continue
+        bb = int(np.float32(p["birth_diam"]).view(np.uint32))
+        if p["essential"]:
+            out.add((int(p["dim"]), int(p["birth"]), -1, bb, -1))
+        else:
+            tb = int(np.float32(p["death_diam"]).view(np.uint32))
+            out.add((int(p["dim"]), int(p["birth"]), int(p["death"]), bb, tb))
+    return out
+
+
+CASES = [
+    ("sphere", 56, 3, float("inf")),
+    ("cube", 120, 2, float("inf")),
+    ("o3", 90, 3, 1.9),
+    ("torus", 200, 2, 1.2),
+]
+
+
+@pytest.mark.parametrize("name,n,max_dim,thr", CASES)
+def test_thread_counts_agree_and_match_oracle(driver, tmp_path, name, n, max_dim, thr):
+    if name == "sphere":
+        X = synth.sphere(n, 3, seed=n)
+    elif name == "cube":
+        X = synth.uniform_cube(n, 3, seed=n)
+    elif name == "o3":
+        X = synth.orthogonal_3x3(n, seed=n)
+    else:
+        X = synth.torus(n, 2.0, 0.5, 0.05, np.random.default_rng(n))
+    D = oracle.pdist(X)
+    tau = min(thr, oracle.enclosing_radius(D))
+    path = str(tmp_path / "m.bin")
+    with open(path, "wb") as f:
+        f.write(np.int32(n).tobytes())
+        f.write(np.ascontiguousarray(D, np.float32).tobytes())
+    one = run(driver, path, max_dim, tau, 1, False)
+    assert one.strip(), "no pairs"
+    # the threads race differently on every run: several runs per count
+    for threads in (2, 8, 8, 16, 16, 16):
+        assert run(driver, path, max_dim, tau, threads, True) == one, f"{threads} threads"
+    assert run(driver, path, max_dim, tau, 8, False) == one
+    assert as_set(one) == oracle_set(D, max_dim, thr)
