@@ -76,6 +76,9 @@ typedef enum {
 /* Unknown flag bits are rejected with VRPH_EINVAL; vrph_batch_plan accepts
  * only VRPH_KEEP_ZERO_PERSISTENCE and VRPH_NO_ENCLOSING_RADIUS. */
 
+/* vrph_boundary_pivots: no clearing step (for a matrix that is not a
+ * boundary matrix, where Lemma 4.2.3 does not hold) */
+#define VRPH_BOUNDARY_NO_CLEARING 32u
 #define VRPH_MAX_DIM 6 /* largest supported max_dim */
 
 typedef struct vrph_ctx vrph_ctx;
@@ -220,6 +223,40 @@ void vrph_batch_destroy(vrph_batch* b);
 vrph_status vrph_backward(vrph_ctx* ctx, const float* X, int64_t n_total, int32_t m,
                           const int32_t* edges, int64_t npairs, const float* g_birth,
                           const float* g_death, float* gX, void* hip_stream);
+
+/* ---- explicit boundary matrices (Sec. 4.3.2-4.3.3, Alg. 2-7) ---------------
+ * The pivots low(R_j) of the Z/2 column reduction of Alg. 2 (R = D V, only
+ * columns to the left added) of an explicit ncols x ncols matrix: the
+ * boundary matrix of a filtration, cells in filtration order, so that the
+ * rows of column j are faces of cell j and come before it. CSC, DEVICE
+ * arrays: col_ptr (int64, ncols + 1 entries, col_ptr[0] = 0, non-decreasing)
+ * and rows (int64, col_ptr[ncols] entries, strictly increasing within a
+ * column, every row of column j in [0, j)).
+ * The device scan (Alg. 3-6) finds the leftmost 1 of every row; a column
+ * whose lowest 1 is the leftmost 1 of its row is a pivot no addition can
+ * change (it is stable), zero columns are stable, and the column named by
+ * such a pivot's row reduces to zero (clearing, Lemma 4.2.3, Alg. 7; left
+ * out with VRPH_BOUNDARY_NO_CLEARING, which makes any strictly upper
+ * triangular Z/2 matrix valid). The host then reduces the other (unstable)
+ * columns in order with Alg. 2, adding stable pivots' columns as they are
+ * and reduced columns of earlier unstable ones.
+ * low_out: HOST array of ncols int64, receives low(R_j), -1 for a zero
+ * column. stats (optional, HOST) receives counts and times. VRPH_EINVAL for
+ * a malformed matrix (also a row outside [0, j)) or ncols >= 2^31. */
+typedef struct {
+  int64_t columns;     /* ncols */
+  int64_t zero;        /* zero columns of the input */
+  int64_t stable;      /* columns the scan settled (zero, pivots, cleared) */
+  int64_t scan_pivots; /* pivots the scan found (Alg. 5) */
+  int64_t unstable;    /* columns reduced on the host */
+  int64_t additions;   /* column additions on the host */
+  double scan_ms;      /* the four scan kernels (HIP events) */
+  double host_ms;      /* host reduction and result assembly */
+} vrph_boundary_stats;
+
+vrph_status vrph_boundary_pivots(vrph_ctx* ctx, int64_t ncols, const int64_t* col_ptr,
+                                 const int64_t* rows, uint32_t flags, void* hip_stream,
+                                 int64_t* low_out, vrph_boundary_stats* stats);
 
 #ifdef __cplusplus
 }

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <iterator>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -201,6 +202,7 @@ struct vrph_ctx {
   std::map<std::tuple<int, int, int>, Tune> tuned;
   DevBuf units;                    // unit table of the d >= 2 enumeration
   DevBuf pfx_v, pfx_cum;           // listed prefixes of sparse dimension-2 and 3 enumerations
+  DevBuf bscan;                    // scratch of the boundary-matrix scan
   std::vector<uint64_t> h_pfx_cum;
   std::vector<uint64_t> h_units;
 };
@@ -1000,6 +1002,125 @@ extern "C" vrph_status vrph_backward(vrph_ctx* c, const float* X, int64_t n_tota
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
   HIP_TRY(launch_backward(X, m, edges, npairs, g_birth, g_death, gX, s));
   HIP_TRY(hipStreamSynchronize(s));
+  return VRPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// explicit boundary matrices
+// ---------------------------------------------------------------------------
+
+extern "C" vrph_status vrph_boundary_pivots(vrph_ctx* c, int64_t ncols, const int64_t* col_ptr,
+                                            const int64_t* rows, uint32_t flags, void* hip_stream,
+                                            int64_t* low_out, vrph_boundary_stats* stats) {
+  if (!c || ncols < 0) return fail(VRPH_EINVAL, "vrph_boundary_pivots: bad argument");
+  if (ncols > 0 && (!col_ptr || !low_out))
+    return fail(VRPH_EINVAL, "vrph_boundary_pivots: NULL argument");
+  if (flags & ~VRPH_BOUNDARY_NO_CLEARING)
+    return fail(VRPH_EINVAL, "vrph_boundary_pivots: unknown flag bits");
+  if (ncols >= ((int64_t)1 << 31) - 1)
+    return fail(VRPH_EINVAL, "vrph_boundary_pivots: ncols must be below 2^31 - 1");
+  vrph_boundary_stats st{};
+  st.columns = ncols;
+  if (ncols == 0) {
+    if (stats) *stats = st;
+    return VRPH_OK;
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  const size_t n = (size_t)ncols;
+  std::vector<int64_t> hptr(n + 1);
+  HIP_TRY(hipMemcpyAsync(hptr.data(), col_ptr, 8 * (n + 1), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t nnz = hptr[n];
+  if (hptr[0] != 0 || nnz < 0)
+    return fail(VRPH_EINVAL, "vrph_boundary_pivots: col_ptr must start at 0 and end at nnz >= 0");
+  if (nnz > 0 && !rows) return fail(VRPH_EINVAL, "vrph_boundary_pivots: NULL rows");
+
+  // scratch: count (u64), err (u32), left (u32 x n), lookup (i32 x n),
+  // unstable (i64 x n), stable (u8 x n)
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t o_left = 256, o_lookup = o_left + up(4 * n), o_unst = o_lookup + up(4 * n),
+               o_stable = o_unst + up(8 * n), total = o_stable + up(n);
+  HIP_TRY(c->bscan.ensure(total));
+  char* base = c->bscan.as<char>();
+  auto* count = reinterpret_cast<unsigned long long*>(base);
+  auto* err = reinterpret_cast<uint32_t*>(base + 8);
+  auto* left = reinterpret_cast<uint32_t*>(base + o_left);
+  auto* lookup = reinterpret_cast<int32_t*>(base + o_lookup);
+  auto* unstable = reinterpret_cast<int64_t*>(base + o_unst);
+  auto* stable = reinterpret_cast<uint8_t*>(base + o_stable);
+  HIP_TRY(hipMemsetAsync(base, 0, 16, s));
+  HIP_TRY(hipEventRecord(c->ev0, s));
+  HIP_TRY(launch_boundary_scan(ncols, col_ptr, rows, nnz, left, lookup, stable, unstable, count, err,
+                               !(flags & VRPH_BOUNDARY_NO_CLEARING), s));
+  HIP_TRY(hipEventRecord(c->ev1, s));
+  uint64_t head[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(head, base, 16, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  float scan_ms = 0;
+  HIP_TRY(hipEventElapsedTime(&scan_ms, c->ev0, c->ev1));
+  const uint32_t e = (uint32_t)head[1];
+  if (e & 1u) return fail(VRPH_EINVAL, "vrph_boundary_pivots: col_ptr decreasing or past nnz");
+  if (e & 2u)
+    return fail(VRPH_EINVAL, "vrph_boundary_pivots: rows not strictly increasing in a column");
+  if (e & 4u) return fail(VRPH_EINVAL, "vrph_boundary_pivots: a row of column j outside [0, j)");
+  const size_t nun = (size_t)head[0];
+  if (nun > n) return fail(VRPH_EDEVICE, "vrph_boundary_pivots: unstable count out of range");
+  std::vector<int32_t> hlookup(n);
+  std::vector<int64_t> hun(nun), hrows((size_t)nnz);
+  HIP_TRY(hipMemcpyAsync(hlookup.data(), lookup, 4 * n, hipMemcpyDeviceToHost, s));
+  if (nun) HIP_TRY(hipMemcpyAsync(hun.data(), unstable, 8 * nun, hipMemcpyDeviceToHost, s));
+  if (nnz) HIP_TRY(hipMemcpyAsync(hrows.data(), rows, 8 * (size_t)nnz, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double t_host = now_ms();
+
+  // Alg. 2 on the unstable columns, in order. pivot_of[r]: the column whose
+  // reduced column has its lowest 1 in row r (stable pivots first).
+  std::vector<int64_t> pivot_of(n, -1);
+  std::fill(low_out, low_out + n, (int64_t)-1);
+  for (size_t r = 0; r < n; ++r)
+    if (hlookup[r] >= 0) {
+      pivot_of[r] = hlookup[r];
+      low_out[hlookup[r]] = (int64_t)r;
+      ++st.scan_pivots;
+    }
+  std::sort(hun.begin(), hun.end());
+  std::vector<std::vector<int64_t>> red;  // reduced unstable columns
+  std::vector<int32_t> red_of(n, -1);
+  std::vector<int64_t> work, tmp;
+  for (int64_t j : hun) {
+    work.assign(hrows.begin() + hptr[(size_t)j], hrows.begin() + hptr[(size_t)j + 1]);
+    while (!work.empty()) {
+      const int64_t k = pivot_of[(size_t)work.back()];
+      if (k < 0) break;
+      if (k >= j) return fail(VRPH_EINVAL, "vrph_boundary_pivots: not a boundary matrix");
+      const int64_t *kb, *ke;
+      if (red_of[(size_t)k] >= 0) {
+        const std::vector<int64_t>& rk = red[(size_t)red_of[(size_t)k]];
+        kb = rk.data();
+        ke = kb + rk.size();
+      } else {  // a stable pivot's column is reduced as it is
+        kb = hrows.data() + hptr[(size_t)k];
+        ke = hrows.data() + hptr[(size_t)k + 1];
+      }
+      tmp.clear();
+      std::set_symmetric_difference(work.begin(), work.end(), kb, ke, std::back_inserter(tmp));
+      work.swap(tmp);
+      ++st.additions;
+    }
+    if (!work.empty()) {
+      low_out[j] = work.back();
+      pivot_of[(size_t)work.back()] = j;
+      red_of[(size_t)j] = (int32_t)red.size();
+      red.push_back(work);
+    }
+  }
+  for (size_t j = 0; j < n; ++j) st.zero += hptr[j + 1] == hptr[j];
+  st.unstable = (int64_t)nun;
+  st.stable = ncols - (int64_t)nun;
+  st.scan_ms = scan_ms;
+  st.host_ms = now_ms() - t_host;
+  if (stats) *stats = st;
   return VRPH_OK;
 }
 

@@ -184,6 +184,14 @@ hipError_t launch_batch_edges(const uint32_t* W, const Cloud* clouds, int count,
 hipError_t launch_set_bits(const uint64_t* idx, int64_t count, uint32_t* bitmap, hipStream_t s);
 // Insert count indices into a clearing set (bitmap or hash).
 hipError_t launch_clear_insert(const uint64_t* idx, int64_t count, ClearSet set, hipStream_t s);
+
+// GPU scan of an explicit boundary matrix (Alg. 3-6): left/lookup/stable
+// have n entries, unstable room for n; *count and *err must be zero on
+// entry. Requires n < 2^31.
+hipError_t launch_boundary_scan(int64_t n, const int64_t* col_ptr, const int64_t* rows, int64_t nnz,
+                                uint32_t* left, int32_t* lookup, uint8_t* stable,
+                                int64_t* unstable, unsigned long long* count, uint32_t* err,
+                                bool clearing, hipStream_t s);
 hipError_t launch_backward(const float* X, int m, const int32_t* edges, int64_t npairs,
                            const float* g_birth, const float* g_death, float* gX, hipStream_t s);
 

@@ -20,6 +20,7 @@ NO_ENCLOSING_RADIUS = 2
 AUTOTUNE = 4
 NO_LDS = 8
 HASHED_CLEARING = 16
+BOUNDARY_NO_CLEARING = 32
 MAX_DIM = 6
 
 PAIR_DTYPE = np.dtype(
@@ -64,6 +65,16 @@ class Stats(ctypes.Structure):
         return out
 
 
+class BoundaryStats(ctypes.Structure):
+    _fields_ = [("columns", ctypes.c_int64), ("zero", ctypes.c_int64), ("stable", ctypes.c_int64),
+                ("scan_pivots", ctypes.c_int64), ("unstable", ctypes.c_int64),
+                ("additions", ctypes.c_int64), ("scan_ms", ctypes.c_double),
+                ("host_ms", ctypes.c_double)]
+
+    def to_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class VrphError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"vrph status {status}: {msg}")
@@ -100,6 +111,7 @@ def lib():
         "vrph_batch_result": (i32, [vp, i32, P(vp)]),
         "vrph_batch_destroy": (None, [vp]),
         "vrph_backward": (i32, [vp, vp, i64, i32, vp, i64, vp, vp, vp, vp]),
+        "vrph_boundary_pivots": (i32, [vp, i64, vp, vp, u32, vp, vp, P(BoundaryStats)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -221,6 +233,30 @@ class Context:
                                               _dev_ptr(val), max_dim, threshold, flags,
                                               _stream_ptr(), ctypes.byref(out)))
         return Barcode(out)
+
+    def boundary_pivots(self, col_ptr, rows, *, clearing=True):
+        """Pivots low(R_j) of Alg. 2 for an explicit boundary matrix in CSC form
+        (col_ptr, rows: 1-D int64 CUDA tensors; rows strictly increasing within a
+        column and below it). Returns (low: int64 numpy array, -1 for a zero
+        column, stats dict)."""
+        import torch
+
+        for t in (col_ptr, rows):
+            if not t.is_cuda or t.dtype != torch.int64 or t.dim() != 1:
+                raise ValueError("col_ptr and rows must be 1-D int64 CUDA tensors")
+        if col_ptr.numel() < 1:
+            raise ValueError("col_ptr needs ncols + 1 entries")
+        col_ptr, rows = col_ptr.contiguous(), rows.contiguous()
+        ncols = col_ptr.numel() - 1
+        if int(col_ptr[-1]) > rows.numel():
+            raise ValueError("col_ptr[-1] is past the end of rows")
+        low = np.empty(max(ncols, 1), np.int64)
+        st = BoundaryStats()
+        _check(lib().vrph_boundary_pivots(self.h, ncols, _dev_ptr(col_ptr),
+                                          _dev_ptr(rows) if rows.numel() else None,
+                                          0 if clearing else BOUNDARY_NO_CLEARING, _stream_ptr(),
+                                          low.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)))
+        return low[:ncols], st.to_dict()
 
     def backward(self, X, edges, g_birth, g_death, gX):
         """gX += scatter of g_birth/g_death onto the diameter edges (edges: int32 [npairs, 4])."""

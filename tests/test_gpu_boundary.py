@@ -1,0 +1,160 @@
+"""Explicit boundary matrices through the C ABI (vrph_boundary_pivots): the GPU
+scan of Sec. 4.3.2 (Alg. 3-6), clearing (Alg. 7), and Alg. 2 on the host for
+the unstable columns. The pivots must be the oracle's Alg. 2 pivots
+(oracle.reduce_explicit) exactly; the scan's counts are checked against
+their definitions (leftmost 1 of a row, zero columns, cleared columns).
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_05063_amd import synth
+
+from test_gpu_parity import ctx  # noqa: F401  (fixture)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def to_dev(columns):
+    import torch
+
+    ptr = np.zeros(len(columns) + 1, np.int64)
+    for j, c in enumerate(columns):
+        ptr[j + 1] = ptr[j] + len(c)
+    rows = np.fromiter(itertools.chain.from_iterable(columns), np.int64, count=int(ptr[-1]))
+    return torch.from_numpy(ptr).cuda(), torch.from_numpy(rows).cuda()
+
+
+def rips_boundary(D, max_dim, tau):
+    """Boundary matrix of the Rips filtration up to max_dim: cells sorted by
+    (diameter, dimension, vertex tuple), which puts faces before cofaces;
+    column j lists the positions of cell j's facets, increasing."""
+    n = D.shape[0]
+    cells = [((0.0, 0, (v,))) for v in range(n)]
+    for k in range(2, max_dim + 2):
+        for s in itertools.combinations(range(n), k):
+            dm = max(D[a, b] for a, b in itertools.combinations(s, 2))
+            if dm <= tau:
+                cells.append((float(dm), k - 1, s))
+    cells.sort()
+    pos = {c[2]: i for i, c in enumerate(cells)}
+    cols = []
+    for _, k, s in cells:
+        if k == 0:
+            cols.append([])
+        else:
+            cols.append(sorted(pos[f] for f in itertools.combinations(s, k)))
+    return cols
+
+
+def scan_expectation(cols, clearing):
+    """Counts of the scan from their definitions."""
+    n = len(cols)
+    left = np.full(n, n, np.int64)
+    for j, c in enumerate(cols):
+        for r in c:
+            left[r] = min(left[r], j)
+    zero = {j for j, c in enumerate(cols) if not c}
+    piv = {j for j, c in enumerate(cols) if c and left[c[-1]] == j}
+    stable = zero | piv
+    if clearing:
+        stable |= {cols[j][-1] for j in piv}
+    return len(zero), len(piv), n - len(stable)
+
+
+def check(ctx, cols, clearing=True):
+    ptr, rows = to_dev(cols)
+    low, st = ctx.boundary_pivots(ptr, rows, clearing=clearing)
+    want = oracle.reduce_explicit(cols)
+    assert np.array_equal(low, want), f"{int((low != want).sum())} pivots differ"
+    zero, piv, unstable = scan_expectation(cols, clearing)
+    assert (st["zero"], st["scan_pivots"], st["unstable"]) == (zero, piv, unstable)
+    assert st["columns"] == len(cols) and st["stable"] == len(cols) - unstable
+    return st
+
+
+def test_fig4_1(ctx):
+    with open(os.path.join(GOLDEN, "fig4_1_boundary.json")) as f:
+        g = json.load(f)
+    cols = [sorted(c) for c in g["columns"]]
+    for clearing in (True, False):
+        check(ctx, cols, clearing)
+    low, _ = ctx.boundary_pivots(*to_dev(cols))
+    pivots = sorted([int(low[j]), j] for j in range(len(cols)) if low[j] >= 0)
+    assert pivots == sorted(g["pivots"])
+
+
+@pytest.mark.parametrize("name,n,max_dim,tau", [("cube", 14, 3, float("inf")),
+                                                 ("sphere", 24, 2, float("inf")),
+                                                 ("o3", 40, 2, 1.6),
+                                                 ("cube", 70, 2, 0.45)])
+def test_rips_boundary_matrices(ctx, name, n, max_dim, tau):
+    if name == "sphere":
+        X = synth.sphere(n, 3, seed=n)
+    elif name == "o3":
+        X = synth.orthogonal_3x3(n, seed=n)
+    else:
+        X = synth.uniform_cube(n, 3, seed=n)
+    D = oracle.pdist(X).astype(np.float64)
+    cols = rips_boundary(D, max_dim, tau)
+    for clearing in (True, False):
+        st = check(ctx, cols, clearing)
+    assert st["unstable"] < len(cols)
+
+
+@pytest.mark.parametrize("seed,n,p", [(1, 300, 0.02), (2, 2000, 0.002), (3, 5000, 0.0008)])
+def test_random_upper_triangular(ctx, seed, n, p):
+    """Any strictly upper triangular Z/2 matrix, without the clearing step
+    (which holds for boundary matrices only); sizes span many workgroups and
+    end in a partial one."""
+    rng = np.random.default_rng(seed)
+    cols = []
+    for j in range(n):
+        k = min(j, rng.binomial(j, p) if j else 0)
+        cols.append(sorted(rng.choice(j, size=k, replace=False).tolist()) if k else [])
+    check(ctx, cols, clearing=False)
+
+
+def test_edge_cases(ctx):
+    import torch
+
+    low, st = ctx.boundary_pivots(torch.zeros(1, dtype=torch.int64, device="cuda"),
+                                  torch.zeros(0, dtype=torch.int64, device="cuda"))
+    assert len(low) == 0 and st["columns"] == 0
+    check(ctx, [[]])
+    check(ctx, [[], [], []])
+    check(ctx, [[], [0], [0], [1, 2]])  # a triangle's boundary: edges 1, 2 share vertex 0
+
+
+@pytest.mark.parametrize("case", ["unsorted", "repeat", "not_below", "negative", "ptr_decreasing",
+                                  "ptr_start"])
+def test_invalid_matrices(ctx, case):
+    import torch
+
+    from paper_2502_05063_amd import vrph
+
+    cols = [[], [], [0, 1], [1]]
+    ptr, rows = to_dev(cols)
+    ptr, rows = ptr.cpu().numpy(), rows.cpu().numpy()
+    if case == "unsorted":
+        rows[0], rows[1] = rows[1], rows[0]
+    elif case == "repeat":
+        rows[1] = rows[0]
+    elif case == "not_below":
+        rows[2] = 3
+    elif case == "negative":
+        rows[2] = -1
+    elif case == "ptr_decreasing":
+        ptr[2], ptr[3] = ptr[3], ptr[2]
+    elif case == "ptr_start":
+        ptr = ptr + 1
+        rows = np.append(rows, 0)  # long enough for col_ptr[-1]: the library rejects it
+    with pytest.raises((vrph.VrphError, ValueError)):
+        ctx.boundary_pivots(torch.from_numpy(ptr).cuda(), torch.from_numpy(rows).cuda())
+    check(ctx, cols)  # the context stays usable
