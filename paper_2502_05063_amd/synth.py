@@ -15,6 +15,9 @@ distance matrices with the shapes and distributions of the workloads:
   permutation_distances(n)    a random permutation of 1..n(n-1)/2 filling a
                               symmetric matrix (random distance matrices of the
                               paper's apparent-fraction experiment)
+  rips2_boundary_csc(D, tau)  the explicit boundary matrix (CSC) of a Rips
+                              2-skeleton, the input of the explicit-matrix
+                              workload
 """
 from __future__ import annotations
 
@@ -105,3 +108,55 @@ CONFIGS = {
     "c4_batch256": dict(max_dim=1, threshold=float("inf")),
     "c5_torus64x500": dict(max_dim=1, threshold=float("inf")),
 }
+
+
+def rips2_boundary_csc(D: np.ndarray, tau: float):
+    """Boundary matrix (CSC: col_ptr, rows; int64) of the Rips 2-skeleton of
+    the distance matrix D up to tau: vertices, edges and triangles within
+    tau, in filtration order (diameter, then dimension, then cell number),
+    which puts faces before cofaces; column j lists the positions of cell
+    j's facets, increasing. An input generator for the explicit-matrix
+    workload."""
+    D = np.asarray(D, np.float64)
+    n = D.shape[0]
+    a, b = np.triu_indices(n, 1)
+    ew = D[a, b]
+    keep = ew <= tau
+    a, b, ew = a[keep], b[keep], ew[keep]
+    eid = np.full((n, n), -1, np.int64)
+    eid[a, b] = np.arange(len(a))
+    eid[b, a] = eid[a, b]
+    tri = []
+    idx = np.arange(n)
+    for x in range(n):
+        nb = np.nonzero((D[x] <= tau) & (idx > x))[0]
+        if len(nb) < 2:
+            continue
+        i, j = np.triu_indices(len(nb), 1)
+        y, z = nb[i], nb[j]
+        ok = D[y, z] <= tau
+        tri.append(np.stack([np.full(int(ok.sum()), x), y[ok], z[ok]], 1))
+    tri = np.concatenate(tri) if tri else np.zeros((0, 3), np.int64)
+    tw = np.maximum(np.maximum(D[tri[:, 0], tri[:, 1]], D[tri[:, 0], tri[:, 2]]),
+                    D[tri[:, 1], tri[:, 2]])
+    nv, ne, nt = n, len(a), len(tri)
+    diam = np.concatenate([np.zeros(nv), ew, tw])
+    dim = np.concatenate([np.zeros(nv), np.ones(ne), np.full(nt, 2.0)])
+    order = np.lexsort((np.arange(nv + ne + nt), dim, diam))  # cell at each position
+    pos = np.empty_like(order)
+    pos[order] = np.arange(len(order))
+    ecols = np.sort(np.stack([pos[a], pos[b]], 1), 1)
+    tcols = np.sort(np.stack([pos[nv + eid[tri[:, 0], tri[:, 1]]], pos[nv + eid[tri[:, 0], tri[:, 2]]],
+                              pos[nv + eid[tri[:, 1], tri[:, 2]]]], 1), 1)
+    lens = np.concatenate([np.zeros(nv, np.int64), np.full(ne, 2, np.int64),
+                           np.full(nt, 3, np.int64)])[order]
+    col_ptr = np.zeros(len(order) + 1, np.int64)
+    col_ptr[1:] = np.cumsum(lens)
+    rows = np.empty(int(col_ptr[-1]), np.int64)
+    pe = np.nonzero((order >= nv) & (order < nv + ne))[0]
+    pt = np.nonzero(order >= nv + ne)[0]
+    for k in range(2):
+        rows[col_ptr[pe] + k] = ecols[order[pe] - nv, k]
+    for k in range(3):
+        rows[col_ptr[pt] + k] = tcols[order[pt] - nv - ne, k]
+    return col_ptr, rows
