@@ -1515,117 +1515,4 @@ hipError_t launch_backward(const float* X, int m, const int32_t* edges, int64_t 
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Explicit boundary matrices: the GPU scan of Sec. 4.3.2 (Alg. 3-6) over a
-// CSC matrix of ncols columns whose rows (strictly increasing within a
-// column, all below the column: faces come first in a filtration) index the
-// same cells as the columns. One lane per column; a column is short, so the
-// lanes of a wave read one contiguous stretch of the row array.
-//   left[r]   smallest column with a 1 in row r (atomicMin), ~0 if none
-//   lookup[r] the column whose lowest 1 is the leftmost 1 of row r, else -1:
-//             no column to its left can ever be added to it (a pivot of the
-//             reduced matrix, Alg. 5), so it is stable
-//   stable[j] zero columns, those pivots' columns and, with clearing, the
-//             columns named by their rows (they reduce to zero: Lemma 4.2.3)
-//   unstable  the other columns, one atomic per wave (any order)
-// err (bits): 1 col_ptr decreasing or out of range, 2 rows not strictly
-// increasing, 4 a row outside [0, column).
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(kBlock) void bscan_init_kernel(int64_t n, uint32_t* __restrict__ left,
-                                                            int32_t* __restrict__ lookup,
-                                                            uint8_t* __restrict__ stable) {
-  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * kBlock) {
-    left[j] = ~0u;
-    lookup[j] = -1;
-    stable[j] = 0;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void bscan_leftmost_kernel(
-    int64_t n, const int64_t* __restrict__ col_ptr, const int64_t* __restrict__ rows,
-    int64_t nnz, uint32_t* __restrict__ left, uint8_t* __restrict__ stable,
-    uint32_t* __restrict__ err) {
-  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * kBlock) {
-    const int64_t b = col_ptr[j], e = col_ptr[j + 1];
-    if (b < 0 || e < b || e > nnz) {
-      atomicOr(err, 1u);
-      continue;
-    }
-    if (b == e) {
-      stable[j] = 1;  // a zero column
-      continue;
-    }
-    int64_t prev = -1;
-    uint32_t bad = 0;
-    for (int64_t q = b; q < e; ++q) {
-      const int64_t r = rows[q];
-      if (r <= prev) bad |= 2u;
-      if (r < 0 || r >= j) {
-        bad |= 4u;
-        break;
-      }
-      prev = r;
-      atomicMin(&left[r], (uint32_t)j);
-    }
-    if (bad) atomicOr(err, bad);
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void bscan_lookup_kernel(
-    int64_t n, const int64_t* __restrict__ col_ptr, const int64_t* __restrict__ rows,
-    int64_t nnz, const uint32_t* __restrict__ left, int32_t* __restrict__ lookup,
-    uint8_t* __restrict__ stable, int clearing) {
-  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * kBlock) {
-    const int64_t b = col_ptr[j], e = col_ptr[j + 1];
-    if (b < 0 || e <= b || e > nnz) continue;  // zero, or flagged by the scan
-    const int64_t r = rows[e - 1];              // the lowest 1
-    if (r < 0 || r >= j) continue;              // flagged by the scan
-    if (left[r] == (uint32_t)j) {
-      lookup[r] = (int32_t)j;
-      stable[j] = 1;
-      if (clearing) stable[r] = 1;
-    }
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void bscan_unstable_kernel(int64_t n,
-                                                                const uint8_t* __restrict__ stable,
-                                                                int64_t* __restrict__ unstable,
-                                                                unsigned long long* __restrict__ count) {
-  const int lane = (int)(threadIdx.x & 63);
-  // every lane of a wave runs the same number of rounds, so the ballot sees
-  // the whole wave
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  const int64_t first = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u);
-  for (int64_t w0 = first; w0 < n; w0 += stride) {
-    const int64_t j = w0 + lane;
-    const bool un = j < n && !stable[j];
-    const unsigned long long m = __ballot(un);
-    if (!m) continue;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(count, (unsigned long long)__popcll(m));
-    base = __shfl(base, 0);
-    if (un) unstable[base + (uint64_t)__popcll(m & ((1ull << lane) - 1ull))] = j;
-  }
-}
-
-hipError_t launch_boundary_scan(int64_t n, const int64_t* col_ptr, const int64_t* rows, int64_t nnz,
-                                uint32_t* left, int32_t* lookup, uint8_t* stable,
-                                int64_t* unstable, unsigned long long* count, uint32_t* err,
-                                bool clearing, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + kBlock - 1) / kBlock;
-  if (blocks > 8192) blocks = 8192;
-  bscan_init_kernel<<<(int)blocks, kBlock, 0, s>>>(n, left, lookup, stable);
-  bscan_leftmost_kernel<<<(int)blocks, kBlock, 0, s>>>(n, col_ptr, rows, nnz, left, stable, err);
-  bscan_lookup_kernel<<<(int)blocks, kBlock, 0, s>>>(n, col_ptr, rows, nnz, left, lookup, stable,
-                                                    clearing ? 1 : 0);
-  bscan_unstable_kernel<<<(int)blocks, kBlock, 0, s>>>(n, stable, unstable, count);
-  return hipGetLastError();
-}
-
 }  // namespace vrph
