@@ -321,6 +321,84 @@ __device__ __forceinline__ unsigned long long edge_key(uint32_t w, int a, int b)
   return ((unsigned long long)w << 32) | (0xFFFFFFFFu - (uint32_t)e);
 }
 
+// Phases 2 and 3 of one cloud, by one workgroup of kH0Threads lanes: the
+// m forest edge keys in mst (LDS, room for a power of two >= m) are sorted,
+// cleared in the dimension-1 bitmap bm and paired by union-find with the
+// elder rule (parent and rep: LDS scratch of n entries); the pairs go to o
+// and their number to *count.
+__device__ void h0_finish(unsigned long long* mst, int m, int* parent, unsigned long long* rep,
+                          int n, uint32_t* bm, H0Pair* o, uint32_t* count) {
+  const int tid = threadIdx.x;
+  // bitonic sort of the m forest edges, ascending (padding with ~0)
+  int P = 1;
+  while (P < m) P <<= 1;
+  for (int i = m + tid; i < P; i += kH0Threads) mst[i] = ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < P; i += kH0Threads) {
+        int l = i ^ j;
+        if (l > i) {
+          unsigned long long a = mst[i], b = mst[l];
+          bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            mst[i] = b;
+            mst[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // the forest edges are H0 deaths: clear them for dimension 1
+  for (int i = tid; i < m; i += kH0Threads) {
+    uint32_t e = 0xFFFFFFFFu - (uint32_t)mst[i];
+    atomicOr(&bm[e >> 5], 1u << (e & 31));
+  }
+
+  // union-find with the elder rule, one lane
+  for (int v = tid; v < n; v += kH0Threads) {
+    parent[v] = v;
+    rep[v] = (unsigned long long)v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int k = 0;
+    for (int i = 0; i < m; ++i) {
+      unsigned long long key = mst[i];
+      uint64_t e = 0xFFFFFFFFu - (uint32_t)key;
+      int a, b;
+      edge_vertices(e, a, b);
+      int ra = a, rb = b;
+      while (parent[ra] != ra) {
+        parent[ra] = parent[parent[ra]];
+        ra = parent[ra];
+      }
+      while (parent[rb] != rb) {
+        parent[rb] = parent[parent[rb]];
+        rb = parent[rb];
+      }
+      const int rep_a = (int)rep[ra], rep_b = (int)rep[rb];
+      int young = rep_a < rep_b ? ra : rb;
+      int old = young == ra ? rb : ra;
+      o[k].death = e;
+      o[k].birth = (uint32_t)(young == ra ? rep_a : rep_b);
+      o[k].diam = (uint32_t)(key >> 32);
+      ++k;
+      parent[young] = old;
+    }
+    for (int v = 0; v < n; ++v)
+      if (parent[v] == v) {
+        o[k].death = ~0ull;
+        o[k].birth = (uint32_t)rep[v];
+        o[k].diam = kInf;
+        ++k;
+      }
+    *count = (uint32_t)k;
+  }
+}
+
 __global__ __launch_bounds__(kH0Threads) void batch_h0_kernel(const uint32_t* __restrict__ W,
                                                               const Cloud* __restrict__ clouds,
                                                               CloudState* __restrict__ st,
@@ -412,84 +490,146 @@ __global__ __launch_bounds__(kH0Threads) void batch_h0_kernel(const uint32_t* __
   }
   const int m = m_sh;
   __syncthreads();
-
-  // bitonic sort of the m forest edges, ascending (padding with ~0)
-  int P = 1;
-  while (P < m) P <<= 1;
-  for (int i = m + tid; i < P; i += kH0Threads) mst[i] = ~0ull;
-  __syncthreads();
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = tid; i < P; i += kH0Threads) {
-        int l = i ^ j;
-        if (l > i) {
-          unsigned long long a = mst[i], b = mst[l];
-          bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            mst[i] = b;
-            mst[l] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-
-  // the forest edges are H0 deaths: clear them for dimension 1
-  uint32_t* bm = bitmaps + cl.bm_off;
-  for (int i = tid; i < m; i += kH0Threads) {
-    uint32_t e = 0xFFFFFFFFu - (uint32_t)mst[i];
-    atomicOr(&bm[e >> 5], 1u << (e & 31));
-  }
-
-  // union-find with the elder rule, one lane (parent in comp[], rep in best[])
-  int* parent = comp;
-  for (int v = tid; v < n; v += kH0Threads) {
-    parent[v] = v;
-    best[v] = (unsigned long long)v;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    H0Pair* o = out + (int64_t)c * out_stride;
-    int k = 0;
-    for (int i = 0; i < m; ++i) {
-      unsigned long long key = mst[i];
-      uint64_t e = 0xFFFFFFFFu - (uint32_t)key;
-      int a, b;
-      edge_vertices(e, a, b);
-      int ra = a, rb = b;
-      while (parent[ra] != ra) {
-        parent[ra] = parent[parent[ra]];
-        ra = parent[ra];
-      }
-      while (parent[rb] != rb) {
-        parent[rb] = parent[parent[rb]];
-        rb = parent[rb];
-      }
-      const int rep_a = (int)best[ra], rep_b = (int)best[rb];
-      int young = rep_a < rep_b ? ra : rb;
-      int old = young == ra ? rb : ra;
-      o[k].death = e;
-      o[k].birth = (uint32_t)(young == ra ? rep_a : rep_b);
-      o[k].diam = (uint32_t)(key >> 32);
-      ++k;
-      parent[young] = old;
-    }
-    for (int v = 0; v < n; ++v)
-      if (parent[v] == v) {
-        o[k].death = ~0ull;
-        o[k].birth = (uint32_t)best[v];
-        o[k].diam = kInf;
-        ++k;
-      }
-    st[c].h0_count = (uint32_t)k;
-  }
+  h0_finish(mst, m, comp, best, n, bitmaps + cl.bm_off, out + (int64_t)c * out_stride,
+            &st[c].h0_count);
 }
 
 hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, CloudState* st,
                            H0Pair* out, int64_t out_stride, uint32_t* bitmaps, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   batch_h0_kernel<<<count, kH0Threads, 0, s>>>(W, clouds, st, out, out_stride, bitmaps);
+  return hipGetLastError();
+}
+
+// The same for one large cloud, with the row scans of every Boruvka round
+// spread over the chip: a wave per row (n / 16 workgroups) folds the row's
+// minimum outgoing edge into its component with a 64-bit atomicMin in
+// global memory; one workgroup then decides, hooks and relabels (O(n) work).
+// Every round halves the components that still have an outgoing edge, so
+// ceil(log2 n) + 1 rounds suffice; the host launches that many without
+// waiting, and a round that changes nothing sets `done`, which turns the
+// launches after it into no-ops. One workgroup finishes as above.
+struct H0Wide {
+  unsigned long long* best;  // per component root: its minimum outgoing edge
+  int* comp;                 // component root of every vertex
+  int* hookto;               // where a root moves this round
+  unsigned long long* mst;   // forest edge keys
+  int* m;                    // forest edges so far
+  int* done;                 // set once a round changes nothing
+};
+
+__global__ __launch_bounds__(kH0Threads) void h0w_init_kernel(int n, H0Wide w) {
+  for (int v = blockIdx.x * kH0Threads + threadIdx.x; v < n; v += gridDim.x * kH0Threads) {
+    w.comp[v] = v;
+    w.best[v] = ~0ull;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *w.m = 0;
+    *w.done = 0;
+  }
+}
+
+__global__ __launch_bounds__(kH0Threads) void h0w_scan_kernel(const uint32_t* __restrict__ W, int n,
+                                                              H0Wide w) {
+  if (*w.done) return;
+  const int lane = (int)(threadIdx.x & 63);
+  const int u = (int)(blockIdx.x * (kH0Threads / 64) + (threadIdx.x >> 6));
+  if (u >= n) return;  // whole waves
+  const int cu = w.comp[u];
+  const uint32_t* Wu = W + (int64_t)u * n;
+  unsigned long long mk = ~0ull;
+  for (int v = lane; v < n; v += 64) {
+    const uint32_t x = Wu[v];
+    if (x != kInf && w.comp[v] != cu) {
+      const unsigned long long k = edge_key(x, u, v);
+      mk = k < mk ? k : mk;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long t = shfl_xor_u64(mk, o);
+    mk = t < mk ? t : mk;
+  }
+  if (lane == 0 && mk != ~0ull) atomicMin(&w.best[cu], mk);
+}
+
+__global__ __launch_bounds__(kH0Threads) void h0w_hook_kernel(int n, H0Wide w) {
+  __shared__ int changed;
+  if (*w.done) return;  // the same value for the whole workgroup
+  const int tid = threadIdx.x;
+  if (tid == 0) changed = 0;
+  __syncthreads();
+  // roots decide while best[] is read-only (the rules of the one-workgroup
+  // kernel: a mutual minimum edge is taken once, only its larger root moves)
+  for (int r = tid; r < n; r += kH0Threads) {
+    w.hookto[r] = r;
+    if (w.comp[r] != r || w.best[r] == ~0ull) continue;
+    const unsigned long long k = w.best[r];
+    int a, b;
+    edge_vertices(0xFFFFFFFFu - (uint32_t)k, a, b);
+    const int other = w.comp[a] == r ? w.comp[b] : w.comp[a];
+    const bool mutual = w.best[other] == k;
+    if (!mutual || r < other) w.mst[atomicAdd(w.m, 1)] = k;
+    if (!mutual || r > other) w.hookto[r] = other;
+    changed = 1;
+  }
+  __syncthreads();
+  if (!changed) {
+    if (tid == 0) *w.done = 1;
+    return;
+  }
+  for (int r = tid; r < n; r += kH0Threads)
+    if (w.comp[r] == r) w.comp[r] = w.hookto[r];
+  __syncthreads();
+  for (int it = 0; it < 32; ++it) {  // pointer jumping; depth halves every step
+    int moved = 0;
+    for (int v = tid; v < n; v += kH0Threads) {
+      const int p = w.comp[v], pp = w.comp[p];
+      if (p != pp) {
+        w.comp[v] = pp;
+        moved = 1;
+      }
+    }
+    __syncthreads();
+    if (!__syncthreads_or(moved)) break;
+  }
+  for (int v = tid; v < n; v += kH0Threads) w.best[v] = ~0ull;  // for the next round
+}
+
+__global__ __launch_bounds__(kH0Threads) void h0w_finish_kernel(int n, H0Wide w,
+                                                                CloudState* __restrict__ st,
+                                                                H0Pair* __restrict__ out,
+                                                                uint32_t* __restrict__ bm) {
+  __shared__ unsigned long long mst[kMaxN];
+  __shared__ unsigned long long rep[kMaxN];
+  __shared__ int parent[kMaxN];
+  const int m = *w.m;  // < n <= kMaxN
+  for (int i = threadIdx.x; i < m; i += kH0Threads) mst[i] = w.mst[i];
+  __syncthreads();
+  h0_finish(mst, m, parent, rep, n, bm, out, &st->h0_count);
+}
+
+size_t h0_wide_scratch_bytes(int n) { return (size_t)n * 24 + 256; }
+
+hipError_t launch_h0_wide(const uint32_t* W, int n, CloudState* st, H0Pair* out, uint32_t* bm,
+                          void* scratch, hipStream_t s) {
+  if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
+  char* p = static_cast<char*>(scratch);
+  H0Wide w;
+  w.best = reinterpret_cast<unsigned long long*>(p);
+  w.mst = reinterpret_cast<unsigned long long*>(p + (size_t)n * 8);
+  w.comp = reinterpret_cast<int*>(p + (size_t)n * 16);
+  w.hookto = reinterpret_cast<int*>(p + (size_t)n * 20);
+  w.m = reinterpret_cast<int*>(p + (size_t)n * 24);
+  w.done = w.m + 1;
+  const unsigned scan_groups = (unsigned)((n + kH0Threads / 64 - 1) / (kH0Threads / 64));
+  h0w_init_kernel<<<(n + kH0Threads - 1) / kH0Threads, kH0Threads, 0, s>>>(n, w);
+  int rounds = 1;
+  while ((1 << (rounds - 1)) < n) ++rounds;  // ceil(log2 n) + 1
+  for (int r = 0; r < rounds; ++r) {
+    h0w_scan_kernel<<<scan_groups, kH0Threads, 0, s>>>(W, n, w);
+    h0w_hook_kernel<<<1, kH0Threads, 0, s>>>(n, w);
+  }
+  h0w_finish_kernel<<<1, kH0Threads, 0, s>>>(n, w, st, out, bm);
   return hipGetLastError();
 }
 

@@ -203,6 +203,7 @@ struct vrph_ctx {
   DevBuf units;                    // unit table of the d >= 2 enumeration
   DevBuf pfx_v, pfx_cum;           // listed prefixes of sparse dimension-2 and 3 enumerations
   DevBuf bscan;                    // scratch of the boundary-matrix scan
+  DevBuf h0w;                      // scratch of H0 for large clouds
   std::vector<uint64_t> h_pfx_cum;
   std::vector<uint64_t> h_units;
 };
@@ -302,7 +303,8 @@ extern "C" void vrph_destroy(vrph_ctx* c) {
   DevBuf* bufs[] = {&c->D,      &c->W,     &c->binom,  &c->bitmaps, &c->cols,
                     &c->cols_tmp, &c->sort_work, &c->ap, &c->scal,  &c->clouds,
                     &c->cstate,  &c->h0,    &c->deaths, &c->units,   &c->wr16,
-                    &c->rank_bits, &c->sink_ctr, &c->ap_ctr, &c->ap_tmp, &c->hflag};
+                    &c->rank_bits, &c->sink_ctr, &c->ap_ctr, &c->ap_tmp, &c->hflag,
+                    &c->pfx_v,     &c->pfx_cum,  &c->bscan,  &c->h0w};
   for (DevBuf* b : bufs) b->release();
   for (DevBuf& b : c->hset) b.release();
   c->h_scal.release();
@@ -546,8 +548,17 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   HIP_TRY(launch_batch_validate_weights(D, c->clouds.as<Cloud>(), 1, n,
                                         !(flags & VRPH_NO_ENCLOSING_RADIUS), c->W.as<uint32_t>(),
                                         c->cstate.as<CloudState>(), s, sp != nullptr));
-  HIP_TRY(launch_batch_h0(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1,
-                          c->cstate.as<CloudState>(), c->h0.as<H0Pair>(), n, bm + bm_off[1], s));
+  // H0: one workgroup for small clouds; above kH0WideMin points the
+  // Boruvka row scans are spread over the chip
+  constexpr int kH0WideMin = 512;
+  if (n >= kH0WideMin) {
+    HIP_TRY(c->h0w.ensure(h0_wide_scratch_bytes(n)));
+    HIP_TRY(launch_h0_wide(c->W.as<uint32_t>(), n, c->cstate.as<CloudState>(), c->h0.as<H0Pair>(),
+                           bm + bm_off[1], c->h0w.p, s));
+  } else {
+    HIP_TRY(launch_batch_h0(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1,
+                            c->cstate.as<CloudState>(), c->h0.as<H0Pair>(), n, bm + bm_off[1], s));
+  }
   HIP_TRY(hipEventRecord(c->ev1, s));
   CloudState cs;
   HIP_TRY(hipMemcpyAsync(c->h_cstate.p, c->cstate.p, sizeof(CloudState), hipMemcpyDeviceToHost, s));
