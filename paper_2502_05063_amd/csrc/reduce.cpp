@@ -341,13 +341,37 @@ class WorkColumn {
   // bucket 0 holds the rows at the current rank that are not in a run yet
   void push(K k) { b_[bucket(ks_.rank(k))].push_back(k); }
 
+  // push m rows in one go: their buckets first, then one resize per bucket
+  // and a scatter (the same bucket contents, in the same order, as m pushes)
+  void push_many(const K* k, size_t m) {
+    if (m < 16) {
+      for (size_t i = 0; i < m; ++i) push(k[i]);
+      return;
+    }
+    bk_.resize(m);
+    uint32_t cnt[kBuckets] = {};
+    for (size_t i = 0; i < m; ++i) {
+      const uint8_t b = (uint8_t)bucket(ks_.rank(k[i]));
+      bk_[i] = b;
+      ++cnt[b];
+    }
+    K* dst[kBuckets];
+    for (int b = 0; b < kBuckets; ++b)
+      if (cnt[b]) {
+        const size_t old = b_[b].size();
+        b_[b].resize(old + cnt[b]);
+        dst[b] = b_[b].data() + old;
+      }
+    for (size_t i = 0; i < m; ++i) *dst[bk_[i]]++ = k[i];
+  }
+
   // the pivot (smallest key of odd multiplicity), kept in the column; false
   // if the column is zero
   bool pivot(K* out) {
     for (;;) {
       if (!b_[0].empty()) {
         KVec& l = b_[0];
-        if (!std::is_sorted(l.begin(), l.end())) std::sort(l.begin(), l.end());
+        sort_runs(l);
         KVec v = take();
         v.swap(l);
         add_run(std::move(v));
@@ -396,6 +420,47 @@ class WorkColumn {
 
   int bucket(uint32_t r) const { return r == cur_ ? 0 : 32 - __builtin_clz(r ^ cur_); }
 
+  // Sort the rows of the current rank. They arrive as a concatenation of
+  // ascending runs (a coboundary is pushed in ascending key order, and moves
+  // between buckets keep the order), usually a few: up to kMergeRuns runs
+  // are merged pairwise, more are sorted.
+  void sort_runs(KVec& l) {
+    constexpr int kMergeRuns = 8;
+    size_t bounds[kMergeRuns + 1];
+    int runs = 1;
+    bounds[0] = 0;
+    for (size_t i = 1; i < l.size(); ++i)
+      if (l[i] < l[i - 1]) {
+        if (runs == kMergeRuns) {
+          std::sort(l.begin(), l.end());
+          return;
+        }
+        bounds[runs++] = i;
+      }
+    if (runs == 1) return;
+    bounds[runs] = l.size();
+    KVec t = take();
+    t.resize(l.size());
+    KVec* src = &l;
+    KVec* dst = &t;
+    while (runs > 1) {
+      int out = 0;
+      for (int r = 0; r < runs; r += 2) {
+        // runs r and r + 1 (a last odd run is copied: m = e)
+        const size_t b = bounds[r], m = bounds[r + 1], e = r + 1 < runs ? bounds[r + 2] : m;
+        std::merge(src->begin() + (std::ptrdiff_t)b, src->begin() + (std::ptrdiff_t)m,
+                   src->begin() + (std::ptrdiff_t)m, src->begin() + (std::ptrdiff_t)e,
+                   dst->begin() + (std::ptrdiff_t)b);
+        bounds[out++] = b;
+      }
+      bounds[out] = l.size();
+      runs = out;
+      std::swap(src, dst);
+    }
+    if (src != &l) l.swap(*src);
+    give(std::move(t));
+  }
+
   KVec take() {
     if (spare_.empty()) return {};
     KVec v = std::move(spare_.back());
@@ -434,7 +499,7 @@ class WorkColumn {
     cur_ = m;
     moved_.clear();
     moved_.swap(src);
-    for (K x : moved_) push(x);
+    push_many(moved_.data(), moved_.size());
     return true;
   }
 
@@ -444,12 +509,13 @@ class WorkColumn {
   std::vector<Run> runs_;
   std::vector<KVec> spare_;
   KVec moved_;
+  std::vector<uint8_t> bk_;
   uint32_t cur_ = 0;
 };
 
 // Push the cofacets of simplex v (index c, diameter rank dr) that are not
 // older than the row `limit`; `reach` is its reach row, computed here unless
-// the caller has it; kb is scratch for n keys. Used to add a reduced column R_k whose pivot is
+// the caller has it; kb is scratch for 2n keys. Used to add a reduced column R_k whose pivot is
 // `limit`: R_k is zero below its pivot, so the parts of its summands below
 // the pivot cancel and are not pushed. Cofacet s + {x} has index (Alg. 14)
 // high + C(x, j+2) + low with j+1 the number of vertices below x: vertices
@@ -495,9 +561,16 @@ static void push_coboundary(const HostComplex& H, const Keys<K>& ks, const int* 
       hi = v[pos];
     }
   }
-  // push in decreasing index order
-  for (int x = n - 1; x >= 0; --x)
-    if (reach[x] != kInf && kb[x] >= limit) w.push(kb[x]);
+  // push in decreasing index order; the rows are selected without branches
+  // (whether a row is kept depends on the data) into the second half of kb
+  K* sel = kb + n;
+  size_t m = 0;
+  for (int x = n - 1; x >= 0; --x) {
+    const K k = kb[x];
+    sel[m] = k;
+    m += (size_t)((reach[x] != kInf) & (k >= limit));
+  }
+  w.push_many(sel, m);
 }
 
 // Row index -> column of this dimension's reduced pivots, shared by the
@@ -587,7 +660,7 @@ static void pre_reduce(const HostComplex& H, const Keys<K>& ks, int d, const Col
     int v[kMaxDim + 3], sv[kMaxDim + 3];
     WorkColumn<K> work(ks);
     std::vector<uint32_t> reach((size_t)H.n), areach((size_t)H.n);
-    std::vector<K> kb((size_t)H.n);
+    std::vector<K> kb(2 * (size_t)H.n);
     int64_t local_adds = 0;
     for (;;) {
       const int64_t j0 = next.fetch_add(kChunk);
@@ -699,7 +772,8 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
     VArena arena;
     std::vector<uint32_t> reach, areach;
     std::vector<K> kb;
-    Scratch(const Keys<K>& k, int n) : work(k), reach((size_t)n), areach((size_t)n), kb((size_t)n) {}
+    Scratch(const Keys<K>& k, int n)
+        : work(k), reach((size_t)n), areach((size_t)n), kb(2 * (size_t)n) {}
   };
   std::vector<std::unique_ptr<Scratch>> scratch((size_t)threads);
   auto worker = [&](int self) {
