@@ -535,6 +535,7 @@ static void push_coboundary(const HostComplex& H, const Keys<K>& ks, const int* 
     common_neighbors(H, v, d, mask);
     uint64_t high = 0, low = c;
     int pos = d;
+    size_t m = 0;  // kept rows, selected without branches into kb
     for_each_desc(mask, H.nbw, [&](int x) {
       while (pos >= 0 && v[pos] > x) {
         high += H.C(v[pos], pos + 2);
@@ -542,9 +543,11 @@ static void push_coboundary(const HostComplex& H, const Keys<K>& ks, const int* 
         --pos;
       }
       const K k = ks.make(std::max(dr, reach_of(H, v, d, x)), high + H.C(x, pos + 2) + low);
-      if (k >= limit) w.push(k);
+      kb[m] = k;
+      m += (size_t)(k >= limit);
       return true;
     });
+    w.push_many(kb, m);
     return;
   }
   if (!have_reach) compute_reach(H, v, d, reach);
