@@ -475,7 +475,7 @@ static int barcode_boundary(const ctx* c, int32_t max_dim, orc_result* res) {
   simplex_vec S = {0};
   int32_t K = max_dim + 1;
   if ((rc = enumerate(c, 0, K, &S))) goto done;
-  /* line 2 of Alg. 11: the simplex-wise refinement */
+  /* Alg. 11: the simplex-wise refinement */
   qsort(S.a, (size_t)S.len, sizeof(simplex), cmp_filtration);
   int64_t N = S.len;
 
@@ -544,7 +544,7 @@ static int barcode_boundary(const ctx* c, int32_t max_dim, orc_result* res) {
     if (R[j].len > 0) L[(int64_t)R[j].a[R[j].len - 1]] = j;
   }
 
-  /* pivots (low(j), j) are the pairs (Alg. 11 line 9) */
+  /* pivots (low(j), j) are the pairs (Alg. 11) */
   for (int64_t j = 0; j < N; j++) {
     if (R[j].len == 0) continue;
     int64_t lo = (int64_t)R[j].a[R[j].len - 1];
