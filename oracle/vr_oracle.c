@@ -505,7 +505,7 @@ static int barcode_boundary(const ctx* c, int32_t max_dim, orc_result* res) {
   }
   for (int32_t q = 0; q <= K; q++) qsort(tab[q], (size_t)tlen[q], sizeof(idx_entry), cmp_idx_entry);
 
-  /* line 3: R <- boundary matrix; column j lists the filtration indices of
+  /* Alg. 11: R <- boundary matrix; column j lists the filtration indices of
    * the facets of simplex j (remove one vertex at a time) */
   for (int64_t j = 0; j < N; j++) {
     int32_t q = S.a[j].dim;

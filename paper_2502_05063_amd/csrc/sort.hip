@@ -1,6 +1,6 @@
 // Stable LSD radix sort of Column records (8-bit digits), used to put the
 // non-apparent columns in coboundary order: diameter descending, index
-// ascending (Alg. 18, line 5), grouped by cloud.
+// ascending (Alg. 18), grouped by cloud.
 //
 // Per digit pass, three kernels:
 //   hist     per tile of kTile records, the digit histogram -> counts[digit][tile]
