@@ -611,6 +611,13 @@ class PivotTable {
       if (s == kEmpty) return false;
     }
   }
+  // start loading the slot of row k (a lookup in a large table misses the
+  // caches)
+  void prefetch(uint64_t k) const {
+    const size_t i = slot(k);
+    __builtin_prefetch(&keys_[i]);
+    __builtin_prefetch(&vals_[i]);
+  }
   void insert(uint64_t k, const Partner& p) {
     for (size_t i = slot(k);; i = (i + 1) & mask_) {
       uint64_t e = kEmpty;
@@ -815,6 +822,11 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
       if (nthr == 1) {  // alone: nothing to publish
         if (next >= end) break;
         j = next++;
+        // the table slots of a column a few ahead: most columns need only
+        // a lookup and an insert, each a cache miss in a large table
+        constexpr int64_t kAhead = 8;
+        if (j + kAhead < end && pre[(size_t)(j + kAhead)].nonzero)
+          pivots.prefetch(pre[(size_t)(j + kAhead)].lc);
       } else {
         for (int spins = 0; take_lock.test_and_set(std::memory_order_acquire); backoff(spins)) {
         }
