@@ -7,6 +7,7 @@
 #include "reduce.h"
 
 #include <algorithm>
+#include <iterator>
 #include <atomic>
 #include <chrono>
 #include <memory>
@@ -982,6 +983,170 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
 
   for (size_t i = first; i < pairs.size(); ++i)
     if (pairs[i].death != ~0ull) deaths.push_back(pairs[i].death);
+}
+
+// Explicit matrices: the same blocks and the same stopping rule as
+// reduce_keys, mirrored (Alg. 2 works left to right and a pivot is a
+// column's lowest row, which only falls as columns are added).
+bool reduce_explicit_columns(int64_t n, const int64_t* ptr, const int64_t* rows,
+                             const int32_t* lookup, const int64_t* unstable, int64_t nun,
+                             int threads, int64_t* low, int64_t* additions, bool always_wide) {
+  std::unique_ptr<std::atomic<int64_t>[]> pivot_of(new std::atomic<int64_t>[(size_t)n]);
+  for (int64_t r = 0; r < n; ++r) {
+    pivot_of[r].store(lookup[r], std::memory_order_relaxed);
+    low[r] = -1;
+  }
+  for (int64_t r = 0; r < n; ++r)
+    if (lookup[r] >= 0) low[lookup[r]] = r;
+  if (nun == 0) return true;
+  // reduced unstable columns, by position in `unstable`; red_of[j] is that
+  // position for column j (written before j's pivot is published)
+  std::vector<std::vector<int64_t>> red((size_t)nun);
+  std::vector<int32_t> red_of((size_t)n, -1);
+  for (int64_t u = 0; u < nun; ++u) red_of[(size_t)unstable[u]] = (int32_t)u;
+
+  threads = std::max(threads, 1);
+  std::unique_ptr<std::atomic<int64_t>[]> held_col(new std::atomic<int64_t>[threads]);
+  std::unique_ptr<std::atomic<int64_t>[]> held_low(new std::atomic<int64_t>[threads]);
+  for (int t = 0; t < threads; ++t) {
+    held_col[t].store(-1, std::memory_order_relaxed);
+    held_low[t].store(-1, std::memory_order_relaxed);
+  }
+  std::atomic_flag take_lock = ATOMIC_FLAG_INIT;
+  int64_t next = 0, end = 0;
+  int nthr = 1;
+  std::atomic<int64_t> adds{0}, busy_ns{0};
+  std::atomic<bool> bad{false};
+  auto backoff = [](int& spins) {
+    if (++spins < 64)
+      std::this_thread::yield();
+    else
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+  };
+  auto worker = [&](int self) {
+    const auto w0 = std::chrono::steady_clock::now();
+    double waited = 0;
+    std::vector<int64_t> work, tmp;
+    int64_t local_adds = 0;
+    // returns once no earlier column held by another thread can still end
+    // at row l (its lowest row is already below l)
+    auto settle = [&](int64_t j, int64_t l) {
+      for (int t = 0; t < nthr; ++t) {
+        if (t == self) continue;
+        std::chrono::steady_clock::time_point s0;
+        for (int spins = 0;; backoff(spins)) {
+          const int64_t k = held_col[t].load(std::memory_order_acquire);
+          if (k < 0 || k >= j || held_low[t].load(std::memory_order_acquire) < l) {
+            if (spins > 0)
+              waited += std::chrono::duration<double, std::nano>(
+                            std::chrono::steady_clock::now() - s0).count();
+            break;
+          }
+          if (spins == 0) s0 = std::chrono::steady_clock::now();
+        }
+      }
+    };
+    for (;;) {
+      int64_t u;
+      if (nthr == 1) {
+        if (next >= end) break;
+        u = next++;
+      } else {
+        for (int spins = 0; take_lock.test_and_set(std::memory_order_acquire); backoff(spins)) {
+        }
+        if (next >= end) {
+          take_lock.clear(std::memory_order_release);
+          break;
+        }
+        u = next++;
+        const int64_t jj = unstable[u];
+        held_low[self].store(ptr[jj + 1] > ptr[jj] ? rows[ptr[jj + 1] - 1] : -1,
+                             std::memory_order_release);
+        held_col[self].store(jj, std::memory_order_release);
+        take_lock.clear(std::memory_order_release);
+      }
+      const int64_t j = unstable[u];
+      work.assign(rows + ptr[j], rows + ptr[j + 1]);
+      while (!work.empty()) {
+        const int64_t l = work.back();
+        int64_t k = pivot_of[l].load(std::memory_order_acquire);
+        if (k < 0) {
+          settle(j, l);
+          k = pivot_of[l].load(std::memory_order_acquire);
+          if (k < 0) {  // j's pivot
+            low[j] = l;
+            red[(size_t)u] = work;
+            pivot_of[l].store(j, std::memory_order_release);
+            break;
+          }
+        }
+        if (k >= j) {
+          bad.store(true);
+          break;
+        }
+        const int64_t *kb, *ke;
+        if (red_of[(size_t)k] >= 0) {
+          const std::vector<int64_t>& rk = red[(size_t)red_of[(size_t)k]];
+          kb = rk.data();
+          ke = kb + rk.size();
+        } else {  // a pivot the scan fixed: its column as it is
+          kb = rows + ptr[k];
+          ke = rows + ptr[k + 1];
+        }
+        tmp.clear();
+        std::set_symmetric_difference(work.begin(), work.end(), kb, ke, std::back_inserter(tmp));
+        work.swap(tmp);
+        ++local_adds;
+        if (nthr > 1)
+          held_low[self].store(work.empty() ? -1 : work.back(), std::memory_order_release);
+      }
+    }
+    held_col[self].store(-1, std::memory_order_release);
+    busy_ns += (int64_t)(std::chrono::duration<double, std::nano>(
+                             std::chrono::steady_clock::now() - w0).count() - waited);
+    adds += local_adds;
+  };
+  constexpr double kParallelNs = 2000.0, kMinSpeedup = 2.0;
+  constexpr int64_t kProbeBlock = 256, kMaxNarrowBlock = 8192, kParallelBlock = 8192;
+  constexpr int kCooldown = 16;
+  bool wide = always_wide && threads > 1;
+  int cooldown = 0;
+  int64_t narrow_block = kProbeBlock;
+  while (next < nun) {
+    const int64_t u0 = next;
+    end = std::min<int64_t>(nun, u0 + (wide ? kParallelBlock : narrow_block));
+    nthr = wide ? (int)std::min<int64_t>(threads, end - u0) : 1;
+    busy_ns = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthr; ++t) pool.emplace_back(worker, t);
+    worker(0);
+    for (std::thread& t : pool) t.join();
+    if (bad.load()) return false;
+    const double wall =
+        std::chrono::duration<double, std::nano>(std::chrono::steady_clock::now() - t0).count();
+    const double per_col = (double)busy_ns.load() / (double)(end - u0);
+    if (always_wide) {
+      wide = threads > 1;
+    } else if (wide) {
+      if ((double)busy_ns.load() < kMinSpeedup * wall) {
+        wide = false;
+        cooldown = kCooldown;
+      } else {
+        wide = per_col > kParallelNs;
+      }
+      narrow_block = kProbeBlock;
+    } else {
+      narrow_block = per_col < 0.25 * kParallelNs ? std::min(2 * narrow_block, kMaxNarrowBlock)
+                                                  : kProbeBlock;
+      if (cooldown > 0)
+        --cooldown;
+      else
+        wide = threads > 1 && per_col > kParallelNs;
+    }
+  }
+  *additions += adds.load();
+  return true;
 }
 
 void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,

@@ -91,4 +91,21 @@ void decode_simplex(const HostComplex& H, uint64_t c, int d, int* v);
 // edges, the one with the largest edge index.
 void diameter_edge(const HostComplex& H, uint64_t c, int d, int32_t* u, int32_t* v);
 
+// Alg. 2 (R = D V, only columns to the left added) on the unstable columns
+// of an explicit n x n matrix in CSC form (ptr, rows: rows strictly
+// increasing within a column, each below its column), given the pivots the
+// device scan fixed: lookup[r] = the column whose lowest 1 is the leftmost
+// 1 of row r, else -1 (such a column is reduced as it is). unstable: the
+// other columns, increasing. low[0..n) receives low(R_j), -1 for zero.
+// Long columns are reduced on `threads` threads at once with exactly the
+// sequential additions (a column's lowest row only falls, so column j may
+// stop at row l once every earlier unfinished column's lowest row is below
+// l); `always_wide` forces that for every block (for tests). Returns false
+// if a column's pivot row belongs to a column to its right (the matrix is
+// not one Alg. 2 can reduce with this lookup).
+bool reduce_explicit_columns(int64_t n, const int64_t* ptr, const int64_t* rows,
+                             const int32_t* lookup, const int64_t* unstable, int64_t nun,
+                             int threads, int64_t* low, int64_t* additions,
+                             bool always_wide = false);
+
 }  // namespace vrph

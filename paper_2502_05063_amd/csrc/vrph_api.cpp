@@ -1085,47 +1085,12 @@ extern "C" vrph_status vrph_boundary_pivots(vrph_ctx* c, int64_t ncols, const in
   HIP_TRY(hipStreamSynchronize(s));
   const double t_host = now_ms();
 
-  // Alg. 2 on the unstable columns, in order. pivot_of[r]: the column whose
-  // reduced column has its lowest 1 in row r (stable pivots first).
-  std::vector<int64_t> pivot_of(n, -1);
-  std::fill(low_out, low_out + n, (int64_t)-1);
-  for (size_t r = 0; r < n; ++r)
-    if (hlookup[r] >= 0) {
-      pivot_of[r] = hlookup[r];
-      low_out[hlookup[r]] = (int64_t)r;
-      ++st.scan_pivots;
-    }
+  // Alg. 2 on the unstable columns (host threads, same result as in order)
+  for (size_t r = 0; r < n; ++r) st.scan_pivots += hlookup[r] >= 0;
   std::sort(hun.begin(), hun.end());
-  std::vector<std::vector<int64_t>> red;  // reduced unstable columns
-  std::vector<int32_t> red_of(n, -1);
-  std::vector<int64_t> work, tmp;
-  for (int64_t j : hun) {
-    work.assign(hrows.begin() + hptr[(size_t)j], hrows.begin() + hptr[(size_t)j + 1]);
-    while (!work.empty()) {
-      const int64_t k = pivot_of[(size_t)work.back()];
-      if (k < 0) break;
-      if (k >= j) return fail(VRPH_EINVAL, "vrph_boundary_pivots: not a boundary matrix");
-      const int64_t *kb, *ke;
-      if (red_of[(size_t)k] >= 0) {
-        const std::vector<int64_t>& rk = red[(size_t)red_of[(size_t)k]];
-        kb = rk.data();
-        ke = kb + rk.size();
-      } else {  // a stable pivot's column is reduced as it is
-        kb = hrows.data() + hptr[(size_t)k];
-        ke = hrows.data() + hptr[(size_t)k + 1];
-      }
-      tmp.clear();
-      std::set_symmetric_difference(work.begin(), work.end(), kb, ke, std::back_inserter(tmp));
-      work.swap(tmp);
-      ++st.additions;
-    }
-    if (!work.empty()) {
-      low_out[j] = work.back();
-      pivot_of[(size_t)work.back()] = j;
-      red_of[(size_t)j] = (int32_t)red.size();
-      red.push_back(work);
-    }
-  }
+  if (!reduce_explicit_columns(ncols, hptr.data(), hrows.data(), hlookup.data(), hun.data(),
+                               (int64_t)nun, host_threads(), low_out, &st.additions))
+    return fail(VRPH_EINVAL, "vrph_boundary_pivots: not a boundary matrix");
   for (size_t j = 0; j < n; ++j) st.zero += hptr[j + 1] == hptr[j];
   st.unstable = (int64_t)nun;
   st.stable = ncols - (int64_t)nun;

@@ -95,3 +95,59 @@ def test_thread_counts_agree_and_match_oracle(driver, tmp_path, name, n, max_dim
         assert run(driver, path, max_dim, tau, threads, True) == one, f"{threads} threads"
     assert run(driver, path, max_dim, tau, 8, False) == one
     assert as_set(one) == oracle_set(D, max_dim, thr)
+
+
+# ---------------------------------------------------------------------------
+# the explicit-matrix path's host part (reduce_explicit_columns)
+
+
+@pytest.fixture(scope="module")
+def explicit_driver(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("edrv") / "explicit_reduce_driver")
+    cmd = [hipcc, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           os.path.join(HERE, "explicit_reduce_driver.cpp"), os.path.join(CSRC, "reduce.cpp"),
+           "-lpthread", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return exe
+
+
+def write_csc(path, ptr, rows):
+    with open(path, "wb") as f:
+        f.write(np.int64(len(ptr) - 1).tobytes())
+        f.write(np.ascontiguousarray(ptr, np.int64).tobytes())
+        f.write(np.ascontiguousarray(rows, np.int64).tobytes())
+
+
+def run_explicit(drv, path, threads, wide, clearing):
+    r = subprocess.run([drv, path, str(threads), "1" if wide else "0", "1" if clearing else "0"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    return np.array([int(x) for x in r.stdout.split()], np.int64)
+
+
+@pytest.mark.parametrize("case", ["rips", "random"])
+def test_explicit_thread_counts_agree_and_match_oracle(explicit_driver, tmp_path, case):
+    if case == "rips":
+        D = oracle.pdist(synth.uniform_cube(500, 3, seed=4))
+        ptr, rows = synth.rips2_boundary_csc(D, 0.2)
+        clearing = True
+    else:  # any strictly upper triangular matrix, without clearing
+        rng = np.random.default_rng(6)
+        cols = []
+        for j in range(6000):
+            k = min(j, rng.binomial(j, 0.0006)) if j else 0
+            cols.append(np.sort(rng.choice(j, size=k, replace=False)) if k else np.zeros(0, np.int64))
+        ptr = np.concatenate([[0], np.cumsum([len(c) for c in cols])]).astype(np.int64)
+        rows = np.concatenate(cols).astype(np.int64)
+        clearing = False
+    path = str(tmp_path / "m.bin")
+    write_csc(path, ptr, rows)
+    one = run_explicit(explicit_driver, path, 1, False, clearing)
+    for threads in (2, 8, 16, 16):
+        assert np.array_equal(run_explicit(explicit_driver, path, threads, True, clearing), one)
+    cols = [rows[ptr[j]:ptr[j + 1]].tolist() for j in range(len(ptr) - 1)]
+    assert np.array_equal(one, oracle.reduce_explicit(cols))
