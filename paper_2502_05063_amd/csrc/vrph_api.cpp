@@ -1323,10 +1323,21 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
   // host submatrix reduction, one cloud per task, on a small thread pool
   const double th = now_ms();
   std::atomic<int> next{0};
+  // longest first: clouds are handed out by their estimated reduction cost
+  // (non-apparent columns x coboundary length), so that a heavy cloud does
+  // not start last and stretch the tail
+  std::vector<int> order((size_t)b->count);
+  for (int i = 0; i < b->count; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const int64_t cx = (col_begin[x + 1] - col_begin[x]) * (int64_t)b->clouds[x].n;
+    const int64_t cy = (col_begin[y + 1] - col_begin[y]) * (int64_t)b->clouds[y].n;
+    return cx > cy;
+  });
   auto work = [&]() {
     for (;;) {
-      const int i = next.fetch_add(1);
-      if (i >= b->count) return;
+      const int q = next.fetch_add(1);
+      if (q >= b->count) return;
+      const int i = order[(size_t)q];
       const Cloud& cl = b->clouds[i];
       HostComplex H;
       H.n = cl.n;
