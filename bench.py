@@ -27,8 +27,11 @@ if ROOT not in sys.path:
 METRIC = "barcode wall time (ms) + simplices/sec and HBM GB/s; batched fwd+bwd clouds/sec vs plain"
 # MI355X published peaks used for the roofline
 HBM_PEAK_GBS = 8000.0
-# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit integer / compare lane-ops per second
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit integer / compare lane-ops
+# per second (a wave64 VALU instruction takes a SIMD 4 cycles)
+CLOCK_HZ = 2.4e9
+SIMDS = 256 * 4
+ALU_PEAK_TOPS = SIMDS * 16 * CLOCK_HZ / 1e12
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2502_05063_amd", "csrc", "kernels.hip")
@@ -36,10 +39,11 @@ LDS_MAX_N = 200  # clouds up to this size enumerate from the LDS rank matrix
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "enum_apparent_lds_kernel_sphere3_192.md")
 
 
-def measured_traffic(grid):
-    """HBM bytes per launch of the dominant kernel, from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy
-    calibration recorded there), or None unless that summary was taken on
+def profile_figures(grid):
+    """Per-launch counter figures of the dominant kernel from the committed
+    rocprofv3 summary: HBM bytes (FETCH_SIZE and WRITE_SIZE, scaled by the
+    copy calibration recorded there) and wave64 VALU / SALU instructions
+    (SQ_INSTS_VALU, SQ_INSTS_SALU). Empty unless that summary was taken on
     the current kernel source with the same launch grid."""
     try:
         with open(TRAFFIC_SUMMARY) as f:
@@ -47,32 +51,59 @@ def measured_traffic(grid):
         with open(KERNEL_SRC, "rb") as f:
             src_hash = hashlib.sha256(f.read()).hexdigest()
     except OSError:
-        return None
+        return {}
     h = re.search(r"kernels_hip_sha256:\s*([0-9a-f]{64})", text)
-    b = re.search(r"hbm_bytes_per_launch:\s*([0-9]+)", text)
     g = re.search(r"grid_workgroups:\s*([0-9]+)", text)
-    if not (h and b and g) or h.group(1) != src_hash or int(g.group(1)) != grid:
-        return None
-    return int(b.group(1))
+    if not (h and g) or h.group(1) != src_hash or int(g.group(1)) != grid:
+        return {}
+    out = {}
+    for key in ("hbm_bytes_per_launch", "sq_insts_valu_per_launch", "sq_insts_salu_per_launch"):
+        m = re.search(key + r":\s*([0-9]+)", text)
+        if m:
+            out[key] = int(m.group(1))
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+# the oracle's sample: the first points of the same S^3 cloud, every dimension
+# 0..3 the GPU computes (the oracle's time grows about as n^5 here; all 192
+# points take minutes)
+CPU_SAMPLE_POINTS = 112
 
 
 def cpu_baseline(X, max_dim):
-    """The oracle as it stands, on a bounded sample: same points, dims 0..2."""
+    """The oracle as it stands (one thread: its reduction is sequential), on a
+    bounded sample of the same workload: the first CPU_SAMPLE_POINTS points of
+    the same cloud, dimensions 0..max_dim, full Rips."""
     import oracle
 
-    n = X.shape[0]
-    sample_dim = min(max_dim, 2)
+    Xs = X[:CPU_SAMPLE_POINTS]
+    n = Xs.shape[0]
     t0 = time.perf_counter()
-    D = oracle.pdist(X)
-    oracle.barcode(D, sample_dim, mode=oracle.M2_STREAMED)
+    D = oracle.pdist(Xs)
+    oracle.barcode(D, max_dim, mode=oracle.M3_REDUCTION_MATRIX)
     dt = time.perf_counter() - t0
-    simplices = sum(math.comb(n, d + 1) for d in range(sample_dim + 1))
+    # candidates as the GPU counts them: every d-simplex index, d = 0..max_dim
+    simplices = sum(math.comb(n, d + 1) for d in range(max_dim + 1))
     return {
         "value": simplices / dt,
         "unit": "simplices/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"same {n} points, dimensions 0..{sample_dim} (streamed mode, Alg. 12), {dt:.1f} s",
+        "sample": (f"first {n} of the same 192 points on S^3, dimensions 0..{max_dim}, full Rips "
+                   f"(streamed reduction-matrix mode, one thread), {dt:.1f} s"),
+        "host_cpus": os.cpu_count(),
+        "cpu_model": cpu_model(),
     }
 
 
@@ -216,27 +247,35 @@ def main():
     simplices = sum(s0["candidates"])
     value = simplices / (ms / 1e3)
 
-    # dominant kernel: the dimension-3 enumeration + apparent-pairs kernel
+    # dominant kernel: the dimension-3 enumeration + apparent-pairs kernel.
+    # It is bound by VALU instruction issue (integer compares, index
+    # arithmetic and control of the apparent-pairs test on 64-wide waves), not
+    # by HBM: its operands come from a rank matrix staged in LDS. Its roofline
+    # is the 32-bit VALU lane-op rate, and `achieved` counts the integer
+    # compares the apparent-pairs test needs (Lemma 5.3.6): C(d+1,2) per
+    # candidate for its diameter, d+1 per cofacet the scan examines, C(d+1,2)
+    # per facet whose diameter the second condition computes.
     d = max_dim
     k_ms = float(np.mean([s["apparent_ms"][d] for s in stats]))
     cand, cof, fac = s0["candidates"][d], s0["cofacets"][d], s0["facets"][d]
     cols, app, nonapp = s0["columns"][d], s0["apparent"][d], s0["reduced"][d]
-    # algorithmic bytes of the enumeration (a4) and apparent-pairs (a6) steps
-    # this launch performs, at the method's per-unit data movement: 1 bit of
-    # clearing bitmap read per candidate, an 8-byte key written (a4) and read
-    # back (a6) per column, 16 bytes per apparent pair, 8 bytes per
-    # non-apparent column and, when a next dimension exists, 1 clearing bit
-    # per apparent pair
-    alg_bytes = (cand / 8 + cols * 8 + cols * 8 + app * 16 + nonapp * 8
-                 + (app / 8 if d < max_dim else 0))
-    achieved_gbs = alg_bytes / (k_ms / 1e3) / 1e9
-    # the same launch as integer compares of the apparent-pairs test
-    # (Lemma 5.3.6): C(d+1,2) per candidate for its diameter, d+1 per cofacet
-    # examined by the scan, C(d+1,2) per facet whose diameter the second
-    # condition computes
     ops = cand * math.comb(d + 1, 2) + cof * (d + 1) + fac * math.comb(d + 1, 2)
     achieved_tops = ops / (k_ms / 1e3) / 1e12
-    traffic = measured_traffic(s0["grid"][d])
+    # Bytes an unfused design would move for the same result (Sec. 5.5: an
+    # 8-byte key written by the enumeration and read back by the
+    # apparent-pairs test per column, 16 bytes per apparent pair, 8 per
+    # non-apparent column, 1 clearing bit per candidate and, when a next
+    # dimension exists, per apparent pair). The fused kernel does not move
+    # them: this is an equivalent rate, not HBM traffic.
+    alg_bytes = (cand / 8 + cols * 8 + cols * 8 + app * 16 + nonapp * 8
+                 + (app / 8 if d < max_dim else 0))
+    equiv_gbs = alg_bytes / (k_ms / 1e3) / 1e9
+    prof = profile_figures(s0["grid"][d])
+    traffic = prof.get("hbm_bytes_per_launch")
+    valu = prof.get("sq_insts_valu_per_launch")
+    salu = prof.get("sq_insts_salu_per_launch")
+    # issue capacity: one wave64 VALU instruction per SIMD every 4 cycles
+    simd_cycles = SIMDS * CLOCK_HZ * (k_ms / 1e3)
     out = {
         "metric": METRIC,
         "value": value,
@@ -258,17 +297,25 @@ def main():
         "host_ms_per_dim": [float(np.mean([s["host_ms"][k] for s in stats])) for k in range(d + 1)],
         "columns_per_dim": s0["columns"],
         "apparent_per_dim": s0["apparent"],
+        "emergent_per_dim": s0["emergent"],
         "reduced_per_dim": s0["reduced"],
-        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
+        "additions_per_dim": s0["additions"],
+        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": ALU_PEAK_TOPS,
+                     "unit": "TOP/s", "frac": achieved_tops / ALU_PEAK_TOPS, "traffic": traffic,
                      # the variant with bitmap clearing sets and dense unit tables
                      "kernel": (f"enum_apparent_lds_kernel<{d}, 0>" if n <= LDS_MAX_N
                                 else f"enum_apparent_kernel<{d}, 0>"), "kernel_ms": k_ms,
-                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "ops_per_launch": ops,
                      "grid_workgroups": s0["grid"][d],
-                     "measured_gbs": (traffic / (k_ms / 1e3) / 1e9) if traffic else None,
-                     "alu": {"achieved": achieved_tops, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                             "frac": achieved_tops / ALU_PEAK_TOPS, "ops_per_launch": ops}},
+                     "valu_issue": ({"sq_insts_valu_per_launch": valu,
+                                     "sq_insts_salu_per_launch": salu,
+                                     "frac": valu * 4 / simd_cycles} if valu else None),
+                     "hbm_measured": ({"gbs": traffic / (k_ms / 1e3) / 1e9,
+                                       "frac": traffic / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+                                      if traffic else None),
+                     "hbm_algorithmic_equivalent": {"bytes_per_launch": alg_bytes,
+                                                    "gbs": equiv_gbs,
+                                                    "frac": equiv_gbs / HBM_PEAK_GBS}},
     }
     if not args.no_batched:
         out["batched_fwd_bwd"] = batched_vs_plain(ctx, max(2, min(args.steps, 5)))

@@ -117,6 +117,10 @@ typedef struct {
  *   cofacets        cofacets examined by the apparent-pairs scans
  *   facets          facets of a found cofacet whose diameter the second
  *                   condition of the apparent-pairs test computed
+ *   emergent        non-apparent columns the host reduction paired at their
+ *                   first pivot without any addition (the emergent-pair
+ *                   shortcut of Sec. 5.2.11; apparent + emergent columns are
+ *                   the columns that needed no reduction, Table 5.1)
  *   gpu_ms          device time of dimension d's kernels (HIP events)
  *   apparent_ms     device time of the enumeration + apparent-pairs kernel
  *                   of dimension d alone (HIP events on the call's stream)
@@ -131,6 +135,7 @@ typedef struct {
   int64_t pairs[VRPH_MAX_DIM + 1];
   int64_t cofacets[VRPH_MAX_DIM + 1];
   int64_t facets[VRPH_MAX_DIM + 1];
+  int64_t emergent[VRPH_MAX_DIM + 1];
   double gpu_ms[VRPH_MAX_DIM + 1];
   double apparent_ms[VRPH_MAX_DIM + 1];
   double host_ms[VRPH_MAX_DIM + 1];
@@ -218,8 +223,13 @@ void vrph_batch_destroy(vrph_batch* b);
  * X (-1 = no edge: vertex birth or essential death). g_birth / g_death hold
  * dL/d(birth value) and dL/d(death value). Since the value is |x_u - x_v|,
  *   gX[u] += g (x_u - x_v) / |x_u - x_v|,  gX[v] -= the same,
- * with nothing added for coincident points. gX (n_total x m) is accumulated
- * into, with float32 atomics (summation order is not fixed). */
+ * with nothing added for coincident points. X and gX are n_total x m
+ * (row-major); gX is accumulated into, with float32 atomics (summation order
+ * is not fixed). Every edge entry must be -1 or in [0, n_total): otherwise
+ * the call returns VRPH_EINVAL and gX is left unchanged (the entries are
+ * checked on the device before anything is read or added). The pairs come
+ * from vrph_barcode_pairs / vrph_batch_result (birth_edge, death_edge; batch
+ * results are cloud-local and are offset by the cloud's first point). */
 vrph_status vrph_backward(vrph_ctx* ctx, const float* X, int64_t n_total, int32_t m,
                           const int32_t* edges, int64_t npairs, const float* g_birth,
                           const float* g_death, float* gX, void* hip_stream);

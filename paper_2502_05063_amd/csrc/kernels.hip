@@ -1618,10 +1618,25 @@ hipError_t launch_set_bits(const uint64_t* idx, int64_t count, uint32_t* bitmap,
 // backward: scatter dL/d(value) onto the two points of each diameter edge
 // ---------------------------------------------------------------------------
 
+// Every edge entry must be -1 (no edge) or a point of X: a flag in device
+// memory records any other value before the scatter reads X or writes gX.
+__global__ void backward_check_kernel(const int32_t* __restrict__ edges, int64_t entries,
+                                      int64_t n_total, uint32_t* __restrict__ bad) {
+  bool out_of_range = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < entries;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t e = edges[i];
+    out_of_range |= e < -1 || (int64_t)e >= n_total;
+  }
+  if (__ballot(out_of_range) != 0 && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+}
+
 __global__ void backward_kernel(const float* __restrict__ X, int m,
                                 const int32_t* __restrict__ edges, int64_t npairs,
                                 const float* __restrict__ g_birth,
-                                const float* __restrict__ g_death, float* __restrict__ gX) {
+                                const float* __restrict__ g_death, float* __restrict__ gX,
+                                const uint32_t* __restrict__ bad) {
+  if (*bad) return;  // an edge names no point of X: nothing is read or written
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < 2 * npairs;
        q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = q >> 1;
@@ -1646,12 +1661,18 @@ __global__ void backward_kernel(const float* __restrict__ X, int m,
   }
 }
 
-hipError_t launch_backward(const float* X, int m, const int32_t* edges, int64_t npairs,
-                           const float* g_birth, const float* g_death, float* gX, hipStream_t s) {
-  if (npairs <= 0) return hipSuccess;
-  int64_t blocks = (2 * npairs + kBlock - 1) / kBlock;
+hipError_t launch_backward(const float* X, int64_t n_total, int m, const int32_t* edges,
+                           int64_t npairs, const float* g_birth, const float* g_death, float* gX,
+                           uint32_t* bad, hipStream_t s) {
+  hipError_t e = launch_fill_u32(bad, 1, 0u, s);
+  if (e != hipSuccess || npairs <= 0) return e;
+  int64_t blocks = (4 * npairs + kBlock - 1) / kBlock;
   if (blocks > 4096) blocks = 4096;
-  backward_kernel<<<(int)blocks, kBlock, 0, s>>>(X, m, edges, npairs, g_birth, g_death, gX);
+  backward_check_kernel<<<(int)blocks, kBlock, 0, s>>>(edges, 4 * npairs, n_total, bad);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  blocks = (2 * npairs + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  backward_kernel<<<(int)blocks, kBlock, 0, s>>>(X, m, edges, npairs, g_birth, g_death, gX, bad);
   return hipGetLastError();
 }
 

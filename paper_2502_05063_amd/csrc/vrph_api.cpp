@@ -204,6 +204,7 @@ struct vrph_ctx {
   DevBuf pfx_v, pfx_cum;           // listed prefixes of sparse dimension-2 and 3 enumerations
   DevBuf bscan;                    // scratch of the boundary-matrix scan
   DevBuf h0w;                      // scratch of H0 for large clouds
+  DevBuf bflag;                    // edge check of the backward
   std::vector<uint64_t> h_pfx_cum;
   std::vector<uint64_t> h_units;
 };
@@ -304,7 +305,8 @@ extern "C" void vrph_destroy(vrph_ctx* c) {
                     &c->cols_tmp, &c->sort_work, &c->ap, &c->scal,  &c->clouds,
                     &c->cstate,  &c->h0,    &c->deaths, &c->units,   &c->wr16,
                     &c->rank_bits, &c->sink_ctr, &c->ap_ctr, &c->ap_tmp, &c->hflag,
-                    &c->pfx_v,     &c->pfx_cum,  &c->bscan,  &c->h0w};
+                    &c->pfx_v,     &c->pfx_cum,  &c->bscan,  &c->h0w,
+                    &c->bflag};
   for (DevBuf* b : bufs) b->release();
   for (DevBuf& b : c->hset) b.release();
   c->h_scal.release();
@@ -910,6 +912,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     }
     reduce_dimension(H, d, hcols.data(), nna, host_threads(), prs, deaths, rs);
     bc->stats.additions[d] = rs.additions;
+    bc->stats.emergent[d] = rs.emergent;
     bc->pairs.reserve(bc->pairs.size() + prs.size() + (keep_zero ? hap.size() : 0));
     for (const PairRec& r : prs) bc->pairs.push_back(make_pair(d, r.birth, r.bdiam, r.death, r.ddiam));
     if (keep_zero) {
@@ -1011,8 +1014,14 @@ extern "C" vrph_status vrph_backward(vrph_ctx* c, const float* X, int64_t n_tota
     return fail(VRPH_EINVAL, "vrph_backward: NULL pair arrays");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
-  HIP_TRY(launch_backward(X, m, edges, npairs, g_birth, g_death, gX, s));
+  HIP_TRY(c->bflag.ensure(sizeof(uint32_t)));
+  HIP_TRY(launch_backward(X, n_total, m, edges, npairs, g_birth, g_death, gX,
+                          c->bflag.as<uint32_t>(), s));
+  uint32_t bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, c->bflag.p, sizeof(bad), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (bad)
+    return fail(VRPH_EINVAL, "vrph_backward: an edge entry is neither -1 nor a point in [0, n_total)");
   return VRPH_OK;
 }
 
@@ -1372,6 +1381,7 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
           }
         r.stats.reduced[1] = ce - cb;
         r.stats.additions[1] = rs.additions;
+        r.stats.emergent[1] = rs.emergent;
       }
       finish_pairs(&r, H, b->max_dim, keep_zero, 1);
     }

@@ -198,8 +198,11 @@ hipError_t launch_boundary_scan(int64_t n, const int64_t* col_ptr, const int64_t
                                 uint32_t* left, int32_t* lookup, uint8_t* stable,
                                 int64_t* unstable, unsigned long long* count, uint32_t* err,
                                 bool clearing, hipStream_t s);
-hipError_t launch_backward(const float* X, int m, const int32_t* edges, int64_t npairs,
-                           const float* g_birth, const float* g_death, float* gX, hipStream_t s);
+// `bad` (one device word) is set when an edge entry is neither -1 nor in
+// [0, n_total); then the scatter reads and writes nothing.
+hipError_t launch_backward(const float* X, int64_t n_total, int m, const int32_t* edges,
+                           int64_t npairs, const float* g_birth, const float* g_death, float* gX,
+                           uint32_t* bad, hipStream_t s);
 
 // ---- sort.hip ----
 // Stable LSD radix sort of Column records ascending by (cloud, key_hi, cidx),

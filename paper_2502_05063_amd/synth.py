@@ -107,6 +107,8 @@ CONFIGS = {
     "c3_o3_1024": dict(max_dim=3, threshold=1.8),
     "c4_batch256": dict(max_dim=1, threshold=float("inf")),
     "c5_torus64x500": dict(max_dim=1, threshold=float("inf")),
+    # the o3 recipe at the paper's size (Table 5.2: 4096 points, threshold 1.4)
+    "o3_4096": dict(max_dim=3, threshold=1.4),
 }
 
 

@@ -48,6 +48,7 @@ class Stats(ctypes.Structure):
         ("pairs", ctypes.c_int64 * (MAX_DIM + 1)),
         ("cofacets", ctypes.c_int64 * (MAX_DIM + 1)),
         ("facets", ctypes.c_int64 * (MAX_DIM + 1)),
+        ("emergent", ctypes.c_int64 * (MAX_DIM + 1)),
         ("gpu_ms", ctypes.c_double * (MAX_DIM + 1)),
         ("apparent_ms", ctypes.c_double * (MAX_DIM + 1)),
         ("host_ms", ctypes.c_double * (MAX_DIM + 1)),
@@ -60,7 +61,8 @@ class Stats(ctypes.Structure):
 
     def to_dict(self):
         k = self.max_dim + 1
-        out = {f: list(getattr(self, f))[:k] for f, _ in self._fields_[:12]}
+        out = {f: list(getattr(self, f))[:k] for f, t in self._fields_
+               if issubclass(t, ctypes.Array)}
         out.update(tau_eff=self.tau_eff, max_dim=self.max_dim, total_ms=self.total_ms)
         return out
 

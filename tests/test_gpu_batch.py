@@ -251,3 +251,25 @@ def test_c5_full_gradient_against_oracle(ctx):
         assert err <= 1e-5, err
     finally:
         b.close()
+
+
+def test_backward_rejects_edges_outside_x(ctx):
+    import torch
+
+    from paper_2502_05063_amd import vrph
+
+    X = torch.rand(10, 3, device="cuda")
+    gX = torch.zeros_like(X)
+    g = torch.ones(1, device="cuda")
+    # a point past the end, an entry below -1, the largest int32
+    for bad in ([0, 10, -1, -1], [-2, 1, -1, -1], [1, 0, 3, 2**31 - 1]):
+        edges = torch.tensor([bad], dtype=torch.int32, device="cuda")
+        with pytest.raises(vrph.VrphError) as ei:
+            ctx.backward(X, edges, g, g, gX)
+        assert ei.value.status == vrph.EINVAL
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(gX)) == 0, "a rejected call changed gX"
+    edges = torch.tensor([[1, 0, -1, -1]], dtype=torch.int32, device="cuda")
+    ctx.backward(X, edges, g, g, gX)
+    d = (X[1] - X[0]) / torch.linalg.norm(X[1] - X[0])
+    assert torch.allclose(gX[1], d) and torch.allclose(gX[0], -d)

@@ -1,5 +1,6 @@
 """Full-size parity: the GPU barcodes of the sphere_3_192-like and o3-like
-workloads against expected values written by the CPU oracle alone
+workloads (and o3 at the paper's size), with the default and with the
+autotuned launches, against expected values written by the CPU oracle alone
 (tests/golden/make_golden.py): every pair including zero-persistence ones
 (SHA-256 of the canonical list), the pairs of nonzero persistence one by
 one, the columns per dimension, and the apparent decisions of sampled
@@ -19,16 +20,13 @@ pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
-@pytest.fixture(scope="module")
-def ctx():
+def new_ctx():
     import torch
 
     from paper_2502_05063_amd import vrph
 
     assert torch.cuda.is_available()
-    c = vrph.Context()
-    yield c
-    c.close()
+    return vrph.Context()
 
 
 def strip(pairs):
@@ -46,37 +44,53 @@ def golden_nonzero(g):
     return out
 
 
-@pytest.mark.parametrize("name,gen", [
+CASES = [
     ("c2_sphere192", lambda: synth.sphere(192, 3, seed=0)),
     ("c3_o3_1024", lambda: synth.orthogonal_3x3(1024, seed=0)),
-])
-def test_full_size_against_oracle_golden(ctx, name, gen):
+    # the o3 recipe at the paper's size (Table 5.2): 4096 points, threshold 1.4
+    ("o3_4096", lambda: synth.orthogonal_3x3(4096, seed=0)),
+]
+
+
+# `autotuned` is the launch the benchmark times: a fresh context tunes the
+# enumeration launches on this very input, then both calls below run with
+# the tuned unit sizes and grids.
+@pytest.mark.parametrize("autotune", [False, True], ids=["default", "autotuned"])
+@pytest.mark.parametrize("name,gen", CASES, ids=[c[0] for c in CASES])
+def test_full_size_against_oracle_golden(name, gen, autotune):
     import torch
 
     path = os.path.join(GOLD, f"{name}.json")
     g = json.load(open(path))
     X = gen()
     thr = float(g["threshold"]) if g["threshold"] != "inf" else float("inf")
-    Xd = torch.from_numpy(X).cuda()
-    # the distances the barcode is computed from equal the oracle's, bit for bit
-    D = ctx.pdist(Xd).cpu().numpy()
-    assert np.array_equal(D.view(np.uint32), oracle.pdist(X).view(np.uint32))
-    bc = ctx.barcode(X=Xd, max_dim=g["max_dim"], threshold=thr)
-    assert np.array_equal(strip(bc.pairs), golden_nonzero(g)), f"{name}: nonzero pairs differ"
-    assert bc.stats["columns"][1:] == g["columns_per_dim"][1:], (bc.stats["columns"], g["columns_per_dim"])
-    full = ctx.barcode(X=Xd, max_dim=g["max_dim"], threshold=thr, keep_zero=True)
-    counts = [int((full.pairs["dim"] == d).sum()) for d in range(g["max_dim"] + 1)]
-    assert counts == g["pairs_per_dim"]
-    rec = strip(full.pairs)
-    assert hashlib.sha256(rec.tobytes()).hexdigest() == g["full_list_sha256"]
+    ctx = new_ctx()
+    try:
+        Xd = torch.from_numpy(X).cuda()
+        # the distances the barcode is computed from equal the oracle's, bit for bit
+        D = ctx.pdist(Xd).cpu().numpy()
+        assert np.array_equal(D.view(np.uint32), oracle.pdist(X).view(np.uint32))
+        bc = ctx.barcode(X=Xd, max_dim=g["max_dim"], threshold=thr, autotune=autotune)
+        assert np.array_equal(strip(bc.pairs), golden_nonzero(g)), f"{name}: nonzero pairs differ"
+        assert bc.stats["columns"][1:] == g["columns_per_dim"][1:], (bc.stats["columns"],
+                                                                      g["columns_per_dim"])
+        full = ctx.barcode(X=Xd, max_dim=g["max_dim"], threshold=thr, keep_zero=True,
+                           autotune=autotune)
+        counts = [int((full.pairs["dim"] == d).sum()) for d in range(g["max_dim"] + 1)]
+        assert counts == g["pairs_per_dim"]
+        rec = strip(full.pairs)
+        del full
+        assert hashlib.sha256(rec.tobytes()).hexdigest() == g["full_list_sha256"]
 
-    # sampled columns: the GPU's apparent count equals Def. 5.3.4, and every
-    # sampled column the oracle finds apparent is paired that way on the GPU
-    rng = np.random.default_rng(7)
-    d = g["max_dim"]
-    cols = full.pairs[full.pairs["dim"] == d]
-    pick = rng.choice(len(cols), 64, replace=False)
-    for p in cols[pick]:
-        t = oracle.is_apparent(D, d, int(p["birth"]), thr)
-        if t is not None:
-            assert int(p["death"]) == t
+        # sampled columns of the top dimension: every sampled column the oracle
+        # finds apparent (Def. 5.3.4) is paired that way on the GPU
+        rng = np.random.default_rng(7)
+        d = g["max_dim"]
+        cols = rec[rec["dim"] == d]
+        pick = rng.choice(len(cols), 256, replace=False)
+        for p in cols[pick]:
+            t = oracle.is_apparent(D, d, int(p["birth"]), thr)
+            if t is not None:
+                assert int(p["death"]) == t
+    finally:
+        ctx.close()
