@@ -78,7 +78,7 @@ def cpu_model():
 # the oracle's sample: the first points of the same S^3 cloud, every dimension
 # 0..3 the GPU computes (the oracle's time grows about as n^5 here; all 192
 # points take minutes)
-CPU_SAMPLE_POINTS = 112
+CPU_SAMPLE_POINTS = 136
 
 
 def cpu_baseline(X, max_dim):
@@ -179,6 +179,8 @@ def boundary_scan(ctx, reps=3):
         runs.append((st["scan_ms"], (time.perf_counter() - t0) * 1e3, st))
     runs.sort(key=lambda r: r[0])
     scan_ms, wall_ms, st = runs[len(runs) // 2]
+    # the same call without the compression step (same pivots), for comparison
+    _, plain = ctx.boundary_pivots(dptr, drows, compression=False)
     ncols, nnz = len(ptr) - 1, len(rows)
     alg = 38 * ncols + 16 * nnz + 6 * st["scan_pivots"] + 8 * st["unstable"]
     gbs = alg / (scan_ms / 1e3) / 1e9
@@ -186,6 +188,8 @@ def boundary_scan(ctx, reps=3):
             "columns": ncols, "nnz": nnz, "scan_ms": scan_ms, "call_ms": wall_ms,
             "host_ms": st["host_ms"], "stable": st["stable"], "unstable": st["unstable"],
             "scan_pivots": st["scan_pivots"], "additions": st["additions"],
+            "compress_additions": st["compress_additions"], "compressed": st["compressed"],
+            "no_compression": {"host_ms": plain["host_ms"], "additions": plain["additions"]},
             "pivots": int((low >= 0).sum()),
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": alg}}

@@ -61,7 +61,8 @@ typedef enum {
  * context. If the environment variable VRPH_TUNING_FILE names a file,
  * tunings are read from it when the context is created and appended to it
  * when found (lines "arch dimension size_bucket variant unit_size
- * groups_per_cu", variant 0 for the global-memory kernel, 1 for the LDS one). */
+ * groups_per_cu", variant 0 for the global-memory kernel, 1 for the LDS one,
+ * 2 for the dimension-1 kernel over neighbour lists). */
 #define VRPH_AUTOTUNE 4u
 /* Use the global-memory enumeration kernels even when the cloud is small
  * enough (n <= 200) for the kernels that read a 16-bit rank matrix from LDS.
@@ -76,9 +77,12 @@ typedef enum {
 /* Unknown flag bits are rejected with VRPH_EINVAL; vrph_batch_plan accepts
  * only VRPH_KEEP_ZERO_PERSISTENCE and VRPH_NO_ENCLOSING_RADIUS. */
 
-/* vrph_boundary_pivots: no clearing step (for a matrix that is not a
- * boundary matrix, where Lemma 4.2.3 does not hold) */
+/* vrph_boundary_pivots: no clearing step and no compression (for a matrix
+ * that is not a boundary matrix, where Lemmas 4.2.3 and 4.2.4 do not hold) */
 #define VRPH_BOUNDARY_NO_CLEARING 32u
+/* vrph_boundary_pivots: no compression step (Sec. 4.3.3, Alg. 8-9) before
+ * the host reduction; the pivots are the same (for comparing the two) */
+#define VRPH_BOUNDARY_NO_COMPRESSION 64u
 #define VRPH_MAX_DIM 6 /* largest supported max_dim */
 
 typedef struct vrph_ctx vrph_ctx;
@@ -247,9 +251,15 @@ vrph_status vrph_backward(vrph_ctx* ctx, const float* X, int64_t n_total, int32_
  * change (it is stable), zero columns are stable, and the column named by
  * such a pivot's row reduces to zero (clearing, Lemma 4.2.3, Alg. 7; left
  * out with VRPH_BOUNDARY_NO_CLEARING, which makes any strictly upper
- * triangular Z/2 matrix valid). The host then reduces the other (unstable)
- * columns in order with Alg. 2, adding stable pivots' columns as they are
- * and reduced columns of earlier unstable ones.
+ * triangular Z/2 matrix valid). With clearing, the host then compresses
+ * the matrix (Sec. 4.3.3, Alg. 8-9): a row whose column holds some row's
+ * leftmost 1 is zeroed (that column keeps a pivot, Lemma 4.2.5, so the row
+ * never holds one, Lemma 4.2.4), and an entry at the row of a scan pivot of
+ * a column to the left is removed by adding that (compressed) column,
+ * without an addition when it is a single 1 (VRPH_BOUNDARY_NO_COMPRESSION
+ * leaves this out). The host then reduces the other (unstable) columns in
+ * order with Alg. 2, adding stable pivots' columns and reduced columns of
+ * earlier unstable ones. Neither step changes a pivot.
  * low_out: HOST array of ncols int64, receives low(R_j), -1 for a zero
  * column. stats (optional, HOST) receives counts and times. VRPH_EINVAL for
  * a malformed matrix (also a row outside [0, j)) or ncols >= 2^31. */
@@ -259,9 +269,11 @@ typedef struct {
   int64_t stable;      /* columns the scan settled (zero, pivots, cleared) */
   int64_t scan_pivots; /* pivots the scan found (Alg. 5) */
   int64_t unstable;    /* columns reduced on the host */
-  int64_t additions;   /* column additions on the host */
+  int64_t additions;   /* column additions of the host reduction (Alg. 2) */
+  int64_t compress_additions; /* column additions made by the compression */
+  int64_t compressed;  /* entries the compression removed without an addition */
   double scan_ms;      /* the four scan kernels (HIP events) */
-  double host_ms;      /* host reduction and result assembly */
+  double host_ms;      /* compression, host reduction and result assembly */
 } vrph_boundary_stats;
 
 vrph_status vrph_boundary_pivots(vrph_ctx* ctx, int64_t ncols, const int64_t* col_ptr,

@@ -22,6 +22,10 @@ namespace vrph {
 //   stable[j] zero columns, those pivots' columns and, with clearing, the
 //             columns named by their rows (they reduce to zero: Lemma 4.2.3)
 //   unstable  the other columns, one atomic per wave (any order)
+//   destroyer[j] column j holds the leftmost 1 of some row, so it keeps a
+//             pivot whatever is added to it (Lemma 4.2.5): in a boundary
+//             matrix row j then never holds a pivot (Lemma 4.2.4), which
+//             the host's compression uses
 // err (bits): 1 col_ptr decreasing or out of range, 2 rows not strictly
 // increasing, 4 a row outside [0, column).
 // ---------------------------------------------------------------------------
@@ -105,18 +109,25 @@ __global__ __launch_bounds__(kBlock) void bscan_leftmost_kernel(
 __global__ __launch_bounds__(kBlock) void bscan_lookup_kernel(
     int64_t n, const int64_t* __restrict__ col_ptr, const int64_t* __restrict__ rows,
     int64_t nnz, const uint32_t* __restrict__ left, int32_t* __restrict__ lookup,
-    uint8_t* __restrict__ stable, int clearing) {
+    uint8_t* __restrict__ stable, uint8_t* __restrict__ destroyer, int clearing) {
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * kBlock) {
     const int64_t b = col_ptr[j], e = col_ptr[j + 1];
-    if (b < 0 || e <= b || e > nnz) continue;  // zero, or flagged by the scan
-    const int64_t r = rows[e - 1];              // the lowest 1
-    if (r < 0 || r >= j) continue;              // flagged by the scan
-    if (left[r] == (uint32_t)j) {
-      lookup[r] = (int32_t)j;
-      stable[j] = 1;
-      if (clearing) stable[r] = 1;
+    uint8_t holds_leftmost = 0;
+    if (b >= 0 && e > b && e <= nnz) {  // not zero, not flagged by the scan
+      int64_t r = -1;
+      for (int64_t q = b; q < e; ++q) {
+        r = rows[q];
+        if (r < 0 || r >= j) break;  // flagged by the scan
+        holds_leftmost |= left[r] == (uint32_t)j ? 1 : 0;
+      }
+      if (r >= 0 && r < j && left[r] == (uint32_t)j) {  // r: the lowest 1
+        lookup[r] = (int32_t)j;
+        stable[j] = 1;
+        if (clearing) stable[r] = 1;
+      }
     }
+    destroyer[j] = holds_leftmost;
   }
 }
 
@@ -170,15 +181,15 @@ __global__ __launch_bounds__(kBlock) void bscan_unstable_kernel(int64_t n,
 
 hipError_t launch_boundary_scan(int64_t n, const int64_t* col_ptr, const int64_t* rows, int64_t nnz,
                                 uint32_t* left, int32_t* lookup, uint8_t* stable,
-                                int64_t* unstable, unsigned long long* count, uint32_t* err,
-                                bool clearing, hipStream_t s) {
+                                uint8_t* destroyer, int64_t* unstable, unsigned long long* count,
+                                uint32_t* err, bool clearing, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + kBlock - 1) / kBlock;
   if (blocks > 8192) blocks = 8192;
   bscan_init_kernel<<<(int)blocks, kBlock, 0, s>>>(n, left, lookup, stable);
   bscan_leftmost_kernel<<<(int)blocks, kBlock, 0, s>>>(n, col_ptr, rows, nnz, left, stable, err);
   bscan_lookup_kernel<<<(int)blocks, kBlock, 0, s>>>(n, col_ptr, rows, nnz, left, lookup, stable,
-                                                    clearing ? 1 : 0);
+                                                    destroyer, clearing ? 1 : 0);
   const int64_t ublocks = (n + (int64_t)kBlock * kScanRounds - 1) / ((int64_t)kBlock * kScanRounds);
   bscan_unstable_kernel<<<(unsigned)ublocks, kBlock, 0, s>>>(n, stable, unstable, count);
   return hipGetLastError();

@@ -321,18 +321,43 @@ __device__ __forceinline__ unsigned long long edge_key(uint32_t w, int a, int b)
   return ((unsigned long long)w << 32) | (0xFFFFFFFFu - (uint32_t)e);
 }
 
+// Root of x under path halving. Every root is the oldest (largest) vertex of
+// its component, since a merge links the younger root below the older one.
+__device__ __forceinline__ int h0_find(int* parent, int x) {
+  int p = parent[x];
+  while (p != x) {
+    const int pp = parent[p];
+    parent[x] = pp;
+    x = p;
+    p = pp;
+  }
+  return x;
+}
+
 // Phases 2 and 3 of one cloud, by one workgroup of kH0Threads lanes: the
 // m forest edge keys in mst (LDS, room for a power of two >= m) are sorted,
 // cleared in the dimension-1 bitmap bm and paired by union-find with the
-// elder rule (parent and rep: LDS scratch of n entries); the pairs go to o
-// and their number to *count.
-__device__ void h0_finish(unsigned long long* mst, int m, int* parent, unsigned long long* rep,
-                          int n, uint32_t* bm, H0Pair* o, uint32_t* count) {
+// elder rule (parent: LDS scratch of n entries); the pairs go to o and their
+// number to *count.
+//
+// The union-find runs on one wave, 64 edges at a time. A component's root is
+// its oldest vertex, so a merge of roots A and B kills min(A, B) (the
+// birth of the pair) and links it below max(A, B). At the start of a block
+// every lane finds the roots of its edge's two vertices (concurrent path
+// halving only shortens paths: nothing is linked meanwhile). The merges of
+// the block then run in edge order on those labels in registers: merge j
+// reads lane j's two current labels, and every lane renames the killed root
+// to the survivor, so each later merge sees the roots as of its own turn.
+// Each edge joins two components (it is a forest edge), so every merge
+// kills a root once; the block's links are written to parent at its end.
+__device__ void h0_finish(unsigned long long* mst, int m, int* parent, int n, uint32_t* bm,
+                          H0Pair* o, uint32_t* count) {
   const int tid = threadIdx.x;
   // bitonic sort of the m forest edges, ascending (padding with ~0)
   int P = 1;
   while (P < m) P <<= 1;
   for (int i = m + tid; i < P; i += kH0Threads) mst[i] = ~0ull;
+  for (int v = tid; v < n; v += kH0Threads) parent[v] = v;
   __syncthreads();
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
@@ -356,47 +381,59 @@ __device__ void h0_finish(unsigned long long* mst, int m, int* parent, unsigned 
     uint32_t e = 0xFFFFFFFFu - (uint32_t)mst[i];
     atomicOr(&bm[e >> 5], 1u << (e & 31));
   }
+  if (tid >= 64) return;  // the rest is one wave's
 
-  // union-find with the elder rule, one lane
-  for (int v = tid; v < n; v += kH0Threads) {
-    parent[v] = v;
-    rep[v] = (unsigned long long)v;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int k = 0;
-    for (int i = 0; i < m; ++i) {
-      unsigned long long key = mst[i];
-      uint64_t e = 0xFFFFFFFFu - (uint32_t)key;
+  const int lane = tid;
+  for (int base = 0; base < m; base += 64) {
+    const int i = base + lane;
+    const bool live = i < m;
+    const unsigned long long key = live ? mst[i] : 0ull;
+    const uint64_t e = 0xFFFFFFFFu - (uint32_t)key;
+    int la = 0, lb = 0;
+    if (live) {
       int a, b;
       edge_vertices(e, a, b);
-      int ra = a, rb = b;
-      while (parent[ra] != ra) {
-        parent[ra] = parent[parent[ra]];
-        ra = parent[ra];
-      }
-      while (parent[rb] != rb) {
-        parent[rb] = parent[parent[rb]];
-        rb = parent[rb];
-      }
-      const int rep_a = (int)rep[ra], rep_b = (int)rep[rb];
-      int young = rep_a < rep_b ? ra : rb;
-      int old = young == ra ? rb : ra;
-      o[k].death = e;
-      o[k].birth = (uint32_t)(young == ra ? rep_a : rep_b);
-      o[k].diam = (uint32_t)(key >> 32);
-      ++k;
-      parent[young] = old;
+      la = h0_find(parent, a);
+      lb = h0_find(parent, b);
     }
-    for (int v = 0; v < n; ++v)
-      if (parent[v] == v) {
-        o[k].death = ~0ull;
-        o[k].birth = (uint32_t)rep[v];
-        o[k].diam = kInf;
-        ++k;
+    __builtin_amdgcn_wave_barrier();
+    const int cnt = m - base < 64 ? m - base : 64;
+    int dead = 0, keep = 0;
+    for (int j = 0; j < cnt; ++j) {
+      const int A = __builtin_amdgcn_readlane(la, j), B = __builtin_amdgcn_readlane(lb, j);
+      const int young = A < B ? A : B, old = A < B ? B : A;
+      if (lane == j) {
+        dead = young;
+        keep = old;
       }
-    *count = (uint32_t)k;
+      la = la == young ? old : la;
+      lb = lb == young ? old : lb;
+    }
+    if (live) {
+      o[i].death = e;
+      o[i].birth = (uint32_t)dead;
+      o[i].diam = (uint32_t)(key >> 32);
+      parent[dead] = keep;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
+  // the roots left are the components' oldest vertices: essential classes,
+  // in increasing vertex order after the m pairs
+  int k = m;
+  for (int v0 = 0; v0 < n; v0 += 64) {
+    const int v = v0 + lane;
+    const bool root = v < n && parent[v] == v;
+    const unsigned long long bal = __ballot(root);
+    if (root) {
+      const int pos = k + __popcll(bal & ((1ull << lane) - 1ull));
+      o[pos].death = ~0ull;
+      o[pos].birth = (uint32_t)v;
+      o[pos].diam = kInf;
+    }
+    k += __popcll(bal);
+  }
+  if (lane == 0) *count = (uint32_t)k;
 }
 
 __global__ __launch_bounds__(kH0Threads) void batch_h0_kernel(const uint32_t* __restrict__ W,
@@ -490,7 +527,7 @@ __global__ __launch_bounds__(kH0Threads) void batch_h0_kernel(const uint32_t* __
   }
   const int m = m_sh;
   __syncthreads();
-  h0_finish(mst, m, comp, best, n, bitmaps + cl.bm_off, out + (int64_t)c * out_stride,
+  h0_finish(mst, m, comp, n, bitmaps + cl.bm_off, out + (int64_t)c * out_stride,
             &st[c].h0_count);
 }
 
@@ -600,12 +637,11 @@ __global__ __launch_bounds__(kH0Threads) void h0w_finish_kernel(int n, H0Wide w,
                                                                 H0Pair* __restrict__ out,
                                                                 uint32_t* __restrict__ bm) {
   __shared__ unsigned long long mst[kMaxN];
-  __shared__ unsigned long long rep[kMaxN];
   __shared__ int parent[kMaxN];
   const int m = *w.m;  // < n <= kMaxN
   for (int i = threadIdx.x; i < m; i += kH0Threads) mst[i] = w.mst[i];
   __syncthreads();
-  h0_finish(mst, m, parent, rep, n, bm, out, &st->h0_count);
+  h0_finish(mst, m, parent, n, bm, out, &st->h0_count);
 }
 
 size_t h0_wide_scratch_bytes(int n) { return (size_t)n * 24 + 256; }
@@ -1575,6 +1611,108 @@ hipError_t launch_batch_edges(const uint32_t* W, const Cloud* clouds, int count,
   batch_edges_kernel<<<grid, kBlock, 0, s>>>(W, clouds, count, total_edges, bitmaps, cols,
                                              cols_cap, ap, ap_cap, clear_out, nullptr, 0,
                                              counters);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Dimension-1 columns of one sparse cloud in neighbour mode (Sec. 5.3.13,
+// Alg. 15 for d = 1): a one-wave workgroup takes a vertex a, lists its
+// neighbours N(a) = {x : W(a, x) <= tau_eff} in LDS in increasing order (a
+// ballot and a prefix count per 64 vertices of row a), and tests the
+// columns (a, b) with b in N(a), b < a, not cleared. A cofacet {x, a, b}
+// keeps the diameter only if x is in N(a), so condition 1 walks N(a) from
+// the top instead of every x from n-1 down; everything else is the full
+// scan's test.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(64) void edges_nb_kernel(
+    const uint32_t* __restrict__ W, int n, const uint32_t* __restrict__ bm1,
+    Column* __restrict__ cols, uint64_t cols_cap, ApparentPair* __restrict__ ap, uint64_t ap_cap,
+    ClearSet clear_out, unsigned long long* __restrict__ counters) {
+  extern __shared__ uint16_t nbl[];  // N(a), n entries at most
+  const int lane = threadIdx.x;
+  const BufferRows rows(W, n);
+  const unsigned long long lower = (1ull << lane) - 1ull;
+  unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0;
+  for (int a = blockIdx.x; a < n; a += gridDim.x) {
+    uint32_t cnt = 0, below = 0;  // |N(a)| and its entries below a
+    for (int x0 = 0; x0 < n; x0 += 64) {
+      const int x = x0 + lane;
+      const uint32_t w = rows.row_at(a, x < n ? x : n - 1);
+      const bool in = x < n && w != kInf;  // the diagonal holds kInf
+      const unsigned long long bal = __ballot(in);
+      if (in) nbl[cnt + (uint32_t)__popcll(bal & lower)] = (uint16_t)x;
+      cnt += (uint32_t)__popcll(bal);
+      below += (uint32_t)__popcll(__ballot(in && x < a));
+    }
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < below; c0 += 64) {
+      const uint32_t ci = c0 + lane;
+      bool is_col = false, is_app = false;
+      uint32_t diam = kInf;
+      uint64_t le = 0, t = 0;
+      if (ci < below) {
+        const int b = nbl[ci];
+        le = edge_index(a, b);
+        diam = rows.row_at(a, b);
+        is_col = !((bm1[le >> 5] >> (le & 31)) & 1u);  // forest edges are cleared
+        if (is_col) {
+          ++n_cols;
+          const int v[2] = {b, a};
+          uint32_t pw[2][2];
+          pw[1][0] = diam;
+          uint32_t st = 0, fa = 0;
+          const int x = apparent_cofacet_nb<1>(rows, n, v, pw, diam, nbl, cnt, st, fa);
+          n_steps += st;
+          n_facets += fa;
+          if (x >= 0) {
+            is_app = true;
+            ++n_app;
+            const int hi = max(x, a), lo = min(x, b), mid = x + a + b - hi - lo;
+            t = (uint64_t)hi * (hi - 1) * (hi - 2) / 6 + (uint64_t)mid * (mid - 1) / 2 +
+                (uint64_t)lo;
+            clear_insert(clear_out, t);
+          }
+        }
+      }
+      bool any;
+      const uint64_t slot = wave_append(is_col && !is_app, &counters[2], any);
+      if (is_col && !is_app && slot < cols_cap) {
+        Column r;
+        r.key_hi = ~diam;
+        r.cloud = 0;
+        r.cidx = le;
+        cols[slot] = r;
+      }
+      if (ap) {
+        const uint64_t as = wave_append(is_app, &counters[4], any);
+        if (is_app && as < ap_cap) {
+          ApparentPair p;
+          p.s = le;
+          p.t = t;
+          p.diam = diam;
+          p.cloud = 0;
+          ap[as] = p;
+        }
+      }
+    }
+    __syncthreads();  // the list is rebuilt for the next vertex
+  }
+  unsigned long long tot[4] = {n_cols, n_app, n_steps, n_facets};
+  unsigned long long* const dst[4] = {&counters[0], &counters[1], &counters[5], &counters[6]};
+  add_block_counters<64, 4>(tot, dst);
+}
+
+hipError_t launch_edges_nb(const uint32_t* W, int n, const uint32_t* bm1, Column* cols,
+                           uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
+                           ClearSet clear_out, unsigned long long* counters, int grid,
+                           hipStream_t s) {
+  if (n < 2) return hipSuccess;
+  if (grid > n) grid = n;
+  if (grid < 1) grid = 1;
+  const size_t lds = ((size_t)n * sizeof(uint16_t) + 15) & ~(size_t)15;
+  edges_nb_kernel<<<grid, 64, lds, s>>>(W, n, bm1, cols, cols_cap, ap, ap_cap, clear_out,
+                                        counters);
   return hipGetLastError();
 }
 

@@ -1149,6 +1149,124 @@ bool reduce_explicit_columns(int64_t n, const int64_t* ptr, const int64_t* rows,
   return true;
 }
 
+bool compress_explicit(int64_t n, const int64_t* ptr, const int64_t* rows, const int32_t* lookup,
+                       const uint8_t* destroyer, const int64_t* unstable, int64_t nun,
+                       int threads, std::vector<int64_t>& cptr, std::vector<int64_t>& crows,
+                       int64_t* additions, int64_t* dropped) {
+  // compressed pivot columns of the scan, and whether one is a single entry
+  std::vector<int64_t> sarena, sbeg((size_t)n, -1);
+  std::vector<int32_t> slen((size_t)n, 0);
+  std::vector<uint8_t> single((size_t)n, 0);
+  // Alg. 8 on one column c (source rows [b, e), increasing) into `out`
+  // (increasing): rows are taken from the lowest up, so what an addition
+  // brings in (rows above the one it removes) is still to be looked at.
+  auto compress = [&](int64_t c, const int64_t* b, const int64_t* e, std::vector<int64_t>& out,
+                      std::vector<int64_t>& work, std::vector<int64_t>& tmp, int64_t& adds,
+                      int64_t& drops) -> bool {
+    work.assign(b, e);
+    out.clear();
+    while (!work.empty()) {
+      const int64_t r = work.back();
+      work.pop_back();
+      if (destroyer[r]) {  // column r keeps a pivot (Lemma 4.2.5): row r is zero (Lemma 4.2.4)
+        ++drops;
+        continue;
+      }
+      const int64_t p = lookup[r];
+      if (p >= 0 && p < c) {
+        if (single[(size_t)p]) {  // adding column p, a single 1 at row r, removes it
+          ++drops;
+          continue;
+        }
+        // add compressed column p; its lowest 1, at r, cancels the one removed
+        const int64_t* pb = sarena.data() + sbeg[(size_t)p];
+        const int64_t* pe = pb + slen[(size_t)p];
+        if (pe[-1] != r) return false;  // the scan's pivot was compressed away: not a boundary matrix
+        tmp.clear();
+        std::set_symmetric_difference(work.begin(), work.end(), pb, pe - 1, std::back_inserter(tmp));
+        work.swap(tmp);
+        ++adds;
+        continue;
+      }
+      out.push_back(r);
+    }
+    std::reverse(out.begin(), out.end());
+    return true;
+  };
+
+  int64_t adds = 0, drops = 0;
+  {
+    // the scan's pivot columns, in increasing order: a column only adds
+    // compressed pivot columns to its left
+    std::vector<int64_t> piv;
+    for (int64_t r = 0; r < n; ++r)
+      if (lookup[r] >= 0) piv.push_back(lookup[r]);
+    std::sort(piv.begin(), piv.end());
+    std::vector<int64_t> out, work, tmp;
+    for (int64_t p : piv) {
+      if (!compress(p, rows + ptr[p], rows + ptr[p + 1], out, work, tmp, adds, drops)) return false;
+      sbeg[(size_t)p] = (int64_t)sarena.size();
+      slen[(size_t)p] = (int32_t)out.size();
+      single[(size_t)p] = out.size() == 1;
+      sarena.insert(sarena.end(), out.begin(), out.end());
+    }
+  }
+  // the unstable columns are independent of each other: ranges of them on
+  // the host threads, each into an arena of its own
+  threads = (int)std::max<int64_t>(1, std::min<int64_t>(threads, (nun + 4095) / 4096));
+  std::vector<std::vector<int64_t>> arena((size_t)threads);
+  std::vector<int64_t> ubeg((size_t)nun), ulen((size_t)nun);
+  std::vector<int64_t> t_adds((size_t)threads, 0), t_drops((size_t)threads, 0);
+  std::vector<char> t_ok((size_t)threads, 1);
+  auto run = [&](int t) {
+    const int64_t u0 = nun * t / threads, u1 = nun * (t + 1) / threads;
+    std::vector<int64_t> out, work, tmp;
+    for (int64_t u = u0; u < u1; ++u) {
+      const int64_t j = unstable[u];
+      if (!compress(j, rows + ptr[j], rows + ptr[j + 1], out, work, tmp, t_adds[(size_t)t],
+                    t_drops[(size_t)t])) {
+        t_ok[(size_t)t] = 0;
+        return;
+      }
+      ubeg[(size_t)u] = (int64_t)arena[(size_t)t].size();
+      ulen[(size_t)u] = (int64_t)out.size();
+      arena[(size_t)t].insert(arena[(size_t)t].end(), out.begin(), out.end());
+    }
+  };
+  {
+    std::vector<std::thread> pool;
+    for (int t = 1; t < threads; ++t) pool.emplace_back(run, t);
+    run(0);
+    for (std::thread& th : pool) th.join();
+  }
+  for (int t = 0; t < threads; ++t) {
+    if (!t_ok[(size_t)t]) return false;
+    adds += t_adds[(size_t)t];
+    drops += t_drops[(size_t)t];
+  }
+  // the compressed matrix: pivot and unstable columns, every other column zero
+  std::vector<int64_t> len((size_t)n, 0);
+  for (int64_t j = 0; j < n; ++j) len[(size_t)j] = slen[(size_t)j];
+  for (int64_t u = 0; u < nun; ++u) len[(size_t)unstable[u]] = ulen[(size_t)u];
+  cptr.assign((size_t)n + 1, 0);
+  for (int64_t j = 0; j < n; ++j) cptr[(size_t)j + 1] = cptr[(size_t)j] + len[(size_t)j];
+  crows.resize((size_t)cptr[(size_t)n]);
+  for (int64_t j = 0; j < n; ++j)
+    if (sbeg[(size_t)j] >= 0)
+      std::copy(sarena.begin() + sbeg[(size_t)j], sarena.begin() + sbeg[(size_t)j] + slen[(size_t)j],
+                crows.begin() + cptr[(size_t)j]);
+  for (int t = 0; t < threads; ++t) {
+    const int64_t u0 = nun * t / threads, u1 = nun * (t + 1) / threads;
+    for (int64_t u = u0; u < u1; ++u)
+      std::copy(arena[(size_t)t].begin() + ubeg[(size_t)u],
+                arena[(size_t)t].begin() + ubeg[(size_t)u] + ulen[(size_t)u],
+                crows.begin() + cptr[(size_t)unstable[u]]);
+  }
+  *additions += adds;
+  *dropped += drops;
+  return true;
+}
+
 void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t ncols,
                       int threads, std::vector<PairRec>& pairs, std::vector<uint64_t>& deaths,
                       ReduceStats& stats, bool always_wide) {

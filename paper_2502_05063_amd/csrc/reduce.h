@@ -108,4 +108,24 @@ bool reduce_explicit_columns(int64_t n, const int64_t* ptr, const int64_t* rows,
                              int threads, int64_t* low, int64_t* additions,
                              bool always_wide = false);
 
+// Compression before the reduction of an explicit boundary matrix (Sec.
+// 4.3.3, Alg. 8-9), in this reading: a row r whose column holds the leftmost
+// 1 of some row (destroyer[r]; that column keeps a pivot, Lemma 4.2.5) never
+// holds a pivot of a boundary matrix (Lemma 4.2.4), so row r is zeroed in
+// every column; and an entry at a row that is the scan's pivot of a column
+// p to the left is removed by adding column p, compressed first, which is
+// free when the compressed column p is that single entry (the stable
+// columns "having all nonzero entries above compressible" of Alg. 9). Only
+// zeroed rows and additions of a column to a column on its right are used,
+// so the pivots of Alg. 2 do not change. The scan's pivot columns are
+// compressed in increasing order, then the unstable columns on `threads`
+// threads. Writes the compressed matrix (those columns; every other column
+// zero) to cptr / crows in the layout of ptr / rows, adds the additions made
+// to *additions and the entries removed without one to *dropped. Returns
+// false if a scan pivot's own row would be removed (not a boundary matrix).
+bool compress_explicit(int64_t n, const int64_t* ptr, const int64_t* rows, const int32_t* lookup,
+                       const uint8_t* destroyer, const int64_t* unstable, int64_t nun,
+                       int threads, std::vector<int64_t>& cptr, std::vector<int64_t>& crows,
+                       int64_t* additions, int64_t* dropped);
+
 }  // namespace vrph

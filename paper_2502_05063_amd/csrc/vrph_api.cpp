@@ -198,7 +198,8 @@ struct vrph_ctx {
   std::vector<uint64_t> h_binom;
   int binom_n = -1, binom_k = -1;
   std::string arch;
-  // (dimension, size bucket, kernel variant: 0 global, 1 LDS) -> setting
+  // (dimension, size bucket, kernel variant: 0 global, 1 LDS, 2 the
+  // dimension-1 neighbour-list kernel) -> setting
   std::map<std::tuple<int, int, int>, Tune> tuned;
   DevBuf units;                    // unit table of the d >= 2 enumeration
   DevBuf pfx_v, pfx_cum;           // listed prefixes of sparse dimension-2 and 3 enumerations
@@ -252,7 +253,7 @@ static void load_tuning(vrph_ctx* c) {
   std::string arch;
   int d, b, var, chunk, mult;
   while (f >> arch >> d >> b >> var >> chunk >> mult)
-    if (arch == c->arch && d >= 1 && d <= kMaxDim && (var == 0 || var == 1) &&
+    if (arch == c->arch && d >= 1 && d <= kMaxDim && var >= 0 && var <= 2 &&
         chunk >= 64 && chunk <= (1 << 20) && chunk % 64 == 0 && mult >= 1 && mult <= 1024)
       c->tuned[{d, b, var}] = Tune{chunk, mult};
 }
@@ -607,15 +608,21 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   // the edges (v3 > v2 >= 2) within the threshold, largest v2 first; the
   // global-memory kernel then enumerates their suffixes over common
   // neighbours (see PrefixList).
+  // Dimension 1 over a sparse edge set walks neighbour lists too
+  // (launch_edges_nb).
   std::vector<uint32_t> pfx2, pfx3;
-  if (max_dim >= 2 && n >= 3 && !use_lds) {
+  bool sparse_edges = false;
+  if (max_dim >= 1 && n >= 3) {
     uint64_t valid = 0, total = 0;
     for (int a = 1; a < n; ++a)
       for (int b = 0; b < a; ++b) {
         ++total;
         valid += hW[(size_t)a * n + b] != kInf;
       }
-    if (2 * valid < total) {
+    sparse_edges = 2 * valid < total;
+  }
+  if (max_dim >= 2 && n >= 3 && !use_lds) {
+    if (sparse_edges) {
       for (int v2 = n - 1; v2 >= 2; --v2) pfx2.push_back((uint32_t)v2);
       if (max_dim >= 3)
         for (int v2 = n - 2; v2 >= 2; --v2)
@@ -713,12 +720,19 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     auto launch_dim = [&](const Tune& t) -> hipError_t {
       const unsigned max_groups = (unsigned)c->num_cus * (unsigned)t.mult;
       if (d == 1) {
-        launched = max_groups;
         HIP_TRY_E(hipEventRecord(c->ev0, s));
-        HIP_TRY_E(launch_batch_edges(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1,
-                                     (int64_t)ncand, clear_in.bits, c->cols.as<Column>(), cap,
-                                     keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
-                                     clear_out, &dsc->columns, (int)max_groups, s));
+        if (sparse_edges) {
+          launched = std::min<uint64_t>(max_groups, (uint64_t)n);
+          HIP_TRY_E(launch_edges_nb(c->W.as<uint32_t>(), n, clear_in.bits, c->cols.as<Column>(),
+                                    cap, keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
+                                    clear_out, &dsc->columns, (int)launched, s));
+        } else {
+          launched = max_groups;
+          HIP_TRY_E(launch_batch_edges(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1,
+                                       (int64_t)ncand, clear_in.bits, c->cols.as<Column>(), cap,
+                                       keep_zero ? c->ap.as<ApparentPair>() : nullptr, ap_cap,
+                                       clear_out, &dsc->columns, (int)max_groups, s));
+        }
         return hipEventRecord(c->ev2, s);
       }
       // dimension 3 over a sparse edge set: list the prefixes (edges) instead
@@ -773,7 +787,8 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
       return hipStreamSynchronize(s);
     };
     const bool lds_dim = use_lds && d >= 2;
-    const std::tuple<int, int, int> tkey{d, size_bucket(n), lds_dim ? 1 : 0};
+    const std::tuple<int, int, int> tkey{d, size_bucket(n),
+                                         lds_dim ? 1 : (d == 1 && sparse_edges) ? 2 : 0};
     // LDS kernels: two workgroups of kLdsBlock lanes fill a compute unit.
     // Default work-unit size: the power of two in [64, 2^17] that gives the
     // unit takers of the default grid (waves of the LDS kernel, workgroups of
@@ -1035,7 +1050,7 @@ extern "C" vrph_status vrph_boundary_pivots(vrph_ctx* c, int64_t ncols, const in
   if (!c || ncols < 0) return fail(VRPH_EINVAL, "vrph_boundary_pivots: bad argument");
   if (ncols > 0 && (!col_ptr || !low_out))
     return fail(VRPH_EINVAL, "vrph_boundary_pivots: NULL argument");
-  if (flags & ~VRPH_BOUNDARY_NO_CLEARING)
+  if (flags & ~(VRPH_BOUNDARY_NO_CLEARING | VRPH_BOUNDARY_NO_COMPRESSION))
     return fail(VRPH_EINVAL, "vrph_boundary_pivots: unknown flag bits");
   if (ncols >= ((int64_t)1 << 31) - 1)
     return fail(VRPH_EINVAL, "vrph_boundary_pivots: ncols must be below 2^31 - 1");
@@ -1057,10 +1072,11 @@ extern "C" vrph_status vrph_boundary_pivots(vrph_ctx* c, int64_t ncols, const in
   if (nnz > 0 && !rows) return fail(VRPH_EINVAL, "vrph_boundary_pivots: NULL rows");
 
   // scratch: count (u64), err (u32), left (u32 x n), lookup (i32 x n),
-  // unstable (i64 x n), stable (u8 x n)
+  // unstable (i64 x n), stable (u8 x n), destroyer (u8 x n)
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t o_left = 256, o_lookup = o_left + up(4 * n), o_unst = o_lookup + up(4 * n),
-               o_stable = o_unst + up(8 * n), total = o_stable + up(n);
+               o_stable = o_unst + up(8 * n), o_destr = o_stable + up(n),
+               total = o_destr + up(n);
   HIP_TRY(c->bscan.ensure(total));
   char* base = c->bscan.as<char>();
   auto* count = reinterpret_cast<unsigned long long*>(base);
@@ -1069,10 +1085,14 @@ extern "C" vrph_status vrph_boundary_pivots(vrph_ctx* c, int64_t ncols, const in
   auto* lookup = reinterpret_cast<int32_t*>(base + o_lookup);
   auto* unstable = reinterpret_cast<int64_t*>(base + o_unst);
   auto* stable = reinterpret_cast<uint8_t*>(base + o_stable);
+  auto* destroyer = reinterpret_cast<uint8_t*>(base + o_destr);
+  const bool clearing = !(flags & VRPH_BOUNDARY_NO_CLEARING);
+  // compression relies on the boundary property, as clearing does
+  const bool compression = clearing && !(flags & VRPH_BOUNDARY_NO_COMPRESSION);
   HIP_TRY(hipMemsetAsync(base, 0, 16, s));
   HIP_TRY(hipEventRecord(c->ev0, s));
-  HIP_TRY(launch_boundary_scan(ncols, col_ptr, rows, nnz, left, lookup, stable, unstable, count, err,
-                               !(flags & VRPH_BOUNDARY_NO_CLEARING), s));
+  HIP_TRY(launch_boundary_scan(ncols, col_ptr, rows, nnz, left, lookup, stable, destroyer,
+                               unstable, count, err, clearing, s));
   HIP_TRY(hipEventRecord(c->ev1, s));
   uint64_t head[2] = {0, 0};
   HIP_TRY(hipMemcpyAsync(head, base, 16, hipMemcpyDeviceToHost, s));
@@ -1088,7 +1108,9 @@ extern "C" vrph_status vrph_boundary_pivots(vrph_ctx* c, int64_t ncols, const in
   if (nun > n) return fail(VRPH_EDEVICE, "vrph_boundary_pivots: unstable count out of range");
   std::vector<int32_t> hlookup(n);
   std::vector<int64_t> hun(nun), hrows((size_t)nnz);
+  std::vector<uint8_t> hdestr(compression ? n : 0);
   HIP_TRY(hipMemcpyAsync(hlookup.data(), lookup, 4 * n, hipMemcpyDeviceToHost, s));
+  if (compression) HIP_TRY(hipMemcpyAsync(hdestr.data(), destroyer, n, hipMemcpyDeviceToHost, s));
   if (nun) HIP_TRY(hipMemcpyAsync(hun.data(), unstable, 8 * nun, hipMemcpyDeviceToHost, s));
   if (nnz) HIP_TRY(hipMemcpyAsync(hrows.data(), rows, 8 * (size_t)nnz, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1097,8 +1119,19 @@ extern "C" vrph_status vrph_boundary_pivots(vrph_ctx* c, int64_t ncols, const in
   // Alg. 2 on the unstable columns (host threads, same result as in order)
   for (size_t r = 0; r < n; ++r) st.scan_pivots += hlookup[r] >= 0;
   std::sort(hun.begin(), hun.end());
-  if (!reduce_explicit_columns(ncols, hptr.data(), hrows.data(), hlookup.data(), hun.data(),
-                               (int64_t)nun, host_threads(), low_out, &st.additions))
+  const int64_t* rptr = hptr.data();
+  const int64_t* rrows = hrows.data();
+  std::vector<int64_t> cptr, crows;
+  if (compression) {  // Sec. 4.3.3, Alg. 8-9
+    if (!compress_explicit(ncols, hptr.data(), hrows.data(), hlookup.data(), hdestr.data(),
+                           hun.data(), (int64_t)nun, host_threads(), cptr, crows,
+                           &st.compress_additions, &st.compressed))
+      return fail(VRPH_EINVAL, "vrph_boundary_pivots: not a boundary matrix");
+    rptr = cptr.data();
+    rrows = crows.data();
+  }
+  if (!reduce_explicit_columns(ncols, rptr, rrows, hlookup.data(), hun.data(), (int64_t)nun,
+                               host_threads(), low_out, &st.additions))
     return fail(VRPH_EINVAL, "vrph_boundary_pivots: not a boundary matrix");
   for (size_t j = 0; j < n; ++j) st.zero += hptr[j + 1] == hptr[j];
   st.unstable = (int64_t)nun;

@@ -187,17 +187,26 @@ hipError_t launch_batch_edges(const uint32_t* W, const Cloud* clouds, int count,
                               uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
                               ClearSet clear_out, unsigned long long* counters, int grid,
                               hipStream_t s);
+// Dimension-1 columns of one cloud in neighbour mode (sparse complexes): a
+// one-wave workgroup per vertex a lists N(a) in LDS and tests the columns
+// (a, b), b < a; same outputs as launch_batch_edges with one cloud. bm1: the
+// dimension-1 clearing bitmap (the forest edges).
+hipError_t launch_edges_nb(const uint32_t* W, int n, const uint32_t* bm1, Column* cols,
+                           uint64_t cols_cap, ApparentPair* ap, uint64_t ap_cap,
+                           ClearSet clear_out, unsigned long long* counters, int grid,
+                           hipStream_t s);
 hipError_t launch_set_bits(const uint64_t* idx, int64_t count, uint32_t* bitmap, hipStream_t s);
 // Insert count indices into a clearing set (bitmap or hash).
 hipError_t launch_clear_insert(const uint64_t* idx, int64_t count, ClearSet set, hipStream_t s);
 
-// GPU scan of an explicit boundary matrix (Alg. 3-6): left/lookup/stable
-// have n entries, unstable room for n; *count and *err must be zero on
-// entry. Requires n < 2^31.
+// GPU scan of an explicit boundary matrix (Alg. 3-6): left/lookup/stable/
+// destroyer have n entries, unstable room for n; *count and *err must be
+// zero on entry. destroyer[j] = 1 iff column j holds the leftmost 1 of some
+// row. Requires n < 2^31.
 hipError_t launch_boundary_scan(int64_t n, const int64_t* col_ptr, const int64_t* rows, int64_t nnz,
                                 uint32_t* left, int32_t* lookup, uint8_t* stable,
-                                int64_t* unstable, unsigned long long* count, uint32_t* err,
-                                bool clearing, hipStream_t s);
+                                uint8_t* destroyer, int64_t* unstable, unsigned long long* count,
+                                uint32_t* err, bool clearing, hipStream_t s);
 // `bad` (one device word) is set when an edge entry is neither -1 nor in
 // [0, n_total); then the scatter reads and writes nothing.
 hipError_t launch_backward(const float* X, int64_t n_total, int m, const int32_t* edges,

@@ -21,6 +21,7 @@ AUTOTUNE = 4
 NO_LDS = 8
 HASHED_CLEARING = 16
 BOUNDARY_NO_CLEARING = 32
+BOUNDARY_NO_COMPRESSION = 64
 MAX_DIM = 6
 
 PAIR_DTYPE = np.dtype(
@@ -70,7 +71,8 @@ class Stats(ctypes.Structure):
 class BoundaryStats(ctypes.Structure):
     _fields_ = [("columns", ctypes.c_int64), ("zero", ctypes.c_int64), ("stable", ctypes.c_int64),
                 ("scan_pivots", ctypes.c_int64), ("unstable", ctypes.c_int64),
-                ("additions", ctypes.c_int64), ("scan_ms", ctypes.c_double),
+                ("additions", ctypes.c_int64), ("compress_additions", ctypes.c_int64),
+                ("compressed", ctypes.c_int64), ("scan_ms", ctypes.c_double),
                 ("host_ms", ctypes.c_double)]
 
     def to_dict(self):
@@ -236,7 +238,7 @@ class Context:
                                               _stream_ptr(), ctypes.byref(out)))
         return Barcode(out)
 
-    def boundary_pivots(self, col_ptr, rows, *, clearing=True):
+    def boundary_pivots(self, col_ptr, rows, *, clearing=True, compression=True):
         """Pivots low(R_j) of Alg. 2 for an explicit boundary matrix in CSC form
         (col_ptr, rows: 1-D int64 CUDA tensors; rows strictly increasing within a
         column and below it). Returns (low: int64 numpy array, -1 for a zero
@@ -256,7 +258,9 @@ class Context:
         st = BoundaryStats()
         _check(lib().vrph_boundary_pivots(self.h, ncols, _dev_ptr(col_ptr),
                                           _dev_ptr(rows) if rows.numel() else None,
-                                          0 if clearing else BOUNDARY_NO_CLEARING, _stream_ptr(),
+                                          (0 if clearing else BOUNDARY_NO_CLEARING)
+                                          | (0 if compression else BOUNDARY_NO_COMPRESSION),
+                                          _stream_ptr(),
                                           low.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)))
         return low[:ncols], st.to_dict()
 

@@ -70,12 +70,16 @@ def scan_expectation(cols, clearing):
 
 def check(ctx, cols, clearing=True):
     ptr, rows = to_dev(cols)
-    low, st = ctx.boundary_pivots(ptr, rows, clearing=clearing)
     want = oracle.reduce_explicit(cols)
-    assert np.array_equal(low, want), f"{int((low != want).sum())} pivots differ"
     zero, piv, unstable = scan_expectation(cols, clearing)
-    assert (st["zero"], st["scan_pivots"], st["unstable"]) == (zero, piv, unstable)
-    assert st["columns"] == len(cols) and st["stable"] == len(cols) - unstable
+    # with clearing, the host compresses the matrix (Alg. 8-9) unless told not to
+    for compression in ((True, False) if clearing else (True,)):
+        low, st = ctx.boundary_pivots(ptr, rows, clearing=clearing, compression=compression)
+        assert np.array_equal(low, want), f"{int((low != want).sum())} pivots differ"
+        assert (st["zero"], st["scan_pivots"], st["unstable"]) == (zero, piv, unstable)
+        assert st["columns"] == len(cols) and st["stable"] == len(cols) - unstable
+        if not (clearing and compression):
+            assert st["compress_additions"] == 0 and st["compressed"] == 0
     return st
 
 
@@ -158,3 +162,22 @@ def test_invalid_matrices(ctx, case):
     with pytest.raises((vrph.VrphError, ValueError)):
         ctx.boundary_pivots(torch.from_numpy(ptr).cuda(), torch.from_numpy(rows).cuda())
     check(ctx, cols)  # the context stays usable
+
+
+@pytest.mark.parametrize("n,tau,seed", [(500, 0.2, 4), (300, 0.35, 9)])
+def test_compression_on_rips_2_skeletons(ctx, n, tau, seed):
+    """The workload of the explicit-matrix benchmark at smaller sizes: the
+    pivots with and without compression are the oracle's, and the reduction
+    after compression makes no more additions than without it."""
+    import torch
+
+    D = oracle.pdist(synth.uniform_cube(n, 3, seed=seed))
+    ptr, rows = synth.rips2_boundary_csc(D, tau)
+    cols = [rows[ptr[j]:ptr[j + 1]].tolist() for j in range(len(ptr) - 1)]
+    want = oracle.reduce_explicit(cols)
+    dptr, drows = torch.from_numpy(ptr).cuda(), torch.from_numpy(rows).cuda()
+    plain_low, plain = ctx.boundary_pivots(dptr, drows, compression=False)
+    low, st = ctx.boundary_pivots(dptr, drows)
+    assert np.array_equal(plain_low, want) and np.array_equal(low, want)
+    assert st["compressed"] + st["compress_additions"] > 0
+    assert st["additions"] <= plain["additions"]

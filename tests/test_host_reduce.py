@@ -122,11 +122,22 @@ def write_csc(path, ptr, rows):
         f.write(np.ascontiguousarray(rows, np.int64).tobytes())
 
 
-def run_explicit(drv, path, threads, wide, clearing):
-    r = subprocess.run([drv, path, str(threads), "1" if wide else "0", "1" if clearing else "0"],
+def run_explicit(drv, path, threads, wide, clearing, compression=False, counts=False):
+    r = subprocess.run([drv, path, str(threads), "1" if wide else "0", "1" if clearing else "0",
+                        "1" if compression else "0"],
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr
-    return np.array([int(x) for x in r.stdout.split()], np.int64)
+    low = np.array([int(x) for x in r.stdout.split()], np.int64)
+    if not counts:
+        return low
+    info = {}
+    for line in r.stderr.splitlines():
+        w = line.split()
+        if w[0] == "compression":
+            info["compress_additions"], info["removed"] = int(w[2]), int(w[4])
+        elif w[0] == "additions":
+            info["additions"] = int(w[1])
+    return low, info
 
 
 @pytest.mark.parametrize("case", ["rips", "random"])
@@ -151,3 +162,25 @@ def test_explicit_thread_counts_agree_and_match_oracle(explicit_driver, tmp_path
         assert np.array_equal(run_explicit(explicit_driver, path, threads, True, clearing), one)
     cols = [rows[ptr[j]:ptr[j + 1]].tolist() for j in range(len(ptr) - 1)]
     assert np.array_equal(one, oracle.reduce_explicit(cols))
+
+
+# Compression (Sec. 4.3.3, Alg. 8-9) must leave every pivot of Alg. 2 as it
+# is: the pivots with compression, on any thread count, equal the oracle's
+# plain Alg. 2 on the uncompressed matrix.
+@pytest.mark.parametrize("n,tau,seed", [(500, 0.2, 4), (300, 0.35, 9), (120, 0.6, 2)])
+def test_compression_keeps_the_pivots(explicit_driver, tmp_path, n, tau, seed):
+    D = oracle.pdist(synth.uniform_cube(n, 3, seed=seed))
+    ptr, rows = synth.rips2_boundary_csc(D, tau)
+    path = str(tmp_path / "m.bin")
+    write_csc(path, ptr, rows)
+    cols = [rows[ptr[j]:ptr[j + 1]].tolist() for j in range(len(ptr) - 1)]
+    ref = oracle.reduce_explicit(cols)
+    plain, p_info = run_explicit(explicit_driver, path, 1, False, True, False, counts=True)
+    comp, c_info = run_explicit(explicit_driver, path, 1, False, True, True, counts=True)
+    assert np.array_equal(plain, ref)
+    assert np.array_equal(comp, ref)
+    for threads in (2, 8, 16):
+        assert np.array_equal(run_explicit(explicit_driver, path, threads, True, True, True), ref)
+    # the compression does work of its own and leaves the reduction less
+    assert c_info["removed"] + c_info["compress_additions"] > 0
+    assert c_info["additions"] <= p_info["additions"]
