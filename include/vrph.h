@@ -74,8 +74,7 @@ typedef enum {
  * itself where a bitmap would exceed 8 GB (e.g. dimension 3 of 4096
  * points); the flag forces it, for testing. Results are identical. */
 #define VRPH_HASHED_CLEARING 16u
-/* Unknown flag bits are rejected with VRPH_EINVAL; vrph_batch_plan accepts
- * only VRPH_KEEP_ZERO_PERSISTENCE and VRPH_NO_ENCLOSING_RADIUS. */
+/* Unknown flag bits are rejected with VRPH_EINVAL. */
 
 /* vrph_boundary_pivots: no clearing step and no compression (for a matrix
  * that is not a boundary matrix, where Lemmas 4.2.3 and 4.2.4 do not hold) */
@@ -83,6 +82,10 @@ typedef enum {
 /* vrph_boundary_pivots: no compression step (Sec. 4.3.3, Alg. 8-9) before
  * the host reduction; the pivots are the same (for comparing the two) */
 #define VRPH_BOUNDARY_NO_COMPRESSION 64u
+/* vrph_batch_plan: reduce the non-apparent columns of dimension 1 on host
+ * threads instead of on the device (the results are the same; for comparing
+ * the two) */
+#define VRPH_HOST_REDUCTION 128u
 #define VRPH_MAX_DIM 6 /* largest supported max_dim */
 
 typedef struct vrph_ctx vrph_ctx;
@@ -144,7 +147,7 @@ typedef struct {
   double apparent_ms[VRPH_MAX_DIM + 1];
   double host_ms[VRPH_MAX_DIM + 1];
   int32_t grid[VRPH_MAX_DIM + 1];
-  int32_t pad_;
+  int32_t device_reduced; /* 1 if dimension 1 was reduced on the device (batches) */
   float tau_eff;       /* the threshold actually applied */
   int32_t max_dim;
   double total_ms;     /* host wall time of the whole call */
@@ -208,10 +211,15 @@ void vrph_barcode_free(vrph_barcode* bc);
  * and flags, and allocates every device buffer the batch needs up front.
  * Clouds are packed row-major one after another in X_packed
  * (sum(sizes) x m floats). vrph_batch_forward replays one captured HIP graph
- * over all clouds (distances, enclosing radii, H0, enumeration and the
- * apparent-pairs test), then reduces the few non-apparent columns of every
- * cloud on host threads. Each size must satisfy 2 <= size <= 4096 and every
- * cloud uses the same max_dim (<= 1). */
+ * over all clouds: distances, enclosing radii, H0, enumeration and the
+ * apparent-pairs test, and the submatrix reduction of the non-apparent
+ * columns of dimension 1 (Sec. 5.2.9-5.2.11), one workgroup per cloud; then
+ * it copies the pairs back. A cloud whose reduction outgrows its device
+ * tables is reduced on host threads instead, as is every cloud under
+ * VRPH_HOST_REDUCTION. Each size must satisfy 2 <= size <= 4096 and every
+ * cloud uses the same max_dim (<= 1). vrph_batch_plan accepts
+ * VRPH_KEEP_ZERO_PERSISTENCE, VRPH_NO_ENCLOSING_RADIUS and
+ * VRPH_HOST_REDUCTION. */
 vrph_status vrph_batch_plan(vrph_ctx* ctx, const int64_t* sizes, int32_t count, int32_t m,
                             int32_t max_dim, float threshold, uint32_t flags, vrph_batch** out);
 vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, void* hip_stream);

@@ -429,6 +429,25 @@ static void parallel_sort(It first, It last, Cmp cmp, int threads) {
 
 // threads: host threads for the edge lookups and the sort (1 where the
 // caller already runs one cloud per thread)
+// Drops zero persistence (unless keep_zero), sorts canonically (dimension,
+// birth, death) and sets the per-dimension offsets.
+static void order_pairs(vrph_barcode* bc, bool keep_zero, int threads) {
+  std::vector<vrph_pair>& P = bc->pairs;
+  if (!keep_zero)
+    P.erase(std::remove_if(P.begin(), P.end(),
+                           [](const vrph_pair& p) { return !p.essential && p.birth_diam == p.death_diam; }),
+            P.end());
+  parallel_sort(P.begin(), P.end(), [](const vrph_pair& a, const vrph_pair& b) {
+    if (a.dim != b.dim) return a.dim < b.dim;
+    if (a.birth != b.birth) return a.birth < b.birth;
+    return a.death < b.death;
+  }, threads);
+  for (int d = 0; d <= VRPH_MAX_DIM + 1; ++d) bc->off[d] = 0;
+  for (const vrph_pair& p : P) bc->off[p.dim + 1]++;
+  for (int d = 1; d <= VRPH_MAX_DIM + 2; ++d) bc->off[d] += bc->off[d - 1];
+}
+
+// Diameter edges of every pair from the host weights, then order_pairs.
 static void finish_pairs(vrph_barcode* bc, const HostComplex& H, int max_dim, bool keep_zero,
                          int threads) {
   std::vector<vrph_pair>& P = bc->pairs;
@@ -445,14 +464,7 @@ static void finish_pairs(vrph_barcode* bc, const HostComplex& H, int max_dim, bo
       if (!p.essential) diameter_edge(H, p.death, p.dim + 1, &p.death_edge[0], &p.death_edge[1]);
     }
   });
-  parallel_sort(P.begin(), P.end(), [](const vrph_pair& a, const vrph_pair& b) {
-    if (a.dim != b.dim) return a.dim < b.dim;
-    if (a.birth != b.birth) return a.birth < b.birth;
-    return a.death < b.death;
-  }, threads);
-  for (int d = 0; d <= VRPH_MAX_DIM + 1; ++d) bc->off[d] = 0;
-  for (const vrph_pair& p : P) bc->off[p.dim + 1]++;
-  for (int d = 1; d <= VRPH_MAX_DIM + 2; ++d) bc->off[d] += bc->off[d - 1];
+  order_pairs(bc, keep_zero, threads);
   (void)max_dim;
 }
 
@@ -1166,7 +1178,89 @@ struct vrph_batch {
   std::vector<ApparentPair> hap;
   bool sorted_in_tmp = false;
   int64_t last_columns = 0, last_apparent = 0, last_nonapparent = 0;
+  // dimension-1 reduction on the device (unless VRPH_HOST_REDUCTION)
+  bool device_reduce = false;
+  std::vector<DredCloud> hdc;
+  DevBuf ddc, ew, eat, egrp, ecnt, epg, tri, tlog, tab_keys, tab_vals, varena, vbits, vtouch,
+      col_begin, col_end, out_death, out_ddiam, out_dedge, col_voff, col_vlen, dstats;
+  std::vector<unsigned long long> hdeath;
+  std::vector<uint32_t> hddiam, hdedge;
+  std::vector<DredStats> hdstats;
 };
+
+// Buffers of the device reduction, each cloud's region sized from its n:
+// the triangle bitmap ceil(C(n, 3) / 32) words; its log of toggled words up
+// to half of that (more: the bitmap is cleared whole); the pivot table a
+// power of two >= max(1024, E / 4) slots, E = C(n, 2) (a cloud with more
+// than half that many non-apparent columns goes to the host); the V arena
+// max(65536, E / 2) edges (more: the host); 16384 logged V words (more: V
+// is read whole). Bitmaps and counts start at zero and the kernel leaves
+// them at zero; epg starts at ~0 (the diagonal stays so).
+static vrph_status dred_plan(vrph_batch* b) {
+  b->hdc.resize((size_t)b->count);
+  int64_t tri = 0, tlog = 0, tab = 0, va = 0, vt = 0;
+  for (int i = 0; i < b->count; ++i) {
+    const int64_t n = b->clouds[i].n, E = n * (n - 1) / 2;
+    DredCloud& d = b->hdc[(size_t)i];
+    d.tri_off = tri;
+    d.tri_words = std::max<int64_t>((n * (n - 1) * (n - 2) / 6 + 31) / 32, 1);
+    d.log_off = tlog;
+    d.log_cap = (int32_t)std::max<int64_t>(1024, std::min<int64_t>(d.tri_words / 2, 1 << 20));
+    int64_t tc = 1024;
+    while (tc < E / 4) tc <<= 1;
+    d.tab_off = tab;
+    d.tab_cap = (int32_t)tc;
+    d.v_off = va;
+    d.v_cap = (int32_t)std::max<int64_t>(65536, E / 2);
+    d.vt_off = vt;
+    d.vt_cap = 16384;
+    // test hook: "log,vtouch,arena" capacities (0 keeps the default), to
+    // run the overflow paths on small inputs
+    if (const char* e = std::getenv("VRPH_DRED_TEST_CAPS")) {
+      long lc = 0, vc = 0, ac = 0;
+      if (std::sscanf(e, "%ld,%ld,%ld", &lc, &vc, &ac) == 3) {
+        if (lc > 0) d.log_cap = (int32_t)std::min<long>(lc, d.log_cap);
+        if (vc > 0) d.vt_cap = (int32_t)std::min<long>(vc, d.vt_cap);
+        if (ac > 0) d.v_cap = (int32_t)std::min<long>(ac, d.v_cap);
+      }
+    }
+    tri += d.tri_words;
+    tlog += d.log_cap;
+    tab += d.tab_cap;
+    va += d.v_cap;
+    vt += d.vt_cap;
+  }
+  const size_t ne = (size_t)std::max<int64_t>(b->total_edges, 1);
+  const size_t cnt = (size_t)b->count;
+  HIP_TRY(b->ddc.ensure(cnt * sizeof(DredCloud)));
+  HIP_TRY(b->ew.ensure(ne * 4));
+  HIP_TRY(b->eat.ensure(ne * 4));
+  HIP_TRY(b->egrp.ensure(ne * 4));
+  HIP_TRY(b->ecnt.ensure(ne * 4));
+  HIP_TRY(b->epg.ensure((size_t)b->total_w * 8));
+  HIP_TRY(b->tri.ensure((size_t)tri * 4));
+  HIP_TRY(b->tlog.ensure((size_t)tlog * 4));
+  HIP_TRY(b->tab_keys.ensure((size_t)tab * 8));
+  HIP_TRY(b->tab_vals.ensure((size_t)tab * 4));
+  HIP_TRY(b->varena.ensure((size_t)va * 4));
+  HIP_TRY(b->vbits.ensure((size_t)std::max<int64_t>(b->total_words, 1) * 4));
+  HIP_TRY(b->vtouch.ensure((size_t)vt * 4));
+  HIP_TRY(b->col_begin.ensure(cnt * 4));
+  HIP_TRY(b->col_end.ensure(cnt * 4));
+  HIP_TRY(b->out_death.ensure(ne * 8));
+  HIP_TRY(b->out_ddiam.ensure(ne * 4));
+  HIP_TRY(b->out_dedge.ensure(ne * 4));
+  HIP_TRY(b->col_voff.ensure(ne * 4));
+  HIP_TRY(b->col_vlen.ensure(ne * 4));
+  HIP_TRY(b->dstats.ensure(cnt * sizeof(DredStats)));
+  HIP_TRY(hipMemcpy(b->ddc.p, b->hdc.data(), cnt * sizeof(DredCloud), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(b->tri.p, 0, (size_t)tri * 4));
+  HIP_TRY(hipMemset(b->ecnt.p, 0, ne * 4));
+  HIP_TRY(hipMemset(b->vbits.p, 0, (size_t)std::max<int64_t>(b->total_words, 1) * 4));
+  HIP_TRY(hipMemset(b->epg.p, 0xFF, (size_t)b->total_w * 8));
+  HIP_TRY(hipDeviceSynchronize());
+  return VRPH_OK;
+}
 
 extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_t count,
                                        int32_t m, int32_t max_dim, float threshold,
@@ -1175,7 +1269,7 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
     return fail(VRPH_EINVAL, "vrph_batch_plan: bad argument");
   *out = nullptr;
   if (max_dim < 0 || max_dim > 1) return fail(VRPH_EINVAL, "vrph_batch_plan: max_dim must be 0 or 1");
-  if (flags & ~(VRPH_KEEP_ZERO_PERSISTENCE | VRPH_NO_ENCLOSING_RADIUS))
+  if (flags & ~(VRPH_KEEP_ZERO_PERSISTENCE | VRPH_NO_ENCLOSING_RADIUS | VRPH_HOST_REDUCTION))
     return fail(VRPH_EINVAL, "vrph_batch_plan: unsupported flag bits");
   if (std::isnan(threshold) || threshold < 0) return fail(VRPH_EINVAL, "threshold must be >= 0");
   HIP_TRY(hipSetDevice(c->device));
@@ -1228,6 +1322,11 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
   HIP_TRY(b->h_W.ensure((size_t)b->total_w * 4));
   HIP_TRY(hipMemcpy(b->dclouds.p, b->clouds.data(), (size_t)count * sizeof(Cloud),
                     hipMemcpyHostToDevice));
+  b->device_reduce = max_dim >= 1 && !(flags & VRPH_HOST_REDUCTION);
+  if (b->device_reduce) {
+    vrph_status st = dred_plan(b.get());
+    if (st != VRPH_OK) return st;
+  }
   b->results.resize(count);
   *out = b.release();
   return VRPH_OK;
@@ -1240,7 +1339,10 @@ extern "C" void vrph_batch_destroy(vrph_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   DevBuf* bufs[] = {&b->X,    &b->D,        &b->W,         &b->dclouds, &b->cstate,
                     &b->h0,   &b->bitmaps,  &b->cols,      &b->cols_tmp, &b->sort_work,
-                    &b->ap,   &b->counters};
+                    &b->ap,   &b->counters, &b->ddc, &b->ew, &b->eat, &b->egrp, &b->ecnt,
+                    &b->epg,  &b->tri,    &b->tlog,    &b->tab_keys, &b->tab_vals, &b->varena,
+                    &b->vbits, &b->vtouch, &b->col_begin, &b->col_end, &b->out_death,
+                    &b->out_ddiam, &b->out_dedge, &b->col_voff, &b->col_vlen, &b->dstats};
   for (DevBuf* d : bufs) d->release();
   b->h_cstate.release();
   b->h_counters.release();
@@ -1274,6 +1376,17 @@ static hipError_t batch_record(vrph_batch* b, hipStream_t s) {
     return e;
   if (b->max_dim >= 1) {
     const uint64_t cap = (uint64_t)std::max<int64_t>(b->total_edges, 1);
+    int cloud_bits = 0;
+    while ((1 << cloud_bits) < b->count) ++cloud_bits;
+    // edge positions for the device reduction (cols / cols_tmp as scratch,
+    // before the enumeration fills them)
+    if (b->device_reduce &&
+        (e = launch_dred_prepare(b->W.as<uint32_t>(), b->dclouds.as<Cloud>(), b->count,
+                                 b->total_edges, cloud_bits, b->cols.as<Column>(),
+                                 b->cols_tmp.as<Column>(), b->sort_work.p, b->ew.as<uint32_t>(),
+                                 b->eat.as<uint32_t>(), b->egrp.as<uint32_t>(),
+                                 b->epg.as<unsigned long long>(), s)))
+      return e;
     if ((e = launch_batch_edges(b->W.as<uint32_t>(), b->dclouds.as<Cloud>(), b->count,
                                 b->total_edges, b->bitmaps.as<uint32_t>(), b->cols.as<Column>(),
                                 cap, keep_zero ? b->ap.as<ApparentPair>() : nullptr,
@@ -1283,14 +1396,43 @@ static hipError_t batch_record(vrph_batch* b, hipStream_t s) {
       return e;
     int max_edges_bits = 0;
     while ((int64_t(1) << max_edges_bits) < (int64_t)b->max_n * (b->max_n - 1) / 2) ++max_edges_bits;
-    int cloud_bits = 0;
-    while ((1 << cloud_bits) < b->count) ++cloud_bits;
     bool in_tmp = false;
     if ((e = radix_sort_columns(b->cols.as<Column>(), b->cols_tmp.as<Column>(), (int64_t)cap,
                                 max_edges_bits, cloud_bits, b->sort_work.p, s, &sc->nonapparent,
                                 &in_tmp)))
       return e;
     b->sorted_in_tmp = in_tmp;
+    if (b->device_reduce) {
+      DredArgs a{};
+      a.clouds = b->dclouds.as<Cloud>();
+      a.dc = b->ddc.as<DredCloud>();
+      a.count = b->count;
+      a.cols = (in_tmp ? b->cols_tmp : b->cols).as<Column>();
+      a.ncols = &sc->nonapparent;
+      a.col_begin_w = b->col_begin.as<uint32_t>();
+      a.col_end_w = b->col_end.as<uint32_t>();
+      a.col_begin = a.col_begin_w;
+      a.col_end = a.col_end_w;
+      a.epg = b->epg.as<unsigned long long>();
+      a.eat = b->eat.as<uint32_t>();
+      a.egrp = b->egrp.as<uint32_t>();
+      a.ew = b->ew.as<uint32_t>();
+      a.cnt = b->ecnt.as<uint32_t>();
+      a.tri = b->tri.as<uint32_t>();
+      a.tlog = b->tlog.as<uint32_t>();
+      a.tab_keys = b->tab_keys.as<unsigned long long>();
+      a.tab_vals = b->tab_vals.as<uint32_t>();
+      a.varena = b->varena.as<uint32_t>();
+      a.vbits = b->vbits.as<uint32_t>();
+      a.vtouch = b->vtouch.as<uint32_t>();
+      a.out_death = b->out_death.as<unsigned long long>();
+      a.out_ddiam = b->out_ddiam.as<uint32_t>();
+      a.out_dedge = b->out_dedge.as<uint32_t>();
+      a.col_voff = b->col_voff.as<uint32_t>();
+      a.col_vlen = b->col_vlen.as<uint32_t>();
+      a.stats = b->dstats.as<DredStats>();
+      if ((e = launch_dred_reduce(a, (int64_t)cap, b->max_n, s))) return e;
+    }
   }
   if ((e = hipMemcpyAsync(b->h_cstate.p, b->cstate.p, (size_t)b->count * sizeof(CloudState),
                           hipMemcpyDeviceToHost, s)))
@@ -1337,9 +1479,9 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
   // results of the device part
   const bool keep_zero = b->flags & VRPH_KEEP_ZERO_PERSISTENCE;
   const int64_t nna = (int64_t)sc.nonapparent;
+  const bool dev = b->device_reduce && b->max_dim >= 1;
   b->hh0.resize((size_t)b->count * b->max_n);
   b->hcols.resize((size_t)nna);
-  HIP_TRY(hipMemcpyAsync(b->h_W.p, b->W.p, (size_t)b->total_w * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(b->hh0.data(), b->h0.p, b->hh0.size() * sizeof(H0Pair),
                          hipMemcpyDeviceToHost, s));
   if (nna)
@@ -1351,7 +1493,34 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
       HIP_TRY(hipMemcpyAsync(b->hap.data(), b->ap.p, sc.apparent_written * sizeof(ApparentPair),
                              hipMemcpyDeviceToHost, s));
   }
+  if (dev) {
+    b->hdeath.resize((size_t)nna);
+    b->hddiam.resize((size_t)nna);
+    b->hdedge.resize((size_t)nna);
+    b->hdstats.resize((size_t)b->count);
+    if (nna) {
+      HIP_TRY(hipMemcpyAsync(b->hdeath.data(), b->out_death.p, (size_t)nna * 8,
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(b->hddiam.data(), b->out_ddiam.p, (size_t)nna * 4,
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(b->hdedge.data(), b->out_dedge.p, (size_t)nna * 4,
+                             hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipMemcpyAsync(b->hdstats.data(), b->dstats.p, (size_t)b->count * sizeof(DredStats),
+                           hipMemcpyDeviceToHost, s));
+  }
   HIP_TRY(hipStreamSynchronize(s));
+  // the weights on the host: for the host reduction, for a cloud the device
+  // reduction left to it, and for the edges of the apparent pairs
+  bool need_w = !dev || keep_zero;
+  int fallback = 0;
+  if (dev)
+    for (int i = 0; i < b->count; ++i) fallback += b->hdstats[(size_t)i].err != 0;
+  need_w |= fallback > 0;
+  if (need_w && b->max_dim >= 1) {
+    HIP_TRY(hipMemcpyAsync(b->h_W.p, b->W.p, (size_t)b->total_w * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
 
   // per-cloud slices of the sorted columns and of the apparent pairs
   std::vector<int64_t> col_begin(b->count + 1, nna);
@@ -1362,7 +1531,7 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
   if (keep_zero)
     for (size_t j = 0; j < b->hap.size(); ++j) ap_of[b->hap[j].cloud].push_back((uint32_t)j);
 
-  // host submatrix reduction, one cloud per task, on a small thread pool
+  // assembly, and the host reduction where it is needed, one cloud per task
   const double th = now_ms();
   std::atomic<int> next{0};
   // longest first: clouds are handed out by their estimated reduction cost
@@ -1370,9 +1539,10 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
   // not start last and stretch the tail
   std::vector<int> order((size_t)b->count);
   for (int i = 0; i < b->count; ++i) order[(size_t)i] = i;
+  auto host_reduced = [&](int i) { return !dev || b->hdstats[(size_t)i].err != 0; };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    const int64_t cx = (col_begin[x + 1] - col_begin[x]) * (int64_t)b->clouds[x].n;
-    const int64_t cy = (col_begin[y + 1] - col_begin[y]) * (int64_t)b->clouds[y].n;
+    const int64_t cx = host_reduced(x) ? (col_begin[x + 1] - col_begin[x]) * (int64_t)b->clouds[x].n : 0;
+    const int64_t cy = host_reduced(y) ? (col_begin[y + 1] - col_begin[y]) * (int64_t)b->clouds[y].n : 0;
     return cx > cy;
   });
   auto work = [&]() {
@@ -1383,7 +1553,7 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
       const Cloud& cl = b->clouds[i];
       HostComplex H;
       H.n = cl.n;
-      H.W = b->h_W.as<uint32_t>() + cl.w_off;
+      H.W = need_w ? b->h_W.as<uint32_t>() + cl.w_off : nullptr;
       H.binom = b->binoms[i].data();
       H.kmax = 3;
       vrph_barcode& r = b->results[i];
@@ -1396,27 +1566,65 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
         r.pairs.push_back(make_pair(0, h0[k].birth, 0u, h0[k].death, h0[k].diam));
       r.stats.pairs[0] = cst[i].h0_count;
       if (b->max_dim >= 1) {
-        std::vector<PairRec> prs;
-        std::vector<uint64_t> deaths;
-        ReduceStats rs;
         const int64_t cb = col_begin[i], ce = col_begin[i + 1];
-        RankTable ranks;
-        if (ce > cb) {
-          ranks.build(cl.n, H.W);
-          ranks.attach(H);
+        if (!host_reduced(i)) {
+          // pairs of the device reduction, with their edges
+          for (int64_t j = cb; j < ce; ++j) {
+            vrph_pair p = make_pair(1, b->hcols[j].cidx, ~b->hcols[j].key_hi, b->hdeath[j],
+                                    b->hddiam[j]);
+            int v[2];
+            decode_simplex(H, p.birth, 1, v);
+            p.birth_edge[0] = v[1];
+            p.birth_edge[1] = v[0];
+            p.death_edge[0] = p.death_edge[1] = -1;
+            if (!p.essential) {
+              p.death_edge[0] = (int32_t)(b->hdedge[j] >> 16);
+              p.death_edge[1] = (int32_t)(b->hdedge[j] & 0xFFFF);
+            }
+            r.pairs.push_back(p);
+          }
+          r.stats.additions[1] = (int64_t)b->hdstats[(size_t)i].additions;
+          r.stats.emergent[1] = b->hdstats[(size_t)i].emergent;
+          r.stats.device_reduced = 1;
+        } else {
+          std::vector<PairRec> prs;
+          std::vector<uint64_t> deaths;
+          ReduceStats rs;
+          RankTable ranks;
+          if (ce > cb) {
+            ranks.build(cl.n, H.W);
+            ranks.attach(H);
+          }
+          reduce_dimension(H, 1, b->hcols.data() + cb, ce - cb, 1, prs, deaths, rs);
+          for (const PairRec& q : prs) r.pairs.push_back(make_pair(1, q.birth, q.bdiam, q.death, q.ddiam));
+          r.stats.additions[1] = rs.additions;
+          r.stats.emergent[1] = rs.emergent;
         }
-        reduce_dimension(H, 1, b->hcols.data() + cb, ce - cb, 1, prs, deaths, rs);
-        for (const PairRec& q : prs) r.pairs.push_back(make_pair(1, q.birth, q.bdiam, q.death, q.ddiam));
         if (keep_zero)
           for (uint32_t j : ap_of[i]) {
             const ApparentPair& a = b->hap[j];
             r.pairs.push_back(make_pair(1, a.s, a.diam, a.t, a.diam));
           }
         r.stats.reduced[1] = ce - cb;
-        r.stats.additions[1] = rs.additions;
-        r.stats.emergent[1] = rs.emergent;
       }
-      finish_pairs(&r, H, b->max_dim, keep_zero, 1);
+      if (need_w || b->max_dim < 1) {
+        finish_pairs(&r, H, b->max_dim, keep_zero, 1);
+      } else {
+        // edges without the weights: vertex births have none, an H0 death
+        // is its own edge, the dimension-1 pairs carry theirs
+        for (vrph_pair& p : r.pairs)
+          if (p.dim == 0) {
+            p.birth_edge[0] = p.birth_edge[1] = -1;
+            p.death_edge[0] = p.death_edge[1] = -1;
+            if (!p.essential) {
+              int v[2];
+              decode_simplex(H, p.death, 1, v);
+              p.death_edge[0] = v[1];
+              p.death_edge[1] = v[0];
+            }
+          }
+        order_pairs(&r, keep_zero, 1);
+      }
     }
   };
   const int nthreads = std::max(1, std::min<int>(b->count, std::min<int>(16, (int)std::thread::hardware_concurrency())));

@@ -213,6 +213,67 @@ hipError_t launch_backward(const float* X, int64_t n_total, int m, const int32_t
                            int64_t npairs, const float* g_birth, const float* g_death, float* gX,
                            uint32_t* bad, hipStream_t s);
 
+// ---- reduce_dev.hip ----
+// Dimension-1 submatrix reduction on the device, one workgroup per cloud.
+constexpr int kDredThreads = 1024;
+// Per-cloud regions of the device reduction's buffers.
+struct DredCloud {
+  int64_t tri_off;    // first word of the cloud's triangle bitmap (the working column)
+  int64_t tri_words;  // ceil(C(n, 3) / 32)
+  int64_t log_off;    // first entry of its log of toggled bitmap words
+  int64_t tab_off;    // first slot of its pivot table
+  int64_t v_off;      // first entry of its V arena
+  int64_t vt_off;     // first entry of its log of toggled V words
+  int32_t log_cap, tab_cap, v_cap, vt_cap;
+};
+// Per-cloud outcome: additions made, columns paired at their first pivot,
+// and a nonzero err when a table overflowed (the cloud is then reduced on
+// the host instead).
+struct DredStats {
+  unsigned long long additions;
+  uint32_t emergent;
+  uint32_t err;
+};
+struct DredArgs {
+  const Cloud* clouds;
+  const DredCloud* dc;
+  int count;
+  const Column* cols;                // non-apparent columns, sorted (cloud, coboundary order)
+  const unsigned long long* ncols;   // their number (device)
+  uint32_t* col_begin_w;             // per cloud [begin, end) in cols
+  uint32_t* col_end_w;
+  const uint32_t* col_begin;
+  const uint32_t* col_end;
+  const unsigned long long* epg;     // n x n per cloud: (class start << 32 | position), ~0 off edges
+  const uint32_t* eat;               // per position: a << 16 | b
+  const uint32_t* egrp;              // per position: first position of its weight class
+  const uint32_t* ew;                // per position: weight bits
+  uint32_t* cnt;                     // per position: live triangles with that diameter edge
+  uint32_t* tri;                     // triangle bitmaps
+  uint32_t* tlog;
+  unsigned long long* tab_keys;
+  uint32_t* tab_vals;
+  uint32_t* varena;
+  uint32_t* vbits;                   // V bitmaps over edges (Cloud::bm_off layout)
+  uint32_t* vtouch;
+  unsigned long long* out_death;     // per column: death triangle, ~0 if essential
+  uint32_t* out_ddiam;               // death diameter bits (kInf if essential)
+  uint32_t* out_dedge;               // death diameter edge a << 16 | b
+  uint32_t* col_voff;                // per paired column: its V in the arena
+  uint32_t* col_vlen;
+  DredStats* stats;                  // per cloud
+};
+// Edge positions of every cloud: records into rec (total_edges), sorted
+// with rec_tmp and sort_work, then ew / eat / egrp per position and epg.
+hipError_t launch_dred_prepare(const uint32_t* W, const Cloud* clouds, int count,
+                               int64_t total_edges, int cloud_bits, Column* rec, Column* rec_tmp,
+                               void* sort_work, uint32_t* ew, uint32_t* eat, uint32_t* egrp,
+                               unsigned long long* epg, hipStream_t s);
+// Column ranges per cloud, then the reduction (one workgroup per cloud).
+// The bitmaps, counts and V bitmaps must be zero on entry; they are zero
+// again on exit.
+hipError_t launch_dred_reduce(const DredArgs& args, int64_t cols_cap, int max_n, hipStream_t s);
+
 // ---- sort.hip ----
 // Stable LSD radix sort of Column records ascending by (cloud, key_hi, cidx),
 // looking only at the low `cidx_bits` of cidx, all 32 bits of key_hi and the

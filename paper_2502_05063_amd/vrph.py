@@ -22,6 +22,7 @@ NO_LDS = 8
 HASHED_CLEARING = 16
 BOUNDARY_NO_CLEARING = 32
 BOUNDARY_NO_COMPRESSION = 64
+HOST_REDUCTION = 128
 MAX_DIM = 6
 
 PAIR_DTYPE = np.dtype(
@@ -54,7 +55,7 @@ class Stats(ctypes.Structure):
         ("apparent_ms", ctypes.c_double * (MAX_DIM + 1)),
         ("host_ms", ctypes.c_double * (MAX_DIM + 1)),
         ("grid", ctypes.c_int32 * (MAX_DIM + 1)),
-        ("pad_", ctypes.c_int32),
+        ("device_reduced", ctypes.c_int32),
         ("tau_eff", ctypes.c_float),
         ("max_dim", ctypes.c_int32),
         ("total_ms", ctypes.c_double),
@@ -64,7 +65,8 @@ class Stats(ctypes.Structure):
         k = self.max_dim + 1
         out = {f: list(getattr(self, f))[:k] for f, t in self._fields_
                if issubclass(t, ctypes.Array)}
-        out.update(tau_eff=self.tau_eff, max_dim=self.max_dim, total_ms=self.total_ms)
+        out.update(tau_eff=self.tau_eff, max_dim=self.max_dim, total_ms=self.total_ms,
+                   device_reduced=self.device_reduced)
         return out
 
 
@@ -279,17 +281,20 @@ class Context:
         return gX
 
     def batch(self, sizes, m, max_dim=1, threshold=float("inf"), keep_zero=False,
-              no_enclosing=False):
-        return Batch(self, sizes, m, max_dim, threshold, keep_zero, no_enclosing)
+              no_enclosing=False, host_reduction=False):
+        return Batch(self, sizes, m, max_dim, threshold, keep_zero, no_enclosing, host_reduction)
 
 
 class Batch:
     """A batch plan: fixed cloud sizes, one captured graph replayed per forward."""
 
-    def __init__(self, ctx, sizes, m, max_dim, threshold, keep_zero, no_enclosing):
+    def __init__(self, ctx, sizes, m, max_dim, threshold, keep_zero, no_enclosing,
+                 host_reduction=False):
         self.ctx = ctx
         self.sizes = np.ascontiguousarray(sizes, dtype=np.int64)
-        flags = (KEEP_ZERO_PERSISTENCE if keep_zero else 0) | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
+        flags = ((KEEP_ZERO_PERSISTENCE if keep_zero else 0)
+                 | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
+                 | (HOST_REDUCTION if host_reduction else 0))
         h = ctypes.c_void_p()
         _check(lib().vrph_batch_plan(ctx.h, self.sizes.ctypes.data_as(ctypes.c_void_p),
                                      len(self.sizes), m, max_dim, threshold, flags,

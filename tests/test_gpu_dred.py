@@ -1,0 +1,156 @@
+"""The dimension-1 submatrix reduction on the device (batches) against the
+host reduction of the same columns and against the oracle.
+
+Pairs (with their edges), the additions made and the columns paired without
+any addition must be the same as on the host, which makes the same
+additions as the column-by-column Alg. 2 with the reduction-matrix
+technique; every cloud must also equal the oracle. Inputs cover ties (lattice
+points: many equal distances), a finite threshold (essential classes in
+dimension 1), graph replays with new data (the working bitmaps and counts
+must return to zero), and the overflow paths (toggle log, V log, V arena:
+the last hands the cloud to the host).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_05063_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2502_05063_amd import vrph
+
+    assert torch.cuda.is_available()
+    c = vrph.Context()
+    yield c
+    c.close()
+
+
+def packed(clouds):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(np.concatenate(clouds), np.float32)).cuda()
+
+
+def strip(pairs):
+    out = np.empty(len(pairs), oracle.PAIR_DTYPE)
+    for f in oracle.PAIR_DTYPE.names:
+        out[f] = pairs[f]
+    return out
+
+
+def lattice(k, jitter_seed=None):
+    g = np.stack(np.meshgrid(*[np.arange(k)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    X = g.astype(np.float32) * 0.25
+    if jitter_seed is not None:
+        rng = np.random.default_rng(jitter_seed)
+        X = X[rng.permutation(len(X))]
+    return np.ascontiguousarray(X)
+
+
+def run_both(ctx, clouds, **kw):
+    dev = ctx.batch([len(c) for c in clouds], 3, max_dim=1, **kw)
+    host = ctx.batch([len(c) for c in clouds], 3, max_dim=1, host_reduction=True, **kw)
+    try:
+        Xp = packed(clouds)
+        return dev.forward(Xp), host.forward(Xp)
+    finally:
+        dev.close()
+        host.close()
+
+
+def check_same(rd, rh, expect_device=True):
+    for i, (a, b) in enumerate(zip(rd, rh)):
+        assert np.array_equal(a.pairs, b.pairs), f"cloud {i}: pairs differ"
+        assert a.stats["reduced"] == b.stats["reduced"], i
+        assert a.stats["additions"] == b.stats["additions"], (i, a.stats["additions"],
+                                                              b.stats["additions"])
+        assert a.stats["emergent"] == b.stats["emergent"], i
+        assert b.stats["device_reduced"] == 0
+        if expect_device:
+            assert a.stats["device_reduced"] == 1, i
+
+
+@pytest.mark.parametrize("case", ["tori", "lattice", "threshold", "keep_zero"])
+def test_device_matches_host_and_oracle(ctx, case):
+    kw = {}
+    if case == "tori":
+        clouds = synth.circle_or_torus_batch(12, 30, 160, 0.05, seed=5)
+    elif case == "lattice":
+        clouds = [lattice(4), lattice(5, jitter_seed=1), lattice(3, jitter_seed=2)]
+    elif case == "threshold":
+        clouds = synth.torus_batch(5, 140, 0.1, seed=6)
+        kw["threshold"] = 0.9
+    else:
+        clouds = synth.circle_or_torus_batch(6, 40, 120, 0.05, seed=7)
+        kw["keep_zero"] = True
+    rd, rh = run_both(ctx, clouds, **kw)
+    check_same(rd, rh)
+    thr = kw.get("threshold", float("inf"))
+    for i, X in enumerate(clouds):
+        ref = oracle.barcode(oracle.pdist(X), 1, thr)
+        if not kw.get("keep_zero"):
+            ref = oracle.nonzero(ref)
+        assert np.array_equal(strip(rd[i].pairs), ref), f"cloud {i} vs oracle"
+    if case == "threshold":
+        # below the enclosing radius: dimension 1 keeps essential classes
+        assert any(((r.dim(1)["essential"] == 1).any() for r in rd))
+
+
+def test_replays_return_to_a_clean_state(ctx):
+    sizes = [120, 45, 200, 80]
+    dev = ctx.batch(sizes, 3, max_dim=1)
+    host = ctx.batch(sizes, 3, max_dim=1, host_reduction=True)
+    try:
+        for seed in range(4):
+            rng = np.random.default_rng(100 + seed)
+            clouds = [synth.torus(n, 2.0, 0.5, 0.1, rng) for n in sizes]
+            Xp = packed(clouds)
+            rd, rh = dev.forward(Xp), host.forward(Xp)
+            check_same(rd, rh)
+    finally:
+        dev.close()
+        host.close()
+
+
+@pytest.mark.parametrize("caps,expect_device", [("16,4,0", True), ("0,0,8", False)],
+                         ids=["logs_overflow", "arena_overflow"])
+def test_overflow_paths(ctx, caps, expect_device):
+    """Tiny toggle and V logs: the bitmaps are cleared whole and V is read
+    whole, still on the device. A tiny V arena: the clouds that outgrow it
+    are reduced on the host. The pairs are the same either way."""
+    clouds = synth.torus_batch(4, 150, 0.1, seed=8)
+    os.environ["VRPH_DRED_TEST_CAPS"] = caps
+    try:
+        dev = ctx.batch([len(c) for c in clouds], 3, max_dim=1)
+    finally:
+        del os.environ["VRPH_DRED_TEST_CAPS"]
+    host = ctx.batch([len(c) for c in clouds], 3, max_dim=1, host_reduction=True)
+    try:
+        Xp = packed(clouds)
+        for _ in range(2):  # and the state left behind is clean for the next forward
+            rd, rh = dev.forward(Xp), host.forward(Xp)
+            check_same(rd, rh, expect_device=expect_device)
+            flags = [r.stats["device_reduced"] for r in rd]
+            if expect_device:
+                assert all(flags)
+            else:
+                assert not all(flags), "no cloud outgrew the 8-entry arena"
+    finally:
+        dev.close()
+        host.close()
+
+
+def test_c5_device_matches_host(ctx):
+    """The differentiable workload at full size (64 tori x 500 points): the
+    same pairs, additions and emergent counts on the device as on the host."""
+    clouds = synth.torus_batch(64, 500, 0.1, seed=0)
+    rd, rh = run_both(ctx, clouds)
+    check_same(rd, rh)
