@@ -109,8 +109,11 @@ def cpu_baseline(X, max_dim):
 
 def batched_vs_plain(ctx, steps):
     """Forward + backward of loss = sum over H1 of (death - birth)^2 on 64 noisy
-    tori of 500 points (sigma 0.1): one batched graph replay vs a per-cloud loop
-    of the single-cloud path, both through torch.autograd on the same GPU."""
+    tori of 500 points (sigma 0.1), through torch.autograd on the same GPU:
+    one batched graph replay that also reduces dimension 1 on the device
+    (nothing but the copy of the pairs on the host), the same batch with that
+    reduction on host threads instead, and a per-cloud loop of the
+    single-cloud path (whose reduction runs on the host)."""
     import numpy as np
     import torch
 
@@ -119,11 +122,15 @@ def batched_vs_plain(ctx, steps):
 
     clouds = synth.torus_batch(64, 500, 0.1, seed=0)
     X = torch.from_numpy(np.concatenate(clouds)).cuda().requires_grad_(True)
-    batch = ctx.batch([len(c) for c in clouds], 3, max_dim=1)
+    sizes = [len(c) for c in clouds]
+    batch = ctx.batch(sizes, 3, max_dim=1)
+    batch_host = ctx.batch(sizes, 3, max_dim=1, host_reduction=True)
 
-    def batched():
-        b, d, _ = batch_persistence(X, batch, 1)
-        ((d - b) ** 2).sum().backward()
+    def batched(b):
+        def run():
+            bi, d, _ = batch_persistence(X, b, 1)
+            ((d - bi) ** 2).sum().backward()
+        return run
 
     parts = [torch.from_numpy(c).cuda().requires_grad_(True) for c in clouds]
 
@@ -133,7 +140,8 @@ def batched_vs_plain(ctx, steps):
             ((d - b) ** 2).sum().backward()
 
     out = {}
-    for name, fn in (("batched", batched), ("plain", plain)):
+    for name, fn in (("batched", batched(batch)), ("batched_host_reduction", batched(batch_host)),
+                     ("plain", plain)):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -145,12 +153,17 @@ def batched_vs_plain(ctx, steps):
         out[f"{name}_ms"] = dt * 1e3
         out[f"{name}_clouds_per_s"] = len(clouds) / dt
     out["speedup"] = out["plain_ms"] / out["batched_ms"]
-    res = batch.forward(X.detach())
-    out["batched_graph_ms"] = res[0].stats["gpu_ms"][0]
-    out["batched_host_reduce_ms"] = res[0].stats["host_ms"][1]
-    out["batched_forward_total_ms"] = res[0].stats["total_ms"]
+    out["speedup_host_reduction"] = out["plain_ms"] / out["batched_host_reduction_ms"]
+    for key, b in (("batched", batch), ("batched_host_reduction", batch_host)):
+        res = b.forward(X.detach())
+        out[f"{key}_graph_ms"] = res[0].stats["gpu_ms"][0]
+        out[f"{key}_host_ms"] = res[0].stats["host_ms"][1]
+        out[f"{key}_forward_total_ms"] = res[0].stats["total_ms"]
+        out[f"{key}_device_reduced_clouds"] = int(sum(r.stats["device_reduced"] for r in res))
+    out["host_threads_batched_host_reduction"] = min(16, os.cpu_count() or 1)
     out["workload"] = "64 noisy tori x 500 points in R^3 (sigma 0.1), dims 0-1, loss sum (death-birth)^2 over H1"
     batch.close()
+    batch_host.close()
     return out
 
 

@@ -15,11 +15,12 @@
 //  - Edges are numbered by their position in the filtration (weight
 //    ascending, index ascending); a triangle's diameter edge is its edge of
 //    largest position (among its longest edges, the one with the largest
-//    index). epg[a][b] holds (first position of the edge's weight class,
-//    position), so the max over a triangle's three entries gives both its
-//    diameter edge and its diameter class. Keys (class << 34 | (2^34 - 1 -
-//    triangle index)) order rows by the filtration: the pivot is the
-//    smallest key.
+//    index), the max of epos[a][b] over its three edges. Positions of equal
+//    weight form a class [start, end). Keys (class start << 34 | (2^34 - 1
+//    - triangle index)) order rows by the filtration: the pivot is the
+//    smallest key. A row is not older than the pivot iff its diameter edge
+//    lies at or after the end of the pivot's class, or within the class and
+//    its triangle index is at most the pivot's.
 //  - The working column is a bitmap over the triangle indices (toggled with
 //    atomic XOR: Z/2 addition) and a count of live triangles per diameter
 //    edge (global) and per 1024 positions (LDS). The pivot only moves up
@@ -34,6 +35,10 @@
 //    zero at the end of each column (or are cleared whole on overflow).
 //
 // A cloud whose tables overflow is flagged and left to the host reduction.
+//
+// All of a cloud's state is touched by its own workgroup only (one compute
+// unit), so its atomics and coherent loads are workgroup-scoped and
+// ordered by the workgroup barrier alone.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -47,7 +52,7 @@ namespace {
 constexpr int kT = kDredThreads;
 constexpr uint64_t kTriMask = (1ull << 34) - 1;
 constexpr unsigned long long kNoKey = ~0ull;
-constexpr unsigned long long kNoEdge = ~0ull;  // epg of a pair that is not an edge
+constexpr uint32_t kNoPos = 0xFFFFFFFFu;           // epos of a pair that is not an edge
 constexpr uint32_t kDredMaxAdditions = 1u << 20;  // per column
 
 __device__ __forceinline__ uint64_t c2(uint64_t v) { return v * (v - 1) / 2; }
@@ -69,8 +74,18 @@ __device__ __forceinline__ void edge_of(uint64_t c, int& a, int& b) {
   b = (int)(c - (uint64_t)x * (uint64_t)(x - 1) / 2);
 }
 
-__device__ __forceinline__ uint32_t load_coherent(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// workgroup-scoped atomics and loads on the cloud's global state
+__device__ __forceinline__ uint32_t wg_load(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t wg_xor(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void wg_add(uint32_t* p, uint32_t v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t wg_exch(uint32_t* p, uint32_t v) {
+  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
@@ -91,6 +106,14 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t w = __shfl_xor(v, o);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
 __device__ __forceinline__ uint64_t table_hash(uint64_t t) { return (t * 0x9E3779B97F4A7C15ull) >> 17; }
 
 // Workgroup-shared state of the reduction kernel.
@@ -99,6 +122,9 @@ struct Shared {
   uint32_t tv[3];               // vertices of the pivot triangle, v2 > v1 > v0
   int32_t owner;                // -1 free, -2 apparent partner, else global column
   uint32_t partner;             // apparent partner (edge index)
+  uint32_t partner_uv;          // its vertices (a << 16 | b)
+  uint32_t partner_pos;         // its position
+  uint32_t gend;                // end of the pivot's weight class
   uint32_t misc[4];
   uint32_t tlog_n, vt_n, arena_n;
   uint32_t tlog_ovf, vt_ovf;
@@ -107,8 +133,21 @@ struct Shared {
   uint32_t err;
   uint32_t list[kT];            // positions of a weight class with live triangles
   uint32_t sedge[kT];           // summand vertices (a << 16 | b)
-  unsigned long long sepg[kT];  // summand epg
+  uint32_t spos[kT];            // summand positions
 };
+
+// the vertices v2 > v1 > v0 of triangle t (Eq. 5.6): the largest v2 with
+// C(v2, 3) <= t (cube root, then an exact fix-up), then the edge t - C(v2, 3)
+__device__ __forceinline__ void tri_vertices(uint64_t t, uint32_t* tv) {
+  int64_t v2 = (int64_t)cbrt(6.0 * (double)t) + 1;
+  while (v2 > 2 && c3((uint64_t)v2) > t) --v2;
+  while (c3((uint64_t)v2 + 1) <= t) ++v2;
+  int v1, v0;
+  edge_of(t - c3((uint64_t)v2), v1, v0);
+  tv[0] = (uint32_t)v2;
+  tv[1] = (uint32_t)v1;
+  tv[2] = (uint32_t)v0;
+}
 
 }  // namespace
 
@@ -151,17 +190,18 @@ __global__ void dred_positions_kernel(const Column* __restrict__ srt, int64_t to
   }
 }
 
-// the first position of every weight class, and epg of every vertex pair
+// the weight class [start, end) of every position, and epos of every vertex pair
 __global__ void dred_groups_kernel(const Column* __restrict__ srt, const Cloud* __restrict__ clouds,
                                    int64_t total_edges, const uint32_t* __restrict__ ew,
-                                   uint32_t* __restrict__ egrp,
-                                   unsigned long long* __restrict__ epg) {
+                                   uint32_t* __restrict__ egrp, uint32_t* __restrict__ egend,
+                                   uint32_t* __restrict__ epos) {
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total_edges;
        g += (int64_t)gridDim.x * blockDim.x) {
     const Column r = srt[g];
     const Cloud cl = clouds[r.cloud];
+    const int64_t end = cl.e_off + (int64_t)cl.n * (cl.n - 1) / 2;
     const uint32_t w = ew[g];
-    // lower bound of w among the cloud's positions (ascending weights)
+    // first and one-past-last position of w among the cloud's (ascending) weights
     int64_t lo = cl.e_off, hi = g;
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;
@@ -170,14 +210,22 @@ __global__ void dred_groups_kernel(const Column* __restrict__ srt, const Cloud* 
       else
         hi = mid;
     }
-    const uint32_t grp = (uint32_t)(lo - cl.e_off), pos = (uint32_t)(g - cl.e_off);
-    egrp[g] = grp;
+    int64_t lo2 = g + 1, hi2 = end;
+    while (lo2 < hi2) {
+      const int64_t mid = (lo2 + hi2) >> 1;
+      if (ew[mid] <= w)
+        lo2 = mid + 1;
+      else
+        hi2 = mid;
+    }
+    const uint32_t pos = (uint32_t)(g - cl.e_off);
+    egrp[g] = (uint32_t)(lo - cl.e_off);
+    egend[g] = (uint32_t)(lo2 - cl.e_off);
     int a, b;
     edge_of(r.cidx, a, b);
-    const unsigned long long v =
-        w == kInf ? kNoEdge : (((unsigned long long)grp << 32) | (unsigned long long)pos);
-    epg[cl.w_off + (int64_t)a * cl.n + b] = v;
-    epg[cl.w_off + (int64_t)b * cl.n + a] = v;
+    const uint32_t v = w == kInf ? kNoPos : pos;
+    epos[cl.w_off + (int64_t)a * cl.n + b] = v;
+    epos[cl.w_off + (int64_t)b * cl.n + a] = v;
   }
 }
 
@@ -199,50 +247,56 @@ __global__ void dred_ranges_kernel(const Column* __restrict__ cols, const unsign
 // the reduction
 // ---------------------------------------------------------------------------
 
-// Pushes the coboundaries of the summands sedge[0..m) (with epg sepg) into
-// the working column: every cofacet with key >= klow toggles its bit and
-// moves its counts.
+// Pushes the coboundaries of the summands sedge[0..m) (positions spos) into
+// the working column: every cofacet not older than the pivot (class start
+// gstart, class end gend, triangle tp; gend = 0 pushes everything) toggles
+// its bit and moves its counts.
 __device__ __forceinline__ void push_rows(const DredArgs& A, const Cloud& cl,
                                           const DredCloud& dc, Shared& sh, uint32_t* cnt1, int m,
-                                          unsigned long long klow) {
+                                          uint32_t gstart, uint32_t gend, uint64_t tp) {
   const int n = cl.n;
   const int64_t items = (int64_t)m * n;
   const int lane = threadIdx.x & 63;
   for (int64_t base = 0; base < items; base += kT) {
     const int64_t it = base + threadIdx.x;
     bool toggled = false;
-    uint32_t word = 0;
+    uint32_t word = 0, lo = 0xFFFFFFFFu, hi = 0;
     if (it < items) {
       const int i = (int)(it / n), x = (int)(it - (int64_t)i * n);
       const uint32_t e = sh.sedge[i];
       const int p = (int)(e >> 16), q = (int)(e & 0xFFFF);
-      const unsigned long long es = sh.sepg[i];
-      const unsigned long long e1 = A.epg[cl.w_off + (int64_t)p * n + x];
-      const unsigned long long e2 = A.epg[cl.w_off + (int64_t)q * n + x];
-      unsigned long long mx = es > e1 ? es : e1;
-      mx = mx > e2 ? mx : e2;
-      if (mx != kNoEdge) {
+      const uint32_t e1 = A.epos[cl.w_off + (int64_t)p * n + x];
+      const uint32_t e2 = A.epos[cl.w_off + (int64_t)q * n + x];
+      uint32_t pm = sh.spos[i] > e1 ? sh.spos[i] : e1;
+      pm = pm > e2 ? pm : e2;
+      if (pm != kNoPos && pm >= gstart) {
         const uint64_t t = tri_index(p, q, x);
-        const unsigned long long key = ((mx >> 32) << 34) | (kTriMask - t);
-        if (key >= klow) {
+        if (pm >= gend || t <= tp) {
           word = (uint32_t)(t >> 5);
           const uint32_t bit = 1u << (t & 31);
-          const uint32_t old = atomicXor(&A.tri[dc.tri_off + word], bit);
-          const uint32_t pos = (uint32_t)mx;
+          const uint32_t old = wg_xor(&A.tri[dc.tri_off + word], bit);
           const uint32_t delta = (old & bit) ? 0xFFFFFFFFu : 1u;
-          atomicAdd(&A.cnt[cl.e_off + pos], delta);
-          atomicAdd(&cnt1[pos >> 10], delta);
-          atomicMin(&sh.pmin, pos);
-          atomicMax(&sh.pmax, pos);
+          wg_add(&A.cnt[cl.e_off + pm], delta);
+          atomicAdd(&cnt1[pm >> 10], delta);
+          lo = hi = pm;
           toggled = true;
         }
       }
     }
-    // log the toggled words (wave-aggregated slots)
+    // log the toggled words (wave-aggregated slots) and the range of positions touched
     const unsigned long long bal = __ballot(toggled);
     if (bal) {
+      for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t l2 = __shfl_xor(lo, o), h2 = __shfl_xor(hi, o);
+        lo = l2 < lo ? l2 : lo;
+        hi = h2 > hi ? h2 : hi;
+      }
       uint32_t first = 0;
-      if (lane == 0) first = atomicAdd(&sh.tlog_n, (uint32_t)__popcll(bal));
+      if (lane == 0) {
+        first = atomicAdd(&sh.tlog_n, (uint32_t)__popcll(bal));
+        atomicMin(&sh.pmin, lo);
+        atomicMax(&sh.pmax, hi);
+      }
       first = __shfl(first, 0);
       if (toggled) {
         const uint32_t k = first + (uint32_t)__popcll(bal & ((1ull << lane) - 1));
@@ -270,9 +324,9 @@ __device__ __forceinline__ void stage_summands(const DredArgs& A, const Cloud& c
     int a, b;
     edge_of(e, a, b);
     sh.sedge[threadIdx.x] = ((uint32_t)a << 16) | (uint32_t)b;
-    sh.sepg[threadIdx.x] = A.epg[cl.w_off + (int64_t)a * cl.n + b];
+    sh.spos[threadIdx.x] = A.epos[cl.w_off + (int64_t)a * cl.n + b];
     word = e >> 5;
-    atomicXor(&A.vbits[cl.bm_off + word], 1u << (e & 31));
+    wg_xor(&A.vbits[cl.bm_off + word], 1u << (e & 31));
     toggled = true;
   }
   const unsigned long long bal = __ballot(toggled);
@@ -290,13 +344,13 @@ __device__ __forceinline__ void stage_summands(const DredArgs& A, const Cloud& c
   }
 }
 
-// The next pivot of the working column (all its rows have keys >= klow):
-// returns kNoKey if the column is zero; sets sh.tv.
+// The next pivot of the working column (every row in it is younger than the
+// current pivot, whose class starts at gstart): returns kNoKey if the column
+// is zero; sets sh.tv and sh.gend.
 __device__ unsigned long long find_pivot(const DredArgs& A, const Cloud& cl, const DredCloud& dc,
                                          Shared& sh, uint32_t* cnt1, int nblk, int64_t E,
-                                         unsigned long long klow) {
+                                         uint32_t gstart) {
   const int n = cl.n;
-  const uint32_t gstart = (uint32_t)(klow >> 34);
   // first block holding live rows
   int blk = -1;
   for (int b0 = (int)(gstart >> 10); b0 < nblk; b0 += kT) {
@@ -313,13 +367,27 @@ __device__ unsigned long long find_pivot(const DredArgs& A, const Cloud& cl, con
     }
   }
   if (blk < 0) return kNoKey;
-  // first position in it with live rows (positions below gstart hold none)
-  if (threadIdx.x == 0) sh.misc[1] = 0xFFFFFFFFu;
+  // the block's counts, classes and edges in one round: the first position
+  // p1 >= gstart with live rows (positions below gstart hold none), then the
+  // live positions of p1's weight class [g1, gend1) in the block
+  if (threadIdx.x == 0) {
+    sh.misc[1] = 0xFFFFFFFFu;
+    sh.list_n = 0;
+    sh.red = 0;
+  }
   __syncthreads();
+  const int64_t pb = (int64_t)blk * 1024 + threadIdx.x;
+  uint32_t cb = 0, gb = 0, ge = 0, uvb = 0;
+  if (pb < E && (uint32_t)pb >= gstart) {
+    cb = wg_load(&A.cnt[cl.e_off + pb]);
+    gb = A.egrp[cl.e_off + pb];
+    ge = A.egend[cl.e_off + pb];
+    uvb = A.eat[cl.e_off + pb];
+  }
   {
-    const int64_t p = (int64_t)blk * 1024 + threadIdx.x;
-    if (p < E && (uint32_t)p >= gstart && load_coherent(&A.cnt[cl.e_off + p]) != 0)
-      atomicMin(&sh.misc[1], (uint32_t)p);
+    const uint32_t mine = cb != 0 ? (uint32_t)pb : 0xFFFFFFFFu;
+    const uint32_t wmin = wave_min_u32(mine);
+    if ((threadIdx.x & 63) == 0 && wmin != 0xFFFFFFFFu) atomicMin(&sh.misc[1], wmin);
   }
   __syncthreads();
   const uint32_t p1 = sh.misc[1];
@@ -328,43 +396,51 @@ __device__ unsigned long long find_pivot(const DredArgs& A, const Cloud& cl, con
     __syncthreads();
     return kNoKey;
   }
-  const uint32_t g1 = A.egrp[cl.e_off + p1];
-  // the largest live triangle index over the positions of p1's weight class
-  // that hold live rows, one window of kT positions at a time
-  if (threadIdx.x == 0) sh.red = 0;
-  for (int64_t w0 = p1;; w0 += kT) {
-    if (threadIdx.x == 0) sh.list_n = 0;
+  if ((uint32_t)pb == p1) {
+    sh.misc[2] = gb;
+    sh.misc[3] = ge;
+  }
+  __syncthreads();
+  const uint32_t g1 = sh.misc[2], gend1 = sh.misc[3];
+  if (cb != 0 && (uint32_t)pb >= p1 && (uint32_t)pb < gend1) {
+    const uint32_t k = atomicAdd(&sh.list_n, 1u);
+    sh.list[k] = (uint32_t)pb;
+    sh.sedge[k] = uvb;  // free here: staging starts after the search
+  }
+  // the largest live triangle index over the listed positions; a class that
+  // runs past the block continues one window of kT positions at a time
+  for (int64_t w0 = (int64_t)blk * 1024 + 1024;; w0 += kT) {
     __syncthreads();
-    const int64_t p = w0 + threadIdx.x;
-    const bool in_class = p < E && A.egrp[cl.e_off + p] == g1;
-    if (in_class && load_coherent(&A.cnt[cl.e_off + p]) != 0)
-      sh.list[atomicAdd(&sh.list_n, 1u)] = (uint32_t)p;
-    // the class goes on past this window only if the window's last position is in it
-    const bool more = __syncthreads_or(threadIdx.x == kT - 1 && in_class) != 0;
     const int L = (int)sh.list_n;
     const int64_t items = (int64_t)L * n;
     unsigned long long best = 0;
     for (int64_t it = threadIdx.x; it < items; it += kT) {
       const int i = (int)(it / n), x = (int)(it - (int64_t)i * n);
       const uint32_t pos = sh.list[i];
-      const uint32_t uv = A.eat[cl.e_off + pos];
+      const uint32_t uv = sh.sedge[i];
       const int u = (int)(uv >> 16), v = (int)(uv & 0xFFFF);
-      const unsigned long long eq = ((unsigned long long)g1 << 32) | pos;
-      const unsigned long long e1 = A.epg[cl.w_off + (int64_t)u * n + x];
-      const unsigned long long e2 = A.epg[cl.w_off + (int64_t)v * n + x];
-      if (e1 < eq && e2 < eq) {  // (u, v) is the diameter edge of {u, v, x}
+      const uint32_t e1 = A.epos[cl.w_off + (int64_t)u * n + x];
+      const uint32_t e2 = A.epos[cl.w_off + (int64_t)v * n + x];
+      if (e1 < pos && e2 < pos) {  // (u, v) is the diameter edge of {u, v, x}
         const uint64_t t = tri_index(u, v, x);
-        const uint32_t wd = load_coherent(&A.tri[dc.tri_off + (t >> 5)]);
-        if ((wd >> (t & 31)) & 1u) {
-          best = t + 1 > best ? t + 1 : best;
-        }
+        const uint32_t wd = wg_load(&A.tri[dc.tri_off + (t >> 5)]);
+        if ((wd >> (t & 31)) & 1u) best = t + 1 > best ? t + 1 : best;
       }
     }
     best = wave_max_u64(best);
     if ((threadIdx.x & 63) == 0 && best) atomicMax(&sh.red, best);
+    if (w0 >= (int64_t)gend1) break;
     __syncthreads();
-    if (!more) break;
+    if (threadIdx.x == 0) sh.list_n = 0;
+    __syncthreads();
+    const int64_t p = w0 + threadIdx.x;
+    if (p < (int64_t)gend1 && wg_load(&A.cnt[cl.e_off + p]) != 0) {
+      const uint32_t k = atomicAdd(&sh.list_n, 1u);
+      sh.list[k] = (uint32_t)p;
+      sh.sedge[k] = A.eat[cl.e_off + p];
+    }
   }
+  __syncthreads();
   const unsigned long long best = sh.red;
   __syncthreads();
   if (best == 0) {  // no live triangle where the counts said: leave the cloud to the host
@@ -374,28 +450,21 @@ __device__ unsigned long long find_pivot(const DredArgs& A, const Cloud& cl, con
   }
   const uint64_t t = best - 1;
   if (threadIdx.x == 0) {
-    // vertices of t from its index (Eq. 5.6): the largest v2 with
-    // C(v2, 3) <= t (cube root, then an exact fix-up), then the edge t - C(v2, 3)
-    int64_t v2 = (int64_t)cbrt(6.0 * (double)t) + 1;
-    while (v2 > 2 && c3((uint64_t)v2) > t) --v2;
-    while (c3((uint64_t)v2 + 1) <= t) ++v2;
-    int v1, v0;
-    edge_of(t - c3((uint64_t)v2), v1, v0);
-    sh.tv[0] = (uint32_t)v2;
-    sh.tv[1] = (uint32_t)v1;
-    sh.tv[2] = (uint32_t)v0;
+    tri_vertices(t, sh.tv);
+    sh.gend = gend1;
   }
   __syncthreads();
   return ((unsigned long long)g1 << 34) | (kTriMask - t);
 }
 
-// Owner of the pivot t = sh.tv with key `key`: sets sh.owner (global column
-// of a finished column, -2 for an apparent partner in sh.partner, -1 free).
+// Owner of the pivot t = sh.tv with key `key` (class [gD, sh.gend)): sets
+// sh.owner (global column of a finished column, -2 for an apparent partner
+// in sh.partner, -1 free).
 __device__ void find_owner(const DredArgs& A, const Cloud& cl, const DredCloud& dc, Shared& sh,
                            uint32_t tcap, unsigned long long key) {
   const int n = cl.n;
   const uint64_t t = kTriMask - (key & kTriMask);
-  const uint32_t gD = (uint32_t)(key >> 34);
+  const uint32_t gD = (uint32_t)(key >> 34), gendD = sh.gend;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (threadIdx.x == 0) {
     sh.owner = -1;
@@ -418,28 +487,55 @@ __device__ void find_owner(const DredArgs& A, const Cloud& cl, const DredCloud& 
       h = (h + 64) & (tcap - 1);
     }
   } else {
-    // Def. 5.3.4: s = the facet of t of smallest index with t's diameter;
-    // apparent iff no x above t's third vertex makes an equal-diameter
-    // cofacet of s (t is then s's oldest cofacet of that diameter)
+    // Def. 5.3.4: s = the facet of t of smallest index with t's diameter
+    // (its edge lies in t's class); apparent iff no x above t's third vertex
+    // makes an equal-diameter cofacet of s (t is then s's oldest cofacet of
+    // that diameter). The rows of all three vertices are read at once, before
+    // s is known.
     const int v2 = (int)sh.tv[0], v1 = (int)sh.tv[1], v0 = (int)sh.tv[2];
     const int64_t wo = cl.w_off;
-    int p, q, r;
-    if ((uint32_t)(A.epg[wo + (int64_t)v1 * n + v0] >> 32) == gD) {
-      p = v1; q = v0; r = v2;
-    } else if ((uint32_t)(A.epg[wo + (int64_t)v2 * n + v0] >> 32) == gD) {
-      p = v2; q = v0; r = v1;
+    const uint32_t f10 = A.epos[wo + (int64_t)v1 * n + v0];
+    const uint32_t f20 = A.epos[wo + (int64_t)v2 * n + v0];
+    const uint32_t f21 = A.epos[wo + (int64_t)v2 * n + v1];
+    const int x0 = v0 + 1 + (int)threadIdx.x - 64, stride = kT - 64;
+    uint32_t r2[4], r1[4], r0[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int x = x0 + k * stride;
+      const bool ok = x < n;
+      r2[k] = ok ? A.epos[wo + (int64_t)v2 * n + x] : kNoPos;
+      r1[k] = ok ? A.epos[wo + (int64_t)v1 * n + x] : kNoPos;
+      r0[k] = ok ? A.epos[wo + (int64_t)v0 * n + x] : kNoPos;
+    }
+    int p, q, r, which;
+    uint32_t fpq;
+    if (f10 >= gD) {
+      p = v1; q = v0; r = v2; which = 0; fpq = f10;
+    } else if (f20 >= gD) {
+      p = v2; q = v0; r = v1; which = 1; fpq = f20;
     } else {
-      p = v2; q = v1; r = v0;
+      p = v2; q = v1; r = v0; which = 2; fpq = f21;
     }
     bool older = false;
-    for (int x = r + 1 + (int)threadIdx.x - 64; x < n; x += kT - 64) {
-      if (x == p || x == q) continue;
-      const uint32_t gp = (uint32_t)(A.epg[wo + (int64_t)p * n + x] >> 32);
-      const uint32_t gq = (uint32_t)(A.epg[wo + (int64_t)q * n + x] >> 32);
-      older |= gp <= gD && gq <= gD;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int x = x0 + k * stride;
+      const uint32_t ep = which == 0 ? r1[k] : r2[k];
+      const uint32_t eq = which == 2 ? r1[k] : r0[k];
+      older |= x > r && x != p && x != q && ep < gendD && eq < gendD;
+    }
+    for (int x = x0 + 4 * stride; x < n; x += stride) {  // n > 3904 only
+      if (x <= r || x == p || x == q) continue;
+      const uint32_t ep = A.epos[wo + (int64_t)p * n + x];
+      const uint32_t eq = A.epos[wo + (int64_t)q * n + x];
+      older |= ep < gendD && eq < gendD;
     }
     if (__ballot(older) && lane == 0) sh.misc[2] = 1;
-    if (threadIdx.x == 64) sh.partner = (uint32_t)(c2((uint64_t)p) + (uint64_t)q);
+    if (threadIdx.x == 64) {
+      sh.partner = (uint32_t)(c2((uint64_t)p) + (uint64_t)q);
+      sh.partner_uv = ((uint32_t)p << 16) | (uint32_t)q;
+      sh.partner_pos = fpq;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0 && sh.owner < 0 && sh.misc[2] == 0) sh.owner = -2;
@@ -465,6 +561,7 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
     sh.arena_n = 0;
     sh.err = tcap > (uint32_t)dc.tab_cap ? 1u : 0u;
     sh.tv[0] = sh.tv[1] = sh.tv[2] = 0;
+    sh.gend = 0;
   }
   __syncthreads();
   if (sh.err) {
@@ -472,7 +569,6 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
     return;
   }
   for (uint32_t s = tid; s < tcap; s += kT) A.tab_keys[dc.tab_off + s] = kNoKey;
-  __threadfence();
   __syncthreads();
   unsigned long long additions = 0;
   uint32_t emergent = 0;
@@ -481,50 +577,54 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
     const uint64_t scidx = A.cols[j].cidx;
     int a, b;
     edge_of(scidx, a, b);
-    const unsigned long long es = A.epg[cl.w_off + (int64_t)a * n + b];
-    // the first pivot: the oldest cofacet, from the coboundary alone
-    unsigned long long kmin = kNoKey;
+    const uint32_t es = A.epos[cl.w_off + (int64_t)a * n + b];
+    // the first pivot, from the coboundary alone: the oldest cofacet, i.e.
+    // the smallest diameter-edge position's class, then the largest index
+    uint32_t pmin = kNoPos;
     for (int x = tid; x < n; x += kT) {
-      const unsigned long long e1 = A.epg[cl.w_off + (int64_t)a * n + x];
-      const unsigned long long e2 = A.epg[cl.w_off + (int64_t)b * n + x];
-      unsigned long long mx = es > e1 ? es : e1;
-      mx = mx > e2 ? mx : e2;
-      if (mx != kNoEdge) {
-        const unsigned long long key = ((mx >> 32) << 34) | (kTriMask - tri_index(a, b, x));
-        kmin = key < kmin ? key : kmin;
-      }
+      const uint32_t e1 = A.epos[cl.w_off + (int64_t)a * n + x];
+      const uint32_t e2 = A.epos[cl.w_off + (int64_t)b * n + x];
+      uint32_t pm = es > e1 ? es : e1;
+      pm = pm > e2 ? pm : e2;
+      pmin = pm < pmin ? pm : pmin;
     }
-    kmin = wave_min_u64(kmin);
-    if (tid == 0) sh.red = kNoKey;
+    pmin = wave_min_u32(pmin);
+    if (tid == 0) sh.misc[0] = kNoPos;
     __syncthreads();
-    if ((tid & 63) == 0 && kmin != kNoKey) atomicMin(&sh.red, kmin);
+    if ((tid & 63) == 0 && pmin != kNoPos) atomicMin(&sh.misc[0], pmin);
     __syncthreads();
-    unsigned long long key = sh.red;
-    __syncthreads();
-    if (key == kNoKey) {  // no cofacet within the threshold: an essential class
+    const uint32_t p0 = sh.misc[0];
+    if (p0 == kNoPos) {  // no cofacet within the threshold: an essential class
       if (tid == 0) {
         A.out_death[j] = kNoKey;
         A.out_ddiam[j] = kInf;
         A.out_dedge[j] = kInf;
         A.col_vlen[j] = 0;
       }
+      __syncthreads();
       continue;
     }
-    {
-      const uint64_t t0 = kTriMask - (key & kTriMask);
-      for (int x = tid; x < n; x += kT) {
-        if (x == a || x == b) continue;
-        if (tri_index(a, b, x) == t0) {
-          int v2 = a, v1 = b, v0 = x;
-          if (v0 > v2) { int tt = v2; v2 = v0; v0 = tt; }
-          if (v0 > v1) { int tt = v1; v1 = v0; v0 = tt; }
-          sh.tv[0] = (uint32_t)v2;
-          sh.tv[1] = (uint32_t)v1;
-          sh.tv[2] = (uint32_t)v0;
-        }
+    const uint32_t g0 = A.egrp[cl.e_off + p0], gend0 = A.egend[cl.e_off + p0];
+    unsigned long long tbest = 0;
+    for (int x = tid; x < n; x += kT) {
+      const uint32_t e1 = A.epos[cl.w_off + (int64_t)a * n + x];
+      const uint32_t e2 = A.epos[cl.w_off + (int64_t)b * n + x];
+      uint32_t pm = es > e1 ? es : e1;
+      pm = pm > e2 ? pm : e2;
+      if (pm != kNoPos && pm < gend0) {
+        const unsigned long long t = tri_index(a, b, x) + 1;
+        tbest = t > tbest ? t : tbest;
       }
     }
+    tbest = wave_max_u64(tbest);
+    if (tid == 0) sh.red = 0;
+    __syncthreads();
+    if ((tid & 63) == 0 && tbest) atomicMax(&sh.red, tbest);
+    __syncthreads();
+    unsigned long long key = ((unsigned long long)g0 << 34) | (kTriMask - (sh.red - 1));
     if (tid == 0) {
+      tri_vertices(sh.red - 1, sh.tv);
+      sh.gend = gend0;
       sh.tlog_n = sh.vt_n = 0;
       sh.tlog_ovf = sh.vt_ovf = 0;
       sh.pmin = 0xFFFFFFFFu;
@@ -541,34 +641,47 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
         // the working column: the coboundary of the column's own edge
         if (tid == 0) {
           sh.sedge[0] = ((uint32_t)a << 16) | (uint32_t)b;
-          sh.sepg[0] = es;
+          sh.spos[0] = es;
         }
         __syncthreads();
-        push_rows(A, cl, dc, sh, cnt1, 1, 0);
+        push_rows(A, cl, dc, sh, cnt1, 1, 0, 0, 0);
         built = true;
       }
       // add the owner's column: its edge, then V (finished columns only)
-      uint32_t first, voff = 0, vlen = 0;
+      const uint32_t gstart = (uint32_t)(key >> 34), gend = sh.gend;
+      const uint64_t tp = kTriMask - (key & kTriMask);
       if (owner == -2) {
-        first = sh.partner;
+        // an apparent column: its edge, known from the lookup
+        __syncthreads();
+        if (tid == 0) {
+          const uint32_t e = sh.partner;
+          sh.sedge[0] = sh.partner_uv;
+          sh.spos[0] = sh.partner_pos;
+          wg_xor(&A.vbits[cl.bm_off + (e >> 5)], 1u << (e & 31));
+          const uint32_t k = sh.vt_n++;
+          if (k < (uint32_t)dc.vt_cap)
+            A.vtouch[dc.vt_off + k] = e >> 5;
+          else
+            sh.vt_ovf = 1;
+        }
+        __syncthreads();
+        push_rows(A, cl, dc, sh, cnt1, 1, gstart, gend, tp);
       } else {
-        first = (uint32_t)A.cols[owner].cidx;
-        voff = A.col_voff[owner];
-        vlen = A.col_vlen[owner];
-      }
-      const int64_t total = 1 + (int64_t)vlen;
-      for (int64_t from = 0; from < total; from += kT) {
-        const int m = (int)(total - from < kT ? total - from : kT);
-        __syncthreads();
-        stage_summands(A, cl, dc, sh, from, m, first, voff);
-        __syncthreads();
-        push_rows(A, cl, dc, sh, cnt1, m, key);
+        const uint32_t first = (uint32_t)A.cols[owner].cidx;
+        const uint32_t voff = A.col_voff[owner], vlen = A.col_vlen[owner];
+        const int64_t total = 1 + (int64_t)vlen;
+        for (int64_t from = 0; from < total; from += kT) {
+          const int m = (int)(total - from < kT ? total - from : kT);
+          __syncthreads();
+          stage_summands(A, cl, dc, sh, from, m, first, voff);
+          __syncthreads();
+          push_rows(A, cl, dc, sh, cnt1, m, gstart, gend, tp);
+        }
       }
       ++nadd;
-      __threadfence();
       __syncthreads();
       const unsigned long long prev = key;
-      key = find_pivot(A, cl, dc, sh, cnt1, nblk, E, key);
+      key = find_pivot(A, cl, dc, sh, cnt1, nblk, E, gstart);
       if (key == kNoKey) break;  // the column is zero: an essential class
       // an addition cancels the pivot, so the next one is younger; a column
       // that would not move on, or that needs more additions than a column
@@ -591,11 +704,10 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
         A.out_ddiam[j] = A.ew[cl.e_off + gD];
         // diameter edge: the largest position among the three edges
         const int v2 = (int)sh.tv[0], v1 = (int)sh.tv[1], v0 = (int)sh.tv[2];
-        const unsigned long long x0 = A.epg[cl.w_off + (int64_t)v2 * n + v1];
-        const unsigned long long x1 = A.epg[cl.w_off + (int64_t)v2 * n + v0];
-        const unsigned long long x2 = A.epg[cl.w_off + (int64_t)v1 * n + v0];
-        uint32_t de = ((uint32_t)v2 << 16) | (uint32_t)v1;
-        unsigned long long m = x0;
+        const uint32_t x0 = A.epos[cl.w_off + (int64_t)v2 * n + v1];
+        const uint32_t x1 = A.epos[cl.w_off + (int64_t)v2 * n + v0];
+        const uint32_t x2 = A.epos[cl.w_off + (int64_t)v1 * n + v0];
+        uint32_t de = ((uint32_t)v2 << 16) | (uint32_t)v1, m = x0;
         if (x1 > m) { m = x1; de = ((uint32_t)v2 << 16) | (uint32_t)v0; }
         if (x2 > m) { de = ((uint32_t)v1 << 16) | (uint32_t)v0; }
         A.out_dedge[j] = de;
@@ -615,7 +727,7 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
       const int64_t words = full ? (E + 31) / 32 : (int64_t)sh.vt_n;
       for (int64_t k = tid; k < words; k += kT) {
         const uint32_t wdi = full ? (uint32_t)k : A.vtouch[dc.vt_off + k];
-        const uint32_t bits = atomicExch(&A.vbits[cl.bm_off + wdi], 0u);
+        const uint32_t bits = wg_exch(&A.vbits[cl.bm_off + wdi], 0u);
         if (bits && paired) {
           const uint32_t at = atomicAdd(&sh.arena_n, (uint32_t)__popc(bits));
           uint32_t bb = bits;
@@ -628,7 +740,6 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
         }
       }
     }
-    __threadfence();
     __syncthreads();
     if (tid == 0) {
       A.col_voff[j] = vstart;
@@ -658,13 +769,12 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
       } else {
         for (uint32_t k = tid; k < sh.tlog_n; k += kT) A.tri[dc.tri_off + A.tlog[dc.log_off + k]] = 0;
       }
-      const uint32_t p0 = sh.pmin, p1 = sh.pmax;
-      if (p0 <= p1) {
-        for (int64_t p = (int64_t)p0 + tid; p <= (int64_t)p1; p += kT) A.cnt[cl.e_off + p] = 0;
-        for (int b2 = (int)(p0 >> 10) + tid; b2 <= (int)(p1 >> 10); b2 += kT) cnt1[b2] = 0;
+      const uint32_t q0 = sh.pmin, q1 = sh.pmax;
+      if (q0 <= q1) {
+        for (int64_t p = (int64_t)q0 + tid; p <= (int64_t)q1; p += kT) A.cnt[cl.e_off + p] = 0;
+        for (int b2 = (int)(q0 >> 10) + tid; b2 <= (int)(q1 >> 10); b2 += kT) cnt1[b2] = 0;
       }
     }
-    __threadfence();
     __syncthreads();
   }
   if (tid == 0) A.stats[c] = DredStats{additions, emergent, sh.err};
@@ -673,7 +783,7 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
 hipError_t launch_dred_prepare(const uint32_t* W, const Cloud* clouds, int count,
                                int64_t total_edges, int cloud_bits, Column* rec, Column* rec_tmp,
                                void* sort_work, uint32_t* ew, uint32_t* eat, uint32_t* egrp,
-                               unsigned long long* epg, hipStream_t s) {
+                               uint32_t* egend, uint32_t* epos, hipStream_t s) {
   if (total_edges <= 0) return hipSuccess;
   int64_t blocks = (total_edges + kBlock - 1) / kBlock;
   if (blocks > 8192) blocks = 8192;
@@ -687,7 +797,8 @@ hipError_t launch_dred_prepare(const uint32_t* W, const Cloud* clouds, int count
   const Column* srt = in_tmp ? rec_tmp : rec;
   dred_positions_kernel<<<(int)blocks, kBlock, 0, s>>>(srt, total_edges, ew, eat);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  dred_groups_kernel<<<(int)blocks, kBlock, 0, s>>>(srt, clouds, total_edges, ew, egrp, epg);
+  dred_groups_kernel<<<(int)blocks, kBlock, 0, s>>>(srt, clouds, total_edges, ew, egrp, egend,
+                                                    epos);
   return hipGetLastError();
 }
 

@@ -1181,7 +1181,7 @@ struct vrph_batch {
   // dimension-1 reduction on the device (unless VRPH_HOST_REDUCTION)
   bool device_reduce = false;
   std::vector<DredCloud> hdc;
-  DevBuf ddc, ew, eat, egrp, ecnt, epg, tri, tlog, tab_keys, tab_vals, varena, vbits, vtouch,
+  DevBuf ddc, ew, eat, egrp, egend, ecnt, epos, tri, tlog, tab_keys, tab_vals, varena, vbits, vtouch,
       col_begin, col_end, out_death, out_ddiam, out_dedge, col_voff, col_vlen, dstats;
   std::vector<unsigned long long> hdeath;
   std::vector<uint32_t> hddiam, hdedge;
@@ -1195,7 +1195,7 @@ struct vrph_batch {
 // than half that many non-apparent columns goes to the host); the V arena
 // max(65536, E / 2) edges (more: the host); 16384 logged V words (more: V
 // is read whole). Bitmaps and counts start at zero and the kernel leaves
-// them at zero; epg starts at ~0 (the diagonal stays so).
+// them at zero; epos starts at ~0 (the diagonal stays so).
 static vrph_status dred_plan(vrph_batch* b) {
   b->hdc.resize((size_t)b->count);
   int64_t tri = 0, tlog = 0, tab = 0, va = 0, vt = 0;
@@ -1236,8 +1236,9 @@ static vrph_status dred_plan(vrph_batch* b) {
   HIP_TRY(b->ew.ensure(ne * 4));
   HIP_TRY(b->eat.ensure(ne * 4));
   HIP_TRY(b->egrp.ensure(ne * 4));
+  HIP_TRY(b->egend.ensure(ne * 4));
   HIP_TRY(b->ecnt.ensure(ne * 4));
-  HIP_TRY(b->epg.ensure((size_t)b->total_w * 8));
+  HIP_TRY(b->epos.ensure((size_t)b->total_w * 4));
   HIP_TRY(b->tri.ensure((size_t)tri * 4));
   HIP_TRY(b->tlog.ensure((size_t)tlog * 4));
   HIP_TRY(b->tab_keys.ensure((size_t)tab * 8));
@@ -1257,7 +1258,7 @@ static vrph_status dred_plan(vrph_batch* b) {
   HIP_TRY(hipMemset(b->tri.p, 0, (size_t)tri * 4));
   HIP_TRY(hipMemset(b->ecnt.p, 0, ne * 4));
   HIP_TRY(hipMemset(b->vbits.p, 0, (size_t)std::max<int64_t>(b->total_words, 1) * 4));
-  HIP_TRY(hipMemset(b->epg.p, 0xFF, (size_t)b->total_w * 8));
+  HIP_TRY(hipMemset(b->epos.p, 0xFF, (size_t)b->total_w * 4));
   HIP_TRY(hipDeviceSynchronize());
   return VRPH_OK;
 }
@@ -1339,8 +1340,8 @@ extern "C" void vrph_batch_destroy(vrph_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   DevBuf* bufs[] = {&b->X,    &b->D,        &b->W,         &b->dclouds, &b->cstate,
                     &b->h0,   &b->bitmaps,  &b->cols,      &b->cols_tmp, &b->sort_work,
-                    &b->ap,   &b->counters, &b->ddc, &b->ew, &b->eat, &b->egrp, &b->ecnt,
-                    &b->epg,  &b->tri,    &b->tlog,    &b->tab_keys, &b->tab_vals, &b->varena,
+                    &b->ap,   &b->counters, &b->ddc, &b->ew, &b->eat, &b->egrp, &b->egend,
+                    &b->ecnt, &b->epos,  &b->tri,    &b->tlog,    &b->tab_keys, &b->tab_vals, &b->varena,
                     &b->vbits, &b->vtouch, &b->col_begin, &b->col_end, &b->out_death,
                     &b->out_ddiam, &b->out_dedge, &b->col_voff, &b->col_vlen, &b->dstats};
   for (DevBuf* d : bufs) d->release();
@@ -1385,7 +1386,7 @@ static hipError_t batch_record(vrph_batch* b, hipStream_t s) {
                                  b->total_edges, cloud_bits, b->cols.as<Column>(),
                                  b->cols_tmp.as<Column>(), b->sort_work.p, b->ew.as<uint32_t>(),
                                  b->eat.as<uint32_t>(), b->egrp.as<uint32_t>(),
-                                 b->epg.as<unsigned long long>(), s)))
+                                 b->egend.as<uint32_t>(), b->epos.as<uint32_t>(), s)))
       return e;
     if ((e = launch_batch_edges(b->W.as<uint32_t>(), b->dclouds.as<Cloud>(), b->count,
                                 b->total_edges, b->bitmaps.as<uint32_t>(), b->cols.as<Column>(),
@@ -1413,9 +1414,10 @@ static hipError_t batch_record(vrph_batch* b, hipStream_t s) {
       a.col_end_w = b->col_end.as<uint32_t>();
       a.col_begin = a.col_begin_w;
       a.col_end = a.col_end_w;
-      a.epg = b->epg.as<unsigned long long>();
+      a.epos = b->epos.as<uint32_t>();
       a.eat = b->eat.as<uint32_t>();
       a.egrp = b->egrp.as<uint32_t>();
+      a.egend = b->egend.as<uint32_t>();
       a.ew = b->ew.as<uint32_t>();
       a.cnt = b->ecnt.as<uint32_t>();
       a.tri = b->tri.as<uint32_t>();

@@ -244,9 +244,10 @@ struct DredArgs {
   uint32_t* col_end_w;
   const uint32_t* col_begin;
   const uint32_t* col_end;
-  const unsigned long long* epg;     // n x n per cloud: (class start << 32 | position), ~0 off edges
+  const uint32_t* epos;              // n x n per cloud: position of the edge, ~0 off edges
   const uint32_t* eat;               // per position: a << 16 | b
   const uint32_t* egrp;              // per position: first position of its weight class
+  const uint32_t* egend;             // per position: one past the last position of its class
   const uint32_t* ew;                // per position: weight bits
   uint32_t* cnt;                     // per position: live triangles with that diameter edge
   uint32_t* tri;                     // triangle bitmaps
@@ -264,11 +265,12 @@ struct DredArgs {
   DredStats* stats;                  // per cloud
 };
 // Edge positions of every cloud: records into rec (total_edges), sorted
-// with rec_tmp and sort_work, then ew / eat / egrp per position and epg.
+// with rec_tmp and sort_work, then ew / eat / egrp / egend per position and
+// epos per vertex pair.
 hipError_t launch_dred_prepare(const uint32_t* W, const Cloud* clouds, int count,
                                int64_t total_edges, int cloud_bits, Column* rec, Column* rec_tmp,
                                void* sort_work, uint32_t* ew, uint32_t* eat, uint32_t* egrp,
-                               unsigned long long* epg, hipStream_t s);
+                               uint32_t* egend, uint32_t* epos, hipStream_t s);
 // Column ranges per cloud, then the reduction (one workgroup per cloud).
 // The bitmaps, counts and V bitmaps must be zero on entry; they are zero
 // again on exit.
