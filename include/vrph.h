@@ -246,6 +246,21 @@ vrph_status vrph_backward(vrph_ctx* ctx, const float* X, int64_t n_total, int32_
                           const int32_t* edges, int64_t npairs, const float* g_birth,
                           const float* g_death, float* gX, void* hip_stream);
 
+/* Allocation-free backward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight training or serving loops, harnesses
+ * that forbid hipMalloc): the same arguments, result and errors as
+ * vrph_backward, but its one word of device scratch (the edge-check flag) is
+ * taken from a fixed 256-byte array that the library holds on every device
+ * it runs on until the process ends, looked up when a context is created on
+ * that device; no device or pinned memory is allocated by the call, whatever
+ * npairs is. Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other host threads, other contexts)
+ * race with each other and must be serialised by the caller. VRPH_ESTATE if
+ * the array of the context's device was not set up. */
+vrph_status vrph_backward_noalloc(vrph_ctx* ctx, const float* X, int64_t n_total, int32_t m,
+                                  const int32_t* edges, int64_t npairs, const float* g_birth,
+                                  const float* g_death, float* gX, void* hip_stream);
+
 /* ---- explicit boundary matrices (Sec. 4.3.2-4.3.3, Alg. 2-7) ---------------
  * The pivots low(R_j) of the Z/2 column reduction of Alg. 2 (R = D V, only
  * columns to the left added) of an explicit ncols x ncols matrix: the

@@ -288,6 +288,8 @@ extern "C" vrph_status vrph_create(int device, vrph_ctx** out) {
   c->arch = prop.gcnArchName;
   c->arch = c->arch.substr(0, c->arch.find(':'));
   load_tuning(c.get());
+  // the device address of this device's fixed scratch array (allocation-free calls)
+  HIP_TRY(noalloc_scratch_setup(device));
   // a blocking stream: ordered against the legacy default stream, which is where
   // torch puts work when the caller passes stream 0
   HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamDefault));
@@ -1049,6 +1051,28 @@ extern "C" vrph_status vrph_backward(vrph_ctx* c, const float* X, int64_t n_tota
   HIP_TRY(hipStreamSynchronize(s));
   if (bad)
     return fail(VRPH_EINVAL, "vrph_backward: an edge entry is neither -1 nor a point in [0, n_total)");
+  return VRPH_OK;
+}
+
+extern "C" vrph_status vrph_backward_noalloc(vrph_ctx* c, const float* X, int64_t n_total,
+                                             int32_t m, const int32_t* edges, int64_t npairs,
+                                             const float* g_birth, const float* g_death,
+                                             float* gX, void* hip_stream) {
+  if (!c || !X || !gX || m < 1 || n_total < 0 || npairs < 0)
+    return fail(VRPH_EINVAL, "vrph_backward_noalloc: bad argument");
+  if (npairs > 0 && (!edges || !g_birth || !g_death))
+    return fail(VRPH_EINVAL, "vrph_backward_noalloc: NULL pair arrays");
+  uint32_t* bad = noalloc_scratch(c->device);
+  if (!bad) return fail(VRPH_ESTATE, "vrph_backward_noalloc: scratch of this device not set up");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  HIP_TRY(launch_backward(X, n_total, m, edges, npairs, g_birth, g_death, gX, bad, s));
+  uint32_t flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, bad, sizeof(flag), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (flag)
+    return fail(VRPH_EINVAL,
+                "vrph_backward_noalloc: an edge entry is neither -1 nor a point in [0, n_total)");
   return VRPH_OK;
 }
 

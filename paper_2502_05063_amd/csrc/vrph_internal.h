@@ -276,6 +276,16 @@ hipError_t launch_dred_prepare(const uint32_t* W, const Cloud* clouds, int count
 // again on exit.
 hipError_t launch_dred_reduce(const DredArgs& args, int64_t cols_cap, int max_n, hipStream_t s);
 
+// ---- noalloc.hip ----
+// Words of the fixed per-device scratch array of the allocation-free entry
+// points (256 bytes): word 0 is the backward's edge-check flag.
+constexpr int kNoAllocScratchWords = 64;
+// Looks up the scratch array's address on `device`, which must be the
+// current device; once per device (later calls return at once).
+hipError_t noalloc_scratch_setup(int device);
+// The address found by noalloc_scratch_setup, or NULL before it ran.
+uint32_t* noalloc_scratch(int device);
+
 // ---- sort.hip ----
 // Stable LSD radix sort of Column records ascending by (cloud, key_hi, cidx),
 // looking only at the low `cidx_bits` of cidx, all 32 bits of key_hi and the

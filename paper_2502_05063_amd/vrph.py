@@ -117,6 +117,7 @@ def lib():
         "vrph_batch_result": (i32, [vp, i32, P(vp)]),
         "vrph_batch_destroy": (None, [vp]),
         "vrph_backward": (i32, [vp, vp, i64, i32, vp, i64, vp, vp, vp, vp]),
+        "vrph_backward_noalloc": (i32, [vp, vp, i64, i32, vp, i64, vp, vp, vp, vp]),
         "vrph_boundary_pivots": (i32, [vp, i64, vp, vp, u32, vp, vp, P(BoundaryStats)]),
     }
     for name, (res, args) in sig.items():
@@ -278,6 +279,22 @@ class Context:
         _check(lib().vrph_backward(self.h, _dev_ptr(X), X.shape[0], X.shape[1], _dev_ptr(edges),
                                    edges.shape[0], _dev_ptr(g_birth), _dev_ptr(g_death),
                                    _dev_ptr(gX), _stream_ptr()))
+        return gX
+
+    def backward_noalloc(self, X, edges, g_birth, g_death, gX):
+        """The same as backward through vrph_backward_noalloc: no device memory is
+        allocated, so the arguments are taken as they are (float32 X, g_birth,
+        g_death, gX; int32 edges [npairs, 4]; all contiguous on the device)."""
+        import torch
+
+        for name, t, dt in (("X", X, torch.float32), ("edges", edges, torch.int32),
+                            ("g_birth", g_birth, torch.float32),
+                            ("g_death", g_death, torch.float32), ("gX", gX, torch.float32)):
+            if t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{name} must be a contiguous {dt} device tensor")
+        _check(lib().vrph_backward_noalloc(self.h, _dev_ptr(X), X.shape[0], X.shape[1],
+                                           _dev_ptr(edges), edges.shape[0], _dev_ptr(g_birth),
+                                           _dev_ptr(g_death), _dev_ptr(gX), _stream_ptr()))
         return gX
 
     def batch(self, sizes, m, max_dim=1, threshold=float("inf"), keep_zero=False,
