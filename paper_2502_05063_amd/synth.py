@@ -109,8 +109,6 @@ CONFIGS = {
     "c5_torus64x500": dict(max_dim=1, threshold=float("inf")),
     # the o3 recipe at the paper's size (Table 5.2: 4096 points, threshold 1.4)
     "o3_4096": dict(max_dim=3, threshold=1.4),
-    # the same input, dimensions 0-2 only (for an oracle run that finishes in minutes)
-    "o3_4096_d2": dict(max_dim=2, threshold=1.4),
 }
 
 

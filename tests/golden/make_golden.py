@@ -16,7 +16,7 @@ zero-persistence pair can be compared bit for bit.
 
     python tests/golden/make_golden.py c2_sphere192 c3_o3_1024
     python tests/golden/make_golden.py c4_batch256 c5_torus64x500
-    python tests/golden/make_golden.py o3_4096 o3_4096_d2
+    python tests/golden/make_golden.py o3_4096
 """
 from __future__ import annotations
 
@@ -44,7 +44,7 @@ def inputs(name):
         return synth.sphere(192, 3, seed=0)
     if name == "c3_o3_1024":
         return synth.orthogonal_3x3(1024, seed=0)
-    if name in ("o3_4096", "o3_4096_d2"):
+    if name == "o3_4096":
         return synth.orthogonal_3x3(4096, seed=0)
     raise KeyError(name)
 
