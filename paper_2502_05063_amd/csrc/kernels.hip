@@ -359,8 +359,30 @@ __device__ void h0_finish(unsigned long long* mst, int m, int* parent, int n, ui
   for (int i = m + tid; i < P; i += kH0Threads) mst[i] = ~0ull;
   for (int v = tid; v < n; v += kH0Threads) parent[v] = v;
   __syncthreads();
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
+  // Stages whose partner distance j is below 64 pair elements of the same
+  // 64-element chunk: a wave sorts a chunk in registers with shuffles (every
+  // k <= 64 at once, then the j < 64 tail of each larger k); only the stages
+  // with j >= 64 go through LDS with a workgroup barrier each.
+  const int wave = tid >> 6, lane = tid & 63;
+  auto chunk_stages = [&](int k_from, int k_to) {
+    for (int c0 = wave * 64; c0 < P; c0 += kH0Threads) {
+      const int i = c0 + lane;
+      unsigned long long x = mst[i];
+      for (int k = k_from; k <= k_to; k <<= 1) {
+        const bool up = (i & k) == 0;
+        for (int j = (k >> 1) < 32 ? (k >> 1) : 32; j > 0; j >>= 1) {
+          const unsigned long long y = shfl_xor_u64(x, j);
+          const bool low = (lane & j) == 0;  // the smaller index of the pair
+          x = ((x > y) == (low == up)) ? y : x;
+        }
+      }
+      mst[i] = x;
+    }
+  };
+  if (P >= 2) chunk_stages(2, P < 64 ? P : 64);
+  __syncthreads();
+  for (int k = 128; k <= P; k <<= 1) {
+    for (int j = k >> 1; j >= 64; j >>= 1) {
       for (int i = tid; i < P; i += kH0Threads) {
         int l = i ^ j;
         if (l > i) {
@@ -374,6 +396,8 @@ __device__ void h0_finish(unsigned long long* mst, int m, int* parent, int n, ui
       }
       __syncthreads();
     }
+    chunk_stages(k, k);
+    __syncthreads();
   }
 
   // the forest edges are H0 deaths: clear them for dimension 1
@@ -383,7 +407,6 @@ __device__ void h0_finish(unsigned long long* mst, int m, int* parent, int n, ui
   }
   if (tid >= 64) return;  // the rest is one wave's
 
-  const int lane = tid;
   for (int base = 0; base < m; base += 64) {
     const int i = base + lane;
     const bool live = i < m;

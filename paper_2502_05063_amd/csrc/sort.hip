@@ -2,9 +2,10 @@
 // non-apparent columns in coboundary order: diameter descending, index
 // ascending (Alg. 18), grouped by cloud.
 //
-// Per digit pass, three kernels:
+// Per digit pass, four kernels:
 //   hist     per tile of kTile records, the digit histogram -> counts[digit][tile]
-//   scan     exclusive scan of counts in digit-major order -> global offsets
+//   scans    exclusive scan of counts in digit-major order: each digit's row
+//            by a workgroup of its own, then the 256 row totals -> offsets
 //   scatter  per tile: stable rank of every record among the equal digits of
 //            its tile (wave64 match by 8 ballots, cross-wave prefix in LDS),
 //            records staged in LDS in digit order, then written out so that
@@ -60,36 +61,52 @@ __global__ __launch_bounds__(kSortThreads) void hist_kernel(const Column* __rest
 }
 
 // Exclusive scan, in digit-major order, of the counters of the tiles that
-// hold records (counts[digit * ntiles + tile], tile < active tiles), with
-// one workgroup of 1024 threads: contiguous chunks per thread, then a scan of
-// the chunk sums.
-__global__ __launch_bounds__(1024) void scan_kernel(uint32_t* __restrict__ c, int ntiles,
-                                                    int64_t n_cap,
-                                                    const unsigned long long* n_dev) {
-  __shared__ uint32_t sums[1024];
+// hold records (counts[digit * ntiles + tile], tile < active tiles), in two
+// steps: every digit's row is scanned by a workgroup of its own (contiguous
+// chunks per thread, then a scan of the chunk sums), which leaves the row's
+// total in row_base[digit]; then one workgroup turns the 256 totals into
+// the rows' starting offsets, which the scatter adds.
+__global__ __launch_bounds__(kRadix) void row_scan_kernel(uint32_t* __restrict__ c, int ntiles,
+                                                          int64_t n_cap,
+                                                          const unsigned long long* n_dev,
+                                                          uint32_t* __restrict__ row_base) {
+  __shared__ uint32_t sums[kRadix];
   const int64_t n = record_count(n_cap, n_dev);
-  const int64_t act = (n + kTile - 1) / kTile;
-  const int64_t len = act * kRadix;
-  auto at = [&](int64_t i) -> uint32_t& { return c[(i / act) * ntiles + (i % act)]; };
-  const int64_t per = (len + 1023) / 1024;
-  const int64_t b = threadIdx.x * per;
-  const int64_t e = b + per < len ? b + per : len;
+  const int act = (int)((n + kTile - 1) / kTile);
+  uint32_t* row = c + (int64_t)blockIdx.x * ntiles;
+  const int per = (act + kRadix - 1) / kRadix;
+  const int b = threadIdx.x * per;
+  const int e = b + per < act ? b + per : act;
   uint32_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += at(i);
+  for (int i = b; i < e; ++i) s += row[i];
   sums[threadIdx.x] = s;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    uint32_t x = threadIdx.x >= (unsigned)o ? sums[threadIdx.x - o] : 0;
+  for (int o = 1; o < kRadix; o <<= 1) {
+    const uint32_t x = threadIdx.x >= (unsigned)o ? sums[threadIdx.x - o] : 0;
     __syncthreads();
     sums[threadIdx.x] += x;
     __syncthreads();
   }
   uint32_t run = threadIdx.x ? sums[threadIdx.x - 1] : 0;
-  for (int64_t i = b; i < e; ++i) {
-    uint32_t x = at(i);
-    at(i) = run;
+  for (int i = b; i < e; ++i) {
+    const uint32_t x = row[i];
+    row[i] = run;
     run += x;
   }
+  if (threadIdx.x == kRadix - 1) row_base[blockIdx.x] = sums[kRadix - 1];
+}
+
+__global__ __launch_bounds__(kRadix) void base_scan_kernel(uint32_t* __restrict__ row_base) {
+  __shared__ uint32_t t[kRadix];
+  t[threadIdx.x] = row_base[threadIdx.x];
+  __syncthreads();
+  for (int o = 1; o < kRadix; o <<= 1) {
+    const uint32_t x = threadIdx.x >= (unsigned)o ? t[threadIdx.x - o] : 0;
+    __syncthreads();
+    t[threadIdx.x] += x;
+    __syncthreads();
+  }
+  row_base[threadIdx.x] = threadIdx.x ? t[threadIdx.x - 1] : 0;
 }
 
 __global__ __launch_bounds__(kSortThreads) void scatter_kernel(const Column* __restrict__ a,
@@ -98,6 +115,7 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(const Column* __r
                                                                const unsigned long long* n_dev,
                                                                Pass p,
                                                                const uint32_t* __restrict__ offs,
+                                                               const uint32_t* __restrict__ row_base,
                                                                int ntiles) {
   __shared__ Column stage[kTile];
   __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
@@ -176,15 +194,16 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(const Column* __r
     if (j < cnt) {
       const Column r = stage[j];
       const uint32_t d = digit_of(r, p);
-      out[(int64_t)offs[(int64_t)d * ntiles + blockIdx.x] + (j - excl[d])] = r;
+      out[(int64_t)row_base[d] + offs[(int64_t)d * ntiles + blockIdx.x] + (j - excl[d])] = r;
     }
   }
 }
 
+// the tile counters, then the 256 row bases
 size_t radix_sort_work_bytes(int64_t n) {
   int64_t ntiles = (n + kTile - 1) / kTile;
   if (ntiles < 1) ntiles = 1;
-  return (size_t)ntiles * kRadix * sizeof(uint32_t);
+  return ((size_t)ntiles + 1) * kRadix * sizeof(uint32_t);
 }
 
 hipError_t radix_sort_columns(Column* a, Column* tmp, int64_t n, int cidx_bits, int cloud_bits,
@@ -195,6 +214,7 @@ hipError_t radix_sort_columns(Column* a, Column* tmp, int64_t n, int cidx_bits, 
   if (n < 1) return hipSuccess;
   const int ntiles = (int)((n + kTile - 1) / kTile);
   uint32_t* counts = static_cast<uint32_t*>(work);
+  uint32_t* row_base = counts + (size_t)ntiles * kRadix;
   Pass passes[8 + 4 + 4];
   int np = 0;
   for (int sh = 0; sh < cidx_bits; sh += 8) passes[np++] = {0, sh};
@@ -204,8 +224,10 @@ hipError_t radix_sort_columns(Column* a, Column* tmp, int64_t n, int cidx_bits, 
   Column* dst = tmp;
   for (int i = 0; i < np; ++i) {
     hist_kernel<<<ntiles, kSortThreads, 0, s>>>(src, n, n_dev, passes[i], counts, ntiles);
-    scan_kernel<<<1, 1024, 0, s>>>(counts, ntiles, n, n_dev);
-    scatter_kernel<<<ntiles, kSortThreads, 0, s>>>(src, dst, n, n_dev, passes[i], counts, ntiles);
+    row_scan_kernel<<<kRadix, kRadix, 0, s>>>(counts, ntiles, n, n_dev, row_base);
+    base_scan_kernel<<<1, kRadix, 0, s>>>(row_base);
+    scatter_kernel<<<ntiles, kSortThreads, 0, s>>>(src, dst, n, n_dev, passes[i], counts,
+                                                   row_base, ntiles);
     Column* t = src;
     src = dst;
     dst = t;
