@@ -8,7 +8,10 @@ Workloads (synthetic, seeded; see synth.py):
   c2-all    the same, every pair reported (zero persistence included)
   c3        1024 random O(3) matrices in R^9, threshold 1.8, dimensions 0-3
   c4        256 clouds of 50-400 points (noisy circles and tori), dimensions
-            0-1, one batch forward
+            0-1, one batch forward (dimension 1 reduced on the device)
+  c5        64 noisy tori of 500 points, dimensions 0-1, one batch forward
+  c4-host, c5-host
+            the same batches with dimension 1 reduced on host threads
   o3-4096   4096 random O(3) matrices, threshold 1.4, dimensions 0-3 (the
             size of the paper's o3 run)
   boundary  the boundary matrix of a Rips 2-skeleton (2000 points, 0.22)
@@ -55,7 +58,7 @@ def run(names=None, reps=3):
         print(json.dumps(rec), flush=True)
         out.append(rec)
 
-    want = set(names or ["c1", "c2", "c2-all", "c3", "c4", "o3-4096", "boundary"])
+    want = set(names or ["c1", "c2", "c2-all", "c3", "c4", "c5", "o3-4096", "boundary"])
     if "c1" in want:
         single("c1", dev(synth.uniform_cube(64, 3, 0)), max_dim=1)
     if "c2" in want:
@@ -67,12 +70,20 @@ def run(names=None, reps=3):
     if "o3-4096" in want:
         single("o3-4096", dev(synth.orthogonal_3x3(4096, 0)), max_dim=3, threshold=1.4,
                autotune=True)
-    if "c4" in want:
-        clouds = synth.circle_or_torus_batch(256, 50, 400, 0.05, seed=0)
-        b = ctx.batch([len(c) for c in clouds], 3, max_dim=1)
+    for name in ("c4", "c4-host", "c5", "c5-host"):
+        if name not in want:
+            continue
+        if name.startswith("c4"):
+            clouds = synth.circle_or_torus_batch(256, 50, 400, 0.05, seed=0)
+        else:
+            clouds = synth.torus_batch(64, 500, 0.1, seed=0)
+        b = ctx.batch([len(c) for c in clouds], 3, max_dim=1,
+                      host_reduction=name.endswith("-host"))
         Xb = dev(np.concatenate(clouds))
         ms, res = _timed(lambda: b.forward(Xb), reps)
-        rec = {"workload": "c4", "ms": ms, "stats": res[0].stats}
+        rec = {"workload": name, "ms": ms, "stats": res[0].stats,
+               "additions": int(sum(r.stats["additions"][1] for r in res)),
+               "device_reduced": int(sum(r.stats["device_reduced"] for r in res))}
         print(json.dumps(rec), flush=True)
         out.append(rec)
         b.close()
