@@ -303,6 +303,55 @@ vrph_status vrph_boundary_pivots(vrph_ctx* ctx, int64_t ncols, const int64_t* co
                                  const int64_t* rows, uint32_t flags, void* hip_stream,
                                  int64_t* low_out, vrph_boundary_stats* stats);
 
+/* ---- extended persistence of graphs (Sec. 7.2, Alg. 27-28) ---------------
+ * A consumer of persistence on a different input: graphs with a value f(v)
+ * per vertex, as used for graph readouts (Ch. 7). The extended filtration of
+ * the coned graph (Eq. 7.3-7.4: the lower filtration of G, edges at
+ * F_low(u, v) = max(f(u), f(v)), then the upper filtration of the cone, cone
+ * edges at f(v) and cone triangles at F_up(u, v) = min(f(u), f(v)),
+ * descending) gives four barcodes (Theorem 7.6.2):
+ *   VRPH_EXT_ORD0  birth a vertex, death an edge (lower filtration)      n - C bars
+ *   VRPH_EXT_REL1  birth a vertex, death an edge (upper filtration)      n - C bars
+ *   VRPH_EXT_EXT0  birth a component's minimum vertex, death its maximum   C bars
+ *   VRPH_EXT_EXT1  birth an edge (lower), death an edge (upper)      m - n + C bars
+ * (C components), n + m bars per graph in all. Ties are broken by an exact
+ * order: vertices by (f, vertex), lower edges by (F_low, F_up, edge id),
+ * upper edges by (F_up, F_low, edge id) descending. birth_vertex /
+ * death_vertex name the vertex whose f is the bar's value (for a lower edge
+ * value the endpoint with the larger (f, vertex), for an upper one the
+ * smaller), where a loss's gradient with respect to f goes. */
+#define VRPH_EXT_ORD0 0
+#define VRPH_EXT_REL1 1
+#define VRPH_EXT_EXT0 2
+#define VRPH_EXT_EXT1 3
+typedef struct {
+  int32_t kind;         /* VRPH_EXT_* */
+  int32_t birth;        /* vertex (ORD0, REL1, EXT0) or edge id (EXT1), local to the graph */
+  int32_t death;        /* edge id (ORD0, REL1, EXT1) or vertex (EXT0) */
+  float birth_value;
+  float death_value;
+  int32_t birth_vertex;
+  int32_t death_vertex;
+} vrph_ext_bar;
+
+/* The four barcodes of each of `count` graphs. v_off and e_off are HOST
+ * arrays of count + 1 offsets (v_off[0] = e_off[0] = 0, non-decreasing):
+ * graph g has vertices [v_off[g], v_off[g+1]) and edges [e_off[g],
+ * e_off[g+1]). f (v_off[count] floats, finite) and edges (2 e_off[count]
+ * int32: the two endpoints of each edge, numbered within its graph, distinct)
+ * are DEVICE arrays; a repeated edge is allowed (a multigraph). bars is a
+ * caller-owned DEVICE array of v_off[count] + e_off[count] records: graph
+ * g's n + m bars fill [v_off[g] + e_off[g], v_off[g+1] + e_off[g+1]), Ord0
+ * and Rel1 bars first in the order their union-find passes find them, then
+ * Ext0, then Ext1 in the order of their death edges in the upper
+ * filtration. 1 <= n <= 4096 per graph, totals below 2^31. VRPH_EINVAL for
+ * bad offsets, an endpoint outside its graph, a loop or a value that is not
+ * finite (checked on the device before anything else runs; bars is then
+ * left unwritten). */
+vrph_status vrph_graph_extended(vrph_ctx* ctx, int32_t count, const int64_t* v_off,
+                                const int64_t* e_off, const float* f, const int32_t* edges,
+                                vrph_ext_bar* bars, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -206,6 +206,8 @@ struct vrph_ctx {
   DevBuf bscan;                    // scratch of the boundary-matrix scan
   DevBuf h0w;                      // scratch of H0 for large clouds
   DevBuf bflag;                    // edge check of the backward
+  // extended persistence of graphs: offsets, sort records, per-graph scratch
+  DevBuf g_off, g_lower, g_upper, g_tmp, g_pos, g_adj_off, g_adj, g_stack, g_err;
   std::vector<uint64_t> h_pfx_cum;
   std::vector<uint64_t> h_units;
 };
@@ -309,7 +311,8 @@ extern "C" void vrph_destroy(vrph_ctx* c) {
                     &c->cstate,  &c->h0,    &c->deaths, &c->units,   &c->wr16,
                     &c->rank_bits, &c->sink_ctr, &c->ap_ctr, &c->ap_tmp, &c->hflag,
                     &c->pfx_v,     &c->pfx_cum,  &c->bscan,  &c->h0w,
-                    &c->bflag};
+                    &c->bflag,     &c->g_off,    &c->g_lower, &c->g_upper, &c->g_tmp,
+                    &c->g_pos,     &c->g_adj_off, &c->g_adj, &c->g_stack,  &c->g_err};
   for (DevBuf* b : bufs) b->release();
   for (DevBuf& b : c->hset) b.release();
   c->h_scal.release();
@@ -1073,6 +1076,66 @@ extern "C" vrph_status vrph_backward_noalloc(vrph_ctx* c, const float* X, int64_
   if (flag)
     return fail(VRPH_EINVAL,
                 "vrph_backward_noalloc: an edge entry is neither -1 nor a point in [0, n_total)");
+  return VRPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// extended persistence of graphs
+// ---------------------------------------------------------------------------
+
+extern "C" vrph_status vrph_graph_extended(vrph_ctx* c, int32_t count, const int64_t* v_off,
+                                           const int64_t* e_off, const float* f,
+                                           const int32_t* edges, vrph_ext_bar* bars,
+                                           void* hip_stream) {
+  if (!c || count < 1 || !v_off || !e_off)
+    return fail(VRPH_EINVAL, "vrph_graph_extended: bad argument");
+  if (v_off[0] != 0 || e_off[0] != 0)
+    return fail(VRPH_EINVAL, "vrph_graph_extended: offsets must start at 0");
+  int max_n = 1;
+  for (int g = 0; g < count; ++g) {
+    const int64_t n = v_off[g + 1] - v_off[g], m = e_off[g + 1] - e_off[g];
+    if (n < 1 || n > kGraphMaxN)
+      return fail(VRPH_EINVAL, "vrph_graph_extended: every graph needs 1 to 4096 vertices");
+    if (m < 0) return fail(VRPH_EINVAL, "vrph_graph_extended: edge offsets decrease");
+    max_n = std::max<int>(max_n, (int)n);
+  }
+  const int64_t V = v_off[count], E = e_off[count];
+  if (V + E >= ((int64_t)1 << 31) || E >= ((int64_t)1 << 31) - 1)
+    return fail(VRPH_EINVAL, "vrph_graph_extended: totals must stay below 2^31");
+  if (!f || !bars || (E > 0 && !edges))
+    return fail(VRPH_EINVAL, "vrph_graph_extended: NULL array");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  const size_t ne = (size_t)std::max<int64_t>(E, 1);
+  HIP_TRY(c->g_off.ensure((size_t)(count + 1) * 2 * sizeof(int64_t)));
+  HIP_TRY(c->g_lower.ensure(ne * sizeof(Column)));
+  HIP_TRY(c->g_upper.ensure(ne * sizeof(Column)));
+  HIP_TRY(c->g_tmp.ensure(ne * sizeof(Column)));
+  HIP_TRY(c->sort_work.ensure(radix_sort_work_bytes((int64_t)ne)));
+  HIP_TRY(c->g_pos.ensure(ne * 4));
+  HIP_TRY(c->g_adj_off.ensure((size_t)(V + count + 1) * 4));
+  HIP_TRY(c->g_adj.ensure((size_t)std::max<int64_t>(2 * V, 1) * 4));
+  HIP_TRY(c->g_stack.ensure((size_t)std::max<int64_t>(V, 1) * 4));
+  HIP_TRY(c->g_err.ensure(sizeof(uint32_t)));
+  int64_t* doff = c->g_off.as<int64_t>();
+  HIP_TRY(hipMemcpyAsync(doff, v_off, (size_t)(count + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(doff + count + 1, e_off, (size_t)(count + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_graph_ext(doff, doff + count + 1, count, V, E, max_n, f, edges,
+                           c->g_lower.as<Column>(), c->g_upper.as<Column>(),
+                           c->g_tmp.as<Column>(), c->sort_work.p, c->g_pos.as<uint32_t>(),
+                           c->g_adj_off.as<uint32_t>(), c->g_adj.as<uint32_t>(),
+                           c->g_stack.as<uint32_t>(), c->g_err.as<uint32_t>(), bars, s));
+  uint32_t err = 0;
+  HIP_TRY(hipMemcpyAsync(&err, c->g_err.p, sizeof(err), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (err & 7u)
+    return fail(VRPH_EINVAL, std::string("vrph_graph_extended:") +
+                                 ((err & 1u) ? " an edge endpoint outside its graph" : "") +
+                                 ((err & 2u) ? " a loop" : "") +
+                                 ((err & 4u) ? " a value that is not finite" : ""));
+  if (err) return fail(VRPH_EDEVICE, "vrph_graph_extended: an internal consistency check failed");
   return VRPH_OK;
 }
 

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "vrph.h"
+
 namespace vrph {
 
 // Edge weights are the IEEE bit patterns of the float32 distances, which
@@ -275,6 +277,21 @@ hipError_t launch_dred_prepare(const uint32_t* W, const Cloud* clouds, int count
 // The bitmaps, counts and V bitmaps must be zero on entry; they are zero
 // again on exit.
 hipError_t launch_dred_reduce(const DredArgs& args, int64_t cols_cap, int max_n, hipStream_t s);
+
+// ---- graph_ext.hip ----
+// Extended persistence of a batch of graphs (Sec. 7.2, Alg. 27-28): v_off /
+// e_off are device copies of the count + 1 offsets; lower / upper / tmp
+// hold total_edges records; pos_list total_edges, adj_off total_vertices +
+// count + 1, adj 2 total_vertices, stack total_vertices entries; err one
+// word (nonzero: invalid input, nothing indexed); bars v_off[count] +
+// e_off[count] records. Every graph has 1 <= n <= max_n <= kGraphMaxN.
+constexpr int kGraphMaxN = 4096;
+hipError_t launch_graph_ext(const int64_t* v_off, const int64_t* e_off, int count,
+                            int64_t total_vertices, int64_t total_edges, int max_n,
+                            const float* f, const int32_t* edges, Column* lower, Column* upper,
+                            Column* tmp, void* sort_work, uint32_t* pos_list, uint32_t* adj_off,
+                            uint32_t* adj, uint32_t* stack, uint32_t* err, vrph_ext_bar* bars,
+                            hipStream_t s);
 
 // ---- noalloc.hip ----
 // Words of the fixed per-device scratch array of the allocation-free entry

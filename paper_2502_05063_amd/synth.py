@@ -162,3 +162,30 @@ def rips2_boundary_csc(D: np.ndarray, tau: float):
     for k in range(3):
         rows[col_ptr[pt] + k] = tcols[order[pt] - nv - ne, k]
     return col_ptr, rows
+
+
+def erdos_renyi(n: int, p: float, seed: int):
+    """An Erdos-Renyi graph G(n, p) with a standard normal value per vertex
+    (the graphs of the paper's extended-persistence timing, Fig. 7.7, with
+    random instead of learned vertex values): int32 edges [m, 2] (a < b)
+    and float32 f [n]."""
+    rng = np.random.default_rng(seed)
+    a, b = np.triu_indices(n, 1)
+    keep = rng.random(len(a)) < p
+    E = np.stack([a[keep], b[keep]], 1).astype(np.int32)
+    f = rng.standard_normal(n).astype(np.float32)
+    return E, f
+
+
+def graph_batch(count: int, n_lo: int, n_hi: int, degree: float, seed: int):
+    """A batch of graph-classification-like graphs: sizes uniform in
+    [n_lo, n_hi], each G(n, degree / (n - 1)) with standard normal vertex
+    values. Returns (graphs, v_off, e_off) with graphs a list of (E, f)."""
+    rng = np.random.default_rng(seed)
+    graphs = []
+    for _ in range(count):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        graphs.append(erdos_renyi(n, min(1.0, degree / max(n - 1, 1)), int(rng.integers(2**31))))
+    v_off = np.concatenate([[0], np.cumsum([len(f) for _, f in graphs])]).astype(np.int64)
+    e_off = np.concatenate([[0], np.cumsum([len(E) for E, _ in graphs])]).astype(np.int64)
+    return graphs, v_off, e_off

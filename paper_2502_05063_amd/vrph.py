@@ -23,6 +23,10 @@ HASHED_CLEARING = 16
 BOUNDARY_NO_CLEARING = 32
 BOUNDARY_NO_COMPRESSION = 64
 HOST_REDUCTION = 128
+EXT_ORD0, EXT_REL1, EXT_EXT0, EXT_EXT1 = 0, 1, 2, 3
+EXT_BAR_DTYPE = np.dtype([("kind", "<i4"), ("birth", "<i4"), ("death", "<i4"),
+                          ("birth_value", "<f4"), ("death_value", "<f4"),
+                          ("birth_vertex", "<i4"), ("death_vertex", "<i4")])
 MAX_DIM = 6
 
 PAIR_DTYPE = np.dtype(
@@ -119,6 +123,7 @@ def lib():
         "vrph_backward": (i32, [vp, vp, i64, i32, vp, i64, vp, vp, vp, vp]),
         "vrph_backward_noalloc": (i32, [vp, vp, i64, i32, vp, i64, vp, vp, vp, vp]),
         "vrph_boundary_pivots": (i32, [vp, i64, vp, vp, u32, vp, vp, P(BoundaryStats)]),
+        "vrph_graph_extended": (i32, [vp, i32, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -296,6 +301,29 @@ class Context:
                                            _dev_ptr(edges), edges.shape[0], _dev_ptr(g_birth),
                                            _dev_ptr(g_death), _dev_ptr(gX), _stream_ptr()))
         return gX
+
+    def graph_extended(self, f, edges, v_off, e_off, host=True):
+        """Extended persistence of a batch of graphs (vrph_graph_extended):
+        f float32 [V] and edges int32 [E, 2] (endpoints numbered within their
+        graph) on the device, v_off / e_off the count + 1 offsets. Returns the
+        device int32 tensor of bars ([V + E, 7], vrph_ext_bar records) and,
+        with host=True, a list of EXT_BAR_DTYPE arrays, one per graph."""
+        import torch
+
+        f = self._f32(f)
+        edges = edges.to(torch.int32).contiguous()
+        v_off = np.ascontiguousarray(v_off, dtype=np.int64)
+        e_off = np.ascontiguousarray(e_off, dtype=np.int64)
+        count = len(v_off) - 1
+        bars = torch.empty((int(v_off[-1] + e_off[-1]), 7), dtype=torch.int32, device=f.device)
+        _check(lib().vrph_graph_extended(self.h, count, v_off.ctypes.data_as(ctypes.c_void_p),
+                                         e_off.ctypes.data_as(ctypes.c_void_p), _dev_ptr(f),
+                                         _dev_ptr(edges), _dev_ptr(bars), _stream_ptr()))
+        if not host:
+            return bars
+        rec = bars.cpu().numpy().reshape(-1).view(EXT_BAR_DTYPE)
+        start = v_off + e_off
+        return bars, [rec[start[g]:start[g + 1]] for g in range(count)]
 
     def batch(self, sizes, m, max_dim=1, threshold=float("inf"), keep_zero=False,
               no_enclosing=False, host_reduction=False):

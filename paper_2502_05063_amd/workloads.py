@@ -16,6 +16,10 @@ Workloads (synthetic, seeded; see synth.py):
             size of the paper's o3 run)
   boundary  the boundary matrix of a Rips 2-skeleton (2000 points, 0.22)
             through the explicit-matrix path
+  graphs    extended persistence of 1024 graphs of 20-300 vertices (mean
+            degree 4), one batch
+  er-N      extended persistence of one Erdos-Renyi graph G(N, 0.1), N in
+            200, 500, 1000, 2000 (the sizes of the paper's Fig. 7.7)
 
 Each line holds the median wall time of the timed calls (after one untimed
 call that also fills the autotuner's choices) and the last call's stats.
@@ -93,6 +97,21 @@ def run(names=None, reps=3):
         dptr, drows = dev(ptr), dev(rows)
         ms, (low, st) = _timed(lambda: ctx.boundary_pivots(dptr, drows), reps)
         rec = {"workload": "boundary", "ms": ms, "stats": st, "pivots": int((low >= 0).sum())}
+        print(json.dumps(rec), flush=True)
+        out.append(rec)
+    gsets = []
+    if "graphs" in want:
+        gsets.append(("graphs",) + synth.graph_batch(1024, 20, 300, 4.0, seed=0))
+    for nn in (200, 500, 1000, 2000):
+        if f"er-{nn}" in want:
+            E, f = synth.erdos_renyi(nn, 0.1, seed=nn)
+            gsets.append((f"er-{nn}", [(E, f)], np.array([0, nn]), np.array([0, len(E)])))
+    for name, graphs, v_off, e_off in gsets:
+        f = dev(np.concatenate([f for _, f in graphs]))
+        E = dev(np.concatenate([E for E, _ in graphs]))
+        ms, _ = _timed(lambda: ctx.graph_extended(f, E, v_off, e_off, host=False), reps)
+        rec = {"workload": name, "ms": ms, "graphs": len(graphs), "vertices": int(v_off[-1]),
+               "edges": int(e_off[-1])}
         print(json.dumps(rec), flush=True)
         out.append(rec)
     ctx.close()
