@@ -48,7 +48,8 @@ typedef enum {
   VRPH_ENOMEM = -2,    /* device or host allocation failed */
   VRPH_EOVERFLOW = -3, /* C(n, max_dim + 2) >= 2^63: indices do not fit */
   VRPH_EDEVICE = -4,   /* a HIP call failed */
-  VRPH_ESTATE = -5     /* call not valid in the object's current state */
+  VRPH_ESTATE = -5     /* call not valid in the object's current state, or a call
+                          that waits for its stream made on a stream under capture */
 } vrph_status;
 
 /* flags */
@@ -219,7 +220,10 @@ void vrph_barcode_free(vrph_barcode* bc);
  * VRPH_HOST_REDUCTION. Each size must satisfy 2 <= size <= 4096 and every
  * cloud uses the same max_dim (<= 1). vrph_batch_plan accepts
  * VRPH_KEEP_ZERO_PERSISTENCE, VRPH_NO_ENCLOSING_RADIUS and
- * VRPH_HOST_REDUCTION. */
+ * VRPH_HOST_REDUCTION. It sizes every device buffer first and returns
+ * VRPH_ENOMEM, allocating nothing, when they exceed the free device memory
+ * or the byte count in the environment variable VRPH_WORKSPACE_CAP (if
+ * set); a plan that fails frees whatever it had allocated. */
 vrph_status vrph_batch_plan(vrph_ctx* ctx, const int64_t* sizes, int32_t count, int32_t m,
                             int32_t max_dim, float threshold, uint32_t flags, vrph_batch** out);
 vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, void* hip_stream);

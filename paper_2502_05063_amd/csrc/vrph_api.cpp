@@ -56,15 +56,37 @@ static vrph_status fail(vrph_status st, const std::string& msg) {
 
 extern "C" const char* vrph_last_error(void) { return g_last_error.c_str(); }
 
+// Entry points that wait for their stream (to hand results back) cannot run
+// under a caller's stream capture: they say so instead of breaking it.
+static vrph_status check_not_capturing(hipStream_t s, const char* who) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return VRPH_OK;  // the call itself reports
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(VRPH_ESTATE, std::string(who) + ": called on a stream under capture");
+  return VRPH_OK;
+}
+
+#define NOT_CAPTURING(s, who)                      \
+  do {                                             \
+    vrph_status st_ = check_not_capturing(s, who); \
+    if (st_ != VRPH_OK) return st_;                \
+  } while (0)
+
 // ---------------------------------------------------------------------------
 // buffers
 // ---------------------------------------------------------------------------
 
 namespace {
 
+// Device buffer owned by a context or a batch plan: grows on demand, freed
+// by release() or when its owner is deleted (also on an owner's failed set-up).
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
   hipError_t ensure(size_t bytes) {
     if (bytes <= cap && p) return hipSuccess;
     if (p) (void)hipFree(p);
@@ -89,6 +111,10 @@ struct DevBuf {
 struct HostPinned {
   void* p = nullptr;
   size_t cap = 0;
+  HostPinned() = default;
+  HostPinned(const HostPinned&) = delete;
+  HostPinned& operator=(const HostPinned&) = delete;
+  ~HostPinned() { release(); }
   hipError_t ensure(size_t bytes) {
     if (bytes <= cap && p) return hipSuccess;
     if (p) (void)hipHostFree(p);
@@ -997,6 +1023,7 @@ extern "C" vrph_status vrph_barcode_from_dist(vrph_ctx* c, const float* D, int64
   if (!D) return fail(VRPH_EINVAL, "D is NULL");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  NOT_CAPTURING(s, "vrph_barcode_from_dist");
   return barcode_impl(c, D, (int)n, max_dim, threshold, flags, s, out);
 }
 
@@ -1009,6 +1036,7 @@ extern "C" vrph_status vrph_barcode_from_points(vrph_ctx* c, const float* X, int
   if (!X || m < 1) return fail(VRPH_EINVAL, "X is NULL or m < 1");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  NOT_CAPTURING(s, "vrph_barcode_from_points");
   HIP_TRY(c->D.ensure((size_t)n * n * 4));
   st = upload_single_cloud(c, (int)n, INFINITY, s);
   if (st) return st;
@@ -1028,6 +1056,7 @@ extern "C" vrph_status vrph_barcode_from_sparse(vrph_ctx* c, int64_t n, int64_t 
   if (nnz > 0 && (!row || !col || !val)) return fail(VRPH_EINVAL, "row, col or val is NULL");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  NOT_CAPTURING(s, "vrph_barcode_from_sparse");
   HIP_TRY(c->D.ensure((size_t)n * n * 4));
   const SparseInput sp{row, col, val, nnz};
   return barcode_impl(c, c->D.as<float>(), (int)n, max_dim, threshold, flags, s, out, &sp);
@@ -1046,6 +1075,7 @@ extern "C" vrph_status vrph_backward(vrph_ctx* c, const float* X, int64_t n_tota
     return fail(VRPH_EINVAL, "vrph_backward: NULL pair arrays");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  NOT_CAPTURING(s, "vrph_backward");
   HIP_TRY(c->bflag.ensure(sizeof(uint32_t)));
   HIP_TRY(launch_backward(X, n_total, m, edges, npairs, g_birth, g_death, gX,
                           c->bflag.as<uint32_t>(), s));
@@ -1069,6 +1099,7 @@ extern "C" vrph_status vrph_backward_noalloc(vrph_ctx* c, const float* X, int64_
   if (!bad) return fail(VRPH_ESTATE, "vrph_backward_noalloc: scratch of this device not set up");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  NOT_CAPTURING(s, "vrph_backward_noalloc");
   HIP_TRY(launch_backward(X, n_total, m, edges, npairs, g_birth, g_death, gX, bad, s));
   uint32_t flag = 0;
   HIP_TRY(hipMemcpyAsync(&flag, bad, sizeof(flag), hipMemcpyDeviceToHost, s));
@@ -1106,6 +1137,7 @@ extern "C" vrph_status vrph_graph_extended(vrph_ctx* c, int32_t count, const int
     return fail(VRPH_EINVAL, "vrph_graph_extended: NULL array");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  NOT_CAPTURING(s, "vrph_graph_extended");
   const size_t ne = (size_t)std::max<int64_t>(E, 1);
   HIP_TRY(c->g_off.ensure((size_t)(count + 1) * 2 * sizeof(int64_t)));
   HIP_TRY(c->g_lower.ensure(ne * sizeof(Column)));
@@ -1161,6 +1193,7 @@ extern "C" vrph_status vrph_boundary_pivots(vrph_ctx* c, int64_t ncols, const in
   }
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  NOT_CAPTURING(s, "vrph_boundary_pivots");
   const size_t n = (size_t)ncols;
   std::vector<int64_t> hptr(n + 1);
   HIP_TRY(hipMemcpyAsync(hptr.data(), col_ptr, 8 * (n + 1), hipMemcpyDeviceToHost, s));
@@ -1283,7 +1316,9 @@ struct vrph_batch {
 // max(65536, E / 2) edges (more: the host); 16384 logged V words (more: V
 // is read whole). Bitmaps and counts start at zero and the kernel leaves
 // them at zero; epos starts at ~0 (the diagonal stays so).
-static vrph_status dred_plan(vrph_batch* b) {
+using Want = std::vector<std::pair<DevBuf*, size_t>>;
+
+static void dred_sizes(vrph_batch* b, Want& want) {
   b->hdc.resize((size_t)b->count);
   int64_t tri = 0, tlog = 0, tab = 0, va = 0, vt = 0;
   for (int i = 0; i < b->count; ++i) {
@@ -1319,32 +1354,30 @@ static vrph_status dred_plan(vrph_batch* b) {
   }
   const size_t ne = (size_t)std::max<int64_t>(b->total_edges, 1);
   const size_t cnt = (size_t)b->count;
-  HIP_TRY(b->ddc.ensure(cnt * sizeof(DredCloud)));
-  HIP_TRY(b->ew.ensure(ne * 4));
-  HIP_TRY(b->eat.ensure(ne * 4));
-  HIP_TRY(b->egrp.ensure(ne * 4));
-  HIP_TRY(b->egend.ensure(ne * 4));
-  HIP_TRY(b->ecnt.ensure(ne * 4));
-  HIP_TRY(b->epos.ensure((size_t)b->total_w * 4));
-  HIP_TRY(b->tri.ensure((size_t)tri * 4));
-  HIP_TRY(b->tlog.ensure((size_t)tlog * 4));
-  HIP_TRY(b->tab_keys.ensure((size_t)tab * 8));
-  HIP_TRY(b->tab_vals.ensure((size_t)tab * 4));
-  HIP_TRY(b->varena.ensure((size_t)va * 4));
-  HIP_TRY(b->vbits.ensure((size_t)std::max<int64_t>(b->total_words, 1) * 4));
-  HIP_TRY(b->vtouch.ensure((size_t)vt * 4));
-  HIP_TRY(b->col_begin.ensure(cnt * 4));
-  HIP_TRY(b->col_end.ensure(cnt * 4));
-  HIP_TRY(b->out_death.ensure(ne * 8));
-  HIP_TRY(b->out_ddiam.ensure(ne * 4));
-  HIP_TRY(b->out_dedge.ensure(ne * 4));
-  HIP_TRY(b->col_voff.ensure(ne * 4));
-  HIP_TRY(b->col_vlen.ensure(ne * 4));
-  HIP_TRY(b->dstats.ensure(cnt * sizeof(DredStats)));
-  HIP_TRY(hipMemcpy(b->ddc.p, b->hdc.data(), cnt * sizeof(DredCloud), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemset(b->tri.p, 0, (size_t)tri * 4));
+  const size_t words = (size_t)std::max<int64_t>(b->total_words, 1);
+  want.insert(want.end(), {{&b->ddc, cnt * sizeof(DredCloud)}, {&b->ew, ne * 4},
+                           {&b->eat, ne * 4}, {&b->egrp, ne * 4}, {&b->egend, ne * 4},
+                           {&b->ecnt, ne * 4}, {&b->epos, (size_t)b->total_w * 4},
+                           {&b->tri, (size_t)tri * 4}, {&b->tlog, (size_t)tlog * 4},
+                           {&b->tab_keys, (size_t)tab * 8}, {&b->tab_vals, (size_t)tab * 4},
+                           {&b->varena, (size_t)va * 4}, {&b->vbits, words * 4},
+                           {&b->vtouch, (size_t)vt * 4}, {&b->col_begin, cnt * 4},
+                           {&b->col_end, cnt * 4}, {&b->out_death, ne * 8},
+                           {&b->out_ddiam, ne * 4}, {&b->out_dedge, ne * 4},
+                           {&b->col_voff, ne * 4}, {&b->col_vlen, ne * 4},
+                           {&b->dstats, cnt * sizeof(DredStats)}});
+}
+
+// The device reduction's tables, once allocated: the per-cloud regions, and
+// the bitmaps and counts at zero, epos at ~0.
+static vrph_status dred_init(vrph_batch* b) {
+  const size_t ne = (size_t)std::max<int64_t>(b->total_edges, 1);
+  const size_t words = (size_t)std::max<int64_t>(b->total_words, 1);
+  HIP_TRY(hipMemcpy(b->ddc.p, b->hdc.data(), (size_t)b->count * sizeof(DredCloud),
+                    hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(b->tri.p, 0, b->tri.cap));
   HIP_TRY(hipMemset(b->ecnt.p, 0, ne * 4));
-  HIP_TRY(hipMemset(b->vbits.p, 0, (size_t)std::max<int64_t>(b->total_words, 1) * 4));
+  HIP_TRY(hipMemset(b->vbits.p, 0, words * 4));
   HIP_TRY(hipMemset(b->epos.p, 0xFF, (size_t)b->total_w * 4));
   HIP_TRY(hipDeviceSynchronize());
   return VRPH_OK;
@@ -1393,26 +1426,46 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
   }
   const uint64_t cap = (uint64_t)std::max<int64_t>(b->total_edges, 1);
   const bool keep_zero = flags & VRPH_KEEP_ZERO_PERSISTENCE;
-  HIP_TRY(b->X.ensure((size_t)b->total_points * m * 4));
-  HIP_TRY(b->D.ensure((size_t)b->total_w * 4));
-  HIP_TRY(b->W.ensure((size_t)b->total_w * 4));
-  HIP_TRY(b->dclouds.ensure((size_t)count * sizeof(Cloud)));
-  HIP_TRY(b->cstate.ensure((size_t)count * sizeof(CloudState)));
-  HIP_TRY(b->h0.ensure((size_t)count * b->max_n * sizeof(H0Pair)));
-  HIP_TRY(b->bitmaps.ensure((size_t)std::max<int64_t>(b->total_words, 1) * 4));
-  HIP_TRY(b->cols.ensure(cap * sizeof(Column)));
-  HIP_TRY(b->cols_tmp.ensure(cap * sizeof(Column)));
-  HIP_TRY(b->sort_work.ensure(radix_sort_work_bytes((int64_t)cap)));
-  if (keep_zero) HIP_TRY(b->ap.ensure(cap * sizeof(ApparentPair)));
-  HIP_TRY(b->counters.ensure(sizeof(Scalars)));
+  b->device_reduce = max_dim >= 1 && !(flags & VRPH_HOST_REDUCTION);
+  // every device buffer the plan needs, sized first: a plan larger than the
+  // free device memory (or than VRPH_WORKSPACE_CAP bytes, if set) is refused
+  // before anything is allocated
+  Want want = {{&b->X, (size_t)b->total_points * m * 4},
+               {&b->D, (size_t)b->total_w * 4},
+               {&b->W, (size_t)b->total_w * 4},
+               {&b->dclouds, (size_t)count * sizeof(Cloud)},
+               {&b->cstate, (size_t)count * sizeof(CloudState)},
+               {&b->h0, (size_t)count * b->max_n * sizeof(H0Pair)},
+               {&b->bitmaps, (size_t)std::max<int64_t>(b->total_words, 1) * 4},
+               {&b->cols, cap * sizeof(Column)},
+               {&b->cols_tmp, cap * sizeof(Column)},
+               {&b->sort_work, radix_sort_work_bytes((int64_t)cap)},
+               {&b->counters, sizeof(Scalars)}};
+  if (keep_zero) want.push_back({&b->ap, cap * sizeof(ApparentPair)});
+  if (b->device_reduce) dred_sizes(b.get(), want);
+  size_t need = 0;
+  for (const auto& w : want) need += w.second;
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  size_t limit = free_b;
+  if (const char* e = std::getenv("VRPH_WORKSPACE_CAP")) {
+    const unsigned long long lim = std::strtoull(e, nullptr, 10);
+    if (lim > 0) limit = std::min<size_t>(limit, (size_t)lim);
+  }
+  if (need > limit)
+    return fail(VRPH_ENOMEM, "vrph_batch_plan: the plan needs " + std::to_string(need) +
+                                 " bytes of device memory, " + std::to_string(limit) +
+                                 " are available");
+  for (const auto& w : want) HIP_TRY(w.first->ensure(w.second));
   HIP_TRY(b->h_cstate.ensure((size_t)count * sizeof(CloudState)));
   HIP_TRY(b->h_counters.ensure(sizeof(Scalars)));
-  HIP_TRY(b->h_W.ensure((size_t)b->total_w * 4));
+  // the weights on the host: for the host reduction and for the edges of
+  // apparent pairs (otherwise allocated only if a cloud falls back to the host)
+  if (!b->device_reduce || keep_zero) HIP_TRY(b->h_W.ensure((size_t)b->total_w * 4));
   HIP_TRY(hipMemcpy(b->dclouds.p, b->clouds.data(), (size_t)count * sizeof(Cloud),
                     hipMemcpyHostToDevice));
-  b->device_reduce = max_dim >= 1 && !(flags & VRPH_HOST_REDUCTION);
   if (b->device_reduce) {
-    vrph_status st = dred_plan(b.get());
+    vrph_status st = dred_init(b.get());
     if (st != VRPH_OK) return st;
   }
   b->results.resize(count);
@@ -1537,6 +1590,7 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
   vrph_ctx* c = b->ctx;
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  NOT_CAPTURING(s, "vrph_batch_forward");
   const double t_start = now_ms();
   HIP_TRY(hipMemcpyAsync(b->X.p, X_packed, (size_t)b->total_points * b->m * 4,
                          hipMemcpyDeviceToDevice, s));
@@ -1607,6 +1661,7 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
     for (int i = 0; i < b->count; ++i) fallback += b->hdstats[(size_t)i].err != 0;
   need_w |= fallback > 0;
   if (need_w && b->max_dim >= 1) {
+    HIP_TRY(b->h_W.ensure((size_t)b->total_w * 4));
     HIP_TRY(hipMemcpyAsync(b->h_W.p, b->W.p, (size_t)b->total_w * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
