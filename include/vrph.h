@@ -63,7 +63,8 @@ typedef enum {
  * tunings are read from it when the context is created and appended to it
  * when found (lines "arch dimension size_bucket variant unit_size
  * groups_per_cu", variant 0 for the global-memory kernel, 1 for the LDS one,
- * 2 for the dimension-1 kernel over neighbour lists). */
+ * 2 for the dimension-1 kernel over neighbour lists, 3 for a batch plan,
+ * see vrph_batch_plan). */
 #define VRPH_AUTOTUNE 4u
 /* Use the global-memory enumeration kernels even when the cloud is small
  * enough (n <= 200) for the kernels that read a 16-bit rank matrix from LDS.
@@ -219,8 +220,15 @@ void vrph_barcode_free(vrph_barcode* bc);
  * tables is reduced on host threads instead, as is every cloud under
  * VRPH_HOST_REDUCTION. Each size must satisfy 2 <= size <= 4096 and every
  * cloud uses the same max_dim (<= 1). vrph_batch_plan accepts
- * VRPH_KEEP_ZERO_PERSISTENCE, VRPH_NO_ENCLOSING_RADIUS and
- * VRPH_HOST_REDUCTION. It sizes every device buffer first and returns
+ * VRPH_KEEP_ZERO_PERSISTENCE, VRPH_NO_ENCLOSING_RADIUS, VRPH_HOST_REDUCTION
+ * and VRPH_AUTOTUNE: the first forward then runs the batch's device work
+ * eagerly for a few launch settings (the device reduction's workgroup size,
+ * 256, 512 or 1024 lanes per cloud; the dimension-1 edge kernel's
+ * workgroups per compute unit), timed with HIP events, and captures the
+ * graph with the fastest; the choice is kept per (GPU architecture, size
+ * bucket of the largest cloud) in the context and in VRPH_TUNING_FILE
+ * (variant 3), and later plans of that bucket use it without tuning. Results
+ * do not depend on the settings. It sizes every device buffer first and returns
  * VRPH_ENOMEM, allocating nothing, when they exceed the free device memory
  * or the byte count in the environment variable VRPH_WORKSPACE_CAP (if
  * set); a plan that fails frees whatever it had allocated. */

@@ -49,7 +49,6 @@ namespace vrph {
 
 namespace {
 
-constexpr int kT = kDredThreads;
 constexpr uint64_t kTriMask = (1ull << 34) - 1;
 constexpr unsigned long long kNoKey = ~0ull;
 constexpr uint32_t kNoPos = 0xFFFFFFFFu;           // epos of a pair that is not an edge
@@ -131,9 +130,9 @@ struct Shared {
   uint32_t pmin, pmax;
   uint32_t list_n;
   uint32_t err;
-  uint32_t list[kT];            // positions of a weight class with live triangles
-  uint32_t sedge[kT];           // summand vertices (a << 16 | b)
-  uint32_t spos[kT];            // summand positions
+  uint32_t list[kDredThreads];   // positions of a weight class with live triangles
+  uint32_t sedge[kDredThreads];  // summand vertices (a << 16 | b)
+  uint32_t spos[kDredThreads];   // summand positions
 };
 
 // the vertices v2 > v1 > v0 of triangle t (Eq. 5.6): the largest v2 with
@@ -251,13 +250,14 @@ __global__ void dred_ranges_kernel(const Column* __restrict__ cols, const unsign
 // the working column: every cofacet not older than the pivot (class start
 // gstart, class end gend, triangle tp; gend = 0 pushes everything) toggles
 // its bit and moves its counts.
+template <int T>
 __device__ __forceinline__ void push_rows(const DredArgs& A, const Cloud& cl,
                                           const DredCloud& dc, Shared& sh, uint32_t* cnt1, int m,
                                           uint32_t gstart, uint32_t gend, uint64_t tp) {
   const int n = cl.n;
   const int64_t items = (int64_t)m * n;
   const int lane = threadIdx.x & 63;
-  for (int64_t base = 0; base < items; base += kT) {
+  for (int64_t base = 0; base < items; base += T) {
     const int64_t it = base + threadIdx.x;
     bool toggled = false;
     uint32_t word = 0, lo = 0xFFFFFFFFu, hi = 0;
@@ -312,6 +312,7 @@ __device__ __forceinline__ void push_rows(const DredArgs& A, const Cloud& cl,
 // Stages summands [from, from + m) of the current addition: the first is an
 // edge index `first`, the others V entries starting at voff. Toggles their
 // bits in V of the column being reduced.
+template <int T>
 __device__ __forceinline__ void stage_summands(const DredArgs& A, const Cloud& cl,
                                                const DredCloud& dc, Shared& sh, int64_t from,
                                                int m, uint32_t first, uint32_t voff) {
@@ -347,13 +348,14 @@ __device__ __forceinline__ void stage_summands(const DredArgs& A, const Cloud& c
 // The next pivot of the working column (every row in it is younger than the
 // current pivot, whose class starts at gstart): returns kNoKey if the column
 // is zero; sets sh.tv and sh.gend.
+template <int T>
 __device__ unsigned long long find_pivot(const DredArgs& A, const Cloud& cl, const DredCloud& dc,
                                          Shared& sh, uint32_t* cnt1, int nblk, int64_t E,
                                          uint32_t gstart) {
   const int n = cl.n;
   // first block holding live rows
   int blk = -1;
-  for (int b0 = (int)(gstart >> 10); b0 < nblk; b0 += kT) {
+  for (int b0 = (int)(gstart >> 10); b0 < nblk; b0 += T) {
     if (threadIdx.x == 0) sh.misc[0] = 0xFFFFFFFFu;
     __syncthreads();
     const int b = b0 + (int)threadIdx.x;
@@ -376,16 +378,22 @@ __device__ unsigned long long find_pivot(const DredArgs& A, const Cloud& cl, con
     sh.red = 0;
   }
   __syncthreads();
-  const int64_t pb = (int64_t)blk * 1024 + threadIdx.x;
-  uint32_t cb = 0, gb = 0, ge = 0, uvb = 0;
-  if (pb < E && (uint32_t)pb >= gstart) {
-    cb = wg_load(&A.cnt[cl.e_off + pb]);
-    gb = A.egrp[cl.e_off + pb];
-    ge = A.egend[cl.e_off + pb];
-    uvb = A.eat[cl.e_off + pb];
+  constexpr int P = 1024 / T;  // positions of the block per lane
+  uint32_t cb[P], gb[P], ge[P], uvb[P];
+  uint32_t mine = 0xFFFFFFFFu;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int64_t pb = (int64_t)blk * 1024 + k * T + threadIdx.x;
+    cb[k] = gb[k] = ge[k] = uvb[k] = 0;
+    if (pb < E && (uint32_t)pb >= gstart) {
+      cb[k] = wg_load(&A.cnt[cl.e_off + pb]);
+      gb[k] = A.egrp[cl.e_off + pb];
+      ge[k] = A.egend[cl.e_off + pb];
+      uvb[k] = A.eat[cl.e_off + pb];
+    }
+    if (cb[k] != 0 && (uint32_t)pb < mine) mine = (uint32_t)pb;
   }
   {
-    const uint32_t mine = cb != 0 ? (uint32_t)pb : 0xFFFFFFFFu;
     const uint32_t wmin = wave_min_u32(mine);
     if ((threadIdx.x & 63) == 0 && wmin != 0xFFFFFFFFu) atomicMin(&sh.misc[1], wmin);
   }
@@ -396,25 +404,31 @@ __device__ unsigned long long find_pivot(const DredArgs& A, const Cloud& cl, con
     __syncthreads();
     return kNoKey;
   }
-  if ((uint32_t)pb == p1) {
-    sh.misc[2] = gb;
-    sh.misc[3] = ge;
-  }
+#pragma unroll
+  for (int k = 0; k < P; ++k)
+    if ((uint32_t)((int64_t)blk * 1024 + k * T + threadIdx.x) == p1) {
+      sh.misc[2] = gb[k];
+      sh.misc[3] = ge[k];
+    }
   __syncthreads();
   const uint32_t g1 = sh.misc[2], gend1 = sh.misc[3];
-  if (cb != 0 && (uint32_t)pb >= p1 && (uint32_t)pb < gend1) {
-    const uint32_t k = atomicAdd(&sh.list_n, 1u);
-    sh.list[k] = (uint32_t)pb;
-    sh.sedge[k] = uvb;  // free here: staging starts after the search
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const uint32_t pb = (uint32_t)((int64_t)blk * 1024 + k * T + threadIdx.x);
+    if (cb[k] != 0 && pb >= p1 && pb < gend1) {
+      const uint32_t q = atomicAdd(&sh.list_n, 1u);
+      sh.list[q] = pb;
+      sh.sedge[q] = uvb[k];  // free here: staging starts after the search
+    }
   }
   // the largest live triangle index over the listed positions; a class that
-  // runs past the block continues one window of kT positions at a time
-  for (int64_t w0 = (int64_t)blk * 1024 + 1024;; w0 += kT) {
+  // runs past the block continues one window of T positions at a time
+  for (int64_t w0 = (int64_t)blk * 1024 + 1024;; w0 += T) {
     __syncthreads();
     const int L = (int)sh.list_n;
     const int64_t items = (int64_t)L * n;
     unsigned long long best = 0;
-    for (int64_t it = threadIdx.x; it < items; it += kT) {
+    for (int64_t it = threadIdx.x; it < items; it += T) {
       const int i = (int)(it / n), x = (int)(it - (int64_t)i * n);
       const uint32_t pos = sh.list[i];
       const uint32_t uv = sh.sedge[i];
@@ -460,6 +474,7 @@ __device__ unsigned long long find_pivot(const DredArgs& A, const Cloud& cl, con
 // Owner of the pivot t = sh.tv with key `key` (class [gD, sh.gend)): sets
 // sh.owner (global column of a finished column, -2 for an apparent partner
 // in sh.partner, -1 free).
+template <int T>
 __device__ void find_owner(const DredArgs& A, const Cloud& cl, const DredCloud& dc, Shared& sh,
                            uint32_t tcap, unsigned long long key) {
   const int n = cl.n;
@@ -497,7 +512,7 @@ __device__ void find_owner(const DredArgs& A, const Cloud& cl, const DredCloud& 
     const uint32_t f10 = A.epos[wo + (int64_t)v1 * n + v0];
     const uint32_t f20 = A.epos[wo + (int64_t)v2 * n + v0];
     const uint32_t f21 = A.epos[wo + (int64_t)v2 * n + v1];
-    const int x0 = v0 + 1 + (int)threadIdx.x - 64, stride = kT - 64;
+    const int x0 = v0 + 1 + (int)threadIdx.x - 64, stride = T - 64;
     uint32_t r2[4], r1[4], r0[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -542,7 +557,8 @@ __device__ void find_owner(const DredArgs& A, const Cloud& cl, const DredCloud& 
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
+template <int T>
+__global__ __launch_bounds__(T) void dred_reduce_kernel(DredArgs A) {
   extern __shared__ uint32_t cnt1[];
   __shared__ Shared sh;
   const int c = blockIdx.x;
@@ -552,7 +568,7 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
   const int64_t E = (int64_t)n * (n - 1) / 2;
   const int nblk = (int)((E + 1023) / 1024);
   const int tid = threadIdx.x;
-  for (int b = tid; b < nblk; b += kT) cnt1[b] = 0;
+  for (int b = tid; b < nblk; b += T) cnt1[b] = 0;
   const uint32_t jb = A.col_begin[c], je = A.col_end[c];
   const uint32_t ncol = je > jb ? je - jb : 0;
   uint32_t tcap = 64;
@@ -568,7 +584,7 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
     if (tid == 0) A.stats[c] = DredStats{0, 0, sh.err};
     return;
   }
-  for (uint32_t s = tid; s < tcap; s += kT) A.tab_keys[dc.tab_off + s] = kNoKey;
+  for (uint32_t s = tid; s < tcap; s += T) A.tab_keys[dc.tab_off + s] = kNoKey;
   __syncthreads();
   unsigned long long additions = 0;
   uint32_t emergent = 0;
@@ -581,7 +597,7 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
     // the first pivot, from the coboundary alone: the oldest cofacet, i.e.
     // the smallest diameter-edge position's class, then the largest index
     uint32_t pmin = kNoPos;
-    for (int x = tid; x < n; x += kT) {
+    for (int x = tid; x < n; x += T) {
       const uint32_t e1 = A.epos[cl.w_off + (int64_t)a * n + x];
       const uint32_t e2 = A.epos[cl.w_off + (int64_t)b * n + x];
       uint32_t pm = es > e1 ? es : e1;
@@ -606,7 +622,7 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
     }
     const uint32_t g0 = A.egrp[cl.e_off + p0], gend0 = A.egend[cl.e_off + p0];
     unsigned long long tbest = 0;
-    for (int x = tid; x < n; x += kT) {
+    for (int x = tid; x < n; x += T) {
       const uint32_t e1 = A.epos[cl.w_off + (int64_t)a * n + x];
       const uint32_t e2 = A.epos[cl.w_off + (int64_t)b * n + x];
       uint32_t pm = es > e1 ? es : e1;
@@ -634,7 +650,7 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
     bool built = false;
     uint32_t nadd = 0;
     for (;;) {
-      find_owner(A, cl, dc, sh, tcap, key);
+      find_owner<T>(A, cl, dc, sh, tcap, key);
       const int32_t owner = sh.owner;
       if (owner == -1) break;  // a free pivot: the column is paired with it
       if (!built) {
@@ -644,7 +660,7 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
           sh.spos[0] = es;
         }
         __syncthreads();
-        push_rows(A, cl, dc, sh, cnt1, 1, 0, 0, 0);
+        push_rows<T>(A, cl, dc, sh, cnt1, 1, 0, 0, 0);
         built = true;
       }
       // add the owner's column: its edge, then V (finished columns only)
@@ -665,23 +681,23 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
             sh.vt_ovf = 1;
         }
         __syncthreads();
-        push_rows(A, cl, dc, sh, cnt1, 1, gstart, gend, tp);
+        push_rows<T>(A, cl, dc, sh, cnt1, 1, gstart, gend, tp);
       } else {
         const uint32_t first = (uint32_t)A.cols[owner].cidx;
         const uint32_t voff = A.col_voff[owner], vlen = A.col_vlen[owner];
         const int64_t total = 1 + (int64_t)vlen;
-        for (int64_t from = 0; from < total; from += kT) {
-          const int m = (int)(total - from < kT ? total - from : kT);
+        for (int64_t from = 0; from < total; from += T) {
+          const int m = (int)(total - from < T ? total - from : T);
           __syncthreads();
-          stage_summands(A, cl, dc, sh, from, m, first, voff);
+          stage_summands<T>(A, cl, dc, sh, from, m, first, voff);
           __syncthreads();
-          push_rows(A, cl, dc, sh, cnt1, m, gstart, gend, tp);
+          push_rows<T>(A, cl, dc, sh, cnt1, m, gstart, gend, tp);
         }
       }
       ++nadd;
       __syncthreads();
       const unsigned long long prev = key;
-      key = find_pivot(A, cl, dc, sh, cnt1, nblk, E, gstart);
+      key = find_pivot<T>(A, cl, dc, sh, cnt1, nblk, E, gstart);
       if (key == kNoKey) break;  // the column is zero: an essential class
       // an addition cancels the pivot, so the next one is younger; a column
       // that would not move on, or that needs more additions than a column
@@ -725,7 +741,7 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
     if (nadd > 0) {
       const bool full = sh.vt_ovf != 0;
       const int64_t words = full ? (E + 31) / 32 : (int64_t)sh.vt_n;
-      for (int64_t k = tid; k < words; k += kT) {
+      for (int64_t k = tid; k < words; k += T) {
         const uint32_t wdi = full ? (uint32_t)k : A.vtouch[dc.vt_off + k];
         const uint32_t bits = wg_exch(&A.vbits[cl.bm_off + wdi], 0u);
         if (bits && paired) {
@@ -765,14 +781,14 @@ __global__ __launch_bounds__(kDredThreads) void dred_reduce_kernel(DredArgs A) {
     // the working column back to zero
     if (built) {
       if (sh.tlog_ovf) {
-        for (int64_t k = tid; k < dc.tri_words; k += kT) A.tri[dc.tri_off + k] = 0;
+        for (int64_t k = tid; k < dc.tri_words; k += T) A.tri[dc.tri_off + k] = 0;
       } else {
-        for (uint32_t k = tid; k < sh.tlog_n; k += kT) A.tri[dc.tri_off + A.tlog[dc.log_off + k]] = 0;
+        for (uint32_t k = tid; k < sh.tlog_n; k += T) A.tri[dc.tri_off + A.tlog[dc.log_off + k]] = 0;
       }
       const uint32_t q0 = sh.pmin, q1 = sh.pmax;
       if (q0 <= q1) {
-        for (int64_t p = (int64_t)q0 + tid; p <= (int64_t)q1; p += kT) A.cnt[cl.e_off + p] = 0;
-        for (int b2 = (int)(q0 >> 10) + tid; b2 <= (int)(q1 >> 10); b2 += kT) cnt1[b2] = 0;
+        for (int64_t p = (int64_t)q0 + tid; p <= (int64_t)q1; p += T) A.cnt[cl.e_off + p] = 0;
+        for (int b2 = (int)(q0 >> 10) + tid; b2 <= (int)(q1 >> 10); b2 += T) cnt1[b2] = 0;
       }
     }
     __syncthreads();
@@ -802,7 +818,8 @@ hipError_t launch_dred_prepare(const uint32_t* W, const Cloud* clouds, int count
   return hipGetLastError();
 }
 
-hipError_t launch_dred_reduce(const DredArgs& args, int64_t cols_cap, int max_n, hipStream_t s) {
+hipError_t launch_dred_reduce(const DredArgs& args, int64_t cols_cap, int max_n, int threads,
+                              hipStream_t s) {
   hipError_t e = launch_fill_u32(args.col_begin_w, args.count, 0u, s);
   if (e != hipSuccess) return e;
   if ((e = launch_fill_u32(args.col_end_w, args.count, 0u, s)) != hipSuccess) return e;
@@ -814,7 +831,19 @@ hipError_t launch_dred_reduce(const DredArgs& args, int64_t cols_cap, int max_n,
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t emax = (int64_t)max_n * (max_n - 1) / 2;
   const size_t lds = (size_t)((emax + 1023) / 1024) * sizeof(uint32_t);
-  dred_reduce_kernel<<<args.count, kDredThreads, lds, s>>>(args);
+  switch (threads) {
+    case 256:
+      dred_reduce_kernel<256><<<args.count, 256, lds, s>>>(args);
+      break;
+    case 512:
+      dred_reduce_kernel<512><<<args.count, 512, lds, s>>>(args);
+      break;
+    case 1024:
+      dred_reduce_kernel<1024><<<args.count, 1024, lds, s>>>(args);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

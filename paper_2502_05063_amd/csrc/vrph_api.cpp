@@ -225,7 +225,9 @@ struct vrph_ctx {
   int binom_n = -1, binom_k = -1;
   std::string arch;
   // (dimension, size bucket, kernel variant: 0 global, 1 LDS, 2 the
-  // dimension-1 neighbour-list kernel) -> setting
+  // dimension-1 neighbour-list kernel, 3 a batch plan: chunk = workgroup
+  // size of the device reduction, mult = edge-kernel workgroups per CU) ->
+  // setting
   std::map<std::tuple<int, int, int>, Tune> tuned;
   DevBuf units;                    // unit table of the d >= 2 enumeration
   DevBuf pfx_v, pfx_cum;           // listed prefixes of sparse dimension-2 and 3 enumerations
@@ -281,7 +283,7 @@ static void load_tuning(vrph_ctx* c) {
   std::string arch;
   int d, b, var, chunk, mult;
   while (f >> arch >> d >> b >> var >> chunk >> mult)
-    if (arch == c->arch && d >= 1 && d <= kMaxDim && var >= 0 && var <= 2 &&
+    if (arch == c->arch && d >= 1 && d <= kMaxDim && var >= 0 && var <= 3 &&
         chunk >= 64 && chunk <= (1 << 20) && chunk % 64 == 0 && mult >= 1 && mult <= 1024)
       c->tuned[{d, b, var}] = Tune{chunk, mult};
 }
@@ -1300,6 +1302,12 @@ struct vrph_batch {
   int64_t last_columns = 0, last_apparent = 0, last_nonapparent = 0;
   // dimension-1 reduction on the device (unless VRPH_HOST_REDUCTION)
   bool device_reduce = false;
+  // launch settings: the device reduction's workgroup size and the
+  // dimension-1 edge kernel's workgroups per compute unit; tuned on the
+  // first forward under VRPH_AUTOTUNE (or read from the tuning file)
+  int dred_threads = 1024;
+  int edge_mult = 8;
+  bool tune = false;
   std::vector<DredCloud> hdc;
   DevBuf ddc, ew, eat, egrp, egend, ecnt, epos, tri, tlog, tab_keys, tab_vals, varena, vbits, vtouch,
       col_begin, col_end, out_death, out_ddiam, out_dedge, col_voff, col_vlen, dstats;
@@ -1390,7 +1398,8 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
     return fail(VRPH_EINVAL, "vrph_batch_plan: bad argument");
   *out = nullptr;
   if (max_dim < 0 || max_dim > 1) return fail(VRPH_EINVAL, "vrph_batch_plan: max_dim must be 0 or 1");
-  if (flags & ~(VRPH_KEEP_ZERO_PERSISTENCE | VRPH_NO_ENCLOSING_RADIUS | VRPH_HOST_REDUCTION))
+  if (flags & ~(VRPH_KEEP_ZERO_PERSISTENCE | VRPH_NO_ENCLOSING_RADIUS | VRPH_HOST_REDUCTION |
+                VRPH_AUTOTUNE))
     return fail(VRPH_EINVAL, "vrph_batch_plan: unsupported flag bits");
   if (std::isnan(threshold) || threshold < 0) return fail(VRPH_EINVAL, "threshold must be >= 0");
   HIP_TRY(hipSetDevice(c->device));
@@ -1468,6 +1477,18 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
     vrph_status st = dred_init(b.get());
     if (st != VRPH_OK) return st;
   }
+  // launch settings: a tuning already found for this size bucket, else
+  // tuned on the first forward if asked
+  {
+    const auto it = c->tuned.find({1, size_bucket(b->max_n), 3});
+    if (it != c->tuned.end() && (it->second.chunk == 256 || it->second.chunk == 512 ||
+                                 it->second.chunk == 1024)) {
+      b->dred_threads = it->second.chunk;
+      b->edge_mult = it->second.mult;
+    } else {
+      b->tune = (flags & VRPH_AUTOTUNE) != 0 && max_dim >= 1;
+    }
+  }
   b->results.resize(count);
   *out = b.release();
   return VRPH_OK;
@@ -1533,7 +1554,7 @@ static hipError_t batch_record(vrph_batch* b, hipStream_t s) {
                                 cap, keep_zero ? b->ap.as<ApparentPair>() : nullptr,
                                 keep_zero ? cap : 0, ClearSet{nullptr, nullptr, 0, nullptr},
                                 &sc->columns,
-                                b->ctx->num_cus * 8, s)))
+                                b->ctx->num_cus * b->edge_mult, s)))
       return e;
     int max_edges_bits = 0;
     while ((int64_t(1) << max_edges_bits) < (int64_t)b->max_n * (b->max_n - 1) / 2) ++max_edges_bits;
@@ -1573,7 +1594,7 @@ static hipError_t batch_record(vrph_batch* b, hipStream_t s) {
       a.col_voff = b->col_voff.as<uint32_t>();
       a.col_vlen = b->col_vlen.as<uint32_t>();
       a.stats = b->dstats.as<DredStats>();
-      if ((e = launch_dred_reduce(a, (int64_t)cap, b->max_n, s))) return e;
+      if ((e = launch_dred_reduce(a, (int64_t)cap, b->max_n, b->dred_threads, s))) return e;
     }
   }
   if ((e = hipMemcpyAsync(b->h_cstate.p, b->cstate.p, (size_t)b->count * sizeof(CloudState),
@@ -1594,6 +1615,46 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
   const double t_start = now_ms();
   HIP_TRY(hipMemcpyAsync(b->X.p, X_packed, (size_t)b->total_points * b->m * 4,
                          hipMemcpyDeviceToDevice, s));
+  if (!b->exec && b->tune) {
+    // the batch autotuner: the whole device part run eagerly (the same work
+    // the graph records) per candidate, timed with HIP events; first the
+    // device reduction's workgroup size, then the edge kernel's grid
+    auto time_once = [&](int threads, int mult, float* ms) -> hipError_t {
+      b->dred_threads = threads;
+      b->edge_mult = mult;
+      hipError_t e = hipEventRecord(c->ev0, s);
+      if (e == hipSuccess) e = batch_record(b, s);
+      if (e == hipSuccess) e = hipEventRecord(c->ev1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(c->ev1);
+      if (e == hipSuccess) e = hipEventElapsedTime(ms, c->ev0, c->ev1);
+      return e;
+    };
+    int best_t = 1024, best_m = 8;
+    float best = 0, ms = 0;
+    HIP_TRY(time_once(best_t, best_m, &ms));  // warm-up (code objects, caches)
+    HIP_TRY(time_once(best_t, best_m, &best));
+    if (b->device_reduce)
+      for (int t : {256, 512}) {
+        HIP_TRY(time_once(t, best_m, &ms));
+        if (ms < best) {
+          best = ms;
+          best_t = t;
+        }
+      }
+    for (int mlt : {2, 4, 16, 32}) {
+      HIP_TRY(time_once(best_t, mlt, &ms));
+      if (ms < best) {
+        best = ms;
+        best_m = mlt;
+      }
+    }
+    b->dred_threads = best_t;
+    b->edge_mult = best_m;
+    b->tune = false;
+    const std::tuple<int, int, int> key{1, size_bucket(b->max_n), 3};
+    c->tuned[key] = Tune{best_t, best_m};
+    save_tuning(c, key, Tune{best_t, best_m});
+  }
   if (!b->exec) {
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = batch_record(b, s);
@@ -1780,6 +1841,7 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
   for (int i = 0; i < b->count; ++i) {
     b->results[i].stats.gpu_ms[0] = gms;
     b->results[i].stats.host_ms[1] = host_ms;
+    b->results[i].stats.grid[1] = b->max_dim >= 1 ? c->num_cus * b->edge_mult : 0;
     b->results[i].stats.total_ms = now_ms() - t_start;
   }
   b->last_columns = (int64_t)sc.columns;

@@ -216,7 +216,8 @@ hipError_t launch_backward(const float* X, int64_t n_total, int m, const int32_t
                            uint32_t* bad, hipStream_t s);
 
 // ---- reduce_dev.hip ----
-// Dimension-1 submatrix reduction on the device, one workgroup per cloud.
+// Dimension-1 submatrix reduction on the device, one workgroup per cloud
+// of up to kDredThreads lanes.
 constexpr int kDredThreads = 1024;
 // Per-cloud regions of the device reduction's buffers.
 struct DredCloud {
@@ -276,7 +277,9 @@ hipError_t launch_dred_prepare(const uint32_t* W, const Cloud* clouds, int count
 // Column ranges per cloud, then the reduction (one workgroup per cloud).
 // The bitmaps, counts and V bitmaps must be zero on entry; they are zero
 // again on exit.
-hipError_t launch_dred_reduce(const DredArgs& args, int64_t cols_cap, int max_n, hipStream_t s);
+// threads: the workgroup size per cloud, 256, 512 or 1024 (kDredThreads).
+hipError_t launch_dred_reduce(const DredArgs& args, int64_t cols_cap, int max_n, int threads,
+                              hipStream_t s);
 
 // ---- graph_ext.hip ----
 // Extended persistence of a batch of graphs (Sec. 7.2, Alg. 27-28): v_off /

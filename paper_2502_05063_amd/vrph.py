@@ -326,20 +326,22 @@ class Context:
         return bars, [rec[start[g]:start[g + 1]] for g in range(count)]
 
     def batch(self, sizes, m, max_dim=1, threshold=float("inf"), keep_zero=False,
-              no_enclosing=False, host_reduction=False):
-        return Batch(self, sizes, m, max_dim, threshold, keep_zero, no_enclosing, host_reduction)
+              no_enclosing=False, host_reduction=False, autotune=False):
+        return Batch(self, sizes, m, max_dim, threshold, keep_zero, no_enclosing, host_reduction,
+                     autotune)
 
 
 class Batch:
     """A batch plan: fixed cloud sizes, one captured graph replayed per forward."""
 
     def __init__(self, ctx, sizes, m, max_dim, threshold, keep_zero, no_enclosing,
-                 host_reduction=False):
+                 host_reduction=False, autotune=False):
         self.ctx = ctx
         self.sizes = np.ascontiguousarray(sizes, dtype=np.int64)
         flags = ((KEEP_ZERO_PERSISTENCE if keep_zero else 0)
                  | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
-                 | (HOST_REDUCTION if host_reduction else 0))
+                 | (HOST_REDUCTION if host_reduction else 0)
+                 | (AUTOTUNE if autotune else 0))
         h = ctypes.c_void_p()
         _check(lib().vrph_batch_plan(ctx.h, self.sizes.ctypes.data_as(ctypes.c_void_p),
                                      len(self.sizes), m, max_dim, threshold, flags,

@@ -154,3 +154,79 @@ def test_c5_device_matches_host(ctx):
     clouds = synth.torus_batch(64, 500, 0.1, seed=0)
     rd, rh = run_both(ctx, clouds)
     check_same(rd, rh)
+
+
+def test_batch_autotune(ctx, tmp_path):
+    """The batch autotuner (VRPH_AUTOTUNE): the tuned plan gives the same
+    pairs as the default one, writes its choice to the tuning file, and a new
+    context reading that file uses it without tuning again."""
+    import torch
+
+    from paper_2502_05063_amd import vrph
+
+    clouds = synth.circle_or_torus_batch(20, 40, 180, 0.05, seed=12)
+    Xp = packed(clouds)
+    sizes = [len(c) for c in clouds]
+    path = str(tmp_path / "tuning.txt")
+    os.environ["VRPH_TUNING_FILE"] = path
+    try:
+        c2 = vrph.Context()
+        try:
+            ref = ctx.batch(sizes, 3, max_dim=1, keep_zero=True)
+            rr = ref.forward(Xp)
+            tuned = c2.batch(sizes, 3, max_dim=1, keep_zero=True, autotune=True)
+            rt = tuned.forward(Xp)
+            for a, b in zip(rt, rr):
+                assert np.array_equal(a.pairs, b.pairs)
+            lines = [ln.split() for ln in open(path).read().splitlines()]
+            batch_lines = [ln for ln in lines if ln[3] == "3"]
+            assert len(batch_lines) == 1
+            threads, mult = int(batch_lines[0][4]), int(batch_lines[0][5])
+            assert threads in (256, 512, 1024) and mult >= 1
+            assert rt[0].stats["grid"][1] == mult * torch.cuda.get_device_properties(0).multi_processor_count
+            # a fresh context reads the choice and does not tune again
+            c3 = vrph.Context()
+            again = c3.batch(sizes, 3, max_dim=1, keep_zero=True, autotune=True)
+            ra = again.forward(Xp)
+            assert ra[0].stats["grid"][1] == rt[0].stats["grid"][1]
+            assert len(open(path).read().splitlines()) == len(lines)
+            for a, b in zip(ra, rr):
+                assert np.array_equal(a.pairs, b.pairs)
+            again.close()
+            tuned.close()
+            ref.close()
+            c3.close()
+        finally:
+            c2.close()
+    finally:
+        del os.environ["VRPH_TUNING_FILE"]
+
+
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_every_workgroup_size_matches_host(tmp_path, threads):
+    """Each workgroup size the autotuner may pick (forced through a tuning
+    file line) gives the host reduction's pairs, additions and emergent
+    counts."""
+    import torch
+
+    from paper_2502_05063_amd import vrph
+
+    clouds = synth.circle_or_torus_batch(10, 60, 300, 0.05, seed=13)
+    bucket = 1
+    while bucket < max(len(c) for c in clouds):
+        bucket <<= 1
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    path = str(tmp_path / "tuning.txt")
+    with open(path, "w") as f:
+        f.write(f"{arch} 1 {bucket} 3 {threads} 4\n")
+    os.environ["VRPH_TUNING_FILE"] = path
+    try:
+        c = vrph.Context()
+    finally:
+        del os.environ["VRPH_TUNING_FILE"]
+    try:
+        rd, rh = run_both(c, clouds)
+        check_same(rd, rh)
+        assert rd[0].stats["grid"][1] == 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    finally:
+        c.close()
