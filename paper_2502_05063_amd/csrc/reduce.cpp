@@ -314,68 +314,71 @@ struct NoInitAlloc : std::allocator<T> {
 
 // The working column: a monotone min-priority queue of row keys. Rows pushed
 // are never older than the current pivot and the pivot only gets younger,
-// so the ranks in play only grow. Rows wait in a radix heap over their rank
-// (bucket = highest bit where the rank differs from the current one), where
-// a push is an append. When the pivot reaches a rank, that rank's rows are
-// sorted once into a run; rows pushed at the current rank later become runs
-// too (each is nearly sorted: a coboundary is enumerated in decreasing index
-// order).
+// so the ranks in play only grow. Rows wait in buckets over ranges of ranks
+// (2^shift consecutive ranks each, at most kMaxBuckets buckets), where a
+// push is an append and a row is never moved; a bitmap marks the buckets
+// that hold rows. When the pivot reaches a bucket, its rows are sorted once
+// into a run (a radix sort over the key bits that vary within it); rows
+// pushed into the pivot's bucket later become runs too (a coboundary is
+// enumerated in decreasing index order, so a push is one ascending run per
+// rank).
 // Runs sit on a stack and the top two are merged while the upper one is at
 // least half the size of the one below, so there are few runs and a row is
-// merged O(log) times. Equal rows cancel in pairs (Z/2): the pivot is the
-// oldest row of odd multiplicity. Rows below the final pivot are appended
-// and at most moved between rank buckets, never sorted.
+// merged O(log) times. Equal rows cancel in pairs (Z/2): a run holds each
+// row at most once (a sorted batch keeps the rows of odd multiplicity), a
+// merge keeps the rows that are in one run but not both, and the pivot is
+// the oldest row held by an odd number of runs. Most rows at the pivot's
+// rank come in pairs, so the runs stay a few times shorter than the rows
+// pushed. Rows beyond the final pivot are appended once and never sorted.
 template <class K>
 class WorkColumn {
   using KVec = std::vector<K, NoInitAlloc<K>>;
 
  public:
-  explicit WorkColumn(const Keys<K>& ks) : ks_(ks) {}
-
-  void clear() {
-    for (auto& b : b_) b.clear();
-    for (Run& r : runs_) give(std::move(r.v));
-    runs_.clear();
-    cur_ = 0;
+  // nranks: the number of weight ranks (every row's rank is below it)
+  WorkColumn(const Keys<K>& ks, uint32_t nranks) : ks_(ks) {
+    while (((uint64_t)nranks >> shift_) >= kMaxBuckets) ++shift_;
+    nb_ = (size_t)((uint64_t)nranks >> shift_) + 1;
+    b_.resize(nb_);
+    used_.assign((nb_ + 63) / 64, 0);
   }
 
-  // bucket 0 holds the rows at the current rank that are not in a run yet
-  void push(K k) { b_[bucket(ks_.rank(k))].push_back(k); }
+  void clear() {
+    for (uint32_t i : touched_) {
+      b_[i].clear();
+      used_[i >> 6] = 0;
+    }
+    touched_.clear();
+    for (Run& r : runs_) give(std::move(r.v));
+    runs_.clear();
+    cb_ = 0;
+  }
 
-  // push m rows in one go: their buckets first, then one resize per bucket
-  // and a scatter (the same bucket contents, in the same order, as m pushes)
+  // the bucket the pivot is in holds the rows at its ranks that are not in a
+  // run yet
+  void push(K k) {
+    const uint32_t i = ks_.rank(k) >> shift_;
+    KVec& v = b_[i];
+    if (v.empty()) mark(i);
+    v.push_back(k);
+  }
+
   void push_many(const K* k, size_t m) {
-    if (m < 16) {
-      for (size_t i = 0; i < m; ++i) push(k[i]);
-      return;
-    }
-    bk_.resize(m);
-    uint32_t cnt[kBuckets] = {};
-    for (size_t i = 0; i < m; ++i) {
-      const uint8_t b = (uint8_t)bucket(ks_.rank(k[i]));
-      bk_[i] = b;
-      ++cnt[b];
-    }
-    K* dst[kBuckets];
-    for (int b = 0; b < kBuckets; ++b)
-      if (cnt[b]) {
-        const size_t old = b_[b].size();
-        b_[b].resize(old + cnt[b]);
-        dst[b] = b_[b].data() + old;
-      }
-    for (size_t i = 0; i < m; ++i) *dst[bk_[i]]++ = k[i];
+    for (size_t i = 0; i < m; ++i) push(k[i]);
   }
 
   // the pivot (smallest key of odd multiplicity), kept in the column; false
   // if the column is zero
   bool pivot(K* out) {
     for (;;) {
-      if (!b_[0].empty()) {
-        KVec& l = b_[0];
+      KVec& l = b_[cb_];
+      if (!l.empty()) {
         sort_runs(l);
-        KVec v = take();
-        v.swap(l);
-        add_run(std::move(v));
+        if (!l.empty()) {
+          KVec v = take();
+          v.swap(l);
+          add_run(std::move(v));
+        }
       }
       K top = 0;
       bool any = false;
@@ -391,16 +394,16 @@ class WorkColumn {
         ++i;
       }
       if (!any) {
-        if (!refill()) return false;
+        if (!advance()) return false;
         continue;
       }
+      // runs hold distinct rows: each run holds top at most once
       size_t k = 0, last = 0;
       for (size_t i = 0; i < runs_.size(); ++i) {
         Run& r = runs_[i];
-        const size_t p0 = r.pos;
-        while (r.pos < r.v.size() && r.v[r.pos] == top) ++r.pos;
-        if (r.pos != p0) {
-          k += r.pos - p0;
+        if (r.v[r.pos] == top) {
+          ++r.pos;
+          ++k;
           last = i;
         }
       }
@@ -419,13 +422,69 @@ class WorkColumn {
     size_t left() const { return v.size() - pos; }
   };
 
-  int bucket(uint32_t r) const { return r == cur_ ? 0 : 32 - __builtin_clz(r ^ cur_); }
+  void mark(uint32_t i) {
+    uint64_t& w = used_[i >> 6];
+    const uint64_t bit = 1ull << (i & 63);
+    if (!(w & bit)) {
+      w |= bit;
+      touched_.push_back(i);
+    }
+  }
 
-  // Sort the rows of the current rank. They arrive as a concatenation of
-  // ascending runs (a coboundary is pushed in ascending key order, and moves
-  // between buckets keep the order), usually a few: up to kMergeRuns runs
-  // are merged pairwise, more are sorted.
+  // the pivot moves on to the next bucket that holds rows
+  bool advance() {
+    used_[cb_ >> 6] &= ~(1ull << (cb_ & 63));
+    size_t i = cb_ + 1;
+    if (i >= nb_) return false;
+    size_t w = i >> 6;
+    uint64_t m = used_[w] & (~0ull << (i & 63));
+    while (!m) {
+      if (++w == used_.size()) return false;
+      m = used_[w];
+    }
+    cb_ = (uint32_t)(w * 64 + (size_t)__builtin_ctzll(m));
+    return true;
+  }
+
+  // Sort a batch of rows and keep one copy of each row of odd multiplicity.
   void sort_runs(KVec& l) {
+    sort_rows(l);
+    l.resize(odd_rows(l.data(), l.size()));
+  }
+
+  // keep one copy of each row of odd multiplicity in a sorted sequence
+  static size_t odd_rows(K* a, size_t n) {
+    size_t o = 0;
+    for (size_t i = 0; i < n;) {
+      size_t j = i + 1;
+      while (j < n && a[j] == a[i]) ++j;
+      a[o] = a[i];
+      o += (j - i) & 1;
+      i = j;
+    }
+    return o;
+  }
+
+  // the rows in exactly one of two runs (each strictly increasing), in
+  // order; branch-free while both have rows
+  static size_t xor_merge(const K* a, size_t na, const K* b, size_t nb, K* out) {
+    size_t i = 0, j = 0, o = 0;
+    while (i < na && j < nb) {
+      const K x = a[i], y = b[j];
+      out[o] = x < y ? x : y;
+      o += (size_t)(x != y);
+      i += (size_t)(x <= y);
+      j += (size_t)(y <= x);
+    }
+    while (i < na) out[o++] = a[i++];
+    while (j < nb) out[o++] = b[j++];
+    return o;
+  }
+
+  // The rows of a batch arrive as a concatenation of ascending runs, one
+  // per push: up to kMergeRuns runs are merged pairwise, more are radix
+  // sorted.
+  void sort_rows(KVec& l) {
     constexpr int kMergeRuns = 8;
     size_t bounds[kMergeRuns + 1];
     int runs = 1;
@@ -433,7 +492,7 @@ class WorkColumn {
     for (size_t i = 1; i < l.size(); ++i)
       if (l[i] < l[i - 1]) {
         if (runs == kMergeRuns) {
-          std::sort(l.begin(), l.end());
+          radix_sort(l);
           return;
         }
         bounds[runs++] = i;
@@ -462,6 +521,43 @@ class WorkColumn {
     give(std::move(t));
   }
 
+  // LSD radix sort, 8 bits a pass, over the bytes in which the keys of the
+  // batch differ (within a bucket only the index part and the low rank bits
+  // vary); small batches and keys that differ above bit 63 go to std::sort
+  void radix_sort(KVec& l) {
+    const size_t n = l.size();
+    K diff = 0;
+    for (size_t i = 1; i < n; ++i) diff |= l[i] ^ l[0];
+    if (n < 64 || (diff >> 32 >> 32) != 0) {
+      std::sort(l.begin(), l.end());
+      return;
+    }
+    const uint64_t dv = (uint64_t)diff;
+    KVec t = take();
+    t.resize(n);
+    KVec* src = &l;
+    KVec* dst = &t;
+    for (int sh = 0; sh < 64; sh += 8) {
+      if (((dv >> sh) & 0xFF) == 0) continue;
+      uint32_t cnt[256] = {};
+      for (size_t i = 0; i < n; ++i) ++cnt[((uint64_t)(*src)[i] >> sh) & 0xFF];
+      uint32_t sum = 0;
+      for (int b = 0; b < 256; ++b) {
+        const uint32_t c = cnt[b];
+        cnt[b] = sum;
+        sum += c;
+      }
+      K* out = dst->data();
+      for (size_t i = 0; i < n; ++i) {
+        const K x = (*src)[i];
+        out[cnt[((uint64_t)x >> sh) & 0xFF]++] = x;
+      }
+      std::swap(src, dst);
+    }
+    if (src != &l) l.swap(*src);
+    give(std::move(t));
+  }
+
   KVec take() {
     if (spare_.empty()) return {};
     KVec v = std::move(spare_.back());
@@ -480,8 +576,7 @@ class WorkColumn {
       Run& b = runs_.back();
       KVec m = take();
       m.resize(a.left() + b.left());
-      std::merge(a.v.begin() + (std::ptrdiff_t)a.pos, a.v.end(), b.v.begin() + (std::ptrdiff_t)b.pos,
-                 b.v.end(), m.begin());
+      m.resize(xor_merge(a.v.data() + a.pos, a.left(), b.v.data() + b.pos, b.left(), m.data()));
       give(std::move(a.v));
       give(std::move(b.v));
       runs_.pop_back();
@@ -489,29 +584,16 @@ class WorkColumn {
     }
   }
 
-  // move to the next rank that holds rows: its rows land in bucket 0
-  bool refill() {
-    int i = 1;
-    while (i < kBuckets && b_[i].empty()) ++i;
-    if (i == kBuckets) return false;
-    KVec& src = b_[i];
-    uint32_t m = ks_.rank(src[0]);
-    for (K x : src) m = std::min(m, ks_.rank(x));
-    cur_ = m;
-    moved_.clear();
-    moved_.swap(src);
-    push_many(moved_.data(), moved_.size());
-    return true;
-  }
-
-  static constexpr int kBuckets = 33;
+  static constexpr uint64_t kMaxBuckets = 1024;
   Keys<K> ks_;
-  KVec b_[kBuckets];
+  int shift_ = 0;
+  size_t nb_ = 0;
+  std::vector<KVec> b_;
+  std::vector<uint64_t> used_;     // buckets holding rows (or once did, this column)
+  std::vector<uint32_t> touched_;  // buckets marked since the last clear
   std::vector<Run> runs_;
   std::vector<KVec> spare_;
-  KVec moved_;
-  std::vector<uint8_t> bk_;
-  uint32_t cur_ = 0;
+  uint32_t cb_ = 0;  // the bucket the pivot is in
 };
 
 // Push the cofacets of simplex v (index c, diameter rank dr) that are not
@@ -669,7 +751,7 @@ static void pre_reduce(const HostComplex& H, const Keys<K>& ks, int d, const Col
   std::atomic<int64_t> next{0}, adds{0};
   auto worker = [&]() {
     int v[kMaxDim + 3], sv[kMaxDim + 3];
-    WorkColumn<K> work(ks);
+    WorkColumn<K> work(ks, H.nranks);
     std::vector<uint32_t> reach((size_t)H.n), areach((size_t)H.n);
     std::vector<K> kb(2 * (size_t)H.n);
     int64_t local_adds = 0;
@@ -783,14 +865,14 @@ static void reduce_keys(const HostComplex& H, const Keys<K>& ks, int d, const Co
     VArena arena;
     std::vector<uint32_t> reach, areach;
     std::vector<K> kb;
-    Scratch(const Keys<K>& k, int n)
-        : work(k), reach((size_t)n), areach((size_t)n), kb(2 * (size_t)n) {}
+    Scratch(const Keys<K>& k, const HostComplex& H)
+        : work(k, H.nranks), reach((size_t)H.n), areach((size_t)H.n), kb(2 * (size_t)H.n) {}
   };
   std::vector<std::unique_ptr<Scratch>> scratch((size_t)threads);
   auto worker = [&](int self) {
     const auto w0 = std::chrono::steady_clock::now();
     double waited = 0;
-    if (!scratch[(size_t)self]) scratch[(size_t)self].reset(new Scratch(ks, H.n));
+    if (!scratch[(size_t)self]) scratch[(size_t)self].reset(new Scratch(ks, H));
     Scratch& sc = *scratch[(size_t)self];
     WorkColumn<K>& work = sc.work;
     std::vector<Simplex>& vj = sc.vj;
