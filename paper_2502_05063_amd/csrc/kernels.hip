@@ -337,27 +337,33 @@ __device__ __forceinline__ int h0_find(int* parent, int x) {
 // Phases 2 and 3 of one cloud, by one workgroup of kH0Threads lanes: the
 // m forest edge keys in mst (LDS, room for a power of two >= m) are sorted,
 // cleared in the dimension-1 bitmap bm and paired by union-find with the
-// elder rule (parent: LDS scratch of n entries); the pairs go to o and their
-// number to *count.
+// elder rule (parent, mark: LDS scratch of n entries each); the pairs go to
+// o and their number to *count.
 //
 // The union-find runs on one wave, 64 edges at a time. A component's root is
 // its oldest vertex, so a merge of roots A and B kills min(A, B) (the
 // birth of the pair) and links it below max(A, B). At the start of a block
 // every lane finds the roots of its edge's two vertices (concurrent path
-// halving only shortens paths: nothing is linked meanwhile). The merges of
-// the block then run in edge order on those labels in registers: merge j
-// reads lane j's two current labels, and every lane renames the killed root
-// to the survivor, so each later merge sees the roots as of its own turn.
-// Each edge joins two components (it is a forest edge), so every merge
-// kills a root once; the block's links are written to parent at its end.
-__device__ void h0_finish(unsigned long long* mst, int m, int* parent, int n, uint32_t* bm,
-                          H0Pair* o, uint32_t* count) {
+// halving only shortens paths: nothing is linked meanwhile). An edge whose
+// two roots appear in no other edge of the block merges them as they are:
+// no other merge of the block renames them or is renamed by it (the lanes
+// count their roots in mark to find such edges). The other edges merge in
+// edge order on their labels in registers: merge j reads lane j's two
+// current labels, and every lane renames the killed root to the survivor,
+// so each later merge sees the roots as of its own turn. Each edge joins
+// two components (it is a forest edge), so every merge kills a root once;
+// the block's links are written to parent at its end.
+__device__ void h0_finish(unsigned long long* mst, int m, int* parent, int* mark, int n,
+                          uint32_t* bm, H0Pair* o, uint32_t* count) {
   const int tid = threadIdx.x;
   // bitonic sort of the m forest edges, ascending (padding with ~0)
   int P = 1;
   while (P < m) P <<= 1;
   for (int i = m + tid; i < P; i += kH0Threads) mst[i] = ~0ull;
-  for (int v = tid; v < n; v += kH0Threads) parent[v] = v;
+  for (int v = tid; v < n; v += kH0Threads) {
+    parent[v] = v;
+    mark[v] = 0;
+  }
   __syncthreads();
   // Stages whose partner distance j is below 64 pair elements of the same
   // 64-element chunk: a wave sorts a chunk in registers with shuffles (every
@@ -418,11 +424,21 @@ __device__ void h0_finish(unsigned long long* mst, int m, int* parent, int n, ui
       edge_vertices(e, a, b);
       la = h0_find(parent, a);
       lb = h0_find(parent, b);
+      __hip_atomic_fetch_add(&mark[la], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      __hip_atomic_fetch_add(&mark[lb], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    const int cnt = m - base < 64 ? m - base : 64;
-    int dead = 0, keep = 0;
-    for (int j = 0; j < cnt; ++j) {
+    bool twice = false;  // a root of this edge is in another edge of the block
+    if (live) twice = (mark[la] | mark[lb]) > 1;
+    __builtin_amdgcn_wave_barrier();
+    if (live) {
+      mark[la] = 0;
+      mark[lb] = 0;
+    }
+    int dead = la < lb ? la : lb, keep = la < lb ? lb : la;
+    for (unsigned long long rest = __ballot(twice); rest; rest &= rest - 1) {
+      const int j = __builtin_ctzll(rest);
       const int A = __builtin_amdgcn_readlane(la, j), B = __builtin_amdgcn_readlane(lb, j);
       const int young = A < B ? A : B, old = A < B ? B : A;
       if (lane == j) {
@@ -550,7 +566,7 @@ __global__ __launch_bounds__(kH0Threads) void batch_h0_kernel(const uint32_t* __
   }
   const int m = m_sh;
   __syncthreads();
-  h0_finish(mst, m, comp, n, bitmaps + cl.bm_off, out + (int64_t)c * out_stride,
+  h0_finish(mst, m, comp, hookto, n, bitmaps + cl.bm_off, out + (int64_t)c * out_stride,
             &st[c].h0_count);
 }
 
@@ -661,10 +677,11 @@ __global__ __launch_bounds__(kH0Threads) void h0w_finish_kernel(int n, H0Wide w,
                                                                 uint32_t* __restrict__ bm) {
   __shared__ unsigned long long mst[kMaxN];
   __shared__ int parent[kMaxN];
+  __shared__ int mark[kMaxN];
   const int m = *w.m;  // < n <= kMaxN
   for (int i = threadIdx.x; i < m; i += kH0Threads) mst[i] = w.mst[i];
   __syncthreads();
-  h0_finish(mst, m, parent, n, bm, out, &st->h0_count);
+  h0_finish(mst, m, parent, mark, n, bm, out, &st->h0_count);
 }
 
 size_t h0_wide_scratch_bytes(int n) { return (size_t)n * 24 + 256; }
