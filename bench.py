@@ -358,9 +358,10 @@ def main():
         "additions_per_dim": s0["additions"],
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": ALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": achieved_tops / ALU_PEAK_TOPS, "traffic": traffic,
-                     # the variant with bitmap clearing sets and dense unit tables
-                     "kernel": (f"enum_apparent_lds_kernel<{d}, 0>" if n <= LDS_MAX_N
-                                else f"enum_apparent_kernel<{d}, 0>"), "kernel_ms": k_ms,
+                     # the top dimension's variant: bitmap clearing set in, dense unit
+                     # tables, no clearing set out and no pair output (mode bits 4)
+                     "kernel": (f"enum_apparent_lds_kernel<{d}, 4>" if n <= LDS_MAX_N
+                                else f"enum_apparent_kernel<{d}, 4>"), "kernel_ms": k_ms,
                      "ops_per_launch": ops,
                      "grid_workgroups": s0["grid"][d],
                      "valu_issue": ({"sq_insts_valu_per_launch": valu,

@@ -11,6 +11,8 @@
 // compacted for the coboundary-order sort and the host reduction.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cstdint>
 
 #include "vrph_internal.h"
@@ -1109,7 +1111,14 @@ __device__ __forceinline__ void add_block_counters(unsigned long long (&v)[N],
 // Kernel variants (Mode bits): kModeHashed when a clearing set is hashed
 // (the bitmap variant keeps the probe loops out of its hot loop),
 // kModeListed when the units are listed prefixes (dimensions 2 and 3 only).
-constexpr int kModeHashed = 1, kModeListed = 2;
+// The outputs beside the non-apparent columns: kModeTop when there is no
+// clearing set for the next dimension and no pair output (the top
+// dimension), kModePairs when every apparent pair is written (the clearing
+// set out is then looked at at run time); neither: a clearing set out and
+// no pair output. Code a launch cannot reach holds registers all the same
+// (the hot loop spills scalars into vector lanes), so each case is a
+// variant of its own.
+constexpr int kModeHashed = 1, kModeListed = 2, kModeTop = 4, kModePairs = 8;
 
 template <int D, int BS, int UL, int Mode, class Rows>
 __device__ __forceinline__ void enum_units(
@@ -1120,12 +1129,19 @@ __device__ __forceinline__ void enum_units(
   constexpr uint32_t kInfW = Rows::kInfV;
   constexpr bool kHashed = (Mode & kModeHashed) != 0;
   constexpr bool kListed = (Mode & kModeListed) != 0;
+  constexpr bool kTop = (Mode & kModeTop) != 0;
+  constexpr bool kPairs = (Mode & kModePairs) != 0;
   static_assert(!kListed || D == 2 || D == 3, "listed prefixes are pairs or single vertices");
+  static_assert(!(kTop && kPairs), "the pair output needs the cofacet indices");
   const int np1 = n + 1;
   auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
   unsigned long long n_cols = 0, n_app = 0, n_steps = 0, n_facets = 0, n_cand = 0;
   DeferredAppend pend;
-  const bool need_t = clear_out.bits || (kHashed && clear_out.keys) || aps.recs;
+  // the cofacet index of an apparent pair: for the clearing set out (the
+  // launch takes the variant without kModeTop or kModePairs only with one)
+  // or for the pair output
+  const bool need_t =
+      kPairs ? (clear_out.bits || (kHashed && clear_out.keys) || aps.recs) : !kTop;
   const int bucket = (int)((blockIdx.x * (BS / 64) +
                             (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))) %
                            kSinkBuckets);
@@ -1367,13 +1383,15 @@ __device__ __forceinline__ void enum_units(
     if (nonapp) key_hi = ~rows.bits(diam);
     pend.reserve(nonapp, bucket_ctr, key_hi, c);
     bool any;
-    if (aps.recs) {
-      ApparentPair p;
-      p.s = c;
-      p.t = tcidx;
-      p.diam = is_app ? rows.bits(diam) : 0u;
-      p.cloud = 0;
-      sink_append(aps, bucket, is_app, p);
+    if constexpr (kPairs) {
+      if (aps.recs) {
+        ApparentPair p;
+        p.s = c;
+        p.t = tcidx;
+        p.diam = is_app ? rows.bits(diam) : 0u;
+        p.cloud = 0;
+        sink_append(aps, bucket, is_app, p);
+      }
     }
   }
   // a unit's counts fit 32 bits: at most chunk / BS candidates per lane,
@@ -1427,32 +1445,39 @@ void enum_apparent_lds_kernel(
                                sink, aps, sc);
 }
 
+// The output bits of a launch (see kModeTop): dimensions 2 and 3 have a
+// variant per case, the others one that decides at run time.
+template <int D, int Base, class Launch>
+static hipError_t with_outputs(const ClearSet& clear_out, const PairSink& aps, Launch&& go) {
+  if constexpr (D == 2 || D == 3) {
+    if (!aps.recs) {
+      if (clear_out.bits || clear_out.keys) return go(std::integral_constant<int, Base>{});
+      return go(std::integral_constant<int, Base | kModeTop>{});
+    }
+  }
+  return go(std::integral_constant<int, Base | kModePairs>{});
+}
+
 template <int D>
 static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom, int chunk,
                                 const uint64_t* unit_cum, uint64_t units, PrefixList pl,
                                 unsigned grid, ClearSet clear_in, ClearSet clear_out,
                                 ColumnSink sink, PairSink aps, Scalars* sc, hipStream_t s) {
+  auto go = [&](auto mode) {
+    enum_apparent_kernel<D, decltype(mode)::value><<<grid, kBlock, 0, s>>>(
+        W, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out, sink, aps, sc);
+    return hipGetLastError();
+  };
   const bool hashed = clear_in.keys || clear_out.keys;
   if constexpr (D == 2 || D == 3) {
-    if (pl.v) {
-      if (hashed)
-        enum_apparent_kernel<D, kModeListed | kModeHashed><<<grid, kBlock, 0, s>>>(
-            W, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out, sink, aps, sc);
-      else
-        enum_apparent_kernel<D, kModeListed><<<grid, kBlock, 0, s>>>(
-            W, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out, sink, aps, sc);
-      return hipGetLastError();
-    }
+    if (pl.v)
+      return hashed ? with_outputs<D, kModeListed | kModeHashed>(clear_out, aps, go)
+                    : with_outputs<D, kModeListed>(clear_out, aps, go);
   } else {
     if (pl.v) return hipErrorInvalidValue;  // prefixes are listed for d = 2, 3 only
   }
-  if (hashed)
-    enum_apparent_kernel<D, kModeHashed><<<grid, kBlock, 0, s>>>(
-        W, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out, sink, aps, sc);
-  else
-    enum_apparent_kernel<D, 0><<<grid, kBlock, 0, s>>>(W, n, binom, chunk, unit_cum, units, pl,
-                                                       clear_in, clear_out, sink, aps, sc);
-  return hipGetLastError();
+  return hashed ? with_outputs<D, kModeHashed>(clear_out, aps, go)
+                : with_outputs<D, 0>(clear_out, aps, go);
 }
 
 template <int D>
@@ -1462,13 +1487,13 @@ static hipError_t launch_enum_lds_D(const uint16_t* Wr, const uint32_t* rank_bit
                                     ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
                                     PairSink aps, Scalars* sc, hipStream_t s) {
   if (pl.v) return hipErrorInvalidValue;  // the LDS kernel takes dense unit tables only
-  if (clear_in.keys || clear_out.keys)
-    enum_apparent_lds_kernel<D, kModeHashed><<<grid, kLdsBlock, 0, s>>>(
+  auto go = [&](auto mode) {
+    enum_apparent_lds_kernel<D, decltype(mode)::value><<<grid, kLdsBlock, 0, s>>>(
         Wr, rank_bits, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out, sink, aps, sc);
-  else
-    enum_apparent_lds_kernel<D, 0><<<grid, kLdsBlock, 0, s>>>(
-        Wr, rank_bits, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out, sink, aps, sc);
-  return hipGetLastError();
+    return hipGetLastError();
+  };
+  if (clear_in.keys || clear_out.keys) return with_outputs<D, kModeHashed>(clear_out, aps, go);
+  return with_outputs<D, 0>(clear_out, aps, go);
 }
 
 hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
