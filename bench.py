@@ -246,6 +246,28 @@ def boundary_scan(ctx, reps=3):
                          "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": alg}}
 
 
+def full_sort_ab(ctx, Xd, max_dim, fused_stats, reps=3):
+    """The fusion of the apparent-pairs test into the enumeration against the
+    paper's unfused order (every column written, sorted into coboundary
+    order, then tested; VRPH_FULL_SORT) on the same input: per dimension the
+    device time of the fused kernel and of the three unfused stages (HIP
+    events around them, stats apparent_ms), and the barcode wall times."""
+    import numpy as np
+
+    ctx.barcode(X=Xd, max_dim=max_dim, full_sort=True)  # buffers, code objects
+    runs = [ctx.barcode(X=Xd, max_dim=max_dim, full_sort=True).stats for _ in range(reps)]
+    dims = range(2, max_dim + 1)
+    fused = {d: float(np.mean([s["apparent_ms"][d] for s in fused_stats])) for d in dims}
+    unfused = {d: float(np.mean([s["apparent_ms"][d] for s in runs])) for d in dims}
+    return {"workload": "the bench's cloud; dimensions 2-3 (the kernels that read the rank matrix from LDS)",
+            "columns_per_dim": {d: runs[-1]["columns"][d] for d in dims},
+            "fused_ms_per_dim": fused,
+            "unfused_ms_per_dim": unfused,
+            "unfused_over_fused": {d: unfused[d] / fused[d] for d in dims},
+            "barcode_ms_fused": float(np.mean([s["total_ms"] for s in fused_stats])),
+            "barcode_ms_unfused": float(np.mean([s["total_ms"] for s in runs]))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +277,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-boundary", action="store_true")
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--no-full-sort", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (the reference for HBM counters)")
     args = ap.parse_args()
@@ -380,6 +403,8 @@ def main():
         out["boundary_scan"] = boundary_scan(ctx)
     if not args.no_graphs:
         out["graph_extended"] = graph_extended(ctx)
+    if not args.no_full_sort:
+        out["full_sort_ab"] = full_sort_ab(ctx, Xd, max_dim, stats)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, max_dim)
     print(json.dumps(out))

@@ -88,6 +88,18 @@ typedef enum {
  * threads instead of on the device (the results are the same; for comparing
  * the two) */
 #define VRPH_HOST_REDUCTION 128u
+/* The paper's unfused order for dimensions 2 and 3 of a cloud of at most 200
+ * points (the kernels that read the rank matrix from LDS): every column
+ * that survives the threshold and clearing is written (Alg. 17), all of
+ * them are sorted into coboundary order (Alg. 18), and the apparent-pairs
+ * test (Lemma 5.3.6, Alg. 13) then runs over the sorted columns, instead of
+ * the test fused into the enumeration with only the non-apparent columns
+ * sorted. The results are the same; it exists to measure what the fusion
+ * saves (stats.apparent_ms covers the three stages). Where it does not apply
+ * (other dimensions, larger clouds, listed prefixes, hashed clearing sets,
+ * or every pair reported) the fused path runs. It needs device memory for
+ * three copies of 16 bytes per candidate of the dimension. */
+#define VRPH_FULL_SORT 256u
 #define VRPH_MAX_DIM 6 /* largest supported max_dim */
 
 typedef struct vrph_ctx vrph_ctx;

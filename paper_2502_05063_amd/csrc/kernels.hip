@@ -1117,8 +1117,11 @@ __device__ __forceinline__ void add_block_counters(unsigned long long (&v)[N],
 // set out is then looked at at run time); neither: a clearing set out and
 // no pair output. Code a launch cannot reach holds registers all the same
 // (the hot loop spills scalars into vector lanes), so each case is a
-// variant of its own.
-constexpr int kModeHashed = 1, kModeListed = 2, kModeTop = 4, kModePairs = 8;
+// variant of its own. kModeFilter (with kModeTop, LDS kernel): the first
+// stage of the paper's unfused order, which writes every column that
+// survives the threshold and clearing and tests none (see
+// apparent_sorted_lds_kernel).
+constexpr int kModeHashed = 1, kModeListed = 2, kModeTop = 4, kModePairs = 8, kModeFilter = 16;
 
 template <int D, int BS, int UL, int Mode, class Rows>
 __device__ __forceinline__ void enum_units(
@@ -1131,7 +1134,9 @@ __device__ __forceinline__ void enum_units(
   constexpr bool kListed = (Mode & kModeListed) != 0;
   constexpr bool kTop = (Mode & kModeTop) != 0;
   constexpr bool kPairs = (Mode & kModePairs) != 0;
+  constexpr bool kFilter = (Mode & kModeFilter) != 0;
   static_assert(!kListed || D == 2 || D == 3, "listed prefixes are pairs or single vertices");
+  static_assert(!kFilter || kTop, "the filter stage writes columns only");
   static_assert(!(kTop && kPairs), "the pair output needs the cofacet indices");
   const int np1 = n + 1;
   auto C = [&](int v, int k) -> uint64_t { return binom[(int64_t)k * np1 + v]; };
@@ -1351,7 +1356,8 @@ __device__ __forceinline__ void enum_units(
       else
         cleared = (cw >> (c & 31)) & 1u;
       is_col = diam != kInfW && !cleared;
-      if (is_col) {
+      if (is_col && kFilter) ++n_cols;
+      if (is_col && !kFilter) {
         ++n_cols;
         int x;
         if constexpr (__is_same(Rows, LdsRows))
@@ -1458,6 +1464,93 @@ static hipError_t with_outputs(const ClearSet& clear_out, const PairSink& aps, L
   return go(std::integral_constant<int, Base | kModePairs>{});
 }
 
+// The paper's unfused order, kept to measure what the fusion saves (the
+// kernels above test each column right after its diameter): Alg. 17 writes
+// every column that survives the threshold and clearing (the enumeration
+// kernel in mode kModeFilter), Alg. 18 sorts them into coboundary order (the
+// radix sort), and this kernel then runs the apparent-pairs test (Lemma
+// 5.3.6, Alg. 13) over the sorted columns: each lane decodes its column's
+// index into vertices (Eq. 5.6, the largest v with C(v, k) <= the rest, by
+// binary search), takes the diameter from the rank matrix in LDS and tests
+// the column as the fused kernel does. Non-apparent columns go to the sink,
+// apparent cofacets set the next dimension's clearing bits (a bitmap or
+// none). The sorted columns are min(*count, cap) (count on the device).
+template <int D>
+__global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(8)))
+void apparent_sorted_lds_kernel(const uint16_t* __restrict__ Wr,
+                                const uint32_t* __restrict__ rank_bits, int n,
+                                const uint64_t* __restrict__ binom, const Column* __restrict__ cols,
+                                const unsigned long long* __restrict__ count, uint64_t cap,
+                                ClearSet clear_out, ColumnSink sink, Scalars* __restrict__ sc) {
+  __shared__ uint4 sw[kLdsMaxN * kLdsMaxN / 8];
+  const int stride = lds_stride(n);
+  const int words = n * stride / 8;
+  const uint4* __restrict__ src = reinterpret_cast<const uint4*>(Wr);
+  for (int i = threadIdx.x; i < words; i += kLdsBlock) sw[i] = src[i];
+  __syncthreads();
+  const LdsRows rows{reinterpret_cast<const uint16_t*>(sw), n, stride, rank_bits};
+  const int np1 = n + 1;
+  const uint64_t total = min((uint64_t)*count, cap);
+  const int lane = (int)(threadIdx.x & 63);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int bucket = (int)((blockIdx.x * (kLdsBlock / 64) + (unsigned)wave) % kSinkBuckets);
+  unsigned long long n_app = 0, n_steps = 0, n_facets = 0;
+  const uint64_t step = (uint64_t)gridDim.x * kLdsBlock;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * kLdsBlock + (uint64_t)wave * 64; b0 < total; b0 += step) {
+    const uint64_t i = b0 + (uint64_t)lane;
+    bool nonapp = false;
+    Column rec{0u, 0u, 0ull};
+    if (i < total) {
+      const uint64_t c = cols[i].cidx;
+      int v[D + 1];
+      uint64_t rest = c;
+      int top = n - 1;
+#pragma unroll
+      for (int k = D + 1; k >= 1; --k) {
+        int lo = k - 1, hi = top;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (binom[(int64_t)k * np1 + mid] <= rest)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        v[k - 1] = lo;
+        rest -= binom[(int64_t)k * np1 + lo];
+        top = lo - 1;
+      }
+      uint32_t pw[D + 1][D + 1];
+      uint32_t diam = 0;
+#pragma unroll
+      for (int a = 1; a <= D; ++a)
+#pragma unroll
+        for (int b = 0; b < a; ++b) {
+          pw[a][b] = rows.lane_at(v[a], v[b]);
+          diam = max(diam, pw[a][b]);
+        }
+      uint32_t steps = 0, facets = 0;
+      const int x = apparent_cofacet_lds<D>(rows, n, v, pw, diam, steps, facets);
+      n_steps += steps;
+      n_facets += facets;
+      if (x >= 0) {
+        ++n_app;
+        if (clear_out.bits) {
+          const uint64_t t = cofacet_index<D>(v, x, binom, np1);
+          atomicOr(&clear_out.bits[t >> 5], 1u << (t & 31));
+        }
+      } else {
+        nonapp = true;
+        rec.key_hi = ~rows.bits(diam);
+        rec.cidx = c;
+      }
+    }
+    sink_append(sink, bucket, nonapp, rec);
+  }
+  unsigned long long tot[3] = {n_app, n_steps, n_facets};
+  unsigned long long* const dst[3] = {&sc->apparent, &sc->scan_steps, &sc->facet_steps};
+  add_block_counters<kLdsBlock, 3>(tot, dst);
+}
+
 template <int D>
 static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom, int chunk,
                                 const uint64_t* unit_cum, uint64_t units, PrefixList pl,
@@ -1516,6 +1609,48 @@ hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* r
     case 6: return launch_enum_lds_D<6>(Wr, rank_bits, n, binom, chunk, unit_cum, units, pl, grid, clear_in, clear_out, sink, aps, sc, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_enum_filter_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
+                                  const uint64_t* binom, int chunk, const uint64_t* unit_cum,
+                                  uint64_t units, unsigned max_groups, ClearSet clear_in,
+                                  ColumnSink sink, Scalars* sc, hipStream_t s) {
+  if (units == 0) return hipSuccess;
+  if (n < 1 || n > kLdsMaxN || chunk < 64 || chunk % 64 || max_groups == 0 || clear_in.keys)
+    return hipErrorInvalidValue;
+  const uint64_t need = (units + kLdsBlock / 64 - 1) / (kLdsBlock / 64);
+  uint64_t g = need < (uint64_t)max_groups ? need : (uint64_t)max_groups;
+  if (g > (uint64_t)kMaxGroups) g = kMaxGroups;
+  const PrefixList pl{nullptr, nullptr, 0};
+  const ClearSet none{nullptr, nullptr, 0, nullptr};
+  const PairSink aps{nullptr, nullptr, 0, 0};
+  constexpr int kMode = kModeFilter | kModeTop;
+  if (d == 2)
+    enum_apparent_lds_kernel<2, kMode><<<(unsigned)g, kLdsBlock, 0, s>>>(
+        Wr, rank_bits, n, binom, chunk, unit_cum, units, pl, clear_in, none, sink, aps, sc);
+  else if (d == 3)
+    enum_apparent_lds_kernel<3, kMode><<<(unsigned)g, kLdsBlock, 0, s>>>(
+        Wr, rank_bits, n, binom, chunk, unit_cum, units, pl, clear_in, none, sink, aps, sc);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_apparent_sorted_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
+                                      const uint64_t* binom, const Column* cols,
+                                      const unsigned long long* count, uint64_t cap,
+                                      unsigned grid, ClearSet clear_out, ColumnSink sink,
+                                      Scalars* sc, hipStream_t s) {
+  if (n < 1 || n > kLdsMaxN || grid == 0 || clear_out.keys) return hipErrorInvalidValue;
+  if (d == 2)
+    apparent_sorted_lds_kernel<2><<<grid, kLdsBlock, 0, s>>>(Wr, rank_bits, n, binom, cols, count,
+                                                             cap, clear_out, sink, sc);
+  else if (d == 3)
+    apparent_sorted_lds_kernel<3><<<grid, kLdsBlock, 0, s>>>(Wr, rank_bits, n, binom, cols, count,
+                                                             cap, clear_out, sink, sc);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,

@@ -218,6 +218,9 @@ struct vrph_ctx {
   DevBuf hflag;              // their overflow flags
   uint64_t hslots[kMaxDim + 2] = {};  // slots the hashed sets last needed
   DevBuf ap_ctr, ap_tmp;   // region counters and packed output of the pair sink
+  // the unfused order (VRPH_FULL_SORT): sink of every column, its counters
+  // and total, the packed columns, the sort's spare buffer and work space
+  DevBuf fcols, fctr, fpacked, fspare, fsort_work;
   uint64_t col_cap = 0;    // non-apparent columns the buffers are sized for
   uint64_t pair_cap = 0;   // apparent pairs the buffers are sized for
   HostPinned h_scal, h_cstate;
@@ -340,7 +343,8 @@ extern "C" void vrph_destroy(vrph_ctx* c) {
                     &c->rank_bits, &c->sink_ctr, &c->ap_ctr, &c->ap_tmp, &c->hflag,
                     &c->pfx_v,     &c->pfx_cum,  &c->bscan,  &c->h0w,
                     &c->bflag,     &c->g_off,    &c->g_lower, &c->g_upper, &c->g_tmp,
-                    &c->g_pos,     &c->g_adj_off, &c->g_adj, &c->g_stack,  &c->g_err};
+                    &c->g_pos,     &c->g_adj_off, &c->g_adj, &c->g_stack,  &c->g_err,
+                    &c->fcols,     &c->fctr,      &c->fpacked, &c->fspare, &c->fsort_work};
   for (DevBuf* b : bufs) b->release();
   for (DevBuf& b : c->hset) b.release();
   c->h_scal.release();
@@ -813,8 +817,38 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
         aps = PairSink{c->ap.as<ApparentPair>(), c->ap_ctr.as<unsigned long long>(),
                        sink_seg(ap_cap), ap_cap};
       }
+      // the paper's unfused order (VRPH_FULL_SORT), where it applies
+      const bool full = (flags & VRPH_FULL_SORT) && use_lds && (d == 2 || d == 3) &&
+                        pfx.empty() && !keep_zero && !clear_in.keys && !clear_out.keys;
+      uint64_t fcap = 0;
+      if (full) {
+        fcap = std::max<uint64_t>(examined, 1);  // every candidate at most
+        HIP_TRY_E(c->fcols.ensure(sink_records(fcap) * sizeof(Column)));
+        HIP_TRY_E(c->fpacked.ensure(fcap * sizeof(Column)));
+        HIP_TRY_E(c->fspare.ensure(fcap * sizeof(Column)));
+        HIP_TRY_E(c->fctr.ensure((kSinkCounters + 1) * sizeof(unsigned long long)));
+        HIP_TRY_E(c->fsort_work.ensure(radix_sort_work_bytes((int64_t)fcap)));
+        HIP_TRY_E(hipMemsetAsync(c->fctr.p, 0, (kSinkCounters + 1) * sizeof(unsigned long long), s));
+      }
       HIP_TRY_E(hipEventRecord(c->ev0, s));
-      if (use_lds)
+      if (full) {
+        const ColumnSink all{c->fcols.as<Column>(), c->fctr.as<unsigned long long>(),
+                             sink_seg(fcap), fcap};
+        unsigned long long* const fcount = c->fctr.as<unsigned long long>() + kSinkCounters;
+        HIP_TRY_E(launch_enum_filter_lds(d, c->wr16.as<uint16_t>(), c->rank_bits.as<uint32_t>(),
+                                         n, c->binom.as<uint64_t>(), t.chunk,
+                                         c->units.as<uint64_t>(), units, max_groups, clear_in,
+                                         all, dsc, s));
+        HIP_TRY_E(launch_gather_columns(all, c->fpacked.as<Column>(), fcap, fcount, s));
+        bool in_spare = false;
+        HIP_TRY_E(radix_sort_columns(c->fpacked.as<Column>(), c->fspare.as<Column>(),
+                                     (int64_t)fcap, bits_needed(ncand), 0, c->fsort_work.p, s,
+                                     fcount, &in_spare));
+        HIP_TRY_E(launch_apparent_sorted_lds(
+            d, c->wr16.as<uint16_t>(), c->rank_bits.as<uint32_t>(), n, c->binom.as<uint64_t>(),
+            in_spare ? c->fspare.as<Column>() : c->fpacked.as<Column>(), fcount, fcap,
+            (unsigned)c->num_cus * 2, clear_out, sink, dsc, s));
+      } else if (use_lds)
         HIP_TRY_E(launch_enum_apparent_lds(
             d, c->wr16.as<uint16_t>(), c->rank_bits.as<uint32_t>(), n, c->binom.as<uint64_t>(),
             t.chunk, c->units.as<uint64_t>(), units, pl, max_groups, clear_in, clear_out, sink,
@@ -848,7 +882,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     auto it = c->tuned.find(tkey);
     if (it != c->tuned.end()) {
       param = it->second;
-    } else if (flags & VRPH_AUTOTUNE) {
+    } else if ((flags & VRPH_AUTOTUNE) && !(flags & VRPH_FULL_SORT)) {
       // time settings on this very input (outputs are rewritten by the run
       // below): for d >= 2 the work-unit size and the workgroups per compute
       // unit, by coordinate search. One launch first sizes the outputs, so
@@ -1004,7 +1038,8 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
 }
 
 constexpr uint32_t kKnownFlags = VRPH_KEEP_ZERO_PERSISTENCE | VRPH_NO_ENCLOSING_RADIUS |
-                                 VRPH_AUTOTUNE | VRPH_NO_LDS | VRPH_HASHED_CLEARING;
+                                 VRPH_AUTOTUNE | VRPH_NO_LDS | VRPH_HASHED_CLEARING |
+                                 VRPH_FULL_SORT;
 
 static vrph_status check_common(vrph_ctx* c, int64_t n, int32_t max_dim, float threshold,
                                 uint32_t flags, vrph_barcode** out) {

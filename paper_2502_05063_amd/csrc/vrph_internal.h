@@ -172,6 +172,23 @@ hipError_t launch_enum_apparent_lds(int d, const uint16_t* Wr, const uint32_t* r
                                     uint64_t units, PrefixList pl, unsigned max_groups,
                                     ClearSet clear_in, ClearSet clear_out, ColumnSink sink,
                                     PairSink aps, Scalars* sc, hipStream_t s);
+// The paper's unfused order (measurement only), d = 2 or 3, rank matrix in
+// LDS, dense units, bitmap clearing: launch_enum_filter_lds writes every
+// column that survives the threshold and clearing set clear_in into sink
+// (not tested; counts columns and candidates into sc), and, once those are
+// gathered and sorted, launch_apparent_sorted_lds tests the min(*count,
+// cap) sorted columns cols, writes the non-apparent ones into sink and sets the
+// apparent cofacets' bits in clear_out (a bitmap, or none); grid
+// workgroups stride over the columns.
+hipError_t launch_enum_filter_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
+                                  const uint64_t* binom, int chunk, const uint64_t* unit_cum,
+                                  uint64_t units, unsigned max_groups, ClearSet clear_in,
+                                  ColumnSink sink, Scalars* sc, hipStream_t s);
+hipError_t launch_apparent_sorted_lds(int d, const uint16_t* Wr, const uint32_t* rank_bits, int n,
+                                      const uint64_t* binom, const Column* cols,
+                                      const unsigned long long* count, uint64_t cap,
+                                      unsigned grid, ClearSet clear_out, ColumnSink sink,
+                                      Scalars* sc, hipStream_t s);
 // d >= 2; unit_cum (n+1 entries, device) and units from enum_units() on the
 // host; at most max_groups workgroups, which stride over the units
 hipError_t launch_enum_apparent(int d, const uint32_t* W, int n, const uint64_t* binom, int chunk,

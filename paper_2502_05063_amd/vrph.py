@@ -23,6 +23,7 @@ HASHED_CLEARING = 16
 BOUNDARY_NO_CLEARING = 32
 BOUNDARY_NO_COMPRESSION = 64
 HOST_REDUCTION = 128
+FULL_SORT = 256
 EXT_ORD0, EXT_REL1, EXT_EXT0, EXT_EXT1 = 0, 1, 2, 3
 EXT_BAR_DTYPE = np.dtype([("kind", "<i4"), ("birth", "<i4"), ("death", "<i4"),
                           ("birth_value", "<f4"), ("death_value", "<f4"),
@@ -208,10 +209,11 @@ class Context:
         return D
 
     def barcode(self, *, X=None, D=None, max_dim=1, threshold=float("inf"), keep_zero=False,
-                no_enclosing=False, autotune=False, lds=True, hashed_clearing=False):
+                no_enclosing=False, autotune=False, lds=True, hashed_clearing=False,
+                full_sort=False):
         flags = ((KEEP_ZERO_PERSISTENCE if keep_zero else 0) | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
                  | (AUTOTUNE if autotune else 0) | (0 if lds else NO_LDS)
-                 | (HASHED_CLEARING if hashed_clearing else 0))
+                 | (HASHED_CLEARING if hashed_clearing else 0) | (FULL_SORT if full_sort else 0))
         out = ctypes.c_void_p()
         if X is not None:
             X = self._f32(X)
