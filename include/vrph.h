@@ -376,6 +376,23 @@ vrph_status vrph_graph_extended(vrph_ctx* ctx, int32_t count, const int64_t* v_o
                                 const int64_t* e_off, const float* f, const int32_t* edges,
                                 vrph_ext_bar* bars, void* hip_stream);
 
+/* The backward of the readout (the bars as a differentiable layer over f,
+ * Ch. 7; Sec. 7.2's values are f at the vertices the bars name): for the
+ * bars of a vrph_graph_extended call with the same count, v_off and e_off
+ * (HOST arrays, checked as there), adds g_birth[i] to g_f at bar i's
+ * birth_vertex and g_death[i] at its death_vertex (vertex numbers within
+ * the bar's graph, which is fixed by its position). bars (v_off[count] +
+ * e_off[count] records), g_birth and g_death (one float per bar; either may
+ * be NULL for zero) and g_f (v_off[count] floats, caller-owned, accumulated
+ * into, not zeroed) are DEVICE arrays. The pairing is piecewise constant in
+ * f, so this is the gradient wherever the vertex values are distinct.
+ * VRPH_EINVAL for bad offsets or a bar whose vertices are not in its graph
+ * (checked before anything is written). */
+vrph_status vrph_graph_extended_backward(vrph_ctx* ctx, int32_t count, const int64_t* v_off,
+                                         const int64_t* e_off, const vrph_ext_bar* bars,
+                                         const float* g_birth, const float* g_death, float* g_f,
+                                         void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

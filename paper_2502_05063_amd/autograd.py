@@ -92,3 +92,38 @@ def cloud_persistence(X: torch.Tensor, lib_ctx: "vrph.Context", dim: int = 1, ma
                       threshold: float = float("inf")):
     """(births, deaths) of the finite dimension-`dim` pairs of one cloud."""
     return _CloudPersistence.apply(X, lib_ctx, dim, max_dim, threshold)
+
+
+class _GraphExtended(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, f, lib_ctx, edges, v_off, e_off):
+        bars = lib_ctx.graph_extended(f.detach(), edges, v_off, e_off, host=False)
+        births = bars[:, 3].contiguous().view(torch.float32)
+        deaths = bars[:, 4].contiguous().view(torch.float32)
+        kinds = bars[:, 0].contiguous()
+        fctx.save_for_backward(bars)
+        fctx.lib = lib_ctx
+        fctx.offsets = (v_off, e_off)
+        fctx.mark_non_differentiable(kinds)
+        return births, deaths, kinds
+
+    @staticmethod
+    def backward(fctx, g_birth, g_death, g_kind):
+        (bars,) = fctx.saved_tensors
+        v_off, e_off = fctx.offsets
+        g_f = torch.zeros(int(np.asarray(v_off)[-1]), device=bars.device, dtype=torch.float32)
+        fctx.lib.graph_extended_backward(
+            bars, None if g_birth is None else g_birth.float().contiguous(),
+            None if g_death is None else g_death.float().contiguous(), v_off, e_off, g_f)
+        return g_f, None, None, None, None
+
+
+def graph_extended_values(lib_ctx, f, edges, v_off, e_off):
+    """Extended persistence of a batch of graphs as a differentiable layer
+    (Sec. 7.2; the readouts of Ch. 7): returns the birth and death values of
+    every bar (differentiable with respect to the vertex values f, float32
+    [V] on the device) and their kinds (vrph.EXT_*), in the bar order of
+    vrph_graph_extended. Each value is f at the vertex the bar names, so the
+    gradient is the library's scatter onto those vertices."""
+    return _GraphExtended.apply(f, lib_ctx, edges, v_off, e_off)
+

@@ -458,4 +458,57 @@ hipError_t launch_graph_ext(const int64_t* v_off, const int64_t* e_off, int coun
   return hipGetLastError();
 }
 
+// The gradient of a loss in the bar values with respect to f (the readout
+// as a differentiable layer, Ch. 7): a bar's birth (death) value is f at its
+// birth (death) vertex, so d(loss)/d(f) is the scatter of the loss's partial
+// derivatives onto those vertices. Graph g's bars are [v_off[g] + e_off[g],
+// v_off[g+1] + e_off[g+1]); its vertices start at v_off[g]. Pass 0 checks
+// that every bar's two vertices lie in its graph (else *bad = 1); pass 1
+// scatters, unless *bad is set. g_birth or g_death may be null (zero).
+__global__ void gext_grad_kernel(int pass, const int64_t* __restrict__ v_off,
+                                 const int64_t* __restrict__ e_off, int count, int64_t nbars,
+                                 const vrph_ext_bar* __restrict__ bars,
+                                 const float* __restrict__ g_birth,
+                                 const float* __restrict__ g_death, float* __restrict__ g_f,
+                                 uint32_t* __restrict__ bad) {
+  if (pass == 1 && *bad) return;
+  bool out = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nbars;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = count - 1;  // the graph g with bar_off[g] <= i
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (v_off[mid] + e_off[mid] <= i)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int64_t v0 = v_off[lo], n = v_off[lo + 1] - v0;
+    const int32_t bv = bars[i].birth_vertex, dv = bars[i].death_vertex;
+    if (pass == 0) {
+      out |= bv < 0 || bv >= n || dv < 0 || dv >= n;
+      continue;
+    }
+    if (g_birth && g_birth[i] != 0.0f) atomicAdd(&g_f[v0 + bv], g_birth[i]);
+    if (g_death && g_death[i] != 0.0f) atomicAdd(&g_f[v0 + dv], g_death[i]);
+  }
+  if (pass == 0 && __ballot(out) != 0 && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+}
+
+hipError_t launch_graph_ext_grad(const int64_t* v_off, const int64_t* e_off, int count,
+                                 int64_t nbars, const vrph_ext_bar* bars, const float* g_birth,
+                                 const float* g_death, float* g_f, uint32_t* bad,
+                                 hipStream_t s) {
+  if (count < 1 || nbars < 1) return hipSuccess;
+  int64_t blocks = (nbars + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  for (int pass = 0; pass < 2; ++pass) {
+    gext_grad_kernel<<<(unsigned)blocks, 256, 0, s>>>(pass, v_off, e_off, count, nbars, bars,
+                                                       g_birth, g_death, g_f, bad);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace vrph

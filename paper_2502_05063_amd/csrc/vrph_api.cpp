@@ -1151,25 +1151,34 @@ extern "C" vrph_status vrph_backward_noalloc(vrph_ctx* c, const float* X, int64_
 // extended persistence of graphs
 // ---------------------------------------------------------------------------
 
+// The offsets of a batch of graphs (host arrays of count + 1 entries):
+// empty string if valid, else the error; *max_n = the largest graph.
+static std::string graph_offsets_error(int32_t count, const int64_t* v_off, const int64_t* e_off,
+                                       int* max_n) {
+  if (count < 1 || !v_off || !e_off) return "bad argument";
+  if (v_off[0] != 0 || e_off[0] != 0) return "offsets must start at 0";
+  *max_n = 1;
+  for (int g = 0; g < count; ++g) {
+    const int64_t n = v_off[g + 1] - v_off[g], m = e_off[g + 1] - e_off[g];
+    if (n < 1 || n > kGraphMaxN) return "every graph needs 1 to 4096 vertices";
+    if (m < 0) return "edge offsets decrease";
+    *max_n = std::max<int>(*max_n, (int)n);
+  }
+  const int64_t V = v_off[count], E = e_off[count];
+  if (V + E >= ((int64_t)1 << 31) || E >= ((int64_t)1 << 31) - 1)
+    return "totals must stay below 2^31";
+  return "";
+}
+
 extern "C" vrph_status vrph_graph_extended(vrph_ctx* c, int32_t count, const int64_t* v_off,
                                            const int64_t* e_off, const float* f,
                                            const int32_t* edges, vrph_ext_bar* bars,
                                            void* hip_stream) {
-  if (!c || count < 1 || !v_off || !e_off)
-    return fail(VRPH_EINVAL, "vrph_graph_extended: bad argument");
-  if (v_off[0] != 0 || e_off[0] != 0)
-    return fail(VRPH_EINVAL, "vrph_graph_extended: offsets must start at 0");
+  if (!c) return fail(VRPH_EINVAL, "vrph_graph_extended: bad argument");
   int max_n = 1;
-  for (int g = 0; g < count; ++g) {
-    const int64_t n = v_off[g + 1] - v_off[g], m = e_off[g + 1] - e_off[g];
-    if (n < 1 || n > kGraphMaxN)
-      return fail(VRPH_EINVAL, "vrph_graph_extended: every graph needs 1 to 4096 vertices");
-    if (m < 0) return fail(VRPH_EINVAL, "vrph_graph_extended: edge offsets decrease");
-    max_n = std::max<int>(max_n, (int)n);
-  }
+  const std::string bad = graph_offsets_error(count, v_off, e_off, &max_n);
+  if (!bad.empty()) return fail(VRPH_EINVAL, "vrph_graph_extended: " + bad);
   const int64_t V = v_off[count], E = e_off[count];
-  if (V + E >= ((int64_t)1 << 31) || E >= ((int64_t)1 << 31) - 1)
-    return fail(VRPH_EINVAL, "vrph_graph_extended: totals must stay below 2^31");
   if (!f || !bars || (E > 0 && !edges))
     return fail(VRPH_EINVAL, "vrph_graph_extended: NULL array");
   HIP_TRY(hipSetDevice(c->device));
@@ -1205,6 +1214,37 @@ extern "C" vrph_status vrph_graph_extended(vrph_ctx* c, int32_t count, const int
                                  ((err & 2u) ? " a loop" : "") +
                                  ((err & 4u) ? " a value that is not finite" : ""));
   if (err) return fail(VRPH_EDEVICE, "vrph_graph_extended: an internal consistency check failed");
+  return VRPH_OK;
+}
+
+extern "C" vrph_status vrph_graph_extended_backward(vrph_ctx* c, int32_t count,
+                                                    const int64_t* v_off, const int64_t* e_off,
+                                                    const vrph_ext_bar* bars,
+                                                    const float* g_birth, const float* g_death,
+                                                    float* g_f, void* hip_stream) {
+  if (!c) return fail(VRPH_EINVAL, "vrph_graph_extended_backward: bad argument");
+  int max_n = 1;
+  const std::string bad = graph_offsets_error(count, v_off, e_off, &max_n);
+  if (!bad.empty()) return fail(VRPH_EINVAL, "vrph_graph_extended_backward: " + bad);
+  if (!bars || !g_f) return fail(VRPH_EINVAL, "vrph_graph_extended_backward: NULL array");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  NOT_CAPTURING(s, "vrph_graph_extended_backward");
+  HIP_TRY(c->g_off.ensure((size_t)(count + 1) * 2 * sizeof(int64_t)));
+  HIP_TRY(c->g_err.ensure(sizeof(uint32_t)));
+  int64_t* doff = c->g_off.as<int64_t>();
+  HIP_TRY(hipMemcpyAsync(doff, v_off, (size_t)(count + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(doff + count + 1, e_off, (size_t)(count + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(c->g_err.p, 0, sizeof(uint32_t), s));
+  HIP_TRY(launch_graph_ext_grad(doff, doff + count + 1, count, v_off[count] + e_off[count], bars,
+                                g_birth, g_death, g_f, c->g_err.as<uint32_t>(), s));
+  uint32_t err = 0;
+  HIP_TRY(hipMemcpyAsync(&err, c->g_err.p, sizeof(err), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (err)
+    return fail(VRPH_EINVAL, "vrph_graph_extended_backward: a bar's vertex is not in its graph");
   return VRPH_OK;
 }
 

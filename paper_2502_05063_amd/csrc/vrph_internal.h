@@ -312,6 +312,14 @@ hipError_t launch_graph_ext(const int64_t* v_off, const int64_t* e_off, int coun
                             Column* tmp, void* sort_work, uint32_t* pos_list, uint32_t* adj_off,
                             uint32_t* adj, uint32_t* stack, uint32_t* err, vrph_ext_bar* bars,
                             hipStream_t s);
+// The gradient of a loss in the bar values with respect to f: g_f (v_off[
+// count] floats, accumulated into) receives g_birth[i] at bar i's birth
+// vertex and g_death[i] at its death vertex (either array may be null).
+// *bad (zeroed by the caller) is set, and nothing written, if a bar's
+// vertices are not in its graph.
+hipError_t launch_graph_ext_grad(const int64_t* v_off, const int64_t* e_off, int count,
+                                 int64_t nbars, const vrph_ext_bar* bars, const float* g_birth,
+                                 const float* g_death, float* g_f, uint32_t* bad, hipStream_t s);
 
 // ---- noalloc.hip ----
 // Words of the fixed per-device scratch array of the allocation-free entry

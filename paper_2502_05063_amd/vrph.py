@@ -125,6 +125,7 @@ def lib():
         "vrph_backward_noalloc": (i32, [vp, vp, i64, i32, vp, i64, vp, vp, vp, vp]),
         "vrph_boundary_pivots": (i32, [vp, i64, vp, vp, u32, vp, vp, P(BoundaryStats)]),
         "vrph_graph_extended": (i32, [vp, i32, vp, vp, vp, vp, vp, vp]),
+        "vrph_graph_extended_backward": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -326,6 +327,20 @@ class Context:
         rec = bars.cpu().numpy().reshape(-1).view(EXT_BAR_DTYPE)
         start = v_off + e_off
         return bars, [rec[start[g]:start[g + 1]] for g in range(count)]
+
+    def graph_extended_backward(self, bars, g_birth, g_death, v_off, e_off, g_f):
+        """vrph_graph_extended_backward: adds g_birth / g_death (float32, one
+        per bar, device; None for zero) to g_f (float32 [V], device) at the
+        vertices the bars (the int32 [V + E, 7] tensor of graph_extended) name."""
+        v_off = np.ascontiguousarray(v_off, dtype=np.int64)
+        e_off = np.ascontiguousarray(e_off, dtype=np.int64)
+        gb = None if g_birth is None else self._f32(g_birth)
+        gd = None if g_death is None else self._f32(g_death)
+        _check(lib().vrph_graph_extended_backward(
+            self.h, len(v_off) - 1, v_off.ctypes.data_as(ctypes.c_void_p),
+            e_off.ctypes.data_as(ctypes.c_void_p), _dev_ptr(bars.contiguous()),
+            None if gb is None else _dev_ptr(gb), None if gd is None else _dev_ptr(gd),
+            _dev_ptr(g_f), _stream_ptr()))
 
     def batch(self, sizes, m, max_dim=1, threshold=float("inf"), keep_zero=False,
               no_enclosing=False, host_reduction=False, autotune=False):
