@@ -107,7 +107,48 @@ def cpu_baseline(X, max_dim):
     }
 
 
-def batched_vs_plain(ctx, steps):
+def _oracle_fwd_bwd(X):
+    """One cloud through the oracle: the barcode of dimensions 0-1 and the
+    gradient of sum over finite H1 pairs of (death - birth)^2 with respect to
+    the points (the batched leg's loss)."""
+    import numpy as np
+
+    import oracle
+
+    D = oracle.pdist(X)
+    pairs = oracle.barcode(D, 1)
+    h1 = pairs[(pairs["dim"] == 1) & (pairs["death"] != np.iinfo(np.uint64).max)]
+    g = 2.0 * (h1["death_diam"].astype(np.float64) - h1["birth_diam"].astype(np.float64))
+    oracle.gradient(X, D, h1, -g, g)
+    return len(h1)
+
+
+def _oracle_ready(_):
+    import oracle
+
+    oracle.lib()
+    return 0
+
+
+def batched_cpu_baseline(clouds):
+    """The oracle on a sample of the batched leg's clouds, one cloud per
+    process across the host's cores (up to 16), forward and backward."""
+    import multiprocessing as mp
+
+    workers = max(1, min(16, os.cpu_count() or 1, len(clouds)))
+    sample = clouds[:workers]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        pool.map(_oracle_ready, range(4 * workers), chunksize=1)  # workers up, oracle loaded
+        t0 = time.perf_counter()
+        pool.map(_oracle_fwd_bwd, sample, chunksize=1)
+        dt = time.perf_counter() - t0
+    return {"value": len(sample) / dt, "unit": "clouds/s", "cores": workers, "kind": "oracle",
+            "sample": (f"the first {len(sample)} of the 64 tori, one per process, barcode of "
+                       f"dimensions 0-1 and the loss gradient, {dt:.1f} s"),
+            "cpu_model": cpu_model()}
+
+
+def batched_vs_plain(ctx, steps, cpu_leg=True):
     """Forward + backward of loss = sum over H1 of (death - birth)^2 on 64 noisy
     tori of 500 points (sigma 0.1), through torch.autograd on the same GPU:
     one batched graph replay that also reduces dimension 1 on the device
@@ -164,6 +205,8 @@ def batched_vs_plain(ctx, steps):
         out[f"{key}_device_reduced_clouds"] = int(sum(r.stats["device_reduced"] for r in res))
     out["host_threads_batched_host_reduction"] = min(16, os.cpu_count() or 1)
     out["workload"] = "64 noisy tori x 500 points in R^3 (sigma 0.1), dims 0-1, loss sum (death-birth)^2 over H1"
+    if cpu_leg:
+        out["cpu_baseline"] = batched_cpu_baseline(clouds)
     batch.close()
     batch_host.close()
     return out
@@ -398,7 +441,8 @@ def main():
                                                     "frac": equiv_gbs / HBM_PEAK_GBS}},
     }
     if not args.no_batched:
-        out["batched_fwd_bwd"] = batched_vs_plain(ctx, max(2, min(args.steps, 5)))
+        out["batched_fwd_bwd"] = batched_vs_plain(ctx, max(2, min(args.steps, 5)),
+                                                  cpu_leg=not args.no_cpu_baseline)
     if not args.no_boundary:
         out["boundary_scan"] = boundary_scan(ctx)
     if not args.no_graphs:
