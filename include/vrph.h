@@ -183,7 +183,8 @@ vrph_status vrph_pdist(vrph_ctx* ctx, const float* X, int64_t n, int32_t m, floa
 
 /* Barcode of a distance matrix. D: n x n float32, finite, >= 0, symmetric,
  * zero diagonal (VRPH_EINVAL otherwise; the triangle inequality is not
- * required, Sec. 5.6.6). 1 <= n <= 4096, 0 <= max_dim <= VRPH_MAX_DIM,
+ * required, Sec. 5.6.6). 1 <= n <= 16384 (the n x n weights take 4 n^2
+ * bytes of device memory, 1 GiB at 16384), 0 <= max_dim <= VRPH_MAX_DIM,
  * threshold >= 0 or +inf. */
 vrph_status vrph_barcode_from_dist(vrph_ctx* ctx, const float* D, int64_t n, int32_t max_dim,
                                    float threshold, uint32_t flags, void* hip_stream,
@@ -205,7 +206,7 @@ vrph_status vrph_barcode_from_points(vrph_ctx* ctx, const float* X, int64_t n, i
  * min_i max_j D_ij with the missing entries infinite, i.e. it only cuts
  * where some point has all its n-1 distances given. VRPH_EINVAL for an
  * index out of range, a diagonal entry, a repeated pair, or a value that is
- * negative or not finite. 1 <= n <= 4096, 0 <= nnz <= n(n-1)/2. */
+ * negative or not finite. 1 <= n <= 16384, 0 <= nnz <= n(n-1)/2. */
 vrph_status vrph_barcode_from_sparse(vrph_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row,
                                      const int32_t* col, const float* val, int32_t max_dim,
                                      float threshold, uint32_t flags, void* hip_stream,

@@ -355,6 +355,8 @@ __device__ __forceinline__ int h0_find(int* parent, int x) {
 // so each later merge sees the roots as of its own turn. Each edge joins
 // two components (it is a forest edge), so every merge kills a root once;
 // the block's links are written to parent at its end.
+__device__ void h0_pair(const unsigned long long* mst, int m, int* parent, int* mark, int n,
+                        uint32_t* bm, H0Pair* o, uint32_t* count);
 __device__ void h0_finish(unsigned long long* mst, int m, int* parent, int* mark, int n,
                           uint32_t* bm, H0Pair* o, uint32_t* count) {
   const int tid = threadIdx.x;
@@ -408,6 +410,16 @@ __device__ void h0_finish(unsigned long long* mst, int m, int* parent, int* mark
     __syncthreads();
   }
 
+  h0_pair(mst, m, parent, mark, n, bm, o, count);
+}
+
+// Phase 3 of h0_finish on keys already sorted ascending (in LDS or in
+// global memory), with parent[v] = v and mark[v] = 0 for every vertex; all
+// threads of the workgroup call it.
+__device__ void h0_pair(const unsigned long long* mst, int m, int* parent, int* mark, int n,
+                        uint32_t* bm, H0Pair* o, uint32_t* count) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
   // the forest edges are H0 deaths: clear them for dimension 1
   for (int i = tid; i < m; i += kH0Threads) {
     uint32_t e = 0xFFFFFFFFu - (uint32_t)mst[i];
@@ -483,10 +495,10 @@ __global__ __launch_bounds__(kH0Threads) void batch_h0_kernel(const uint32_t* __
                                                               H0Pair* __restrict__ out,
                                                               int64_t out_stride,
                                                               uint32_t* __restrict__ bitmaps) {
-  __shared__ unsigned long long best[kMaxN];  // per component root: its minimum outgoing edge
-  __shared__ unsigned long long mst[kMaxN];
-  __shared__ int comp[kMaxN];                 // component root of every vertex
-  __shared__ int hookto[kMaxN];               // where a root moves this round
+  __shared__ unsigned long long best[kBatchMaxN];  // per component root: its minimum outgoing edge
+  __shared__ unsigned long long mst[kBatchMaxN];
+  __shared__ int comp[kBatchMaxN];                 // component root of every vertex
+  __shared__ int hookto[kBatchMaxN];               // where a root moves this round
   __shared__ int m_sh, changed;
   constexpr unsigned long long kNone = ~0ull;
 
@@ -677,21 +689,66 @@ __global__ __launch_bounds__(kH0Threads) void h0w_finish_kernel(int n, H0Wide w,
                                                                 CloudState* __restrict__ st,
                                                                 H0Pair* __restrict__ out,
                                                                 uint32_t* __restrict__ bm) {
-  __shared__ unsigned long long mst[kMaxN];
-  __shared__ int parent[kMaxN];
-  __shared__ int mark[kMaxN];
-  const int m = *w.m;  // < n <= kMaxN
+  __shared__ unsigned long long mst[kH0LdsN];
+  __shared__ int parent[kH0LdsN];
+  __shared__ int mark[kH0LdsN];
+  const int m = *w.m;  // < n <= kH0LdsN
   for (int i = threadIdx.x; i < m; i += kH0Threads) mst[i] = w.mst[i];
   __syncthreads();
   h0_finish(mst, m, parent, mark, n, bm, out, &st->h0_count);
 }
 
-size_t h0_wide_scratch_bytes(int n) { return (size_t)n * 24 + 256; }
+// Clouds above kH0LdsN points: the forest's keys do not fit LDS next to the
+// union-find's arrays, so they are sorted in global memory by the radix sort
+// (as Column records: the weight bits, then the reversed edge index, which
+// orders them as the 64-bit keys) and read from there by the same pairing
+// as above, with parent and mark in dynamic LDS (8 bytes per vertex).
+__global__ void h0w_keys_to_cols_kernel(H0Wide w, Column* __restrict__ cols,
+                                        unsigned long long* __restrict__ m64) {
+  const int m = *w.m;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    const unsigned long long k = w.mst[i];
+    cols[i] = Column{(uint32_t)(k >> 32), 0u, (uint64_t)(uint32_t)k};
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *m64 = (unsigned long long)m;
+}
+
+__global__ void h0w_cols_to_keys_kernel(const Column* __restrict__ cols, H0Wide w) {
+  const int m = *w.m;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+    w.mst[i] = ((unsigned long long)cols[i].key_hi << 32) | cols[i].cidx;
+}
+
+__global__ __launch_bounds__(kH0Threads) void h0w_finish_big_kernel(int n, H0Wide w,
+                                                                    CloudState* __restrict__ st,
+                                                                    H0Pair* __restrict__ out,
+                                                                    uint32_t* __restrict__ bm) {
+  extern __shared__ int h0_lds[];  // parent[n], then mark[n]
+  int* const parent = h0_lds;
+  int* const mark = h0_lds + n;
+  for (int v = threadIdx.x; v < n; v += kH0Threads) {
+    parent[v] = v;
+    mark[v] = 0;
+  }
+  __syncthreads();
+  h0_pair(w.mst, *w.m, parent, mark, n, bm, out, &st->h0_count);
+}
+
+// scratch of launch_h0_wide: best, mst, comp, hookto, m, done; above
+// kH0LdsN points also two Column arrays, a 64-bit count and the sort's work
+// (the Column arrays start on a 256-byte boundary)
+static size_t h0_wide_base(int n) { return ((size_t)n * 24 + 256 + 255) & ~(size_t)255; }
+size_t h0_wide_scratch_bytes(int n) {
+  size_t b = h0_wide_base(n);
+  if (n > kH0LdsN) b += (size_t)n * 32 + 256 + ((radix_sort_work_bytes(n) + 255) & ~(size_t)255);
+  return b;
+}
 
 hipError_t launch_h0_wide(const uint32_t* W, int n, CloudState* st, H0Pair* out, uint32_t* bm,
                           void* scratch, hipStream_t s) {
   if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
   char* p = static_cast<char*>(scratch);
+  const size_t base = h0_wide_base(n);
   H0Wide w;
   w.best = reinterpret_cast<unsigned long long*>(p);
   w.mst = reinterpret_cast<unsigned long long*>(p + (size_t)n * 8);
@@ -707,7 +764,27 @@ hipError_t launch_h0_wide(const uint32_t* W, int n, CloudState* st, H0Pair* out,
     h0w_scan_kernel<<<scan_groups, kH0Threads, 0, s>>>(W, n, w);
     h0w_hook_kernel<<<1, kH0Threads, 0, s>>>(n, w);
   }
-  h0w_finish_kernel<<<1, kH0Threads, 0, s>>>(n, w, st, out, bm);
+  if (n <= kH0LdsN) {
+    h0w_finish_kernel<<<1, kH0Threads, 0, s>>>(n, w, st, out, bm);
+    return hipGetLastError();
+  }
+  Column* cols = reinterpret_cast<Column*>(p + base);
+  Column* tmp = cols + n;
+  unsigned long long* m64 = reinterpret_cast<unsigned long long*>(tmp + n);
+  void* work = p + base + (size_t)n * 32 + 256;
+  const unsigned cg = (unsigned)((n + kBlock - 1) / kBlock);
+  h0w_keys_to_cols_kernel<<<cg, kBlock, 0, s>>>(w, cols, m64);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  bool in_tmp = false;
+  if ((e = radix_sort_columns(cols, tmp, n, 32, 0, work, s, m64, &in_tmp)) != hipSuccess) return e;
+  h0w_cols_to_keys_kernel<<<cg, kBlock, 0, s>>>(in_tmp ? tmp : cols, w);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t lds = (size_t)n * 2 * sizeof(int);
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&h0w_finish_big_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+    return e;
+  h0w_finish_big_kernel<<<1, kH0Threads, lds, s>>>(n, w, st, out, bm);
   return hipGetLastError();
 }
 
@@ -1251,7 +1328,7 @@ __device__ __forceinline__ void enum_units(
   uint32_t nb_all = 0;  // common neighbours; the first nb_below are below v2
   if constexpr (kNeighbours) {
     if (listed) {
-      __shared__ uint16_t cn[kMaxN];
+      extern __shared__ uint16_t cn[];  // n entries: the launch sizes it
       __shared__ uint32_t wcount[BS / 64];
       const int wave = (int)(threadIdx.x >> 6), l64 = (int)(threadIdx.x & 63);
       uint32_t cnt = 0;
@@ -1307,14 +1384,14 @@ __device__ __forceinline__ void enum_units(
     for (int i = 2; i <= D; ++i) vv[i] = v[i];
     if (k < k_end) {
       // suffix: largest v1 with C(v1, 2) <= k, i.e. floor((1 + sqrt(8k+1))/2),
-      // then v0. k < C(n, 2) < 2^23, so 8k + 1 < 2^26 is exact in 32 bits and
-      // within a relative 2^-24 as a float; the hardware square root adds at
-      // most 1 ulp (2^-10 at 8192). The estimate is then within 3e-3 of the
-      // exact quotient and its floor is off by at most one either way: one
-      // exact integer step corrects it.
+      // then v0. k < C(n, 2) < 2^27 (n <= 16384), so 8k + 1 < 2^30 is exact
+      // in 32 bits and within a relative 2^-24 as a float; the hardware
+      // square root adds at most 1 ulp (2^-8 below 2^15). The estimate is
+      // then within 1e-2 of the exact quotient and its floor is off by at
+      // most one either way: one exact integer step corrects it.
       const uint32_t k32 = (uint32_t)k;
       int v1 = (int)((1.0f + __builtin_amdgcn_sqrtf((float)(8u * k32 + 1u))) * 0.5f);
-      uint32_t t1 = __umul24(v1, v1 - 1) >> 1;  // C(v1, 2); v1 <= n <= 2^12
+      uint32_t t1 = __umul24(v1, v1 - 1) >> 1;  // C(v1, 2); v1 <= n <= 2^14: < 2^28
       if (t1 > k32) {
         --v1;
         t1 -= v1;
@@ -1557,7 +1634,10 @@ static hipError_t launch_enum_D(const uint32_t* W, int n, const uint64_t* binom,
                                 unsigned grid, ClearSet clear_in, ClearSet clear_out,
                                 ColumnSink sink, PairSink aps, Scalars* sc, hipStream_t s) {
   auto go = [&](auto mode) {
-    enum_apparent_kernel<D, decltype(mode)::value><<<grid, kBlock, 0, s>>>(
+    constexpr int kMode = decltype(mode)::value;
+    // listed units build a common-neighbour list of up to n entries in LDS
+    const size_t lds = (kMode & kModeListed) ? (((size_t)n * 2 + 15) & ~(size_t)15) : 0;
+    enum_apparent_kernel<D, kMode><<<grid, kBlock, lds, s>>>(
         W, n, binom, chunk, unit_cum, units, pl, clear_in, clear_out, sink, aps, sc);
     return hipGetLastError();
   };

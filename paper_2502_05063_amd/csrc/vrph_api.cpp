@@ -1046,7 +1046,7 @@ static vrph_status check_common(vrph_ctx* c, int64_t n, int32_t max_dim, float t
   if (!c || !out) return fail(VRPH_EINVAL, "NULL context or output");
   *out = nullptr;
   if (flags & ~kKnownFlags) return fail(VRPH_EINVAL, "unknown flag bits");
-  if (n < 1 || n > kMaxN) return fail(VRPH_EINVAL, "n must be in [1, 4096]");
+  if (n < 1 || n > kMaxN) return fail(VRPH_EINVAL, "n must be in [1, 16384]");
   if (max_dim < 0 || max_dim > VRPH_MAX_DIM) return fail(VRPH_EINVAL, "max_dim out of range");
   if (std::isnan(threshold) || threshold < 0) return fail(VRPH_EINVAL, "threshold must be >= 0");
   return VRPH_OK;
@@ -1491,7 +1491,7 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
   b->binoms.resize(count);
   for (int i = 0; i < count; ++i) {
     const int64_t n = sizes[i];
-    if (n < 2 || n > kMaxN) return fail(VRPH_EINVAL, "vrph_batch_plan: cloud size out of [2, 4096]");
+    if (n < 2 || n > kBatchMaxN) return fail(VRPH_EINVAL, "vrph_batch_plan: cloud size out of [2, 4096]");
     Cloud& cl = b->clouds[i];
     cl.x_off = b->total_points;
     cl.w_off = b->total_w;

@@ -15,7 +15,9 @@ namespace vrph {
 // threshold (and the diagonal) hold kInf, larger than any finite pattern.
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr int kMaxDim = 6;        // largest max_dim
-constexpr int kMaxN = 4096;       // largest cloud the one-workgroup H0 kernel takes
+constexpr int kMaxN = 16384;      // largest single cloud
+constexpr int kBatchMaxN = 4096;  // largest cloud of a batch (one-workgroup H0 in LDS)
+constexpr int kH0LdsN = 4096;     // largest cloud whose H0 finish sorts its forest in LDS
 constexpr int kBlock = 256;       // threads per workgroup of the streaming kernels
 // clouds up to kLdsMaxN points enumerate from a 16-bit rank matrix in LDS
 // (at most 80,000 bytes, two workgroups of kLdsBlock per 160 KB CU)

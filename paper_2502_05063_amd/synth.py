@@ -109,6 +109,11 @@ CONFIGS = {
     "c5_torus64x500": dict(max_dim=1, threshold=float("inf")),
     # the o3 recipe at the paper's size (Table 5.2: 4096 points, threshold 1.4)
     "o3_4096": dict(max_dim=3, threshold=1.4),
+    # clouds above 4096 points (sparse complexes: about 15-25 neighbours per
+    # point within the threshold)
+    "cube6000": dict(max_dim=2, threshold=0.09),
+    "cube10000": dict(max_dim=1, threshold=0.06),
+    "cube16384": dict(max_dim=1, threshold=0.05),
 }
 
 

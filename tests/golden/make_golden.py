@@ -17,6 +17,7 @@ zero-persistence pair can be compared bit for bit.
     python tests/golden/make_golden.py c2_sphere192 c3_o3_1024
     python tests/golden/make_golden.py c4_batch256 c5_torus64x500
     python tests/golden/make_golden.py o3_4096
+    python tests/golden/make_golden.py cube6000 cube10000 cube16384
 """
 from __future__ import annotations
 
@@ -46,6 +47,9 @@ def inputs(name):
         return synth.orthogonal_3x3(1024, seed=0)
     if name == "o3_4096":
         return synth.orthogonal_3x3(4096, seed=0)
+    if name in ("cube6000", "cube10000", "cube16384"):
+        n = int(name[4:])
+        return synth.uniform_cube(n, 3, seed=n)
     raise KeyError(name)
 
 
@@ -65,7 +69,8 @@ def make(name):
     nz = oracle.nonzero(P)
     out = {
         "config": name,
-        "generator": f"paper_2502_05063_amd.synth ({name}, seed 0)",
+        "generator": (f"paper_2502_05063_amd.synth.uniform_cube({name[4:]}, 3, seed={name[4:]})"
+                      if name.startswith("cube") else f"paper_2502_05063_amd.synth ({name}, seed 0)"),
         "max_dim": cfg["max_dim"],
         "threshold": cfg["threshold"] if np.isfinite(cfg["threshold"]) else "inf",
         "enclosing_radius": float(oracle.enclosing_radius(D)),
