@@ -14,6 +14,9 @@ Workloads (synthetic, seeded; see synth.py):
             the same batches with dimension 1 reduced on host threads
   o3-4096   4096 random O(3) matrices, threshold 1.4, dimensions 0-3 (the
             size of the paper's o3 run)
+  cube6000, cube10000, cube16384
+            uniform clouds in the unit cube above 4096 points under low
+            thresholds (0.09, dimensions 0-2; 0.06 and 0.05, dimensions 0-1)
   boundary  the boundary matrix of a Rips 2-skeleton (2000 points, 0.22)
             through the explicit-matrix path
   graphs    extended persistence of 1024 graphs of 20-300 vertices (mean
@@ -74,6 +77,11 @@ def run(names=None, reps=3):
     if "o3-4096" in want:
         single("o3-4096", dev(synth.orthogonal_3x3(4096, 0)), max_dim=3, threshold=1.4,
                autotune=True)
+    for name, cfg in synth.CONFIGS.items():
+        if name.startswith("cube") and name in want:
+            nn = int(name[4:])
+            single(name, dev(synth.uniform_cube(nn, 3, seed=nn)), max_dim=cfg["max_dim"],
+                   threshold=cfg["threshold"], autotune=True)
     for name in ("c4", "c4-host", "c5", "c5-host"):
         if name not in want:
             continue
