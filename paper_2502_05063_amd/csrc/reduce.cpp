@@ -1373,14 +1373,34 @@ void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t n
 // pattern, which orders non-negative floats), and equal weights share a rank.
 void RankTable::build(int n, const uint32_t* W) {
   const size_t nn = (size_t)n * (size_t)n;
-  Wr.assign(nn, kInf);
   bits.clear();
-  std::vector<uint64_t> e, tmp;  // weight << 32 | position a*n + b
-  for (int a = 1; a < n; ++a)
-    for (int b = 0; b < a; ++b) {
-      const uint32_t w = W[(size_t)a * n + b];
-      if (w != kInf) e.push_back(((uint64_t)w << 32) | (uint32_t)((size_t)a * n + b));
-    }
+  // the n x n fill and the scan of the lower triangle run on several
+  // threads for large clouds (row blocks; the edges are concatenated in row
+  // order, as one thread would list them)
+  const int nt = n >= 2048 ? (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency())) : 1;
+  std::vector<std::vector<uint64_t>> part((size_t)nt);  // weight << 32 | position a*n + b
+  Wr.resize(nn);
+  auto scan = [&](int t) {
+    const int a0 = (int)((int64_t)n * t / nt), a1 = (int)((int64_t)n * (t + 1) / nt);
+    std::fill(Wr.begin() + (std::ptrdiff_t)((size_t)a0 * n), Wr.begin() + (std::ptrdiff_t)((size_t)a1 * n),
+              kInf);
+    for (int a = std::max(a0, 1); a < a1; ++a)
+      for (int b = 0; b < a; ++b) {
+        const uint32_t w = W[(size_t)a * n + b];
+        if (w != kInf) part[(size_t)t].push_back(((uint64_t)w << 32) | (uint32_t)((size_t)a * n + b));
+      }
+  };
+  {
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(scan, t);
+    scan(0);
+    for (std::thread& th : pool) th.join();
+  }
+  std::vector<uint64_t> e, tmp;
+  size_t total = 0;
+  for (const auto& v : part) total += v.size();
+  e.reserve(total);
+  for (const auto& v : part) e.insert(e.end(), v.begin(), v.end());
   tmp.resize(e.size());
   for (int shift = 32; shift < 64; shift += 11) {
     size_t cnt[2049] = {0};

@@ -224,6 +224,8 @@ struct vrph_ctx {
   uint64_t col_cap = 0;    // non-apparent columns the buffers are sized for
   uint64_t pair_cap = 0;   // apparent pairs the buffers are sized for
   HostPinned h_scal, h_cstate;
+  HostPinned h_Wn;   // a single cloud's weights on the host (n x n)
+  RankTable ranks;   // its weight ranks (host reduction, LDS kernels)
   std::vector<uint64_t> h_binom;
   int binom_n = -1, binom_k = -1;
   std::string arch;
@@ -349,6 +351,7 @@ extern "C" void vrph_destroy(vrph_ctx* c) {
   for (DevBuf& b : c->hset) b.release();
   c->h_scal.release();
   c->h_cstate.release();
+  c->h_Wn.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->ev2) (void)hipEventDestroy(c->ev2);
@@ -614,9 +617,12 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   HIP_TRY(hipEventRecord(c->ev1, s));
   CloudState cs;
   HIP_TRY(hipMemcpyAsync(c->h_cstate.p, c->cstate.p, sizeof(CloudState), hipMemcpyDeviceToHost, s));
-  std::vector<uint32_t> hW((size_t)n * n);
+  // the weights on the host, in a pinned buffer the context keeps (no page
+  // faults or zero fill per call, and the copy is a straight DMA)
+  HIP_TRY(c->h_Wn.ensure((size_t)n * n * 4));
+  uint32_t* const hW = c->h_Wn.as<uint32_t>();
   std::vector<H0Pair> h0(n);
-  HIP_TRY(hipMemcpyAsync(hW.data(), c->W.p, (size_t)n * n * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hW, c->W.p, (size_t)n * n * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(h0.data(), c->h0.p, (size_t)n * sizeof(H0Pair), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   std::memcpy(&cs, c->h_cstate.p, sizeof(cs));
@@ -627,14 +633,14 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
                                  ((cs.err & 8) ? " nonzero diagonal" : "") +
                                  ((cs.err & 16) ? " entry index out of range or on the diagonal" : "") +
                                  ((cs.err & 32) ? " repeated pair" : ""));
-  H.W = hW.data();
+  H.W = hW;
   // Weight ranks: needed by the host reduction and, for small clouds, by the
   // LDS enumeration kernels (16-bit ranks: C(kLdsMaxN, 2) < 0xFFFF).
-  RankTable ranks;
+  RankTable& ranks = c->ranks;  // its storage is reused across calls
   std::vector<uint16_t> h_wr16;
   const bool use_lds = max_dim >= 2 && n <= kLdsMaxN && !(flags & VRPH_NO_LDS);
   if (use_lds) {
-    ranks.build(n, hW.data());
+    ranks.build(n, hW);
     ranks.attach(H);
     const size_t stride = (size_t)lds_stride((int)n);
     h_wr16.assign((size_t)n * stride, 0xFFFF);
@@ -662,21 +668,29 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   std::vector<uint32_t> pfx2, pfx3;
   bool sparse_edges = false;
   if (max_dim >= 1 && n >= 3) {
-    uint64_t valid = 0, total = 0;
-    for (int a = 1; a < n; ++a)
-      for (int b = 0; b < a; ++b) {
-        ++total;
-        valid += hW[(size_t)a * n + b] != kInf;
-      }
-    sparse_edges = 2 * valid < total;
+    // the lower triangle's finite entries, rows interleaved over threads
+    std::atomic<uint64_t> valid{0};
+    const int nt = n >= 2048 ? host_threads() : 1;
+    auto count_rows = [&](int t) {
+      uint64_t v = 0;
+      for (size_t a = 1 + (size_t)t; a < (size_t)n; a += (size_t)nt)
+        for (size_t b = 0; b < a; ++b) v += hW[a * n + b] != kInf;
+      valid += v;
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(count_rows, t);
+    count_rows(0);
+    for (std::thread& th : pool) th.join();
+    const uint64_t total = (uint64_t)n * (uint64_t)(n - 1) / 2;
+    sparse_edges = 2 * valid.load() < total;
   }
   if (max_dim >= 2 && n >= 3 && !use_lds) {
     if (sparse_edges) {
       for (int v2 = n - 1; v2 >= 2; --v2) pfx2.push_back((uint32_t)v2);
       if (max_dim >= 3)
         for (int v2 = n - 2; v2 >= 2; --v2)
-          for (int v3 = v2 + 1; v3 < n; ++v3)
-            if (hW[(size_t)v3 * n + v2] != kInf) pfx3.push_back(((uint32_t)v3 << 16) | (uint32_t)v2);
+          for (int v3 = v2 + 1; v3 < n; ++v3)  // row v2 (W is symmetric): contiguous
+            if (hW[(size_t)v2 * n + v3] != kInf) pfx3.push_back(((uint32_t)v3 << 16) | (uint32_t)v2);
       HIP_TRY(c->pfx_v.ensure(std::max<size_t>(pfx2.size() + pfx3.size(), 1) * sizeof(uint32_t)));
       if (!pfx2.empty())
         HIP_TRY(hipMemcpyAsync(c->pfx_v.p, pfx2.data(), pfx2.size() * sizeof(uint32_t),
@@ -1001,7 +1015,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     deaths.clear();
     ReduceStats rs;
     if (nna > 0 && !H.Wr) {  // not built yet (no LDS kernel in this call)
-      ranks.build(n, hW.data());
+      ranks.build(n, hW);
       ranks.attach(H);
     }
     reduce_dimension(H, d, hcols.data(), nna, host_threads(), prs, deaths, rs);
