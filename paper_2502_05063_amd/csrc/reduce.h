@@ -65,8 +65,9 @@ struct ReduceStats {
 // Reduce the non-apparent columns of dimension d, given in coboundary order,
 // with the reduction-matrix technique (Sec. 5.2.9: R = D V; a column adds the
 // reduced columns of earlier pivots, so its pivot only moves up). H must
-// carry a RankTable: rows are compared by weight rank. The working column is
-// a radix heap over ranks with sorted runs for the rank the pivot is in.
+// carry a RankTable: rows are compared by weight rank. The working column
+// keeps its rows in buckets over rank ranges, with sorted runs for the
+// bucket the pivot is in.
 // Pivot lookups go to a table of the pairs found so far, then to the apparent
 // pairs, recognised on the fly from Def. 5.3.4 instead of a stored array.
 // While a column's pivot is the cofacet of an apparent pair, the addition it
