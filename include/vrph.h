@@ -88,6 +88,11 @@ typedef enum {
  * threads instead of on the device (the results are the same; for comparing
  * the two) */
 #define VRPH_HOST_REDUCTION 128u
+/* vrph_batch_plan: reduce every cloud's dimension 1 on the device (unless its
+ * tables overflow), instead of handing the clouds the cost model deems
+ * heaviest to host threads that run beside the device reduction (the
+ * results are the same; for comparing the two) */
+#define VRPH_DEVICE_REDUCTION 512u
 /* The paper's unfused order for dimensions 2 and 3 of a cloud of at most 200
  * points (the kernels that read the rank matrix from LDS): every column
  * that survives the threshold and clearing is written (Alg. 17), all of
@@ -225,21 +230,28 @@ void vrph_barcode_free(vrph_barcode* bc);
  * A plan fixes the cloud sizes, the ambient dimension m, max_dim, threshold
  * and flags, and allocates every device buffer the batch needs up front.
  * Clouds are packed row-major one after another in X_packed
- * (sum(sizes) x m floats). vrph_batch_forward replays one captured HIP graph
+ * (sum(sizes) x m floats). vrph_batch_forward replays a captured HIP graph
  * over all clouds: distances, enclosing radii, H0, enumeration and the
- * apparent-pairs test, and the submatrix reduction of the non-apparent
- * columns of dimension 1 (Sec. 5.2.9-5.2.11), one workgroup per cloud; then
- * it copies the pairs back. A cloud whose reduction outgrows its device
- * tables is reduced on host threads instead, as is every cloud under
- * VRPH_HOST_REDUCTION. Each size must satisfy 2 <= size <= 4096 and every
- * cloud uses the same max_dim (<= 1). vrph_batch_plan accepts
- * VRPH_KEEP_ZERO_PERSISTENCE, VRPH_NO_ENCLOSING_RADIUS, VRPH_HOST_REDUCTION
- * and VRPH_AUTOTUNE: the first forward then runs the batch's device work
+ * apparent-pairs test and the sort of the non-apparent columns of dimension
+ * 1. A second captured graph then reduces those columns (Sec.
+ * 5.2.9-5.2.11), one workgroup per cloud, while host threads reduce the
+ * clouds that a cost model (non-apparent columns x points, and a
+ * host-to-device time ratio the batch updates from what each forward
+ * measures) deems heaviest; the forward then copies the pairs back. A cloud
+ * whose reduction outgrows its device tables is reduced on host threads
+ * too. Under VRPH_DEVICE_REDUCTION every cloud is reduced on the device,
+ * under VRPH_HOST_REDUCTION every cloud on host threads; the results do not
+ * depend on where a cloud is reduced (stats.device_reduced tells which).
+ * Each size must satisfy 2 <= size <= 4096 and every cloud uses the same
+ * max_dim (<= 1). vrph_batch_plan accepts VRPH_KEEP_ZERO_PERSISTENCE,
+ * VRPH_NO_ENCLOSING_RADIUS, VRPH_HOST_REDUCTION, VRPH_DEVICE_REDUCTION (not
+ * both) and VRPH_AUTOTUNE: the first forward then runs the batch's device work
  * eagerly for a few launch settings (the device reduction's workgroup size,
  * 256, 512 or 1024 lanes per cloud; the dimension-1 edge kernel's
- * workgroups per compute unit), timed with HIP events, and captures the
- * graph with the fastest; the choice is kept per (GPU architecture, size
- * bucket of the largest cloud) in the context and in VRPH_TUNING_FILE
+ * workgroups per compute unit), timed with HIP events with every cloud
+ * reduced on the device, and captures the graphs with the fastest; the
+ * choice is kept per (GPU architecture, size bucket of the largest cloud)
+ * in the context and in VRPH_TUNING_FILE
  * (variant 3), and later plans of that bucket use it without tuning. Results
  * do not depend on the settings. It sizes every device buffer first and returns
  * VRPH_ENOMEM, allocating nothing, when they exceed the free device memory

@@ -562,6 +562,10 @@ __global__ __launch_bounds__(T) void dred_reduce_kernel(DredArgs A) {
   extern __shared__ uint32_t cnt1[];
   __shared__ Shared sh;
   const int c = blockIdx.x;
+  if (A.skip && A.skip[c]) {  // the host reduces this cloud (same value for the whole workgroup)
+    if (threadIdx.x == 0) A.stats[c] = DredStats{0, 0, 0};
+    return;
+  }
   const Cloud cl = A.clouds[c];
   const DredCloud dc = A.dc[c];
   const int n = cl.n;

@@ -13,9 +13,11 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <memory>
 #include <new>
+#include <queue>
 #include <sstream>
 #include <string>
 #include <thread>
@@ -1380,8 +1382,11 @@ struct vrph_batch {
   int max_kmax = 0;
   DevBuf X, D, W, dclouds, cstate, h0, bitmaps, cols, cols_tmp, sort_work, ap, counters;
   HostPinned h_cstate, h_counters, h_W;  // h_W: every cloud's weights, read by the host reduction
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // the forward's device work as two graphs: everything up to the sorted
+  // non-apparent columns (front), then the device reduction (back)
+  hipGraph_t graph = nullptr, graph_b = nullptr;
+  hipGraphExec_t exec = nullptr, exec_b = nullptr;
+  hipEvent_t ev[4] = {};
   std::vector<std::vector<uint64_t>> binoms;  // per cloud, k-major (kmax+1) x (n+1)
   std::vector<vrph_barcode> results;
   std::vector<H0Pair> hh0;
@@ -1391,6 +1396,17 @@ struct vrph_batch {
   int64_t last_columns = 0, last_apparent = 0, last_nonapparent = 0;
   // dimension-1 reduction on the device (unless VRPH_HOST_REDUCTION)
   bool device_reduce = false;
+  // Split (unless VRPH_DEVICE_REDUCTION): the clouds the cost model deems
+  // heaviest are reduced on host threads while the device reduces the rest.
+  // split_ratio: host-thread time per unit of estimated cost over the device
+  // time per unit, updated from the times each split forward measures.
+  bool split = false;
+  double split_ratio = 0.35;
+  // per cloud, the previous forward's dimension-1 columns and additions
+  std::vector<int64_t> last_cols, last_add;
+  DevBuf dskip;
+  HostPinned h_skip;
+  std::vector<char> w_on_host;
   // launch settings: the device reduction's workgroup size and the
   // dimension-1 edge kernel's workgroups per compute unit; tuned on the
   // first forward under VRPH_AUTOTUNE (or read from the tuning file)
@@ -1488,8 +1504,10 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
   *out = nullptr;
   if (max_dim < 0 || max_dim > 1) return fail(VRPH_EINVAL, "vrph_batch_plan: max_dim must be 0 or 1");
   if (flags & ~(VRPH_KEEP_ZERO_PERSISTENCE | VRPH_NO_ENCLOSING_RADIUS | VRPH_HOST_REDUCTION |
-                VRPH_AUTOTUNE))
+                VRPH_AUTOTUNE | VRPH_DEVICE_REDUCTION))
     return fail(VRPH_EINVAL, "vrph_batch_plan: unsupported flag bits");
+  if ((flags & VRPH_HOST_REDUCTION) && (flags & VRPH_DEVICE_REDUCTION))
+    return fail(VRPH_EINVAL, "vrph_batch_plan: VRPH_HOST_REDUCTION and VRPH_DEVICE_REDUCTION exclude each other");
   if (std::isnan(threshold) || threshold < 0) return fail(VRPH_EINVAL, "threshold must be >= 0");
   HIP_TRY(hipSetDevice(c->device));
   std::unique_ptr<vrph_batch> b(new (std::nothrow) vrph_batch());
@@ -1525,6 +1543,7 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
   const uint64_t cap = (uint64_t)std::max<int64_t>(b->total_edges, 1);
   const bool keep_zero = flags & VRPH_KEEP_ZERO_PERSISTENCE;
   b->device_reduce = max_dim >= 1 && !(flags & VRPH_HOST_REDUCTION);
+  b->split = b->device_reduce && !(flags & VRPH_DEVICE_REDUCTION);
   // every device buffer the plan needs, sized first: a plan larger than the
   // free device memory (or than VRPH_WORKSPACE_CAP bytes, if set) is refused
   // before anything is allocated
@@ -1540,7 +1559,10 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
                {&b->sort_work, radix_sort_work_bytes((int64_t)cap)},
                {&b->counters, sizeof(Scalars)}};
   if (keep_zero) want.push_back({&b->ap, cap * sizeof(ApparentPair)});
-  if (b->device_reduce) dred_sizes(b.get(), want);
+  if (b->device_reduce) {
+    dred_sizes(b.get(), want);
+    want.push_back({&b->dskip, (size_t)count * 4});
+  }
   size_t need = 0;
   for (const auto& w : want) need += w.second;
   size_t free_b = 0, total_b = 0;
@@ -1557,6 +1579,14 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
   for (const auto& w : want) HIP_TRY(w.first->ensure(w.second));
   HIP_TRY(b->h_cstate.ensure((size_t)count * sizeof(CloudState)));
   HIP_TRY(b->h_counters.ensure(sizeof(Scalars)));
+  if (b->device_reduce) {
+    HIP_TRY(b->h_skip.ensure((size_t)count * 4));
+    std::memset(b->h_skip.p, 0, (size_t)count * 4);
+    HIP_TRY(hipMemcpy(b->dskip.p, b->h_skip.p, (size_t)count * 4, hipMemcpyHostToDevice));
+  }
+  b->w_on_host.assign((size_t)count, 0);
+  b->last_cols.assign((size_t)count, 0);
+  b->last_add.assign((size_t)count, 0);
   // the weights on the host: for the host reduction and for the edges of
   // apparent pairs (otherwise allocated only if a cloud falls back to the host)
   if (!b->device_reduce || keep_zero) HIP_TRY(b->h_W.ensure((size_t)b->total_w * 4));
@@ -1579,6 +1609,14 @@ extern "C" vrph_status vrph_batch_plan(vrph_ctx* c, const int64_t* sizes, int32_
     }
   }
   b->results.resize(count);
+  for (hipEvent_t& ev : b->ev) {
+    const hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) {
+      for (hipEvent_t& x : b->ev)
+        if (x) (void)hipEventDestroy(x);
+      return fail(VRPH_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    }
+  }
   *out = b.release();
   return VRPH_OK;
 }
@@ -1588,25 +1626,31 @@ extern "C" void vrph_batch_destroy(vrph_batch* b) {
   (void)hipSetDevice(b->ctx->device);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->exec_b) (void)hipGraphExecDestroy(b->exec_b);
+  if (b->graph_b) (void)hipGraphDestroy(b->graph_b);
+  for (hipEvent_t e : b->ev)
+    if (e) (void)hipEventDestroy(e);
   DevBuf* bufs[] = {&b->X,    &b->D,        &b->W,         &b->dclouds, &b->cstate,
                     &b->h0,   &b->bitmaps,  &b->cols,      &b->cols_tmp, &b->sort_work,
                     &b->ap,   &b->counters, &b->ddc, &b->ew, &b->eat, &b->egrp, &b->egend,
                     &b->ecnt, &b->epos,  &b->tri,    &b->tlog,    &b->tab_keys, &b->tab_vals, &b->varena,
                     &b->vbits, &b->vtouch, &b->col_begin, &b->col_end, &b->out_death,
-                    &b->out_ddiam, &b->out_dedge, &b->col_voff, &b->col_vlen, &b->dstats};
+                    &b->out_ddiam, &b->out_dedge, &b->col_voff, &b->col_vlen, &b->dstats, &b->dskip};
   for (DevBuf* d : bufs) d->release();
   b->h_cstate.release();
   b->h_counters.release();
   b->h_W.release();
+  b->h_skip.release();
   delete b;
 }
 
-// Device work of one forward, recorded once into a graph and replayed:
-// reset of the per-cloud state with fill kernels (no memset nodes), distances,
-// validation + weights, H0, the dimension-1 enumeration + apparent test over
-// the edges of every cloud, the coboundary-order sort with the record count
-// read on the device, and the copies of the small results to pinned memory.
-static hipError_t batch_record(vrph_batch* b, hipStream_t s) {
+// Device work of one forward up to the sorted columns, recorded once into a
+// graph and replayed: reset of the per-cloud state with fill kernels (no
+// memset nodes), distances, validation + weights, H0, the dimension-1
+// enumeration + apparent test over the edges of every cloud, the
+// coboundary-order sort with the record count read on the device, and the
+// copies of the small results to pinned memory.
+static hipError_t batch_record_front(vrph_batch* b, hipStream_t s) {
   const bool keep_zero = b->flags & VRPH_KEEP_ZERO_PERSISTENCE;
   const bool enclosing = !(b->flags & VRPH_NO_ENCLOSING_RADIUS);
   Scalars* sc = b->counters.as<Scalars>();
@@ -1653,46 +1697,87 @@ static hipError_t batch_record(vrph_batch* b, hipStream_t s) {
                                 &in_tmp)))
       return e;
     b->sorted_in_tmp = in_tmp;
-    if (b->device_reduce) {
-      DredArgs a{};
-      a.clouds = b->dclouds.as<Cloud>();
-      a.dc = b->ddc.as<DredCloud>();
-      a.count = b->count;
-      a.cols = (in_tmp ? b->cols_tmp : b->cols).as<Column>();
-      a.ncols = &sc->nonapparent;
-      a.col_begin_w = b->col_begin.as<uint32_t>();
-      a.col_end_w = b->col_end.as<uint32_t>();
-      a.col_begin = a.col_begin_w;
-      a.col_end = a.col_end_w;
-      a.epos = b->epos.as<uint32_t>();
-      a.eat = b->eat.as<uint32_t>();
-      a.egrp = b->egrp.as<uint32_t>();
-      a.egend = b->egend.as<uint32_t>();
-      a.ew = b->ew.as<uint32_t>();
-      a.cnt = b->ecnt.as<uint32_t>();
-      a.tri = b->tri.as<uint32_t>();
-      a.tlog = b->tlog.as<uint32_t>();
-      a.tab_keys = b->tab_keys.as<unsigned long long>();
-      a.tab_vals = b->tab_vals.as<uint32_t>();
-      a.varena = b->varena.as<uint32_t>();
-      a.vbits = b->vbits.as<uint32_t>();
-      a.vtouch = b->vtouch.as<uint32_t>();
-      a.out_death = b->out_death.as<unsigned long long>();
-      a.out_ddiam = b->out_ddiam.as<uint32_t>();
-      a.out_dedge = b->out_dedge.as<uint32_t>();
-      a.col_voff = b->col_voff.as<uint32_t>();
-      a.col_vlen = b->col_vlen.as<uint32_t>();
-      a.stats = b->dstats.as<DredStats>();
-      if ((e = launch_dred_reduce(a, (int64_t)cap, b->max_n, b->dred_threads, s))) return e;
-    }
   }
   if ((e = hipMemcpyAsync(b->h_cstate.p, b->cstate.p, (size_t)b->count * sizeof(CloudState),
                           hipMemcpyDeviceToHost, s)))
     return e;
-  if ((e = hipMemcpyAsync(b->h_counters.p, b->counters.p, sizeof(Scalars), hipMemcpyDeviceToHost,
-                          s)))
-    return e;
-  return hipSuccess;
+  return hipMemcpyAsync(b->h_counters.p, b->counters.p, sizeof(Scalars), hipMemcpyDeviceToHost, s);
+}
+
+// The device reduction of dimension 1, recorded into a graph of its own: it
+// runs while host threads reduce the clouds flagged in dskip.
+static hipError_t batch_record_back(vrph_batch* b, hipStream_t s) {
+  if (!b->device_reduce || b->max_dim < 1) return hipSuccess;
+  const uint64_t cap = (uint64_t)std::max<int64_t>(b->total_edges, 1);
+  Scalars* sc = b->counters.as<Scalars>();
+  const bool in_tmp = b->sorted_in_tmp;
+  DredArgs a{};
+  a.clouds = b->dclouds.as<Cloud>();
+  a.dc = b->ddc.as<DredCloud>();
+  a.count = b->count;
+  a.cols = (in_tmp ? b->cols_tmp : b->cols).as<Column>();
+  a.ncols = &sc->nonapparent;
+  a.col_begin_w = b->col_begin.as<uint32_t>();
+  a.col_end_w = b->col_end.as<uint32_t>();
+  a.col_begin = a.col_begin_w;
+  a.col_end = a.col_end_w;
+  a.epos = b->epos.as<uint32_t>();
+  a.eat = b->eat.as<uint32_t>();
+  a.egrp = b->egrp.as<uint32_t>();
+  a.egend = b->egend.as<uint32_t>();
+  a.ew = b->ew.as<uint32_t>();
+  a.cnt = b->ecnt.as<uint32_t>();
+  a.tri = b->tri.as<uint32_t>();
+  a.tlog = b->tlog.as<uint32_t>();
+  a.tab_keys = b->tab_keys.as<unsigned long long>();
+  a.tab_vals = b->tab_vals.as<uint32_t>();
+  a.varena = b->varena.as<uint32_t>();
+  a.vbits = b->vbits.as<uint32_t>();
+  a.vtouch = b->vtouch.as<uint32_t>();
+  a.out_death = b->out_death.as<unsigned long long>();
+  a.out_ddiam = b->out_ddiam.as<uint32_t>();
+  a.out_dedge = b->out_dedge.as<uint32_t>();
+  a.col_voff = b->col_voff.as<uint32_t>();
+  a.col_vlen = b->col_vlen.as<uint32_t>();
+  a.stats = b->dstats.as<DredStats>();
+  a.skip = b->dskip.as<uint32_t>();
+  return launch_dred_reduce(a, (int64_t)cap, b->max_n, b->dred_threads, s);
+}
+
+// Which clouds host threads reduce while the device reduces the others. The
+// clouds come in decreasing estimated cost; the first k go to the host, k minimising the larger of the two sides'
+// estimated times: on the host the longest-processing-time schedule of
+// those clouds over `threads` threads, each taking `ratio` x its cost; on
+// the device the costliest remaining cloud (one workgroup each, all at
+// once), or their total over `units` workgroups at a time if that is larger.
+// Clouds without columns stay on the device. Ties keep the smaller k.
+static int choose_split(const std::vector<double>& cost, const std::vector<int>& order,
+                        int threads, double ratio, int units, double* host_est, double* dev_est) {
+  const int count = (int)order.size();
+  double rest = 0;
+  for (int i : order) rest += cost[(size_t)i];
+  std::priority_queue<double, std::vector<double>, std::greater<double>> loads;
+  for (int t = 0; t < std::max(1, threads); ++t) loads.push(0.0);
+  double host = 0, best = -1;
+  int best_k = 0;
+  for (int k = 0; k <= count; ++k) {
+    const double top = k < count ? cost[(size_t)order[(size_t)k]] : 0.0;
+    const double dev = std::max(top, rest / std::max(1, units));
+    const double t = std::max(host, dev);
+    if (best < 0 || t < best) {
+      best = t;
+      best_k = k;
+      *host_est = host;
+      *dev_est = dev;
+    }
+    if (k == count || top == 0) break;
+    const double l = loads.top() + ratio * top;
+    loads.pop();
+    loads.push(l);
+    host = std::max(host, l);
+    rest -= top;
+  }
+  return best_k;
 }
 
 extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, void* hip_stream) {
@@ -1702,17 +1787,25 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
   hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
   NOT_CAPTURING(s, "vrph_batch_forward");
   const double t_start = now_ms();
+  const bool dev = b->device_reduce && b->max_dim >= 1;
   HIP_TRY(hipMemcpyAsync(b->X.p, X_packed, (size_t)b->total_points * b->m * 4,
                          hipMemcpyDeviceToDevice, s));
   if (!b->exec && b->tune) {
     // the batch autotuner: the whole device part run eagerly (the same work
-    // the graph records) per candidate, timed with HIP events; first the
-    // device reduction's workgroup size, then the edge kernel's grid
+    // the graphs record, every cloud reduced on the device) per candidate,
+    // timed with HIP events; first the device reduction's workgroup size,
+    // then the edge kernel's grid
+    if (dev) {
+      std::memset(b->h_skip.p, 0, (size_t)b->count * 4);
+      HIP_TRY(hipMemcpyAsync(b->dskip.p, b->h_skip.p, (size_t)b->count * 4,
+                             hipMemcpyHostToDevice, s));
+    }
     auto time_once = [&](int threads, int mult, float* ms) -> hipError_t {
       b->dred_threads = threads;
       b->edge_mult = mult;
       hipError_t e = hipEventRecord(c->ev0, s);
-      if (e == hipSuccess) e = batch_record(b, s);
+      if (e == hipSuccess) e = batch_record_front(b, s);
+      if (e == hipSuccess) e = batch_record_back(b, s);
       if (e == hipSuccess) e = hipEventRecord(c->ev1, s);
       if (e == hipSuccess) e = hipEventSynchronize(c->ev1);
       if (e == hipSuccess) e = hipEventElapsedTime(ms, c->ev0, c->ev1);
@@ -1744,9 +1837,10 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
     c->tuned[key] = Tune{best_t, best_m};
     save_tuning(c, key, Tune{best_t, best_m});
   }
-  if (!b->exec) {
+  auto capture = [&](hipError_t (*rec)(vrph_batch*, hipStream_t), hipGraph_t* graph,
+                     hipGraphExec_t* exec) -> vrph_status {
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t e = batch_record(b, s);
+    hipError_t e = rec(b, s);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -1754,25 +1848,34 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
       return fail(VRPH_EDEVICE, std::string("graph capture failed: ") +
                                     hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    b->graph = g;
-    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    *graph = g;
+    HIP_TRY(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
+    return VRPH_OK;
+  };
+  if (!b->exec) {
+    vrph_status st = capture(batch_record_front, &b->graph, &b->exec);
+    if (st != VRPH_OK) return st;
   }
-  HIP_TRY(hipEventRecord(c->ev0, s));
+  if (dev && !b->exec_b) {
+    vrph_status st = capture(batch_record_back, &b->graph_b, &b->exec_b);
+    if (st != VRPH_OK) return st;
+  }
+  hipEvent_t* ev = b->ev;
+  HIP_TRY(hipEventRecord(ev[0], s));
   HIP_TRY(hipGraphLaunch(b->exec, s));
-  HIP_TRY(hipEventRecord(c->ev1, s));
+  HIP_TRY(hipEventRecord(ev[1], s));
   HIP_TRY(hipStreamSynchronize(s));
-  float gms = 0;
-  HIP_TRY(hipEventElapsedTime(&gms, c->ev0, c->ev1));
+  float front_ms = 0, back_ms = 0;
+  HIP_TRY(hipEventElapsedTime(&front_ms, ev[0], ev[1]));
   Scalars sc;
   std::memcpy(&sc, b->h_counters.p, sizeof(sc));
   const CloudState* cst = b->h_cstate.as<CloudState>();
   for (int i = 0; i < b->count; ++i)
     if (cst[i].err) return fail(VRPH_EINVAL, "invalid distances in cloud " + std::to_string(i));
 
-  // results of the device part
+  // results of the front part
   const bool keep_zero = b->flags & VRPH_KEEP_ZERO_PERSISTENCE;
   const int64_t nna = (int64_t)sc.nonapparent;
-  const bool dev = b->device_reduce && b->max_dim >= 1;
   b->hh0.resize((size_t)b->count * b->max_n);
   b->hcols.resize((size_t)nna);
   HIP_TRY(hipMemcpyAsync(b->hh0.data(), b->h0.p, b->hh0.size() * sizeof(H0Pair),
@@ -1786,7 +1889,173 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
       HIP_TRY(hipMemcpyAsync(b->hap.data(), b->ap.p, sc.apparent_written * sizeof(ApparentPair),
                              hipMemcpyDeviceToHost, s));
   }
+  HIP_TRY(hipStreamSynchronize(s));
+
+  // per-cloud slices of the sorted columns and of the apparent pairs
+  std::vector<int64_t> col_begin(b->count + 1, nna);
+  for (int64_t j = nna - 1; j >= 0; --j) col_begin[b->hcols[j].cloud] = j;
+  for (int i = b->count - 1; i >= 0; --i)
+    if (col_begin[i] > col_begin[i + 1]) col_begin[i] = col_begin[i + 1];
+  std::vector<std::vector<uint32_t>> ap_of(keep_zero ? b->count : 0);
+  if (keep_zero)
+    for (size_t j = 0; j < b->hap.size(); ++j) ap_of[b->hap[j].cloud].push_back((uint32_t)j);
+
+  // clouds in decreasing estimated reduction cost: the non-apparent columns
+  // times one plus the additions per column the previous forward made on
+  // that cloud (a batch is usually replayed on the same clouds as they
+  // move), else times the points / 16; the host hands them out in this
+  // order, so that a heavy cloud does not start last and stretch the tail
+  std::vector<double> cost((size_t)b->count);
+  for (int i = 0; i < b->count; ++i) {
+    const double nc = (double)(col_begin[i + 1] - col_begin[i]);
+    const int64_t lc = b->last_cols[(size_t)i];
+    cost[(size_t)i] = lc > 0 ? nc * (1.0 + (double)b->last_add[(size_t)i] / (double)lc)
+                             : nc * b->clouds[i].n / 16.0;
+  }
+  std::vector<int> order((size_t)b->count);
+  for (int i = 0; i < b->count; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return cost[(size_t)x] > cost[(size_t)y]; });
+  const int nthreads = std::max(1, std::min<int>(b->count, std::min<int>(16, (int)std::thread::hardware_concurrency())));
+  // the first n_host clouds of `order` are reduced on host threads
+  int n_host = b->count;
+  double host_est = 0, dev_est = 0;
   if (dev) {
+    n_host = b->split ? choose_split(cost, order, nthreads, b->split_ratio, c->num_cus, &host_est,
+                                     &dev_est)
+                      : 0;
+    uint32_t* skip = b->h_skip.as<uint32_t>();
+    std::memset(skip, 0, (size_t)b->count * 4);
+    for (int q = 0; q < n_host; ++q) skip[order[(size_t)q]] = 1;
+    HIP_TRY(hipMemcpyAsync(b->dskip.p, skip, (size_t)b->count * 4, hipMemcpyHostToDevice, s));
+  }
+  // the weights on the host: all of them for the host reduction and for the
+  // edges of apparent pairs, else those of the clouds the host reduces
+  std::fill(b->w_on_host.begin(), b->w_on_host.end(), 0);
+  auto copy_w = [&](int i) -> hipError_t {
+    const Cloud& cl = b->clouds[(size_t)i];
+    b->w_on_host[(size_t)i] = 1;
+    return hipMemcpyAsync(b->h_W.as<uint32_t>() + cl.w_off, b->W.as<uint32_t>() + cl.w_off,
+                          (size_t)cl.n * cl.n * 4, hipMemcpyDeviceToHost, s);
+  };
+  if (b->max_dim >= 1 && (!dev || keep_zero || n_host > 0)) {
+    HIP_TRY(b->h_W.ensure((size_t)b->total_w * 4));
+    if (!dev || keep_zero) {
+      HIP_TRY(hipMemcpyAsync(b->h_W.p, b->W.p, (size_t)b->total_w * 4, hipMemcpyDeviceToHost, s));
+      std::fill(b->w_on_host.begin(), b->w_on_host.end(), 1);
+    } else {
+      for (int q = 0; q < n_host; ++q) HIP_TRY(copy_w(order[(size_t)q]));
+    }
+  }
+  // the device reduction of the other clouds runs while the host reduces
+  HIP_TRY(hipEventRecord(ev[2], s));
+  if (dev) {
+    HIP_TRY(hipGraphLaunch(b->exec_b, s));
+    HIP_TRY(hipEventRecord(ev[3], s));
+  }
+  HIP_TRY(hipEventSynchronize(ev[2]));
+
+  auto host_reduced = [&](int i) { return !dev || b->h_skip.as<uint32_t>()[i] != 0 || b->hdstats[(size_t)i].err != 0; };
+  // one cloud's pairs: H0 from the device, dimension 1 reduced here or by
+  // the device, edges from the host weights where they are here
+  auto assemble = [&](int i) {
+    const Cloud& cl = b->clouds[i];
+    HostComplex H;
+    H.n = cl.n;
+    H.W = b->w_on_host[(size_t)i] ? b->h_W.as<uint32_t>() + cl.w_off : nullptr;
+    H.binom = b->binoms[i].data();
+    H.kmax = 3;
+    vrph_barcode& r = b->results[i];
+    r.pairs.clear();
+    std::memset(&r.stats, 0, sizeof(r.stats));
+    r.stats.max_dim = b->max_dim;
+    r.stats.tau_eff = bitsf(cst[i].tau_bits);
+    const H0Pair* h0 = b->hh0.data() + (size_t)i * b->max_n;
+    for (uint32_t k = 0; k < cst[i].h0_count && k < (uint32_t)cl.n; ++k)
+      r.pairs.push_back(make_pair(0, h0[k].birth, 0u, h0[k].death, h0[k].diam));
+    r.stats.pairs[0] = cst[i].h0_count;
+    if (b->max_dim >= 1) {
+      const int64_t cb = col_begin[i], ce = col_begin[i + 1];
+      if (!host_reduced(i)) {
+        // pairs of the device reduction, with their edges
+        for (int64_t j = cb; j < ce; ++j) {
+          vrph_pair p = make_pair(1, b->hcols[j].cidx, ~b->hcols[j].key_hi, b->hdeath[j],
+                                  b->hddiam[j]);
+          int v[2];
+          decode_simplex(H, p.birth, 1, v);
+          p.birth_edge[0] = v[1];
+          p.birth_edge[1] = v[0];
+          p.death_edge[0] = p.death_edge[1] = -1;
+          if (!p.essential) {
+            p.death_edge[0] = (int32_t)(b->hdedge[j] >> 16);
+            p.death_edge[1] = (int32_t)(b->hdedge[j] & 0xFFFF);
+          }
+          r.pairs.push_back(p);
+        }
+        r.stats.additions[1] = (int64_t)b->hdstats[(size_t)i].additions;
+        r.stats.emergent[1] = b->hdstats[(size_t)i].emergent;
+        r.stats.device_reduced = 1;
+      } else {
+        std::vector<PairRec> prs;
+        std::vector<uint64_t> deaths;
+        ReduceStats rs;
+        RankTable ranks;
+        if (ce > cb) {
+          ranks.build(cl.n, H.W);
+          ranks.attach(H);
+        }
+        reduce_dimension(H, 1, b->hcols.data() + cb, ce - cb, 1, prs, deaths, rs);
+        for (const PairRec& q : prs) r.pairs.push_back(make_pair(1, q.birth, q.bdiam, q.death, q.ddiam));
+        r.stats.additions[1] = rs.additions;
+        r.stats.emergent[1] = rs.emergent;
+      }
+      if (keep_zero)
+        for (uint32_t j : ap_of[i]) {
+          const ApparentPair& a = b->hap[j];
+          r.pairs.push_back(make_pair(1, a.s, a.diam, a.t, a.diam));
+        }
+      r.stats.reduced[1] = ce - cb;
+    }
+    if (H.W) {
+      finish_pairs(&r, H, b->max_dim, keep_zero, 1);
+    } else {
+      // edges without the weights: vertex births have none, an H0 death
+      // is its own edge, the dimension-1 pairs carry theirs
+      for (vrph_pair& p : r.pairs)
+        if (p.dim == 0) {
+          p.birth_edge[0] = p.birth_edge[1] = -1;
+          p.death_edge[0] = p.death_edge[1] = -1;
+          if (!p.essential) {
+            int v[2];
+            decode_simplex(H, p.death, 1, v);
+            p.death_edge[0] = v[1];
+            p.death_edge[1] = v[0];
+          }
+        }
+      order_pairs(&r, keep_zero, 1);
+    }
+  };
+  // clouds order[from, to) on the host threads
+  auto run_pool = [&](int from, int to) {
+    std::atomic<int> next{from};
+    auto work = [&]() {
+      for (int q; (q = next.fetch_add(1)) < to;) assemble(order[(size_t)q]);
+    };
+    const int nt = std::max(1, std::min(nthreads, to - from));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (std::thread& t : pool) t.join();
+  };
+
+  const double th = now_ms();
+  run_pool(0, n_host);
+  const double host_split_ms = now_ms() - th;
+  double tail_ms = 0;
+  if (dev) {
+    HIP_TRY(hipEventSynchronize(ev[3]));
+    HIP_TRY(hipEventElapsedTime(&back_ms, ev[2], ev[3]));
+    const double t2 = now_ms();
     b->hdeath.resize((size_t)nna);
     b->hddiam.resize((size_t)nna);
     b->hdedge.resize((size_t)nna);
@@ -1801,134 +2070,34 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
     }
     HIP_TRY(hipMemcpyAsync(b->hdstats.data(), b->dstats.p, (size_t)b->count * sizeof(DredStats),
                            hipMemcpyDeviceToHost, s));
-  }
-  HIP_TRY(hipStreamSynchronize(s));
-  // the weights on the host: for the host reduction, for a cloud the device
-  // reduction left to it, and for the edges of the apparent pairs
-  bool need_w = !dev || keep_zero;
-  int fallback = 0;
-  if (dev)
-    for (int i = 0; i < b->count; ++i) fallback += b->hdstats[(size_t)i].err != 0;
-  need_w |= fallback > 0;
-  if (need_w && b->max_dim >= 1) {
-    HIP_TRY(b->h_W.ensure((size_t)b->total_w * 4));
-    HIP_TRY(hipMemcpyAsync(b->h_W.p, b->W.p, (size_t)b->total_w * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-  }
-
-  // per-cloud slices of the sorted columns and of the apparent pairs
-  std::vector<int64_t> col_begin(b->count + 1, nna);
-  for (int64_t j = nna - 1; j >= 0; --j) col_begin[b->hcols[j].cloud] = j;
-  for (int i = b->count - 1; i >= 0; --i)
-    if (col_begin[i] > col_begin[i + 1]) col_begin[i] = col_begin[i + 1];
-  std::vector<std::vector<uint32_t>> ap_of(keep_zero ? b->count : 0);
-  if (keep_zero)
-    for (size_t j = 0; j < b->hap.size(); ++j) ap_of[b->hap[j].cloud].push_back((uint32_t)j);
-
-  // assembly, and the host reduction where it is needed, one cloud per task
-  const double th = now_ms();
-  std::atomic<int> next{0};
-  // longest first: clouds are handed out by their estimated reduction cost
-  // (non-apparent columns x coboundary length), so that a heavy cloud does
-  // not start last and stretch the tail
-  std::vector<int> order((size_t)b->count);
-  for (int i = 0; i < b->count; ++i) order[(size_t)i] = i;
-  auto host_reduced = [&](int i) { return !dev || b->hdstats[(size_t)i].err != 0; };
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    const int64_t cx = host_reduced(x) ? (col_begin[x + 1] - col_begin[x]) * (int64_t)b->clouds[x].n : 0;
-    const int64_t cy = host_reduced(y) ? (col_begin[y + 1] - col_begin[y]) * (int64_t)b->clouds[y].n : 0;
-    return cx > cy;
-  });
-  auto work = [&]() {
-    for (;;) {
-      const int q = next.fetch_add(1);
-      if (q >= b->count) return;
+    // a cloud whose tables overflowed on the device is reduced here
+    bool more_w = false;
+    for (int q = n_host; q < b->count; ++q) {
       const int i = order[(size_t)q];
-      const Cloud& cl = b->clouds[i];
-      HostComplex H;
-      H.n = cl.n;
-      H.W = need_w ? b->h_W.as<uint32_t>() + cl.w_off : nullptr;
-      H.binom = b->binoms[i].data();
-      H.kmax = 3;
-      vrph_barcode& r = b->results[i];
-      r.pairs.clear();
-      std::memset(&r.stats, 0, sizeof(r.stats));
-      r.stats.max_dim = b->max_dim;
-      r.stats.tau_eff = bitsf(cst[i].tau_bits);
-      const H0Pair* h0 = b->hh0.data() + (size_t)i * b->max_n;
-      for (uint32_t k = 0; k < cst[i].h0_count && k < (uint32_t)cl.n; ++k)
-        r.pairs.push_back(make_pair(0, h0[k].birth, 0u, h0[k].death, h0[k].diam));
-      r.stats.pairs[0] = cst[i].h0_count;
-      if (b->max_dim >= 1) {
-        const int64_t cb = col_begin[i], ce = col_begin[i + 1];
-        if (!host_reduced(i)) {
-          // pairs of the device reduction, with their edges
-          for (int64_t j = cb; j < ce; ++j) {
-            vrph_pair p = make_pair(1, b->hcols[j].cidx, ~b->hcols[j].key_hi, b->hdeath[j],
-                                    b->hddiam[j]);
-            int v[2];
-            decode_simplex(H, p.birth, 1, v);
-            p.birth_edge[0] = v[1];
-            p.birth_edge[1] = v[0];
-            p.death_edge[0] = p.death_edge[1] = -1;
-            if (!p.essential) {
-              p.death_edge[0] = (int32_t)(b->hdedge[j] >> 16);
-              p.death_edge[1] = (int32_t)(b->hdedge[j] & 0xFFFF);
-            }
-            r.pairs.push_back(p);
-          }
-          r.stats.additions[1] = (int64_t)b->hdstats[(size_t)i].additions;
-          r.stats.emergent[1] = b->hdstats[(size_t)i].emergent;
-          r.stats.device_reduced = 1;
-        } else {
-          std::vector<PairRec> prs;
-          std::vector<uint64_t> deaths;
-          ReduceStats rs;
-          RankTable ranks;
-          if (ce > cb) {
-            ranks.build(cl.n, H.W);
-            ranks.attach(H);
-          }
-          reduce_dimension(H, 1, b->hcols.data() + cb, ce - cb, 1, prs, deaths, rs);
-          for (const PairRec& q : prs) r.pairs.push_back(make_pair(1, q.birth, q.bdiam, q.death, q.ddiam));
-          r.stats.additions[1] = rs.additions;
-          r.stats.emergent[1] = rs.emergent;
-        }
-        if (keep_zero)
-          for (uint32_t j : ap_of[i]) {
-            const ApparentPair& a = b->hap[j];
-            r.pairs.push_back(make_pair(1, a.s, a.diam, a.t, a.diam));
-          }
-        r.stats.reduced[1] = ce - cb;
-      }
-      if (need_w || b->max_dim < 1) {
-        finish_pairs(&r, H, b->max_dim, keep_zero, 1);
-      } else {
-        // edges without the weights: vertex births have none, an H0 death
-        // is its own edge, the dimension-1 pairs carry theirs
-        for (vrph_pair& p : r.pairs)
-          if (p.dim == 0) {
-            p.birth_edge[0] = p.birth_edge[1] = -1;
-            p.death_edge[0] = p.death_edge[1] = -1;
-            if (!p.essential) {
-              int v[2];
-              decode_simplex(H, p.death, 1, v);
-              p.death_edge[0] = v[1];
-              p.death_edge[1] = v[0];
-            }
-          }
-        order_pairs(&r, keep_zero, 1);
+      if (b->hdstats[(size_t)i].err != 0 && !b->w_on_host[(size_t)i]) {
+        HIP_TRY(b->h_W.ensure((size_t)b->total_w * 4));
+        HIP_TRY(copy_w(i));
+        more_w = true;
       }
     }
-  };
-  const int nthreads = std::max(1, std::min<int>(b->count, std::min<int>(16, (int)std::thread::hardware_concurrency())));
-  std::vector<std::thread> pool;
-  for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
-  work();
-  for (std::thread& t : pool) t.join();
-  const double host_ms = now_ms() - th;
+    if (more_w) HIP_TRY(hipStreamSynchronize(s));
+    run_pool(n_host, b->count);
+    tail_ms = now_ms() - t2;
+    // the host-to-device time ratio, from what this forward measured
+    if (n_host > 0 && n_host < b->count && host_est > 0 && dev_est > 0 && back_ms > 1.0 &&
+        host_split_ms > 1.0) {
+      const double dev_rate = back_ms / dev_est;
+      const double host_rate = host_split_ms / (host_est / b->split_ratio);
+      const double r = std::sqrt(b->split_ratio * (host_rate / dev_rate));
+      b->split_ratio = std::min(50.0, std::max(0.02, r));
+    }
+  }
+  const double host_ms = host_split_ms + tail_ms;
   for (int i = 0; i < b->count; ++i) {
-    b->results[i].stats.gpu_ms[0] = gms;
+    b->last_cols[(size_t)i] = b->results[i].stats.reduced[1];
+    b->last_add[(size_t)i] = b->results[i].stats.additions[1];
+    b->results[i].stats.gpu_ms[0] = front_ms + back_ms;
     b->results[i].stats.host_ms[1] = host_ms;
     b->results[i].stats.grid[1] = b->max_dim >= 1 ? c->num_cus * b->edge_mult : 0;
     b->results[i].stats.total_ms = now_ms() - t_start;

@@ -285,6 +285,7 @@ struct DredArgs {
   uint32_t* col_voff;                // per paired column: its V in the arena
   uint32_t* col_vlen;
   DredStats* stats;                  // per cloud
+  const uint32_t* skip;              // per cloud: nonzero = reduced on host threads (null: none)
 };
 // Edge positions of every cloud: records into rec (total_edges), sorted
 // with rec_tmp and sort_work, then ew / eat / egrp / egend per position and

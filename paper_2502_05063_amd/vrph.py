@@ -23,6 +23,7 @@ HASHED_CLEARING = 16
 BOUNDARY_NO_CLEARING = 32
 BOUNDARY_NO_COMPRESSION = 64
 HOST_REDUCTION = 128
+DEVICE_REDUCTION = 512
 FULL_SORT = 256
 EXT_ORD0, EXT_REL1, EXT_EXT0, EXT_EXT1 = 0, 1, 2, 3
 EXT_BAR_DTYPE = np.dtype([("kind", "<i4"), ("birth", "<i4"), ("death", "<i4"),
@@ -343,21 +344,22 @@ class Context:
             _dev_ptr(g_f), _stream_ptr()))
 
     def batch(self, sizes, m, max_dim=1, threshold=float("inf"), keep_zero=False,
-              no_enclosing=False, host_reduction=False, autotune=False):
+              no_enclosing=False, host_reduction=False, autotune=False, device_reduction=False):
         return Batch(self, sizes, m, max_dim, threshold, keep_zero, no_enclosing, host_reduction,
-                     autotune)
+                     autotune, device_reduction)
 
 
 class Batch:
     """A batch plan: fixed cloud sizes, one captured graph replayed per forward."""
 
     def __init__(self, ctx, sizes, m, max_dim, threshold, keep_zero, no_enclosing,
-                 host_reduction=False, autotune=False):
+                 host_reduction=False, autotune=False, device_reduction=False):
         self.ctx = ctx
         self.sizes = np.ascontiguousarray(sizes, dtype=np.int64)
         flags = ((KEEP_ZERO_PERSISTENCE if keep_zero else 0)
                  | (NO_ENCLOSING_RADIUS if no_enclosing else 0)
                  | (HOST_REDUCTION if host_reduction else 0)
+                 | (DEVICE_REDUCTION if device_reduction else 0)
                  | (AUTOTUNE if autotune else 0))
         h = ctypes.c_void_p()
         _check(lib().vrph_batch_plan(ctx.h, self.sizes.ctypes.data_as(ctypes.c_void_p),

@@ -8,8 +8,11 @@ Workloads (synthetic, seeded; see synth.py):
   c2-all    the same, every pair reported (zero persistence included)
   c3        1024 random O(3) matrices in R^9, threshold 1.8, dimensions 0-3
   c4        256 clouds of 50-400 points (noisy circles and tori), dimensions
-            0-1, one batch forward (dimension 1 reduced on the device)
+            0-1, one batch forward (dimension 1 reduced on the device, the
+            clouds the cost model deems heaviest on host threads beside it)
   c5        64 noisy tori of 500 points, dimensions 0-1, one batch forward
+  c4-device, c5-device
+            the same batches with every cloud reduced on the device
   c4-host, c5-host
             the same batches with dimension 1 reduced on host threads
   o3-4096   4096 random O(3) matrices, threshold 1.4, dimensions 0-3 (the
@@ -82,7 +85,7 @@ def run(names=None, reps=3):
             nn = int(name[4:])
             single(name, dev(synth.uniform_cube(nn, 3, seed=nn)), max_dim=cfg["max_dim"],
                    threshold=cfg["threshold"], autotune=True)
-    for name in ("c4", "c4-host", "c5", "c5-host"):
+    for name in ("c4", "c4-device", "c4-host", "c5", "c5-device", "c5-host"):
         if name not in want:
             continue
         if name.startswith("c4"):
@@ -90,7 +93,8 @@ def run(names=None, reps=3):
         else:
             clouds = synth.torus_batch(64, 500, 0.1, seed=0)
         b = ctx.batch([len(c) for c in clouds], 3, max_dim=1,
-                      host_reduction=name.endswith("-host"))
+                      host_reduction=name.endswith("-host"),
+                      device_reduction=name.endswith("-device"))
         Xb = dev(np.concatenate(clouds))
         ms, res = _timed(lambda: b.forward(Xb), reps)
         rec = {"workload": name, "ms": ms, "stats": res[0].stats,

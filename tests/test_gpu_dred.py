@@ -1,5 +1,7 @@
 """The dimension-1 submatrix reduction on the device (batches) against the
-host reduction of the same columns and against the oracle.
+host reduction of the same columns and against the oracle, and the split
+forward (the clouds the cost model picks reduced on host threads while the
+device reduces the others) against both.
 
 Pairs (with their edges), the additions made and the columns paired without
 any addition must be the same as on the host, which makes the same
@@ -56,14 +58,30 @@ def lattice(k, jitter_seed=None):
 
 
 def run_both(ctx, clouds, **kw):
-    dev = ctx.batch([len(c) for c in clouds], 3, max_dim=1, **kw)
-    host = ctx.batch([len(c) for c in clouds], 3, max_dim=1, host_reduction=True, **kw)
+    """Device-only and host-only reductions of the same batch; the split
+    forward is checked against the host one here too."""
+    sizes = [len(c) for c in clouds]
+    dev = ctx.batch(sizes, 3, max_dim=1, device_reduction=True, **kw)
+    host = ctx.batch(sizes, 3, max_dim=1, host_reduction=True, **kw)
+    split = ctx.batch(sizes, 3, max_dim=1, **kw)
     try:
         Xp = packed(clouds)
-        return dev.forward(Xp), host.forward(Xp)
+        rd, rh = dev.forward(Xp), host.forward(Xp)
+        for _ in range(2):  # the second forward uses the ratio the first measured
+            check_split(split.forward(Xp), rh)
+        return rd, rh
     finally:
         dev.close()
         host.close()
+        split.close()
+
+
+def check_split(rs, rh):
+    for i, (a, b) in enumerate(zip(rs, rh)):
+        assert np.array_equal(a.pairs, b.pairs), f"cloud {i}: pairs differ (split)"
+        assert a.stats["reduced"] == b.stats["reduced"], i
+        assert a.stats["additions"] == b.stats["additions"], i
+        assert a.stats["emergent"] == b.stats["emergent"], i
 
 
 def check_same(rd, rh, expect_device=True):
@@ -106,8 +124,9 @@ def test_device_matches_host_and_oracle(ctx, case):
 
 def test_replays_return_to_a_clean_state(ctx):
     sizes = [120, 45, 200, 80]
-    dev = ctx.batch(sizes, 3, max_dim=1)
+    dev = ctx.batch(sizes, 3, max_dim=1, device_reduction=True)
     host = ctx.batch(sizes, 3, max_dim=1, host_reduction=True)
+    split = ctx.batch(sizes, 3, max_dim=1)
     try:
         for seed in range(4):
             rng = np.random.default_rng(100 + seed)
@@ -115,21 +134,25 @@ def test_replays_return_to_a_clean_state(ctx):
             Xp = packed(clouds)
             rd, rh = dev.forward(Xp), host.forward(Xp)
             check_same(rd, rh)
+            check_split(split.forward(Xp), rh)
     finally:
         dev.close()
         host.close()
+        split.close()
 
 
 @pytest.mark.parametrize("caps,expect_device", [("16,4,0", True), ("0,0,8", False)],
                          ids=["logs_overflow", "arena_overflow"])
-def test_overflow_paths(ctx, caps, expect_device):
+@pytest.mark.parametrize("device_only", [True, False], ids=["device", "split"])
+def test_overflow_paths(ctx, caps, expect_device, device_only):
     """Tiny toggle and V logs: the bitmaps are cleared whole and V is read
     whole, still on the device. A tiny V arena: the clouds that outgrow it
-    are reduced on the host. The pairs are the same either way."""
+    are reduced on the host. The pairs are the same either way, also when
+    the split forward gives some clouds to host threads from the start."""
     clouds = synth.torus_batch(4, 150, 0.1, seed=8)
     os.environ["VRPH_DRED_TEST_CAPS"] = caps
     try:
-        dev = ctx.batch([len(c) for c in clouds], 3, max_dim=1)
+        dev = ctx.batch([len(c) for c in clouds], 3, max_dim=1, device_reduction=device_only)
     finally:
         del os.environ["VRPH_DRED_TEST_CAPS"]
     host = ctx.batch([len(c) for c in clouds], 3, max_dim=1, host_reduction=True)
@@ -137,11 +160,14 @@ def test_overflow_paths(ctx, caps, expect_device):
         Xp = packed(clouds)
         for _ in range(2):  # and the state left behind is clean for the next forward
             rd, rh = dev.forward(Xp), host.forward(Xp)
-            check_same(rd, rh, expect_device=expect_device)
-            flags = [r.stats["device_reduced"] for r in rd]
-            if expect_device:
-                assert all(flags)
+            if device_only:
+                check_same(rd, rh, expect_device=expect_device)
             else:
+                check_split(rd, rh)
+            flags = [r.stats["device_reduced"] for r in rd]
+            if expect_device and device_only:
+                assert all(flags)
+            elif not expect_device:
                 assert not all(flags), "no cloud outgrew the 8-entry arena"
     finally:
         dev.close()
@@ -150,10 +176,20 @@ def test_overflow_paths(ctx, caps, expect_device):
 
 def test_c5_device_matches_host(ctx):
     """The differentiable workload at full size (64 tori x 500 points): the
-    same pairs, additions and emergent counts on the device as on the host."""
+    same pairs, additions and emergent counts on the device as on the host,
+    and in the split forward, which gives some of the clouds to the host
+    threads and leaves the others on the device."""
     clouds = synth.torus_batch(64, 500, 0.1, seed=0)
     rd, rh = run_both(ctx, clouds)
     check_same(rd, rh)
+    split = ctx.batch([len(c) for c in clouds], 3, max_dim=1)
+    try:
+        rs = split.forward(packed(clouds))
+        check_split(rs, rh)
+        on_device = sum(r.stats["device_reduced"] for r in rs)
+        assert 0 < on_device < len(clouds), on_device
+    finally:
+        split.close()
 
 
 def test_batch_autotune(ctx, tmp_path):
@@ -230,3 +266,11 @@ def test_every_workgroup_size_matches_host(tmp_path, threads):
         assert rd[0].stats["grid"][1] == 4 * torch.cuda.get_device_properties(0).multi_processor_count
     finally:
         c.close()
+
+
+def test_reduction_flags_exclude_each_other(ctx):
+    from paper_2502_05063_amd import vrph
+
+    with pytest.raises(vrph.VrphError) as ei:
+        ctx.batch([50, 60], 3, max_dim=1, host_reduction=True, device_reduction=True)
+    assert ei.value.status == vrph.EINVAL
