@@ -12,6 +12,7 @@ kernel, the oracle baseline and the batched forward+backward comparison.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -199,6 +200,9 @@ def batched_vs_plain(ctx, steps, cpu_leg=True):
                      ("batched_host_reduction", batched_leg("batched_host_reduction")),
                      ("plain", plain)):
         fn()
+        # the garbage of earlier legs is collected before, not inside, the
+        # timed steps (the collector stays on while they run)
+        gc.collect()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(steps):
@@ -369,6 +373,7 @@ def main():
         # in the context and reused by every later step
         bc = ctx.barcode(X=Xd, max_dim=max_dim, autotune=(i == 0))
         print(f"warmup {i}: {bc.stats['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+    gc.collect()  # before, not inside, the timed steps (the collector stays on)
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()

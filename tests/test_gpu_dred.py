@@ -274,3 +274,22 @@ def test_reduction_flags_exclude_each_other(ctx):
     with pytest.raises(vrph.VrphError) as ei:
         ctx.batch([50, 60], 3, max_dim=1, host_reduction=True, device_reduction=True)
     assert ei.value.status == vrph.EINVAL
+
+
+@pytest.mark.parametrize("count", [1, 2, 3])
+def test_split_small_batches(ctx, count):
+    """Batches of one to three clouds: whatever the split picks (possibly
+    every cloud on one side), three forwards in a row give the host
+    reduction's pairs and counts."""
+    clouds = synth.torus_batch(count, 300, 0.1, seed=20 + count)
+    sizes = [len(c) for c in clouds]
+    host = ctx.batch(sizes, 3, max_dim=1, host_reduction=True)
+    split = ctx.batch(sizes, 3, max_dim=1)
+    try:
+        Xp = packed(clouds)
+        rh = host.forward(Xp)
+        for _ in range(3):
+            check_split(split.forward(Xp), rh)
+    finally:
+        host.close()
+        split.close()
