@@ -1371,6 +1371,11 @@ extern "C" vrph_status vrph_boundary_pivots(vrph_ctx* c, int64_t ncols, const in
 // batched point clouds
 // ---------------------------------------------------------------------------
 
+// starting host-to-device time ratio of a batch's split (one host thread's
+// time per unit of estimated cost over the device's, measured on the 64-torus
+// batch)
+constexpr double kSplitRatio0 = 0.35;
+
 struct vrph_batch {
   vrph_ctx* ctx = nullptr;
   int count = 0, m = 0, max_dim = 0, max_n = 0;
@@ -1401,7 +1406,7 @@ struct vrph_batch {
   // split_ratio: host-thread time per unit of estimated cost over the device
   // time per unit, updated from the times each split forward measures.
   bool split = false;
-  double split_ratio = 0.35;
+  double split_ratio = kSplitRatio0;
   // per cloud, the previous forward's dimension-1 columns and additions
   std::vector<int64_t> last_cols, last_add;
   DevBuf dskip;
@@ -2084,13 +2089,20 @@ extern "C" vrph_status vrph_batch_forward(vrph_batch* b, const float* X_packed, 
     if (more_w) HIP_TRY(hipStreamSynchronize(s));
     run_pool(n_host, b->count);
     tail_ms = now_ms() - t2;
-    // the host-to-device time ratio, from what this forward measured
-    if (n_host > 0 && n_host < b->count && host_est > 0 && dev_est > 0 && back_ms > 1.0 &&
-        host_split_ms > 1.0) {
-      const double dev_rate = back_ms / dev_est;
-      const double host_rate = host_split_ms / (host_est / b->split_ratio);
-      const double r = std::sqrt(b->split_ratio * (host_rate / dev_rate));
-      b->split_ratio = std::min(50.0, std::max(0.02, r));
+    // the host-to-device time ratio, from what this forward measured; a
+    // forward that left one side without clouds measures nothing, and the
+    // ratio then moves back toward its starting value, so that one odd
+    // measurement cannot keep every cloud on one side for good
+    if (b->split) {
+      if (n_host > 0 && n_host < b->count && host_est > 0 && dev_est > 0 && back_ms > 1.0 &&
+          host_split_ms > 1.0) {
+        const double dev_rate = back_ms / dev_est;
+        const double host_rate = host_split_ms / (host_est / b->split_ratio);
+        const double r = std::sqrt(b->split_ratio * (host_rate / dev_rate));
+        b->split_ratio = std::min(50.0, std::max(0.02, r));
+      } else if (n_host == 0 || n_host == b->count) {
+        b->split_ratio = std::sqrt(b->split_ratio * kSplitRatio0);
+      }
     }
   }
   const double host_ms = host_split_ms + tail_ms;
