@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvrph.so")
 
-SOURCES = ["kernels.hip", "sort.hip", "boundary.hip", "reduce_dev.hip", "graph_ext.hip", "noalloc.hip", "reduce.cpp", "vrph_api.cpp"]
+SOURCES = ["kernels.hip", "sort.hip", "edges.hip", "boundary.hip", "reduce_dev.hip", "graph_ext.hip", "noalloc.hip", "reduce.cpp", "vrph_api.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -35,22 +35,20 @@ void decode_simplex(const HostComplex& H, uint64_t c, int d, int* v) {
   v[0] = (int)c;
 }
 
-static uint32_t diameter_of(const HostComplex& H, const int* v, int d) {
-  uint32_t m = 0;
-  for (int i = 1; i <= d; ++i)
-    for (int j = 0; j < i; ++j) m = std::max(m, H.w(v[i], v[j]));
-  return m;
-}
-
 void diameter_edge(const HostComplex& H, uint64_t c, int d, int32_t* u, int32_t* w) {
   int v[kMaxDim + 3];
   decode_simplex(H, c, d, v);
-  uint32_t dm = diameter_of(H, v, d);
+  // weights, or their ranks when only those are here: the same order and
+  // the same ties
+  auto wt = [&](int a, int b) { return H.W ? H.w(a, b) : H.wr(a, b); };
+  uint32_t dm = 0;
+  for (int i = 1; i <= d; ++i)
+    for (int j = 0; j < i; ++j) dm = std::max(dm, wt(v[i], v[j]));
   uint64_t best = 0;
   bool have = false;
   for (int i = 1; i <= d; ++i)
     for (int j = 0; j < i; ++j)
-      if (H.w(v[i], v[j]) == dm) {
+      if (wt(v[i], v[j]) == dm) {
         uint64_t e = H.C(v[i], 2) + (uint64_t)v[j];
         if (!have || e > best) {
           best = e;
@@ -1373,6 +1371,7 @@ void reduce_dimension(const HostComplex& H, int d, const Column* cols, int64_t n
 // pattern, which orders non-negative floats), and equal weights share a rank.
 void RankTable::build(int n, const uint32_t* W) {
   const size_t nn = (size_t)n * (size_t)n;
+  tracked_n = 0;  // every entry is rewritten here
   bits.clear();
   // the n x n fill and the scan of the lower triangle run on several
   // threads for large clouds (row blocks; the edges are concatenated in row
@@ -1425,6 +1424,47 @@ void RankTable::build(int n, const uint32_t* W) {
     nb[(size_t)b * nbw + (a >> 6)] |= 1ull << (a & 63);
   }
   sparse = (uint64_t)e.size() * 4 < (uint64_t)n * (uint64_t)(n - 1) / 2;
+}
+
+void RankTable::build_from_edges(int n, const Column* e, size_t m) {
+  const size_t nn = (size_t)n * (size_t)n;
+  if (tracked_n == n && Wr.size() == nn) {
+    // undo the previous build's entries; every neighbour bit it set belongs
+    // to one of them, so their words go back to zero whole
+    for (uint64_t p : last) {
+      const size_t a = (size_t)(p >> 32), b = (size_t)(uint32_t)p;
+      Wr[a * n + b] = Wr[b * n + a] = kInf;
+      nb[a * (size_t)nbw + (b >> 6)] = 0;
+      nb[b * (size_t)nbw + (a >> 6)] = 0;
+    }
+  } else {
+    Wr.resize(nn);
+    const int nt = n >= 2048 ? (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency())) : 1;
+    auto fill = [&](int t) {
+      const size_t r0 = (size_t)n * (size_t)t / (size_t)nt, r1 = (size_t)n * (size_t)(t + 1) / (size_t)nt;
+      std::fill(Wr.begin() + (std::ptrdiff_t)(r0 * n), Wr.begin() + (std::ptrdiff_t)(r1 * n), kInf);
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(fill, t);
+    fill(0);
+    for (std::thread& th : pool) th.join();
+    nbw = (n + 63) / 64;
+    nb.assign((size_t)n * (size_t)nbw, 0);
+  }
+  bits.clear();
+  last.resize(m);
+  for (size_t k = 0; k < m; ++k) {
+    const uint32_t w = e[k].key_hi;
+    if (bits.empty() || bits.back() != w) bits.push_back(w);
+    const uint32_t r = (uint32_t)(bits.size() - 1);
+    const size_t a = (size_t)(e[k].cidx >> 32), b = (size_t)(uint32_t)e[k].cidx;
+    Wr[a * n + b] = Wr[b * n + a] = r;
+    nb[a * (size_t)nbw + (b >> 6)] |= 1ull << (b & 63);
+    nb[b * (size_t)nbw + (a >> 6)] |= 1ull << (a & 63);
+    last[k] = e[k].cidx;
+  }
+  sparse = (uint64_t)m * 4 < (uint64_t)n * (uint64_t)(n - 1) / 2;
+  tracked_n = n;
 }
 
 }  // namespace vrph

@@ -11,7 +11,9 @@ namespace vrph {
 // Read-only view of one cloud's filtration data on the host.
 struct HostComplex {
   int n = 0;
-  const uint32_t* W = nullptr;      // n x n weights (float bits, kInf above tau_eff)
+  // n x n weights (float bits, kInf above tau_eff); may be null once Wr is
+  // attached (the weights are then rank_bits[Wr])
+  const uint32_t* W = nullptr;
   // Ranks of the same weights among the distinct finite ones (kInf stays
   // kInf) and the weight of each rank; filled by build_ranks. Only the
   // reduction reads them.
@@ -42,6 +44,15 @@ struct RankTable {
   int nbw = 0;
   bool sparse = false;         // fewer than a quarter of the edges are finite
   void build(int n, const uint32_t* W);
+  // The same table from the m finite edges of the lower triangle, sorted by
+  // weight: e[k].key_hi = weight bits, e[k].cidx = a << 32 | b with a > b.
+  // When the previous build was this one at the same n, only the entries it
+  // wrote are reset (O(m) instead of O(n^2)).
+  void build_from_edges(int n, const Column* e, size_t m);
+  // entries written by the last build_from_edges (a << 32 | b), valid while
+  // tracked_n == n
+  std::vector<uint64_t> last;
+  int tracked_n = 0;
   void attach(HostComplex& H) const {
     H.Wr = Wr.data();
     H.rank_bits = bits.data();

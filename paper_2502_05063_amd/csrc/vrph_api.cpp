@@ -203,6 +203,10 @@ double now_ms() {
 // units pay off where a threshold skips most prefixes
 constexpr int kMaxChunk = 1 << 17;
 
+// clouds from this size on may hand the host their finite edges instead of
+// the n x n weights (when their complex is sparse)
+constexpr int64_t kEdgeListMinN = 2048;
+
 struct Tune {
   int chunk;
   int mult;
@@ -227,6 +231,10 @@ struct vrph_ctx {
   uint64_t pair_cap = 0;   // apparent pairs the buffers are sized for
   HostPinned h_scal, h_cstate;
   HostPinned h_Wn;   // a single cloud's weights on the host (n x n)
+  // or, for a large sparse cloud, its finite edges sorted by weight: device
+  // records, the sort's spare buffer and work space, the count, host copies
+  DevBuf fe_cols, fe_tmp, fe_work, fe_count;
+  HostPinned h_fe, h_fe_count;
   RankTable ranks;   // its weight ranks (host reduction, LDS kernels)
   std::vector<uint64_t> h_binom;
   int binom_n = -1, binom_k = -1;
@@ -348,12 +356,15 @@ extern "C" void vrph_destroy(vrph_ctx* c) {
                     &c->pfx_v,     &c->pfx_cum,  &c->bscan,  &c->h0w,
                     &c->bflag,     &c->g_off,    &c->g_lower, &c->g_upper, &c->g_tmp,
                     &c->g_pos,     &c->g_adj_off, &c->g_adj, &c->g_stack,  &c->g_err,
-                    &c->fcols,     &c->fctr,      &c->fpacked, &c->fspare, &c->fsort_work};
+                    &c->fcols,     &c->fctr,      &c->fpacked, &c->fspare, &c->fsort_work,
+                    &c->fe_cols,   &c->fe_tmp,    &c->fe_work, &c->fe_count};
   for (DevBuf* b : bufs) b->release();
   for (DevBuf& b : c->hset) b.release();
   c->h_scal.release();
   c->h_cstate.release();
   c->h_Wn.release();
+  c->h_fe.release();
+  c->h_fe_count.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->ev2) (void)hipEventDestroy(c->ev2);
@@ -618,13 +629,36 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   }
   HIP_TRY(hipEventRecord(c->ev1, s));
   CloudState cs;
+  // A large cloud whose complex is sparse (fewer than half of the vertex
+  // pairs within the threshold) sends the host its finite edges sorted by
+  // weight instead of the n x n weights, and the host builds its rank table
+  // from them in O(edges) (VRPH_DENSE_HOST_WEIGHTS in the environment keeps
+  // the matrix, for comparing the two). The finite entries are counted on
+  // the device first.
+  const uint64_t n_pairs = (uint64_t)n * (uint64_t)(n - 1) / 2;
+  const bool count_edges =
+      max_dim >= 1 && n >= kEdgeListMinN && !std::getenv("VRPH_DENSE_HOST_WEIGHTS");
+  if (count_edges) {
+    HIP_TRY(c->fe_count.ensure(sizeof(unsigned long long)));
+    HIP_TRY(c->h_fe_count.ensure(sizeof(unsigned long long)));
+    HIP_TRY(hipMemsetAsync(c->fe_count.p, 0, sizeof(unsigned long long), s));
+    HIP_TRY(launch_finite_edges(c->W.as<uint32_t>(), (int)n, nullptr, 0,
+                                c->fe_count.as<unsigned long long>(), s));
+    HIP_TRY(hipMemcpyAsync(c->h_fe_count.p, c->fe_count.p, sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s));
+  }
   HIP_TRY(hipMemcpyAsync(c->h_cstate.p, c->cstate.p, sizeof(CloudState), hipMemcpyDeviceToHost, s));
   // the weights on the host, in a pinned buffer the context keeps (no page
   // faults or zero fill per call, and the copy is a straight DMA)
-  HIP_TRY(c->h_Wn.ensure((size_t)n * n * 4));
-  uint32_t* const hW = c->h_Wn.as<uint32_t>();
+  uint32_t* hW = nullptr;
+  auto copy_weights = [&]() -> hipError_t {
+    hipError_t e = c->h_Wn.ensure((size_t)n * n * 4);
+    if (e != hipSuccess) return e;
+    hW = c->h_Wn.as<uint32_t>();
+    return hipMemcpyAsync(hW, c->W.p, (size_t)n * n * 4, hipMemcpyDeviceToHost, s);
+  };
+  if (!count_edges) HIP_TRY(copy_weights());
   std::vector<H0Pair> h0(n);
-  HIP_TRY(hipMemcpyAsync(hW, c->W.p, (size_t)n * n * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(h0.data(), c->h0.p, (size_t)n * sizeof(H0Pair), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   std::memcpy(&cs, c->h_cstate.p, sizeof(cs));
@@ -635,10 +669,39 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
                                  ((cs.err & 8) ? " nonzero diagonal" : "") +
                                  ((cs.err & 16) ? " entry index out of range or on the diagonal" : "") +
                                  ((cs.err & 32) ? " repeated pair" : ""));
-  H.W = hW;
+  RankTable& ranks = c->ranks;  // its storage is reused across calls
+  uint64_t n_finite = 0;
+  bool edge_list = false;
+  const Column* fe = nullptr;  // the finite edges, sorted by weight (edge-list mode)
+  if (count_edges) {
+    std::memcpy(&n_finite, c->h_fe_count.p, sizeof(n_finite));
+    edge_list = 2 * n_finite < n_pairs;
+    if (edge_list) {
+      const size_t m = (size_t)std::max<uint64_t>(n_finite, 1);
+      HIP_TRY(c->fe_cols.ensure(m * sizeof(Column)));
+      HIP_TRY(c->fe_tmp.ensure(m * sizeof(Column)));
+      HIP_TRY(c->fe_work.ensure(radix_sort_work_bytes((int64_t)m)));
+      HIP_TRY(c->h_fe.ensure(m * sizeof(Column)));
+      HIP_TRY(hipMemsetAsync(c->fe_count.p, 0, sizeof(unsigned long long), s));
+      HIP_TRY(launch_finite_edges(c->W.as<uint32_t>(), (int)n, c->fe_cols.as<Column>(), n_finite,
+                                  c->fe_count.as<unsigned long long>(), s));
+      bool in_tmp = false;
+      HIP_TRY(radix_sort_columns(c->fe_cols.as<Column>(), c->fe_tmp.as<Column>(), (int64_t)n_finite,
+                                 0, 0, c->fe_work.p, s, nullptr, &in_tmp));
+      HIP_TRY(hipMemcpyAsync(c->h_fe.p, in_tmp ? c->fe_tmp.p : c->fe_cols.p,
+                             (size_t)n_finite * sizeof(Column), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      fe = c->h_fe.as<Column>();
+      ranks.build_from_edges((int)n, fe, (size_t)n_finite);
+      ranks.attach(H);
+    } else {
+      HIP_TRY(copy_weights());
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+  }
+  H.W = hW;  // null in edge-list mode: the host reads ranks only
   // Weight ranks: needed by the host reduction and, for small clouds, by the
   // LDS enumeration kernels (16-bit ranks: C(kLdsMaxN, 2) < 0xFFFF).
-  RankTable& ranks = c->ranks;  // its storage is reused across calls
   std::vector<uint16_t> h_wr16;
   const bool use_lds = max_dim >= 2 && n <= kLdsMaxN && !(flags & VRPH_NO_LDS);
   if (use_lds) {
@@ -669,7 +732,9 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   // (launch_edges_nb).
   std::vector<uint32_t> pfx2, pfx3;
   bool sparse_edges = false;
-  if (max_dim >= 1 && n >= 3) {
+  if (count_edges) {
+    sparse_edges = edge_list;
+  } else if (max_dim >= 1 && n >= 3) {
     // the lower triangle's finite entries, rows interleaved over threads
     std::atomic<uint64_t> valid{0};
     const int nt = n >= 2048 ? host_threads() : 1;
@@ -689,10 +754,28 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   if (max_dim >= 2 && n >= 3 && !use_lds) {
     if (sparse_edges) {
       for (int v2 = n - 1; v2 >= 2; --v2) pfx2.push_back((uint32_t)v2);
-      if (max_dim >= 3)
+      if (max_dim >= 3 && fe) {
+        // the edges (v3 > v2 >= 2), v2 descending and v3 ascending: two
+        // stable counting passes over the edge list, by v3 then by v2
+        std::vector<uint32_t> tmp, cnt((size_t)n + 1);
+        for (size_t k = 0; k < (size_t)n_finite; ++k)
+          if ((uint32_t)fe[k].cidx >= 2) ++cnt[(size_t)(fe[k].cidx >> 32) + 1];
+        for (size_t v = 1; v <= (size_t)n; ++v) cnt[v] += cnt[v - 1];
+        tmp.resize(cnt[(size_t)n]);
+        for (size_t k = 0; k < (size_t)n_finite; ++k) {
+          const uint32_t v3 = (uint32_t)(fe[k].cidx >> 32), v2 = (uint32_t)fe[k].cidx;
+          if (v2 >= 2) tmp[cnt[v3]++] = (v3 << 16) | v2;
+        }
+        std::fill(cnt.begin(), cnt.end(), 0u);
+        for (uint32_t e : tmp) ++cnt[(size_t)(n - 1 - (int)(e & 0xFFFF)) + 1];
+        for (size_t v = 1; v <= (size_t)n; ++v) cnt[v] += cnt[v - 1];
+        pfx3.resize(tmp.size());
+        for (uint32_t e : tmp) pfx3[cnt[(size_t)(n - 1 - (int)(e & 0xFFFF))]++] = e;
+      } else if (max_dim >= 3) {
         for (int v2 = n - 2; v2 >= 2; --v2)
           for (int v3 = v2 + 1; v3 < n; ++v3)  // row v2 (W is symmetric): contiguous
             if (hW[(size_t)v2 * n + v3] != kInf) pfx3.push_back(((uint32_t)v3 << 16) | (uint32_t)v2);
+      }
       HIP_TRY(c->pfx_v.ensure(std::max<size_t>(pfx2.size() + pfx3.size(), 1) * sizeof(uint32_t)));
       if (!pfx2.empty())
         HIP_TRY(hipMemcpyAsync(c->pfx_v.p, pfx2.data(), pfx2.size() * sizeof(uint32_t),

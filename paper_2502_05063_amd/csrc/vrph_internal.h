@@ -334,6 +334,14 @@ hipError_t noalloc_scratch_setup(int device);
 // The address found by noalloc_scratch_setup, or NULL before it ran.
 uint32_t* noalloc_scratch(int device);
 
+// ---- edges.hip ----
+// The finite entries of the lower triangle of the n x n weights W, appended
+// to `out` as Column{weight bits, 0, a << 32 | b} (a > b) in no particular
+// order, at most `cap` of them; *count (zeroed by the caller) receives their
+// number, also past `cap`. out = nullptr only counts.
+hipError_t launch_finite_edges(const uint32_t* W, int n, Column* out, uint64_t cap,
+                               unsigned long long* count, hipStream_t s);
+
 // ---- sort.hip ----
 // Stable LSD radix sort of Column records ascending by (cloud, key_hi, cidx),
 // looking only at the low `cidx_bits` of cidx, all 32 bits of key_hi and the

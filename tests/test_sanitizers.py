@@ -1,7 +1,8 @@
 """The host code and the oracle under the address and undefined-behaviour
-sanitizers (no GPU): the host reduction (tests/host_reduce_driver.cpp) and
-the explicit-matrix reduction with compression
-(tests/explicit_reduce_driver.cpp) over reduce.cpp, and the C oracle
+sanitizers (no GPU): the host reduction (tests/host_reduce_driver.cpp), the
+explicit-matrix reduction with compression
+(tests/explicit_reduce_driver.cpp) and the rank table built from edge lists
+(tests/rank_table_driver.cpp) over reduce.cpp, and the C oracle
 (tests/oracle_driver.c), built with -fsanitize=address,undefined for the
 host only and run on small inputs on several thread counts. A report from
 either sanitizer (or a leak) fails the test; the results must still equal
@@ -37,7 +38,7 @@ def _hipcc():
 def drivers(tmp_path_factory):
     d = tmp_path_factory.mktemp("san")
     out = {}
-    for name in ("host_reduce_driver", "explicit_reduce_driver"):
+    for name in ("host_reduce_driver", "explicit_reduce_driver", "rank_table_driver"):
         exe = str(d / name)
         cmd = [_hipcc(), "-O1", "-g", "-std=c++17", *HOST_SAN, "-I", os.path.join(ROOT, "include"),
                "-I", CSRC, os.path.join(HERE, name + ".cpp"), os.path.join(CSRC, "reduce.cpp"),
@@ -114,3 +115,22 @@ def test_oracle_clean(drivers, tmp_path, n, max_dim, thr):
     _write_dist(path, D)
     out = _run([drivers["oracle_driver"], path, str(max_dim), thr])
     assert int(out.split()[0]) == len(oracle.barcode(D, max_dim, float(thr)))
+
+
+def test_rank_table_from_edges_clean(drivers, tmp_path):
+    """The edge-list rank table over a sequence of matrices (same size twice,
+    then a size change), checked against the matrix-built table."""
+    paths = []
+    for i, (n, thr, seed) in enumerate([(200, 0.3, 1), (200, 0.2, 2), (90, 0.5, 3)]):
+        rng = np.random.default_rng(seed)
+        X = rng.random((n, 3))
+        D = np.sqrt(((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)).astype(np.float32)
+        W = D.view(np.uint32).copy()
+        W[D > np.float32(thr)] = np.uint32(0xFFFFFFFF)
+        np.fill_diagonal(W, np.uint32(0xFFFFFFFF))
+        p = str(tmp_path / f"w{i}.bin")
+        with open(p, "wb") as f:
+            f.write(np.int32(n).tobytes())
+            f.write(W.tobytes())
+        paths.append(p)
+    assert _run([drivers["rank_table_driver"], *paths]).strip() == "ok"
