@@ -205,7 +205,7 @@ constexpr int kMaxChunk = 1 << 17;
 
 // clouds from this size on may hand the host their finite edges instead of
 // the n x n weights (when their complex is sparse)
-constexpr int64_t kEdgeListMinN = 2048;
+constexpr int64_t kEdgeListMinN = 512;
 
 struct Tune {
   int chunk;

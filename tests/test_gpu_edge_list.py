@@ -1,4 +1,4 @@
-"""Large sparse clouds (2048 points and more, fewer than half of the vertex
+"""Large sparse clouds (512 points and more, fewer than half of the vertex
 pairs within the threshold) hand the host their finite edges sorted by
 weight instead of the n x n weights. On one context, over a sequence of
 clouds and thresholds (the same size twice in a row, so that the host's
