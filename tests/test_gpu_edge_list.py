@@ -41,7 +41,7 @@ def test_edge_list_matches_matrix_path():
     ctx = vrph.Context()
     try:
         seq = [(2500, 0.08, 1, 2), (2500, 0.06, 2, 2), (2048, 2.0, 3, 1), (3000, 0.07, 4, 3),
-               (3000, 0.075, 5, 1), (2500, 0.09, 6, 2)]
+               (3000, 0.075, 5, 1), (700, 0.15, 7, 3), (700, 0.12, 8, 2), (2500, 0.09, 6, 2)]
         for n, thr, seed, max_dim in seq:
             X = synth.uniform_cube(n, 3, seed=seed)
             kw = dict(max_dim=max_dim, threshold=thr, keep_zero=True)
