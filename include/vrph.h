@@ -190,7 +190,12 @@ vrph_status vrph_pdist(vrph_ctx* ctx, const float* X, int64_t n, int32_t m, floa
  * zero diagonal (VRPH_EINVAL otherwise; the triangle inequality is not
  * required, Sec. 5.6.6). 1 <= n <= 16384 (the n x n weights take 4 n^2
  * bytes of device memory, 1 GiB at 16384), 0 <= max_dim <= VRPH_MAX_DIM,
- * threshold >= 0 or +inf. */
+ * threshold >= 0 or +inf. The host reduction receives the weights as the
+ * n x n matrix, or, for a cloud of 512 points or more whose complex is
+ * sparse (fewer than half of the vertex pairs within the threshold), as
+ * its finite edges sorted by weight (16 bytes each); the environment
+ * variable VRPH_DENSE_HOST_WEIGHTS, when set, keeps the matrix in every
+ * case (the results are the same). */
 vrph_status vrph_barcode_from_dist(vrph_ctx* ctx, const float* D, int64_t n, int32_t max_dim,
                                    float threshold, uint32_t flags, void* hip_stream,
                                    vrph_barcode** out);
