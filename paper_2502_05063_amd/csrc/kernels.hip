@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void batch_validate_kernel(const float* __r
                                                                 const Cloud* __restrict__ clouds,
                                                                 int count,
                                                                 CloudState* __restrict__ st,
-                                                                int allow_inf) {
+                                                                int allow_inf, int check_sym) {
   __shared__ uint32_t red[kBlock / 64];
   __shared__ uint32_t errs;
   const int64_t row = blockIdx.x;
@@ -192,7 +192,9 @@ __global__ __launch_bounds__(kBlock) void batch_validate_kernel(const float* __r
     // takes part in the row maximum of the enclosing radius
     if (!isfinite(x) && !(allow_inf && x == INFINITY)) err |= 1u;
     if (x < 0.0f) err |= 2u;
-    if (x != D[cl.w_off + (int64_t)j * cl.n + i]) err |= 4u;
+    // (column reads: skipped where D is pdist's own output, symmetric by
+    // construction)
+    if (check_sym && x != D[cl.w_off + (int64_t)j * cl.n + i]) err |= 4u;
     if (j == i && x != 0.0f) err |= 8u;
     uint32_t k = float_key(x);
     if (!isnan(x) && x >= 0.0f && k > mx) mx = k;
@@ -214,7 +216,9 @@ __global__ __launch_bounds__(kBlock) void batch_weights_kernel(const float* __re
                                                                const Cloud* __restrict__ clouds,
                                                                int count, int enclosing,
                                                                uint32_t* __restrict__ W,
-                                                               CloudState* __restrict__ st) {
+                                                               CloudState* __restrict__ st,
+                                                               unsigned long long* __restrict__ finite_lower) {
+  __shared__ uint32_t lower[kBlock / 64];
   const int64_t row = blockIdx.x;
   const int c = find_cloud(clouds, count, row, &Cloud::x_off);
   const Cloud cl = clouds[c];
@@ -224,22 +228,38 @@ __global__ __launch_bounds__(kBlock) void batch_weights_kernel(const float* __re
   if (i == 0 && threadIdx.x == 0) st[c].tau_bits = tau;
   const float* Drow = D + cl.w_off + (int64_t)i * cl.n;
   uint32_t* Wrow = W + cl.w_off + (int64_t)i * cl.n;
+  uint32_t fin = 0;  // finite entries left of the diagonal
   for (int j = threadIdx.x; j < cl.n; j += blockDim.x) {
     uint32_t k = float_key(Drow[j]);
     // +inf (a pair that is not an edge of a sparse matrix) is never an edge
-    Wrow[j] = (j != i && k <= tau && k < 0x7F800000u) ? k : kInf;
+    const bool edge = j != i && k <= tau && k < 0x7F800000u;
+    Wrow[j] = edge ? k : kInf;
+    fin += (edge && j < i) ? 1u : 0u;
+  }
+  if (finite_lower) {
+    for (int o = 32; o > 0; o >>= 1) fin += (uint32_t)__shfl_xor(fin, o);
+    if ((threadIdx.x & 63) == 0) lower[threadIdx.x >> 6] = fin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += lower[w];
+      if (t) atomicAdd(finite_lower, (unsigned long long)t);
+    }
   }
 }
 
 hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, int count,
                                          int64_t total_points, bool enclosing, uint32_t* W,
-                                         CloudState* st, hipStream_t s, bool allow_inf) {
+                                         CloudState* st, hipStream_t s, bool allow_inf,
+                                         bool check_sym, unsigned long long* finite_lower) {
   if (total_points <= 0) return hipSuccess;
   if (total_points > kMaxGroups) return hipErrorInvalidValue;
   batch_validate_kernel<<<(unsigned)total_points, kBlock, 0, s>>>(D, clouds, count, st,
-                                                                  allow_inf ? 1 : 0);
+                                                                  allow_inf ? 1 : 0,
+                                                                  check_sym ? 1 : 0);
   batch_weights_kernel<<<(unsigned)total_points, kBlock, 0, s>>>(D, clouds, count,
-                                                                 enclosing ? 1 : 0, W, st);
+                                                                 enclosing ? 1 : 0, W, st,
+                                                                 finite_lower);
   return hipGetLastError();
 }
 

@@ -543,9 +543,11 @@ struct SparseInput {
 
 // D: the dense n x n matrix, or, with sp, the context's buffer that the
 // sparse entries are written into first (+inf where a pair is not given).
+// d_from_pdist: D is pdist's own output (symmetric by construction, so its
+// validation skips the symmetry check)
 static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim, float threshold,
                                 uint32_t flags, hipStream_t s, vrph_barcode** out,
-                                const SparseInput* sp = nullptr) {
+                                const SparseInput* sp = nullptr, bool d_from_pdist = false) {
   const double t_start = now_ms();
   const bool keep_zero = flags & VRPH_KEEP_ZERO_PERSISTENCE;
   const int kmax = max_dim + 2;
@@ -612,10 +614,27 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   if (sp)
     HIP_TRY(launch_sparse_matrix(sp->row, sp->col, sp->val, sp->nnz, n, const_cast<float*>(D),
                                  c->cstate.as<CloudState>(), s));
+  // A large cloud whose complex is sparse (fewer than half of the vertex
+  // pairs within the threshold) sends the host its finite edges sorted by
+  // weight instead of the n x n weights, and the host builds its rank table
+  // from them in O(edges) (VRPH_DENSE_HOST_WEIGHTS in the environment keeps
+  // the matrix, for comparing the two). The weights kernel counts the
+  // finite pairs.
+  const uint64_t n_pairs = (uint64_t)n * (uint64_t)(n - 1) / 2;
+  const bool count_edges =
+      max_dim >= 1 && n >= kEdgeListMinN && !std::getenv("VRPH_DENSE_HOST_WEIGHTS");
+  if (count_edges) {
+    HIP_TRY(c->fe_count.ensure(sizeof(unsigned long long)));
+    HIP_TRY(c->h_fe_count.ensure(sizeof(unsigned long long)));
+    HIP_TRY(hipMemsetAsync(c->fe_count.p, 0, sizeof(unsigned long long), s));
+  }
   HIP_TRY(hipEventRecord(c->ev0, s));
   HIP_TRY(launch_batch_validate_weights(D, c->clouds.as<Cloud>(), 1, n,
                                         !(flags & VRPH_NO_ENCLOSING_RADIUS), c->W.as<uint32_t>(),
-                                        c->cstate.as<CloudState>(), s, sp != nullptr));
+                                        c->cstate.as<CloudState>(), s, sp != nullptr,
+                                        !d_from_pdist,
+                                        count_edges ? c->fe_count.as<unsigned long long>()
+                                                    : nullptr));
   // H0: one workgroup for small clouds; above kH0WideMin points the
   // Boruvka row scans are spread over the chip
   constexpr int kH0WideMin = 512;
@@ -629,24 +648,9 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
   }
   HIP_TRY(hipEventRecord(c->ev1, s));
   CloudState cs;
-  // A large cloud whose complex is sparse (fewer than half of the vertex
-  // pairs within the threshold) sends the host its finite edges sorted by
-  // weight instead of the n x n weights, and the host builds its rank table
-  // from them in O(edges) (VRPH_DENSE_HOST_WEIGHTS in the environment keeps
-  // the matrix, for comparing the two). The finite entries are counted on
-  // the device first.
-  const uint64_t n_pairs = (uint64_t)n * (uint64_t)(n - 1) / 2;
-  const bool count_edges =
-      max_dim >= 1 && n >= kEdgeListMinN && !std::getenv("VRPH_DENSE_HOST_WEIGHTS");
-  if (count_edges) {
-    HIP_TRY(c->fe_count.ensure(sizeof(unsigned long long)));
-    HIP_TRY(c->h_fe_count.ensure(sizeof(unsigned long long)));
-    HIP_TRY(hipMemsetAsync(c->fe_count.p, 0, sizeof(unsigned long long), s));
-    HIP_TRY(launch_finite_edges(c->W.as<uint32_t>(), (int)n, nullptr, 0,
-                                c->fe_count.as<unsigned long long>(), s));
+  if (count_edges)
     HIP_TRY(hipMemcpyAsync(c->h_fe_count.p, c->fe_count.p, sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, s));
-  }
   HIP_TRY(hipMemcpyAsync(c->h_cstate.p, c->cstate.p, sizeof(CloudState), hipMemcpyDeviceToHost, s));
   // the weights on the host, in a pinned buffer the context keeps (no page
   // faults or zero fill per call, and the copy is a straight DMA)
@@ -1177,7 +1181,8 @@ extern "C" vrph_status vrph_barcode_from_points(vrph_ctx* c, const float* X, int
   st = upload_single_cloud(c, (int)n, INFINITY, s);
   if (st) return st;
   HIP_TRY(launch_batch_pdist(X, m, c->clouds.as<Cloud>(), 1, n, c->D.as<float>(), s));
-  return barcode_impl(c, c->D.as<float>(), (int)n, max_dim, threshold, flags, s, out);
+  return barcode_impl(c, c->D.as<float>(), (int)n, max_dim, threshold, flags, s, out, nullptr,
+                      true);
 }
 
 extern "C" vrph_status vrph_barcode_from_sparse(vrph_ctx* c, int64_t n, int64_t nnz,
@@ -1749,9 +1754,10 @@ static hipError_t batch_record_front(vrph_batch* b, hipStream_t s) {
   if ((e = launch_batch_pdist(b->X.as<float>(), b->m, b->dclouds.as<Cloud>(), b->count,
                               b->total_points, b->D.as<float>(), s)))
     return e;
+  // (the clouds' D comes from pdist: symmetric by construction)
   if ((e = launch_batch_validate_weights(b->D.as<float>(), b->dclouds.as<Cloud>(), b->count,
                                          b->total_points, enclosing, b->W.as<uint32_t>(),
-                                         b->cstate.as<CloudState>(), s)))
+                                         b->cstate.as<CloudState>(), s, false, false)))
     return e;
   if ((e = launch_batch_h0(b->W.as<uint32_t>(), b->dclouds.as<Cloud>(), b->count,
                            b->cstate.as<CloudState>(), b->h0.as<H0Pair>(), b->max_n,

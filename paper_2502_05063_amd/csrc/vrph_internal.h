@@ -149,10 +149,17 @@ struct CloudState {
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);
 hipError_t launch_batch_pdist(const float* X, int m, const Cloud* clouds, int count,
                               int64_t total_points, float* D, hipStream_t s);
+// Validation of every cloud's D (finite unless allow_inf admits +inf, >= 0,
+// zero diagonal, and symmetric unless check_sym is off: D made by pdist is
+// symmetric by construction and the check reads columns) with the row
+// maxima of the enclosing radius, then the weights W; finite_lower (if not
+// null; zeroed by the caller) receives the number of finite weights below
+// the diagonal.
 hipError_t launch_batch_validate_weights(const float* D, const Cloud* clouds, int count,
                                          int64_t total_points, bool enclosing, uint32_t* W,
                                          CloudState* st, hipStream_t s,
-                                         bool allow_inf = false);
+                                         bool allow_inf = false, bool check_sym = true,
+                                         unsigned long long* finite_lower = nullptr);
 // Sparse input: D (n x n) <- +inf off the diagonal, 0 on it, then the nnz
 // given entries in both orientations; input errors are or-ed into st->err.
 hipError_t launch_sparse_matrix(const int32_t* row, const int32_t* col, const float* val,
