@@ -662,6 +662,25 @@ __global__ __launch_bounds__(kH0Threads) void h0w_scan_kernel(const uint32_t* __
   if (lane == 0 && mk != ~0ull) atomicMin(&w.best[cu], mk);
 }
 
+// The same minimum outgoing edge per component from a list of the finite
+// edges (records {weight bits, 0, a << 32 | b}): each edge between two
+// components offers its key to both. O(edges) a round instead of O(n^2).
+__global__ __launch_bounds__(kBlock) void h0w_scan_edges_kernel(const Column* __restrict__ e,
+                                                                int64_t m, H0Wide w) {
+  if (*w.done) return;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m;
+       k += (int64_t)gridDim.x * kBlock) {
+    const Column r = e[k];
+    const int a = (int)(r.cidx >> 32), b = (int)(uint32_t)r.cidx;
+    const int ca = w.comp[a], cb = w.comp[b];
+    if (ca != cb) {
+      const unsigned long long key = edge_key(r.key_hi, a, b);
+      atomicMin(&w.best[ca], key);
+      atomicMin(&w.best[cb], key);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kH0Threads) void h0w_hook_kernel(int n, H0Wide w) {
   __shared__ int changed;
   if (*w.done) return;  // the same value for the whole workgroup
@@ -765,7 +784,7 @@ size_t h0_wide_scratch_bytes(int n) {
 }
 
 hipError_t launch_h0_wide(const uint32_t* W, int n, CloudState* st, H0Pair* out, uint32_t* bm,
-                          void* scratch, hipStream_t s) {
+                          void* scratch, hipStream_t s, const Column* edges, int64_t m) {
   if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
   char* p = static_cast<char*>(scratch);
   const size_t base = h0_wide_base(n);
@@ -780,8 +799,13 @@ hipError_t launch_h0_wide(const uint32_t* W, int n, CloudState* st, H0Pair* out,
   h0w_init_kernel<<<(n + kH0Threads - 1) / kH0Threads, kH0Threads, 0, s>>>(n, w);
   int rounds = 1;
   while ((1 << (rounds - 1)) < n) ++rounds;  // ceil(log2 n) + 1
+  const int64_t eg = (m + kBlock - 1) / kBlock;
+  const unsigned edge_groups = (unsigned)(eg < 1 ? 1 : eg > 4096 ? 4096 : eg);
   for (int r = 0; r < rounds; ++r) {
-    h0w_scan_kernel<<<scan_groups, kH0Threads, 0, s>>>(W, n, w);
+    if (edges)
+      h0w_scan_edges_kernel<<<edge_groups, kBlock, 0, s>>>(edges, m, w);
+    else
+      h0w_scan_kernel<<<scan_groups, kH0Threads, 0, s>>>(W, n, w);
     h0w_hook_kernel<<<1, kH0Threads, 0, s>>>(n, w);
   }
   if (n <= kH0LdsN) {

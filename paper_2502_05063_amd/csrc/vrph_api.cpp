@@ -635,23 +635,7 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
                                         !d_from_pdist,
                                         count_edges ? c->fe_count.as<unsigned long long>()
                                                     : nullptr));
-  // H0: one workgroup for small clouds; above kH0WideMin points the
-  // Boruvka row scans are spread over the chip
-  constexpr int kH0WideMin = 512;
-  if (n >= kH0WideMin) {
-    HIP_TRY(c->h0w.ensure(h0_wide_scratch_bytes(n)));
-    HIP_TRY(launch_h0_wide(c->W.as<uint32_t>(), n, c->cstate.as<CloudState>(), c->h0.as<H0Pair>(),
-                           bm + bm_off[1], c->h0w.p, s));
-  } else {
-    HIP_TRY(launch_batch_h0(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1,
-                            c->cstate.as<CloudState>(), c->h0.as<H0Pair>(), n, bm + bm_off[1], s));
-  }
-  HIP_TRY(hipEventRecord(c->ev1, s));
   CloudState cs;
-  if (count_edges)
-    HIP_TRY(hipMemcpyAsync(c->h_fe_count.p, c->fe_count.p, sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(c->h_cstate.p, c->cstate.p, sizeof(CloudState), hipMemcpyDeviceToHost, s));
   // the weights on the host, in a pinned buffer the context keeps (no page
   // faults or zero fill per call, and the copy is a straight DMA)
   uint32_t* hW = nullptr;
@@ -661,7 +645,52 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
     hW = c->h_Wn.as<uint32_t>();
     return hipMemcpyAsync(hW, c->W.p, (size_t)n * n * 4, hipMemcpyDeviceToHost, s);
   };
-  if (!count_edges) HIP_TRY(copy_weights());
+  // In edge-list mode the finite edges are listed before H0, whose Boruvka
+  // rounds then scan that list instead of the rows of W.
+  uint64_t n_finite = 0;
+  bool edge_list = false;
+  if (count_edges) {
+    HIP_TRY(hipMemcpyAsync(c->h_fe_count.p, c->fe_count.p, sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(&n_finite, c->h_fe_count.p, sizeof(n_finite));
+    edge_list = 2 * n_finite < n_pairs;
+    if (edge_list) {
+      const size_t m = (size_t)std::max<uint64_t>(n_finite, 1);
+      HIP_TRY(c->fe_cols.ensure(m * sizeof(Column)));
+      HIP_TRY(c->fe_tmp.ensure(m * sizeof(Column)));
+      HIP_TRY(c->fe_work.ensure(radix_sort_work_bytes((int64_t)m)));
+      HIP_TRY(c->h_fe.ensure(m * sizeof(Column)));
+      HIP_TRY(hipMemsetAsync(c->fe_count.p, 0, sizeof(unsigned long long), s));
+      HIP_TRY(launch_finite_edges(c->W.as<uint32_t>(), (int)n, c->fe_cols.as<Column>(), n_finite,
+                                  c->fe_count.as<unsigned long long>(), s));
+    }
+  }
+  // H0: one workgroup for small clouds; above kH0WideMin points the
+  // Boruvka rounds are spread over the chip
+  constexpr int kH0WideMin = 512;
+  if (n >= kH0WideMin) {
+    HIP_TRY(c->h0w.ensure(h0_wide_scratch_bytes(n)));
+    HIP_TRY(launch_h0_wide(c->W.as<uint32_t>(), n, c->cstate.as<CloudState>(), c->h0.as<H0Pair>(),
+                           bm + bm_off[1], c->h0w.p, s,
+                           edge_list ? c->fe_cols.as<Column>() : nullptr,
+                           edge_list ? (int64_t)n_finite : 0));
+  } else {
+    HIP_TRY(launch_batch_h0(c->W.as<uint32_t>(), c->clouds.as<Cloud>(), 1,
+                            c->cstate.as<CloudState>(), c->h0.as<H0Pair>(), n, bm + bm_off[1], s));
+  }
+  HIP_TRY(hipEventRecord(c->ev1, s));
+  HIP_TRY(hipMemcpyAsync(c->h_cstate.p, c->cstate.p, sizeof(CloudState), hipMemcpyDeviceToHost, s));
+  if (edge_list) {
+    // the host's copy, sorted by weight
+    bool in_tmp = false;
+    HIP_TRY(radix_sort_columns(c->fe_cols.as<Column>(), c->fe_tmp.as<Column>(), (int64_t)n_finite,
+                               0, 0, c->fe_work.p, s, nullptr, &in_tmp));
+    HIP_TRY(hipMemcpyAsync(c->h_fe.p, in_tmp ? c->fe_tmp.p : c->fe_cols.p,
+                           (size_t)n_finite * sizeof(Column), hipMemcpyDeviceToHost, s));
+  } else {
+    HIP_TRY(copy_weights());
+  }
   std::vector<H0Pair> h0(n);
   HIP_TRY(hipMemcpyAsync(h0.data(), c->h0.p, (size_t)n * sizeof(H0Pair), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -674,34 +703,11 @@ static vrph_status barcode_impl(vrph_ctx* c, const float* D, int n, int max_dim,
                                  ((cs.err & 16) ? " entry index out of range or on the diagonal" : "") +
                                  ((cs.err & 32) ? " repeated pair" : ""));
   RankTable& ranks = c->ranks;  // its storage is reused across calls
-  uint64_t n_finite = 0;
-  bool edge_list = false;
   const Column* fe = nullptr;  // the finite edges, sorted by weight (edge-list mode)
-  if (count_edges) {
-    std::memcpy(&n_finite, c->h_fe_count.p, sizeof(n_finite));
-    edge_list = 2 * n_finite < n_pairs;
-    if (edge_list) {
-      const size_t m = (size_t)std::max<uint64_t>(n_finite, 1);
-      HIP_TRY(c->fe_cols.ensure(m * sizeof(Column)));
-      HIP_TRY(c->fe_tmp.ensure(m * sizeof(Column)));
-      HIP_TRY(c->fe_work.ensure(radix_sort_work_bytes((int64_t)m)));
-      HIP_TRY(c->h_fe.ensure(m * sizeof(Column)));
-      HIP_TRY(hipMemsetAsync(c->fe_count.p, 0, sizeof(unsigned long long), s));
-      HIP_TRY(launch_finite_edges(c->W.as<uint32_t>(), (int)n, c->fe_cols.as<Column>(), n_finite,
-                                  c->fe_count.as<unsigned long long>(), s));
-      bool in_tmp = false;
-      HIP_TRY(radix_sort_columns(c->fe_cols.as<Column>(), c->fe_tmp.as<Column>(), (int64_t)n_finite,
-                                 0, 0, c->fe_work.p, s, nullptr, &in_tmp));
-      HIP_TRY(hipMemcpyAsync(c->h_fe.p, in_tmp ? c->fe_tmp.p : c->fe_cols.p,
-                             (size_t)n_finite * sizeof(Column), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      fe = c->h_fe.as<Column>();
-      ranks.build_from_edges((int)n, fe, (size_t)n_finite);
-      ranks.attach(H);
-    } else {
-      HIP_TRY(copy_weights());
-      HIP_TRY(hipStreamSynchronize(s));
-    }
+  if (edge_list) {
+    fe = c->h_fe.as<Column>();
+    ranks.build_from_edges((int)n, fe, (size_t)n_finite);
+    ranks.attach(H);
   }
   H.W = hW;  // null in edge-list mode: the host reads ranks only
   // Weight ranks: needed by the host reduction and, for small clouds, by the

@@ -168,10 +168,13 @@ hipError_t launch_batch_h0(const uint32_t* W, const Cloud* clouds, int count, Cl
                            H0Pair* out, int64_t out_stride, uint32_t* bitmaps, hipStream_t s);
 // H0 of one cloud (W: its n x n weights, 1 <= n <= kMaxN) with the Boruvka
 // row scans spread over the chip; scratch: h0_wide_scratch_bytes(n) bytes of
-// device memory. Same outputs as launch_batch_h0 for that cloud.
+// device memory. Same outputs as launch_batch_h0 for that cloud. With
+// `edges` (the m finite edges of the lower triangle as launch_finite_edges
+// writes them, in any order) the rounds scan that list instead of W's rows.
 size_t h0_wide_scratch_bytes(int n);
 hipError_t launch_h0_wide(const uint32_t* W, int n, CloudState* st, H0Pair* out, uint32_t* bm,
-                          void* scratch, hipStream_t s);
+                          void* scratch, hipStream_t s, const Column* edges = nullptr,
+                          int64_t m = 0);
 // Rank-matrix variant of the same: Wr holds n rows of lds_stride(n) 16-bit
 // weight ranks (0xFFFF above tau_eff, on the diagonal and in the padding
 // past column n-1), n <= kLdsMaxN; rank_bits maps a rank to its weight.
